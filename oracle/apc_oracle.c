@@ -1,0 +1,1208 @@
+/*
+ * apc_oracle.c -- FP64 CPU oracle of the AP-Cloud field solve.
+ *
+ * TEST INFRASTRUCTURE ONLY: loaded by the test suite, the smoke check and the
+ * CPU-baseline leg of the benchmark, never by the product path.  Plain, serial,
+ * deliberately unoptimised C that follows the paper's steps in order:
+ *
+ *   Sec. 4      particles sorted by Morton key; pointer octree whose cells keep
+ *               (first particle, particle count)
+ *   Sec. 4.1    error-balance criterion h < c N'^(-1/(2k-2)) tested over the
+ *               queue Q (eq. errorbalance_implementation)
+ *   Sec. 4.2-3  2:1 face balance, processed from the deepest level upward, with
+ *               the face-neighbour definition of Sec. 4.3
+ *   Sec. 4.3    boundary nodes; k-ring neighbour search up to the 5-ring
+ *   Sec. 3.1    weighted least squares GFD fit (scaled Vandermonde V0, Gaussian
+ *               weight with c = 4) solved by Householder QR
+ *   Sec. 3.2    density rows B = a^T V^+ C (eq. density_linear_system), GFD
+ *               Poisson rows, Taylor interpolation of phi and grad phi
+ *   Sec. 5      BiCGSTAB (the paper leaves the sparse solver open) and a dense
+ *               LU cross-check
+ *
+ * Readings of points the paper leaves open are stated where they are used.
+ */
+#include "apc_oracle.h"
+
+#include <math.h>
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define MAXP 34
+#define MAXM 64
+
+/* ------------------------------------------------------------------ */
+/* Monomials: fitted unknowns are d^alpha f for 1 <= |alpha| <= k (the constant
+   term is removed by differencing, eq. gfd); columns are ordered by degree and,
+   within a degree, by descending exponent tuple (x first), as in the 2-D
+   example matrix of Sec. 3.1. */
+
+int apco_num_unknowns(int order) {
+  if (order < 1 || order > 4) return APCO_EINVAL;
+  return (order + 1) * (order + 2) * (order + 3) / 6 - 1;
+}
+
+int apco_monomials(int order, int32_t *al) {
+  int p = apco_num_unknowns(order);
+  if (p < 0) return p;
+  int c = 0;
+  for (int d = 1; d <= order; d++)
+    for (int a = d; a >= 0; a--)
+      for (int b = d - a; b >= 0; b--) {
+        al[3 * c + 0] = a;
+        al[3 * c + 1] = b;
+        al[3 * c + 2] = d - a - b;
+        c++;
+      }
+  return 0;
+}
+
+static double factorial(int a) {
+  double f = 1.0;
+  for (int i = 2; i <= a; i++) f *= (double)i;
+  return f;
+}
+
+static double ipow(double x, int a) {
+  double r = 1.0;
+  for (int i = 0; i < a; i++) r *= x;
+  return r;
+}
+
+/* xi^alpha / alpha! */
+static double mono(const int32_t *a, double x, double y, double z) {
+  return ipow(x, a[0]) / factorial(a[0]) * ipow(y, a[1]) / factorial(a[1]) * ipow(z, a[2]) /
+         factorial(a[2]);
+}
+
+/* ------------------------------------------------------------------ */
+/* Weighted least squares fit (Sec. 3.1).
+   delta_j = y^j - y^0, h = max_{d,j} |delta_d^j|, xi = delta / h,
+   V0 row j = [xi_j^alpha / alpha!], W_j = (exp(-r_j^2/r_max^2) - e^-4)/(1 - e^-4).
+   Reading: rows are scaled by W (minimise sum_j (W_j (V0 a - df)_j)^2).
+   X = (W V0)^+ W = R^{-1} Q^T W via Householder QR of W V0, so that the scaled
+   derivatives h^{|alpha|} d^alpha f(y0) are X (f_j - f_0). */
+static int wls_core(int order, int m, const double *dx, const double *dy, const double *dz,
+                    double *X, double *hout, double *ratio) {
+  int p = apco_num_unknowns(order);
+  int32_t al[3 * MAXP];
+  apco_monomials(order, al);
+  if (m < 1 || m > MAXM) return APCO_EINVAL;
+  double h = 0.0, r2max = 0.0;
+  double r2[MAXM], W[MAXM];
+  for (int j = 0; j < m; j++) {
+    if (fabs(dx[j]) > h) h = fabs(dx[j]);
+    if (fabs(dy[j]) > h) h = fabs(dy[j]);
+    if (fabs(dz[j]) > h) h = fabs(dz[j]);
+    r2[j] = dx[j] * dx[j] + dy[j] * dy[j] + dz[j] * dz[j];
+    if (r2[j] > r2max) r2max = r2[j];
+  }
+  *hout = h;
+  if (h == 0.0 || m < p) {
+    *ratio = 0.0;
+    return 0;
+  }
+  const double e4 = exp(-4.0);
+  for (int j = 0; j < m; j++) W[j] = (exp(-r2[j] / r2max) - e4) / (1.0 - e4);
+
+  /* A = W V0, column-major m x p */
+  static double A[MAXP * MAXM], V[MAXP * MAXM], Q[MAXP * MAXM];
+  double beta[MAXP], R[MAXP * MAXP];
+  for (int c = 0; c < p; c++)
+    for (int j = 0; j < m; j++)
+      A[c * m + j] = W[j] * mono(&al[3 * c], dx[j] / h, dy[j] / h, dz[j] / h);
+
+  /* Householder QR */
+  for (int c = 0; c < p; c++) {
+    double nrm2 = 0.0;
+    for (int j = c; j < m; j++) nrm2 += A[c * m + j] * A[c * m + j];
+    double nrm = sqrt(nrm2);
+    for (int j = 0; j < m; j++) V[c * m + j] = 0.0;
+    if (nrm == 0.0) {
+      beta[c] = 0.0;
+      continue;
+    }
+    double alpha = A[c * m + c] >= 0.0 ? -nrm : nrm;
+    for (int j = c; j < m; j++) V[c * m + j] = A[c * m + j];
+    V[c * m + c] -= alpha;
+    double vn2 = 0.0;
+    for (int j = c; j < m; j++) vn2 += V[c * m + j] * V[c * m + j];
+    beta[c] = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    for (int c2 = c + 1; c2 < p; c2++) {
+      double s = 0.0;
+      for (int j = c; j < m; j++) s += V[c * m + j] * A[c2 * m + j];
+      s *= beta[c];
+      for (int j = c; j < m; j++) A[c2 * m + j] -= s * V[c * m + j];
+    }
+    A[c * m + c] = alpha;
+    for (int j = c + 1; j < m; j++) A[c * m + j] = 0.0;
+  }
+  double rmin = INFINITY, rmax = 0.0;
+  for (int c = 0; c < p; c++) {
+    for (int i = 0; i < p; i++) R[i * p + c] = (i <= c) ? A[c * m + i] : 0.0;
+    double d = fabs(R[c * p + c]);
+    if (d < rmin) rmin = d;
+    if (d > rmax) rmax = d;
+  }
+  *ratio = rmax > 0.0 ? rmin / rmax : 0.0;
+  if (rmin == 0.0) return 0;
+
+  /* thin Q = H_0 ... H_{p-1} [I_p; 0], column-major m x p */
+  for (int c = 0; c < p; c++)
+    for (int j = 0; j < m; j++) Q[c * m + j] = (j == c) ? 1.0 : 0.0;
+  for (int c = p - 1; c >= 0; c--)
+    for (int q = 0; q < p; q++) {
+      double s = 0.0;
+      for (int j = c; j < m; j++) s += V[c * m + j] * Q[q * m + j];
+      s *= beta[c];
+      for (int j = c; j < m; j++) Q[q * m + j] -= s * V[c * m + j];
+    }
+  /* X[:, j] = R^{-1} (Q[j, :]^T W_j) by back substitution */
+  for (int j = 0; j < m; j++) {
+    double x[MAXP];
+    for (int i = p - 1; i >= 0; i--) {
+      double s = Q[i * m + j] * W[j];
+      for (int k = i + 1; k < p; k++) s -= R[i * p + k] * x[k];
+      x[i] = s / R[i * p + i];
+    }
+    for (int i = 0; i < p; i++) X[i * m + j] = x[i];
+  }
+  return 0;
+}
+
+int apco_wls_fit(int order, int m, const double *delta, double *X, double *h, double *ratio) {
+  if (apco_num_unknowns(order) < 0 || m < 1 || m > MAXM) return APCO_EINVAL;
+  double dx[MAXM], dy[MAXM], dz[MAXM];
+  for (int j = 0; j < m; j++) {
+    dx[j] = delta[3 * j];
+    dy[j] = delta[3 * j + 1];
+    dz[j] = delta[3 * j + 2];
+  }
+  return wls_core(order, m, dx, dy, dz, X, h, ratio);
+}
+
+/* ------------------------------------------------------------------ */
+/* Octree (Sec. 4).  Reading of the Morton key: 3 bits per level, the x bit
+   highest in each triple; particles are quantised at the deepest level
+   max_depth: u_d = floor((x_d - lo_d) * (2^max_depth / L)), clamped into
+   [0, 2^max_depth - 1]. */
+
+typedef struct {
+  int32_t level, ix, iy, iz;
+  int64_t child;  /* index of the first of 8 children, -1 for a leaf */
+  int64_t first, count;
+  int32_t opened; /* 0 leaf, 1 criterion, 2 balance */
+} ocell;
+
+struct apco_cloud {
+  apco_params P;
+  int64_t N;
+  int p;
+  double T[32];
+  double unit;
+  int64_t *perm;
+  uint64_t *skey;
+  ocell *cells;
+  int64_t ncells, capcells, nopened;
+  int64_t n, nb;
+  int64_t *node_cell;
+  int64_t *cell_node;
+  int32_t *crd; /* 3*(n+nb), node-major */
+  int32_t *bowner, *bface;
+  int32_t *bidx; /* 6*n: boundary node index of (node, face) or -1 */
+  int32_t *r1off, *r1;
+  int32_t *st_off, *st, *st_ring;
+};
+
+static uint64_t morton(uint64_t x, uint64_t y, uint64_t z, int bits) {
+  uint64_t k = 0;
+  for (int b = 0; b < bits; b++) {
+    k |= ((x >> b) & 1ull) << (3 * b + 2);
+    k |= ((y >> b) & 1ull) << (3 * b + 1);
+    k |= ((z >> b) & 1ull) << (3 * b);
+  }
+  return k;
+}
+
+typedef struct {
+  uint64_t key;
+  int64_t idx;
+} kpair;
+
+static int cmp_kpair(const void *a, const void *b) {
+  const kpair *x = a, *y = b;
+  if (x->key != y->key) return x->key < y->key ? -1 : 1;
+  return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/* first position in [lo,hi) with skey >= v */
+static int64_t lower_bound(const uint64_t *a, int64_t lo, int64_t hi, uint64_t v) {
+  while (lo < hi) {
+    int64_t mid = lo + (hi - lo) / 2;
+    if (a[mid] < v) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo;
+}
+
+int apco_thresholds(const apco_params *P, double *T) {
+  /* T_l = t^(2k-2), t = c 2^l / L: the criterion h < c N'^(-1/(2k-2)) with
+     h = L 2^-l (cell edge, as in the worked example of Sec. 4.3) is N' < T_l;
+     a cell is opened when N' >= T_l.  Evaluated as t = (c * 2^l) / L and then
+     repeated multiplication from 1.0. */
+  for (int l = 0; l <= P->max_depth; l++) {
+    double t = (P->c * ldexp(1.0, l)) / P->L;
+    double v = 1.0;
+    for (int e = 0; e < 2 * P->order - 2; e++) v *= t;
+    T[l] = v;
+  }
+  return 0;
+}
+
+static int push_cell(apco_cloud *C, ocell c) {
+  if (C->ncells == C->capcells) {
+    int64_t nc = C->capcells ? 2 * C->capcells : 1024;
+    ocell *q = realloc(C->cells, (size_t)nc * sizeof(ocell));
+    if (!q) return APCO_ENOMEM;
+    C->cells = q;
+    C->capcells = nc;
+  }
+  C->cells[C->ncells++] = c;
+  return 0;
+}
+
+/* "open" a cell (Sec. 4.3): mark it non-node and append its 8 children to Q;
+   each child's particle range is the sub-range of its parent's sorted range
+   carrying the child's key prefix. */
+static int open_cell(apco_cloud *C, int64_t i, int why) {
+  int D = C->P.max_depth;
+  ocell par = C->cells[i];
+  int64_t first = C->ncells;
+  int lv = par.level + 1;
+  int sh = 3 * (D - lv);
+  for (int c = 0; c < 8; c++) {
+    ocell ch;
+    ch.level = lv;
+    ch.ix = 2 * par.ix + ((c >> 2) & 1);
+    ch.iy = 2 * par.iy + ((c >> 1) & 1);
+    ch.iz = 2 * par.iz + (c & 1);
+    ch.child = -1;
+    ch.opened = 0;
+    uint64_t pre = morton((uint64_t)ch.ix, (uint64_t)ch.iy, (uint64_t)ch.iz, lv);
+    int64_t a = lower_bound(C->skey, par.first, par.first + par.count, pre << sh);
+    int64_t b = lower_bound(C->skey, par.first, par.first + par.count, (pre + 1) << sh);
+    ch.first = a;
+    ch.count = b - a;
+    int rc = push_cell(C, ch);
+    if (rc) return rc;
+  }
+  C->cells[i].child = first;
+  C->cells[i].opened = why;
+  C->nopened++;
+  return 0;
+}
+
+/* Face neighbour of cell i across face f (Sec. 4.3), read as the deepest cell of
+   Q with level <= level(i) that shares face f with cell i (the paper's wording
+   "no ancestor" is read as "no descendant": the neighbour's level only grows as
+   cells open).  -1 if the face lies on the domain boundary. */
+static int64_t face_nb(const apco_cloud *C, int64_t i, int f) {
+  const ocell *y = &C->cells[i];
+  int32_t t[3] = {y->ix, y->iy, y->iz};
+  int d = f / 2;
+  t[d] += (f & 1) ? 1 : -1;
+  if (t[d] < 0 || t[d] >= (1 << y->level)) return -1;
+  int64_t cur = 0;
+  while (C->cells[cur].child >= 0 && C->cells[cur].level < y->level) {
+    int sh = y->level - C->cells[cur].level - 1;
+    int c = (((t[0] >> sh) & 1) << 2) | (((t[1] >> sh) & 1) << 1) | ((t[2] >> sh) & 1);
+    cur = C->cells[cur].child + c;
+  }
+  return cur;
+}
+
+typedef struct {
+  uint64_t code;
+  int64_t cell;
+} lpair;
+
+static int cmp_lpair(const void *a, const void *b) {
+  const lpair *x = a, *y = b;
+  return (x->code > y->code) - (x->code < y->code);
+}
+
+typedef struct {
+  int64_t r2;
+  int32_t idx;
+} cand_t;
+
+static int cmp_cand(const void *a, const void *b) {
+  const cand_t *x = a, *y = b;
+  if (x->r2 != y->r2) return x->r2 < y->r2 ? -1 : 1;
+  return (x->idx > y->idx) - (x->idx < y->idx);
+}
+
+/* Octant membership with closed octants (a zero offset counts on both sides). */
+static int in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
+  int sx = (o >> 2) & 1 ? 1 : -1, sy = (o >> 1) & 1 ? 1 : -1, sz = o & 1 ? 1 : -1;
+  return sx * d0 >= 0 && sy * d1 >= 0 && sz * d2 >= 0;
+}
+
+/* Stencil choice from a candidate ring sorted by (r^2, index) -- the quadrant
+   criterion of Sec. 3.1 read for 3-D octants: first the two nearest candidates of
+   every closed octant, then the nearest remaining candidates, until
+   min(count, m_cap) nodes are chosen; the chosen set is kept in candidate order.
+   It is accepted when (i) every closed octant holds at least one chosen node,
+   (ii) m >= p + 1 and (iii) the weighted V0 has full column rank:
+   min|R_ii| / max|R_ii| >= 1e-6.  Returns m (>0) on acceptance, 0 otherwise; the
+   chosen candidates are compacted to the front of cd. */
+#define TAU_RANK 1e-6
+static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cnt, int m_cap) {
+  const int32_t *c0 = &C->crd[3 * y];
+  int64_t want = cnt < m_cap ? cnt : m_cap;
+  static unsigned char pick[1 << 20];
+  if (cnt > (int64_t)sizeof(pick)) return 0;
+  memset(pick, 0, (size_t)cnt);
+  int64_t got = 0;
+  for (int o = 0; o < 8; o++) {
+    int taken = 0;
+    for (int64_t j = 0; j < cnt && taken < 2; j++) {
+      const int32_t *c1 = &C->crd[3 * cd[j].idx];
+      if (!in_octant(o, c1[0] - c0[0], c1[1] - c0[1], c1[2] - c0[2])) continue;
+      taken++;
+      if (!pick[j] && got < want) {
+        pick[j] = 1;
+        got++;
+      }
+    }
+  }
+  for (int64_t j = 0; j < cnt && got < want; j++)
+    if (!pick[j]) {
+      pick[j] = 1;
+      got++;
+    }
+  int m = 0;
+  for (int64_t j = 0; j < cnt; j++)
+    if (pick[j]) cd[m++] = cd[j];
+  if (m < C->p + 1 || m > MAXM) return 0;
+  int oct[8] = {0};
+  double dx[MAXM], dy[MAXM], dz[MAXM];
+  for (int j = 0; j < m; j++) {
+    const int32_t *c1 = &C->crd[3 * cd[j].idx];
+    int64_t d0 = c1[0] - c0[0], d1 = c1[1] - c0[1], d2 = c1[2] - c0[2];
+    dx[j] = (double)d0;
+    dy[j] = (double)d1;
+    dz[j] = (double)d2;
+    for (int o = 0; o < 8; o++) oct[o] += in_octant(o, d0, d1, d2);
+  }
+  for (int o = 0; o < 8; o++)
+    if (oct[o] < 1) return 0;
+  static double X[MAXP * MAXM];
+  double h, ratio;
+  wls_core(C->P.order, m, dx, dy, dz, X, &h, &ratio);
+  return ratio >= TAU_RANK ? m : 0;
+}
+
+void apco_destroy(apco_cloud *C) {
+  if (!C) return;
+  free(C->perm);
+  free(C->skey);
+  free(C->cells);
+  free(C->node_cell);
+  free(C->cell_node);
+  free(C->crd);
+  free(C->bowner);
+  free(C->bface);
+  free(C->bidx);
+  free(C->r1off);
+  free(C->r1);
+  free(C->st_off);
+  free(C->st);
+  free(C->st_ring);
+  free(C);
+}
+
+#define CHECK_ALLOC(p)       \
+  do {                       \
+    if (!(p)) {              \
+      apco_destroy(C);       \
+      return APCO_ENOMEM;    \
+    }                        \
+  } while (0)
+
+int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cloud **out) {
+  *out = NULL;
+  int p = apco_num_unknowns(P->order);
+  if (!(P->order == 2 || P->order == 4) || P->max_depth < 1 || P->max_depth > 20 ||
+      !(P->L > 0.0) || !(P->c > 0.0) || P->ring_min < 1 || P->ring_max < P->ring_min ||
+      P->m_cap > MAXM || P->m_cap < p + 1 || N < 1)
+    return APCO_EINVAL;
+  apco_cloud *C = calloc(1, sizeof(apco_cloud));
+  if (!C) return APCO_ENOMEM;
+  C->P = *P;
+  C->N = N;
+  C->p = p;
+  const int D = P->max_depth;
+  apco_thresholds(P, C->T);
+  C->unit = P->L / ldexp(1.0, D + 1);
+
+  /* Morton keys and sort (Sec. 4): stable by (key, original index) */
+  kpair *kp = malloc((size_t)N * sizeof(kpair));
+  CHECK_ALLOC(kp);
+  const double s = ldexp(1.0, D) / P->L;
+  const int64_t top = ((int64_t)1 << D) - 1;
+  for (int64_t i = 0; i < N; i++) {
+    int64_t u[3];
+    for (int d = 0; d < 3; d++) {
+      double x = xyz[d * N + i];
+      if (isnan(x)) {
+        free(kp);
+        apco_destroy(C);
+        return APCO_EINVAL;
+      }
+      if (x < P->lo[d] || x > P->lo[d] + P->L) {
+        free(kp);
+        apco_destroy(C);
+        return APCO_EDOMAIN;
+      }
+      double q = floor((x - P->lo[d]) * s);
+      int64_t v = (int64_t)q;
+      if (v < 0) v = 0;
+      if (v > top) v = top;
+      u[d] = v;
+    }
+    kp[i].key = morton((uint64_t)u[0], (uint64_t)u[1], (uint64_t)u[2], D);
+    kp[i].idx = i;
+  }
+  qsort(kp, (size_t)N, sizeof(kpair), cmp_kpair);
+  C->perm = malloc((size_t)N * sizeof(int64_t));
+  C->skey = malloc((size_t)N * sizeof(uint64_t));
+  if (!C->perm || !C->skey) {
+    free(kp);
+    apco_destroy(C);
+    return APCO_ENOMEM;
+  }
+  for (int64_t i = 0; i < N; i++) {
+    C->perm[i] = kp[i].idx;
+    C->skey[i] = kp[i].key;
+  }
+  free(kp);
+
+  /* Node selection (Sec. 4.3).  Step 1: Q = {root}. */
+  ocell root = {0, 0, 0, 0, -1, 0, N, 0};
+  if (push_cell(C, root)) {
+    apco_destroy(C);
+    return APCO_ENOMEM;
+  }
+  /* Step 2: traverse Q (children appended during the traversal are visited too);
+     open every cell violating the error-balance criterion, below max_depth. */
+  for (int64_t i = 0; i < C->ncells; i++) {
+    const ocell *c = &C->cells[i];
+    if (c->level < D && (double)c->count >= C->T[c->level])
+      if (open_cell(C, i, 1)) {
+        apco_destroy(C);
+        return APCO_ENOMEM;
+      }
+  }
+  int lq = 0;
+  for (int64_t i = 0; i < C->ncells; i++)
+    if (C->cells[i].level > lq) lq = C->cells[i].level;
+  /* Steps 3-4: from the deepest level up, every leaf at level l opens each face
+     neighbour that is a leaf more than one level coarser (re-resolving the
+     neighbour after each opening). */
+  for (int l = lq; l >= 1; l--) {
+    for (int64_t i = 0; i < C->ncells; i++) {
+      if (C->cells[i].child >= 0 || C->cells[i].level != l) continue;
+      for (int f = 0; f < 6; f++) {
+        for (;;) {
+          int64_t z = face_nb(C, i, f);
+          if (z < 0) break;
+          if (C->cells[z].child < 0 && C->cells[z].level < l - 1) {
+            if (open_cell(C, z, 2)) {
+              apco_destroy(C);
+              return APCO_ENOMEM;
+            }
+          } else {
+            break;
+          }
+        }
+      }
+    }
+  }
+
+  /* Nodes: every leaf (node candidate), ordered by the Morton code of its
+     minimum corner at max_depth. */
+  int64_t n = C->ncells - C->nopened;
+  lpair *lp = malloc((size_t)n * sizeof(lpair));
+  CHECK_ALLOC(lp);
+  int64_t k = 0;
+  for (int64_t i = 0; i < C->ncells; i++) {
+    const ocell *c = &C->cells[i];
+    if (c->child >= 0) continue;
+    int sh = D - c->level;
+    lp[k].code = morton((uint64_t)c->ix << sh, (uint64_t)c->iy << sh, (uint64_t)c->iz << sh, D);
+    lp[k].cell = i;
+    k++;
+  }
+  if (k != n) {
+    free(lp);
+    apco_destroy(C);
+    return APCO_EINVAL;
+  }
+  qsort(lp, (size_t)n, sizeof(lpair), cmp_lpair);
+  C->n = n;
+  C->node_cell = malloc((size_t)n * sizeof(int64_t));
+  C->cell_node = malloc((size_t)C->ncells * sizeof(int64_t));
+  C->bidx = malloc((size_t)n * 6 * sizeof(int32_t));
+  if (!C->node_cell || !C->cell_node || !C->bidx) {
+    free(lp);
+    apco_destroy(C);
+    return APCO_ENOMEM;
+  }
+  for (int64_t i = 0; i < C->ncells; i++) C->cell_node[i] = -1;
+  for (int64_t j = 0; j < n; j++) {
+    C->node_cell[j] = lp[j].cell;
+    C->cell_node[lp[j].cell] = j;
+  }
+  free(lp);
+
+  /* Boundary nodes (Sec. 4.3 "add additional nodes on the boundary"): read as one
+     node at the centre of every leaf face lying on the domain boundary. */
+  int64_t nb = 0;
+  for (int64_t j = 0; j < n; j++) {
+    const ocell *c = &C->cells[C->node_cell[j]];
+    int32_t ii[3] = {c->ix, c->iy, c->iz};
+    for (int f = 0; f < 6; f++) {
+      int d = f / 2;
+      int on = (f & 1) ? (ii[d] == (1 << c->level) - 1) : (ii[d] == 0);
+      C->bidx[6 * j + f] = on ? (int32_t)(n + nb++) : -1;
+    }
+  }
+  C->nb = nb;
+  C->crd = malloc((size_t)3 * (n + nb) * sizeof(int32_t));
+  C->bowner = malloc((size_t)(nb + 1) * sizeof(int32_t));
+  C->bface = malloc((size_t)(nb + 1) * sizeof(int32_t));
+  CHECK_ALLOC(C->crd);
+  CHECK_ALLOC(C->bowner);
+  CHECK_ALLOC(C->bface);
+  for (int64_t j = 0; j < n; j++) {
+    const ocell *c = &C->cells[C->node_cell[j]];
+    int32_t sz = 1 << (D - c->level);
+    C->crd[3 * j + 0] = (2 * c->ix + 1) * sz;
+    C->crd[3 * j + 1] = (2 * c->iy + 1) * sz;
+    C->crd[3 * j + 2] = (2 * c->iz + 1) * sz;
+    for (int f = 0; f < 6; f++) {
+      int32_t b = C->bidx[6 * j + f];
+      if (b < 0) continue;
+      int d = f / 2;
+      for (int e = 0; e < 3; e++) C->crd[3 * b + e] = C->crd[3 * j + e];
+      C->crd[3 * b + d] = (f & 1) ? (1 << (D + 1)) : 0;
+      C->bowner[b - n] = (int32_t)j;
+      C->bface[b - n] = f;
+    }
+  }
+
+  /* 1-ring (Sec. 4.3): for each face, the neighbour if it is a node, else the 4
+     children of the neighbour sharing that face (nodes by 2:1 balance); a face on
+     the domain boundary contributes its boundary node. */
+  C->r1off = malloc((size_t)(n + 1) * sizeof(int32_t));
+  C->r1 = malloc((size_t)n * 24 * sizeof(int32_t));
+  CHECK_ALLOC(C->r1off);
+  CHECK_ALLOC(C->r1);
+  int64_t e = 0;
+  for (int64_t j = 0; j < n; j++) {
+    C->r1off[j] = (int32_t)e;
+    int64_t ci = C->node_cell[j];
+    for (int f = 0; f < 6; f++) {
+      int64_t z = face_nb(C, ci, f);
+      if (z < 0) {
+        C->r1[e++] = C->bidx[6 * j + f];
+        continue;
+      }
+      if (C->cells[z].child < 0) {
+        C->r1[e++] = (int32_t)C->cell_node[z];
+        continue;
+      }
+      int d = f / 2;
+      int side = (f & 1) ? 0 : 1; /* children of z on the face shared with cell j */
+      for (int c = 0; c < 8; c++) {
+        int bit = (c >> (2 - d)) & 1;
+        if (bit != side) continue;
+        int64_t ch = C->cells[z].child + c;
+        if (C->cells[ch].child >= 0) { /* cannot happen in a 2:1-balanced tree */
+          apco_destroy(C);
+          return APCO_EINVAL;
+        }
+        C->r1[e++] = (int32_t)C->cell_node[ch];
+      }
+    }
+  }
+  C->r1off[n] = (int32_t)e;
+
+  /* Stencils (Sec. 4.3): the R-ring = nodes within R face-adjacency steps
+     (boundary nodes hang off their owner), sorted by (integer squared distance,
+     node index); a stencil is chosen from ring_min upward until one is accepted;
+     past ring_max the build fails. */
+  int64_t ntot = n + nb;
+  int32_t *stamp = malloc((size_t)ntot * sizeof(int32_t));
+  int32_t *front = malloc((size_t)ntot * sizeof(int32_t));
+  cand_t *cand = malloc((size_t)ntot * sizeof(cand_t));
+  C->st_off = malloc((size_t)(n + 1) * sizeof(int32_t));
+  C->st_ring = malloc((size_t)(n + 1) * sizeof(int32_t));
+  int64_t stcap = n * 32 + 64;
+  C->st = malloc((size_t)stcap * sizeof(int32_t));
+  if (!stamp || !front || !cand || !C->st_off || !C->st_ring || !C->st) {
+    free(stamp);
+    free(front);
+    free(cand);
+    apco_destroy(C);
+    return APCO_ENOMEM;
+  }
+  for (int64_t i = 0; i < ntot; i++) stamp[i] = -1;
+  int64_t ne = 0;
+  int rc = 0;
+  for (int64_t y = 0; y < n && !rc; y++) {
+    C->st_off[y] = (int32_t)ne;
+    int done = 0;
+    for (int R = P->ring_min; R <= P->ring_max && !done; R++) {
+      /* depth-limited BFS */
+      int64_t nf = 0, cnt = 0;
+      stamp[y] = (int32_t)y;
+      front[nf++] = (int32_t)y;
+      int64_t lo = 0;
+      for (int depth = 1; depth <= R; depth++) {
+        int64_t hi = nf;
+        for (int64_t t = lo; t < hi; t++) {
+          int32_t u = front[t];
+          if (u >= n) { /* boundary node: adjacent to its owner only */
+            int32_t v = C->bowner[u - n];
+            if (stamp[v] != (int32_t)y) {
+              stamp[v] = (int32_t)y;
+              front[nf++] = v;
+            }
+            continue;
+          }
+          for (int32_t a = C->r1off[u]; a < C->r1off[u + 1]; a++) {
+            int32_t v = C->r1[a];
+            if (stamp[v] != (int32_t)y) {
+              stamp[v] = (int32_t)y;
+              front[nf++] = v;
+            }
+          }
+        }
+        lo = hi;
+      }
+      for (int64_t t = 1; t < nf; t++) {
+        int32_t v = front[t];
+        int64_t d0 = C->crd[3 * v] - C->crd[3 * y];
+        int64_t d1 = C->crd[3 * v + 1] - C->crd[3 * y + 1];
+        int64_t d2 = C->crd[3 * v + 2] - C->crd[3 * y + 2];
+        cand[cnt].r2 = d0 * d0 + d1 * d1 + d2 * d2;
+        cand[cnt].idx = v;
+        cnt++;
+      }
+      /* reset stamps for the next ring size of this node */
+      for (int64_t t = 0; t < nf; t++) stamp[front[t]] = -1;
+      qsort(cand, (size_t)cnt, sizeof(cand_t), cmp_cand);
+      int m = choose_stencil(C, (int32_t)y, cand, cnt, P->m_cap);
+      if (m > 0) {
+        if (ne + m > stcap) {
+          stcap = 2 * stcap + m;
+          int32_t *q = realloc(C->st, (size_t)stcap * sizeof(int32_t));
+          if (!q) {
+            rc = APCO_ENOMEM;
+            break;
+          }
+          C->st = q;
+        }
+        for (int j = 0; j < m; j++) C->st[ne++] = cand[j].idx;
+        C->st_ring[y] = R;
+        done = 1;
+      }
+    }
+    if (!done && !rc) rc = APCO_ESTENCIL;
+  }
+  C->st_off[n] = (int32_t)ne;
+  free(stamp);
+  free(front);
+  free(cand);
+  if (rc) {
+    apco_destroy(C);
+    return rc;
+  }
+  *out = C;
+  return 0;
+}
+
+int apco_info(const apco_cloud *C, int64_t *n, int64_t *nb, int64_t *nnz, int64_t *n_opened,
+              int64_t *ncells) {
+  if (n) *n = C->n;
+  if (nb) *nb = C->nb;
+  if (nnz) *nnz = C->st_off[C->n];
+  if (n_opened) *n_opened = C->nopened;
+  if (ncells) *ncells = C->ncells;
+  return 0;
+}
+
+int apco_get_nodes(const apco_cloud *C, int64_t *perm, uint64_t *code, int32_t *level,
+                   int64_t *first, int64_t *count, int32_t *bowner, int32_t *bface,
+                   int32_t *st_off, int32_t *st_idx, int32_t *st_ring) {
+  const int D = C->P.max_depth;
+  if (perm) memcpy(perm, C->perm, (size_t)C->N * sizeof(int64_t));
+  for (int64_t j = 0; j < C->n; j++) {
+    const ocell *c = &C->cells[C->node_cell[j]];
+    int sh = D - c->level;
+    if (code)
+      code[j] = morton((uint64_t)c->ix << sh, (uint64_t)c->iy << sh, (uint64_t)c->iz << sh, D);
+    if (level) level[j] = c->level;
+    if (first) first[j] = c->first;
+    if (count) count[j] = c->count;
+    if (st_ring) st_ring[j] = C->st_ring[j];
+  }
+  if (bowner) memcpy(bowner, C->bowner, (size_t)C->nb * sizeof(int32_t));
+  if (bface) memcpy(bface, C->bface, (size_t)C->nb * sizeof(int32_t));
+  if (st_off) memcpy(st_off, C->st_off, (size_t)(C->n + 1) * sizeof(int32_t));
+  if (st_idx) memcpy(st_idx, C->st, (size_t)C->st_off[C->n] * sizeof(int32_t));
+  return 0;
+}
+
+int apco_node_coords(const apco_cloud *C, int32_t *ixyz) {
+  int64_t nt = C->n + C->nb;
+  for (int64_t j = 0; j < nt; j++)
+    for (int d = 0; d < 3; d++) ixyz[d * nt + j] = C->crd[3 * j + d];
+  return 0;
+}
+
+int apco_get_cells(const apco_cloud *C, int32_t *level, int32_t *ijk, int64_t *count,
+                   int32_t *opened) {
+  for (int64_t i = 0; i < C->ncells; i++) {
+    const ocell *c = &C->cells[i];
+    if (level) level[i] = c->level;
+    if (ijk) {
+      ijk[3 * i] = c->ix;
+      ijk[3 * i + 1] = c->iy;
+      ijk[3 * i + 2] = c->iz;
+    }
+    if (count) count[i] = c->count;
+    if (opened) opened[i] = c->opened;
+  }
+  return 0;
+}
+
+int apco_ring1(const apco_cloud *C, int32_t *off, int32_t *idx, int64_t cap) {
+  if (C->r1off[C->n] > cap) return APCO_EINVAL;
+  memcpy(off, C->r1off, (size_t)(C->n + 1) * sizeof(int32_t));
+  memcpy(idx, C->r1, (size_t)C->r1off[C->n] * sizeof(int32_t));
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Per-node fit on the cloud's stencil, in integer units. */
+static int node_fit(const apco_cloud *C, int64_t y, double *X, int *m, double *hphys) {
+  int32_t a = C->st_off[y], b = C->st_off[y + 1];
+  *m = b - a;
+  double dx[MAXM], dy[MAXM], dz[MAXM];
+  for (int j = 0; j < *m; j++) {
+    int32_t v = C->st[a + j];
+    dx[j] = (double)(C->crd[3 * v] - C->crd[3 * y]);
+    dy[j] = (double)(C->crd[3 * v + 1] - C->crd[3 * y + 1]);
+    dz[j] = (double)(C->crd[3 * v + 2] - C->crd[3 * y + 2]);
+  }
+  double h, ratio;
+  int rc = wls_core(C->P.order, *m, dx, dy, dz, X, &h, &ratio);
+  if (rc) return rc;
+  if (ratio < TAU_RANK) return APCO_ESTENCIL;
+  *hphys = h * C->unit;
+  return 0;
+}
+
+static int find_alpha(const int32_t *al, int p, int a, int b, int c) {
+  for (int i = 0; i < p; i++)
+    if (al[3 * i] == a && al[3 * i + 1] == b && al[3 * i + 2] == c) return i;
+  return -1;
+}
+
+/* GFD Poisson row (Sec. 3.2 step 2): Delta f(y0) = sum_d d^{2 e_d} f(y0)
+   = h^-2 sum_d X[2e_d] (f - f_0); off-diagonal weights w_j and diagonal -sum w_j. */
+int apco_assemble(const apco_cloud *C, double *w, double *diag) {
+  int p = C->p;
+  int32_t al[3 * MAXP];
+  apco_monomials(C->P.order, al);
+  int ixx = find_alpha(al, p, 2, 0, 0), iyy = find_alpha(al, p, 0, 2, 0),
+      izz = find_alpha(al, p, 0, 0, 2);
+  static double X[MAXP * MAXM];
+  for (int64_t y = 0; y < C->n; y++) {
+    int m;
+    double hp;
+    int rc = node_fit(C, y, X, &m, &hp);
+    if (rc) return rc;
+    double s = 0.0;
+    int32_t a = C->st_off[y];
+    for (int j = 0; j < m; j++) {
+      double v = (X[ixx * m + j] + X[iyy * m + j] + X[izz * m + j]) / (hp * hp);
+      w[a + j] = v;
+      s += v;
+    }
+    diag[y] = -s;
+  }
+  return 0;
+}
+
+/* Density row (eq. density_linear_system): b = a^T V^+ C, with the kernel moments
+   a_alpha = (1/h_c^3) int_cell (x - y)^alpha dx / alpha! of the NGP kernel (the
+   characteristic function of the node's own cell, edge h_c).  Reading: the
+   Taylor terms carry 1/alpha!, so a^T d rho~ is the cell average of the Taylor
+   polynomial; odd moments vanish and a_alpha = prod_d mu(alpha_d) / alpha! with
+   mu(e) = (h_c/2)^e / (e + 1). */
+int apco_density_rows(const apco_cloud *C, double *bw, double *bdiag) {
+  int p = C->p;
+  int32_t al[3 * MAXP];
+  apco_monomials(C->P.order, al);
+  static double X[MAXP * MAXM];
+  for (int64_t y = 0; y < C->n; y++) {
+    int m;
+    double hp;
+    int rc = node_fit(C, y, X, &m, &hp);
+    if (rc) return rc;
+    double hc = C->P.L / ldexp(1.0, C->cells[C->node_cell[y]].level);
+    double coef[MAXP];
+    for (int i = 0; i < p; i++) {
+      const int32_t *a = &al[3 * i];
+      coef[i] = 0.0;
+      if ((a[0] | a[1] | a[2]) & 1) continue;
+      double mom = 1.0;
+      for (int d = 0; d < 3; d++) mom *= ipow(hc / 2.0, a[d]) / (double)(a[d] + 1) / factorial(a[d]);
+      coef[i] = mom / ipow(hp, a[0] + a[1] + a[2]);
+    }
+    double s = 0.0;
+    int32_t a0 = C->st_off[y];
+    for (int j = 0; j < m; j++) {
+      double v = 0.0;
+      for (int i = 0; i < p; i++) v += coef[i] * X[i * m + j];
+      bw[a0 + j] = v;
+      s += v;
+    }
+    bdiag[y] = 1.0 - s;
+  }
+  return 0;
+}
+
+/* rho_M(y_j) = (1/h_c^3) sum_{particles in cell j} q_i (eq. density_apcloud with
+   the NGP kernel); summed in sorted order.  q == NULL: each particle carries 1/N
+   (total charge 1, Sec. 2) and the sum is count * (1/N). */
+int apco_deposit(const apco_cloud *C, const double *q, double *rho_M) {
+  double q0 = 1.0 / (double)C->N;
+  for (int64_t j = 0; j < C->n; j++) {
+    const ocell *c = &C->cells[C->node_cell[j]];
+    double sum = 0.0;
+    if (q) {
+      for (int64_t s = c->first; s < c->first + c->count; s++) sum += q[C->perm[s]];
+    } else {
+      sum = (double)c->count * q0;
+    }
+    double hc = C->P.L / ldexp(1.0, c->level);
+    rho_M[j] = sum / (hc * hc * hc);
+  }
+  /* boundary nodes carry their owner's value (reading: boundary density is not
+     solved for; it enters the rhs) */
+  for (int64_t b = 0; b < C->nb; b++) rho_M[C->n + b] = rho_M[C->bowner[b]];
+  return 0;
+}
+
+/* ------------------------------------------------------------------ */
+/* Krylov solver on rows (diag, w) over the interior unknowns. */
+
+static void rows_matvec(const apco_cloud *C, const double *diag, const double *w,
+                        const double *x, double *y) {
+  for (int64_t i = 0; i < C->n; i++) {
+    double s = diag[i] * x[i];
+    for (int32_t e = C->st_off[i]; e < C->st_off[i + 1]; e++) {
+      int32_t j = C->st[e];
+      if (j < C->n) s += w[e] * x[j];
+    }
+    y[i] = s;
+  }
+}
+
+static double dot(const double *a, const double *b, int64_t n) {
+  double s = 0.0;
+  for (int64_t i = 0; i < n; i++) s += a[i] * b[i];
+  return s;
+}
+
+/* BiCGSTAB (van der Vorst), x0 = 0, shadow residual r^ = r0, optional right
+   Jacobi preconditioning; stops when the recursive ||r||/||b|| <= tol and the
+   recomputed true residual agrees; restarts from the true residual on
+   breakdown or disagreement. */
+static int bicgstab(const apco_cloud *C, const double *diag, const double *w, const double *b,
+                    double *x, double tol, int maxit, int precond, apco_stats *st) {
+  int64_t n = C->n;
+  double *r = calloc((size_t)n, sizeof(double)), *rh = calloc((size_t)n, sizeof(double)),
+         *pv = calloc((size_t)n, sizeof(double)), *v = calloc((size_t)n, sizeof(double)),
+         *s = calloc((size_t)n, sizeof(double)), *t = calloc((size_t)n, sizeof(double)),
+         *ph = calloc((size_t)n, sizeof(double)), *sh = calloc((size_t)n, sizeof(double));
+  if (!r || !rh || !pv || !v || !s || !t || !ph || !sh) {
+    free(r); free(rh); free(pv); free(v); free(s); free(t); free(ph); free(sh);
+    return APCO_ENOMEM;
+  }
+  for (int64_t i = 0; i < n; i++) x[i] = 0.0;
+  double bn = sqrt(dot(b, b, n));
+  int it = 0, status = APCO_ENOCONV;
+  double rel = 0.0, relt = 0.0;
+  if (bn == 0.0) {
+    status = 0;
+    goto done;
+  }
+  memcpy(r, b, (size_t)n * sizeof(double));
+  for (;;) {
+    /* (re)start */
+    memcpy(rh, r, (size_t)n * sizeof(double));
+    for (int64_t i = 0; i < n; i++) pv[i] = v[i] = 0.0;
+    double rho_old = 1.0, alpha = 1.0, omega = 1.0;
+    int restart = 0;
+    while (it < maxit && !restart) {
+      it++;
+      double rho = dot(rh, r, n);
+      if (rho == 0.0 || !isfinite(rho)) {
+        restart = 1;
+        break;
+      }
+      double beta = (rho / rho_old) * (alpha / omega);
+      for (int64_t i = 0; i < n; i++) pv[i] = r[i] + beta * (pv[i] - omega * v[i]);
+      for (int64_t i = 0; i < n; i++) ph[i] = precond ? pv[i] / diag[i] : pv[i];
+      rows_matvec(C, diag, w, ph, v);
+      double rv = dot(rh, v, n);
+      if (rv == 0.0 || !isfinite(rv)) {
+        restart = 1;
+        break;
+      }
+      alpha = rho / rv;
+      for (int64_t i = 0; i < n; i++) s[i] = r[i] - alpha * v[i];
+      for (int64_t i = 0; i < n; i++) sh[i] = precond ? s[i] / diag[i] : s[i];
+      rows_matvec(C, diag, w, sh, t);
+      double tt = dot(t, t, n);
+      omega = tt > 0.0 ? dot(t, s, n) / tt : 0.0;
+      for (int64_t i = 0; i < n; i++) x[i] += alpha * ph[i] + omega * sh[i];
+      for (int64_t i = 0; i < n; i++) r[i] = s[i] - omega * t[i];
+      rho_old = rho;
+      rel = sqrt(dot(r, r, n)) / bn;
+      if (rel <= tol || omega == 0.0) {
+        /* true residual */
+        rows_matvec(C, diag, w, x, t);
+        for (int64_t i = 0; i < n; i++) r[i] = b[i] - t[i];
+        relt = sqrt(dot(r, r, n)) / bn;
+        if (relt <= tol) {
+          status = 0;
+          goto done;
+        }
+        restart = 1;
+      }
+    }
+    if (it >= maxit) break;
+    if (restart) {
+      rows_matvec(C, diag, w, x, t);
+      for (int64_t i = 0; i < n; i++) r[i] = b[i] - t[i];
+    }
+  }
+done:
+  if (bn != 0.0) {
+    rows_matvec(C, diag, w, x, t);
+    for (int64_t i = 0; i < n; i++) r[i] = b[i] - t[i];
+    relt = sqrt(dot(r, r, n)) / bn;
+  }
+  if (st) {
+    st->iters = it;
+    st->status = status;
+    st->rel_resid = rel;
+    st->rel_resid_true = relt;
+  }
+  free(r); free(rh); free(pv); free(v); free(s); free(t); free(ph); free(sh);
+  return 0;
+}
+
+static void bnd_rhs(const apco_cloud *C, const double *w, const double *bval, double *rhs) {
+  for (int64_t i = 0; i < C->n; i++)
+    for (int32_t e = C->st_off[i]; e < C->st_off[i + 1]; e++) {
+      int32_t j = C->st[e];
+      if (j >= C->n) rhs[i] -= w[e] * bval[j - C->n];
+    }
+}
+
+int apco_density_solve(const apco_cloud *C, const double *rho_M, double *rho_t, double tol,
+                       int maxit, int precond, apco_stats *st) {
+  int64_t n = C->n, nnz = C->st_off[n];
+  double *bw = malloc((size_t)(nnz + 1) * sizeof(double));
+  double *bd = malloc((size_t)(n + 1) * sizeof(double));
+  double *rhs = malloc((size_t)(n + 1) * sizeof(double));
+  if (!bw || !bd || !rhs) {
+    free(bw); free(bd); free(rhs);
+    return APCO_ENOMEM;
+  }
+  int rc = apco_density_rows(C, bw, bd);
+  if (!rc) {
+    for (int64_t i = 0; i < n; i++) rhs[i] = rho_M[i];
+    bnd_rhs(C, bw, rho_M + n, rhs);
+    rc = bicgstab(C, bd, bw, rhs, rho_t, tol, maxit, precond, st);
+    for (int64_t b = 0; b < C->nb; b++) rho_t[n + b] = rho_M[n + b];
+  }
+  free(bw); free(bd); free(rhs);
+  return rc;
+}
+
+static int poisson_system(const apco_cloud *C, const double *rho_t, const double *g, double **w,
+                          double **diag, double **rhs) {
+  int64_t n = C->n, nnz = C->st_off[n];
+  *w = malloc((size_t)(nnz + 1) * sizeof(double));
+  *diag = malloc((size_t)(n + 1) * sizeof(double));
+  *rhs = malloc((size_t)(n + 1) * sizeof(double));
+  if (!*w || !*diag || !*rhs) return APCO_ENOMEM;
+  int rc = apco_assemble(C, *w, *diag);
+  if (rc) return rc;
+  for (int64_t i = 0; i < n; i++) (*rhs)[i] = C->P.poisson_c * rho_t[i];
+  if (g) bnd_rhs(C, *w, g, *rhs);
+  return 0;
+}
+
+int apco_poisson_solve(const apco_cloud *C, const double *rho_t, const double *g, double *phi,
+                       double tol, int maxit, int precond, apco_stats *st) {
+  double *w = NULL, *diag = NULL, *rhs = NULL;
+  int rc = poisson_system(C, rho_t, g, &w, &diag, &rhs);
+  if (!rc) rc = bicgstab(C, diag, w, rhs, phi, tol, maxit, precond, st);
+  if (!rc)
+    for (int64_t b = 0; b < C->nb; b++) phi[C->n + b] = g ? g[b] : 0.0;
+  free(w); free(diag); free(rhs);
+  return rc;
+}
+
+int apco_poisson_lu(const apco_cloud *C, const double *rho_t, const double *g, double *phi) {
+  int64_t n = C->n;
+  double *w = NULL, *diag = NULL, *rhs = NULL;
+  int rc = poisson_system(C, rho_t, g, &w, &diag, &rhs);
+  double *A = rc ? NULL : calloc((size_t)(n * n), sizeof(double));
+  if (!rc && !A) rc = APCO_ENOMEM;
+  if (!rc) {
+    for (int64_t i = 0; i < n; i++) {
+      A[i * n + i] = diag[i];
+      for (int32_t e = C->st_off[i]; e < C->st_off[i + 1]; e++)
+        if (C->st[e] < n) A[i * n + C->st[e]] += w[e];
+    }
+    /* Gaussian elimination with partial pivoting */
+    for (int64_t k = 0; k < n && !rc; k++) {
+      int64_t piv = k;
+      for (int64_t i = k + 1; i < n; i++)
+        if (fabs(A[i * n + k]) > fabs(A[piv * n + k])) piv = i;
+      if (A[piv * n + k] == 0.0) {
+        rc = APCO_EINVAL;
+        break;
+      }
+      if (piv != k) {
+        for (int64_t j = 0; j < n; j++) {
+          double t = A[k * n + j];
+          A[k * n + j] = A[piv * n + j];
+          A[piv * n + j] = t;
+        }
+        double t = rhs[k];
+        rhs[k] = rhs[piv];
+        rhs[piv] = t;
+      }
+      for (int64_t i = k + 1; i < n; i++) {
+        double f = A[i * n + k] / A[k * n + k];
+        if (f == 0.0) continue;
+        for (int64_t j = k; j < n; j++) A[i * n + j] -= f * A[k * n + j];
+        rhs[i] -= f * rhs[k];
+      }
+    }
+    for (int64_t i = n - 1; i >= 0 && !rc; i--) {
+      double s = rhs[i];
+      for (int64_t j = i + 1; j < n; j++) s -= A[i * n + j] * phi[j];
+      phi[i] = s / A[i * n + i];
+    }
+    for (int64_t b = 0; b < C->nb; b++) phi[n + b] = g ? g[b] : 0.0;
+  }
+  free(A); free(w); free(diag); free(rhs);
+  return rc;
+}
+
+int apco_apply_laplacian(const apco_cloud *C, const double *f, double *out) {
+  int64_t n = C->n, nnz = C->st_off[n];
+  double *w = malloc((size_t)(nnz + 1) * sizeof(double));
+  double *diag = malloc((size_t)(n + 1) * sizeof(double));
+  if (!w || !diag) {
+    free(w); free(diag);
+    return APCO_ENOMEM;
+  }
+  int rc = apco_assemble(C, w, diag);
+  if (!rc)
+    for (int64_t i = 0; i < n; i++) {
+      double s = diag[i] * f[i];
+      for (int32_t e = C->st_off[i]; e < C->st_off[i + 1]; e++) s += w[e] * f[C->st[e]];
+      out[i] = s;
+    }
+  free(w); free(diag);
+  return rc;
+}
+
+/* d^alpha f(y_j) = h^{-|alpha|} sum_i X[alpha][i] (f_i - f_j)  (Sec. 3.1) */
+int apco_node_derivs(const apco_cloud *C, const double *f, double *Dout) {
+  int p = C->p;
+  int32_t al[3 * MAXP];
+  apco_monomials(C->P.order, al);
+  static double X[MAXP * MAXM];
+  for (int64_t y = 0; y < C->n; y++) {
+    int m;
+    double hp;
+    int rc = node_fit(C, y, X, &m, &hp);
+    if (rc) return rc;
+    int32_t a = C->st_off[y];
+    for (int i = 0; i < p; i++) {
+      double s = 0.0;
+      for (int j = 0; j < m; j++) s += X[i * m + j] * (f[C->st[a + j]] - f[y]);
+      Dout[y * p + i] = s / ipow(hp, al[3 * i] + al[3 * i + 1] + al[3 * i + 2]);
+    }
+  }
+  return 0;
+}
+
+/* Taylor interpolation (Sec. 3.2 step 3): a particle in leaf j takes
+   phi(p) = phi_j + sum_alpha d^alpha phi_j delta^alpha / alpha!  and its gradient,
+   delta = p - y_j (reading: the leaf containing the particle interpolates it). */
+int apco_interpolate(const apco_cloud *C, const double *phi, const double *xyz, double *phi_p,
+                     double *grad_p) {
+  int p = C->p;
+  int64_t n = C->n, N = C->N;
+  int32_t al[3 * MAXP];
+  apco_monomials(C->P.order, al);
+  double *Dv = malloc((size_t)n * p * sizeof(double));
+  if (!Dv) return APCO_ENOMEM;
+  int rc = apco_node_derivs(C, phi, Dv);
+  if (rc) {
+    free(Dv);
+    return rc;
+  }
+  for (int64_t j = 0; j < n; j++) {
+    const ocell *c = &C->cells[C->node_cell[j]];
+    double yc[3];
+    for (int d = 0; d < 3; d++) yc[d] = C->P.lo[d] + C->unit * (double)C->crd[3 * j + d];
+    const double *Dj = &Dv[j * p];
+    for (int64_t s = c->first; s < c->first + c->count; s++) {
+      int64_t i = C->perm[s];
+      double dl[3];
+      for (int d = 0; d < 3; d++) dl[d] = xyz[d * N + i] - yc[d];
+      double v = phi[j], g[3] = {0.0, 0.0, 0.0};
+      for (int a = 0; a < p; a++) {
+        const int32_t *A = &al[3 * a];
+        v += Dj[a] * mono(A, dl[0], dl[1], dl[2]);
+        for (int d = 0; d < 3; d++) {
+          if (A[d] == 0) continue;
+          int32_t B[3] = {A[0], A[1], A[2]};
+          B[d] -= 1;
+          g[d] += Dj[a] * mono(B, dl[0], dl[1], dl[2]);
+        }
+      }
+      phi_p[i] = v;
+      for (int d = 0; d < 3; d++) grad_p[d * N + i] = g[d];
+    }
+  }
+  free(Dv);
+  return 0;
+}

@@ -1,0 +1,117 @@
+/*
+ * apc_oracle.h -- plain, slow, FP64 CPU oracle of the AP-Cloud field solve
+ * (Wang, Samulyak, Jiao, Yu, "AP-Cloud: Adaptive Particle-in-Cloud Method for
+ * Optimal Solutions to Vlasov-Poisson Equation").
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test suite, the smoke check and the CPU
+ * baseline leg of the benchmark may load this library.  It shares no source
+ * with the HIP library (no headers, helpers or tables); the two agree only
+ * through the paper and the readings written down beside each function.
+ *
+ * All pointers are host pointers.  All functions return 0 on success and a
+ * negative APCO_E* code on failure.  Node numbering: interior nodes (octree
+ * leaves) 0..n-1 in ascending Morton order of their minimum corner, then
+ * boundary nodes n..n+nb-1 ordered by (owner node, face id), face ids
+ * 0..5 = -x,+x,-y,+y,-z,+z.  Integer node coordinates are in units of
+ * L * 2^-(max_depth+1) measured from lo (cell centres are odd multiples).
+ */
+#ifndef APC_ORACLE_H
+#define APC_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define APCO_OK 0
+#define APCO_EINVAL (-1)
+#define APCO_ENOMEM (-2)
+#define APCO_EDOMAIN (-4)
+#define APCO_ESTENCIL (-5)
+#define APCO_ENOCONV 1
+
+typedef struct {
+  double lo[3];   /* domain Omega = [lo, lo+L]^3 */
+  double L;
+  int order;      /* GFD order k: 2 or 4 */
+  double c;       /* error-balance tuning constant (Sec. 4.3, eq. errorbalance_implementation) */
+  int max_depth;  /* deepest octree level, <= 20 */
+  int ring_min;   /* first ring searched for a stencil (2 for k=2, 3 for k=4) */
+  int ring_max;   /* last ring searched (5, Sec. 4.3) */
+  int m_cap;      /* stencil size cap (40 for k=2, 56 for k=4); hard cap 64 */
+  double poisson_c; /* Delta phi = c rho (eq. Poisson) */
+} apco_params;
+
+typedef struct {
+  int iters;
+  int status;           /* 0 converged, APCO_ENOCONV otherwise */
+  double rel_resid;     /* recursive ||r||/||b|| at exit */
+  double rel_resid_true;/* ||b - A x|| / ||b|| recomputed at exit */
+} apco_stats;
+
+typedef struct apco_cloud apco_cloud;
+
+/* Number of fitted derivative unknowns p = C(k+3,3) - 1 (9 for k=2, 34 for k=4). */
+int apco_num_unknowns(int order);
+/* Multi-index table of the fitted unknowns in column order (p x 3 ints). */
+int apco_monomials(int order, int32_t *alpha);
+/* Refinement thresholds T_l = (c 2^l / L)^(2k-2), l = 0..max_depth. */
+int apco_thresholds(const apco_params *P, double *T);
+
+/* Build octree, node set, boundary nodes and GFD stencils from N particles
+   (xyz: 3 x N structure of arrays). */
+int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cloud **out);
+void apco_destroy(apco_cloud *C);
+int apco_info(const apco_cloud *C, int64_t *n, int64_t *nb, int64_t *nnz, int64_t *n_opened,
+              int64_t *ncells);
+/* perm[N] (sorted position -> original index), node codes/levels/particle ranges,
+   boundary owner/face, stencil CSR (off-diagonal neighbours only). Any pointer may be NULL. */
+int apco_get_nodes(const apco_cloud *C, int64_t *perm, uint64_t *code, int32_t *level,
+                   int64_t *first, int64_t *count, int32_t *bowner, int32_t *bface,
+                   int32_t *st_off, int32_t *st_idx, int32_t *st_ring);
+/* Integer coordinates of all n+nb nodes, 3 x (n+nb) SoA. */
+int apco_node_coords(const apco_cloud *C, int32_t *ixyz);
+/* All cells of the queue Q in creation order: level, integer index (3), particle count,
+   opened flag (0 leaf, 1 opened by the criterion, 2 opened for 2:1 balance). */
+int apco_get_cells(const apco_cloud *C, int32_t *level, int32_t *ijk, int64_t *count,
+                   int32_t *opened);
+/* 1-ring adjacency of interior nodes (incl. their boundary nodes): offsets n+1, idx. */
+int apco_ring1(const apco_cloud *C, int32_t *off, int32_t *idx, int64_t cap);
+
+/* Weighted least-squares GFD fit on an explicit stencil (Sec. 3.1): delta is m x 3
+   (row-major) of neighbour offsets; returns X (p x m, row-major) with
+   h^{|alpha|} d^alpha f(y0) ~= sum_j X[alpha][j] (f_j - f_0), the stencil scale
+   h = max |delta| and the R-diagonal ratio min|R_ii| / max|R_ii|. */
+int apco_wls_fit(int order, int m, const double *delta, double *X, double *h, double *ratio);
+
+/* Poisson rows: off-diagonal weights w (nnz, aligned with the stencil CSR) and the
+   diagonal (n), so that (L f)_i = diag_i f_i + sum_j w_ij f_j. */
+int apco_assemble(const apco_cloud *C, double *w, double *diag);
+/* Density rows B (eq. density_linear_system), same layout. */
+int apco_density_rows(const apco_cloud *C, double *bw, double *bdiag);
+/* NGP deposit (Sec. 5.1 kernel choice): rho_M for all n+nb nodes (boundary node takes
+   its owner's value).  q may be NULL: every particle then carries 1/N. */
+int apco_deposit(const apco_cloud *C, const double *q, double *rho_M);
+/* Solve B rho~ = rho_M over interior nodes (boundary values moved to the rhs).
+   rho_M, rho_t: n+nb. precond: 0 none, 1 Jacobi (right). */
+int apco_density_solve(const apco_cloud *C, const double *rho_M, double *rho_t, double tol,
+                       int maxit, int precond, apco_stats *st);
+/* Solve the GFD Poisson system for phi at interior nodes with phi = g on boundary
+   nodes (g may be NULL: zero).  rho_t: n (or n+nb); phi: n+nb out. */
+int apco_poisson_solve(const apco_cloud *C, const double *rho_t, const double *g, double *phi,
+                       double tol, int maxit, int precond, apco_stats *st);
+/* Same system solved by dense LU with partial pivoting (small n only). */
+int apco_poisson_lu(const apco_cloud *C, const double *rho_t, const double *g, double *phi);
+/* Apply the Poisson operator: out_i = (L f)_i for interior i, f over n+nb nodes. */
+int apco_apply_laplacian(const apco_cloud *C, const double *f, double *out);
+/* Scaled-back derivatives d^alpha f at every interior node (n x p, row-major). */
+int apco_node_derivs(const apco_cloud *C, const double *f, double *D);
+/* Taylor interpolation of phi and grad phi to the particles, original order.
+   grad: 3 x N SoA. */
+int apco_interpolate(const apco_cloud *C, const double *phi, const double *xyz, double *phi_p,
+                     double *grad_p);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,254 @@
+"""ctypes binding of the C oracle (oracle/apc_oracle.c).  Test infrastructure only."""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "apc_oracle.c")
+_LIB = os.path.join(_HERE, "libapc_oracle.so")
+_lib = None
+
+ERRORS = {0: "ok", -1: "invalid argument", -2: "out of memory", -4: "particle outside domain",
+          -5: "no acceptable stencil", 1: "not converged"}
+
+
+def build_oracle_lib() -> str:
+    """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
+    cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
+           "-o", _LIB, _SRC, "-lm"]
+    subprocess.run(cmd, check=True)
+    return _LIB
+
+
+class _Params(ct.Structure):
+    _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
+                ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
+                ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double)]
+
+
+class _Stats(ct.Structure):
+    _fields_ = [("iters", ct.c_int), ("status", ct.c_int), ("rel_resid", ct.c_double),
+                ("rel_resid_true", ct.c_double)]
+
+
+def _load():
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+        build_oracle_lib()
+    lib = ct.CDLL(_LIB)
+    P = ct.c_void_p
+    lib.apco_build_cloud.argtypes = [ct.POINTER(_Params), P, ct.c_int64, ct.POINTER(ct.c_void_p)]
+    lib.apco_destroy.argtypes = [P]
+    lib.apco_destroy.restype = None
+    lib.apco_info.argtypes = [P] + [ct.POINTER(ct.c_int64)] * 5
+    lib.apco_get_nodes.argtypes = [P] * 11
+    lib.apco_node_coords.argtypes = [P, P]
+    lib.apco_get_cells.argtypes = [P] * 5
+    lib.apco_ring1.argtypes = [P, P, P, ct.c_int64]
+    lib.apco_wls_fit.argtypes = [ct.c_int, ct.c_int, P, P, P, P]
+    lib.apco_assemble.argtypes = [P, P, P]
+    lib.apco_density_rows.argtypes = [P, P, P]
+    lib.apco_deposit.argtypes = [P, P, P]
+    lib.apco_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.c_int,
+                                       ct.POINTER(_Stats)]
+    lib.apco_poisson_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int,
+                                       ct.POINTER(_Stats)]
+    lib.apco_poisson_lu.argtypes = [P, P, P, P]
+    lib.apco_apply_laplacian.argtypes = [P, P, P]
+    lib.apco_node_derivs.argtypes = [P, P, P]
+    lib.apco_interpolate.argtypes = [P, P, P, P, P]
+    lib.apco_num_unknowns.argtypes = [ct.c_int]
+    lib.apco_monomials.argtypes = [ct.c_int, P]
+    lib.apco_thresholds.argtypes = [ct.POINTER(_Params), P]
+    _lib = lib
+    return lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ct.c_void_p)
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise RuntimeError(f"oracle {what}: {ERRORS.get(rc, rc)} ({rc})")
+    return rc
+
+
+def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
+                ring_max=5, m_cap=None, poisson_c=1.0):
+    P = _Params()
+    P.lo[:] = lo
+    P.L = L
+    P.order = order
+    P.c = c
+    P.max_depth = max_depth
+    P.ring_min = ring_min if ring_min is not None else (2 if order == 2 else 3)
+    P.ring_max = ring_max
+    P.m_cap = m_cap if m_cap is not None else (40 if order == 2 else 56)
+    P.poisson_c = poisson_c
+    return P
+
+
+def num_unknowns(order: int) -> int:
+    return _load().apco_num_unknowns(order)
+
+
+def monomials(order: int) -> np.ndarray:
+    p = num_unknowns(order)
+    a = np.zeros((p, 3), dtype=np.int32)
+    _check(_load().apco_monomials(order, _ptr(a)), "monomials")
+    return a
+
+
+def thresholds(**kw) -> np.ndarray:
+    P = make_params(**kw)
+    T = np.zeros(P.max_depth + 1)
+    _load().apco_thresholds(ct.byref(P), _ptr(T))
+    return T
+
+
+def wls_fit(order: int, delta: np.ndarray):
+    """X (p x m), h, R-diagonal ratio for an explicit stencil delta (m x 3)."""
+    d = np.ascontiguousarray(delta, dtype=np.float64)
+    m = d.shape[0]
+    p = num_unknowns(order)
+    X = np.zeros((p, m))
+    h = ct.c_double()
+    r = ct.c_double()
+    _check(_load().apco_wls_fit(order, m, _ptr(d), _ptr(X), ct.byref(h), ct.byref(r)), "wls_fit")
+    return X, h.value, r.value
+
+
+class OracleCloud:
+    """An oracle node cloud built from particles (3 x N float64)."""
+
+    def __init__(self, xyz: np.ndarray, **params):
+        self.lib = _load()
+        self.params = make_params(**params)
+        self.xyz = np.ascontiguousarray(xyz, dtype=np.float64)
+        assert self.xyz.ndim == 2 and self.xyz.shape[0] == 3
+        self.N = self.xyz.shape[1]
+        h = ct.c_void_p()
+        _check(self.lib.apco_build_cloud(ct.byref(self.params), _ptr(self.xyz), self.N,
+                                         ct.byref(h)), "build_cloud")
+        self.h = h
+        v = [ct.c_int64() for _ in range(5)]
+        self.lib.apco_info(self.h, *[ct.byref(x) for x in v])
+        self.n, self.nb, self.nnz, self.n_opened, self.ncells = [x.value for x in v]
+        self.order = self.params.order
+        self.p = num_unknowns(self.order)
+        self.L = self.params.L
+        self.lo = np.array(self.params.lo[:])
+        self.max_depth = self.params.max_depth
+        self.unit = self.L / 2.0 ** (self.max_depth + 1)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.apco_destroy(self.h)
+            self.h = None
+
+    def nodes(self):
+        n, nb, nnz = self.n, self.nb, self.nnz
+        out = dict(perm=np.zeros(self.N, np.int64), code=np.zeros(n, np.uint64),
+                   level=np.zeros(n, np.int32), first=np.zeros(n, np.int64),
+                   count=np.zeros(n, np.int64), bowner=np.zeros(nb, np.int32),
+                   bface=np.zeros(nb, np.int32), st_off=np.zeros(n + 1, np.int32),
+                   st_idx=np.zeros(nnz, np.int32), st_ring=np.zeros(n, np.int32))
+        self.lib.apco_get_nodes(self.h, *[_ptr(out[k]) for k in
+                                          ["perm", "code", "level", "first", "count", "bowner",
+                                           "bface", "st_off", "st_idx", "st_ring"]])
+        return out
+
+    def coords(self) -> np.ndarray:
+        a = np.zeros((3, self.n + self.nb), np.int32)
+        self.lib.apco_node_coords(self.h, _ptr(a))
+        return a
+
+    def positions(self) -> np.ndarray:
+        return self.lo[:, None] + self.unit * self.coords().astype(np.float64)
+
+    def cells(self):
+        nc = self.ncells
+        lv = np.zeros(nc, np.int32)
+        ijk = np.zeros((nc, 3), np.int32)
+        cnt = np.zeros(nc, np.int64)
+        op = np.zeros(nc, np.int32)
+        self.lib.apco_get_cells(self.h, _ptr(lv), _ptr(ijk), _ptr(cnt), _ptr(op))
+        return dict(level=lv, ijk=ijk, count=cnt, opened=op)
+
+    def ring1(self):
+        off = np.zeros(self.n + 1, np.int32)
+        idx = np.zeros(24 * self.n + 6, np.int32)
+        _check(self.lib.apco_ring1(self.h, _ptr(off), _ptr(idx), idx.size), "ring1")
+        return off, idx[: off[-1]].copy()
+
+    def assemble(self):
+        w = np.zeros(self.nnz)
+        d = np.zeros(self.n)
+        _check(self.lib.apco_assemble(self.h, _ptr(w), _ptr(d)), "assemble")
+        return w, d
+
+    def density_rows(self):
+        w = np.zeros(self.nnz)
+        d = np.zeros(self.n)
+        _check(self.lib.apco_density_rows(self.h, _ptr(w), _ptr(d)), "density_rows")
+        return w, d
+
+    def deposit(self, q=None):
+        r = np.zeros(self.n + self.nb)
+        qq = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        _check(self.lib.apco_deposit(self.h, _ptr(qq), _ptr(r)), "deposit")
+        return r
+
+    def density_solve(self, rho_M, tol=1e-12, maxit=10000, precond=0):
+        rho_M = np.ascontiguousarray(rho_M, dtype=np.float64)
+        out = np.zeros(self.n + self.nb)
+        st = _Stats()
+        _check(self.lib.apco_density_solve(self.h, _ptr(rho_M), _ptr(out), tol, maxit, precond,
+                                           ct.byref(st)), "density_solve")
+        return out, dict(iters=st.iters, status=st.status, rel_resid=st.rel_resid,
+                         rel_resid_true=st.rel_resid_true)
+
+    def poisson_solve(self, rho_t, g=None, tol=1e-12, maxit=20000, precond=1):
+        rho_t = np.ascontiguousarray(rho_t, dtype=np.float64)
+        gg = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
+        out = np.zeros(self.n + self.nb)
+        st = _Stats()
+        _check(self.lib.apco_poisson_solve(self.h, _ptr(rho_t), _ptr(gg), _ptr(out), tol, maxit,
+                                           precond, ct.byref(st)), "poisson_solve")
+        return out, dict(iters=st.iters, status=st.status, rel_resid=st.rel_resid,
+                         rel_resid_true=st.rel_resid_true)
+
+    def poisson_lu(self, rho_t, g=None):
+        rho_t = np.ascontiguousarray(rho_t, dtype=np.float64)
+        gg = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
+        out = np.zeros(self.n + self.nb)
+        _check(self.lib.apco_poisson_lu(self.h, _ptr(rho_t), _ptr(gg), _ptr(out)), "poisson_lu")
+        return out
+
+    def apply_laplacian(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros(self.n)
+        _check(self.lib.apco_apply_laplacian(self.h, _ptr(f), _ptr(out)), "apply_laplacian")
+        return out
+
+    def node_derivs(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        out = np.zeros((self.n, self.p))
+        _check(self.lib.apco_node_derivs(self.h, _ptr(f), _ptr(out)), "node_derivs")
+        return out
+
+    def interpolate(self, phi, xyz=None):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        xyz = self.xyz if xyz is None else np.ascontiguousarray(xyz, dtype=np.float64)
+        pp = np.zeros(self.N)
+        gp = np.zeros((3, self.N))
+        _check(self.lib.apco_interpolate(self.h, _ptr(phi), _ptr(xyz), _ptr(pp), _ptr(gp)),
+               "interpolate")
+        return pp, gp

@@ -1,0 +1,9 @@
+"""Seeded synthetic inputs shared by the HIP path's tests/bench and the CPU oracle.
+
+This package holds only random-number draws and array shapes.  It contains none of
+the method's arithmetic (no keys, no tree, no stencils), so it may be imported by
+both sides without coupling them.
+"""
+from .beam_halo import beam_halo, batch_specs, uniform_lattice_points, CONFIGS
+
+__all__ = ["beam_halo", "batch_specs", "uniform_lattice_points", "CONFIGS"]

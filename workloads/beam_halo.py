@@ -1,0 +1,83 @@
+"""Beam-with-halo particle clouds (numpy PCG64), the synthetic stand-in for the
+paper's Gaussian-beam-with-halo workloads (Sec. 5.1, eq. GaussianDist; Sec. 5.2).
+
+Recipe (all in the unit cube [0,1)^3, structure-of-arrays float64, shape (3, N)):
+  * core: round(N*(1-halo_frac)) points ~ N(centre, diag(sigma^2)), each point
+    re-drawn until it lies inside [0,1)^3;
+  * halo: the remaining points with radius r, r^3 ~ U[r_in^3, r_out^3], about the
+    centre, in an isotropic direction (normalised Gaussian triple).
+Draw order: the core block first, then the halo block, from one Generator.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+CENTRE = (0.5, 0.5, 0.5)
+
+# Named workloads: particle count, seed, core sigma, halo fraction, octree depth,
+# GFD order and the error-balance constant used with them.
+CONFIGS = {
+    "beam_halo_1e5": dict(N=100_000, seed=1, sigma=(0.08, 0.08, 0.08), halo_frac=0.05,
+                          max_depth=6, order=2, c=0.35),
+    "beam_halo_1e7": dict(N=10_000_000, seed=2, sigma=(0.08, 0.08, 0.08), halo_frac=0.05,
+                          max_depth=10, order=2, c=0.04),
+    "beam_halo_1e8_k4": dict(N=100_000_000, seed=5, sigma=(0.05, 0.05, 0.2), halo_frac=0.03,
+                             max_depth=12, order=4, c=0.007),
+}
+
+
+def _core(rng: np.random.Generator, n: int, sigma) -> np.ndarray:
+    sig = np.asarray(sigma, dtype=np.float64).reshape(3, 1)
+    cen = np.asarray(CENTRE, dtype=np.float64).reshape(3, 1)
+    out = np.empty((3, n), dtype=np.float64)
+    todo = np.arange(n)
+    while todo.size:
+        pts = cen + sig * rng.standard_normal((3, todo.size))
+        ok = np.all((pts >= 0.0) & (pts < 1.0), axis=0)
+        out[:, todo[ok]] = pts[:, ok]
+        todo = todo[~ok]
+    return out
+
+
+def _halo(rng: np.random.Generator, n: int, r_in: float, r_out: float) -> np.ndarray:
+    cen = np.asarray(CENTRE, dtype=np.float64).reshape(3, 1)
+    u = rng.random(n)
+    r = np.cbrt(r_in ** 3 + u * (r_out ** 3 - r_in ** 3))
+    d = rng.standard_normal((3, n))
+    d /= np.linalg.norm(d, axis=0, keepdims=True)
+    return cen + r * d
+
+
+def beam_halo(N: int, seed: int, sigma=(0.08, 0.08, 0.08), halo_frac: float = 0.05,
+              shell=(0.25, 0.4)) -> np.ndarray:
+    """Return a (3, N) float64 SoA array of particle positions in [0,1)^3."""
+    rng = np.random.default_rng(seed)
+    n_core = int(round(N * (1.0 - halo_frac)))
+    n_halo = N - n_core
+    core = _core(rng, n_core, sigma)
+    halo = _halo(rng, n_halo, shell[0], shell[1])
+    xyz = np.ascontiguousarray(np.concatenate([core, halo], axis=1))
+    return xyz
+
+
+def batch_specs(master_seed: int = 3, count: int = 64):
+    """Per-cloud parameters of the many-cloud workload: N log-uniform in [1e4, 1e6],
+    core sigma in [0.05, 0.15], halo fraction in [0.01, 0.1]; cloud i's positions
+    use seed 3000 + i."""
+    rng = np.random.default_rng(master_seed)
+    specs = []
+    for i in range(count):
+        n = int(round(10.0 ** rng.uniform(4.0, 6.0)))
+        s = float(rng.uniform(0.05, 0.15))
+        hf = float(rng.uniform(0.01, 0.1))
+        specs.append(dict(N=n, seed=3000 + i, sigma=(s, s, s), halo_frac=hf))
+    return specs
+
+
+def uniform_lattice_points(depth: int) -> np.ndarray:
+    """One point at the centre of every cell of the uniform 2^depth grid on [0,1)^3,
+    shape (3, 8**depth).  Used to force a uniform octree."""
+    m = 1 << depth
+    g = (np.arange(m, dtype=np.float64) + 0.5) / m
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    return np.ascontiguousarray(np.stack([x.ravel(), y.ravel(), z.ravel()]))
