@@ -1,0 +1,218 @@
+#!/usr/bin/env python3
+"""Benchmark of the AP-Cloud field-solve hot path on one MI355X.
+
+A step is one pass of the whole path over the synthetic beam-with-halo cloud:
+build_cloud -> assemble_gfd -> deposit (NGP + density solve) -> solve (Poisson,
+BiCGSTAB to relative residual 1e-8) -> interpolate_force.  The reported value is
+nodes / (assembly time + Poisson solve time), from HIP events on the stream the
+library runs on, averaged over the timed steps.  Inputs are resident in HBM
+before the timed region starts.
+
+Prints one JSON line.  `--gpus N` with N > 1 is not supported (single-GPU build).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "nodes/s for GFD assembly+solve to 1e-8 resid; learned/mixed vs plain speedup"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol):
+    """Run warmup + timed steps; returns per-phase mean ms and the last cloud."""
+    stream = torch.cuda.current_stream()
+    names = ["build", "assemble", "deposit", "solve", "interpolate"]
+    acc = {k: 0.0 for k in names}
+    info = {}
+    t_wall = 0.0
+    kw = dict(order=cfg["order"], c=cfg["c"], max_depth=cfg["max_depth"], precision=precision)
+    for it in range(warmup + steps):
+        timed = it >= warmup
+        if timed and it == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev[0].record(stream)
+        cloud = apc.Cloud(xyz_d, **kw)
+        ev[1].record(stream)
+        cloud.assemble_gfd()
+        ev[2].record(stream)
+        rho_M, rho_t, std = cloud.deposit(tol=1e-10, maxit=2000)
+        ev[3].record(stream)
+        phi, st = cloud.solve(rho_t[:cloud.n], tol=tol, maxit=20000,
+                              precond=apc.APC_PRECOND_JACOBI)
+        ev[4].record(stream)
+        phi_p, grad_p = cloud.interpolate_force(phi)
+        ev[5].record(stream)
+        ev[5].synchronize()
+        if st["status"] != 0:
+            raise RuntimeError(f"solve did not converge: {st}")
+        if timed:
+            for k, name in enumerate(names):
+                acc[name] += ev[k].elapsed_time(ev[k + 1])
+        info = dict(n=cloud.n, nb=cloud.nb, nnz=cloud.nnz, iters=st["iters"],
+                    sweeps=st["sweeps"], rel_resid_true=st["rel_resid_true"],
+                    density_iters=std["iters"])
+        last = cloud if it == warmup + steps - 1 else None
+        if last is None:
+            cloud.close()
+    torch.cuda.synchronize()
+    t_wall = time.perf_counter() - t0
+    ms = {k: v / steps for k, v in acc.items()}
+    return ms, info, t_wall * 1000.0 / steps, last, phi
+
+
+def spmv_roofline(torch, cloud, reps, mixed):
+    """Average duration of the operator SpMV (the solver's dominant kernel) over
+    `reps` back-to-back launches, HIP events on the library's stream."""
+    stream = torch.cuda.current_stream()
+    f = torch.rand(cloud.n + cloud.nb, dtype=torch.float64, device="cuda")
+    for _ in range(5):
+        cloud.apply_operator(f)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        cloud.apply_operator(f)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    n, nnz = cloud.n, cloud.nnz
+    vbytes = 4 if mixed else 8
+    # algorithmic bytes: weights + column indices + row offsets + x (once) + y
+    byts = nnz * (vbytes + 4) + (n + 1) * 4 + n * 8 + n * 8
+    gbs = byts / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="k_apply<%s> (operator SpMV)" % ("V32A64" if mixed else "V64"),
+                avg_us=round(ms * 1e3, 2), bytes_per_launch=int(byts))
+
+
+def cpu_baseline(xyz, cfg, iters_full, n_sample_iters=20):
+    """The oracle (plain serial C, FP64) on the same cloud: assembly of all nodes
+    plus `n_sample_iters` BiCGSTAB iterations, the solve time scaled to the
+    iteration count of the plain FP64 GPU solve (same algorithm and matrix)."""
+    import numpy as np
+    from oracle.oracle import OracleCloud
+    t = time.perf_counter()
+    O = OracleCloud(xyz, order=cfg["order"], c=cfg["c"], max_depth=cfg["max_depth"])
+    t_build = time.perf_counter() - t
+    t = time.perf_counter()
+    w, d = O.assemble()
+    t_asm = time.perf_counter() - t
+    rt = O.deposit()  # rho_M stands in for rho~ (same magnitude; only timing matters)
+    t = time.perf_counter()
+    _, st = O.poisson_solve(rt[:O.n], tol=1e-30, maxit=n_sample_iters, precond=1)
+    t_it = (time.perf_counter() - t) / max(1, st["iters"])
+    t_solve = t_it * iters_full
+    val = O.n / (t_asm + t_solve)
+    return dict(value=round(val, 1), unit="nodes/s", cores=1, kind="oracle",
+                sample=(f"oracle on the same {O.n}-node cloud: assembly of all nodes "
+                        f"({t_asm:.2f} s) + {st['iters']} Jacobi-BiCGSTAB iterations "
+                        f"({t_it * 1e3:.1f} ms each) scaled to {iters_full} iterations; "
+                        f"oracle build {t_build:.1f} s not counted"))
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", default="beam_halo_1e7")
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--spmv-reps", type=int, default=50)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1603_04039_amd import apcloud as apc
+    from workloads import CONFIGS, beam_halo
+
+    apc.load_library()
+    cfg = CONFIGS[args.workload]
+    torch.cuda.set_device(0)
+    log(f"generating {args.workload}: N={cfg['N']}")
+    xyz = beam_halo(cfg["N"], seed=cfg["seed"], sigma=cfg["sigma"], halo_frac=cfg["halo_frac"])
+    xyz_d = torch.from_numpy(xyz).cuda()
+    torch.cuda.synchronize()
+
+    prec = apc.APC_MIXED if args.precision == "mixed" else apc.APC_FP64
+    log(f"timed steps ({args.precision}): warmup={args.warmup} steps={args.steps}")
+    ms, info, ms_step, cloud, phi = run_steps(apc, torch, xyz_d, cfg, prec, args.steps,
+                                              args.warmup, args.tol)
+    t_metric = (ms["assemble"] + ms["solve"]) * 1e-3
+    value = info["n"] / t_metric
+    log(f"{args.precision}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
+    roof = spmv_roofline(torch, cloud, args.spmv_reps, prec == apc.APC_MIXED)
+    log(f"spmv roofline: {roof}")
+    cloud.close()
+
+    plain = None
+    if prec == apc.APC_MIXED and not args.no_plain:
+        log("plain FP64 comparison")
+        ms64, info64, _, c64, _ = run_steps(apc, torch, xyz_d, cfg, apc.APC_FP64,
+                                            max(2, args.steps // 2), 1, args.tol)
+        c64.close()
+        v64 = info64["n"] / ((ms64["assemble"] + ms64["solve"]) * 1e-3)
+        plain = dict(nodes_per_s=round(v64, 1), iters=info64["iters"],
+                     assemble_ms=round(ms64["assemble"], 3), solve_ms=round(ms64["solve"], 3))
+        iters_fp64 = info64["iters"]
+    else:
+        iters_fp64 = info["iters"]
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle)")
+        cpu = cpu_baseline(xyz, cfg, iters_fp64)
+
+    out = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "nodes/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32+f64" if prec == apc.APC_MIXED else "f64",
+        "data": "synthetic",
+        "config": {"workload": args.workload, "particles": cfg["N"], "nodes": info["n"],
+                   "boundary_nodes": info["nb"], "nnz": info["nnz"],
+                   "max_depth": cfg["max_depth"], "order": cfg["order"], "c": cfg["c"],
+                   "precision": args.precision, "tol": args.tol, "precond": "jacobi"},
+        "phases_ms": {k: round(v, 3) for k, v in ms.items()},
+        "solve": {"iters": info["iters"], "sweeps": info["sweeps"],
+                  "rel_resid_true": info["rel_resid_true"],
+                  "density_iters": info["density_iters"]},
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    if plain is not None:
+        out["plain_fp64"] = plain
+        out["speedup_mixed_vs_plain"] = round(value / plain["nodes_per_s"], 3)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

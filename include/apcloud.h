@@ -1,0 +1,174 @@
+/*
+ * apcloud.h -- C ABI of the MI355X (gfx950) AP-Cloud field-solve library.
+ *
+ * AP-Cloud (Wang, Samulyak, Jiao, Yu, "AP-Cloud: Adaptive Particle-in-Cloud
+ * Method for Optimal Solutions to Vlasov-Poisson Equation") replaces the PIC
+ * mesh by an adaptive octree node cloud.  Given N charged particles it computes,
+ * in three steps (Sec. 3.2):
+ *   1. the node density rho~ from the WLS charge assignment B rho~ = rho_M
+ *      (eq. density_apcloud, eq. density_linear_system), NGP kernel (Sec. 5.1);
+ *   2. phi at the nodes from the GFD discretisation of Delta phi = c rho
+ *      (eq. Poisson, Sec. 3.1), solved by a Krylov method;
+ *   3. phi and E = grad phi at the particles by Taylor expansion from GFD
+ *      derivatives (Sec. 3.2 step 3).
+ * The node cloud itself comes from the error-balance criterion and 2:1 face
+ * balance on a Morton-sorted octree (Sec. 4).
+ *
+ * Conventions
+ *  - Every array argument is a DEVICE pointer unless the name ends in _host.
+ *    The caller owns every buffer it passes; the library never frees them.
+ *  - Every call is ordered on the given HIP stream.  Calls that report solver
+ *    statistics (apc_deposit, apc_density_solve, apc_solve) synchronise that
+ *    stream before returning; the others return without synchronising.
+ *  - A cloud handle owns its internal device workspaces; apc_destroy frees
+ *    them.  A handle is bound to the device that was current at build time and
+ *    must not be used from two host threads at once.
+ *  - Particle positions are a 3 x N structure of arrays of float64
+ *    (x[0..N), y[0..N), z[0..N)).  Node numbering: interior nodes (octree
+ *    leaves) 0..n-1 in ascending Morton order of their minimum corner, then
+ *    boundary nodes n..n+nb-1 by (owner node, face), faces -x,+x,-y,+y,-z,+z.
+ *  - Return value: APC_OK (0) on success, a negative APC_E* code on failure
+ *    (outputs then undefined), APC_ENOCONV (+1) when a solve stopped at maxit
+ *    (outputs hold the last iterate; stats say how far it got).
+ */
+#ifndef APCLOUD_H
+#define APCLOUD_H
+
+#include <hip/hip_runtime_api.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define APC_OK 0
+#define APC_EINVAL (-1)   /* bad parameter, NaN input, wrong call order */
+#define APC_ENOMEM (-2)   /* device allocation failed */
+#define APC_EHIP (-3)     /* a HIP runtime call failed (apc_last_error has text) */
+#define APC_EDOMAIN (-4)  /* a particle lies outside the domain */
+#define APC_ESTENCIL (-5) /* a node found no acceptable stencil up to ring_max */
+#define APC_ENOCONV 1     /* solver hit maxit (warning) */
+
+#define APC_FP64 0  /* FP64 stencil fit, FP64 matrix values, FP64 Krylov */
+#define APC_MIXED 1 /* FP32 fit/values/SpMV, FP64 fallback rows, FP64 dots + refinement */
+
+#define APC_PRECOND_NONE 0
+#define APC_PRECOND_JACOBI 1
+
+typedef struct apc_cloud apc_cloud;
+
+typedef struct {
+  double lo[3];     /* domain Omega = [lo, lo + L]^3 */
+  double L;         /* domain edge, > 0 */
+  int order;        /* GFD order k (Sec. 3.1): 2 */
+  double c;         /* error-balance constant (Sec. 4.3, eq. errorbalance_implementation), > 0 */
+  int max_depth;    /* deepest octree level, 1..20 */
+  int ring_min;     /* first k-ring searched for a stencil (Sec. 4.3); 2 for k = 2 */
+  int ring_max;     /* last ring searched; the paper finds 5 always enough */
+  int m_cap;        /* stencil size cap (<= 64); 40 for k = 2 */
+  double poisson_c; /* c in Delta phi = c rho (eq. Poisson); 1 */
+  int precision;    /* APC_FP64 or APC_MIXED, fixed at build time */
+} apc_params;
+
+typedef struct {
+  int iters;             /* Krylov iterations (summed over refinement sweeps) */
+  int restarts;          /* BiCGSTAB restarts (breakdown or residual disagreement) */
+  int sweeps;            /* iterative-refinement sweeps (APC_MIXED), else 1 */
+  int status;            /* APC_OK or APC_ENOCONV */
+  double rel_resid;      /* recursive ||r|| / ||b|| at exit */
+  double rel_resid_true; /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
+  int64_t n_fp64_rows;   /* APC_MIXED: stencils refitted in FP64 (R-diagonal test) */
+  double ms;             /* device time of the call, milliseconds */
+} apc_stats;
+
+/* Fill *p with the defaults above for order k (domain [0,1]^3, c, max_depth left
+   as given by the caller afterwards). */
+void apc_default_params(apc_params *p, int order);
+
+/* Build the node cloud (Sec. 4): Morton keys and a stable radix sort of the
+   particles, the error-balance criterion opening cells with N' >= T_l where
+   T_l = t^(2k-2), t = (c 2^l) / L evaluated in FP64 by repeated multiplication,
+   level-by-level 2:1 face balance to the unique minimal balanced refinement,
+   boundary face nodes, and per-node GFD stencils from the k-ring (Sec. 3.1
+   octant rule; see the library documentation for the exact acceptance test).
+   xyz: 3 x N float64, read during the call and copied (sorted) into the
+   handle.  Errors: APC_EINVAL (parameters, NaN), APC_EDOMAIN (a particle outside
+   Omega), APC_ESTENCIL, APC_ENOMEM, APC_EHIP.  Synchronises the stream. */
+int apc_build_cloud(const apc_params *p, const double *xyz, int64_t N, hipStream_t stream,
+                    apc_cloud **out);
+
+/* Sizes: interior nodes n, boundary nodes nb, stencil entries nnz (off-diagonal),
+   cells opened by the criterion or the balance (n = 1 + 7 n_opened). */
+int apc_cloud_info(const apc_cloud *c, int64_t *n, int64_t *nb, int64_t *nnz,
+                   int64_t *n_opened);
+
+/* Host copies of the cloud structure (any pointer may be NULL): perm_host[N]
+   (sorted position -> original particle index), code_host[n] (Morton code of the
+   minimum corner at max_depth), level_host[n], first_host[n], count_host[n]
+   (sorted particle range of each leaf), bowner_host[nb], bface_host[nb],
+   st_off_host[n+1], st_idx_host[nnz] (stencil CSR), ixyz_host[3*(n+nb)]
+   (integer node coordinates in units of L 2^-(max_depth+1), SoA).
+   Synchronises the handle's build stream. */
+int apc_get_nodes(const apc_cloud *c, int32_t *perm_host, uint64_t *code_host,
+                  int32_t *level_host, int32_t *first_host, int32_t *count_host,
+                  int32_t *bowner_host, int32_t *bface_host, int32_t *st_off_host,
+                  int32_t *st_idx_host, int32_t *ixyz_host);
+
+/* Assemble the GFD Poisson operator (Sec. 3.1, 3.2 step 2): per node the weighted
+   least-squares fit of the scaled Taylor Vandermonde V0 over its stencil
+   (h = max |delta|, Gaussian weight with c = 4), giving the off-diagonal weights
+   w_ij of Delta at node i; the diagonal is -sum_j w_ij.  Must follow
+   apc_build_cloud.  Does not synchronise. */
+int apc_assemble_gfd(apc_cloud *c, hipStream_t stream);
+
+/* Host copy of the assembled operator: w_host[nnz] aligned with the stencil
+   CSR, diag_host[n].  In APC_MIXED the FP32 values are widened exactly. */
+int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host);
+
+/* WLS charge assignment (Sec. 3.2 step 1): rho_M_j = (1/h_j^3) sum_{i in cell j} q_i
+   (NGP kernel: the node's own octree cell, edge h_j), then B rho~ = rho_M with
+   B = I + diag(h_j^2 / 24) L for k = 2 (kernel moments of the cell), boundary
+   nodes carrying their owner's rho_M.  q: N charges in the caller's particle
+   order, or NULL for 1/N each (total charge 1, Sec. 2).  rho_M (may be NULL)
+   and rho_t: n+nb.  Requires apc_assemble_gfd.  BiCGSTAB to relative residual
+   tol (maxit iterations).  Synchronises the stream. */
+int apc_deposit(apc_cloud *c, const double *q, double *rho_M, double *rho_t, double tol,
+                int maxit, apc_stats *st, hipStream_t stream);
+
+/* The density solve of apc_deposit on a caller-supplied rho_M (n+nb). */
+int apc_density_solve(apc_cloud *c, const double *rho_M, double *rho_t, double tol, int maxit,
+                      apc_stats *st, hipStream_t stream);
+
+/* GFD Poisson solve (Sec. 3.2 step 2): L phi = poisson_c rho~ at interior nodes,
+   phi = g at boundary nodes (Dirichlet; g: nb values or NULL for 0).  rho_t: n
+   (or n+nb, tail ignored); phi: n+nb out.  BiCGSTAB with optional right Jacobi
+   preconditioning to recursive relative residual tol, confirmed by the true
+   FP64 residual.  APC_MIXED: FP32 SpMV inside FP64 iterative refinement.
+   Requires apc_assemble_gfd.  Synchronises the stream. */
+int apc_solve(apc_cloud *c, const double *rho_t, const double *g, double *phi, double tol,
+              int maxit, int precond, apc_stats *st, hipStream_t stream);
+
+/* Interpolation (Sec. 3.2 step 3): GFD derivatives of phi at every node, then
+   for each particle the k-th order Taylor polynomial of its leaf's node
+   evaluated at the particle: phi_p[N], grad_p[3 x N] (= grad phi, the paper's E),
+   both in the caller's original particle order.  phi: n+nb.  Does not
+   synchronise. */
+int apc_interpolate_force(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
+                          hipStream_t stream);
+
+/* Scaled-back GFD derivatives d^alpha f at every interior node (n x p row-major,
+   p = 9 for k = 2, columns x,y,z,xx,xy,xz,yy,yz,zz).  f: n+nb. */
+int apc_node_derivs(apc_cloud *c, const double *f, double *D, hipStream_t stream);
+
+/* Apply the assembled operator: out[i] = (L f)_i for interior i; f: n+nb. */
+int apc_apply_operator(apc_cloud *c, const double *f, double *out, hipStream_t stream);
+
+void apc_destroy(apc_cloud *c);
+const char *apc_strerror(int code);
+/* Text of the last HIP error seen by the calling thread (empty if none). */
+const char *apc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

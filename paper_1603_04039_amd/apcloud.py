@@ -1,0 +1,280 @@
+"""Thin ctypes binding of libapcloud.so (include/apcloud.h).
+
+Argument marshalling only: every step runs in the HIP library.  Device buffers
+are torch CUDA tensors (PyTorch-ROCm provides device memory and streams); the
+calls receive their raw pointers and the current stream.  There is no CPU
+fallback: without the built library every call raises.
+"""
+from __future__ import annotations
+
+import ctypes as ct
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libapcloud.so")
+
+APC_OK, APC_EINVAL, APC_ENOMEM, APC_EHIP, APC_EDOMAIN, APC_ESTENCIL = 0, -1, -2, -3, -4, -5
+APC_ENOCONV = 1
+APC_FP64, APC_MIXED = 0, 1
+APC_PRECOND_NONE, APC_PRECOND_JACOBI = 0, 1
+
+# every symbol declared in include/apcloud.h
+EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_nodes",
+           "apc_assemble_gfd", "apc_get_operator", "apc_deposit", "apc_density_solve",
+           "apc_solve", "apc_interpolate_force", "apc_node_derivs", "apc_apply_operator",
+           "apc_destroy", "apc_strerror", "apc_last_error"]
+
+
+class ApcError(RuntimeError):
+    def __init__(self, code, what):
+        self.code = code
+        super().__init__(f"{what}: {_strerror(code)} ({code}) {_last_error()}")
+
+
+class Params(ct.Structure):
+    _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
+                ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
+                ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
+                ("precision", ct.c_int)]
+
+
+class Stats(ct.Structure):
+    _fields_ = [("iters", ct.c_int), ("restarts", ct.c_int), ("sweeps", ct.c_int),
+                ("status", ct.c_int), ("rel_resid", ct.c_double),
+                ("rel_resid_true", ct.c_double), ("n_fp64_rows", ct.c_int64), ("ms", ct.c_double)]
+
+    def as_dict(self):
+        return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libapcloud.so; raises if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is missing: build it with paper_1603_04039_amd/build.py "
+                          "(or __graft_entry__.build()); there is no fallback path")
+    lib = ct.CDLL(path)
+    P = ct.c_void_p
+    I64 = ct.c_int64
+    lib.apc_default_params.argtypes = [ct.POINTER(Params), ct.c_int]
+    lib.apc_default_params.restype = None
+    lib.apc_build_cloud.argtypes = [ct.POINTER(Params), P, I64, P, ct.POINTER(P)]
+    lib.apc_cloud_info.argtypes = [P] + [ct.POINTER(I64)] * 4
+    lib.apc_get_nodes.argtypes = [P] * 11
+    lib.apc_assemble_gfd.argtypes = [P, P]
+    lib.apc_get_operator.argtypes = [P, P, P]
+    lib.apc_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
+    lib.apc_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
+    lib.apc_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, ct.POINTER(Stats), P]
+    lib.apc_interpolate_force.argtypes = [P, P, P, P, P]
+    lib.apc_node_derivs.argtypes = [P, P, P, P]
+    lib.apc_apply_operator.argtypes = [P, P, P, P]
+    lib.apc_destroy.argtypes = [P]
+    lib.apc_destroy.restype = None
+    lib.apc_strerror.argtypes = [ct.c_int]
+    lib.apc_strerror.restype = ct.c_char_p
+    lib.apc_last_error.argtypes = []
+    lib.apc_last_error.restype = ct.c_char_p
+    _lib = lib
+    return lib
+
+
+def _strerror(code):
+    return load_library().apc_strerror(code).decode()
+
+
+def _last_error():
+    return load_library().apc_last_error().decode()
+
+
+def _check(rc, what):
+    if rc < 0:
+        raise ApcError(rc, what)
+    return rc
+
+
+def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
+                ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64) -> Params:
+    p = Params()
+    load_library().apc_default_params(ct.byref(p), order)
+    p.lo[:] = lo
+    p.L = L
+    p.c = c
+    p.max_depth = max_depth
+    if ring_min is not None:
+        p.ring_min = ring_min
+    p.ring_max = ring_max
+    if m_cap is not None:
+        p.m_cap = m_cap
+    p.poisson_c = poisson_c
+    p.precision = precision
+    return p
+
+
+def _stream(stream=None):
+    import torch
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ct.c_void_p(s.cuda_stream)
+
+
+def _dptr(t, dtype=None, numel=None):
+    """Raw device pointer of a contiguous CUDA tensor (None passes NULL)."""
+    if t is None:
+        return None
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.is_cuda and t.is_contiguous()):
+        raise ValueError("expected a contiguous CUDA tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise ValueError(f"expected {dtype}, got {t.dtype}")
+    if numel is not None and t.numel() < numel:
+        raise ValueError(f"tensor too small: {t.numel()} < {numel}")
+    return ct.c_void_p(t.data_ptr())
+
+
+class Cloud:
+    """A node cloud built on the GPU from particles xyz (3 x N float64 CUDA tensor)."""
+
+    def __init__(self, xyz, stream=None, **params):
+        import torch
+        self.lib = load_library()
+        self.params = make_params(**params)
+        self.xyz = xyz
+        assert xyz.dim() == 2 and xyz.shape[0] == 3
+        self.N = xyz.shape[1]
+        h = ct.c_void_p()
+        _check(self.lib.apc_build_cloud(ct.byref(self.params), _dptr(xyz, torch.float64),
+                                        self.N, _stream(stream), ct.byref(h)), "apc_build_cloud")
+        self.h = h
+        v = [ct.c_int64() for _ in range(4)]
+        _check(self.lib.apc_cloud_info(self.h, *[ct.byref(x) for x in v]), "apc_cloud_info")
+        self.n, self.nb, self.nnz, self.n_opened = [x.value for x in v]
+        self.L = self.params.L
+        self.lo = np.array(self.params.lo[:])
+        self.max_depth = self.params.max_depth
+        self.unit = self.L / 2.0 ** (self.max_depth + 1)
+        self.assembled = False
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.apc_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    # ---- structure (host copies)
+    def nodes(self):
+        n, nb, nnz = self.n, self.nb, self.nnz
+        out = dict(perm=np.zeros(self.N, np.int32), code=np.zeros(n, np.uint64),
+                   level=np.zeros(n, np.int32), first=np.zeros(n, np.int32),
+                   count=np.zeros(n, np.int32), bowner=np.zeros(nb, np.int32),
+                   bface=np.zeros(nb, np.int32), st_off=np.zeros(n + 1, np.int32),
+                   st_idx=np.zeros(nnz, np.int32), ixyz=np.zeros((3, n + nb), np.int32))
+        ptrs = [out[k].ctypes.data_as(ct.c_void_p) for k in
+                ["perm", "code", "level", "first", "count", "bowner", "bface", "st_off",
+                 "st_idx", "ixyz"]]
+        _check(self.lib.apc_get_nodes(self.h, *ptrs), "apc_get_nodes")
+        return out
+
+    def positions(self):
+        return self.lo[:, None] + self.unit * self.nodes()["ixyz"].astype(np.float64)
+
+    # ---- the hot path
+    def assemble_gfd(self, stream=None):
+        _check(self.lib.apc_assemble_gfd(self.h, _stream(stream)), "apc_assemble_gfd")
+        self.assembled = True
+
+    def operator(self):
+        w = np.zeros(self.nnz)
+        d = np.zeros(self.n)
+        _check(self.lib.apc_get_operator(self.h, w.ctypes.data_as(ct.c_void_p),
+                                         d.ctypes.data_as(ct.c_void_p)), "apc_get_operator")
+        return w, d
+
+    def deposit(self, q=None, tol=1e-12, maxit=1000, stream=None, rho_M=None, rho_t=None):
+        import torch
+        nt = self.n + self.nb
+        rho_M = rho_M if rho_M is not None else torch.empty(nt, dtype=torch.float64, device="cuda")
+        rho_t = rho_t if rho_t is not None else torch.empty(nt, dtype=torch.float64, device="cuda")
+        st = Stats()
+        rc = _check(self.lib.apc_deposit(self.h, _dptr(q, torch.float64, self.N),
+                                         _dptr(rho_M, torch.float64, nt),
+                                         _dptr(rho_t, torch.float64, nt), tol, maxit,
+                                         ct.byref(st), _stream(stream)), "apc_deposit")
+        return rho_M, rho_t, dict(st.as_dict(), rc=rc)
+
+    def density_solve(self, rho_M, tol=1e-12, maxit=1000, stream=None, rho_t=None):
+        import torch
+        nt = self.n + self.nb
+        rho_t = rho_t if rho_t is not None else torch.empty(nt, dtype=torch.float64, device="cuda")
+        st = Stats()
+        rc = _check(self.lib.apc_density_solve(self.h, _dptr(rho_M, torch.float64, nt),
+                                               _dptr(rho_t, torch.float64, nt), tol, maxit,
+                                               ct.byref(st), _stream(stream)), "apc_density_solve")
+        return rho_t, dict(st.as_dict(), rc=rc)
+
+    def solve(self, rho_t, g=None, tol=1e-8, maxit=20000, precond=APC_PRECOND_JACOBI,
+              stream=None, phi=None):
+        import torch
+        nt = self.n + self.nb
+        phi = phi if phi is not None else torch.empty(nt, dtype=torch.float64, device="cuda")
+        st = Stats()
+        rc = _check(self.lib.apc_solve(self.h, _dptr(rho_t, torch.float64, self.n),
+                                       _dptr(g, torch.float64, self.nb),
+                                       _dptr(phi, torch.float64, nt), tol, maxit, precond,
+                                       ct.byref(st), _stream(stream)), "apc_solve")
+        return phi, dict(st.as_dict(), rc=rc)
+
+    def interpolate_force(self, phi, stream=None, phi_p=None, grad_p=None):
+        import torch
+        phi_p = phi_p if phi_p is not None else torch.empty(self.N, dtype=torch.float64,
+                                                            device="cuda")
+        grad_p = grad_p if grad_p is not None else torch.empty((3, self.N), dtype=torch.float64,
+                                                               device="cuda")
+        _check(self.lib.apc_interpolate_force(self.h, _dptr(phi, torch.float64, self.n + self.nb),
+                                              _dptr(phi_p, torch.float64, self.N),
+                                              _dptr(grad_p, torch.float64, 3 * self.N),
+                                              _stream(stream)), "apc_interpolate_force")
+        return phi_p, grad_p
+
+    def node_derivs(self, f, stream=None):
+        import torch
+        D = torch.empty((self.n, 9), dtype=torch.float64, device="cuda")
+        _check(self.lib.apc_node_derivs(self.h, _dptr(f, torch.float64, self.n + self.nb),
+                                        _dptr(D), _stream(stream)), "apc_node_derivs")
+        return D
+
+    def apply_operator(self, f, stream=None):
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(self.lib.apc_apply_operator(self.h, _dptr(f, torch.float64, self.n + self.nb),
+                                           _dptr(out), _stream(stream)), "apc_apply_operator")
+        return out
+
+
+# C-ABI names as free functions
+def build_cloud(xyz, stream=None, **params) -> Cloud:
+    return Cloud(xyz, stream=stream, **params)
+
+
+def assemble_gfd(cloud: Cloud, stream=None):
+    return cloud.assemble_gfd(stream)
+
+
+def deposit(cloud: Cloud, q=None, **kw):
+    return cloud.deposit(q, **kw)
+
+
+def solve(cloud: Cloud, rho_t, g=None, **kw):
+    return cloud.solve(rho_t, g, **kw)
+
+
+def interpolate_force(cloud: Cloud, phi, stream=None):
+    return cloud.interpolate_force(phi, stream)

@@ -1,0 +1,137 @@
+// Internal declarations of the gfx950 AP-Cloud library (not part of the C ABI).
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/apcloud.h"
+
+#define APC_BLOCK 256
+#define APC_MAXM 64      // hard stencil cap: one wavefront
+#define APC_RING_CAP 2048 // per-node candidate capacity of the ring search
+#define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
+
+void apc_set_hip_error(hipError_t e, const char *what, const char *file, int line);
+
+#define HIPCHK(x)                                          \
+  do {                                                     \
+    hipError_t e_ = (x);                                   \
+    if (e_ != hipSuccess) {                                \
+      apc_set_hip_error(e_, #x, __FILE__, __LINE__);       \
+      return e_ == hipErrorOutOfMemory ? APC_ENOMEM : APC_EHIP; \
+    }                                                      \
+  } while (0)
+
+#define APCCHK(x)        \
+  do {                   \
+    int r_ = (x);        \
+    if (r_ < 0) return r_; \
+  } while (0)
+
+static inline unsigned grid_for(int64_t n, int per_block = APC_BLOCK) {
+  int64_t g = (n + per_block - 1) / per_block;
+  return (unsigned)(g < 1 ? 1 : g);
+}
+
+// ---------------------------------------------------------------- Morton codes
+// 3 bits per level, x highest in each triple; bits spread with magic masks.
+__host__ __device__ inline uint64_t apc_spread3(uint64_t v) {
+  v &= 0x1fffffull;
+  v = (v | (v << 32)) & 0x1f00000000ffffull;
+  v = (v | (v << 16)) & 0x1f0000ff0000ffull;
+  v = (v | (v << 8)) & 0x100f00f00f00f00full;
+  v = (v | (v << 4)) & 0x10c30c30c30c30c3ull;
+  v = (v | (v << 2)) & 0x1249249249249249ull;
+  return v;
+}
+__host__ __device__ inline uint32_t apc_compact3(uint64_t v) {
+  v &= 0x1249249249249249ull;
+  v = (v ^ (v >> 2)) & 0x10c30c30c30c30c3ull;
+  v = (v ^ (v >> 4)) & 0x100f00f00f00f00full;
+  v = (v ^ (v >> 8)) & 0x1f0000ff0000ffull;
+  v = (v ^ (v >> 16)) & 0x1f00000000ffffull;
+  v = (v ^ (v >> 32)) & 0x1fffffull;
+  return (uint32_t)v;
+}
+__host__ __device__ inline uint64_t apc_morton(uint32_t x, uint32_t y, uint32_t z) {
+  return (apc_spread3(x) << 2) | (apc_spread3(y) << 1) | apc_spread3(z);
+}
+
+// first index in [lo, hi) with a[i] >= v
+__device__ inline int64_t apc_lower_bound(const uint64_t *a, int64_t lo, int64_t hi, uint64_t v) {
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] < v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo;
+}
+// last index in [0, n) with a[i] <= v (a[0] <= v assumed)
+__device__ inline int64_t apc_last_le(const uint64_t *a, int64_t n, uint64_t v) {
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = lo + ((hi - lo) >> 1);
+    if (a[mid] <= v)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  return lo - 1;
+}
+
+// ---------------------------------------------------------------- cloud handle
+struct apc_solver_ws;
+
+struct apc_cloud {
+  apc_params P;
+  int device = 0;
+  int p = 9;
+  int64_t N = 0, n = 0, nb = 0, nnz = 0, n_opened = 0;
+  double unit = 0.0; // L / 2^(max_depth+1)
+  double T[24];
+  // particles (sorted by key)
+  int32_t *perm = nullptr;  // N: sorted position -> original index
+  double *sxyz = nullptr;   // 3 x N sorted positions
+  int32_t *pnode = nullptr; // N: sorted position -> leaf
+  // leaves
+  uint64_t *code = nullptr; // n
+  int32_t *level = nullptr, *first = nullptr, *count = nullptr;
+  int32_t *crd = nullptr; // 3 x (n+nb) SoA integer coordinates
+  int32_t *bowner = nullptr, *bface = nullptr;
+  int32_t *st_off = nullptr, *st_idx = nullptr; // stencil CSR
+  // operator
+  bool assembled = false;
+  double *w64 = nullptr; // nnz (APC_FP64)
+  float *w32 = nullptr;  // nnz (APC_MIXED)
+  double *diag = nullptr, *inv_diag = nullptr; // n
+  double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator)
+  uint8_t *fp64row = nullptr;                  // n (APC_MIXED): refitted in FP64
+  int64_t n_fp64_rows = 0;
+  apc_solver_ws *ws = nullptr;
+};
+
+// ---------------------------------------------------------------- host utilities
+int apc_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);  // exclusive
+int apc_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);  // exclusive
+int apc_sum_i32(const int32_t *in, int64_t n, int64_t *host_out, hipStream_t s);
+int apc_radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+
+int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_t s,
+                   apc_cloud **out);
+int apc_assemble_impl(apc_cloud *c, hipStream_t s);
+int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s);
+int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
+                    hipStream_t s);
+int apc_deposit_impl(apc_cloud *c, const double *q, double *rho_M, hipStream_t s);
+int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, double tol,
+                           int maxit, apc_stats *st, hipStream_t s);
+int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *phi,
+                   double tol, int maxit, int precond, apc_stats *st, hipStream_t s);
+int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s);
+void apc_free_solver(apc_cloud *c);
+// stencil rank test of pending nodes (k = 2); clears m[y] of rejected nodes
+int apc_rank_check(const apc_cloud *c, const int32_t *pending, int64_t np, const int32_t *cand,
+                   int32_t *m, hipStream_t s);

@@ -1,0 +1,195 @@
+// C ABI of the gfx950 AP-Cloud library (declared in include/apcloud.h).
+#include <hip/hip_runtime.h>
+
+#include <cstdio>
+#include <cstring>
+
+#include "apc_internal.h"
+
+void apc_free_cloud(apc_cloud *c);
+
+static thread_local char g_err[512] = {0};
+
+void apc_set_hip_error(hipError_t e, const char *what, const char *file, int line) {
+  snprintf(g_err, sizeof(g_err), "%s: %s (%s:%d)", hipGetErrorString(e), what, file, line);
+}
+
+// Every entry point runs on the device the handle was built on.
+namespace {
+struct DeviceGuard {
+  int prev = -1;
+  bool ok = true;
+  explicit DeviceGuard(int dev) {
+    if (hipGetDevice(&prev) != hipSuccess) {
+      ok = false;
+      return;
+    }
+    if (prev != dev && hipSetDevice(dev) != hipSuccess) ok = false;
+  }
+  ~DeviceGuard() {
+    int cur = -1;
+    if (prev >= 0 && hipGetDevice(&cur) == hipSuccess && cur != prev) (void)hipSetDevice(prev);
+  }
+};
+} // namespace
+
+extern "C" {
+
+void apc_default_params(apc_params *p, int order) {
+  if (!p) return;
+  memset(p, 0, sizeof(*p));
+  p->lo[0] = p->lo[1] = p->lo[2] = 0.0;
+  p->L = 1.0;
+  p->order = order;
+  p->c = 0.35;
+  p->max_depth = 6;
+  p->ring_min = order == 2 ? 2 : 3;
+  p->ring_max = 5;
+  p->m_cap = order == 2 ? 40 : 56;
+  p->poisson_c = 1.0;
+  p->precision = APC_FP64;
+}
+
+int apc_build_cloud(const apc_params *p, const double *xyz, int64_t N, hipStream_t stream,
+                    apc_cloud **out) {
+  if (!out) return APC_EINVAL;
+  g_err[0] = 0;
+  return apc_build_impl(p, xyz, N, stream, out);
+}
+
+int apc_cloud_info(const apc_cloud *c, int64_t *n, int64_t *nb, int64_t *nnz, int64_t *n_opened) {
+  if (!c) return APC_EINVAL;
+  if (n) *n = c->n;
+  if (nb) *nb = c->nb;
+  if (nnz) *nnz = c->nnz;
+  if (n_opened) *n_opened = c->n_opened;
+  return APC_OK;
+}
+
+int apc_get_nodes(const apc_cloud *c, int32_t *perm_host, uint64_t *code_host, int32_t *level_host,
+                  int32_t *first_host, int32_t *count_host, int32_t *bowner_host,
+                  int32_t *bface_host, int32_t *st_off_host, int32_t *st_idx_host,
+                  int32_t *ixyz_host) {
+  if (!c) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  HIPCHK(hipDeviceSynchronize());
+  const int64_t n = c->n, nb = c->nb, ntot = n + nb;
+  struct {
+    void *dst;
+    const void *src;
+    size_t bytes;
+  } cp[] = {
+      {perm_host, c->perm, (size_t)c->N * 4},       {code_host, c->code, (size_t)n * 8},
+      {level_host, c->level, (size_t)n * 4},        {first_host, c->first, (size_t)n * 4},
+      {count_host, c->count, (size_t)n * 4},        {bowner_host, c->bowner, (size_t)nb * 4},
+      {bface_host, c->bface, (size_t)nb * 4},       {st_off_host, c->st_off, (size_t)(n + 1) * 4},
+      {st_idx_host, c->st_idx, (size_t)c->nnz * 4}, {ixyz_host, c->crd, (size_t)ntot * 3 * 4},
+  };
+  for (auto &e : cp)
+    if (e.dst && e.bytes) HIPCHK(hipMemcpy(e.dst, e.src, e.bytes, hipMemcpyDeviceToHost));
+  return APC_OK;
+}
+
+int apc_assemble_gfd(apc_cloud *c, hipStream_t stream) {
+  if (!c) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_assemble_impl(c, stream);
+}
+
+int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host) {
+  if (!c || !c->assembled) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  HIPCHK(hipDeviceSynchronize());
+  if (w_host && c->nnz) {
+    if (c->P.precision == APC_MIXED) {
+      float *tmp = new float[c->nnz];
+      hipError_t e = hipMemcpy(tmp, c->w32, (size_t)c->nnz * 4, hipMemcpyDeviceToHost);
+      for (int64_t i = 0; i < c->nnz; i++) w_host[i] = (double)tmp[i];
+      delete[] tmp;
+      HIPCHK(e);
+    } else {
+      HIPCHK(hipMemcpy(w_host, c->w64, (size_t)c->nnz * 8, hipMemcpyDeviceToHost));
+    }
+  }
+  if (diag_host) HIPCHK(hipMemcpy(diag_host, c->diag, (size_t)c->n * 8, hipMemcpyDeviceToHost));
+  return APC_OK;
+}
+
+int apc_deposit(apc_cloud *c, const double *q, double *rho_M, double *rho_t, double tol, int maxit,
+                apc_stats *st, hipStream_t stream) {
+  if (!c || !rho_t || !(tol > 0.0) || maxit < 1) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  if (!c->assembled) return APC_EINVAL;
+  double *rm = rho_M;
+  if (!rm) HIPCHK(hipMallocAsync((void **)&rm, (size_t)(c->n + c->nb) * sizeof(double), stream));
+  int rc = apc_deposit_impl(c, q, rm, stream);
+  if (rc == APC_OK) rc = apc_density_solve_impl(c, rm, rho_t, tol, maxit, st, stream);
+  if (!rho_M) HIPCHK(hipFreeAsync(rm, stream));
+  return rc;
+}
+
+int apc_density_solve(apc_cloud *c, const double *rho_M, double *rho_t, double tol, int maxit,
+                      apc_stats *st, hipStream_t stream) {
+  if (!c || !rho_M || !rho_t || !(tol > 0.0) || maxit < 1) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_density_solve_impl(c, rho_M, rho_t, tol, maxit, st, stream);
+}
+
+int apc_solve(apc_cloud *c, const double *rho_t, const double *gvals, double *phi, double tol,
+              int maxit, int precond, apc_stats *st, hipStream_t stream) {
+  if (!c || !rho_t || !phi || !(tol > 0.0) || maxit < 1) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_solve_impl(c, rho_t, gvals, phi, tol, maxit, precond, st, stream);
+}
+
+int apc_interpolate_force(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
+                          hipStream_t stream) {
+  if (!c || !phi || !phi_p || !grad_p) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_interp_impl(c, phi, phi_p, grad_p, stream);
+}
+
+int apc_node_derivs(apc_cloud *c, const double *f, double *D, hipStream_t stream) {
+  if (!c || !f || !D) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_node_derivs_impl(c, f, D, stream);
+}
+
+int apc_apply_operator(apc_cloud *c, const double *f, double *out, hipStream_t stream) {
+  if (!c || !f || !out) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_apply_impl(c, f, out, stream);
+}
+
+void apc_destroy(apc_cloud *c) {
+  if (!c) return;
+  DeviceGuard g(c->device);
+  (void)hipDeviceSynchronize();
+  apc_free_cloud(c);
+}
+
+const char *apc_strerror(int code) {
+  switch (code) {
+  case APC_OK: return "ok";
+  case APC_EINVAL: return "invalid argument";
+  case APC_ENOMEM: return "out of device memory";
+  case APC_EHIP: return "HIP runtime error";
+  case APC_EDOMAIN: return "particle outside the domain";
+  case APC_ESTENCIL: return "no acceptable stencil up to ring_max";
+  case APC_ENOCONV: return "solver did not converge within maxit";
+  default: return "unknown error";
+  }
+}
+
+const char *apc_last_error(void) { return g_err; }
+
+} // extern "C"

@@ -1,0 +1,758 @@
+// Node-cloud build on the GPU (Sec. 4): Morton keys, stable radix sort, the
+// error-balance criterion expanded level by level, 2:1 face balance to its
+// unique minimal fixed point, boundary face nodes, face adjacency (1-ring) and
+// per-node k-ring stencil choice.  All geometry is integer, so the result is
+// independent of evaluation order.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <vector>
+
+#include "apc_internal.h"
+
+namespace {
+
+struct Thr {
+  double T[24];
+};
+
+// ---------------------------------------------------------------- keys
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_keys(const double *__restrict__ xyz, int64_t N, double lo0, double lo1, double lo2, double L,
+           double s, int D, uint64_t *__restrict__ keys, int32_t *__restrict__ vals,
+           int *__restrict__ err) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= N) return;
+  const double lo[3] = {lo0, lo1, lo2};
+  const uint32_t top = (1u << D) - 1u;
+  uint32_t u[3];
+  int e = 0;
+#pragma unroll
+  for (int d = 0; d < 3; d++) {
+    const double x = xyz[(int64_t)d * N + i];
+    if (isnan(x)) e |= 1;
+    if (x < lo[d] || x > lo[d] + L) e |= 2;
+    double q = floor((x - lo[d]) * s);
+    if (!(q >= 0.0)) q = 0.0;
+    if (q > (double)top) q = (double)top;
+    u[d] = (uint32_t)q;
+  }
+  if (e) atomicOr(err, e);
+  keys[i] = apc_morton(u[0], u[1], u[2]);
+  vals[i] = (int32_t)i;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_gather_xyz(const double *__restrict__ xyz, const int32_t *__restrict__ perm, int64_t N,
+                 double *__restrict__ sxyz) {
+  int64_t s = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (s >= N) return;
+  const int64_t i = perm[s];
+  sxyz[s] = xyz[i];
+  sxyz[N + s] = xyz[N + i];
+  sxyz[2 * N + s] = xyz[2 * N + i];
+}
+
+// ---------------------------------------------------------------- cell lists
+struct Cells {
+  uint64_t *pre = nullptr; // key prefix at the cell's own level
+  int32_t *lev = nullptr, *fst = nullptr, *cnt = nullptr, *flag = nullptr;
+  int64_t n = 0;
+};
+
+int cells_alloc(Cells &c, int64_t n, hipStream_t s) {
+  c.n = n;
+  size_t m = (size_t)(n > 0 ? n : 1);
+  HIPCHK(hipMallocAsync((void **)&c.pre, m * sizeof(uint64_t), s));
+  HIPCHK(hipMallocAsync((void **)&c.lev, m * sizeof(int32_t), s));
+  HIPCHK(hipMallocAsync((void **)&c.fst, m * sizeof(int32_t), s));
+  HIPCHK(hipMallocAsync((void **)&c.cnt, m * sizeof(int32_t), s));
+  HIPCHK(hipMallocAsync((void **)&c.flag, m * sizeof(int32_t), s));
+  return APC_OK;
+}
+int cells_free(Cells &c, hipStream_t s) {
+  if (c.pre) HIPCHK(hipFreeAsync(c.pre, s));
+  if (c.lev) HIPCHK(hipFreeAsync(c.lev, s));
+  if (c.fst) HIPCHK(hipFreeAsync(c.fst, s));
+  if (c.cnt) HIPCHK(hipFreeAsync(c.cnt, s));
+  if (c.flag) HIPCHK(hipFreeAsync(c.flag, s));
+  c = Cells();
+  return APC_OK;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK) k_sizes(const int32_t *flag, int64_t n, int32_t *sz) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) sz[i] = flag[i] ? 8 : 1;
+}
+
+// Replace every flagged cell by its 8 children (Morton child order keeps the list
+// sorted); each child's particle range is the sub-range of its parent carrying the
+// child's key prefix.  With `criterion`, a child is flagged for the next pass when
+// it lies above max_depth and holds N' >= T_l particles.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_expand(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
+             const int32_t *__restrict__ fst, const int32_t *__restrict__ cnt,
+             const int32_t *__restrict__ flag, const int32_t *__restrict__ off, int64_t n,
+             const uint64_t *__restrict__ keys, int D, Thr thr, int criterion,
+             uint64_t *__restrict__ opre, int32_t *__restrict__ olev, int32_t *__restrict__ ofst,
+             int32_t *__restrict__ ocnt, int32_t *__restrict__ oflag) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const int64_t o = off[i];
+  if (!flag[i]) {
+    opre[o] = pre[i];
+    olev[o] = lev[i];
+    ofst[o] = fst[i];
+    ocnt[o] = cnt[i];
+    oflag[o] = 0;
+    return;
+  }
+  const int l = lev[i] + 1;
+  const int sh = 3 * (D - l);
+  const int64_t a0 = fst[i], a1 = (int64_t)fst[i] + cnt[i];
+  int64_t a = a0;
+  for (int c = 0; c < 8; c++) {
+    const uint64_t cp = pre[i] * 8ull + (uint64_t)c;
+    const int64_t b = apc_lower_bound(keys, a, a1, (cp + 1ull) << sh);
+    const int32_t k = (int32_t)(b - a);
+    opre[o + c] = cp;
+    olev[o + c] = l;
+    ofst[o + c] = (int32_t)a;
+    ocnt[o + c] = k;
+    oflag[o + c] = criterion ? (l < D && (double)k >= thr.T[l]) : 0;
+    a = b;
+  }
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_mincorner(const uint64_t *pre, const int32_t *lev, int64_t n, int D, uint64_t *mc) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) mc[i] = pre[i] << (3 * (D - lev[i]));
+}
+
+__device__ inline void cell_index(uint64_t pre, uint32_t t[3]) {
+  t[0] = apc_compact3(pre >> 2);
+  t[1] = apc_compact3(pre >> 1);
+  t[2] = apc_compact3(pre);
+}
+
+// 2:1 face balance: a leaf at level l marks every face-neighbouring leaf coarser
+// than l - 1.  The neighbour across a face is the leaf containing the minimum
+// corner of the same-level cell across it.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_balance_mark(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
+                   const uint64_t *__restrict__ mc, int64_t n, int D, int32_t *__restrict__ mark) {
+  int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y >= n) return;
+  const int l = lev[y];
+  if (l < 2) return;
+  uint32_t t0[3];
+  cell_index(pre[y], t0);
+  const int sh = D - l;
+  for (int f = 0; f < 6; f++) {
+    const int d = f >> 1;
+    uint32_t t[3] = {t0[0], t0[1], t0[2]};
+    if (f & 1) {
+      if (t[d] + 1u >= (1u << l)) continue;
+      t[d] += 1u;
+    } else {
+      if (t[d] == 0u) continue;
+      t[d] -= 1u;
+    }
+    const uint64_t pc = apc_morton(t[0] << sh, t[1] << sh, t[2] << sh);
+    const int64_t z = apc_last_le(mc, n, pc);
+    if (lev[z] < l - 1) mark[z] = 1;
+  }
+}
+
+// number of faces of each leaf lying on the domain boundary
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_bcount(const uint64_t *pre, const int32_t *lev, int64_t n, int32_t *bc) {
+  int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y >= n) return;
+  uint32_t t[3];
+  cell_index(pre[y], t);
+  const uint32_t top = (1u << lev[y]) - 1u;
+  int k = 0;
+  for (int d = 0; d < 3; d++) k += (t[d] == 0u) + (t[d] == top);
+  bc[y] = k;
+}
+
+// Node coordinates (units of L 2^-(D+1)): centre of a level-l cell with index i is
+// (2i+1) 2^(D-l); boundary nodes sit at the centre of their owner's face.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_nodes(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
+            const int32_t *__restrict__ bstart, int64_t n, int64_t ntot, int D,
+            int32_t *__restrict__ crd, int32_t *__restrict__ bowner, int32_t *__restrict__ bface) {
+  int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y >= n) return;
+  const int l = lev[y];
+  uint32_t t[3];
+  cell_index(pre[y], t);
+  const int32_t sz = 1 << (D - l);
+  int32_t c[3];
+  for (int d = 0; d < 3; d++) {
+    c[d] = (int32_t)(2u * t[d] + 1u) * sz;
+    crd[(int64_t)d * ntot + y] = c[d];
+  }
+  const uint32_t top = (1u << l) - 1u;
+  int64_t b = n + bstart[y];
+  for (int f = 0; f < 6; f++) {
+    const int d = f >> 1;
+    const bool on = (f & 1) ? (t[d] == top) : (t[d] == 0u);
+    if (!on) continue;
+    for (int e = 0; e < 3; e++) crd[(int64_t)e * ntot + b] = c[e];
+    crd[(int64_t)d * ntot + b] = (f & 1) ? (1 << (D + 1)) : 0;
+    bowner[b - n] = (int32_t)y;
+    bface[b - n] = f;
+    b++;
+  }
+}
+
+// 1-ring (Sec. 4.3): per face, the neighbouring leaf if it is not finer, else the
+// 4 level-(l+1) leaves touching the face; boundary faces give the boundary node.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_ring1(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
+            const uint64_t *__restrict__ mc, const int32_t *__restrict__ bstart, int64_t n, int D,
+            int32_t *__restrict__ r1cnt, int32_t *__restrict__ r1, int *__restrict__ err) {
+  int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y >= n) return;
+  const int l = lev[y];
+  uint32_t t0[3];
+  cell_index(pre[y], t0);
+  const uint32_t top = (1u << l) - 1u;
+  int32_t *out = r1 + y * 24;
+  int k = 0, kb = 0;
+  for (int f = 0; f < 6; f++) {
+    const int d = f >> 1;
+    const bool bnd = (f & 1) ? (t0[d] == top) : (t0[d] == 0u);
+    if (bnd) {
+      out[k++] = (int32_t)(n + bstart[y] + kb++);
+      continue;
+    }
+    uint32_t t[3] = {t0[0], t0[1], t0[2]};
+    t[d] = (f & 1) ? t[d] + 1u : t[d] - 1u;
+    const int sh = D - l;
+    const uint64_t pc = apc_morton(t[0] << sh, t[1] << sh, t[2] << sh);
+    const int64_t z = apc_last_le(mc, n, pc);
+    if (lev[z] <= l) {
+      out[k++] = (int32_t)z;
+      continue;
+    }
+    if (l + 1 > D) {
+      atomicOr(err, 4);
+      continue;
+    }
+    const int side = (f & 1) ? 0 : 1;
+    for (int a = 0; a < 2; a++)
+      for (int b = 0; b < 2; b++) {
+        uint32_t u[3];
+        int q = 0;
+        for (int e = 0; e < 3; e++) {
+          if (e == d) {
+            u[e] = 2u * t[e] + (uint32_t)side;
+          } else {
+            u[e] = 2u * t[e] + (uint32_t)(q == 0 ? a : b);
+            q++;
+          }
+        }
+        const int sh1 = D - l - 1;
+        const uint64_t pc1 = apc_morton(u[0] << sh1, u[1] << sh1, u[2] << sh1);
+        const int64_t zc = apc_last_le(mc, n, pc1);
+        if (lev[zc] != l + 1 || mc[zc] != pc1) atomicOr(err, 4);
+        out[k++] = (int32_t)zc;
+      }
+  }
+  r1cnt[y] = k;
+}
+
+__device__ inline bool in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
+  const int64_t sx = (o & 4) ? 1 : -1, sy = (o & 2) ? 1 : -1, sz = (o & 1) ? 1 : -1;
+  return sx * d0 >= 0 && sy * d1 >= 0 && sz * d2 >= 0;
+}
+
+// Stencil of node y from its R-ring (nodes within R face-adjacency steps, boundary
+// nodes hanging off their owner): candidates sorted by (squared integer distance,
+// node index); the two nearest of every closed octant are chosen first, then the
+// nearest remaining ones up to min(count, m_cap).  Accepted (m > 0) when every
+// closed octant holds a chosen node and m >= p + 1; the rank test follows in a
+// separate kernel.  One thread per pending node; the ring lives in a per-thread
+// slice of global scratch.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_stencil(const int32_t *__restrict__ pending, int64_t np, int R, int m_cap, int p,
+              const int32_t *__restrict__ crd, int64_t ntot, int64_t n,
+              const int32_t *__restrict__ r1cnt, const int32_t *__restrict__ r1,
+              const int32_t *__restrict__ bowner, int32_t *__restrict__ lst_all,
+              int64_t *__restrict__ key_all, int32_t *__restrict__ cand, int32_t *__restrict__ mout,
+              int *__restrict__ err) {
+  int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (t >= np) return;
+  const int32_t y = pending[t];
+  int32_t *lst = lst_all + t * APC_RING_CAP;
+  int64_t *key = key_all + t * APC_RING_CAP;
+  int cnt = 0;
+  lst[cnt++] = y;
+  int lo = 0;
+  bool overflow = false;
+  for (int depth = 1; depth <= R && !overflow; depth++) {
+    const int hi = cnt;
+    for (int q = lo; q < hi && !overflow; q++) {
+      const int32_t u = lst[q];
+      int na;
+      const int32_t *adj;
+      int32_t own;
+      if (u >= n) {
+        own = bowner[u - n];
+        adj = &own;
+        na = 1;
+      } else {
+        adj = r1 + (int64_t)u * 24;
+        na = r1cnt[u];
+      }
+      for (int a = 0; a < na; a++) {
+        const int32_t v = adj[a];
+        bool seen = false;
+        for (int s = 0; s < cnt; s++)
+          if (lst[s] == v) {
+            seen = true;
+            break;
+          }
+        if (seen) continue;
+        if (cnt == APC_RING_CAP) {
+          overflow = true;
+          break;
+        }
+        lst[cnt++] = v;
+      }
+    }
+    lo = hi;
+  }
+  if (overflow) {
+    atomicOr(err, 8);
+    mout[t] = 0;
+    return;
+  }
+  const int32_t cy0 = crd[y], cy1 = crd[ntot + y], cy2 = crd[2 * ntot + y];
+  // candidates = lst[1..cnt); insertion sort by (r2, index)
+  for (int j = 1; j < cnt; j++) {
+    const int32_t v = lst[j];
+    const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
+    const int64_t k = d0 * d0 + d1 * d1 + d2 * d2;
+    int s = j - 1;
+    while (s >= 1 && (key[s] > k || (key[s] == k && lst[s] > v))) {
+      key[s + 1] = key[s];
+      lst[s + 1] = lst[s];
+      s--;
+    }
+    key[s + 1] = k;
+    lst[s + 1] = v;
+  }
+  const int nc = cnt - 1;
+  const int want = nc < m_cap ? nc : m_cap;
+  int got = 0;
+  // picked candidates are marked by storing -(v+1)
+  for (int o = 0; o < 8; o++) {
+    int taken = 0;
+    for (int j = 1; j < cnt && taken < 2; j++) {
+      int32_t v = lst[j];
+      const bool picked = v < 0;
+      if (picked) v = -v - 1;
+      const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
+      if (!in_octant(o, d0, d1, d2)) continue;
+      taken++;
+      if (!picked && got < want) {
+        lst[j] = -v - 1;
+        got++;
+      }
+    }
+  }
+  for (int j = 1; j < cnt && got < want; j++)
+    if (lst[j] >= 0) {
+      lst[j] = -lst[j] - 1;
+      got++;
+    }
+  int m = 0;
+  int oct[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+  int32_t *out = cand + t * APC_MAXM;
+  for (int j = 1; j < cnt; j++) {
+    if (lst[j] >= 0) continue;
+    const int32_t v = -lst[j] - 1;
+    if (m < APC_MAXM) out[m] = v;
+    m++;
+    const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
+    for (int o = 0; o < 8; o++) oct[o] += in_octant(o, d0, d1, d2);
+  }
+  bool ok = m >= p + 1 && m <= APC_MAXM;
+  for (int o = 0; o < 8; o++) ok = ok && oct[o] >= 1;
+  mout[t] = ok ? m : 0;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_accept(const int32_t *__restrict__ pending, int64_t np, const int32_t *__restrict__ cand,
+             const int32_t *__restrict__ m, int32_t *__restrict__ stbuf,
+             int32_t *__restrict__ mnode, int32_t *__restrict__ still) {
+  int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (t >= np) return;
+  const int32_t y = pending[t];
+  const int mm = m[t];
+  still[t] = mm > 0 ? 0 : 1;
+  if (mm <= 0) return;
+  mnode[y] = mm;
+  for (int j = 0; j < mm; j++) stbuf[(int64_t)y * APC_MAXM + j] = cand[t * APC_MAXM + j];
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_compact_idx(const int32_t *flag, const int32_t *off, const int32_t *src, int64_t n,
+                  int32_t *dst) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n && flag[i]) dst[off[i]] = src ? src[i] : (int32_t)i;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_csr_fill(const int32_t *__restrict__ stbuf, const int32_t *__restrict__ off, int64_t n,
+               int32_t *__restrict__ idx) {
+  int64_t e = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  // one thread per (node, slot) pair
+  const int64_t y = e / APC_MAXM;
+  const int j = (int)(e % APC_MAXM);
+  if (y >= n) return;
+  const int32_t a = off[y], b = off[y + 1];
+  if (j < b - a) idx[a + j] = stbuf[y * APC_MAXM + j];
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_leaf_out(const uint64_t *mc, const int32_t *lev, int64_t n, uint64_t *code, int32_t *level) {
+  int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y >= n) return;
+  code[y] = mc[y];
+  level[y] = lev[y];
+}
+
+// leaf of every sorted particle: the last leaf whose range starts at or before it
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_pnode(const int32_t *__restrict__ first, int64_t n, int64_t N, int32_t *__restrict__ pnode) {
+  int64_t s = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (s >= N) return;
+  int64_t lo = 0, hi = n;
+  while (lo < hi) {
+    int64_t mid = (lo + hi) >> 1;
+    if (first[mid] <= s)
+      lo = mid + 1;
+    else
+      hi = mid;
+  }
+  pnode[s] = (int32_t)(lo - 1);
+}
+
+template <typename T>
+int dalloc(T **p, int64_t n, hipStream_t s) {
+  HIPCHK(hipMallocAsync((void **)p, (size_t)(n > 0 ? n : 1) * sizeof(T), s));
+  return APC_OK;
+}
+template <typename T>
+int dfree(T *&p, hipStream_t s) {
+  if (p) HIPCHK(hipFreeAsync(p, s));
+  p = nullptr;
+  return APC_OK;
+}
+
+// flagged cells -> 8 children; returns the new list in `c`
+int expand(Cells &c, const uint64_t *keys, int D, const Thr &thr, int criterion, hipStream_t s) {
+  int32_t *sz = nullptr, *off = nullptr;
+  APCCHK(dalloc(&sz, c.n, s));
+  APCCHK(dalloc(&off, c.n, s));
+  hipLaunchKernelGGL(k_sizes, dim3(grid_for(c.n)), dim3(APC_BLOCK), 0, s, c.flag, c.n, sz);
+  HIPCHK(hipGetLastError());
+  APCCHK(apc_scan_i32(sz, off, c.n, s));
+  int32_t last[2];
+  HIPCHK(hipMemcpyAsync(&last[0], off + c.n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&last[1], sz + c.n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t m = (int64_t)last[0] + last[1];
+  Cells o;
+  APCCHK(cells_alloc(o, m, s));
+  hipLaunchKernelGGL(k_expand, dim3(grid_for(c.n)), dim3(APC_BLOCK), 0, s, c.pre, c.lev, c.fst,
+                     c.cnt, c.flag, off, c.n, keys, D, thr, criterion, o.pre, o.lev, o.fst, o.cnt,
+                     o.flag);
+  HIPCHK(hipGetLastError());
+  APCCHK(dfree(sz, s));
+  APCCHK(dfree(off, s));
+  APCCHK(cells_free(c, s));
+  c = o;
+  return APC_OK;
+}
+
+int read_err(int *err, hipStream_t s, int *host) {
+  HIPCHK(hipMemcpyAsync(host, err, sizeof(int), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return APC_OK;
+}
+
+void free_cloud_arrays(apc_cloud *c) {
+  void *ptrs[] = {c->perm, c->sxyz, c->pnode, c->code, c->level, c->first, c->count, c->crd,
+                  c->bowner, c->bface, c->st_off, c->st_idx};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+}
+
+} // namespace
+
+void apc_free_cloud(apc_cloud *c) {
+  if (!c) return;
+  apc_free_solver(c);
+  free_cloud_arrays(c);
+  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row};
+  for (void *q : ops)
+    if (q) (void)hipFree(q);
+  delete c;
+}
+
+static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
+  const apc_params &P = c->P;
+  const int D = P.max_depth;
+  const int64_t N = c->N;
+  Thr thr;
+  for (int l = 0; l < 24; l++) thr.T[l] = 0.0;
+  for (int l = 0; l <= D; l++) thr.T[l] = c->T[l];
+
+  // keys + sort
+  uint64_t *keys = nullptr;
+  int *err = nullptr;
+  APCCHK(dalloc(&keys, N, s));
+  HIPCHK(hipMalloc((void **)&c->perm, (size_t)N * sizeof(int32_t)));
+  APCCHK(dalloc(&err, 1, s));
+  HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+  const double scale = ldexp(1.0, D) / P.L;
+  hipLaunchKernelGGL(k_keys, dim3(grid_for(N)), dim3(APC_BLOCK), 0, s, xyz, N, P.lo[0], P.lo[1],
+                     P.lo[2], P.L, scale, D, keys, c->perm, err);
+  HIPCHK(hipGetLastError());
+  int herr = 0;
+  APCCHK(read_err(err, s, &herr));
+  if (herr & 1) return APC_EINVAL;
+  if (herr & 2) return APC_EDOMAIN;
+  APCCHK(apc_radix_sort(keys, c->perm, N, 3 * D, s));
+
+  // criterion phase, one level per pass
+  Cells cl;
+  APCCHK(cells_alloc(cl, 1, s));
+  {
+    const uint64_t z = 0;
+    const int32_t zi = 0, n32 = (int32_t)N;
+    const int32_t op = (0 < D && (double)N >= c->T[0]) ? 1 : 0;
+    HIPCHK(hipMemcpyAsync(cl.pre, &z, sizeof(z), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cl.lev, &zi, sizeof(zi), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cl.fst, &zi, sizeof(zi), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cl.cnt, &n32, sizeof(n32), hipMemcpyHostToDevice, s));
+    HIPCHK(hipMemcpyAsync(cl.flag, &op, sizeof(op), hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+  }
+  int64_t opened = 0;
+  for (;;) {
+    int64_t nf = 0;
+    APCCHK(apc_sum_i32(cl.flag, cl.n, &nf, s));
+    if (nf == 0) break;
+    opened += nf;
+    APCCHK(expand(cl, keys, D, thr, 1, s));
+  }
+  // balance phase: mark, expand, repeat until no leaf is marked
+  uint64_t *mc = nullptr;
+  for (;;) {
+    APCCHK(dfree(mc, s));
+    APCCHK(dalloc(&mc, cl.n, s));
+    hipLaunchKernelGGL(k_mincorner, dim3(grid_for(cl.n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev,
+                       cl.n, D, mc);
+    HIPCHK(hipMemsetAsync(cl.flag, 0, (size_t)cl.n * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_balance_mark, dim3(grid_for(cl.n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev,
+                       mc, cl.n, D, cl.flag);
+    HIPCHK(hipGetLastError());
+    int64_t nm = 0;
+    APCCHK(apc_sum_i32(cl.flag, cl.n, &nm, s));
+    if (nm == 0) break;
+    opened += nm;
+    APCCHK(expand(cl, keys, D, thr, 0, s));
+  }
+  const int64_t n = cl.n;
+  c->n = n;
+  c->n_opened = opened;
+
+  // leaves
+  HIPCHK(hipMalloc((void **)&c->code, (size_t)n * sizeof(uint64_t)));
+  HIPCHK(hipMalloc((void **)&c->level, (size_t)n * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->first, (size_t)n * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->count, (size_t)n * sizeof(int32_t)));
+  hipLaunchKernelGGL(k_leaf_out, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, mc, cl.lev, n, c->code,
+                     c->level);
+  HIPCHK(hipMemcpyAsync(c->first, cl.fst, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  HIPCHK(hipMemcpyAsync(c->count, cl.cnt, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+
+  // boundary nodes
+  int32_t *bcnt = nullptr, *bstart = nullptr;
+  APCCHK(dalloc(&bcnt, n, s));
+  APCCHK(dalloc(&bstart, n, s));
+  hipLaunchKernelGGL(k_bcount, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, n, bcnt);
+  APCCHK(apc_scan_i32(bcnt, bstart, n, s));
+  int32_t last[2];
+  HIPCHK(hipMemcpyAsync(&last[0], bstart + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&last[1], bcnt + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t nb = (int64_t)last[0] + last[1];
+  c->nb = nb;
+  const int64_t ntot = n + nb;
+  HIPCHK(hipMalloc((void **)&c->crd, (size_t)3 * ntot * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->bowner, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->bface, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
+  hipLaunchKernelGGL(k_nodes, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, bstart, n,
+                     ntot, D, c->crd, c->bowner, c->bface);
+  HIPCHK(hipGetLastError());
+
+  // 1-ring adjacency
+  int32_t *r1cnt = nullptr, *r1 = nullptr;
+  APCCHK(dalloc(&r1cnt, n, s));
+  APCCHK(dalloc(&r1, n * 24, s));
+  HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_ring1, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, mc, bstart,
+                     n, D, r1cnt, r1, err);
+  HIPCHK(hipGetLastError());
+  APCCHK(read_err(err, s, &herr));
+  if (herr) return APC_EINVAL; // an unbalanced face: cannot happen after the balance phase
+  APCCHK(dfree(bcnt, s));
+  APCCHK(dfree(bstart, s));
+  APCCHK(dfree(mc, s));
+  APCCHK(cells_free(cl, s));
+
+  // stencils, ring by ring over the nodes still pending
+  int32_t *stbuf = nullptr, *mnode = nullptr, *pending = nullptr;
+  APCCHK(dalloc(&stbuf, n * APC_MAXM, s));
+  APCCHK(dalloc(&mnode, n, s));
+  APCCHK(dalloc(&pending, n, s));
+  HIPCHK(hipMemsetAsync(mnode, 0, (size_t)n * sizeof(int32_t), s));
+  {
+    std::vector<int32_t> h(0);
+    // pending = 0..n-1
+    int32_t *ones = nullptr, *offs = nullptr;
+    APCCHK(dalloc(&ones, n, s));
+    APCCHK(dalloc(&offs, n, s));
+    // all flags 1 -> compaction yields the identity list
+    hipLaunchKernelGGL(k_sizes, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, mnode, n, ones);
+    // k_sizes writes 1 where mnode == 0 (all), 8 otherwise (none)
+    APCCHK(apc_scan_i32(ones, offs, n, s));
+    hipLaunchKernelGGL(k_compact_idx, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, ones, offs,
+                       (const int32_t *)nullptr, n, pending);
+    HIPCHK(hipGetLastError());
+    APCCHK(dfree(ones, s));
+    APCCHK(dfree(offs, s));
+  }
+  int64_t np = n;
+  const int64_t CH = 32768; // nodes per ring-search chunk (scratch ~ CH * 24 KB)
+  int32_t *lst = nullptr, *cand = nullptr, *mch = nullptr, *still = nullptr, *soff = nullptr,
+          *npend = nullptr;
+  int64_t *key = nullptr;
+  APCCHK(dalloc(&lst, CH * APC_RING_CAP, s));
+  APCCHK(dalloc(&key, CH * APC_RING_CAP, s));
+  APCCHK(dalloc(&cand, CH * APC_MAXM, s));
+  APCCHK(dalloc(&mch, CH, s));
+  APCCHK(dalloc(&still, n, s));
+  APCCHK(dalloc(&soff, n, s));
+  APCCHK(dalloc(&npend, n, s));
+  for (int R = P.ring_min; R <= P.ring_max && np > 0; R++) {
+    HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+    for (int64_t c0 = 0; c0 < np; c0 += CH) {
+      const int64_t cn = (np - c0) < CH ? (np - c0) : CH;
+      hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, R,
+                         P.m_cap, c->p, c->crd, ntot, n, r1cnt, r1, c->bowner, lst, key, cand, mch,
+                         err);
+      HIPCHK(hipGetLastError());
+      APCCHK(apc_rank_check(c, pending + c0, cn, cand, mch, s));
+      hipLaunchKernelGGL(k_accept, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, cand,
+                         mch, stbuf, mnode, still + c0);
+      HIPCHK(hipGetLastError());
+    }
+    APCCHK(read_err(err, s, &herr));
+    if (herr) return APC_EINVAL; // ring larger than the search capacity
+    APCCHK(apc_scan_i32(still, soff, np, s));
+    int64_t left = 0;
+    APCCHK(apc_sum_i32(still, np, &left, s));
+    hipLaunchKernelGGL(k_compact_idx, dim3(grid_for(np)), dim3(APC_BLOCK), 0, s, still, soff,
+                       pending, np, npend);
+    HIPCHK(hipGetLastError());
+    int32_t *tmp = pending;
+    pending = npend;
+    npend = tmp;
+    np = left;
+  }
+  APCCHK(dfree(lst, s));
+  APCCHK(dfree(key, s));
+  APCCHK(dfree(cand, s));
+  APCCHK(dfree(mch, s));
+  APCCHK(dfree(still, s));
+  APCCHK(dfree(soff, s));
+  APCCHK(dfree(npend, s));
+  APCCHK(dfree(pending, s));
+  APCCHK(dfree(r1cnt, s));
+  APCCHK(dfree(r1, s));
+  if (np > 0) return APC_ESTENCIL;
+
+  // stencil CSR
+  HIPCHK(hipMalloc((void **)&c->st_off, (size_t)(n + 1) * sizeof(int32_t)));
+  APCCHK(apc_scan_i32(mnode, c->st_off, n, s));
+  int32_t lastm[2];
+  HIPCHK(hipMemcpyAsync(&lastm[0], c->st_off + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&lastm[1], mnode + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  const int64_t nnz = (int64_t)lastm[0] + lastm[1];
+  c->nnz = nnz;
+  const int32_t nnz32 = (int32_t)nnz;
+  HIPCHK(hipMemcpyAsync(c->st_off + n, &nnz32, sizeof(int32_t), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMalloc((void **)&c->st_idx, (size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
+  hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n * APC_MAXM)), dim3(APC_BLOCK), 0, s, stbuf,
+                     c->st_off, n, c->st_idx);
+  HIPCHK(hipGetLastError());
+  APCCHK(dfree(stbuf, s));
+  APCCHK(dfree(mnode, s));
+
+  // particles: leaf of each sorted particle, sorted positions
+  HIPCHK(hipMalloc((void **)&c->pnode, (size_t)N * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->sxyz, (size_t)3 * N * sizeof(double)));
+  hipLaunchKernelGGL(k_pnode, dim3(grid_for(N)), dim3(APC_BLOCK), 0, s, c->first, n, N, c->pnode);
+  hipLaunchKernelGGL(k_gather_xyz, dim3(grid_for(N)), dim3(APC_BLOCK), 0, s, xyz, c->perm, N,
+                     c->sxyz);
+  HIPCHK(hipGetLastError());
+  APCCHK(dfree(keys, s));
+  APCCHK(dfree(err, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return APC_OK;
+}
+
+int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_t s,
+                   apc_cloud **out) {
+  *out = nullptr;
+  if (!p || !xyz || N < 1 || N > INT32_MAX) return APC_EINVAL;
+  if (p->order != 2) return APC_EINVAL;
+  if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
+      p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 ||
+      !(p->precision == APC_FP64 || p->precision == APC_MIXED) || !std::isfinite(p->poisson_c))
+    return APC_EINVAL;
+  apc_cloud *c = new apc_cloud();
+  c->P = *p;
+  HIPCHK(hipGetDevice(&c->device));
+  c->N = N;
+  c->p = 9;
+  c->unit = p->L / ldexp(1.0, p->max_depth + 1);
+  // T_l = t^(2k-2), t = (c 2^l) / L, by repeated multiplication from 1.0
+  for (int l = 0; l < 24; l++) {
+    double t = (p->c * ldexp(1.0, l)) / p->L;
+    double v = 1.0;
+    for (int e = 0; e < 2 * p->order - 2; e++) v *= t;
+    c->T[l] = v;
+  }
+  int rc = build_body(c, xyz, s);
+  if (rc != APC_OK) {
+    (void)hipStreamSynchronize(s);
+    apc_free_cloud(c);
+    return rc;
+  }
+  *out = c;
+  return APC_OK;
+}

@@ -1,0 +1,206 @@
+// Device-wide primitives used by the cloud build: exclusive scan, integer sum and
+// a stable LSD radix sort of (64-bit key, 32-bit value) pairs.
+#include <hip/hip_runtime.h>
+
+#include "apc_internal.h"
+
+namespace {
+
+constexpr int SCAN_IPT = 8;
+constexpr int SCAN_TILE = APC_BLOCK * SCAN_IPT;
+
+// One tile of 2048 elements per block: per-thread serial sums, wave64 shuffle
+// scan of the thread totals, 4 wave totals combined through LDS.
+template <typename T>
+__global__ void __launch_bounds__(APC_BLOCK) k_scan_tile(const T *in, T *out, T *bsum, int64_t n) {
+  __shared__ T wsum[APC_BLOCK / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE + (int64_t)threadIdx.x * SCAN_IPT;
+  T v[SCAN_IPT];
+  T tot = 0;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; i++) {
+    int64_t idx = base + i;
+    v[i] = idx < n ? in[idx] : (T)0;
+    tot += v[i];
+  }
+  T x = tot;
+#pragma unroll
+  for (int o = 1; o < 64; o <<= 1) {
+    T y = __shfl_up(x, o, 64);
+    if (lane >= o) x += y;
+  }
+  if (lane == 63) wsum[w] = x;
+  __syncthreads();
+  T wpre = 0;
+  for (int k = 0; k < w; k++) wpre += wsum[k];
+  T run = wpre + x - tot;
+#pragma unroll
+  for (int i = 0; i < SCAN_IPT; i++) {
+    int64_t idx = base + i;
+    if (idx < n) out[idx] = run;
+    run += v[i];
+  }
+  if (threadIdx.x == APC_BLOCK - 1) bsum[blockIdx.x] = wpre + x;
+}
+
+template <typename T>
+__global__ void __launch_bounds__(APC_BLOCK) k_scan_add(T *out, const T *boff, int64_t n) {
+  const int64_t base = (int64_t)blockIdx.x * SCAN_TILE;
+  const T add = boff[blockIdx.x];
+  for (int i = threadIdx.x; i < SCAN_TILE; i += APC_BLOCK) {
+    int64_t idx = base + i;
+    if (idx < n) out[idx] += add;
+  }
+}
+
+template <typename T>
+int scan_rec(const T *in, T *out, int64_t n, hipStream_t s) {
+  if (n <= 0) return APC_OK;
+  const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+  T *bsum = nullptr;
+  HIPCHK(hipMallocAsync((void **)&bsum, (size_t)nb * sizeof(T), s));
+  hipLaunchKernelGGL(k_scan_tile<T>, dim3((unsigned)nb), dim3(APC_BLOCK), 0, s, in, out, bsum, n);
+  HIPCHK(hipGetLastError());
+  if (nb > 1) {
+    int rc = scan_rec<T>(bsum, bsum, nb, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)nb), dim3(APC_BLOCK), 0, s, out, bsum, n);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipFreeAsync(bsum, s));
+  return APC_OK;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK) k_sum_i32(const int32_t *in, int64_t n,
+                                                       unsigned long long *acc) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  long long v = 0;
+  for (; i < n; i += (int64_t)gridDim.x * APC_BLOCK) v += in[i];
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
+  if ((threadIdx.x & 63) == 0 && v) atomicAdd(acc, (unsigned long long)v);
+}
+
+// ---------------------------------------------------------------- radix sort
+// Each wavefront owns a tile of RS_TILE consecutive keys.  Pass 1 counts the 8-bit
+// digit of every tile; the digit-major table of counts is scanned; pass 2 revisits
+// each tile in the same order and places every key at its digit's running offset
+// plus its rank among equal digits of lower lanes (ballot match), which keeps the
+// sort stable.
+constexpr int RS_IPT = 16;
+constexpr int RS_TILE = 64 * RS_IPT;
+constexpr int RS_WAVES = APC_BLOCK / 64;
+
+__global__ void __launch_bounds__(APC_BLOCK) k_rs_hist(const uint64_t *keys, int64_t n, int shift,
+                                                       int64_t ntiles, int32_t *hist) {
+  __shared__ int32_t cnt[RS_WAVES][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * RS_WAVES + w;
+  for (int d = lane; d < 256; d += 64) cnt[w][d] = 0;
+  __syncthreads();
+  if (tile < ntiles) {
+    for (int r = 0; r < RS_IPT; r++) {
+      int64_t idx = tile * RS_TILE + r * 64 + lane;
+      if (idx < n) atomicAdd(&cnt[w][(keys[idx] >> shift) & 255u], 1);
+    }
+  }
+  __syncthreads();
+  if (tile < ntiles)
+    for (int d = lane; d < 256; d += 64) hist[(int64_t)d * ntiles + tile] = cnt[w][d];
+}
+
+__global__ void __launch_bounds__(APC_BLOCK) k_rs_scatter(const uint64_t *kin, const int32_t *vin,
+                                                          uint64_t *kout, int32_t *vout, int64_t n,
+                                                          int shift, int64_t ntiles,
+                                                          const int32_t *offs) {
+  __shared__ int32_t run[RS_WAVES][256];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t tile = (int64_t)blockIdx.x * RS_WAVES + w;
+  if (tile < ntiles)
+    for (int d = lane; d < 256; d += 64) run[w][d] = offs[(int64_t)d * ntiles + tile];
+  __syncthreads();
+  if (tile >= ntiles) return;
+  const uint64_t below = (1ull << lane) - 1ull;
+  for (int r = 0; r < RS_IPT; r++) {
+    const int64_t idx = tile * RS_TILE + r * 64 + lane;
+    const bool valid = idx < n;
+    const uint64_t key = valid ? kin[idx] : 0ull;
+    const int32_t val = valid ? vin[idx] : 0;
+    const unsigned d = (unsigned)(key >> shift) & 255u;
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int b = 0; b < 8; b++) {
+      const int bit = (d >> b) & 1u;
+      const uint64_t bal = __ballot(bit);
+      peers &= bit ? bal : ~bal;
+    }
+    const int32_t base = run[w][d];
+    if (valid) {
+      const int32_t pos = base + __popcll(peers & below);
+      kout[pos] = key;
+      vout[pos] = val;
+      if ((peers >> lane) == 1ull) run[w][d] = base + __popcll(peers);
+    }
+  }
+}
+
+} // namespace
+
+int apc_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s) {
+  return scan_rec<int32_t>(in, out, n, s);
+}
+int apc_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
+  return scan_rec<int64_t>(in, out, n, s);
+}
+
+int apc_sum_i32(const int32_t *in, int64_t n, int64_t *host_out, hipStream_t s) {
+  unsigned long long *acc = nullptr;
+  HIPCHK(hipMallocAsync((void **)&acc, sizeof(unsigned long long), s));
+  HIPCHK(hipMemsetAsync(acc, 0, sizeof(unsigned long long), s));
+  unsigned g = grid_for(n);
+  if (g > 4096) g = 4096;
+  hipLaunchKernelGGL(k_sum_i32, dim3(g), dim3(APC_BLOCK), 0, s, in, n, acc);
+  HIPCHK(hipGetLastError());
+  unsigned long long h = 0;
+  HIPCHK(hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipFreeAsync(acc, s));
+  *host_out = (int64_t)h;
+  return APC_OK;
+}
+
+int apc_radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s) {
+  if (n <= 1 || bits <= 0) return APC_OK;
+  const int64_t ntiles = (n + RS_TILE - 1) / RS_TILE;
+  const unsigned nblk = (unsigned)((ntiles + RS_WAVES - 1) / RS_WAVES);
+  uint64_t *k2 = nullptr;
+  int32_t *v2 = nullptr, *hist = nullptr;
+  HIPCHK(hipMallocAsync((void **)&k2, (size_t)n * sizeof(uint64_t), s));
+  HIPCHK(hipMallocAsync((void **)&v2, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(hipMallocAsync((void **)&hist, (size_t)ntiles * 256 * sizeof(int32_t), s));
+  uint64_t *ka = keys, *kb = k2;
+  int32_t *va = vals, *vb = v2;
+  for (int shift = 0; shift < bits; shift += 8) {
+    hipLaunchKernelGGL(k_rs_hist, dim3(nblk), dim3(APC_BLOCK), 0, s, ka, n, shift, ntiles, hist);
+    HIPCHK(hipGetLastError());
+    int rc = apc_scan_i32(hist, hist, ntiles * 256, s);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_rs_scatter, dim3(nblk), dim3(APC_BLOCK), 0, s, ka, va, kb, vb, n, shift,
+                       ntiles, hist);
+    HIPCHK(hipGetLastError());
+    uint64_t *tk = ka;
+    ka = kb;
+    kb = tk;
+    int32_t *tv = va;
+    va = vb;
+    vb = tv;
+  }
+  if (ka != keys) {
+    HIPCHK(hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(vals, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
+  }
+  HIPCHK(hipFreeAsync(k2, s));
+  HIPCHK(hipFreeAsync(v2, s));
+  HIPCHK(hipFreeAsync(hist, s));
+  return APC_OK;
+}

@@ -1,0 +1,656 @@
+// Charge deposit and Krylov solves on gfx950.
+//
+// Operators are applied in difference form, (A x)_i = a_i x_i + s_i sum_j w_ij (x_j - x_i)
+// with (a, s) = (0, 1) for the GFD Laplacian and (1, h_c^2/24) for the k = 2
+// density operator B = I + diag(h_c^2/24) L.  Row sums of L are zero by
+// construction (the constant is removed by differencing in the GFD fit), so this
+// form never forms the large diagonal and stays accurate when x is smooth, also
+// with FP32 weights.  Krylov vectors have n + nb entries; the boundary tail stays
+// zero, boundary data enter through the right-hand side.
+//
+// BiCGSTAB runs as 8 kernels per iteration: 2 SpMV with fused dot products, 3
+// fused vector updates and 3 one-block finalize kernels.  Dot products are
+// reduced deterministically (per-block partials, then a fixed-order sum) and the
+// solver scalars live on the device, so the host only polls a status word every
+// few iterations.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+
+#include "apc_internal.h"
+
+namespace {
+
+enum { V64 = 0, V32A32 = 1, V32A64 = 2 }; // value type / arithmetic of the SpMV
+
+struct Scal {
+  double rho, alpha, omega, beta;
+  double bnorm, rnorm, rtrue;
+  double rv, ts, tt;
+  double tol;
+  int it, maxit, done, pad;
+};
+
+struct Op {
+  const int32_t *off;
+  const int32_t *idx;
+  const double *w64;
+  const float *w32;
+  const double *hs; // nullptr => Laplacian
+  int64_t n;
+};
+
+constexpr int GL = 8;                 // lanes per matrix row
+constexpr int RPB = APC_BLOCK / GL;   // rows per block
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  return v;
+}
+
+// Reductions: kernels that produce dot products run on a capped grid of GRED
+// blocks (grid-stride) and store one partial per block; a one-block finalize
+// kernel sums the partials in a fixed order and updates the solver scalars.  No
+// atomics or device-scope fences inside kernels (the 8 XCD L2s are not coherent
+// with each other within a kernel); kernel boundaries order everything.
+constexpr unsigned GRED = 2048;
+
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double *part) {
+  __shared__ double sh[NV][APC_BLOCK / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    const double s = wave_sum(v[k]);
+    if (lane == 0) sh[k][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      double s = 0.0;
+      for (int q = 0; q < APC_BLOCK / 64; q++) s += sh[k][q];
+      part[(size_t)k * gridDim.x + blockIdx.x] = s;
+    }
+  }
+}
+
+// sum of partials part[k*G .. k*G+G) in one block, fixed order; valid in thread 0
+template <int NV>
+__device__ __forceinline__ void fin_sum(const double *part, unsigned G, double (&out)[NV]) {
+  __shared__ double sh[NV][APC_BLOCK / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+#pragma unroll
+  for (int k = 0; k < NV; k++) {
+    double s = 0.0;
+    for (unsigned q = threadIdx.x; q < G; q += APC_BLOCK) s += part[(size_t)k * G + q];
+    s = wave_sum(s);
+    if (lane == 0) sh[k][w] = s;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+#pragma unroll
+    for (int k = 0; k < NV; k++) {
+      double t = 0.0;
+      for (int q = 0; q < APC_BLOCK / 64; q++) t += sh[k][q];
+      out[k] = t;
+    }
+  }
+}
+
+// Row blocks (RPB rows each) are split into 8 contiguous ranges, one per XCD
+// (blocks are dealt round-robin over the 8 XCDs), so that neighbour gathers reuse
+// the XCD's own L2; within a range the XCD's blocks stride over row blocks.
+struct RowIter {
+  int64_t rb, end, step;
+};
+__device__ __forceinline__ RowIter row_iter(int64_t n) {
+  const int64_t nrb = (n + RPB - 1) / RPB;
+  const int64_t per = (nrb + 7) / 8;
+  const int64_t x = blockIdx.x & 7u, j = blockIdx.x >> 3;
+  RowIter it;
+  it.rb = x * per + j;
+  it.end = (x + 1) * per < nrb ? (x + 1) * per : nrb;
+  it.step = gridDim.x >> 3;
+  return it;
+}
+static inline unsigned spmv_grid(int64_t n) {
+  const int64_t nrb = (n + RPB - 1) / RPB;
+  int64_t g = ((nrb + 7) / 8) * 8;
+  return (unsigned)(g < (int64_t)GRED ? g : (int64_t)GRED);
+}
+static inline unsigned vec_grid(int64_t n) {
+  const unsigned g = grid_for(n);
+  return g < GRED ? g : GRED;
+}
+
+// y_i for row i, computed by the GL lanes of one group; result valid in all lanes.
+template <int MODE>
+__device__ __forceinline__ double op_row(const Op &op, const double *__restrict__ x, int64_t i,
+                                         int gl) {
+  const int32_t a = op.off[i], b = op.off[i + 1];
+  const double xi = x[i];
+  double acc;
+  if (MODE == V32A32) {
+    float af = 0.0f;
+    for (int32_t e = a + gl; e < b; e += GL) af += op.w32[e] * (float)(x[op.idx[e]] - xi);
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) af += __shfl_xor(af, o, GL);
+    acc = (double)af;
+  } else {
+    double ad = 0.0;
+    for (int32_t e = a + gl; e < b; e += GL) {
+      const double w = (MODE == V64) ? op.w64[e] : (double)op.w32[e];
+      ad += w * (x[op.idx[e]] - xi);
+    }
+#pragma unroll
+    for (int o = GL / 2; o > 0; o >>= 1) ad += __shfl_xor(ad, o, GL);
+    acc = ad;
+  }
+  return op.hs ? xi + op.hs[i] * acc : acc;
+}
+
+// ---------------------------------------------------------------- BiCGSTAB kernels
+// v = A ph ; partial (rh, v)
+template <int MODE>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_spmv_v(Op op, const double *__restrict__ ph, double *__restrict__ v,
+             const double *__restrict__ rh, double *part, const Scal *sc) {
+  if (sc->done) return;
+  const int gl = threadIdx.x % GL;
+  double val[1] = {0.0};
+  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
+    const int64_t i = it.rb * RPB + threadIdx.x / GL;
+    if (i < op.n) {
+      const double y = op_row<MODE>(op, ph, i, gl);
+      if (gl == 0) {
+        v[i] = y;
+        val[0] += rh[i] * y;
+      }
+    }
+  }
+  block_partials<1>(val, part);
+}
+
+// t = A sh ; partials (t, s), (t, t)
+template <int MODE>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_spmv_t(Op op, const double *__restrict__ sh, const double *__restrict__ s,
+             double *__restrict__ t, double *part, const Scal *sc) {
+  if (sc->done) return;
+  const int gl = threadIdx.x % GL;
+  double val[2] = {0.0, 0.0};
+  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
+    const int64_t i = it.rb * RPB + threadIdx.x / GL;
+    if (i < op.n) {
+      const double y = op_row<MODE>(op, sh, i, gl);
+      if (gl == 0) {
+        t[i] = y;
+        val[0] += y * s[i];
+        val[1] += y * y;
+      }
+    }
+  }
+  block_partials<2>(val, part);
+}
+
+// alpha = rho / (rh, v)
+__global__ void __launch_bounds__(APC_BLOCK) k_fin_alpha(const double *part, unsigned G, Scal *sc) {
+  if (sc->done) return;
+  double out[1];
+  fin_sum<1>(part, G, out);
+  if (threadIdx.x == 0) {
+    sc->rv = out[0];
+    const double al = sc->rho / out[0];
+    if (out[0] == 0.0 || !isfinite(al))
+      sc->done = 2;
+    else
+      sc->alpha = al;
+  }
+}
+
+// omega = (t, s) / (t, t)
+__global__ void __launch_bounds__(APC_BLOCK) k_fin_omega(const double *part, unsigned G, Scal *sc) {
+  if (sc->done) return;
+  double out[2];
+  fin_sum<2>(part, G, out);
+  if (threadIdx.x == 0) {
+    sc->ts = out[0];
+    sc->tt = out[1];
+    sc->omega = out[1] > 0.0 ? out[0] / out[1] : 0.0;
+  }
+}
+
+// p = r + beta (p - omega v); ph = M p
+template <bool JAC>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_upd_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+            const double *__restrict__ v, double *__restrict__ ph,
+            const double *__restrict__ invd, const Scal *sc) {
+  if (sc->done) return;
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const double pi = r[i] + sc->beta * (p[i] - sc->omega * v[i]);
+  p[i] = pi;
+  if (JAC) ph[i] = pi * invd[i];
+}
+
+// s = r - alpha v; sh = M s
+template <bool JAC>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_upd_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+            double *__restrict__ s, double *__restrict__ sh, const double *__restrict__ invd,
+            const Scal *sc) {
+  if (sc->done) return;
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const double si = r[i] - sc->alpha * v[i];
+  s[i] = si;
+  if (JAC) sh[i] = si * invd[i];
+}
+
+// x += alpha ph + omega sh; r = s - omega t; partials (rh, r), (r, r)
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_upd_xr(int64_t n, double *__restrict__ x, const double *__restrict__ ph,
+             const double *__restrict__ sh, const double *__restrict__ s,
+             const double *__restrict__ t, double *__restrict__ r,
+             const double *__restrict__ rh, double *part, const Scal *sc) {
+  if (sc->done) return;
+  const double al = sc->alpha, om = sc->omega;
+  double val[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * APC_BLOCK) {
+    x[i] += al * ph[i] + om * sh[i];
+    const double ri = s[i] - om * t[i];
+    r[i] = ri;
+    val[0] += rh[i] * ri;
+    val[1] += ri * ri;
+  }
+  block_partials<2>(val, part);
+}
+
+// rho' = (rh, r): convergence test, beta for the next iteration
+__global__ void __launch_bounds__(APC_BLOCK) k_fin_rho(const double *part, unsigned G, Scal *sc) {
+  if (sc->done) return;
+  double out[2];
+  fin_sum<2>(part, G, out);
+  if (threadIdx.x == 0) {
+    const double rho_new = out[0];
+    const double al = sc->alpha, om = sc->omega;
+    sc->rnorm = sqrt(out[1]);
+    sc->it += 1;
+    if (sc->rnorm <= sc->tol * sc->bnorm) {
+      sc->done = 1;
+    } else if (rho_new == 0.0 || om == 0.0 || !isfinite(rho_new)) {
+      sc->done = 2;
+    } else if (sc->it >= sc->maxit) {
+      sc->done = 3;
+    } else {
+      sc->beta = (rho_new / sc->rho) * (al / om);
+      sc->rho = rho_new;
+    }
+  }
+}
+
+// (re)start from x: r = b - A x (true residual, arithmetic MODE), rh = r, p = v = 0;
+// partials (r, r), (b, b)
+template <int MODE>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_restart(Op op, const double *__restrict__ b, const double *__restrict__ x,
+              double *__restrict__ r, double *__restrict__ rh, double *__restrict__ p,
+              double *__restrict__ v, double *part, int first) {
+  const int gl = threadIdx.x % GL;
+  double val[2] = {0.0, 0.0};
+  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
+    const int64_t i = it.rb * RPB + threadIdx.x / GL;
+    if (i < op.n) {
+      const double y = first ? 0.0 : op_row<MODE>(op, x, i, gl);
+      if (gl == 0) {
+        const double ri = b[i] - y;
+        r[i] = ri;
+        rh[i] = ri;
+        p[i] = 0.0;
+        v[i] = 0.0;
+        val[0] += ri * ri;
+        val[1] += b[i] * b[i];
+      }
+    }
+  }
+  block_partials<2>(val, part);
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_fin_restart(const double *part, unsigned G, Scal *sc, int first) {
+  double out[2];
+  fin_sum<2>(part, G, out);
+  if (threadIdx.x == 0) {
+    if (first) sc->bnorm = sqrt(out[1]);
+    sc->rho = out[0];
+    sc->rnorm = sqrt(out[0]);
+    sc->rtrue = sc->bnorm > 0.0 ? sc->rnorm / sc->bnorm : 0.0;
+    sc->beta = 0.0;
+    sc->alpha = 1.0;
+    sc->omega = 1.0;
+    sc->done = (sc->bnorm == 0.0 || sc->rnorm <= sc->tol * sc->bnorm) ? 1 : 0;
+  }
+}
+
+// ---------------------------------------------------------------- right-hand sides
+// Poisson: b_i = c rho_i - sum_{j boundary} w_ij g_j
+// Density: b_i = rhoM_i - hs_i sum_{j boundary} w_ij rhoM_j
+template <int MODE>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_rhs(Op op, int64_t n, const double *__restrict__ src, double srcscale,
+          const double *__restrict__ bval, double *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  double acc = 0.0;
+  if (bval) {
+    for (int32_t e = op.off[i]; e < op.off[i + 1]; e++) {
+      const int32_t j = op.idx[e];
+      if (j >= n) acc += ((MODE == V64) ? op.w64[e] : (double)op.w32[e]) * bval[j - n];
+    }
+  }
+  b[i] = srcscale * src[i] - (op.hs ? op.hs[i] * acc : acc);
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_write_out(int64_t n, int64_t nb, const double *__restrict__ x,
+                const double *__restrict__ bval, double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n)
+    out[i] = x[i];
+  else if (i < n + nb)
+    out[i] = bval ? bval[i - n] : 0.0;
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_apply(Op op, const double *__restrict__ x, double *__restrict__ y) {
+  const int gl = threadIdx.x % GL;
+  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
+    const int64_t i = it.rb * RPB + threadIdx.x / GL;
+    if (i < op.n) {
+      const double v = op_row<MODE>(op, x, i, gl);
+      if (gl == 0) y[i] = v;
+    }
+  }
+}
+
+// NGP deposit: rho_M_j = (sum of the charges in cell j) / h_j^3
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_deposit(int64_t n, int64_t N, const int32_t *__restrict__ first,
+              const int32_t *__restrict__ count, const int32_t *__restrict__ level,
+              const int32_t *__restrict__ perm, const double *__restrict__ q, double L,
+              double *__restrict__ rho) {
+  const int64_t j = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (j >= n) return;
+  double sum;
+  if (q) {
+    sum = 0.0;
+    const int32_t a = first[j], b = a + count[j];
+    for (int32_t s = a; s < b; s++) sum += q[perm[s]];
+  } else {
+    sum = (double)count[j] * (1.0 / (double)N);
+  }
+  const double hc = L / (double)(1 << level[j]);
+  rho[j] = sum / (hc * hc * hc);
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_bnd_copy(int64_t n, int64_t nb, const int32_t *__restrict__ bowner, double *__restrict__ v) {
+  const int64_t b = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (b < nb) v[n + b] = v[bowner[b]];
+}
+
+} // namespace
+
+// ---------------------------------------------------------------- workspace
+struct apc_solver_ws {
+  int64_t n = 0, ntot = 0;
+  double *x = nullptr, *r = nullptr, *rh = nullptr, *p = nullptr, *v = nullptr, *s = nullptr,
+         *t = nullptr, *ph = nullptr, *sh = nullptr, *b = nullptr;
+  double *part = nullptr;
+  Scal *sc = nullptr;
+  Scal *sc_host = nullptr;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+};
+
+void apc_free_solver(apc_cloud *c) {
+  apc_solver_ws *w = c->ws;
+  if (!w) return;
+  double *vs[] = {w->x, w->r, w->rh, w->p, w->v, w->s, w->t, w->ph, w->sh, w->b, w->part};
+  for (double *q : vs)
+    if (q) (void)hipFree(q);
+  if (w->sc) (void)hipFree(w->sc);
+  if (w->sc_host) (void)hipHostFree(w->sc_host);
+  if (w->e0) (void)hipEventDestroy(w->e0);
+  if (w->e1) (void)hipEventDestroy(w->e1);
+  delete w;
+  c->ws = nullptr;
+}
+
+static int ensure_ws(apc_cloud *c) {
+  if (c->ws) return APC_OK;
+  apc_solver_ws *w = new apc_solver_ws();
+  c->ws = w;
+  w->n = c->n;
+  w->ntot = c->n + c->nb;
+  const size_t bytes = (size_t)w->ntot * sizeof(double);
+  double **vs[] = {&w->x, &w->r, &w->rh, &w->p, &w->v, &w->s, &w->t, &w->ph, &w->sh, &w->b};
+  for (double **q : vs) {
+    HIPCHK(hipMalloc((void **)q, bytes));
+    HIPCHK(hipMemset(*q, 0, bytes)); // boundary tails stay zero for good
+  }
+  HIPCHK(hipMalloc((void **)&w->part, 2 * (size_t)GRED * sizeof(double)));
+  HIPCHK(hipMalloc((void **)&w->sc, sizeof(Scal)));
+  HIPCHK(hipMemset(w->sc, 0, sizeof(Scal)));
+  HIPCHK(hipHostMalloc((void **)&w->sc_host, sizeof(Scal), hipHostMallocDefault));
+  HIPCHK(hipEventCreate(&w->e0));
+  HIPCHK(hipEventCreate(&w->e1));
+  return APC_OK;
+}
+
+static Op make_op(const apc_cloud *c, bool density) {
+  Op op;
+  op.off = c->st_off;
+  op.idx = c->st_idx;
+  op.w64 = c->w64;
+  op.w32 = c->w32;
+  op.hs = density ? c->hscale : nullptr;
+  op.n = c->n;
+  return op;
+}
+
+static int read_sc(apc_solver_ws *w, hipStream_t s) {
+  HIPCHK(hipMemcpyAsync(w->sc_host, w->sc, sizeof(Scal), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  return APC_OK;
+}
+
+template <int MODE>
+static int launch_restart(apc_solver_ws *w, const Op &op, const double *b, const double *x,
+                          int first, hipStream_t s) {
+  const unsigned g = spmv_grid(w->n);
+  hipLaunchKernelGGL(k_restart<MODE>, dim3(g), dim3(APC_BLOCK), 0, s, op, b, x, w->r, w->rh, w->p,
+                     w->v, w->part, first);
+  hipLaunchKernelGGL(k_fin_restart, dim3(1), dim3(APC_BLOCK), 0, s, w->part, g, w->sc, first);
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
+template <int MODE>
+static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const double *invd,
+                             bool jac, hipStream_t s) {
+  const int64_t n = w->n;
+  const unsigned gv = grid_for(n), gs = spmv_grid(n), gr = vec_grid(n);
+  double *ph = jac ? w->ph : w->p;
+  double *sh = jac ? w->sh : w->s;
+  if (jac)
+    hipLaunchKernelGGL(k_upd_p<true>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->p, w->v, ph,
+                       invd, w->sc);
+  else
+    hipLaunchKernelGGL(k_upd_p<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->p, w->v, ph,
+                       invd, w->sc);
+  hipLaunchKernelGGL(k_spmv_v<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, ph, w->v, w->rh, w->part,
+                     w->sc);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(APC_BLOCK), 0, s, w->part, gs, w->sc);
+  if (jac)
+    hipLaunchKernelGGL(k_upd_s<true>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->v, w->s, sh,
+                       invd, w->sc);
+  else
+    hipLaunchKernelGGL(k_upd_s<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->v, w->s, sh,
+                       invd, w->sc);
+  hipLaunchKernelGGL(k_spmv_t<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, sh, w->s, w->t, w->part,
+                     w->sc);
+  hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(APC_BLOCK), 0, s, w->part, gs, w->sc);
+  hipLaunchKernelGGL(k_upd_xr, dim3(gr), dim3(APC_BLOCK), 0, s, n, x, ph, sh, w->s, w->t, w->r,
+                     w->rh, w->part, w->sc);
+  hipLaunchKernelGGL(k_fin_rho, dim3(1), dim3(APC_BLOCK), 0, s, w->part, gr, w->sc);
+}
+
+// BiCGSTAB on A x = b from x = 0.  MODE is the SpMV of the iteration, TMODE the
+// one of the true residual; when the recursive residual meets tol (or the method
+// breaks down) the true residual b - A x is recomputed and, if it does not meet
+// tol, the iteration restarts from it.  With FP32 iteration arithmetic and FP64
+// true residuals this restart is the iterative refinement of the mixed mode.
+template <int MODE, int TMODE>
+static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, double tol, int maxit,
+                    bool jac, apc_stats *st, hipStream_t s) {
+  apc_solver_ws *w = c->ws;
+  const int64_t n = w->n;
+  Scal init;
+  memset(&init, 0, sizeof(init));
+  init.tol = tol;
+  init.maxit = maxit;
+  HIPCHK(hipMemcpyAsync(w->sc, &init, sizeof(Scal), hipMemcpyHostToDevice, s));
+  HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
+  APCCHK(launch_restart<TMODE>(w, op, b, x, 1, s));
+  int chunk = 8, nrest = 0, status = APC_ENOCONV;
+  for (;;) {
+    for (int k = 0; k < chunk; k++) launch_iteration<MODE>(w, op, x, c->inv_diag, jac, s);
+    HIPCHK(hipGetLastError());
+    APCCHK(read_sc(w, s));
+    Scal &h = *w->sc_host;
+    if (!h.done) {
+      if (chunk < 32) chunk *= 2;
+      continue;
+    }
+    const int reason = h.done;
+    APCCHK(launch_restart<TMODE>(w, op, b, x, 0, s));
+    APCCHK(read_sc(w, s));
+    if (h.rtrue <= tol) {
+      status = APC_OK;
+      break;
+    }
+    if (reason == 3 || h.it >= maxit || nrest >= 50) break;
+    nrest++;
+    chunk = 8;
+  }
+  const Scal &h = *w->sc_host;
+  if (st) {
+    st->iters = h.it;
+    st->restarts = nrest;
+    st->sweeps = 1 + nrest;
+    st->status = status;
+    st->rel_resid = h.bnorm > 0.0 ? h.rnorm / h.bnorm : 0.0;
+    st->rel_resid_true = h.rtrue;
+  }
+  return status;
+}
+
+// FP64: FP64 weights and arithmetic throughout.  Mixed: FP32 weights and FP32
+// SpMV arithmetic in the iteration, FP64 vectors and dot products, FP64 true
+// residuals (the FP32 weights widened exactly) deciding convergence.
+static int run_solve(apc_cloud *c, bool density, const double *b, double *x, double tol, int maxit,
+                     bool jac, apc_stats *st, hipStream_t s) {
+  const Op op = make_op(c, density);
+  if (c->P.precision == APC_MIXED)
+    return bicgstab<V32A32, V32A64>(c, op, b, x, tol, maxit, jac, st, s);
+  return bicgstab<V64, V64>(c, op, b, x, tol, maxit, jac, st, s);
+}
+
+int apc_deposit_impl(apc_cloud *c, const double *q, double *rho_M, hipStream_t s) {
+  hipLaunchKernelGGL(k_deposit, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->N, c->first,
+                     c->count, c->level, c->perm, q, c->P.L, rho_M);
+  if (c->nb > 0)
+    hipLaunchKernelGGL(k_bnd_copy, dim3(grid_for(c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
+                       c->bowner, rho_M);
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
+int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, double tol,
+                           int maxit, apc_stats *st, hipStream_t s) {
+  if (!c->assembled) return APC_EINVAL;
+  APCCHK(ensure_ws(c));
+  apc_solver_ws *w = c->ws;
+  const Op op = make_op(c, true);
+  HIPCHK(hipEventRecord(w->e0, s));
+  if (c->P.precision == APC_MIXED)
+    hipLaunchKernelGGL(k_rhs<V32A64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_M,
+                       1.0, rho_M + c->n, w->b);
+  else
+    hipLaunchKernelGGL(k_rhs<V64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_M,
+                       1.0, rho_M + c->n, w->b);
+  HIPCHK(hipGetLastError());
+  int rc = run_solve(c, true, w->b, w->x, tol, maxit, false, st, s);
+  if (rc < 0) return rc;
+  hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
+                     w->x, rho_M + c->n, rho_t);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(w->e1, s));
+  HIPCHK(hipEventSynchronize(w->e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, w->e0, w->e1));
+  if (st) {
+    st->ms = ms;
+    st->n_fp64_rows = c->n_fp64_rows;
+  }
+  return rc;
+}
+
+int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *phi, double tol,
+                   int maxit, int precond, apc_stats *st, hipStream_t s) {
+  if (!c->assembled) return APC_EINVAL;
+  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI) return APC_EINVAL;
+  APCCHK(ensure_ws(c));
+  apc_solver_ws *w = c->ws;
+  const Op op = make_op(c, false);
+  HIPCHK(hipEventRecord(w->e0, s));
+  if (c->P.precision == APC_MIXED)
+    hipLaunchKernelGGL(k_rhs<V32A64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_t,
+                       c->P.poisson_c, g, w->b);
+  else
+    hipLaunchKernelGGL(k_rhs<V64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_t,
+                       c->P.poisson_c, g, w->b);
+  HIPCHK(hipGetLastError());
+  int rc = run_solve(c, false, w->b, w->x, tol, maxit, precond == APC_PRECOND_JACOBI, st, s);
+  if (rc < 0) return rc;
+  hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
+                     w->x, g, phi);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipEventRecord(w->e1, s));
+  HIPCHK(hipEventSynchronize(w->e1));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, w->e0, w->e1));
+  if (st) {
+    st->ms = ms;
+    st->n_fp64_rows = c->n_fp64_rows;
+  }
+  return rc;
+}
+
+int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s) {
+  if (!c->assembled) return APC_EINVAL;
+  const Op op = make_op(c, false);
+  // f has n+nb entries: boundary values take part as given (no zero tail here)
+  if (c->P.precision == APC_MIXED)
+    hipLaunchKernelGGL(k_apply<V32A64>, dim3(spmv_grid(c->n)), dim3(APC_BLOCK), 0, s, op, f, out);
+  else
+    hipLaunchKernelGGL(k_apply<V64>, dim3(spmv_grid(c->n)), dim3(APC_BLOCK), 0, s, op, f, out);
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
