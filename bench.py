@@ -130,7 +130,7 @@ def main():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="beam_halo_1e7")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64"])
+    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed_f32acc"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -155,29 +155,36 @@ def main():
     xyz_d = torch.from_numpy(xyz).cuda()
     torch.cuda.synchronize()
 
-    prec = apc.APC_MIXED if args.precision == "mixed" else apc.APC_FP64
+    PREC = {"fp64": apc.APC_FP64, "mixed": apc.APC_MIXED, "mixed_f32acc": apc.APC_MIXED_F32ACC}
+    prec = PREC[args.precision]
     log(f"timed steps ({args.precision}): warmup={args.warmup} steps={args.steps}")
     ms, info, ms_step, cloud, phi = run_steps(apc, torch, xyz_d, cfg, prec, args.steps,
                                               args.warmup, args.tol)
     t_metric = (ms["assemble"] + ms["solve"]) * 1e-3
     value = info["n"] / t_metric
     log(f"{args.precision}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
-    roof = spmv_roofline(torch, cloud, args.spmv_reps, prec == apc.APC_MIXED)
+    roof = spmv_roofline(torch, cloud, args.spmv_reps, prec != apc.APC_FP64)
     log(f"spmv roofline: {roof}")
     cloud.close()
 
     plain = None
-    if prec == apc.APC_MIXED and not args.no_plain:
-        log("plain FP64 comparison")
-        ms64, info64, _, c64, _ = run_steps(apc, torch, xyz_d, cfg, apc.APC_FP64,
-                                            max(2, args.steps // 2), 1, args.tol)
-        c64.close()
-        v64 = info64["n"] / ((ms64["assemble"] + ms64["solve"]) * 1e-3)
-        plain = dict(nodes_per_s=round(v64, 1), iters=info64["iters"],
-                     assemble_ms=round(ms64["assemble"], 3), solve_ms=round(ms64["solve"], 3))
-        iters_fp64 = info64["iters"]
-    else:
-        iters_fp64 = info["iters"]
+    variants = {}
+    iters_fp64 = info["iters"]
+    if prec != apc.APC_FP64 and not args.no_plain:
+        for name in ("fp64", "mixed_f32acc"):
+            if PREC[name] == prec:
+                continue
+            log(f"comparison variant {name}")
+            msv, infov, _, cv, _ = run_steps(apc, torch, xyz_d, cfg, PREC[name],
+                                             max(2, args.steps // 2), 1, args.tol)
+            cv.close()
+            vv = infov["n"] / ((msv["assemble"] + msv["solve"]) * 1e-3)
+            variants[name] = dict(nodes_per_s=round(vv, 1), iters=infov["iters"],
+                                  sweeps=infov["sweeps"], assemble_ms=round(msv["assemble"], 3),
+                                  solve_ms=round(msv["solve"], 3))
+            if name == "fp64":
+                plain = variants[name]
+                iters_fp64 = infov["iters"]
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -195,7 +202,7 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32+f64" if prec == apc.APC_MIXED else "f64",
+        "dtype": "f64" if prec == apc.APC_FP64 else "f32+f64",
         "data": "synthetic",
         "config": {"workload": args.workload, "particles": cfg["N"], "nodes": info["n"],
                    "boundary_nodes": info["nb"], "nnz": info["nnz"],
@@ -208,8 +215,9 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if variants:
+        out["variants"] = variants
     if plain is not None:
-        out["plain_fp64"] = plain
         out["speedup_mixed_vs_plain"] = round(value / plain["nodes_per_s"], 3)
     print(json.dumps(out), flush=True)
 

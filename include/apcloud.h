@@ -50,7 +50,8 @@ extern "C" {
 #define APC_ENOCONV 1     /* solver hit maxit (warning) */
 
 #define APC_FP64 0  /* FP64 stencil fit, FP64 matrix values, FP64 Krylov */
-#define APC_MIXED 1 /* FP32 fit/values/SpMV, FP64 fallback rows, FP64 dots + refinement */
+#define APC_MIXED 1 /* FP32 matrix values, FP64 SpMV accumulation, FP64 dots + refinement */
+#define APC_MIXED_F32ACC 2 /* as APC_MIXED with FP32 SpMV arithmetic in the iteration */
 
 #define APC_PRECOND_NONE 0
 #define APC_PRECOND_JACOBI 1
@@ -67,7 +68,7 @@ typedef struct {
   int ring_max;     /* last ring searched; the paper finds 5 always enough */
   int m_cap;        /* stencil size cap (<= 64); 40 for k = 2 */
   double poisson_c; /* c in Delta phi = c rho (eq. Poisson); 1 */
-  int precision;    /* APC_FP64 or APC_MIXED, fixed at build time */
+  int precision;    /* APC_FP64, APC_MIXED or APC_MIXED_F32ACC, fixed at build time */
 } apc_params;
 
 typedef struct {
@@ -143,7 +144,9 @@ int apc_density_solve(apc_cloud *c, const double *rho_M, double *rho_t, double t
    phi = g at boundary nodes (Dirichlet; g: nb values or NULL for 0).  rho_t: n
    (or n+nb, tail ignored); phi: n+nb out.  BiCGSTAB with optional right Jacobi
    preconditioning to recursive relative residual tol, confirmed by the true
-   FP64 residual.  APC_MIXED: FP32 SpMV inside FP64 iterative refinement.
+   FP64 residual.  APC_MIXED: FP32 weights inside FP64 iterative refinement (the
+   true residual, with the FP32 weights widened exactly, restarts the iteration
+   until it meets tol).
    Requires apc_assemble_gfd.  Synchronises the stream. */
 int apc_solve(apc_cloud *c, const double *rho_t, const double *g, double *phi, double tol,
               int maxit, int precond, apc_stats *st, hipStream_t stream);

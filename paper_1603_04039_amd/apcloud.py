@@ -17,7 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libapcloud.so")
 
 APC_OK, APC_EINVAL, APC_ENOMEM, APC_EHIP, APC_EDOMAIN, APC_ESTENCIL = 0, -1, -2, -3, -4, -5
 APC_ENOCONV = 1
-APC_FP64, APC_MIXED = 0, 1
+APC_FP64, APC_MIXED, APC_MIXED_F32ACC = 0, 1, 2
 APC_PRECOND_NONE, APC_PRECOND_JACOBI = 0, 1
 
 # every symbol declared in include/apcloud.h

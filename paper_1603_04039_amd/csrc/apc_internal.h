@@ -110,6 +110,12 @@ struct apc_cloud {
   double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator)
   uint8_t *fp64row = nullptr;                  // n (APC_MIXED): refitted in FP64
   int64_t n_fp64_rows = 0;
+  // rows whose stencil is the uniform 24-node 2-ring of their own level share one
+  // set of weights c_shell / h_c^2 (shells r^2 = s^2, 2 s^2, 4 s^2): rkind[i] is
+  // the level of such a row, -1 for a general row
+  int8_t *rkind = nullptr;
+  double tmpl[3] = {0.0, 0.0, 0.0};
+  int64_t n_template = 0;
   apc_solver_ws *ws = nullptr;
 };
 

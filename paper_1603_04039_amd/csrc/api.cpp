@@ -104,7 +104,7 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host) {
   if (!g.ok) return APC_EHIP;
   HIPCHK(hipDeviceSynchronize());
   if (w_host && c->nnz) {
-    if (c->P.precision == APC_MIXED) {
+    if (c->P.precision != APC_FP64) {
       float *tmp = new float[c->nnz];
       hipError_t e = hipMemcpy(tmp, c->w32, (size_t)c->nnz * 4, hipMemcpyDeviceToHost);
       for (int64_t i = 0; i < c->nnz; i++) w_host[i] = (double)tmp[i];

@@ -503,7 +503,7 @@ void apc_free_cloud(apc_cloud *c) {
   if (!c) return;
   apc_free_solver(c);
   free_cloud_arrays(c);
-  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row};
+  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row, c->rkind};
   for (void *q : ops)
     if (q) (void)hipFree(q);
   delete c;
@@ -732,7 +732,8 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   if (p->order != 2) return APC_EINVAL;
   if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
       p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 ||
-      !(p->precision == APC_FP64 || p->precision == APC_MIXED) || !std::isfinite(p->poisson_c))
+      !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
+        p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c))
     return APC_EINVAL;
   apc_cloud *c = new apc_cloud();
   c->P = *p;

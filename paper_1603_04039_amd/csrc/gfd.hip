@@ -151,47 +151,112 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // Laplacian row of node y: with c = e_xx + e_yy + e_zz and z = G^{-1} c, the
 // weight of neighbour j is W_j^2 (v_j . z) / (h unit)^2 (the V0 columns of the
 // second derivatives carry 1/2, so their unknowns are h^2 f_dd); diagonal -sum.
+//
+// A row whose stencil is the full uniform 2-ring of its own level (24 same-level
+// nodes at offsets with L1 norm <= 2 cells) has, by symmetry, the same weights as
+// every other such row up to 1/h_c^2: c_k / h_c^2 on the shells r^2 = 1, 2, 4
+// (cells), which come first, second and third in the (r^2, index) order.  Those
+// rows are stored with the canonical constants (the fit of the canonical
+// stencil) and flagged by their level in rkind, so the SpMV reads no weights
+// for them.
+__global__ void k_canon24(const int32_t *__restrict__ crd, double *__restrict__ tc) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t ntot = 25;
+  int32_t nb[24];
+  for (int j = 0; j < 24; j++) nb[j] = j + 1;
+  const NodeGeom g = node_geom(nb, 24, crd, ntot, 0);
+  double G[G45];
+  gram(nb, 24, g, crd, ntot, G);
+  cholesky9(G);
+  double z[P9] = {0, 0, 0, 1, 0, 0, 1, 0, 1};
+  chol_solve9(G, z);
+  const double hp = (double)g.h; // spacing 1, unit 1
+  const int pick[3] = {0, 6, 18};
+  for (int k = 0; k < 3; k++) {
+    double vv[P9];
+    const double w2 = row_w2(g, crd, ntot, nb[pick[k]], vv);
+    double dotv = 0.0;
+    for (int q = 0; q < P9; q++) dotv += vv[q] * z[q];
+    tc[k] = w2 * dotv / (hp * hp);
+  }
+}
+
 template <bool MIXED>
 __global__ void __launch_bounds__(APC_BLOCK)
     k_assemble(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
                const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
-               double unit, double L, double *__restrict__ w64, float *__restrict__ w32,
-               double *__restrict__ diag, double *__restrict__ inv_diag,
-               double *__restrict__ hscale, int *__restrict__ err) {
+               int D, double unit, double L, const double *__restrict__ tc,
+               double *__restrict__ w64, float *__restrict__ w32, double *__restrict__ diag,
+               double *__restrict__ inv_diag, double *__restrict__ hscale,
+               int8_t *__restrict__ rkind, int *__restrict__ err) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
   const int32_t a = st_off[y];
   const int m = st_off[y + 1] - a;
   const int32_t *nb = st_idx + a;
+  const int l = level[y];
+  const double hc = L / (double)(1 << l);
   const NodeGeom g = node_geom(nb, m, crd, ntot, (int32_t)y);
-  double G[G45];
-  gram(nb, m, g, crd, ntot, G);
-  const double ratio = cholesky9(G);
-  if (!(ratio >= APC_TAU_RANK)) atomicOr(err, 1);
-  double z[P9] = {0, 0, 0, 1, 0, 0, 1, 0, 1};
-  chol_solve9(G, z);
-  const double hp = (double)g.h * unit;
-  const double inv_h2 = 1.0 / (hp * hp);
-  double sum = 0.0;
-  for (int j = 0; j < m; j++) {
-    double vv[P9];
-    const double w2 = row_w2(g, crd, ntot, nb[j], vv);
-    double dotv = 0.0;
-#pragma unroll
-    for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
-    const double w = w2 * dotv * inv_h2;
-    if (MIXED) {
-      const float wf = (float)w;
-      w32[a + j] = wf;
-      sum += (double)wf;
-    } else {
-      w64[a + j] = w;
-      sum += w;
+  // uniform 2-ring of the node's own level?
+  bool tmpl = (m == 24);
+  if (tmpl) {
+    const int32_t sp = 1 << (D - l + 1);
+    for (int j = 0; j < 24 && tmpl; j++) {
+      const int32_t v = nb[j];
+      const int32_t d[3] = {abs(crd[v] - g.c0), abs(crd[ntot + v] - g.c1),
+                            abs(crd[2 * ntot + v] - g.c2)};
+      int32_t l1 = 0;
+      for (int k = 0; k < 3; k++) {
+        tmpl = tmpl && (d[k] == 0 || d[k] == sp || d[k] == 2 * sp);
+        l1 += d[k];
+      }
+      tmpl = tmpl && l1 <= 2 * sp;
     }
+  }
+  double sum = 0.0;
+  if (tmpl) {
+    const double ih2 = 1.0 / (hc * hc);
+    for (int j = 0; j < 24; j++) {
+      const double w = tc[j < 6 ? 0 : (j < 18 ? 1 : 2)] * ih2;
+      if (MIXED) {
+        const float wf = (float)w;
+        w32[a + j] = wf;
+        sum += (double)wf;
+      } else {
+        w64[a + j] = w;
+        sum += w;
+      }
+    }
+    rkind[y] = (int8_t)l;
+  } else {
+    double G[G45];
+    gram(nb, m, g, crd, ntot, G);
+    const double ratio = cholesky9(G);
+    if (!(ratio >= APC_TAU_RANK)) atomicOr(err, 1);
+    double z[P9] = {0, 0, 0, 1, 0, 0, 1, 0, 1};
+    chol_solve9(G, z);
+    const double hp = (double)g.h * unit;
+    const double inv_h2 = 1.0 / (hp * hp);
+    for (int j = 0; j < m; j++) {
+      double vv[P9];
+      const double w2 = row_w2(g, crd, ntot, nb[j], vv);
+      double dotv = 0.0;
+#pragma unroll
+      for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
+      const double w = w2 * dotv * inv_h2;
+      if (MIXED) {
+        const float wf = (float)w;
+        w32[a + j] = wf;
+        sum += (double)wf;
+      } else {
+        w64[a + j] = w;
+        sum += w;
+      }
+    }
+    rkind[y] = -1;
   }
   diag[y] = -sum;
   inv_diag[y] = -1.0 / sum;
-  const double hc = L / (double)(1 << level[y]);
   hscale[y] = hc * hc / 24.0;
 }
 
@@ -276,28 +341,56 @@ int apc_rank_check(const apc_cloud *c, const int32_t *pending, int64_t np, const
 
 int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
   const int64_t n = c->n, ntot = c->n + c->nb;
-  const bool mixed = c->P.precision == APC_MIXED;
+  const bool mixed = c->P.precision != APC_FP64;
   if (!c->diag) {
     HIPCHK(hipMalloc((void **)&c->diag, (size_t)n * sizeof(double)));
     HIPCHK(hipMalloc((void **)&c->inv_diag, (size_t)n * sizeof(double)));
     HIPCHK(hipMalloc((void **)&c->hscale, (size_t)n * sizeof(double)));
+    HIPCHK(hipMalloc((void **)&c->rkind, (size_t)n * sizeof(int8_t)));
     if (mixed)
       HIPCHK(hipMalloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
     else
       HIPCHK(hipMalloc((void **)&c->w64, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
   }
+  // canonical uniform 2-ring (spacing 1) around (4,4,4), sorted by r^2
+  int32_t hcrd[3 * 25];
+  {
+    int k = 1;
+    hcrd[0] = hcrd[25] = hcrd[50] = 4;
+    for (int r2 = 1; r2 <= 4; r2++)
+      for (int dx = -2; dx <= 2; dx++)
+        for (int dy = -2; dy <= 2; dy++)
+          for (int dz = -2; dz <= 2; dz++) {
+            if (dx * dx + dy * dy + dz * dz != r2) continue;
+            if (abs(dx) + abs(dy) + abs(dz) > 2) continue;
+            hcrd[k] = 4 + dx;
+            hcrd[25 + k] = 4 + dy;
+            hcrd[50 + k] = 4 + dz;
+            k++;
+          }
+  }
+  int32_t *dcrd = nullptr;
+  double *dtc = nullptr;
   int *err = nullptr;
+  HIPCHK(hipMallocAsync((void **)&dcrd, sizeof(hcrd), s));
+  HIPCHK(hipMallocAsync((void **)&dtc, 3 * sizeof(double), s));
   HIPCHK(hipMallocAsync((void **)&err, sizeof(int), s));
+  HIPCHK(hipMemcpyAsync(dcrd, hcrd, sizeof(hcrd), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+  hipLaunchKernelGGL(k_canon24, dim3(1), dim3(64), 0, s, dcrd, dtc);
   if (mixed)
     hipLaunchKernelGGL(k_assemble<true>, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
-                       c->st_idx, c->crd, ntot, c->level, c->unit, c->P.L, c->w64, c->w32, c->diag,
-                       c->inv_diag, c->hscale, err);
+                       c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->unit, c->P.L, dtc,
+                       c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, err);
   else
     hipLaunchKernelGGL(k_assemble<false>, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
-                       c->st_idx, c->crd, ntot, c->level, c->unit, c->P.L, c->w64, c->w32, c->diag,
-                       c->inv_diag, c->hscale, err);
+                       c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->unit, c->P.L, dtc,
+                       c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, err);
   HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(c->tmpl, dtc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipFreeAsync(dcrd, s));
+  HIPCHK(hipFreeAsync(dtc, s));
   HIPCHK(hipFreeAsync(err, s));
   c->assembled = true;
   return APC_OK;

@@ -38,6 +38,9 @@ struct Op {
   const double *w64;
   const float *w32;
   const double *hs; // nullptr => Laplacian
+  const int8_t *rk; // level of a uniform 2-ring row, -1 for a general row
+  double tc[3];     // shell weights of the uniform 2-ring at h_c = 1
+  double invL2;     // 1 / L^2: a level-l row scales tc by 4^l / L^2
   int64_t n;
 };
 
@@ -127,27 +130,56 @@ static inline unsigned vec_grid(int64_t n) {
 }
 
 // y_i for row i, computed by the GL lanes of one group; result valid in all lanes.
+// Uniform 2-ring rows read only their 24 column indices: lane g takes entries g,
+// g+8 and g+16, i.e. shells (g < 6 ? 1 : 2), 2 and (g < 2 ? 2 : 3).
+static_assert(GL == 8, "the uniform 2-ring split assumes 8 lanes per row");
 template <int MODE>
 __device__ __forceinline__ double op_row(const Op &op, const double *__restrict__ x, int64_t i,
                                          int gl) {
-  const int32_t a = op.off[i], b = op.off[i + 1];
+  const int32_t a = op.off[i];
   const double xi = x[i];
+  const int rk = op.rk[i];
   double acc;
-  if (MODE == V32A32) {
-    float af = 0.0f;
-    for (int32_t e = a + gl; e < b; e += GL) af += op.w32[e] * (float)(x[op.idx[e]] - xi);
+  if (rk >= 0) {
+    const double d0 = x[op.idx[a + gl]] - xi;
+    const double d1 = x[op.idx[a + gl + 8]] - xi;
+    const double d2 = x[op.idx[a + gl + 16]] - xi;
+    const double ca = gl < 6 ? op.tc[0] : op.tc[1];
+    const double cb = gl < 2 ? op.tc[1] : op.tc[2];
+    const double scale = ldexp(op.invL2, 2 * rk);
+    if (MODE == V32A32) {
+      float af = (float)ca * (float)d0 + (float)op.tc[1] * (float)d1 + (float)cb * (float)d2;
 #pragma unroll
-    for (int o = GL / 2; o > 0; o >>= 1) af += __shfl_xor(af, o, GL);
-    acc = (double)af;
-  } else {
-    double ad = 0.0;
-    for (int32_t e = a + gl; e < b; e += GL) {
-      const double w = (MODE == V64) ? op.w64[e] : (double)op.w32[e];
-      ad += w * (x[op.idx[e]] - xi);
+      for (int o = GL / 2; o > 0; o >>= 1) af += __shfl_xor(af, o, GL);
+      acc = (double)af * scale;
+    } else {
+      double ad;
+      if (MODE == V64)
+        ad = ca * d0 + op.tc[1] * d1 + cb * d2;
+      else
+        ad = (double)(float)ca * d0 + (double)(float)op.tc[1] * d1 + (double)(float)cb * d2;
+#pragma unroll
+      for (int o = GL / 2; o > 0; o >>= 1) ad += __shfl_xor(ad, o, GL);
+      acc = ad * scale;
     }
+  } else {
+    const int32_t b = op.off[i + 1];
+    if (MODE == V32A32) {
+      float af = 0.0f;
+      for (int32_t e = a + gl; e < b; e += GL) af += op.w32[e] * (float)(x[op.idx[e]] - xi);
 #pragma unroll
-    for (int o = GL / 2; o > 0; o >>= 1) ad += __shfl_xor(ad, o, GL);
-    acc = ad;
+      for (int o = GL / 2; o > 0; o >>= 1) af += __shfl_xor(af, o, GL);
+      acc = (double)af;
+    } else {
+      double ad = 0.0;
+      for (int32_t e = a + gl; e < b; e += GL) {
+        const double w = (MODE == V64) ? op.w64[e] : (double)op.w32[e];
+        ad += w * (x[op.idx[e]] - xi);
+      }
+#pragma unroll
+      for (int o = GL / 2; o > 0; o >>= 1) ad += __shfl_xor(ad, o, GL);
+      acc = ad;
+    }
   }
   return op.hs ? xi + op.hs[i] * acc : acc;
 }
@@ -460,6 +492,9 @@ static Op make_op(const apc_cloud *c, bool density) {
   op.w64 = c->w64;
   op.w32 = c->w32;
   op.hs = density ? c->hscale : nullptr;
+  op.rk = c->rkind;
+  for (int k = 0; k < 3; k++) op.tc[k] = c->tmpl[k];
+  op.invL2 = 1.0 / (c->P.L * c->P.L);
   op.n = c->n;
   return op;
 }
@@ -561,14 +596,18 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
   return status;
 }
 
-// FP64: FP64 weights and arithmetic throughout.  Mixed: FP32 weights and FP32
-// SpMV arithmetic in the iteration, FP64 vectors and dot products, FP64 true
-// residuals (the FP32 weights widened exactly) deciding convergence.
+// FP64: FP64 weights and arithmetic throughout.  Mixed: FP32 weights (half the
+// matrix bytes), FP64 SpMV accumulation, FP64 vectors and dot products, FP64
+// true residuals deciding convergence.  Mixed with FP32 accumulation: FP32 SpMV
+// arithmetic in the iteration, the FP64 true residual restarting it (iterative
+// refinement) until it meets tol.
 static int run_solve(apc_cloud *c, bool density, const double *b, double *x, double tol, int maxit,
                      bool jac, apc_stats *st, hipStream_t s) {
   const Op op = make_op(c, density);
-  if (c->P.precision == APC_MIXED)
+  if (c->P.precision == APC_MIXED_F32ACC)
     return bicgstab<V32A32, V32A64>(c, op, b, x, tol, maxit, jac, st, s);
+  if (c->P.precision == APC_MIXED)
+    return bicgstab<V32A64, V32A64>(c, op, b, x, tol, maxit, jac, st, s);
   return bicgstab<V64, V64>(c, op, b, x, tol, maxit, jac, st, s);
 }
 
@@ -589,7 +628,7 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
   apc_solver_ws *w = c->ws;
   const Op op = make_op(c, true);
   HIPCHK(hipEventRecord(w->e0, s));
-  if (c->P.precision == APC_MIXED)
+  if (c->P.precision != APC_FP64)
     hipLaunchKernelGGL(k_rhs<V32A64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_M,
                        1.0, rho_M + c->n, w->b);
   else
@@ -620,7 +659,7 @@ int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *p
   apc_solver_ws *w = c->ws;
   const Op op = make_op(c, false);
   HIPCHK(hipEventRecord(w->e0, s));
-  if (c->P.precision == APC_MIXED)
+  if (c->P.precision != APC_FP64)
     hipLaunchKernelGGL(k_rhs<V32A64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_t,
                        c->P.poisson_c, g, w->b);
   else
@@ -647,7 +686,7 @@ int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s) {
   if (!c->assembled) return APC_EINVAL;
   const Op op = make_op(c, false);
   // f has n+nb entries: boundary values take part as given (no zero tail here)
-  if (c->P.precision == APC_MIXED)
+  if (c->P.precision != APC_FP64)
     hipLaunchKernelGGL(k_apply<V32A64>, dim3(spmv_grid(c->n)), dim3(APC_BLOCK), 0, s, op, f, out);
   else
     hipLaunchKernelGGL(k_apply<V64>, dim3(spmv_grid(c->n)), dim3(APC_BLOCK), 0, s, op, f, out);
