@@ -88,15 +88,20 @@ def spmv_roofline(torch, cloud, reps, mixed):
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    n, nnz = cloud.n, cloud.nnz
+    n = cloud.n
+    oi = cloud.operator_info()
     vbytes = 4 if mixed else 8
-    # algorithmic bytes: weights + column indices + row offsets + x (once) + y
-    byts = nnz * (vbytes + 4) + (n + 1) * 4 + n * 8 + n * 8
+    # algorithmic bytes (padding excluded): uniform 2-ring rows read 24 column
+    # indices and their level, other rows column index + weight per entry; every
+    # row reads its row id, x_i and writes y_i (x_j gathers counted once, in x_i)
+    byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["nnz_general"] * (4 + vbytes)
+            + n * (4 + 8 + 8))
     gbs = byts / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="k_apply<%s> (operator SpMV)" % ("V32A64" if mixed else "V64"),
-                avg_us=round(ms * 1e3, 2), bytes_per_launch=int(byts))
+                kernel="k_apply<%s> (sliced-ELL operator SpMV)" % ("V32A64" if mixed else "V64"),
+                avg_us=round(ms * 1e3, 2), bytes_per_launch=int(byts),
+                uniform_rows=oi["n_uniform"], sell_entries=oi["sell_entries"])
 
 
 def cpu_baseline(xyz, cfg, iters_full, n_sample_iters=20):

@@ -126,6 +126,13 @@ int apc_assemble_gfd(apc_cloud *c, hipStream_t stream);
    CSR, diag_host[n].  In APC_MIXED the FP32 values are widened exactly. */
 int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host);
 
+/* Layout of the assembled operator as the solver streams it: n_uniform rows have
+   the uniform 24-node 2-ring stencil of their own level (their weights are the
+   shared shell constants and are not read), nnz_general entries belong to the
+   other rows, sell_entries is the padded entry count of the sliced layout. */
+int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
+                      int64_t *sell_entries);
+
 /* WLS charge assignment (Sec. 3.2 step 1): rho_M_j = (1/h_j^3) sum_{i in cell j} q_i
    (NGP kernel: the node's own octree cell, edge h_j), then B rho~ = rho_M with
    B = I + diag(h_j^2 / 24) L for k = 2 (kernel moments of the cell), boundary

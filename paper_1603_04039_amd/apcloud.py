@@ -22,7 +22,7 @@ APC_PRECOND_NONE, APC_PRECOND_JACOBI = 0, 1
 
 # every symbol declared in include/apcloud.h
 EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_nodes",
-           "apc_assemble_gfd", "apc_get_operator", "apc_deposit", "apc_density_solve",
+           "apc_assemble_gfd", "apc_get_operator", "apc_operator_info", "apc_deposit", "apc_density_solve",
            "apc_solve", "apc_interpolate_force", "apc_node_derivs", "apc_apply_operator",
            "apc_destroy", "apc_strerror", "apc_last_error"]
 
@@ -70,6 +70,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_get_nodes.argtypes = [P] * 11
     lib.apc_assemble_gfd.argtypes = [P, P]
     lib.apc_get_operator.argtypes = [P, P, P]
+    lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 3
     lib.apc_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, ct.POINTER(Stats), P]
@@ -197,6 +198,11 @@ class Cloud:
         _check(self.lib.apc_get_operator(self.h, w.ctypes.data_as(ct.c_void_p),
                                          d.ctypes.data_as(ct.c_void_p)), "apc_get_operator")
         return w, d
+
+    def operator_info(self):
+        v = [ct.c_int64() for _ in range(3)]
+        _check(self.lib.apc_operator_info(self.h, *[ct.byref(x) for x in v]), "apc_operator_info")
+        return dict(n_uniform=v[0].value, nnz_general=v[1].value, sell_entries=v[2].value)
 
     def deposit(self, q=None, tol=1e-12, maxit=1000, stream=None, rho_M=None, rho_t=None):
         import torch

@@ -11,6 +11,7 @@
 #define APC_MAXM 64      // hard stencil cap: one wavefront
 #define APC_RING_CAP 2048 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
+#define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
 
 void apc_set_hip_error(hipError_t e, const char *what, const char *file, int line);
 
@@ -116,6 +117,16 @@ struct apc_cloud {
   int8_t *rkind = nullptr;
   double tmpl[3] = {0.0, 0.0, 0.0};
   int64_t n_template = 0;
+  // sliced-ELL copy of the operator used by the SpMV (see sell.hip)
+  int64_t nsl = 0, sl_entries = 0;
+  int64_t sl_cs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}; // slice range of each XCD chunk
+  int32_t *sl_rows = nullptr;  // nsl * 64 row ids (-1 = padding lane)
+  int32_t *sl_len = nullptr;   // entries per row in the slice
+  int32_t *sl_tmpl = nullptr;  // 1: uniform 2-ring slice (no weights); 32-bit: scalar loads
+  int64_t *sl_off = nullptr;   // first entry of the slice
+  int32_t *sl_idx = nullptr;   // column indices, entry-major within a slice
+  double *sl_w64 = nullptr;    // weights (general slices), APC_FP64
+  float *sl_w32 = nullptr;     // weights (general slices), mixed modes
   apc_solver_ws *ws = nullptr;
 };
 
@@ -138,6 +149,8 @@ int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *p
                    double tol, int maxit, int precond, apc_stats *st, hipStream_t s);
 int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s);
 void apc_free_solver(apc_cloud *c);
+int apc_build_sell(apc_cloud *c, hipStream_t s);
+void apc_free_sell(apc_cloud *c);
 // stencil rank test of pending nodes (k = 2); clears m[y] of rejected nodes
 int apc_rank_check(const apc_cloud *c, const int32_t *pending, int64_t np, const int32_t *cand,
                    int32_t *m, hipStream_t s);

@@ -118,6 +118,15 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host) {
   return APC_OK;
 }
 
+int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
+                      int64_t *sell_entries) {
+  if (!c || !c->assembled) return APC_EINVAL;
+  if (n_uniform) *n_uniform = c->n_template;
+  if (nnz_general) *nnz_general = c->nnz - 24 * c->n_template;
+  if (sell_entries) *sell_entries = c->sl_entries;
+  return APC_OK;
+}
+
 int apc_deposit(apc_cloud *c, const double *q, double *rho_M, double *rho_t, double tol, int maxit,
                 apc_stats *st, hipStream_t stream) {
   if (!c || !rho_t || !(tol > 0.0) || maxit < 1) return APC_EINVAL;

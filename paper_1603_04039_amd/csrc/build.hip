@@ -502,6 +502,7 @@ void free_cloud_arrays(apc_cloud *c) {
 void apc_free_cloud(apc_cloud *c) {
   if (!c) return;
   apc_free_solver(c);
+  apc_free_sell(c);
   free_cloud_arrays(c);
   void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row, c->rkind};
   for (void *q : ops)

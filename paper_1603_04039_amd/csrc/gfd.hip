@@ -392,6 +392,8 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
   HIPCHK(hipFreeAsync(dcrd, s));
   HIPCHK(hipFreeAsync(dtc, s));
   HIPCHK(hipFreeAsync(err, s));
+  apc_free_sell(c);
+  APCCHK(apc_build_sell(c, s));
   c->assembled = true;
   return APC_OK;
 }

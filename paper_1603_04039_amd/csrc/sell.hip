@@ -1,0 +1,188 @@
+// Sliced-ELL layout of the assembled operator for the solver's SpMV.
+//
+// Rows are cut into 8 contiguous chunks (one per XCD; the XCDs' L2s then each
+// hold the x-vector neighbourhood of one chunk).  Inside a chunk the uniform
+// 2-ring rows and the general rows each form slices of 64 rows (one wavefront,
+// one thread per row) in ascending row order.  A slice stores its column indices
+// entry-major (entry k of lane r at off + 64 k + r), so every index/weight load
+// of a wavefront is one contiguous 256-byte (or 512-byte) request and every lane
+// has all its neighbour gathers independent of each other.  Uniform slices have
+// exactly 24 entries and no weights (the weights are the shell constants);
+// general slices are padded to their longest row with (own index, weight 0).
+#include <hip/hip_runtime.h>
+
+#include "apc_internal.h"
+
+namespace {
+
+constexpr int SL = APC_SLICE;
+
+__global__ void __launch_bounds__(APC_BLOCK) k_tflag(const int8_t *rk, int64_t n, int32_t *t) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) t[i] = rk[i] >= 0 ? 1 : 0;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_split(const int8_t *rk, const int32_t *tpos, int64_t n, int32_t *srow_t, int32_t *srow_g) {
+  int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  if (rk[i] >= 0)
+    srow_t[tpos[i]] = (int32_t)i;
+  else
+    srow_g[i - tpos[i]] = (int32_t)i;
+}
+
+// slice groups g = 2 * chunk + (0 uniform, 1 general)
+struct Groups {
+  int64_t sl0[16], nsl[16], r0[16], nr[16];
+};
+
+__device__ __forceinline__ int wave_max_i(int v) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+  return v;
+}
+
+// one 64-thread block per slice
+__global__ void __launch_bounds__(SL)
+    k_slices(Groups G, const int32_t *__restrict__ srow_t, const int32_t *__restrict__ srow_g,
+             const int32_t *__restrict__ st_off, int32_t *__restrict__ sl_rows,
+             int32_t *__restrict__ sl_len, int32_t *__restrict__ sl_tmpl,
+             int64_t *__restrict__ sl_ent) {
+  const int64_t s = blockIdx.x;
+  const int lane = threadIdx.x;
+  int g = 0;
+  while (g < 15 && !(s >= G.sl0[g] && s < G.sl0[g] + G.nsl[g])) g++;
+  const int type = g & 1;
+  const int64_t k = s - G.sl0[g];
+  const int64_t q = k * SL + lane;
+  const bool valid = q < G.nr[g];
+  const int32_t row = valid ? (type == 0 ? srow_t[G.r0[g] + q] : srow_g[G.r0[g] + q]) : -1;
+  sl_rows[s * SL + lane] = row;
+  const int m = valid ? st_off[row + 1] - st_off[row] : 0;
+  const int len = type == 0 ? 24 : wave_max_i(m);
+  if (lane == 0) {
+    sl_len[s] = len;
+    sl_tmpl[s] = type == 0 ? 1 : 0;
+    sl_ent[s] = (int64_t)len * SL;
+  }
+}
+
+__global__ void __launch_bounds__(SL)
+    k_sell_fill(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
+                const int64_t *__restrict__ sl_off, const int32_t *__restrict__ sl_tmpl,
+                const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+                const double *__restrict__ w64, const float *__restrict__ w32,
+                int32_t *__restrict__ idx, double *__restrict__ sw64, float *__restrict__ sw32) {
+  const int64_t s = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int32_t row = sl_rows[s * SL + lane];
+  const int len = sl_len[s];
+  const bool tm = sl_tmpl[s] != 0;
+  const int64_t off = sl_off[s] + lane;
+  const int32_t a = row >= 0 ? st_off[row] : 0;
+  const int m = row >= 0 ? st_off[row + 1] - a : 0;
+  for (int k = 0; k < len; k++) {
+    const int64_t e = off + (int64_t)k * SL;
+    const bool real = k < m;
+    idx[e] = real ? st_idx[a + k] : (row >= 0 ? row : 0);
+    if (!tm) {
+      if (w64) sw64[e] = real ? w64[a + k] : 0.0;
+      if (w32) sw32[e] = real ? w32[a + k] : 0.0f;
+    }
+  }
+}
+
+} // namespace
+
+int apc_build_sell(apc_cloud *c, hipStream_t s) {
+  const int64_t n = c->n;
+  int32_t *tf = nullptr, *tpos = nullptr, *srow_t = nullptr, *srow_g = nullptr;
+  HIPCHK(hipMallocAsync((void **)&tf, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(hipMallocAsync((void **)&tpos, (size_t)(n + 1) * sizeof(int32_t), s));
+  HIPCHK(hipMallocAsync((void **)&srow_t, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(hipMallocAsync((void **)&srow_g, (size_t)n * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_tflag, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, n, tf);
+  APCCHK(apc_scan_i32(tf, tpos, n, s));
+  hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, tpos, n, srow_t,
+                     srow_g);
+  HIPCHK(hipGetLastError());
+  // template-row prefix counts at the 8 chunk boundaries
+  int64_t lo[9];
+  int32_t T[9];
+  for (int k = 0; k <= 8; k++) lo[k] = (int64_t)k * n / 8;
+  for (int k = 0; k < 8; k++)
+    HIPCHK(hipMemcpyAsync(&T[k], tpos + lo[k], sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t lastf = 0;
+  HIPCHK(hipMemcpyAsync(&lastf, tf + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  int32_t lastp = 0;
+  HIPCHK(hipMemcpyAsync(&lastp, tpos + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  T[8] = lastp + lastf;
+  c->n_template = T[8];
+  Groups G;
+  int64_t ns = 0;
+  for (int k = 0; k < 8; k++) {
+    const int64_t nt = T[k + 1] - T[k];
+    const int64_t ng = (lo[k + 1] - T[k + 1]) - (lo[k] - T[k]);
+    G.sl0[2 * k] = ns;
+    G.nsl[2 * k] = (nt + SL - 1) / SL;
+    G.r0[2 * k] = T[k];
+    G.nr[2 * k] = nt;
+    c->sl_cs[k] = ns;
+    ns += G.nsl[2 * k];
+    G.sl0[2 * k + 1] = ns;
+    G.nsl[2 * k + 1] = (ng + SL - 1) / SL;
+    G.r0[2 * k + 1] = lo[k] - T[k];
+    G.nr[2 * k + 1] = ng;
+    ns += G.nsl[2 * k + 1];
+  }
+  c->sl_cs[8] = ns;
+  c->nsl = ns;
+  const size_t nsz = (size_t)(ns > 0 ? ns : 1);
+  HIPCHK(hipMalloc((void **)&c->sl_rows, nsz * SL * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->sl_len, nsz * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->sl_tmpl, nsz * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->sl_off, nsz * sizeof(int64_t)));
+  int64_t *ent = nullptr;
+  HIPCHK(hipMallocAsync((void **)&ent, nsz * sizeof(int64_t), s));
+  if (ns > 0) {
+    hipLaunchKernelGGL(k_slices, dim3((unsigned)ns), dim3(SL), 0, s, G, srow_t, srow_g, c->st_off,
+                       c->sl_rows, c->sl_len, c->sl_tmpl, ent);
+    HIPCHK(hipGetLastError());
+    APCCHK(apc_scan_i64(ent, c->sl_off, ns, s));
+    int64_t lasto = 0, laste = 0;
+    HIPCHK(hipMemcpyAsync(&lasto, c->sl_off + ns - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&laste, ent + ns - 1, sizeof(int64_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    c->sl_entries = lasto + laste;
+  }
+  const size_t ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 1);
+  HIPCHK(hipMalloc((void **)&c->sl_idx, ne * sizeof(int32_t)));
+  if (c->P.precision == APC_FP64)
+    HIPCHK(hipMalloc((void **)&c->sl_w64, ne * sizeof(double)));
+  else
+    HIPCHK(hipMalloc((void **)&c->sl_w32, ne * sizeof(float)));
+  if (ns > 0) {
+    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)ns), dim3(SL), 0, s, c->sl_rows, c->sl_len,
+                       c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->w64, c->w32, c->sl_idx,
+                       c->sl_w64, c->sl_w32);
+    HIPCHK(hipGetLastError());
+  }
+  HIPCHK(hipFreeAsync(ent, s));
+  HIPCHK(hipFreeAsync(tf, s));
+  HIPCHK(hipFreeAsync(tpos, s));
+  HIPCHK(hipFreeAsync(srow_t, s));
+  HIPCHK(hipFreeAsync(srow_g, s));
+  return APC_OK;
+}
+
+void apc_free_sell(apc_cloud *c) {
+  void *ptrs[] = {c->sl_rows, c->sl_len, c->sl_tmpl, c->sl_off, c->sl_idx, c->sl_w64, c->sl_w32};
+  for (void *q : ptrs)
+    if (q) (void)hipFree(q);
+  c->sl_rows = c->sl_len = c->sl_idx = c->sl_tmpl = nullptr;
+  c->sl_off = nullptr;
+  c->sl_w64 = nullptr;
+  c->sl_w32 = nullptr;
+}

@@ -42,10 +42,14 @@ struct Op {
   double tc[3];     // shell weights of the uniform 2-ring at h_c = 1
   double invL2;     // 1 / L^2: a level-l row scales tc by 4^l / L^2
   int64_t n;
+  // sliced-ELL copy (the SpMV reads only this)
+  const int32_t *sl_rows, *sl_len, *sl_idx, *sl_tmpl;
+  const int64_t *sl_off;
+  const double *sl_w64;
+  const float *sl_w32;
+  int64_t cs[9];
 };
 
-constexpr int GL = 8;                 // lanes per matrix row
-constexpr int RPB = APC_BLOCK / GL;   // rows per block
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -103,85 +107,107 @@ __device__ __forceinline__ void fin_sum(const double *part, unsigned G, double (
   }
 }
 
-// Row blocks (RPB rows each) are split into 8 contiguous ranges, one per XCD
-// (blocks are dealt round-robin over the 8 XCDs), so that neighbour gathers reuse
-// the XCD's own L2; within a range the XCD's blocks stride over row blocks.
-struct RowIter {
-  int64_t rb, end, step;
+// Slices (64 rows, one per wavefront) are grouped in 8 contiguous row chunks, one
+// per XCD (workgroups are dealt round-robin over the 8 XCDs): block b works on
+// chunk b mod 8, so neighbour gathers reuse that XCD's own L2.  Within a chunk
+// the XCD's wavefronts stride over its slices.  The slice index is made
+// wave-uniform (readfirstlane) so that the slice's offset, kind and length come
+// from scalar loads and its column-index loads issue at once.
+constexpr int SL = APC_SLICE;
+constexpr unsigned GSPMV = 4096;
+struct SlIter {
+  int s, end, step;
 };
-__device__ __forceinline__ RowIter row_iter(int64_t n) {
-  const int64_t nrb = (n + RPB - 1) / RPB;
-  const int64_t per = (nrb + 7) / 8;
-  const int64_t x = blockIdx.x & 7u, j = blockIdx.x >> 3;
-  RowIter it;
-  it.rb = x * per + j;
-  it.end = (x + 1) * per < nrb ? (x + 1) * per : nrb;
-  it.step = gridDim.x >> 3;
+__device__ __forceinline__ SlIter sl_iter(const Op &op) {
+  const int xcd = blockIdx.x & 7u, j = blockIdx.x >> 3;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  SlIter it;
+  it.s = (int)op.cs[xcd] + j * (APC_BLOCK / 64) + wv;
+  it.end = (int)op.cs[xcd + 1];
+  it.step = (int)(gridDim.x >> 3) * (APC_BLOCK / 64);
   return it;
 }
-static inline unsigned spmv_grid(int64_t n) {
-  const int64_t nrb = (n + RPB - 1) / RPB;
-  int64_t g = ((nrb + 7) / 8) * 8;
-  return (unsigned)(g < (int64_t)GRED ? g : (int64_t)GRED);
+static inline unsigned spmv_grid(const apc_cloud *c) {
+  int64_t mx = 0;
+  for (int k = 0; k < 8; k++) mx = (c->sl_cs[k + 1] - c->sl_cs[k]) > mx ? (c->sl_cs[k + 1] - c->sl_cs[k]) : mx;
+  int64_t per = (mx + (APC_BLOCK / 64) - 1) / (APC_BLOCK / 64);
+  if (per < 1) per = 1;
+  const int64_t g = 8 * per;
+  return (unsigned)(g < (int64_t)GSPMV ? g : (int64_t)GSPMV);
 }
 static inline unsigned vec_grid(int64_t n) {
   const unsigned g = grid_for(n);
   return g < GRED ? g : GRED;
 }
 
-// y_i for row i, computed by the GL lanes of one group; result valid in all lanes.
-// Uniform 2-ring rows read only their 24 column indices: lane g takes entries g,
-// g+8 and g+16, i.e. shells (g < 6 ? 1 : 2), 2 and (g < 2 ? 2 : 3).
-static_assert(GL == 8, "the uniform 2-ring split assumes 8 lanes per row");
+// (A x)_row for the lane's row of slice s (row = -1 on padding lanes, result 0).
+// Uniform 2-ring slices hold 24 entries ordered by shell (6 at r = 1 cell, 12 at
+// sqrt 2, 6 at 2) and no weights: their index loads go out before the row id.
+// General slices run their entry loop unrolled by 8 so that 8 index/weight loads
+// and then 8 gathers are in flight together.
 template <int MODE>
-__device__ __forceinline__ double op_row(const Op &op, const double *__restrict__ x, int64_t i,
-                                         int gl) {
-  const int32_t a = op.off[i];
-  const double xi = x[i];
-  const int rk = op.rk[i];
+__device__ __forceinline__ double sell_apply(const Op &op, const double *__restrict__ x, int s_in,
+                                             int32_t &row) {
+  const int s = __builtin_amdgcn_readfirstlane(s_in);
+  const int lane = threadIdx.x & 63;
+  const int64_t off = op.sl_off[s] + lane;
+  const int32_t *__restrict__ ix = op.sl_idx + off;
   double acc;
-  if (rk >= 0) {
-    const double d0 = x[op.idx[a + gl]] - xi;
-    const double d1 = x[op.idx[a + gl + 8]] - xi;
-    const double d2 = x[op.idx[a + gl + 16]] - xi;
-    const double ca = gl < 6 ? op.tc[0] : op.tc[1];
-    const double cb = gl < 2 ? op.tc[1] : op.tc[2];
-    const double scale = ldexp(op.invL2, 2 * rk);
+  double xi;
+  if (op.sl_tmpl[s]) {
+    int32_t jj[24];
+#pragma unroll
+    for (int k = 0; k < 24; k++) jj[k] = ix[k * SL];
+    row = op.sl_rows[(int64_t)s * SL + lane];
+    if (row < 0) return 0.0;
+    xi = x[row];
+    const double scale = ldexp(op.invL2, 2 * (int)op.rk[row]);
     if (MODE == V32A32) {
-      float af = (float)ca * (float)d0 + (float)op.tc[1] * (float)d1 + (float)cb * (float)d2;
+      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
-      for (int o = GL / 2; o > 0; o >>= 1) af += __shfl_xor(af, o, GL);
-      acc = (double)af * scale;
+      for (int k = 0; k < 24; k++) {
+        const float d = (float)(x[jj[k]] - xi);
+        if (k < 6) a0 += d; else if (k < 18) a1 += d; else a2 += d;
+      }
+      acc = (double)((float)op.tc[0] * a0 + (float)op.tc[1] * a1 + (float)op.tc[2] * a2) * scale;
     } else {
-      double ad;
-      if (MODE == V64)
-        ad = ca * d0 + op.tc[1] * d1 + cb * d2;
-      else
-        ad = (double)(float)ca * d0 + (double)(float)op.tc[1] * d1 + (double)(float)cb * d2;
+      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
-      for (int o = GL / 2; o > 0; o >>= 1) ad += __shfl_xor(ad, o, GL);
-      acc = ad * scale;
+      for (int k = 0; k < 24; k++) {
+        const double d = x[jj[k]] - xi;
+        if (k < 6) a0 += d; else if (k < 18) a1 += d; else a2 += d;
+      }
+      const double c0 = MODE == V64 ? op.tc[0] : (double)(float)op.tc[0];
+      const double c1 = MODE == V64 ? op.tc[1] : (double)(float)op.tc[1];
+      const double c2 = MODE == V64 ? op.tc[2] : (double)(float)op.tc[2];
+      acc = (c0 * a0 + c1 * a1 + c2 * a2) * scale;
     }
   } else {
-    const int32_t b = op.off[i + 1];
+    const int len = op.sl_len[s];
+    row = op.sl_rows[(int64_t)s * SL + lane];
+    if (row < 0) return 0.0;
+    xi = x[row];
     if (MODE == V32A32) {
-      float af = 0.0f;
-      for (int32_t e = a + gl; e < b; e += GL) af += op.w32[e] * (float)(x[op.idx[e]] - xi);
-#pragma unroll
-      for (int o = GL / 2; o > 0; o >>= 1) af += __shfl_xor(af, o, GL);
+      const float *__restrict__ wv = op.sl_w32 + off;
+      float af = 0.f;
+#pragma unroll 8
+      for (int k = 0; k < len; k++) af += wv[k * SL] * (float)(x[ix[k * SL]] - xi);
       acc = (double)af;
-    } else {
+    } else if (MODE == V64) {
+      const double *__restrict__ wv = op.sl_w64 + off;
       double ad = 0.0;
-      for (int32_t e = a + gl; e < b; e += GL) {
-        const double w = (MODE == V64) ? op.w64[e] : (double)op.w32[e];
-        ad += w * (x[op.idx[e]] - xi);
-      }
-#pragma unroll
-      for (int o = GL / 2; o > 0; o >>= 1) ad += __shfl_xor(ad, o, GL);
+#pragma unroll 8
+      for (int k = 0; k < len; k++) ad += wv[k * SL] * (x[ix[k * SL]] - xi);
+      acc = ad;
+    } else {
+      const float *__restrict__ wv = op.sl_w32 + off;
+      double ad = 0.0;
+#pragma unroll 8
+      for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (x[ix[k * SL]] - xi);
       acc = ad;
     }
   }
-  return op.hs ? xi + op.hs[i] * acc : acc;
+  return op.hs ? xi + op.hs[row] * acc : acc;
 }
 
 // ---------------------------------------------------------------- BiCGSTAB kernels
@@ -191,16 +217,13 @@ __global__ void __launch_bounds__(APC_BLOCK)
     k_spmv_v(Op op, const double *__restrict__ ph, double *__restrict__ v,
              const double *__restrict__ rh, double *part, const Scal *sc) {
   if (sc->done) return;
-  const int gl = threadIdx.x % GL;
   double val[1] = {0.0};
-  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
-    const int64_t i = it.rb * RPB + threadIdx.x / GL;
-    if (i < op.n) {
-      const double y = op_row<MODE>(op, ph, i, gl);
-      if (gl == 0) {
-        v[i] = y;
-        val[0] += rh[i] * y;
-      }
+  for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
+    int32_t i;
+    const double y = sell_apply<MODE>(op, ph, it.s, i);
+    if (i >= 0) {
+      v[i] = y;
+      val[0] += rh[i] * y;
     }
   }
   block_partials<1>(val, part);
@@ -212,17 +235,14 @@ __global__ void __launch_bounds__(APC_BLOCK)
     k_spmv_t(Op op, const double *__restrict__ sh, const double *__restrict__ s,
              double *__restrict__ t, double *part, const Scal *sc) {
   if (sc->done) return;
-  const int gl = threadIdx.x % GL;
   double val[2] = {0.0, 0.0};
-  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
-    const int64_t i = it.rb * RPB + threadIdx.x / GL;
-    if (i < op.n) {
-      const double y = op_row<MODE>(op, sh, i, gl);
-      if (gl == 0) {
-        t[i] = y;
-        val[0] += y * s[i];
-        val[1] += y * y;
-      }
+  for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
+    int32_t i;
+    const double y = sell_apply<MODE>(op, sh, it.s, i);
+    if (i >= 0) {
+      t[i] = y;
+      val[0] += y * s[i];
+      val[1] += y * y;
     }
   }
   block_partials<2>(val, part);
@@ -333,21 +353,19 @@ __global__ void __launch_bounds__(APC_BLOCK)
     k_restart(Op op, const double *__restrict__ b, const double *__restrict__ x,
               double *__restrict__ r, double *__restrict__ rh, double *__restrict__ p,
               double *__restrict__ v, double *part, int first) {
-  const int gl = threadIdx.x % GL;
   double val[2] = {0.0, 0.0};
-  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
-    const int64_t i = it.rb * RPB + threadIdx.x / GL;
-    if (i < op.n) {
-      const double y = first ? 0.0 : op_row<MODE>(op, x, i, gl);
-      if (gl == 0) {
-        const double ri = b[i] - y;
-        r[i] = ri;
-        rh[i] = ri;
-        p[i] = 0.0;
-        v[i] = 0.0;
-        val[0] += ri * ri;
-        val[1] += b[i] * b[i];
-      }
+  for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
+    int32_t i = op.sl_rows[(int64_t)it.s * SL + (threadIdx.x & 63)];
+    double y = 0.0;
+    if (!first) y = sell_apply<MODE>(op, x, it.s, i);
+    if (i >= 0) {
+      const double ri = b[i] - y;
+      r[i] = ri;
+      rh[i] = ri;
+      p[i] = 0.0;
+      v[i] = 0.0;
+      val[0] += ri * ri;
+      val[1] += b[i] * b[i];
     }
   }
   block_partials<2>(val, part);
@@ -401,13 +419,10 @@ __global__ void __launch_bounds__(APC_BLOCK)
 template <int MODE>
 __global__ void __launch_bounds__(APC_BLOCK)
     k_apply(Op op, const double *__restrict__ x, double *__restrict__ y) {
-  const int gl = threadIdx.x % GL;
-  for (RowIter it = row_iter(op.n); it.rb < it.end; it.rb += it.step) {
-    const int64_t i = it.rb * RPB + threadIdx.x / GL;
-    if (i < op.n) {
-      const double v = op_row<MODE>(op, x, i, gl);
-      if (gl == 0) y[i] = v;
-    }
+  for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
+    int32_t i;
+    const double v = sell_apply<MODE>(op, x, it.s, i);
+    if (i >= 0) y[i] = v;
   }
 }
 
@@ -476,7 +491,7 @@ static int ensure_ws(apc_cloud *c) {
     HIPCHK(hipMalloc((void **)q, bytes));
     HIPCHK(hipMemset(*q, 0, bytes)); // boundary tails stay zero for good
   }
-  HIPCHK(hipMalloc((void **)&w->part, 2 * (size_t)GRED * sizeof(double)));
+  HIPCHK(hipMalloc((void **)&w->part, 2 * (size_t)GSPMV * sizeof(double)));
   HIPCHK(hipMalloc((void **)&w->sc, sizeof(Scal)));
   HIPCHK(hipMemset(w->sc, 0, sizeof(Scal)));
   HIPCHK(hipHostMalloc((void **)&w->sc_host, sizeof(Scal), hipHostMallocDefault));
@@ -496,6 +511,14 @@ static Op make_op(const apc_cloud *c, bool density) {
   for (int k = 0; k < 3; k++) op.tc[k] = c->tmpl[k];
   op.invL2 = 1.0 / (c->P.L * c->P.L);
   op.n = c->n;
+  op.sl_rows = c->sl_rows;
+  op.sl_len = c->sl_len;
+  op.sl_idx = c->sl_idx;
+  op.sl_tmpl = c->sl_tmpl;
+  op.sl_off = c->sl_off;
+  op.sl_w64 = c->sl_w64;
+  op.sl_w32 = c->sl_w32;
+  for (int k = 0; k < 9; k++) op.cs[k] = c->sl_cs[k];
   return op;
 }
 
@@ -507,8 +530,7 @@ static int read_sc(apc_solver_ws *w, hipStream_t s) {
 
 template <int MODE>
 static int launch_restart(apc_solver_ws *w, const Op &op, const double *b, const double *x,
-                          int first, hipStream_t s) {
-  const unsigned g = spmv_grid(w->n);
+                          int first, unsigned g, hipStream_t s) {
   hipLaunchKernelGGL(k_restart<MODE>, dim3(g), dim3(APC_BLOCK), 0, s, op, b, x, w->r, w->rh, w->p,
                      w->v, w->part, first);
   hipLaunchKernelGGL(k_fin_restart, dim3(1), dim3(APC_BLOCK), 0, s, w->part, g, w->sc, first);
@@ -518,9 +540,9 @@ static int launch_restart(apc_solver_ws *w, const Op &op, const double *b, const
 
 template <int MODE>
 static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const double *invd,
-                             bool jac, hipStream_t s) {
+                             bool jac, unsigned gs, hipStream_t s) {
   const int64_t n = w->n;
-  const unsigned gv = grid_for(n), gs = spmv_grid(n), gr = vec_grid(n);
+  const unsigned gv = grid_for(n), gr = vec_grid(n);
   double *ph = jac ? w->ph : w->p;
   double *sh = jac ? w->sh : w->s;
   if (jac)
@@ -556,16 +578,17 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
                     bool jac, apc_stats *st, hipStream_t s) {
   apc_solver_ws *w = c->ws;
   const int64_t n = w->n;
+  const unsigned gs = spmv_grid(c);
   Scal init;
   memset(&init, 0, sizeof(init));
   init.tol = tol;
   init.maxit = maxit;
   HIPCHK(hipMemcpyAsync(w->sc, &init, sizeof(Scal), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
-  APCCHK(launch_restart<TMODE>(w, op, b, x, 1, s));
+  APCCHK(launch_restart<TMODE>(w, op, b, x, 1, gs, s));
   int chunk = 8, nrest = 0, status = APC_ENOCONV;
   for (;;) {
-    for (int k = 0; k < chunk; k++) launch_iteration<MODE>(w, op, x, c->inv_diag, jac, s);
+    for (int k = 0; k < chunk; k++) launch_iteration<MODE>(w, op, x, c->inv_diag, jac, gs, s);
     HIPCHK(hipGetLastError());
     APCCHK(read_sc(w, s));
     Scal &h = *w->sc_host;
@@ -574,7 +597,7 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
       continue;
     }
     const int reason = h.done;
-    APCCHK(launch_restart<TMODE>(w, op, b, x, 0, s));
+    APCCHK(launch_restart<TMODE>(w, op, b, x, 0, gs, s));
     APCCHK(read_sc(w, s));
     if (h.rtrue <= tol) {
       status = APC_OK;
@@ -687,9 +710,9 @@ int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s) {
   const Op op = make_op(c, false);
   // f has n+nb entries: boundary values take part as given (no zero tail here)
   if (c->P.precision != APC_FP64)
-    hipLaunchKernelGGL(k_apply<V32A64>, dim3(spmv_grid(c->n)), dim3(APC_BLOCK), 0, s, op, f, out);
+    hipLaunchKernelGGL(k_apply<V32A64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, op, f, out);
   else
-    hipLaunchKernelGGL(k_apply<V64>, dim3(spmv_grid(c->n)), dim3(APC_BLOCK), 0, s, op, f, out);
+    hipLaunchKernelGGL(k_apply<V64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, op, f, out);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
