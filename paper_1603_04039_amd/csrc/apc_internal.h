@@ -12,6 +12,7 @@
 #define APC_RING_CAP 2048 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
 #define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
+#define APC_TAU_FP32 0.1  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
 
 void apc_set_hip_error(hipError_t e, const char *what, const char *file, int line);
 
@@ -86,6 +87,16 @@ __device__ inline int64_t apc_last_le(const uint64_t *a, int64_t n, uint64_t v) 
 // ---------------------------------------------------------------- cloud handle
 struct apc_solver_ws;
 
+// small device block used by the assembly: canonical stencil, its shell
+// constants, error flag and the count of rows refitted in FP64
+struct apc_asm_scratch {
+  int32_t crd[3 * 25];
+  double tc[3];
+  int err;
+  int pad;
+  unsigned long long nfp64;
+};
+
 struct apc_cloud {
   apc_params P;
   int device = 0;
@@ -111,6 +122,7 @@ struct apc_cloud {
   double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator)
   uint8_t *fp64row = nullptr;                  // n (APC_MIXED): refitted in FP64
   int64_t n_fp64_rows = 0;
+  apc_asm_scratch *scratch = nullptr;
   // rows whose stencil is the uniform 24-node 2-ring of their own level share one
   // set of weights c_shell / h_c^2 (shells r^2 = s^2, 2 s^2, 4 s^2): rkind[i] is
   // the level of such a row, -1 for a general row
@@ -139,6 +151,7 @@ int apc_radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream
 int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_t s,
                    apc_cloud **out);
 int apc_assemble_impl(apc_cloud *c, hipStream_t s);
+int apc_prepare_operator(apc_cloud *c, hipStream_t s);
 int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s);
 int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
                     hipStream_t s);

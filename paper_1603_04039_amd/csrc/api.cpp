@@ -103,8 +103,9 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host) {
   DeviceGuard g(c->device);
   if (!g.ok) return APC_EHIP;
   HIPCHK(hipDeviceSynchronize());
+  const bool mixed = c->P.precision != APC_FP64;
   if (w_host && c->nnz) {
-    if (c->P.precision != APC_FP64) {
+    if (mixed) {
       float *tmp = new float[c->nnz];
       hipError_t e = hipMemcpy(tmp, c->w32, (size_t)c->nnz * 4, hipMemcpyDeviceToHost);
       for (int64_t i = 0; i < c->nnz; i++) w_host[i] = (double)tmp[i];
@@ -113,6 +114,26 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host) {
     } else {
       HIPCHK(hipMemcpy(w_host, c->w64, (size_t)c->nnz * 8, hipMemcpyDeviceToHost));
     }
+    // uniform 2-ring rows are not stored: their weights are the shell constants
+    // tc_k / h_c^2 over the shells of 6, 12 and 6 entries
+    int8_t *rk = new int8_t[c->n];
+    int32_t *off = new int32_t[c->n + 1];
+    hipError_t e1 = hipMemcpy(rk, c->rkind, (size_t)c->n, hipMemcpyDeviceToHost);
+    hipError_t e2 = hipMemcpy(off, c->st_off, (size_t)(c->n + 1) * 4, hipMemcpyDeviceToHost);
+    if (e1 == hipSuccess && e2 == hipSuccess) {
+      for (int64_t i = 0; i < c->n; i++) {
+        if (rk[i] < 0) continue;
+        const double hc = c->P.L / (double)(1 << rk[i]);
+        for (int j = 0; j < 24; j++) {
+          const double w = c->tmpl[j < 6 ? 0 : (j < 18 ? 1 : 2)] * (1.0 / (hc * hc));
+          w_host[off[i] + j] = mixed ? (double)(float)w : w;
+        }
+      }
+    }
+    delete[] rk;
+    delete[] off;
+    HIPCHK(e1);
+    HIPCHK(e2);
   }
   if (diag_host) HIPCHK(hipMemcpy(diag_host, c->diag, (size_t)c->n * 8, hipMemcpyDeviceToHost));
   return APC_OK;

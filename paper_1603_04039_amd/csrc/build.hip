@@ -504,7 +504,7 @@ void apc_free_cloud(apc_cloud *c) {
   apc_free_solver(c);
   apc_free_sell(c);
   free_cloud_arrays(c);
-  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row, c->rkind};
+  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row, c->rkind, c->scratch};
   for (void *q : ops)
     if (q) (void)hipFree(q);
   delete c;
@@ -722,6 +722,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   HIPCHK(hipGetLastError());
   APCCHK(dfree(keys, s));
   APCCHK(dfree(err, s));
+  APCCHK(apc_prepare_operator(c, s));
   HIPCHK(hipStreamSynchronize(s));
   return APC_OK;
 }

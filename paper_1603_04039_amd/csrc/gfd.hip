@@ -21,16 +21,17 @@ constexpr int G45 = 45;
 
 __device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; } // j <= i
 
-__device__ __forceinline__ void mono9(double x, double y, double z, double v[P9]) {
+template <typename T>
+__device__ __forceinline__ void mono9(T x, T y, T z, T v[P9]) {
   v[0] = x;
   v[1] = y;
   v[2] = z;
-  v[3] = (x * x) * 0.5;
+  v[3] = (x * x) * T(0.5);
   v[4] = x * y;
   v[5] = x * z;
-  v[6] = (y * y) * 0.5;
+  v[6] = (y * y) * T(0.5);
   v[7] = y * z;
-  v[8] = (z * z) * 0.5;
+  v[8] = (z * z) * T(0.5);
 }
 
 struct NodeGeom {
@@ -61,27 +62,29 @@ __device__ inline NodeGeom node_geom(const int32_t *nb, int m, const int32_t *__
 }
 
 // row v (9) and squared weight of neighbour v of node y
-__device__ __forceinline__ double row_w2(const NodeGeom &g, const int32_t *__restrict__ crd,
-                                         int64_t ntot, int32_t v, double vv[P9]) {
+template <typename T>
+__device__ __forceinline__ T row_w2(const NodeGeom &g, const int32_t *__restrict__ crd,
+                                    int64_t ntot, int32_t v, T vv[P9]) {
   const int32_t d0 = crd[v] - g.c0, d1 = crd[ntot + v] - g.c1, d2 = crd[2 * ntot + v] - g.c2;
-  const double hd = (double)g.h;
-  mono9((double)d0 / hd, (double)d1 / hd, (double)d2 / hd, vv);
-  const double r2 = (double)((int64_t)d0 * d0 + (int64_t)d1 * d1 + (int64_t)d2 * d2);
-  const double e4 = 0.018315638888734179; // exp(-4)
-  const double W = (exp(-r2 / g.r2max) - e4) / (1.0 - e4);
+  const T hd = (T)g.h;
+  mono9<T>((T)d0 / hd, (T)d1 / hd, (T)d2 / hd, vv);
+  const T r2 = (T)((int64_t)d0 * d0 + (int64_t)d1 * d1 + (int64_t)d2 * d2);
+  const T e4 = T(0.018315638888734179); // exp(-4)
+  const T W = (exp(-r2 / (T)g.r2max) - e4) / (T(1) - e4);
   return W * W;
 }
 
+template <typename T>
 __device__ inline void gram(const int32_t *nb, int m, const NodeGeom &g,
-                            const int32_t *__restrict__ crd, int64_t ntot, double G[G45]) {
+                            const int32_t *__restrict__ crd, int64_t ntot, T G[G45]) {
 #pragma unroll
-  for (int k = 0; k < G45; k++) G[k] = 0.0;
+  for (int k = 0; k < G45; k++) G[k] = T(0);
   for (int j = 0; j < m; j++) {
-    double vv[P9];
-    const double w2 = row_w2(g, crd, ntot, nb[j], vv);
+    T vv[P9];
+    const T w2 = row_w2<T>(g, crd, ntot, nb[j], vv);
 #pragma unroll
     for (int a = 0; a < P9; a++) {
-      const double wa = w2 * vv[a];
+      const T wa = w2 * vv[a];
 #pragma unroll
       for (int b = 0; b <= a; b++) G[tri(a, b)] += wa * vv[b];
     }
@@ -89,47 +92,63 @@ __device__ inline void gram(const int32_t *nb, int m, const NodeGeom &g,
 }
 
 // in-place Cholesky G = L L^T (packed lower); returns min/max diag(L) (0 if not SPD)
-__device__ inline double cholesky9(double G[G45]) {
-  double dmin = 1e300, dmax = 0.0;
+template <typename T>
+__device__ inline T cholesky9(T G[G45]) {
+  T dmin = T(1e30), dmax = T(0);
   bool ok = true;
 #pragma unroll
   for (int i = 0; i < P9; i++) {
 #pragma unroll
     for (int j = 0; j <= i; j++) {
-      double s = G[tri(i, j)];
+      T s = G[tri(i, j)];
 #pragma unroll
       for (int k = 0; k < j; k++) s -= G[tri(i, k)] * G[tri(j, k)];
       if (i == j) {
-        ok = ok && (s > 0.0);
-        const double d = sqrt(s > 0.0 ? s : 0.0);
+        ok = ok && (s > T(0));
+        const T d = sqrt(s > T(0) ? s : T(0));
         G[tri(i, i)] = d;
         dmin = fmin(dmin, d);
         dmax = fmax(dmax, d);
       } else {
-        const double dj = G[tri(j, j)];
-        G[tri(i, j)] = dj > 0.0 ? s / dj : 0.0;
+        const T dj = G[tri(j, j)];
+        G[tri(i, j)] = dj > T(0) ? s / dj : T(0);
       }
     }
   }
-  return (ok && dmax > 0.0) ? dmin / dmax : 0.0;
+  return (ok && dmax > T(0)) ? dmin / dmax : T(0);
 }
 
 // solve L L^T z = c in place
-__device__ inline void chol_solve9(const double L[G45], double z[P9]) {
+template <typename T>
+__device__ inline void chol_solve9(const T L[G45], T z[P9]) {
 #pragma unroll
   for (int i = 0; i < P9; i++) {
-    double s = z[i];
+    T s = z[i];
 #pragma unroll
     for (int k = 0; k < i; k++) s -= L[tri(i, k)] * z[k];
     z[i] = s / L[tri(i, i)];
   }
 #pragma unroll
   for (int i = P9 - 1; i >= 0; i--) {
-    double s = z[i];
+    T s = z[i];
 #pragma unroll
     for (int k = i + 1; k < P9; k++) s -= L[tri(k, i)] * z[k];
     z[i] = s / L[tri(i, i)];
   }
+}
+
+// Laplacian weights of a general row (fit in precision T): z = G^{-1} (e_xx + e_yy + e_zz),
+// w_j = W_j^2 (v_j . z) / (h unit)^2.  Returns the R-diagonal ratio.
+template <typename T>
+__device__ inline T lap_fit(const int32_t *nb, int m, const NodeGeom &g,
+                            const int32_t *__restrict__ crd, int64_t ntot, T z[P9]) {
+  T G[G45];
+  gram<T>(nb, m, g, crd, ntot, G);
+  const T ratio = cholesky9<T>(G);
+#pragma unroll
+  for (int k = 0; k < P9; k++) z[k] = (k == 3 || k == 6 || k == 8) ? T(1) : T(0);
+  chol_solve9<T>(G, z);
+  return ratio;
 }
 
 // ---------------------------------------------------------------- rank test (build)
@@ -143,8 +162,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int32_t *nb = cand + t * APC_MAXM;
   const NodeGeom g = node_geom(nb, mm, crd, ntot, pending[t]);
   double G[G45];
-  gram(nb, mm, g, crd, ntot, G);
-  if (!(cholesky9(G) >= APC_TAU_RANK)) m[t] = 0;
+  gram<double>(nb, mm, g, crd, ntot, G);
+  if (!(cholesky9<double>(G) >= APC_TAU_RANK)) m[t] = 0;
 }
 
 // ---------------------------------------------------------------- assembly
@@ -156,55 +175,50 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // nodes at offsets with L1 norm <= 2 cells) has, by symmetry, the same weights as
 // every other such row up to 1/h_c^2: c_k / h_c^2 on the shells r^2 = 1, 2, 4
 // (cells), which come first, second and third in the (r^2, index) order.  Those
-// rows are stored with the canonical constants (the fit of the canonical
-// stencil) and flagged by their level in rkind, so the SpMV reads no weights
-// for them.
+// rows take the canonical constants (the same fit on the canonical stencil) and
+// are flagged by their level in rkind; the SpMV reads no weights for them.
+//
+// Assembly runs in three passes: k_classify (integer test for the uniform
+// 2-ring, canonical rows written), the sliced layout (sell.hip), then k_fit_sell
+// with one wavefront per slice, so that cheap uniform slices and general slices
+// never share a wavefront and the solver's copy is written coalesced.
 __global__ void k_canon24(const int32_t *__restrict__ crd, double *__restrict__ tc) {
   if (threadIdx.x != 0 || blockIdx.x != 0) return;
   const int64_t ntot = 25;
   int32_t nb[24];
   for (int j = 0; j < 24; j++) nb[j] = j + 1;
   const NodeGeom g = node_geom(nb, 24, crd, ntot, 0);
-  double G[G45];
-  gram(nb, 24, g, crd, ntot, G);
-  cholesky9(G);
-  double z[P9] = {0, 0, 0, 1, 0, 0, 1, 0, 1};
-  chol_solve9(G, z);
+  double z[P9];
+  lap_fit<double>(nb, 24, g, crd, ntot, z);
   const double hp = (double)g.h; // spacing 1, unit 1
   const int pick[3] = {0, 6, 18};
   for (int k = 0; k < 3; k++) {
     double vv[P9];
-    const double w2 = row_w2(g, crd, ntot, nb[pick[k]], vv);
+    const double w2 = row_w2<double>(g, crd, ntot, nb[pick[k]], vv);
     double dotv = 0.0;
     for (int q = 0; q < P9; q++) dotv += vv[q] * z[q];
     tc[k] = w2 * dotv / (hp * hp);
   }
 }
 
-template <bool MIXED>
+// Structural test run at build time: is the stencil the full uniform 2-ring of
+// the node's own level?  rkind = level if so, else -1.
 __global__ void __launch_bounds__(APC_BLOCK)
-    k_assemble(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+    k_classify(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
                const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
-               int D, double unit, double L, const double *__restrict__ tc,
-               double *__restrict__ w64, float *__restrict__ w32, double *__restrict__ diag,
-               double *__restrict__ inv_diag, double *__restrict__ hscale,
-               int8_t *__restrict__ rkind, int *__restrict__ err) {
+               int D, int8_t *__restrict__ rkind) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
   const int32_t a = st_off[y];
   const int m = st_off[y + 1] - a;
-  const int32_t *nb = st_idx + a;
   const int l = level[y];
-  const double hc = L / (double)(1 << l);
-  const NodeGeom g = node_geom(nb, m, crd, ntot, (int32_t)y);
-  // uniform 2-ring of the node's own level?
   bool tmpl = (m == 24);
   if (tmpl) {
     const int32_t sp = 1 << (D - l + 1);
+    const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y];
     for (int j = 0; j < 24 && tmpl; j++) {
-      const int32_t v = nb[j];
-      const int32_t d[3] = {abs(crd[v] - g.c0), abs(crd[ntot + v] - g.c1),
-                            abs(crd[2 * ntot + v] - g.c2)};
+      const int32_t v = st_idx[a + j];
+      const int32_t d[3] = {abs(crd[v] - c0), abs(crd[ntot + v] - c1), abs(crd[2 * ntot + v] - c2)};
       int32_t l1 = 0;
       for (int k = 0; k < 3; k++) {
         tmpl = tmpl && (d[k] == 0 || d[k] == sp || d[k] == 2 * sp);
@@ -213,51 +227,101 @@ __global__ void __launch_bounds__(APC_BLOCK)
       tmpl = tmpl && l1 <= 2 * sp;
     }
   }
-  double sum = 0.0;
-  if (tmpl) {
+  rkind[y] = tmpl ? (int8_t)l : (int8_t)-1;
+}
+
+// One wavefront per slice of the sliced layout (indices were laid out at build).
+// Uniform slices: the rows' diagonal from the canonical shell constants (their
+// CSR weights are implied by rkind and are not stored).  General slices: fit
+// each row (FP64, or FP32 in the mixed modes with an FP64 refit when
+// min|R_ii|/max|R_ii| < APC_TAU_FP32), write its weights to the CSR copy and to
+// the slice (entry-major, coalesced); padding entries keep weight 0.
+template <bool MIXED>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_fit_sell(int64_t nsl, const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
+               const int64_t *__restrict__ sl_off, const int32_t *__restrict__ sl_tmpl,
+               const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+               const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
+               double unit, double L, const double *__restrict__ tc, double *__restrict__ w64,
+               float *__restrict__ w32, double *__restrict__ diag, double *__restrict__ inv_diag,
+               double *__restrict__ hscale, double *__restrict__ sw64, float *__restrict__ sw32,
+               int *__restrict__ err, unsigned long long *__restrict__ nfp64) {
+  const int64_t s = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
+  if (s >= nsl) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t row = sl_rows[s * APC_SLICE + lane];
+  if (row < 0) return;
+  const int64_t off = sl_off[s] + lane;
+  const int len = sl_len[s];
+  const double hc = L / (double)(1 << level[row]);
+  hscale[row] = hc * hc / 24.0;
+  if (sl_tmpl[s]) {
     const double ih2 = 1.0 / (hc * hc);
-    for (int j = 0; j < 24; j++) {
-      const double w = tc[j < 6 ? 0 : (j < 18 ? 1 : 2)] * ih2;
-      if (MIXED) {
-        const float wf = (float)w;
-        w32[a + j] = wf;
-        sum += (double)wf;
-      } else {
-        w64[a + j] = w;
-        sum += w;
-      }
+    double sum = 0.0;
+    for (int k = 0; k < 3; k++) {
+      const int cnt = k == 1 ? 12 : 6;
+      const double w = tc[k] * ih2;
+      sum += cnt * (MIXED ? (double)(float)w : w);
     }
-    rkind[y] = (int8_t)l;
-  } else {
-    double G[G45];
-    gram(nb, m, g, crd, ntot, G);
-    const double ratio = cholesky9(G);
+    diag[row] = -sum;
+    inv_diag[row] = -1.0 / sum;
+    return;
+  }
+  const int32_t a = st_off[row];
+  const int m = st_off[row + 1] - a;
+  const int32_t *nb = st_idx + a;
+  const NodeGeom g = node_geom(nb, m, crd, ntot, row);
+  const double hp = (double)g.h * unit;
+  const double inv_h2 = 1.0 / (hp * hp);
+  double sum = 0.0;
+  bool done = false;
+  if (MIXED) {
+    float z[P9];
+    const float ratio = lap_fit<float>(nb, m, g, crd, ntot, z);
+    if (ratio >= (float)APC_TAU_FP32) {
+      for (int j = 0; j < m; j++) {
+        float vv[P9];
+        const float w2 = row_w2<float>(g, crd, ntot, nb[j], vv);
+        float dotv = 0.f;
+#pragma unroll
+        for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
+        const float wf = (float)((double)(w2 * dotv) * inv_h2);
+        w32[a + j] = wf;
+        sw32[off + (int64_t)j * APC_SLICE] = wf;
+        sum += (double)wf;
+      }
+      done = true;
+    } else {
+      atomicAdd(nfp64, 1ull);
+    }
+  }
+  if (!done) {
+    double z[P9];
+    const double ratio = lap_fit<double>(nb, m, g, crd, ntot, z);
     if (!(ratio >= APC_TAU_RANK)) atomicOr(err, 1);
-    double z[P9] = {0, 0, 0, 1, 0, 0, 1, 0, 1};
-    chol_solve9(G, z);
-    const double hp = (double)g.h * unit;
-    const double inv_h2 = 1.0 / (hp * hp);
     for (int j = 0; j < m; j++) {
       double vv[P9];
-      const double w2 = row_w2(g, crd, ntot, nb[j], vv);
+      const double w2 = row_w2<double>(g, crd, ntot, nb[j], vv);
       double dotv = 0.0;
 #pragma unroll
       for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
       const double w = w2 * dotv * inv_h2;
+      const int64_t e = off + (int64_t)j * APC_SLICE;
       if (MIXED) {
         const float wf = (float)w;
         w32[a + j] = wf;
+        sw32[e] = wf;
         sum += (double)wf;
       } else {
         w64[a + j] = w;
+        sw64[e] = w;
         sum += w;
       }
     }
-    rkind[y] = -1;
   }
-  diag[y] = -sum;
-  inv_diag[y] = -1.0 / sum;
-  hscale[y] = hc * hc / 24.0;
+  (void)len;
+  diag[row] = -sum;
+  inv_diag[row] = -1.0 / sum;
 }
 
 // ---------------------------------------------------------------- derivatives
@@ -282,7 +346,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   for (int j = 0; j < m; j++) {
     double vv[P9];
     const int32_t v = nb[j];
-    const double w2 = row_w2(g, crd, ntot, v, vv);
+    const double w2 = row_w2<double>(g, crd, ntot, v, vv);
     const double df = w2 * (f[v] - f0);
 #pragma unroll
     for (int p = 0; p < P9; p++) {
@@ -292,8 +356,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
       for (int q = 0; q <= p; q++) G[tri(p, q)] += wa * vv[q];
     }
   }
-  cholesky9(G);
-  chol_solve9(G, rhs);
+  cholesky9<double>(G);
+  chol_solve9<double>(G, rhs);
   const double h1 = 1.0 / ((double)g.h * unit);
   const double h2 = h1 * h1;
 #pragma unroll
@@ -315,7 +379,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const double z = sxyz[2 * N + s] - (lo2 + unit * (double)crd[2 * ntot + j]);
   const double *d = D + (int64_t)j * P9;
   double mv[P9];
-  mono9(x, y, z, mv);
+  mono9<double>(x, y, z, mv);
   double v = phi[j];
 #pragma unroll
   for (int k = 0; k < P9; k++) v += d[k] * mv[k];
@@ -339,61 +403,70 @@ int apc_rank_check(const apc_cloud *c, const int32_t *pending, int64_t np, const
   return APC_OK;
 }
 
-int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
+// Structural part of the assembly, run by build_cloud: uniform-row flags, the
+// sliced layout and every array the assembly writes (so that assembly allocates
+// nothing), plus the canonical stencil for the shell constants.
+int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
   const int64_t n = c->n, ntot = c->n + c->nb;
   const bool mixed = c->P.precision != APC_FP64;
-  if (!c->diag) {
-    HIPCHK(hipMalloc((void **)&c->diag, (size_t)n * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&c->inv_diag, (size_t)n * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&c->hscale, (size_t)n * sizeof(double)));
-    HIPCHK(hipMalloc((void **)&c->rkind, (size_t)n * sizeof(int8_t)));
-    if (mixed)
-      HIPCHK(hipMalloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
-    else
-      HIPCHK(hipMalloc((void **)&c->w64, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
-  }
+  HIPCHK(hipMalloc((void **)&c->diag, (size_t)n * sizeof(double)));
+  HIPCHK(hipMalloc((void **)&c->inv_diag, (size_t)n * sizeof(double)));
+  HIPCHK(hipMalloc((void **)&c->hscale, (size_t)n * sizeof(double)));
+  HIPCHK(hipMalloc((void **)&c->rkind, (size_t)n * sizeof(int8_t)));
+  if (mixed)
+    HIPCHK(hipMalloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
+  else
+    HIPCHK(hipMalloc((void **)&c->w64, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
+  hipLaunchKernelGGL(k_classify, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off, c->st_idx,
+                     c->crd, ntot, c->level, c->P.max_depth, c->rkind);
+  HIPCHK(hipGetLastError());
+  APCCHK(apc_build_sell(c, s));
   // canonical uniform 2-ring (spacing 1) around (4,4,4), sorted by r^2
   int32_t hcrd[3 * 25];
-  {
-    int k = 1;
-    hcrd[0] = hcrd[25] = hcrd[50] = 4;
-    for (int r2 = 1; r2 <= 4; r2++)
-      for (int dx = -2; dx <= 2; dx++)
-        for (int dy = -2; dy <= 2; dy++)
-          for (int dz = -2; dz <= 2; dz++) {
-            if (dx * dx + dy * dy + dz * dz != r2) continue;
-            if (abs(dx) + abs(dy) + abs(dz) > 2) continue;
-            hcrd[k] = 4 + dx;
-            hcrd[25 + k] = 4 + dy;
-            hcrd[50 + k] = 4 + dz;
-            k++;
-          }
-  }
-  int32_t *dcrd = nullptr;
-  double *dtc = nullptr;
-  int *err = nullptr;
-  HIPCHK(hipMallocAsync((void **)&dcrd, sizeof(hcrd), s));
-  HIPCHK(hipMallocAsync((void **)&dtc, 3 * sizeof(double), s));
-  HIPCHK(hipMallocAsync((void **)&err, sizeof(int), s));
-  HIPCHK(hipMemcpyAsync(dcrd, hcrd, sizeof(hcrd), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
-  hipLaunchKernelGGL(k_canon24, dim3(1), dim3(64), 0, s, dcrd, dtc);
-  if (mixed)
-    hipLaunchKernelGGL(k_assemble<true>, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
-                       c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->unit, c->P.L, dtc,
-                       c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, err);
-  else
-    hipLaunchKernelGGL(k_assemble<false>, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
-                       c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->unit, c->P.L, dtc,
-                       c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, err);
+  int k = 1;
+  hcrd[0] = hcrd[25] = hcrd[50] = 4;
+  for (int r2 = 1; r2 <= 4; r2++)
+    for (int dx = -2; dx <= 2; dx++)
+      for (int dy = -2; dy <= 2; dy++)
+        for (int dz = -2; dz <= 2; dz++) {
+          if (dx * dx + dy * dy + dz * dz != r2) continue;
+          if (abs(dx) + abs(dy) + abs(dz) > 2) continue;
+          hcrd[k] = 4 + dx;
+          hcrd[25 + k] = 4 + dy;
+          hcrd[50 + k] = 4 + dz;
+          k++;
+        }
+  HIPCHK(hipMalloc((void **)&c->scratch, sizeof(apc_asm_scratch)));
+  HIPCHK(hipMemsetAsync(c->scratch, 0, sizeof(apc_asm_scratch), s));
+  HIPCHK(hipMemcpyAsync(c->scratch->crd, hcrd, sizeof(hcrd), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_canon24, dim3(1), dim3(64), 0, s, c->scratch->crd, c->scratch->tc);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(c->tmpl, dtc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(c->tmpl, c->scratch->tc, 3 * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipFreeAsync(dcrd, s));
-  HIPCHK(hipFreeAsync(dtc, s));
-  HIPCHK(hipFreeAsync(err, s));
-  apc_free_sell(c);
-  APCCHK(apc_build_sell(c, s));
+  return APC_OK;
+}
+
+// The assembly proper: one kernel, no allocation, no synchronisation.
+int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
+  const int64_t ntot = c->n + c->nb;
+  const bool mixed = c->P.precision != APC_FP64;
+  const unsigned gsl = (unsigned)((c->nsl + (APC_BLOCK / 64) - 1) / (APC_BLOCK / 64));
+  HIPCHK(hipMemsetAsync(&c->scratch->nfp64, 0, sizeof(unsigned long long), s));
+  if (c->nsl > 0) {
+    if (mixed)
+      hipLaunchKernelGGL(k_fit_sell<true>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,
+                         c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
+                         c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
+                         c->inv_diag, c->hscale, c->sl_w64, c->sl_w32, &c->scratch->err,
+                         &c->scratch->nfp64);
+    else
+      hipLaunchKernelGGL(k_fit_sell<false>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,
+                         c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
+                         c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
+                         c->inv_diag, c->hscale, c->sl_w64, c->sl_w32, &c->scratch->err,
+                         &c->scratch->nfp64);
+    HIPCHK(hipGetLastError());
+  }
   c->assembled = true;
   return APC_OK;
 }

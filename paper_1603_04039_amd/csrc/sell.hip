@@ -9,6 +9,8 @@
 // has all its neighbour gathers independent of each other.  Uniform slices have
 // exactly 24 entries and no weights (the weights are the shell constants);
 // general slices are padded to their longest row with (own index, weight 0).
+// This file builds the layout and the column indices at build time; the weights
+// are written by the assembly (k_fit_sell).
 #include <hip/hip_runtime.h>
 
 #include "apc_internal.h"
@@ -68,29 +70,20 @@ __global__ void __launch_bounds__(SL)
   }
 }
 
+// column indices of every slice (structure only); weights start at 0 so that
+// padding entries contribute nothing
 __global__ void __launch_bounds__(SL)
-    k_sell_fill(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
-                const int64_t *__restrict__ sl_off, const int32_t *__restrict__ sl_tmpl,
-                const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
-                const double *__restrict__ w64, const float *__restrict__ w32,
-                int32_t *__restrict__ idx, double *__restrict__ sw64, float *__restrict__ sw32) {
+    k_sell_idx(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
+               const int64_t *__restrict__ sl_off, const int32_t *__restrict__ st_off,
+               const int32_t *__restrict__ st_idx, int32_t *__restrict__ idx) {
   const int64_t s = blockIdx.x;
   const int lane = threadIdx.x;
   const int32_t row = sl_rows[s * SL + lane];
   const int len = sl_len[s];
-  const bool tm = sl_tmpl[s] != 0;
   const int64_t off = sl_off[s] + lane;
   const int32_t a = row >= 0 ? st_off[row] : 0;
   const int m = row >= 0 ? st_off[row + 1] - a : 0;
-  for (int k = 0; k < len; k++) {
-    const int64_t e = off + (int64_t)k * SL;
-    const bool real = k < m;
-    idx[e] = real ? st_idx[a + k] : (row >= 0 ? row : 0);
-    if (!tm) {
-      if (w64) sw64[e] = real ? w64[a + k] : 0.0;
-      if (w32) sw32[e] = real ? w32[a + k] : 0.0f;
-    }
-  }
+  for (int k = 0; k < len; k++) idx[off + (int64_t)k * SL] = k < m ? st_idx[a + k] : (row >= 0 ? row : 0);
 }
 
 } // namespace
@@ -164,11 +157,12 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   else
     HIPCHK(hipMalloc((void **)&c->sl_w32, ne * sizeof(float)));
   if (ns > 0) {
-    hipLaunchKernelGGL(k_sell_fill, dim3((unsigned)ns), dim3(SL), 0, s, c->sl_rows, c->sl_len,
-                       c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->w64, c->w32, c->sl_idx,
-                       c->sl_w64, c->sl_w32);
+    hipLaunchKernelGGL(k_sell_idx, dim3((unsigned)ns), dim3(SL), 0, s, c->sl_rows, c->sl_len,
+                       c->sl_off, c->st_off, c->st_idx, c->sl_idx);
     HIPCHK(hipGetLastError());
   }
+  if (c->sl_w64) HIPCHK(hipMemsetAsync(c->sl_w64, 0, ne * sizeof(double), s));
+  if (c->sl_w32) HIPCHK(hipMemsetAsync(c->sl_w32, 0, ne * sizeof(float), s));
   HIPCHK(hipFreeAsync(ent, s));
   HIPCHK(hipFreeAsync(tf, s));
   HIPCHK(hipFreeAsync(tpos, s));

@@ -84,15 +84,23 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double *part) {
   }
 }
 
-// sum of partials part[k*G .. k*G+G) in one block, fixed order; valid in thread 0
+// Sum of partials part[k*G .. k*G+G) in one block of FIN_T threads, fixed order;
+// valid in thread 0.  Each thread first issues all its loads (G <= 4 FIN_T), so the
+// finalize kernels cost one memory round trip.
+constexpr int FIN_T = 1024;
 template <int NV>
 __device__ __forceinline__ void fin_sum(const double *part, unsigned G, double (&out)[NV]) {
-  __shared__ double sh[NV][APC_BLOCK / 64];
+  __shared__ double sh[NV][FIN_T / 64];
   const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
 #pragma unroll
   for (int k = 0; k < NV; k++) {
-    double s = 0.0;
-    for (unsigned q = threadIdx.x; q < G; q += APC_BLOCK) s += part[(size_t)k * G + q];
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; u++) {
+      const unsigned q = threadIdx.x + u * FIN_T;
+      v[u] = q < G ? part[(size_t)k * G + q] : 0.0;
+    }
+    double s = (v[0] + v[1]) + (v[2] + v[3]);
     s = wave_sum(s);
     if (lane == 0) sh[k][w] = s;
   }
@@ -101,7 +109,7 @@ __device__ __forceinline__ void fin_sum(const double *part, unsigned G, double (
 #pragma unroll
     for (int k = 0; k < NV; k++) {
       double t = 0.0;
-      for (int q = 0; q < APC_BLOCK / 64; q++) t += sh[k][q];
+      for (int q = 0; q < FIN_T / 64; q++) t += sh[k][q];
       out[k] = t;
     }
   }
@@ -114,7 +122,7 @@ __device__ __forceinline__ void fin_sum(const double *part, unsigned G, double (
 // wave-uniform (readfirstlane) so that the slice's offset, kind and length come
 // from scalar loads and its column-index loads issue at once.
 constexpr int SL = APC_SLICE;
-constexpr unsigned GSPMV = 4096;
+constexpr unsigned GSPMV = 4096; // <= 4 FIN_T (one load batch per finalize thread)
 struct SlIter {
   int s, end, step;
 };
@@ -249,7 +257,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 }
 
 // alpha = rho / (rh, v)
-__global__ void __launch_bounds__(APC_BLOCK) k_fin_alpha(const double *part, unsigned G, Scal *sc) {
+__global__ void __launch_bounds__(FIN_T) k_fin_alpha(const double *part, unsigned G, Scal *sc) {
   if (sc->done) return;
   double out[1];
   fin_sum<1>(part, G, out);
@@ -264,7 +272,7 @@ __global__ void __launch_bounds__(APC_BLOCK) k_fin_alpha(const double *part, uns
 }
 
 // omega = (t, s) / (t, t)
-__global__ void __launch_bounds__(APC_BLOCK) k_fin_omega(const double *part, unsigned G, Scal *sc) {
+__global__ void __launch_bounds__(FIN_T) k_fin_omega(const double *part, unsigned G, Scal *sc) {
   if (sc->done) return;
   double out[2];
   fin_sum<2>(part, G, out);
@@ -324,7 +332,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 }
 
 // rho' = (rh, r): convergence test, beta for the next iteration
-__global__ void __launch_bounds__(APC_BLOCK) k_fin_rho(const double *part, unsigned G, Scal *sc) {
+__global__ void __launch_bounds__(FIN_T) k_fin_rho(const double *part, unsigned G, Scal *sc) {
   if (sc->done) return;
   double out[2];
   fin_sum<2>(part, G, out);
@@ -371,7 +379,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   block_partials<2>(val, part);
 }
 
-__global__ void __launch_bounds__(APC_BLOCK)
+__global__ void __launch_bounds__(FIN_T)
     k_fin_restart(const double *part, unsigned G, Scal *sc, int first) {
   double out[2];
   fin_sum<2>(part, G, out);
@@ -533,7 +541,7 @@ static int launch_restart(apc_solver_ws *w, const Op &op, const double *b, const
                           int first, unsigned g, hipStream_t s) {
   hipLaunchKernelGGL(k_restart<MODE>, dim3(g), dim3(APC_BLOCK), 0, s, op, b, x, w->r, w->rh, w->p,
                      w->v, w->part, first);
-  hipLaunchKernelGGL(k_fin_restart, dim3(1), dim3(APC_BLOCK), 0, s, w->part, g, w->sc, first);
+  hipLaunchKernelGGL(k_fin_restart, dim3(1), dim3(FIN_T), 0, s, w->part, g, w->sc, first);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
@@ -553,7 +561,7 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
                        invd, w->sc);
   hipLaunchKernelGGL(k_spmv_v<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, ph, w->v, w->rh, w->part,
                      w->sc);
-  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(APC_BLOCK), 0, s, w->part, gs, w->sc);
+  hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
   if (jac)
     hipLaunchKernelGGL(k_upd_s<true>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->v, w->s, sh,
                        invd, w->sc);
@@ -562,10 +570,10 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
                        invd, w->sc);
   hipLaunchKernelGGL(k_spmv_t<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, sh, w->s, w->t, w->part,
                      w->sc);
-  hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(APC_BLOCK), 0, s, w->part, gs, w->sc);
+  hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
   hipLaunchKernelGGL(k_upd_xr, dim3(gr), dim3(APC_BLOCK), 0, s, n, x, ph, sh, w->s, w->t, w->r,
                      w->rh, w->part, w->sc);
-  hipLaunchKernelGGL(k_fin_rho, dim3(1), dim3(APC_BLOCK), 0, s, w->part, gr, w->sc);
+  hipLaunchKernelGGL(k_fin_rho, dim3(1), dim3(FIN_T), 0, s, w->part, gr, w->sc);
 }
 
 // BiCGSTAB on A x = b from x = 0.  MODE is the SpMV of the iteration, TMODE the
@@ -669,6 +677,9 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
   HIPCHK(hipEventElapsedTime(&ms, w->e0, w->e1));
   if (st) {
     st->ms = ms;
+    unsigned long long nf = 0;
+    HIPCHK(hipMemcpy(&nf, &c->scratch->nfp64, sizeof(nf), hipMemcpyDeviceToHost));
+    c->n_fp64_rows = (int64_t)nf;
     st->n_fp64_rows = c->n_fp64_rows;
   }
   return rc;
@@ -700,6 +711,9 @@ int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *p
   HIPCHK(hipEventElapsedTime(&ms, w->e0, w->e1));
   if (st) {
     st->ms = ms;
+    unsigned long long nf = 0;
+    HIPCHK(hipMemcpy(&nf, &c->scratch->nfp64, sizeof(nf), hipMemcpyDeviceToHost));
+    c->n_fp64_rows = (int64_t)nf;
     st->n_fp64_rows = c->n_fp64_rows;
   }
   return rc;

@@ -241,9 +241,12 @@ def test_batch_recipe_clouds(apc, oracle_mod, i):
 
 @pytest.mark.parametrize("mode", ["mixed", "mixed_f32acc"])
 def test_mixed_precision_error_reported(apc, oracle_mod, c1, mode):
-    """FP32 weights (FP64 or FP32 SpMV accumulation) inside FP64 iterative
-    refinement: converges to the true residual of its own FP32-valued operator;
-    the distance to the FP64 oracle potential is reported and bounded."""
+    """FP32 stencil fit (FP64 refit when min|R_ii|/max|R_ii| < 0.1) and FP32 weights,
+    FP64 or FP32 SpMV accumulation, inside FP64 iterative refinement: converges to
+    the true residual of its own FP32-valued operator; the distances to the FP64
+    oracle's weights and potential are reported and bounded.  The normal-equation
+    fit in FP32 errs by about kappa(W V0)^2 eps_32 (kappa <~ 30 after the ratio
+    test): 1e-4 of the row scale."""
     note(f"{mode} beam_halo_1e5")
     xyz, O, _ = c1
     prec = apc.APC_MIXED if mode == "mixed" else apc.APC_MIXED_F32ACC
@@ -252,8 +255,10 @@ def test_mixed_precision_error_reported(apc, oracle_mod, c1, mode):
     w_g, d_g = G.operator()
     w_o, d_o = O.assemble()
     m = np.diff(O.nodes()["st_off"])
-    # FP32 rounding of each weight is the only difference from the FP64 rows
-    assert np.max(np.abs(w_g - w_o) / np.repeat(np.abs(d_o), m)) <= 2 ** -24
+    werr = np.max(np.abs(w_g - w_o) / np.repeat(np.abs(d_o), m))
+    note(f"  {mode}: max |w32 - w64| / |diag| = {werr:.2e}, rows refitted in FP64: "
+         f"{G.stats_fp64_rows() if hasattr(G, 'stats_fp64_rows') else 'n/a'}")
+    assert werr <= 1e-4
     rt_o, _ = O.density_solve(O.deposit(), tol=1e-13)
     phi_o, _ = O.poisson_solve(rt_o[:O.n], tol=1e-12, precond=1)
     phi, st = G.solve(torch.from_numpy(rt_o[:O.n].copy()).cuda(), tol=1e-8)
@@ -261,8 +266,9 @@ def test_mixed_precision_error_reported(apc, oracle_mod, c1, mode):
     err = np.linalg.norm(phi_g - phi_o) / np.linalg.norm(phi_o)
     note(f"  {mode}: iters={st['iters']} sweeps={st['sweeps']} true={st['rel_resid_true']:.2e} "
          f"|phi32-phi64|/|phi64|={err:.2e}")
+    note(f"  {mode}: fp64 refits {st['n_fp64_rows']} of {G.n} rows")
     assert st["status"] == 0 and st["rel_resid_true"] <= 1e-8
-    assert err < 1e-5
+    assert err < 1e-4
 
 
 def test_uniform_rows_use_lattice_constants(apc, oracle_mod):
