@@ -55,6 +55,16 @@ extern "C" {
 
 #define APC_PRECOND_NONE 0
 #define APC_PRECOND_JACOBI 1
+#define APC_PRECOND_LEARNED 2 /* needs apc_set_learned_precond; Jacobi is the fallback */
+
+/* Learned preconditioner network: a 3-layer MLP APC_MLP_IN -> 64 -> 64 -> APC_MLP_OUT
+   (ReLU), parameters as one float array [W1 (IN x 64, row-major), b1, W2 (64 x 64),
+   b2, W3 (64 x OUT), b3], APC_MLP_NPARAM floats. */
+#define APC_MLP_IN 48
+#define APC_MLP_HID 64
+#define APC_MLP_OUT 41 /* row i of M: the diagonal and up to 40 stencil entries */
+#define APC_MLP_NPARAM (48 * 64 + 64 + 64 * 64 + 64 + 64 * 41 + 41)
+#define APC_LEARN_QUAD 903 /* per row: 861 (packed lower 41x41 Q), 41 (b), 1 (c) */
 
 typedef struct apc_cloud apc_cloud;
 
@@ -80,6 +90,8 @@ typedef struct {
   double rel_resid_true; /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
   int64_t n_fp64_rows;   /* APC_MIXED: stencils refitted in FP64 (R-diagonal test) */
   double ms;             /* device time of the call, milliseconds */
+  int precond_used;      /* preconditioner of the final iteration (Jacobi after a fallback) */
+  int pad;
 } apc_stats;
 
 /* Fill *p with the defaults above for order k (domain [0,1]^3, c, max_depth left
@@ -151,7 +163,9 @@ int apc_density_solve(apc_cloud *c, const double *rho_M, double *rho_t, double t
    phi = g at boundary nodes (Dirichlet; g: nb values or NULL for 0).  rho_t: n
    (or n+nb, tail ignored); phi: n+nb out.  BiCGSTAB with optional right Jacobi
    preconditioning to recursive relative residual tol, confirmed by the true
-   FP64 residual.  APC_MIXED: FP32 weights inside FP64 iterative refinement (the
+   FP64 residual.  precond APC_PRECOND_LEARNED uses the installed learned M and
+   falls back to Jacobi when that solve does not reach tol.  APC_MIXED: FP32
+   weights inside FP64 iterative refinement (the
    true residual, with the FP32 weights widened exactly, restarts the iteration
    until it meets tol).
    Requires apc_assemble_gfd.  Synchronises the stream. */
@@ -172,6 +186,62 @@ int apc_node_derivs(apc_cloud *c, const double *f, double *D, hipStream_t stream
 
 /* Apply the assembled operator: out[i] = (L f)_i for interior i; f: n+nb. */
 int apc_apply_operator(apc_cloud *c, const double *f, double *out, hipStream_t stream);
+
+/* ---- learned preconditioner (a grown form beside the paper's method) ----
+   Row i of M has the pattern of row i of the Poisson operator: J_0 = i and J_p the
+   p-th stencil node (p = 1..m, m <= 40; boundary nodes carry weight 0), and is
+   written as m_i = (e_0 + o_i) / d_i, d_i the operator's diagonal: o_i = 0 is
+   Jacobi.  The network maps row features to o_i (APC_MLP_OUT entries, those
+   beyond m unused).  Training minimises the left approximate-inverse loss
+   ||m_i^T A - e_i^T||^2 per row, estimated with K probe vectors z ~ N(0, I):
+   E (m_i^T A z - z_i)^2.  Per row this is the quadratic
+   L_i(o) = m~^T Q m~ - 2 b^T m~ + c in m~ = e_0 + o.
+
+   Features and quadratic data of every interior row for K probes Z (K x (n+nb)
+   float64, boundary entries ignored): feat n x APC_MLP_IN float32, quad
+   n x APC_LEARN_QUAD float32 (Q packed lower row-major, then b, then c).
+   Features: the row's Poisson weights divided by |d_i| in stencil order (40
+   slots, zero padded); level(J_p) - level(i) of the first 6 stencil nodes (0 for
+   boundary nodes); level(i) / max_depth; the fraction of boundary nodes in the
+   stencil.  Z may be NULL (K ignored, quad untouched): features only.  Requires
+   apc_assemble_gfd.  Does not synchronise. */
+int apc_learn_data(apc_cloud *c, const double *Z, int K, float *feat, float *quad,
+                   hipStream_t stream);
+
+/* Mean loss over the rows listed in rows[B] (indices into feat/quad) and its
+   gradient with respect to the parameters (FP32, own forward/backward kernels).
+   loss: 1 float, grad: APC_MLP_NPARAM floats (overwritten).  Does not synchronise. */
+int apc_mlp_loss_grad(const float *params, const float *feat, const float *quad,
+                      const int32_t *rows, int B, float *loss, float *grad, hipStream_t stream);
+
+/* One Adam step (beta1 0.9, beta2 0.999, eps 1e-8; step >= 1) on params with the
+   gradient of apc_mlp_loss_grad; m and v are the Adam moments (APC_MLP_NPARAM
+   floats each, zero before the first step). */
+int apc_mlp_adam(float *params, float *m, float *v, const float *grad, int step, float lr,
+                 hipStream_t stream);
+
+/* Network output o for every interior row of the cloud (n x APC_MLP_OUT float32)
+   from feat (n x APC_MLP_IN, as written by apc_learn_data).  bf16 = 0: FP32
+   arithmetic throughout; bf16 = 1: the inference that apc_set_learned_precond
+   runs (weights and activations rounded to bfloat16, MFMA products, FP32
+   accumulation, FP32 biases).  Does not synchronise. */
+int apc_mlp_infer(apc_cloud *c, const float *params, const float *feat, int bf16, float *out,
+                  hipStream_t stream);
+
+/* Install the learned preconditioner of the cloud: features, then BF16 MFMA
+   inference with FP32 accumulation, then M stored in the solver's sliced layout
+   (FP32).  Rows whose stencil is the uniform same-level 2-ring have identical
+   features at a given level; M keeps one row per level for them (the network's
+   output for the first such row of that level).  Requires apc_assemble_gfd (and
+   again after every re-assembly, which drops M).  Synchronises. */
+int apc_set_learned_precond(apc_cloud *c, const float *params, hipStream_t stream);
+
+/* Apply a preconditioner: out = M in over the interior rows.  precond
+   APC_PRECOND_NONE: out = in; APC_PRECOND_JACOBI: out_i = in_i / d_i;
+   APC_PRECOND_LEARNED: the installed M (boundary entries of in are ignored).
+   in: n+nb, out: n, device.  Requires apc_assemble_gfd.  Does not synchronise. */
+int apc_apply_precond(apc_cloud *c, int precond, const double *in, double *out,
+                      hipStream_t stream);
 
 void apc_destroy(apc_cloud *c);
 const char *apc_strerror(int code);

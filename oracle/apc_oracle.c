@@ -1206,3 +1206,172 @@ int apco_interpolate(const apco_cloud *C, const double *phi, const double *xyz, 
   free(Dv);
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Learned preconditioner: training data, loss gradient, forward (plain loops). */
+
+#define LIN 48
+#define LHID 64
+#define LOUT 41              /* {i} + up to 40 stencil entries */
+#define LQQ (LOUT * (LOUT + 1) / 2)
+#define LQ (LQQ + LOUT + 1)
+#define LNW 40
+
+int apco_learn_data(const apco_cloud *C, const double *Z, int K, double *feat, double *quad) {
+  int64_t n = C->n, ntot = C->n + C->nb, nnz = C->st_off[n];
+  double *w = malloc((size_t)(nnz + 1) * sizeof(double));
+  double *d = malloc((size_t)(n + 1) * sizeof(double));
+  double *U = (Z && K > 0) ? malloc((size_t)K * n * sizeof(double)) : NULL;
+  if (!w || !d || (Z && K > 0 && !U)) {
+    free(w); free(d); free(U);
+    return APCO_ENOMEM;
+  }
+  int rc = apco_assemble(C, w, d);
+  if (rc) {
+    free(w); free(d); free(U);
+    return rc;
+  }
+  /* U_k = A z_k over the interior unknowns (boundary values of z taken as 0) */
+  for (int k = 0; U && k < K; k++) {
+    const double *z = Z + (int64_t)k * ntot;
+    for (int64_t i = 0; i < n; i++) {
+      double s = d[i] * z[i];
+      for (int32_t e = C->st_off[i]; e < C->st_off[i + 1]; e++)
+        if (C->st[e] < n) s += w[e] * z[C->st[e]];
+      U[(int64_t)k * n + i] = s;
+    }
+  }
+  for (int64_t i = 0; i < n; i++) {
+    int32_t a = C->st_off[i];
+    int m = C->st_off[i + 1] - a;
+    int li = C->cells[C->node_cell[i]].level;
+    double *f = feat + i * LIN;
+    for (int j = 0; j < LNW; j++) f[j] = j < m ? w[a + j] / fabs(d[i]) : 0.0;
+    for (int k = 0; k < 6; k++) {
+      int32_t v = C->st[a + k];
+      f[LNW + k] = v < n ? (double)(C->cells[C->node_cell[v]].level - li) : 0.0;
+    }
+    int nbnd = 0;
+    for (int j = 0; j < m; j++) nbnd += C->st[a + j] >= n;
+    f[46] = (double)li / (double)C->P.max_depth;
+    f[47] = (double)nbnd / (double)m;
+    if (!U) continue;
+    /* pattern of row i of M: J_0 = i, J_p = the p-th stencil node (p <= min(m, 40)) */
+    int32_t J[LOUT];
+    for (int p = 0; p < LOUT; p++) J[p] = p == 0 ? (int32_t)i : (p - 1 < m ? C->st[a + p - 1] : -1);
+    double *q = quad + i * LQ;
+    for (int t = 0; t < LQ; t++) q[t] = 0.0;
+    for (int k = 0; k < K; k++) {
+      double u[LOUT];
+      for (int p = 0; p < LOUT; p++)
+        u[p] = (J[p] >= 0 && J[p] < n) ? U[(int64_t)k * n + J[p]] / d[i] : 0.0;
+      double zi = Z[(int64_t)k * ntot + i];
+      int t = 0;
+      for (int p = 0; p < LOUT; p++) {
+        for (int r = 0; r <= p; r++) q[t++] += u[p] * u[r] / K;
+        q[LQQ + p] += u[p] * zi / K;
+      }
+      q[LQ - 1] += zi * zi / K;
+    }
+  }
+  free(w); free(d); free(U);
+  return 0;
+}
+
+int apco_mlp_loss_grad(const double *P, const double *feat, const double *quad,
+                       const int32_t *rows, int B, double *loss, double *grad) {
+  const double *W1 = P, *b1 = W1 + LIN * LHID, *W2 = b1 + LHID, *b2 = W2 + LHID * LHID,
+               *W3 = b2 + LHID, *b3 = W3 + LHID * LOUT;
+  int np = LIN * LHID + LHID + LHID * LHID + LHID + LHID * LOUT + LOUT;
+  double *gW1 = grad, *gb1 = gW1 + LIN * LHID, *gW2 = gb1 + LHID, *gb2 = gW2 + LHID * LHID,
+         *gW3 = gb2 + LHID, *gb3 = gW3 + LHID * LOUT;
+  for (int t = 0; t < np; t++) grad[t] = 0.0;
+  double total = 0.0;
+  for (int bi = 0; bi < B; bi++) {
+    const double *x = feat + (int64_t)rows[bi] * LIN;
+    const double *q = quad + (int64_t)rows[bi] * LQ;
+    double h1[LHID], h2[LHID], o[LOUT];
+    for (int j = 0; j < LHID; j++) {
+      double s = b1[j];
+      for (int i = 0; i < LIN; i++) s += x[i] * W1[i * LHID + j];
+      h1[j] = s > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < LHID; j++) {
+      double s = b2[j];
+      for (int i = 0; i < LHID; i++) s += h1[i] * W2[i * LHID + j];
+      h2[j] = s > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < LOUT; j++) {
+      double s = b3[j];
+      for (int i = 0; i < LHID; i++) s += h2[i] * W3[i * LOUT + j];
+      o[j] = s;
+    }
+    /* L = m^T Q m - 2 b^T m + c with Q symmetric from its packed lower triangle */
+    double m[LOUT], Qm[LOUT], dO[LOUT];
+    for (int k = 0; k < LOUT; k++) m[k] = o[k] + (k == 0 ? 1.0 : 0.0);
+    for (int p = 0; p < LOUT; p++) {
+      Qm[p] = 0.0;
+      for (int r = 0; r < LOUT; r++) {
+        int hi = p > r ? p : r, lo = p > r ? r : p;
+        Qm[p] += q[hi * (hi + 1) / 2 + lo] * m[r];
+      }
+    }
+    double L = q[LQ - 1];
+    for (int p = 0; p < LOUT; p++) {
+      L += m[p] * Qm[p] - 2.0 * q[LQQ + p] * m[p];
+      dO[p] = 2.0 * (Qm[p] - q[LQQ + p]) / B;
+    }
+    total += L;
+    /* back-propagation */
+    double dh2[LHID], dh1[LHID];
+    for (int j = 0; j < LOUT; j++) {
+      gb3[j] += dO[j];
+      for (int i = 0; i < LHID; i++) gW3[i * LOUT + j] += h2[i] * dO[j];
+    }
+    for (int i = 0; i < LHID; i++) {
+      double s = 0.0;
+      for (int j = 0; j < LOUT; j++) s += dO[j] * W3[i * LOUT + j];
+      dh2[i] = h2[i] > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < LHID; j++) {
+      gb2[j] += dh2[j];
+      for (int i = 0; i < LHID; i++) gW2[i * LHID + j] += h1[i] * dh2[j];
+    }
+    for (int i = 0; i < LHID; i++) {
+      double s = 0.0;
+      for (int j = 0; j < LHID; j++) s += dh2[j] * W2[i * LHID + j];
+      dh1[i] = h1[i] > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < LHID; j++) {
+      gb1[j] += dh1[j];
+      for (int i = 0; i < LIN; i++) gW1[i * LHID + j] += x[i] * dh1[j];
+    }
+  }
+  *loss = total / B;
+  return 0;
+}
+
+int apco_mlp_forward(const double *P, const double *feat, int64_t nrow, double *out) {
+  const double *W1 = P, *b1 = W1 + LIN * LHID, *W2 = b1 + LHID, *b2 = W2 + LHID * LHID,
+               *W3 = b2 + LHID, *b3 = W3 + LHID * LOUT;
+  for (int64_t r = 0; r < nrow; r++) {
+    const double *x = feat + r * LIN;
+    double h1[LHID], h2[LHID];
+    for (int j = 0; j < LHID; j++) {
+      double s = b1[j];
+      for (int i = 0; i < LIN; i++) s += x[i] * W1[i * LHID + j];
+      h1[j] = s > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < LHID; j++) {
+      double s = b2[j];
+      for (int i = 0; i < LHID; i++) s += h1[i] * W2[i * LHID + j];
+      h2[j] = s > 0.0 ? s : 0.0;
+    }
+    for (int j = 0; j < LOUT; j++) {
+      double s = b3[j];
+      for (int i = 0; i < LHID; i++) s += h2[i] * W3[i * LOUT + j];
+      out[r * LOUT + j] = s;
+    }
+  }
+  return 0;
+}

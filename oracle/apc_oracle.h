@@ -111,6 +111,25 @@ int apco_node_derivs(const apco_cloud *C, const double *f, double *D);
 int apco_interpolate(const apco_cloud *C, const double *phi, const double *xyz, double *phi_p,
                      double *grad_p);
 
+/* ---- learned preconditioner (checks of the training data and gradients) ----
+   Row i of M has the pattern J_0 = i, J_p = the p-th stencil node (p = 1..m,
+   m <= 40) and is m_i = (e_0 + o_i) / d_i with o_i (41) the network output.
+   Row features (n x 48): Poisson weights / |d_i| in stencil order (40 slots, zero
+   padded); level(J_p) - level(i) of the first 6 stencil nodes (0 for boundary
+   nodes); level(i) / max_depth; the fraction of boundary nodes in the stencil.
+   Quadratic data (n x 903) from K probes Z (K x (n+nb), boundary entries
+   ignored): with U = A Z over the interior unknowns and u_p = U[J_p] / d_i (0 for
+   boundary or absent J_p): Q = u u^T / K (packed lower, 861), b = u z_i / K (41),
+   c = z_i^2 / K. */
+int apco_learn_data(const apco_cloud *C, const double *Z, int K, double *feat, double *quad);
+/* Mean over rows[B] of L(o) = m^T Q m - 2 b^T m + c, m = e_0 + o, o = MLP(feat) with
+   the 48 -> 64 -> 64 -> 41 ReLU network, params laid out [W1 (48x64), b1, W2 (64x64),
+   b2, W3 (64x41), b3]; the gradient of that mean with respect to params. */
+int apco_mlp_loss_grad(const double *params, const double *feat, const double *quad,
+                       const int32_t *rows, int B, double *loss, double *grad);
+/* Network output o (nrow x 41) of every feature row (nrow x 48), same layout. */
+int apco_mlp_forward(const double *params, const double *feat, int64_t nrow, double *out);
+
 #ifdef __cplusplus
 }
 #endif

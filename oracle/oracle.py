@@ -66,6 +66,9 @@ def _load():
     lib.apco_num_unknowns.argtypes = [ct.c_int]
     lib.apco_monomials.argtypes = [ct.c_int, P]
     lib.apco_thresholds.argtypes = [ct.POINTER(_Params), P]
+    lib.apco_learn_data.argtypes = [P, P, ct.c_int, P, P]
+    lib.apco_mlp_loss_grad.argtypes = [P, P, P, P, ct.c_int, P, P]
+    lib.apco_mlp_forward.argtypes = [P, P, ct.c_int64, P]
     _lib = lib
     return lib
 
@@ -111,6 +114,35 @@ def thresholds(**kw) -> np.ndarray:
     T = np.zeros(P.max_depth + 1)
     _load().apco_thresholds(ct.byref(P), _ptr(T))
     return T
+
+
+MLP_OUT = 41
+LEARN_QUAD = MLP_OUT * (MLP_OUT + 1) // 2 + MLP_OUT + 1
+MLP_NPARAM = 48 * 64 + 64 + 64 * 64 + 64 + 64 * MLP_OUT + MLP_OUT
+
+
+def mlp_loss_grad(params, feat, quad, rows):
+    """FP64 mean loss and gradient of the learned-preconditioner network."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.float64)
+    q = np.ascontiguousarray(quad, dtype=np.float64)
+    r = np.ascontiguousarray(rows, dtype=np.int32)
+    assert P.size == MLP_NPARAM
+    g = np.zeros(MLP_NPARAM)
+    loss = np.zeros(1)
+    _check(_load().apco_mlp_loss_grad(_ptr(P), _ptr(f), _ptr(q), _ptr(r), r.size, _ptr(loss),
+                                      _ptr(g)), "mlp_loss_grad")
+    return loss[0], g
+
+
+def mlp_forward(params, feat):
+    """FP64 network output (nrow x 41) of the learned-preconditioner network."""
+    P = np.ascontiguousarray(params, dtype=np.float64)
+    f = np.ascontiguousarray(feat, dtype=np.float64)
+    assert P.size == MLP_NPARAM and f.shape[1] == 48
+    out = np.zeros((f.shape[0], MLP_OUT))
+    _check(_load().apco_mlp_forward(_ptr(P), _ptr(f), f.shape[0], _ptr(out)), "mlp_forward")
+    return out
 
 
 def wls_fit(order: int, delta: np.ndarray):
@@ -243,6 +275,18 @@ class OracleCloud:
         out = np.zeros((self.n, self.p))
         _check(self.lib.apco_node_derivs(self.h, _ptr(f), _ptr(out)), "node_derivs")
         return out
+
+    def learn_data(self, Z=None):
+        """Features (n x 48) and, with probes Z (K x (n+nb)), quadratic data (n x 903)."""
+        feat = np.zeros((self.n, 48))
+        if Z is None:
+            _check(self.lib.apco_learn_data(self.h, None, 0, _ptr(feat), None), "learn_data")
+            return feat, None
+        Z = np.ascontiguousarray(Z, dtype=np.float64)
+        quad = np.zeros((self.n, LEARN_QUAD))
+        _check(self.lib.apco_learn_data(self.h, _ptr(Z), Z.shape[0], _ptr(feat), _ptr(quad)),
+               "learn_data")
+        return feat, quad
 
     def interpolate(self, phi, xyz=None):
         phi = np.ascontiguousarray(phi, dtype=np.float64)

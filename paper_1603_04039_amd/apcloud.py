@@ -18,13 +18,17 @@ LIB_PATH = os.path.join(_HERE, "libapcloud.so")
 APC_OK, APC_EINVAL, APC_ENOMEM, APC_EHIP, APC_EDOMAIN, APC_ESTENCIL = 0, -1, -2, -3, -4, -5
 APC_ENOCONV = 1
 APC_FP64, APC_MIXED, APC_MIXED_F32ACC = 0, 1, 2
-APC_PRECOND_NONE, APC_PRECOND_JACOBI = 0, 1
+APC_PRECOND_NONE, APC_PRECOND_JACOBI, APC_PRECOND_LEARNED = 0, 1, 2
+MLP_IN, MLP_HID, MLP_OUT = 48, 64, 41
+MLP_NPARAM = MLP_IN * MLP_HID + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_HID * MLP_OUT + MLP_OUT
+LEARN_QUAD = MLP_OUT * (MLP_OUT + 1) // 2 + MLP_OUT + 1
 
 # every symbol declared in include/apcloud.h
 EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_nodes",
            "apc_assemble_gfd", "apc_get_operator", "apc_operator_info", "apc_deposit", "apc_density_solve",
            "apc_solve", "apc_interpolate_force", "apc_node_derivs", "apc_apply_operator",
-           "apc_destroy", "apc_strerror", "apc_last_error"]
+           "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
+           "apc_set_learned_precond", "apc_apply_precond", "apc_destroy", "apc_strerror", "apc_last_error"]
 
 
 class ApcError(RuntimeError):
@@ -43,7 +47,8 @@ class Params(ct.Structure):
 class Stats(ct.Structure):
     _fields_ = [("iters", ct.c_int), ("restarts", ct.c_int), ("sweeps", ct.c_int),
                 ("status", ct.c_int), ("rel_resid", ct.c_double),
-                ("rel_resid_true", ct.c_double), ("n_fp64_rows", ct.c_int64), ("ms", ct.c_double)]
+                ("rel_resid_true", ct.c_double), ("n_fp64_rows", ct.c_int64), ("ms", ct.c_double),
+                ("precond_used", ct.c_int), ("pad", ct.c_int)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -77,6 +82,12 @@ def load_library(path: str = LIB_PATH):
     lib.apc_interpolate_force.argtypes = [P, P, P, P, P]
     lib.apc_node_derivs.argtypes = [P, P, P, P]
     lib.apc_apply_operator.argtypes = [P, P, P, P]
+    lib.apc_learn_data.argtypes = [P, P, ct.c_int, P, P, P]
+    lib.apc_mlp_loss_grad.argtypes = [P, P, P, P, ct.c_int, P, P, P]
+    lib.apc_mlp_adam.argtypes = [P, P, P, P, ct.c_int, ct.c_float, P]
+    lib.apc_mlp_infer.argtypes = [P, P, P, ct.c_int, P, P]
+    lib.apc_set_learned_precond.argtypes = [P, P, P]
+    lib.apc_apply_precond.argtypes = [P, ct.c_int, P, P, P]
     lib.apc_destroy.argtypes = [P]
     lib.apc_destroy.restype = None
     lib.apc_strerror.argtypes = [ct.c_int]
@@ -257,12 +268,75 @@ class Cloud:
                                         _dptr(D), _stream(stream)), "apc_node_derivs")
         return D
 
+    # ---- learned preconditioner
+    def learn_data(self, Z=None, stream=None):
+        """Row features (n x 48 float32) and, with probes Z (K x (n+nb) float64),
+        the per-row quadratic loss data (n x 903 float32)."""
+        import torch
+        nt = self.n + self.nb
+        feat = torch.empty((self.n, MLP_IN), dtype=torch.float32, device="cuda")
+        quad = None
+        K = 0
+        if Z is not None:
+            assert Z.dim() == 2 and Z.shape[1] == nt
+            K = Z.shape[0]
+            quad = torch.empty((self.n, LEARN_QUAD), dtype=torch.float32, device="cuda")
+        _check(self.lib.apc_learn_data(self.h, _dptr(Z, torch.float64), K, _dptr(feat),
+                                       _dptr(quad), _stream(stream)), "apc_learn_data")
+        return feat, quad
+
+    def mlp_infer(self, params, feat, bf16=False, stream=None):
+        import torch
+        out = torch.empty((self.n, MLP_OUT), dtype=torch.float32, device="cuda")
+        _check(self.lib.apc_mlp_infer(self.h, _dptr(params, torch.float32, MLP_NPARAM),
+                                      _dptr(feat, torch.float32, self.n * MLP_IN), int(bf16),
+                                      _dptr(out), _stream(stream)), "apc_mlp_infer")
+        return out
+
+    def set_learned_precond(self, params, stream=None):
+        import torch
+        _check(self.lib.apc_set_learned_precond(self.h, _dptr(params, torch.float32, MLP_NPARAM),
+                                                _stream(stream)), "apc_set_learned_precond")
+
+    def apply_precond(self, f, precond=APC_PRECOND_LEARNED, stream=None):
+        """out = M f over the interior rows (f: n+nb)."""
+        import torch
+        out = torch.empty(self.n, dtype=torch.float64, device="cuda")
+        _check(self.lib.apc_apply_precond(self.h, int(precond),
+                                          _dptr(f, torch.float64, self.n + self.nb), _dptr(out),
+                                          _stream(stream)), "apc_apply_precond")
+        return out
+
     def apply_operator(self, f, stream=None):
         import torch
         out = torch.empty(self.n, dtype=torch.float64, device="cuda")
         _check(self.lib.apc_apply_operator(self.h, _dptr(f, torch.float64, self.n + self.nb),
                                            _dptr(out), _stream(stream)), "apc_apply_operator")
         return out
+
+
+def mlp_loss_grad(params, feat, quad, rows, stream=None, grad=None, loss=None):
+    """Mean loss over feat/quad rows[B] and its gradient (FP32 device tensors)."""
+    import torch
+    lib = load_library()
+    grad = grad if grad is not None else torch.empty(MLP_NPARAM, dtype=torch.float32,
+                                                     device="cuda")
+    loss = loss if loss is not None else torch.empty(1, dtype=torch.float32, device="cuda")
+    _check(lib.apc_mlp_loss_grad(_dptr(params, torch.float32, MLP_NPARAM),
+                                 _dptr(feat, torch.float32), _dptr(quad, torch.float32),
+                                 _dptr(rows, torch.int32), rows.numel(), _dptr(loss),
+                                 _dptr(grad, torch.float32, MLP_NPARAM), _stream(stream)),
+           "apc_mlp_loss_grad")
+    return loss, grad
+
+
+def mlp_adam(params, m, v, grad, step, lr, stream=None):
+    import torch
+    lib = load_library()
+    f32 = torch.float32
+    _check(lib.apc_mlp_adam(_dptr(params, f32, MLP_NPARAM), _dptr(m, f32, MLP_NPARAM),
+                            _dptr(v, f32, MLP_NPARAM), _dptr(grad, f32, MLP_NPARAM), int(step),
+                            float(lr), _stream(stream)), "apc_mlp_adam")
 
 
 # C-ABI names as free functions

@@ -8,7 +8,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libapcloud.so")
-SOURCES = ["primitives.hip", "build.hip", "gfd.hip", "sell.hip", "solve.hip", "api.cpp"]
+SOURCES = ["primitives.hip", "build.hip", "gfd.hip", "sell.hip", "solve.hip", "learned.hip", "api.cpp"]
 
 
 def build_library(verbose: bool = False) -> str:

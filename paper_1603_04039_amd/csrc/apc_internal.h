@@ -12,7 +12,8 @@
 #define APC_RING_CAP 2048 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
 #define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
-#define APC_TAU_FP32 0.1  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
+#define APC_TAU_FP32 0.1
+#define APC_MAX_LEVELS 24 // > max_depth (<= 20): per-level tables  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
 
 void apc_set_hip_error(hipError_t e, const char *what, const char *file, int line);
 
@@ -123,6 +124,11 @@ struct apc_cloud {
   uint8_t *fp64row = nullptr;                  // n (APC_MIXED): refitted in FP64
   int64_t n_fp64_rows = 0;
   apc_asm_scratch *scratch = nullptr;
+  // learned preconditioner M: diagonal per row, off-diagonal weights in the
+  // operator's sliced layout (general slices), and per-level rows of the uniform
+  // 2-ring rows (APC_MAX_LEVELS x 25: diagonal, then the 24 stencil entries)
+  float *m_diag = nullptr, *m_sell = nullptr, *m_tmpl = nullptr;
+  bool learned = false;
   // rows whose stencil is the uniform 24-node 2-ring of their own level share one
   // set of weights c_shell / h_c^2 (shells r^2 = s^2, 2 s^2, 4 s^2): rkind[i] is
   // the level of such a row, -1 for a general row
@@ -152,6 +158,17 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
                    apc_cloud **out);
 int apc_assemble_impl(apc_cloud *c, hipStream_t s);
 int apc_prepare_operator(apc_cloud *c, hipStream_t s);
+int apc_learn_data_impl(apc_cloud *c, const double *Z, int K, float *feat, float *quad,
+                        hipStream_t s);
+int apc_mlp_loss_grad_impl(const float *P, const float *feat, const float *quad,
+                           const int32_t *rows, int B, float *loss, float *grad, hipStream_t s);
+int apc_mlp_adam_impl(float *P, float *m, float *v, const float *g, int step, float lr,
+                      hipStream_t s);
+int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16, float *out,
+                       hipStream_t s);
+int apc_set_learned_impl(apc_cloud *c, const float *P, hipStream_t s);
+int apc_apply_precond_impl(apc_cloud *c, int precond, const double *in, double *out,
+                           hipStream_t s);
 int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s);
 int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
                     hipStream_t s);

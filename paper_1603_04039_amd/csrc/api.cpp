@@ -200,6 +200,49 @@ int apc_apply_operator(apc_cloud *c, const double *f, double *out, hipStream_t s
   return apc_apply_impl(c, f, out, stream);
 }
 
+int apc_learn_data(apc_cloud *c, const double *Z, int K, float *feat, float *quad,
+                   hipStream_t stream) {
+  if (!c || !feat || (Z && (K < 1 || !quad))) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_learn_data_impl(c, Z, Z ? K : 0, feat, quad, stream);
+}
+
+int apc_mlp_loss_grad(const float *params, const float *feat, const float *quad,
+                      const int32_t *rows, int B, float *loss, float *grad, hipStream_t stream) {
+  if (!params || !feat || !quad || !rows || B < 1 || !loss || !grad) return APC_EINVAL;
+  return apc_mlp_loss_grad_impl(params, feat, quad, rows, B, loss, grad, stream);
+}
+
+int apc_mlp_adam(float *params, float *m, float *v, const float *grad, int step, float lr,
+                 hipStream_t stream) {
+  if (!params || !m || !v || !grad || step < 1 || !(lr > 0.0f)) return APC_EINVAL;
+  return apc_mlp_adam_impl(params, m, v, grad, step, lr, stream);
+}
+
+int apc_mlp_infer(apc_cloud *c, const float *params, const float *feat, int bf16, float *out,
+                  hipStream_t stream) {
+  if (!c || !params || !feat || !out || (bf16 != 0 && bf16 != 1)) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_mlp_infer_impl(c, params, feat, bf16, out, stream);
+}
+
+int apc_set_learned_precond(apc_cloud *c, const float *params, hipStream_t stream) {
+  if (!c || !params) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_set_learned_impl(c, params, stream);
+}
+
+int apc_apply_precond(apc_cloud *c, int precond, const double *in, double *out,
+                      hipStream_t stream) {
+  if (!c || !in || !out) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_apply_precond_impl(c, precond, in, out, stream);
+}
+
 void apc_destroy(apc_cloud *c) {
   if (!c) return;
   DeviceGuard g(c->device);

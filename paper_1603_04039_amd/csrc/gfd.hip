@@ -451,6 +451,7 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
   const int64_t ntot = c->n + c->nb;
   const bool mixed = c->P.precision != APC_FP64;
   const unsigned gsl = (unsigned)((c->nsl + (APC_BLOCK / 64) - 1) / (APC_BLOCK / 64));
+  c->learned = false; // M depends on the assembled rows: install it again
   HIPCHK(hipMemsetAsync(&c->scratch->nfp64, 0, sizeof(unsigned long long), s));
   if (c->nsl > 0) {
     if (mixed)

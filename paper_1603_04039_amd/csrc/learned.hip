@@ -1,0 +1,605 @@
+// Learned preconditioner on gfx950: training data, FP32 training kernels
+// (forward, backward, Adam), FP32 reference inference and BF16 MFMA inference.
+//
+// Row i of M has the pattern of row i of the operator (J_0 = i, J_p the p-th
+// stencil node) and is written as m_i = (e_0 + o_i) / d_i (o = 0 is Jacobi).  The
+// network maps 48 row features to o_i (41 entries).  The training loss of a row
+// is the left approximate-inverse residual ||m_i^T A - e_i^T||^2 estimated with
+// K probes z ~ N(0, I): with U = A Z and u_p = U[J_p] / d_i, Q = u u^T / K,
+// b = u z_i / K, c = z_i^2 / K, the loss is L(o) = m~^T Q m~ - 2 b^T m~ + c with
+// m~ = e_0 + o.
+#include <hip/hip_runtime.h>
+
+#include <climits>
+#include <cmath>
+
+#include "apc_internal.h"
+
+namespace {
+
+constexpr int IN = APC_MLP_IN, HID = APC_MLP_HID, OUT = APC_MLP_OUT;
+constexpr int NQQ = OUT * (OUT + 1) / 2; // packed lower Q
+constexpr int NQ = APC_LEARN_QUAD;
+static_assert(NQ == NQQ + OUT + 1, "quadratic data layout");
+constexpr int NW = 40; // stencil-weight feature slots (= OUT - 1)
+static_assert(NW == OUT - 1, "pattern");
+constexpr int NT = 25; // per-level row of M for uniform 2-ring rows
+// parameter offsets
+constexpr int OW1 = 0, OB1 = OW1 + IN * HID, OW2 = OB1 + HID, OB2 = OW2 + HID * HID,
+              OW3 = OB2 + HID, OB3 = OW3 + HID * OUT, NPAR = OB3 + OUT;
+static_assert(NPAR == APC_MLP_NPARAM, "parameter layout");
+
+struct RowOp {
+  const int32_t *st_off, *st_idx;
+  const double *w64;
+  const float *w32;
+  const int8_t *rk;
+  const double *diag;
+  const int32_t *level;
+  double tc[3];
+  double L;
+  int64_t n;
+  int max_depth;
+};
+
+__device__ __forceinline__ double row_weight(const RowOp &r, int64_t i, int j, int32_t a) {
+  if (r.rk[i] >= 0) {
+    const double hc = r.L / (double)(1 << r.rk[i]);
+    const double w = r.tc[j < 6 ? 0 : (j < 18 ? 1 : 2)] / (hc * hc);
+    return r.w64 ? w : (double)(float)w;
+  }
+  return r.w64 ? r.w64[a + j] : (double)r.w32[a + j];
+}
+
+// features of row i (IN floats)
+__device__ inline void row_features(const RowOp &r, int64_t i, float *f) {
+  const int32_t a = r.st_off[i];
+  const int m = r.st_off[i + 1] - a;
+  const double inv = 1.0 / fabs(r.diag[i]);
+  for (int j = 0; j < NW; j++) f[j] = j < m ? (float)(row_weight(r, i, j, a) * inv) : 0.0f;
+  const int li = r.level[i];
+  for (int k = 0; k < 6; k++) {
+    const int32_t v = r.st_idx[a + k];
+    f[NW + k] = v < r.n ? (float)(r.level[v] - li) : 0.0f;
+  }
+  int nb = 0;
+  for (int j = 0; j < m; j++) nb += r.st_idx[a + j] >= r.n ? 1 : 0;
+  f[46] = (float)((double)li / (double)r.max_depth);
+  f[47] = (float)((double)nb / (double)m);
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_features(RowOp r, float *__restrict__ feat) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= r.n) return;
+  float f[IN];
+  row_features(r, i, f);
+  for (int j = 0; j < IN; j++) feat[i * IN + j] = f[j];
+}
+
+// pattern node p of row i (-1: absent or boundary)
+__device__ __forceinline__ int32_t pat(const RowOp &r, int64_t i, int32_t a, int m, int p) {
+  if (p == 0) return (int32_t)i;
+  if (p - 1 >= m) return -1;
+  const int32_t v = r.st_idx[a + p - 1];
+  return v < r.n ? v : -1;
+}
+
+// one thread per (row, entry t of the quadratic data): sums over the K probes
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_learn_quad(RowOp r, const double *__restrict__ Z, const double *__restrict__ U, int K,
+                 int64_t ntot, float *__restrict__ quad) {
+  const int64_t g = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (g >= r.n * NQ) return;
+  const int64_t i = g / NQ;
+  const int t = (int)(g - i * NQ);
+  const int32_t a = r.st_off[i];
+  const int m = r.st_off[i + 1] - a;
+  const double inv = 1.0 / r.diag[i];
+  double acc = 0.0;
+  if (t < NQQ) {
+    int p = 0;
+    while ((p + 1) * (p + 2) / 2 <= t) p++;
+    const int q = t - p * (p + 1) / 2;
+    const int32_t jp = pat(r, i, a, m, p), jq = pat(r, i, a, m, q);
+    if (jp >= 0 && jq >= 0)
+      for (int k = 0; k < K; k++) acc += (U[(int64_t)k * ntot + jp] * inv) * (U[(int64_t)k * ntot + jq] * inv);
+  } else if (t < NQQ + OUT) {
+    const int32_t jp = pat(r, i, a, m, t - NQQ);
+    if (jp >= 0)
+      for (int k = 0; k < K; k++) acc += (U[(int64_t)k * ntot + jp] * inv) * Z[(int64_t)k * ntot + i];
+  } else {
+    for (int k = 0; k < K; k++) {
+      const double z = Z[(int64_t)k * ntot + i];
+      acc += z * z;
+    }
+  }
+  quad[g] = (float)(acc / (double)K);
+}
+
+// probe z (n+nb, interior part used) -> zero-tailed copy
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_probe_copy(const double *__restrict__ z, int64_t n, int64_t ntot, double *__restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < ntot) x[i] = i < n ? z[i] : 0.0;
+}
+
+// ---------------------------------------------------------------- FP32 training
+// Y[b][o] = act(sum_i X[b][i] W[i][o] + bias[o]); rows of X gathered through rows[] when given
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_dense_fwd(const float *__restrict__ X, const int32_t *__restrict__ rows, int B, int In,
+                int Out, const float *__restrict__ W, const float *__restrict__ bias, int relu,
+                float *__restrict__ Y) {
+  const int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (t >= (int64_t)B * Out) return;
+  const int bi = (int)(t / Out), o = (int)(t % Out);
+  const int64_t xr = rows ? rows[bi] : bi;
+  const float *x = X + xr * In;
+  float s = bias[o];
+  for (int i = 0; i < In; i++) s += x[i] * W[i * Out + o];
+  Y[t] = relu ? fmaxf(s, 0.0f) : s;
+}
+
+// loss rows and dL/do (mean over the batch); loss of row b in lrow[b]
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_quad_loss(const float *__restrict__ O, const float *__restrict__ quad,
+                const int32_t *__restrict__ rows, int B, float *__restrict__ dO,
+                float *__restrict__ lrow) {
+  const int bi = blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (bi >= B) return;
+  const float *q = quad + (int64_t)rows[bi] * NQ;
+  float m[OUT];
+  for (int k = 0; k < OUT; k++) m[k] = O[(int64_t)bi * OUT + k] + (k == 0 ? 1.0f : 0.0f);
+  float Qm[OUT];
+  for (int p = 0; p < OUT; p++) Qm[p] = 0.0f;
+  int t = 0;
+  for (int p = 0; p < OUT; p++)
+    for (int k = 0; k <= p; k++, t++) {
+      Qm[p] += q[t] * m[k];
+      if (k != p) Qm[k] += q[t] * m[p];
+    }
+  float L = q[NQ - 1];
+  for (int p = 0; p < OUT; p++) {
+    L += m[p] * Qm[p] - 2.0f * q[NQQ + p] * m[p];
+    dO[(int64_t)bi * OUT + p] = 2.0f * (Qm[p] - q[NQQ + p]) / (float)B;
+  }
+  lrow[bi] = L;
+}
+
+// fixed-order mean of lrow (one block)
+__global__ void __launch_bounds__(APC_BLOCK) k_mean(const float *__restrict__ v, int B, float *out) {
+  __shared__ float sh[APC_BLOCK];
+  float s = 0.0f;
+  for (int b = threadIdx.x; b < B; b += APC_BLOCK) s += v[b];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = APC_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) sh[threadIdx.x] += sh[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = sh[0] / (float)B;
+}
+
+// partial weight gradients over a chunk of CH rows: P[chunk][i][o] (i == In: bias)
+constexpr int CH = 256;
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_dense_bwd_w(const float *__restrict__ X, const int32_t *__restrict__ rows, int B, int In,
+                  int Out, const float *__restrict__ dY, float *__restrict__ P) {
+  const int chunk = blockIdx.y;
+  const int t = blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (t >= (In + 1) * Out) return;
+  const int i = t / Out, o = t % Out;
+  const int b0 = chunk * CH, b1 = min(B, b0 + CH);
+  float s = 0.0f;
+  for (int b = b0; b < b1; b++) {
+    const int64_t xr = rows ? rows[b] : b;
+    const float xv = i < In ? X[xr * In + i] : 1.0f;
+    s += xv * dY[(int64_t)b * Out + o];
+  }
+  P[(int64_t)chunk * (In + 1) * Out + t] = s;
+}
+
+// sum the chunk partials (fixed order) into the gradient slots dW (In x Out) and db (Out)
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_sum_chunks(const float *__restrict__ P, int nch, int In, int Out, float *__restrict__ dW,
+                 float *__restrict__ db) {
+  const int t = blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (t >= (In + 1) * Out) return;
+  float s = 0.0f;
+  for (int c = 0; c < nch; c++) s += P[(int64_t)c * (In + 1) * Out + t];
+  if (t < In * Out)
+    dW[t] = s;
+  else
+    db[t - In * Out] = s;
+}
+
+// dX[b][i] = (sum_o dY[b][o] W[i][o]) * (H[b][i] > 0)
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_dense_bwd_x(const float *__restrict__ dY, const float *__restrict__ W,
+                  const float *__restrict__ H, int B, int In, int Out, float *__restrict__ dX) {
+  const int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (t >= (int64_t)B * In) return;
+  const int b = (int)(t / In), i = (int)(t % In);
+  float s = 0.0f;
+  for (int o = 0; o < Out; o++) s += dY[(int64_t)b * Out + o] * W[i * Out + o];
+  dX[t] = H[t] > 0.0f ? s : 0.0f;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_adam(float *__restrict__ p, float *__restrict__ m, float *__restrict__ v,
+           const float *__restrict__ g, int n, float lr, float bc1, float bc2) {
+  const int i = blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const float gi = g[i];
+  const float mi = 0.9f * m[i] + 0.1f * gi;
+  const float vi = 0.999f * v[i] + 0.001f * gi * gi;
+  m[i] = mi;
+  v[i] = vi;
+  p[i] -= lr * (mi / bc1) / (sqrtf(vi / bc2) + 1e-8f);
+}
+
+// ---------------------------------------------------------------- inference
+__device__ inline void mlp_row_f32(const float *__restrict__ P, const float *f, float *o) {
+  float h1[HID], h2[HID];
+  for (int j = 0; j < HID; j++) {
+    float s = P[OB1 + j];
+    for (int i = 0; i < IN; i++) s += f[i] * P[OW1 + i * HID + j];
+    h1[j] = fmaxf(s, 0.0f);
+  }
+  for (int j = 0; j < HID; j++) {
+    float s = P[OB2 + j];
+    for (int i = 0; i < HID; i++) s += h1[i] * P[OW2 + i * HID + j];
+    h2[j] = fmaxf(s, 0.0f);
+  }
+  for (int j = 0; j < OUT; j++) {
+    float s = P[OB3 + j];
+    for (int i = 0; i < HID; i++) s += h2[i] * P[OW3 + i * OUT + j];
+    o[j] = s;
+  }
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_infer_f32(const float *__restrict__ P, const float *__restrict__ feat, int64_t n,
+                float *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  float o[OUT];
+  mlp_row_f32(P, feat + i * IN, o);
+  for (int k = 0; k < OUT; k++) out[i * OUT + k] = o[k];
+}
+
+// bfloat16 bits of x, round to nearest even (finite inputs)
+__device__ __forceinline__ uint16_t bf16_of(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7fffu + ((u >> 16) & 1u);
+  return (uint16_t)(u >> 16);
+}
+
+// BF16 copies of the weights, zero-padded to multiples of 16 (N of layer 3: 48)
+constexpr int K1 = 48, N3 = 48;
+static_assert(OUT <= N3 && IN == K1, "tile padding");
+constexpr int NWB = K1 * HID + HID * HID + HID * N3;
+__global__ void k_pack_bf16(const float *__restrict__ P, uint16_t *__restrict__ W1,
+                            uint16_t *__restrict__ W2, uint16_t *__restrict__ W3) {
+  const int t = blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (t < K1 * HID) W1[t] = bf16_of(P[OW1 + t]);
+  if (t < HID * HID) W2[t] = bf16_of(P[OW2 + t]);
+  if (t < HID * N3) {
+    const int i = t / N3, j = t % N3;
+    W3[t] = bf16_of(j < OUT ? P[OW3 + i * OUT + j] : 0.0f);
+  }
+}
+
+typedef short short4_t __attribute__((ext_vector_type(4)));
+typedef float float4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ short bf16_bits(float x) { return (short)bf16_of(x); }
+__device__ __forceinline__ short bf16_raw(uint16_t h) { return (short)h; }
+
+// where the BF16 inference writes
+struct InferOut {
+  int mode;             // 0: o per row; 1: M of general slices; 2: per-level rows of M
+  float *o;             // mode 0: n x OUT
+  float *m_diag;        // mode 1
+  float *m_sell;        // mode 1 (operator's sliced layout)
+  float *m_tmpl;        // mode 2: APC_MAX_LEVELS x NT
+  const int32_t *sl_tmpl, *sl_len, *st_off, *st_idx;
+  const int64_t *sl_off;
+  const int8_t *rk;
+  const double *diag;
+  int64_t n;
+};
+
+// One wavefront per slice of 64 rows, 4 passes of 16 rows.  v_mfma_f32_16x16x16
+// bf16: lane l holds A[l%16][4(l/16)..+3], B[4(l/16)..+3][l%16] and
+// D[4(l/16)..+3][l%16].  Hidden activations go through LDS to turn the D layout
+// into the next A layout; the 16 x 48 outputs of a pass are written out from LDS
+// by all 64 lanes.
+__global__ void __launch_bounds__(64)
+    k_infer_bf16(const int32_t *__restrict__ rows_tab, int64_t nsl, const float *__restrict__ feat,
+                 const float *__restrict__ P, const uint16_t *__restrict__ W1,
+                 const uint16_t *__restrict__ W2, const uint16_t *__restrict__ W3, InferOut io) {
+  __shared__ float hs[16][HID + 1];
+  const int64_t s = blockIdx.x;
+  if (s >= nsl) return;
+  if (io.mode == 1 && io.sl_tmpl[s]) return; // uniform slices use the per-level rows
+  const int l = threadIdx.x, r16 = l & 15, kb = (l >> 4) * 4;
+  for (int sub = 0; sub < 4; sub++) {
+    const int32_t row = rows_tab[s * APC_SLICE + sub * 16 + r16];
+    // layer 1: A = features (16 x 48), B = W1 (48 x 64)
+    float4_t acc[4];
+    for (int nt = 0; nt < 4; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < K1 / 16; kk++) {
+      short4_t a;
+      for (int q = 0; q < 4; q++)
+        a[q] = row >= 0 ? bf16_bits(feat[(int64_t)row * IN + 16 * kk + kb + q]) : (short)0;
+      for (int nt = 0; nt < 4; nt++) {
+        short4_t b;
+        for (int q = 0; q < 4; q++) b[q] = bf16_raw(W1[(16 * kk + kb + q) * HID + 16 * nt + r16]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+      }
+    }
+    for (int nt = 0; nt < 4; nt++)
+      for (int q = 0; q < 4; q++)
+        hs[kb + q][16 * nt + r16] = fmaxf(acc[nt][q] + P[OB1 + 16 * nt + r16], 0.f);
+    __syncthreads();
+    // layer 2
+    for (int nt = 0; nt < 4; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < HID / 16; kk++) {
+      short4_t a;
+      for (int q = 0; q < 4; q++) a[q] = bf16_bits(hs[r16][16 * kk + kb + q]);
+      for (int nt = 0; nt < 4; nt++) {
+        short4_t b;
+        for (int q = 0; q < 4; q++) b[q] = bf16_raw(W2[(16 * kk + kb + q) * HID + 16 * nt + r16]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    for (int nt = 0; nt < 4; nt++)
+      for (int q = 0; q < 4; q++)
+        hs[kb + q][16 * nt + r16] = fmaxf(acc[nt][q] + P[OB2 + 16 * nt + r16], 0.f);
+    __syncthreads();
+    // layer 3: N = 48 (41 used)
+    for (int nt = 0; nt < N3 / 16; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+    for (int kk = 0; kk < HID / 16; kk++) {
+      short4_t a;
+      for (int q = 0; q < 4; q++) a[q] = bf16_bits(hs[r16][16 * kk + kb + q]);
+      for (int nt = 0; nt < N3 / 16; nt++) {
+        short4_t b;
+        for (int q = 0; q < 4; q++) b[q] = bf16_raw(W3[(16 * kk + kb + q) * N3 + 16 * nt + r16]);
+        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+      }
+    }
+    __syncthreads();
+    for (int nt = 0; nt < N3 / 16; nt++)
+      for (int q = 0; q < 4; q++) {
+        const int col = 16 * nt + r16;
+        hs[kb + q][col] = acc[nt][q] + (col < OUT ? P[OB3 + col] : 0.f);
+      }
+    __syncthreads();
+    for (int e = l; e < 16 * OUT; e += 64) {
+      const int q = e / OUT, p = e % OUT;
+      const int lane_row = sub * 16 + q;
+      const int32_t rr = rows_tab[s * APC_SLICE + lane_row];
+      if (rr < 0) continue;
+      const float o = hs[q][p];
+      if (io.mode == 0) {
+        io.o[(int64_t)rr * OUT + p] = o;
+        continue;
+      }
+      const double inv = 1.0 / io.diag[rr];
+      if (io.mode == 2) {
+        if (p < NT) io.m_tmpl[NT * (int)io.rk[rr] + p] = (float)(((p == 0 ? 1.0 : 0.0) + (double)o) * inv);
+        continue;
+      }
+      if (p == 0) {
+        io.m_diag[rr] = (float)((1.0 + (double)o) * inv);
+        continue;
+      }
+      const int len = io.sl_len[s];
+      if (p - 1 >= len) continue;
+      const int32_t a0 = io.st_off[rr];
+      const int m = io.st_off[rr + 1] - a0;
+      const bool live = p - 1 < m && io.st_idx[a0 + p - 1] < io.n;
+      io.m_sell[io.sl_off[s] + lane_row + (int64_t)(p - 1) * APC_SLICE] = live ? (float)((double)o * inv) : 0.f;
+    }
+    __syncthreads();
+  }
+}
+
+// smallest uniform 2-ring row of each level
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_rep_rows(const int8_t *__restrict__ rk, int64_t n, int32_t *__restrict__ rep) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n && rk[i] >= 0) atomicMin(&rep[rk[i]], (int32_t)i);
+}
+
+// rep (APC_MAX_LEVELS, INT_MAX = none) -> one slice of rows (-1 padded); template rows zeroed
+__global__ void k_rep_slice(const int32_t *__restrict__ rep, int32_t *__restrict__ tab,
+                            float *__restrict__ tmpl) {
+  const int t = threadIdx.x;
+  if (t < APC_SLICE) tab[t] = (t < APC_MAX_LEVELS && rep[t] != INT_MAX) ? rep[t] : -1;
+  for (int q = t; q < APC_MAX_LEVELS * NT; q += blockDim.x) tmpl[q] = 0.f;
+}
+
+__global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t < n) p[t] = v;
+}
+
+RowOp make_rowop(const apc_cloud *c) {
+  RowOp r;
+  r.st_off = c->st_off;
+  r.st_idx = c->st_idx;
+  r.w64 = c->w64;
+  r.w32 = c->w32;
+  r.rk = c->rkind;
+  r.diag = c->diag;
+  r.level = c->level;
+  for (int k = 0; k < 3; k++) r.tc[k] = c->tmpl[k];
+  r.L = c->P.L;
+  r.n = c->n;
+  r.max_depth = c->P.max_depth;
+  return r;
+}
+
+InferOut make_out(const apc_cloud *c, int mode) {
+  InferOut io;
+  io.mode = mode;
+  io.o = nullptr;
+  io.m_diag = c->m_diag;
+  io.m_sell = c->m_sell;
+  io.m_tmpl = c->m_tmpl;
+  io.sl_tmpl = c->sl_tmpl;
+  io.sl_len = c->sl_len;
+  io.st_off = c->st_off;
+  io.st_idx = c->st_idx;
+  io.sl_off = c->sl_off;
+  io.rk = c->rkind;
+  io.diag = c->diag;
+  io.n = c->n;
+  return io;
+}
+
+} // namespace
+
+int apc_learn_data_impl(apc_cloud *c, const double *Z, int K, float *feat, float *quad,
+                        hipStream_t s) {
+  if (!c->assembled) return APC_EINVAL;
+  const int64_t n = c->n, ntot = c->n + c->nb;
+  const RowOp r = make_rowop(c);
+  hipLaunchKernelGGL(k_features, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, r, feat);
+  HIPCHK(hipGetLastError());
+  if (!Z || K < 1 || n == 0) return APC_OK;
+  double *U = nullptr, *Zc = nullptr;
+  HIPCHK(hipMallocAsync((void **)&U, (size_t)K * ntot * sizeof(double), s));
+  HIPCHK(hipMallocAsync((void **)&Zc, (size_t)K * ntot * sizeof(double), s));
+  for (int k = 0; k < K; k++) {
+    double *zt = Zc + (int64_t)k * ntot;
+    hipLaunchKernelGGL(k_probe_copy, dim3(grid_for(ntot)), dim3(APC_BLOCK), 0, s,
+                       Z + (int64_t)k * ntot, n, ntot, zt);
+    APCCHK(apc_apply_impl(c, zt, U + (int64_t)k * ntot, s));
+  }
+  hipLaunchKernelGGL(k_learn_quad, dim3(grid_for(n * NQ)), dim3(APC_BLOCK), 0, s, r,
+                     (const double *)Zc, (const double *)U, K, ntot, quad);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipFreeAsync(U, s));
+  HIPCHK(hipFreeAsync(Zc, s));
+  return APC_OK;
+}
+
+int apc_mlp_loss_grad_impl(const float *P, const float *feat, const float *quad,
+                           const int32_t *rows, int B, float *loss, float *grad, hipStream_t s) {
+  if (B < 1) return APC_EINVAL;
+  float *H1 = nullptr, *H2 = nullptr, *O = nullptr, *dO = nullptr, *dH2 = nullptr, *dH1 = nullptr,
+        *lrow = nullptr, *part = nullptr;
+  const int nch = (B + CH - 1) / CH;
+  HIPCHK(hipMallocAsync((void **)&H1, (size_t)B * HID * 4, s));
+  HIPCHK(hipMallocAsync((void **)&H2, (size_t)B * HID * 4, s));
+  HIPCHK(hipMallocAsync((void **)&O, (size_t)B * OUT * 4, s));
+  HIPCHK(hipMallocAsync((void **)&dO, (size_t)B * OUT * 4, s));
+  HIPCHK(hipMallocAsync((void **)&dH2, (size_t)B * HID * 4, s));
+  HIPCHK(hipMallocAsync((void **)&dH1, (size_t)B * HID * 4, s));
+  HIPCHK(hipMallocAsync((void **)&lrow, (size_t)B * 4, s));
+  HIPCHK(hipMallocAsync((void **)&part, (size_t)nch * (HID + 1) * HID * 4, s));
+  auto g = [](int64_t t) { return dim3(grid_for(t)); };
+  hipLaunchKernelGGL(k_dense_fwd, g((int64_t)B * HID), dim3(APC_BLOCK), 0, s, feat, rows, B, IN, HID,
+                     P + OW1, P + OB1, 1, H1);
+  hipLaunchKernelGGL(k_dense_fwd, g((int64_t)B * HID), dim3(APC_BLOCK), 0, s, H1,
+                     (const int32_t *)nullptr, B, HID, HID, P + OW2, P + OB2, 1, H2);
+  hipLaunchKernelGGL(k_dense_fwd, g((int64_t)B * OUT), dim3(APC_BLOCK), 0, s, H2,
+                     (const int32_t *)nullptr, B, HID, OUT, P + OW3, P + OB3, 0, O);
+  hipLaunchKernelGGL(k_quad_loss, g(B), dim3(APC_BLOCK), 0, s, O, quad, rows, B, dO, lrow);
+  hipLaunchKernelGGL(k_mean, dim3(1), dim3(APC_BLOCK), 0, s, lrow, B, loss);
+  // layer 3
+  hipLaunchKernelGGL(k_dense_bwd_w, dim3(grid_for((HID + 1) * OUT), nch), dim3(APC_BLOCK), 0, s, H2,
+                     (const int32_t *)nullptr, B, HID, OUT, dO, part);
+  hipLaunchKernelGGL(k_sum_chunks, g((HID + 1) * OUT), dim3(APC_BLOCK), 0, s, part, nch, HID, OUT,
+                     grad + OW3, grad + OB3);
+  hipLaunchKernelGGL(k_dense_bwd_x, g((int64_t)B * HID), dim3(APC_BLOCK), 0, s, dO, P + OW3, H2, B,
+                     HID, OUT, dH2);
+  // layer 2
+  hipLaunchKernelGGL(k_dense_bwd_w, dim3(grid_for((HID + 1) * HID), nch), dim3(APC_BLOCK), 0, s, H1,
+                     (const int32_t *)nullptr, B, HID, HID, dH2, part);
+  hipLaunchKernelGGL(k_sum_chunks, g((HID + 1) * HID), dim3(APC_BLOCK), 0, s, part, nch, HID, HID,
+                     grad + OW2, grad + OB2);
+  hipLaunchKernelGGL(k_dense_bwd_x, g((int64_t)B * HID), dim3(APC_BLOCK), 0, s, dH2, P + OW2, H1, B,
+                     HID, HID, dH1);
+  // layer 1
+  hipLaunchKernelGGL(k_dense_bwd_w, dim3(grid_for((IN + 1) * HID), nch), dim3(APC_BLOCK), 0, s, feat,
+                     rows, B, IN, HID, dH1, part);
+  hipLaunchKernelGGL(k_sum_chunks, g((IN + 1) * HID), dim3(APC_BLOCK), 0, s, part, nch, IN, HID,
+                     grad + OW1, grad + OB1);
+  HIPCHK(hipGetLastError());
+  float *bufs[] = {H1, H2, O, dO, dH2, dH1, lrow, part};
+  for (float *b : bufs) HIPCHK(hipFreeAsync(b, s));
+  return APC_OK;
+}
+
+int apc_mlp_adam_impl(float *P, float *m, float *v, const float *g, int step, float lr,
+                      hipStream_t s) {
+  if (step < 1) return APC_EINVAL;
+  const float bc1 = 1.0f - powf(0.9f, (float)step), bc2 = 1.0f - powf(0.999f, (float)step);
+  hipLaunchKernelGGL(k_adam, dim3(grid_for(NPAR)), dim3(APC_BLOCK), 0, s, P, m, v, g, NPAR, lr, bc1,
+                     bc2);
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
+int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16, float *out,
+                       hipStream_t s) {
+  if (!bf16) {
+    hipLaunchKernelGGL(k_infer_f32, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, P, feat, c->n, out);
+    HIPCHK(hipGetLastError());
+    return APC_OK;
+  }
+  uint16_t *wb = nullptr;
+  HIPCHK(hipMallocAsync((void **)&wb, (size_t)NWB * 2, s));
+  hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(HID * HID)), dim3(APC_BLOCK), 0, s, P, wb,
+                     wb + K1 * HID, wb + K1 * HID + HID * HID);
+  InferOut io = make_out(c, 0);
+  io.o = out;
+  if (c->nsl > 0)
+    hipLaunchKernelGGL(k_infer_bf16, dim3((unsigned)c->nsl), dim3(64), 0, s, c->sl_rows, c->nsl,
+                       feat, P, wb, wb + K1 * HID, wb + K1 * HID + HID * HID, io);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipFreeAsync(wb, s));
+  return APC_OK;
+}
+
+int apc_set_learned_impl(apc_cloud *c, const float *P, hipStream_t s) {
+  if (!c->assembled) return APC_EINVAL;
+  const int64_t n = c->n;
+  if (!c->m_diag) HIPCHK(hipMalloc((void **)&c->m_diag, (size_t)(n > 0 ? n : 1) * sizeof(float)));
+  if (!c->m_sell)
+    HIPCHK(hipMalloc((void **)&c->m_sell, (size_t)(c->sl_entries > 0 ? c->sl_entries : 1) * sizeof(float)));
+  if (!c->m_tmpl) HIPCHK(hipMalloc((void **)&c->m_tmpl, (size_t)APC_MAX_LEVELS * NT * sizeof(float)));
+  float *feat = nullptr;
+  uint16_t *wb = nullptr;
+  int32_t *rep = nullptr;
+  HIPCHK(hipMallocAsync((void **)&feat, (size_t)(n > 0 ? n : 1) * IN * sizeof(float), s));
+  HIPCHK(hipMallocAsync((void **)&wb, (size_t)NWB * 2, s));
+  HIPCHK(hipMallocAsync((void **)&rep, (size_t)(APC_MAX_LEVELS + APC_SLICE) * sizeof(int32_t), s));
+  int32_t *tab = rep + APC_MAX_LEVELS;
+  hipLaunchKernelGGL(k_features, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, make_rowop(c), feat);
+  hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(HID * HID)), dim3(APC_BLOCK), 0, s, P, wb,
+                     wb + K1 * HID, wb + K1 * HID + HID * HID);
+  hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, rep, APC_MAX_LEVELS, INT_MAX);
+  hipLaunchKernelGGL(k_rep_rows, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, n, rep);
+  hipLaunchKernelGGL(k_rep_slice, dim3(1), dim3(APC_BLOCK), 0, s, (const int32_t *)rep, tab,
+                     c->m_tmpl);
+  const uint16_t *W1 = wb, *W2 = wb + K1 * HID, *W3 = wb + K1 * HID + HID * HID;
+  // general slices: per-row M; then the per-level rows of the uniform slices
+  if (c->nsl > 0)
+    hipLaunchKernelGGL(k_infer_bf16, dim3((unsigned)c->nsl), dim3(64), 0, s, c->sl_rows, c->nsl,
+                       (const float *)feat, P, W1, W2, W3, make_out(c, 1));
+  hipLaunchKernelGGL(k_infer_bf16, dim3(1), dim3(64), 0, s, (const int32_t *)tab, (int64_t)1,
+                     (const float *)feat, P, W1, W2, W3, make_out(c, 2));
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipFreeAsync(feat, s));
+  HIPCHK(hipFreeAsync(wb, s));
+  HIPCHK(hipFreeAsync(rep, s));
+  HIPCHK(hipStreamSynchronize(s));
+  c->learned = true;
+  return APC_OK;
+}

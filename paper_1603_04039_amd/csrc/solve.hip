@@ -311,6 +311,54 @@ __global__ void __launch_bounds__(APC_BLOCK)
   if (JAC) sh[i] = si * invd[i];
 }
 
+// out = M in for the learned preconditioner.  Row i of M has the operator's
+// pattern: m_ii in_i + sum_k m_ik in_{J_k}.  Uniform 2-ring slices read the
+// per-level row of M (25 floats: diagonal, then the 24 entries in slice order)
+// and no weights; general slices read their own weights, stored like the
+// operator's (entry-major; padding and boundary columns carry weight 0).
+struct MOp {
+  const float *diag, *sell, *tmpl;
+};
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_prec_apply(Op op, MOp M, const double *__restrict__ in, double *__restrict__ out,
+                 const Scal *sc) {
+  if (sc && sc->done) return;
+  const int lane = threadIdx.x & 63;
+  for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
+    const int s = __builtin_amdgcn_readfirstlane(it.s);
+    const int64_t off = op.sl_off[s] + lane;
+    const int32_t *__restrict__ ix = op.sl_idx + off;
+    if (op.sl_tmpl[s]) {
+      int32_t jj[24];
+#pragma unroll
+      for (int k = 0; k < 24; k++) jj[k] = ix[k * SL];
+      const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
+      if (row < 0) continue;
+      const float *__restrict__ T = M.tmpl + 25 * (int)op.rk[row];
+      double acc = (double)T[0] * in[row];
+#pragma unroll
+      for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * in[jj[k]];
+      out[row] = acc;
+    } else {
+      const int len = op.sl_len[s];
+      const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
+      if (row < 0) continue;
+      const float *__restrict__ wv = M.sell + off;
+      double acc = (double)M.diag[row] * in[row];
+#pragma unroll 8
+      for (int k = 0; k < len; k++) acc += (double)wv[k * SL] * in[ix[k * SL]];
+      out[row] = acc;
+    }
+  }
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_scale_copy(int64_t n, const double *__restrict__ in, const double *__restrict__ invd,
+                 double *__restrict__ out) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) out[i] = invd ? in[i] * invd[i] : in[i];
+}
+
 // x += alpha ph + omega sh; r = s - omega t; partials (rh, r), (r, r)
 __global__ void __launch_bounds__(APC_BLOCK)
     k_upd_xr(int64_t n, double *__restrict__ x, const double *__restrict__ ph,
@@ -548,17 +596,19 @@ static int launch_restart(apc_solver_ws *w, const Op &op, const double *b, const
 
 template <int MODE>
 static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const double *invd,
-                             bool jac, unsigned gs, hipStream_t s) {
+                             const MOp &mw, int prec, unsigned gs, hipStream_t s) {
   const int64_t n = w->n;
   const unsigned gv = grid_for(n), gr = vec_grid(n);
-  double *ph = jac ? w->ph : w->p;
-  double *sh = jac ? w->sh : w->s;
+  const bool jac = prec == APC_PRECOND_JACOBI, lrn = prec == APC_PRECOND_LEARNED;
+  double *ph = (jac || lrn) ? w->ph : w->p;
+  double *sh = (jac || lrn) ? w->sh : w->s;
   if (jac)
     hipLaunchKernelGGL(k_upd_p<true>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->p, w->v, ph,
                        invd, w->sc);
   else
     hipLaunchKernelGGL(k_upd_p<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->p, w->v, ph,
                        invd, w->sc);
+  if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), 0, s, op, mw, w->p, ph, w->sc);
   hipLaunchKernelGGL(k_spmv_v<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, ph, w->v, w->rh, w->part,
                      w->sc);
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
@@ -568,6 +618,7 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
   else
     hipLaunchKernelGGL(k_upd_s<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->v, w->s, sh,
                        invd, w->sc);
+  if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), 0, s, op, mw, w->s, sh, w->sc);
   hipLaunchKernelGGL(k_spmv_t<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, sh, w->s, w->t, w->part,
                      w->sc);
   hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
@@ -583,7 +634,7 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
 // true residuals this restart is the iterative refinement of the mixed mode.
 template <int MODE, int TMODE>
 static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, double tol, int maxit,
-                    bool jac, apc_stats *st, hipStream_t s) {
+                    int prec, apc_stats *st, hipStream_t s) {
   apc_solver_ws *w = c->ws;
   const int64_t n = w->n;
   const unsigned gs = spmv_grid(c);
@@ -596,7 +647,9 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
   APCCHK(launch_restart<TMODE>(w, op, b, x, 1, gs, s));
   int chunk = 8, nrest = 0, status = APC_ENOCONV;
   for (;;) {
-    for (int k = 0; k < chunk; k++) launch_iteration<MODE>(w, op, x, c->inv_diag, jac, gs, s);
+    for (int k = 0; k < chunk; k++)
+      launch_iteration<MODE>(w, op, x, c->inv_diag, MOp{c->m_diag, c->m_sell, c->m_tmpl}, prec,
+                             gs, s);
     HIPCHK(hipGetLastError());
     APCCHK(read_sc(w, s));
     Scal &h = *w->sc_host;
@@ -623,6 +676,7 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
     st->status = status;
     st->rel_resid = h.bnorm > 0.0 ? h.rnorm / h.bnorm : 0.0;
     st->rel_resid_true = h.rtrue;
+    st->precond_used = prec;
   }
   return status;
 }
@@ -632,14 +686,27 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
 // true residuals deciding convergence.  Mixed with FP32 accumulation: FP32 SpMV
 // arithmetic in the iteration, the FP64 true residual restarting it (iterative
 // refinement) until it meets tol.
-static int run_solve(apc_cloud *c, bool density, const double *b, double *x, double tol, int maxit,
-                     bool jac, apc_stats *st, hipStream_t s) {
-  const Op op = make_op(c, density);
+static int run_once(apc_cloud *c, const Op &op, const double *b, double *x, double tol, int maxit,
+                    int prec, apc_stats *st, hipStream_t s) {
   if (c->P.precision == APC_MIXED_F32ACC)
-    return bicgstab<V32A32, V32A64>(c, op, b, x, tol, maxit, jac, st, s);
+    return bicgstab<V32A32, V32A64>(c, op, b, x, tol, maxit, prec, st, s);
   if (c->P.precision == APC_MIXED)
-    return bicgstab<V32A64, V32A64>(c, op, b, x, tol, maxit, jac, st, s);
-  return bicgstab<V64, V64>(c, op, b, x, tol, maxit, jac, st, s);
+    return bicgstab<V32A64, V32A64>(c, op, b, x, tol, maxit, prec, st, s);
+  return bicgstab<V64, V64>(c, op, b, x, tol, maxit, prec, st, s);
+}
+
+// The learned preconditioner only changes the iteration; the true residual decides.
+// When the learned solve does not reach tol, the solve is repeated with Jacobi.
+static int run_solve(apc_cloud *c, bool density, const double *b, double *x, double tol, int maxit,
+                     int prec, apc_stats *st, hipStream_t s) {
+  const Op op = make_op(c, density);
+  int rc = run_once(c, op, b, x, tol, maxit, prec, st, s);
+  if (rc == APC_ENOCONV && prec == APC_PRECOND_LEARNED) {
+    const int it = st ? st->iters : 0;
+    rc = run_once(c, op, b, x, tol, maxit, APC_PRECOND_JACOBI, st, s);
+    if (st) st->iters += it;
+  }
+  return rc;
 }
 
 int apc_deposit_impl(apc_cloud *c, const double *q, double *rho_M, hipStream_t s) {
@@ -666,7 +733,7 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
     hipLaunchKernelGGL(k_rhs<V64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_M,
                        1.0, rho_M + c->n, w->b);
   HIPCHK(hipGetLastError());
-  int rc = run_solve(c, true, w->b, w->x, tol, maxit, false, st, s);
+  int rc = run_solve(c, true, w->b, w->x, tol, maxit, APC_PRECOND_NONE, st, s);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
                      w->x, rho_M + c->n, rho_t);
@@ -688,7 +755,10 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
 int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *phi, double tol,
                    int maxit, int precond, apc_stats *st, hipStream_t s) {
   if (!c->assembled) return APC_EINVAL;
-  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI) return APC_EINVAL;
+  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI &&
+      precond != APC_PRECOND_LEARNED)
+    return APC_EINVAL;
+  if (precond == APC_PRECOND_LEARNED && !c->learned) return APC_EINVAL;
   APCCHK(ensure_ws(c));
   apc_solver_ws *w = c->ws;
   const Op op = make_op(c, false);
@@ -700,7 +770,7 @@ int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *p
     hipLaunchKernelGGL(k_rhs<V64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_t,
                        c->P.poisson_c, g, w->b);
   HIPCHK(hipGetLastError());
-  int rc = run_solve(c, false, w->b, w->x, tol, maxit, precond == APC_PRECOND_JACOBI, st, s);
+  int rc = run_solve(c, false, w->b, w->x, tol, maxit, precond, st, s);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
                      w->x, g, phi);
@@ -727,6 +797,24 @@ int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s) {
     hipLaunchKernelGGL(k_apply<V32A64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, op, f, out);
   else
     hipLaunchKernelGGL(k_apply<V64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, op, f, out);
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
+int apc_apply_precond_impl(apc_cloud *c, int precond, const double *in, double *out,
+                           hipStream_t s) {
+  if (!c->assembled) return APC_EINVAL;
+  if (precond == APC_PRECOND_LEARNED) {
+    if (!c->learned) return APC_EINVAL;
+    if (c->nsl > 0)
+      hipLaunchKernelGGL(k_prec_apply, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, make_op(c, false),
+                         MOp{c->m_diag, c->m_sell, c->m_tmpl}, in, out, (const Scal *)nullptr);
+  } else if (precond == APC_PRECOND_JACOBI || precond == APC_PRECOND_NONE) {
+    hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, in,
+                       precond == APC_PRECOND_JACOBI ? (const double *)c->inv_diag : nullptr, out);
+  } else {
+    return APC_EINVAL;
+  }
   HIPCHK(hipGetLastError());
   return APC_OK;
 }

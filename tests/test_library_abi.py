@@ -46,7 +46,7 @@ def test_error_strings_and_defaults(apc):
 def test_struct_layouts_match_header(apc):
     # apc_params: lo[3], L, order, c, max_depth, ring_min, ring_max, m_cap, poisson_c, precision
     assert ct.sizeof(apc.Params) == 3 * 8 + 8 + 8 + 8 + 4 * 4 + 8 + 8
-    assert ct.sizeof(apc.Stats) == 4 * 4 + 8 + 8 + 8 + 8
+    assert ct.sizeof(apc.Stats) == 4 * 4 + 8 + 8 + 8 + 8 + 4 + 4
 
 
 def test_binding_fails_loudly_without_library(apc, tmp_path):
