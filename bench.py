@@ -2,11 +2,15 @@
 """Benchmark of the AP-Cloud field-solve hot path on one MI355X.
 
 A step is one pass of the whole path over the synthetic beam-with-halo cloud:
-build_cloud -> assemble_gfd -> deposit (NGP + density solve) -> solve (Poisson,
-BiCGSTAB to relative residual 1e-8) -> interpolate_force.  The reported value is
-nodes / (assembly time + Poisson solve time), from HIP events on the stream the
-library runs on, averaged over the timed steps.  Inputs are resident in HBM
-before the timed region starts.
+build_cloud -> assemble_gfd (+ install of the learned preconditioner) -> deposit
+(NGP + density solve) -> solve (Poisson, BiCGSTAB to relative residual 1e-8) ->
+interpolate_force.  The reported value is nodes / (assembly + preconditioner
+install + Poisson solve time), from HIP events on the stream the library runs
+on, averaged over the timed steps.  Inputs are resident in HBM before the timed
+region starts.  The learned preconditioner's parameters come from
+paper_1603_04039_amd/learned_params.npy (written by `python -m
+paper_1603_04039_amd.learned`); without that file they are trained here, on the
+GPU, before the timed region.
 
 Prints one JSON line.  `--gpus N` with N > 1 is not supported (single-GPU build).
 """
@@ -29,10 +33,12 @@ def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol):
+def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="jacobi",
+              params=None):
     """Run warmup + timed steps; returns per-phase mean ms and the last cloud."""
     stream = torch.cuda.current_stream()
-    names = ["build", "assemble", "deposit", "solve", "interpolate"]
+    names = ["build", "assemble", "install", "deposit", "solve", "interpolate"]
+    pc = apc.APC_PRECOND_LEARNED if precond == "learned" else apc.APC_PRECOND_JACOBI
     acc = {k: 0.0 for k in names}
     info = {}
     t_wall = 0.0
@@ -42,22 +48,27 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol):
         if timed and it == warmup:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
-        ev = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
         ev[0].record(stream)
         cloud = apc.Cloud(xyz_d, **kw)
         ev[1].record(stream)
         cloud.assemble_gfd()
         ev[2].record(stream)
-        rho_M, rho_t, std = cloud.deposit(tol=1e-10, maxit=2000)
+        if pc == apc.APC_PRECOND_LEARNED:
+            from paper_1603_04039_amd import learned
+            cloud.set_learned_precond(params, learned.probes(cloud, seed=it))
         ev[3].record(stream)
-        phi, st = cloud.solve(rho_t[:cloud.n], tol=tol, maxit=20000,
-                              precond=apc.APC_PRECOND_JACOBI)
+        rho_M, rho_t, std = cloud.deposit(tol=1e-10, maxit=2000)
         ev[4].record(stream)
-        phi_p, grad_p = cloud.interpolate_force(phi)
+        phi, st = cloud.solve(rho_t[:cloud.n], tol=tol, maxit=20000, precond=pc)
         ev[5].record(stream)
-        ev[5].synchronize()
+        phi_p, grad_p = cloud.interpolate_force(phi)
+        ev[6].record(stream)
+        ev[6].synchronize()
         if st["status"] != 0:
             raise RuntimeError(f"solve did not converge: {st}")
+        if st["precond_used"] != pc:
+            raise RuntimeError(f"learned preconditioner fell back to Jacobi: {st}")
         if timed:
             for k, name in enumerate(names):
                 acc[name] += ev[k].elapsed_time(ev[k + 1])
@@ -71,6 +82,35 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol):
     t_wall = time.perf_counter() - t0
     ms = {k: v / steps for k, v in acc.items()}
     return ms, info, t_wall * 1000.0 / steps, last, phi
+
+
+def precond_roofline(torch, cloud, reps):
+    """Average duration of the learned M apply (k_prec_apply), same method."""
+    stream = torch.cuda.current_stream()
+    f = torch.rand(cloud.n + cloud.nb, dtype=torch.float64, device="cuda")
+    from paper_1603_04039_amd import apcloud as apc
+    for _ in range(5):
+        cloud.apply_precond(f, apc.APC_PRECOND_LEARNED)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        cloud.apply_precond(f, apc.APC_PRECOND_LEARNED)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    oi = cloud.operator_info()
+    n_gen = cloud.n - oi["n_uniform"]
+    # uniform rows: 24 indices + level byte (per-level M rows stay in cache);
+    # general rows: index + FP32 weight per entry and an FP32 diagonal; every
+    # row: row id, in_i, out_i
+    byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["nnz_general"] * 8 + n_gen * 4
+            + cloud.n * (4 + 8 + 8))
+    gbs = byts / (ms * 1e-3) / 1e9
+    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                kernel="k_prec_apply (learned M, sliced layout)", avg_us=round(ms * 1e3, 2),
+                bytes_per_launch=int(byts))
 
 
 def spmv_roofline(torch, cloud, reps, mixed):
@@ -136,6 +176,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="beam_halo_1e7")
     ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed_f32acc"])
+    ap.add_argument("--precond", default="jacobi", choices=["learned", "jacobi"])
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -162,34 +203,60 @@ def main():
 
     PREC = {"fp64": apc.APC_FP64, "mixed": apc.APC_MIXED, "mixed_f32acc": apc.APC_MIXED_F32ACC}
     prec = PREC[args.precision]
-    log(f"timed steps ({args.precision}): warmup={args.warmup} steps={args.steps}")
+    params = None
+    params_src = None
+    if args.precond == "learned" or not args.no_plain:
+        from paper_1603_04039_amd import learned
+        if os.path.exists(learned.PARAMS_PATH):
+            params = torch.from_numpy(np.load(learned.PARAMS_PATH)).cuda()
+            params_src = "learned_params.npy"
+        else:
+            log("training the learned preconditioner (no learned_params.npy)")
+            feat, quad = learned.training_data()
+            params, _ = learned.train(feat, quad, steps=3000, batch=4096, lr=2e-3)
+            del feat, quad
+            params_src = "trained in this run (200 clouds, 3000 Adam steps)"
+        assert params.numel() == apc.MLP_NPARAM
+    log(f"timed steps ({args.precision}, {args.precond}): warmup={args.warmup} steps={args.steps}")
     ms, info, ms_step, cloud, phi = run_steps(apc, torch, xyz_d, cfg, prec, args.steps,
-                                              args.warmup, args.tol)
-    t_metric = (ms["assemble"] + ms["solve"]) * 1e-3
+                                              args.warmup, args.tol, args.precond, params)
+    t_metric = (ms["assemble"] + ms["install"] + ms["solve"]) * 1e-3
     value = info["n"] / t_metric
-    log(f"{args.precision}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
+    log(f"{args.precision}/{args.precond}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
     roof = spmv_roofline(torch, cloud, args.spmv_reps, prec != apc.APC_FP64)
     log(f"spmv roofline: {roof}")
+    roof_m = None
+    if args.precond == "learned":
+        roof_m = precond_roofline(torch, cloud, args.spmv_reps)
+        log(f"precond roofline: {roof_m}")
     cloud.close()
 
     plain = None
+    jac = None
     variants = {}
     iters_fp64 = info["iters"]
-    if prec != apc.APC_FP64 and not args.no_plain:
-        for name in ("fp64", "mixed_f32acc"):
-            if PREC[name] == prec:
+    if not args.no_plain:
+        todo = [("fp64", "jacobi"), ("mixed", "jacobi"), ("mixed", "learned"),
+                ("mixed_f32acc", "jacobi")]
+        for name, pcn in todo:
+            if (PREC[name], pcn) == (prec, args.precond):
                 continue
-            log(f"comparison variant {name}")
+            log(f"comparison variant {name}/{pcn}")
             msv, infov, _, cv, _ = run_steps(apc, torch, xyz_d, cfg, PREC[name],
-                                             max(2, args.steps // 2), 1, args.tol)
+                                             max(2, args.steps // 2), 1, args.tol, pcn, params)
             cv.close()
-            vv = infov["n"] / ((msv["assemble"] + msv["solve"]) * 1e-3)
-            variants[name] = dict(nodes_per_s=round(vv, 1), iters=infov["iters"],
-                                  sweeps=infov["sweeps"], assemble_ms=round(msv["assemble"], 3),
-                                  solve_ms=round(msv["solve"], 3))
-            if name == "fp64":
-                plain = variants[name]
+            vv = infov["n"] / ((msv["assemble"] + msv["install"] + msv["solve"]) * 1e-3)
+            key = f"{name}_{pcn}"
+            variants[key] = dict(nodes_per_s=round(vv, 1), iters=infov["iters"],
+                                 sweeps=infov["sweeps"], assemble_ms=round(msv["assemble"], 3),
+                                 solve_ms=round(msv["solve"], 3))
+            if key == "fp64_jacobi":
+                plain = variants[key]
                 iters_fp64 = infov["iters"]
+            if key == f"{args.precision}_jacobi":
+                jac = variants[key]
+            if pcn == "learned":
+                variants[key]["install_ms"] = round(msv["install"], 3)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -212,7 +279,7 @@ def main():
         "config": {"workload": args.workload, "particles": cfg["N"], "nodes": info["n"],
                    "boundary_nodes": info["nb"], "nnz": info["nnz"],
                    "max_depth": cfg["max_depth"], "order": cfg["order"], "c": cfg["c"],
-                   "precision": args.precision, "tol": args.tol, "precond": "jacobi"},
+                   "precision": args.precision, "tol": args.tol, "precond": args.precond},
         "phases_ms": {k: round(v, 3) for k, v in ms.items()},
         "solve": {"iters": info["iters"], "sweeps": info["sweeps"],
                   "rel_resid_true": info["rel_resid_true"],
@@ -220,10 +287,18 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if roof_m is not None:
+        out["roofline_precond"] = roof_m
+        out["learned_params"] = params_src
     if variants:
         out["variants"] = variants
     if plain is not None:
-        out["speedup_mixed_vs_plain"] = round(value / plain["nodes_per_s"], 3)
+        out["speedup_vs_plain_fp64_jacobi"] = round(value / plain["nodes_per_s"], 3)
+    if jac is not None:
+        out["speedup_learned_vs_jacobi"] = round(value / jac["nodes_per_s"], 3)
+    lv = variants.get(f"{args.precision}_learned")
+    if lv is not None and args.precond == "jacobi":
+        out["speedup_learned_vs_jacobi"] = round(lv["nodes_per_s"] / value, 3)
     print(json.dumps(out), flush=True)
 
 

@@ -202,8 +202,9 @@ int apc_apply_operator(apc_cloud *c, const double *f, double *out, hipStream_t s
    n x APC_LEARN_QUAD float32 (Q packed lower row-major, then b, then c).
    Features: the row's Poisson weights divided by |d_i| in stencil order (40
    slots, zero padded); level(J_p) - level(i) of the first 6 stencil nodes (0 for
-   boundary nodes); level(i) / max_depth; the fraction of boundary nodes in the
-   stencil.  Z may be NULL (K ignored, quad untouched): features only.  Requires
+   boundary nodes); m / 40; the fraction of boundary nodes in the stencil.  All
+   are scale-free, so clouds of any depth share one network.  Z may be NULL (K
+   ignored, quad untouched): features only.  Requires
    apc_assemble_gfd.  Does not synchronise. */
 int apc_learn_data(apc_cloud *c, const double *Z, int K, float *feat, float *quad,
                    hipStream_t stream);
@@ -232,9 +233,16 @@ int apc_mlp_infer(apc_cloud *c, const float *params, const float *feat, int bf16
    inference with FP32 accumulation, then M stored in the solver's sliced layout
    (FP32).  Rows whose stencil is the uniform same-level 2-ring have identical
    features at a given level; M keeps one row per level for them (the network's
-   output for the first such row of that level).  Requires apc_assemble_gfd (and
-   again after every re-assembly, which drops M).  Synchronises. */
-int apc_set_learned_precond(apc_cloud *c, const float *params, hipStream_t stream);
+   output for the first such row of that level).
+   Safeguard (Z != NULL): K probe vectors Z (K x (n+nb) float64, boundary
+   entries ignored).  Every other row becomes m_i = j_i + alpha_i (m_i - j_i),
+   j_i the Jacobi row, with alpha_i in [0, 1] minimising the probe estimate
+   sum_k ((j_i + alpha (m_i - j_i))^T A z_k - z_ki)^2 (alpha_i = 1 when the two
+   rows agree), so that rows the network does not know fall back towards
+   Jacobi.  Z = NULL: alpha = 1 everywhere.  Requires apc_assemble_gfd (and again
+   after every re-assembly, which drops M).  Synchronises. */
+int apc_set_learned_precond(apc_cloud *c, const float *params, const double *Z, int K,
+                            hipStream_t stream);
 
 /* Apply a preconditioner: out = M in over the interior rows.  precond
    APC_PRECOND_NONE: out = in; APC_PRECOND_JACOBI: out_i = in_i / d_i;

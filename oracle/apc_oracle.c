@@ -1253,7 +1253,7 @@ int apco_learn_data(const apco_cloud *C, const double *Z, int K, double *feat, d
     }
     int nbnd = 0;
     for (int j = 0; j < m; j++) nbnd += C->st[a + j] >= n;
-    f[46] = (double)li / (double)C->P.max_depth;
+    f[46] = (double)m / (double)LNW;
     f[47] = (double)nbnd / (double)m;
     if (!U) continue;
     /* pattern of row i of M: J_0 = i, J_p = the p-th stencil node (p <= min(m, 40)) */
@@ -1373,5 +1373,83 @@ int apco_mlp_forward(const double *P, const double *feat, int64_t nrow, double *
       out[r * LOUT + j] = s;
     }
   }
+  return 0;
+}
+
+/* Rows of M: the network output on every row (m_i = (e_0 + o_i) / d_i on the
+   operator's pattern, boundary columns 0), then, with probes, the safeguard
+   m_i <- j_i + alpha_i (m_i - j_i) on every row that is not a uniform 2-ring
+   row (24 stencil nodes at offsets, in cells of the row's level, with
+   components in {0, 1, 2} and L1 norm <= 2). */
+int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, int K,
+                   double *mdiag, double *mw) {
+  int64_t n = C->n, ntot = C->n + C->nb, nnz = C->st_off[n];
+  double *w = malloc((size_t)(nnz + 1) * sizeof(double));
+  double *d = malloc((size_t)(n + 1) * sizeof(double));
+  double *feat = malloc((size_t)(n + 1) * LIN * sizeof(double));
+  double *o = malloc((size_t)(n + 1) * LOUT * sizeof(double));
+  int32_t *ixyz = malloc((size_t)(3 * ntot + 1) * sizeof(int32_t));
+  double *U = (Z && K > 0) ? malloc((size_t)K * n * sizeof(double)) : NULL;
+  int rc = (!w || !d || !feat || !o || !ixyz || (Z && K > 0 && !U)) ? APCO_ENOMEM : 0;
+  if (!rc) rc = apco_assemble(C, w, d);
+  if (!rc) rc = apco_learn_data(C, NULL, 0, feat, NULL);
+  if (!rc) rc = apco_mlp_forward(params, feat, n, o);
+  if (!rc) rc = apco_node_coords(C, ixyz);
+  if (rc) {
+    free(w); free(d); free(feat); free(o); free(ixyz); free(U);
+    return rc;
+  }
+  for (int64_t i = 0; i < n; i++) {
+    int32_t a = C->st_off[i];
+    int m = C->st_off[i + 1] - a;
+    mdiag[i] = (1.0 + o[i * LOUT]) / d[i];
+    for (int p = 1; p <= m; p++) {
+      int32_t v = C->st[a + p - 1];
+      mw[a + p - 1] = (v < n && p < LOUT) ? o[i * LOUT + p] / d[i] : 0.0;
+    }
+  }
+  for (int k = 0; U && k < K; k++) {
+    const double *z = Z + (int64_t)k * ntot;
+    for (int64_t i = 0; i < n; i++) {
+      double s = d[i] * z[i];
+      for (int32_t e = C->st_off[i]; e < C->st_off[i + 1]; e++)
+        if (C->st[e] < n) s += w[e] * z[C->st[e]];
+      U[(int64_t)k * n + i] = s;
+    }
+  }
+  for (int64_t i = 0; U && i < n; i++) {
+    int32_t a = C->st_off[i];
+    int m = C->st_off[i + 1] - a;
+    int uniform = m == 24;
+    int lv = C->cells[C->node_cell[i]].level;
+    int32_t sp = 1 << (C->P.max_depth - lv + 1);
+    for (int j = 0; j < m && uniform; j++) {
+      int32_t v = C->st[a + j], l1 = 0;
+      for (int c = 0; c < 3; c++) {
+        int32_t dd = abs(ixyz[c * ntot + v] - ixyz[c * ntot + i]);
+        uniform = uniform && (dd == 0 || dd == sp || dd == 2 * sp);
+        l1 += dd;
+      }
+      uniform = uniform && l1 <= 2 * sp;
+    }
+    if (uniform) continue;
+    double jd = 1.0 / d[i], st = 0.0, tt = 0.0;
+    for (int k = 0; k < K; k++) {
+      const double *Uk = U + (int64_t)k * n;
+      double sk = Uk[i] * jd - Z[(int64_t)k * ntot + i];
+      double tk = (mdiag[i] - jd) * Uk[i];
+      for (int p = 1; p <= m; p++) {
+        int32_t v = C->st[a + p - 1];
+        if (v < n) tk += mw[a + p - 1] * Uk[v];
+      }
+      st += sk * tk;
+      tt += tk * tk;
+    }
+    double al = tt > 0.0 ? -st / tt : 1.0;
+    al = al < 0.0 ? 0.0 : (al > 1.0 ? 1.0 : al);
+    mdiag[i] = jd + al * (mdiag[i] - jd);
+    for (int p = 1; p <= m; p++) mw[a + p - 1] *= al;
+  }
+  free(w); free(d); free(feat); free(o); free(ixyz); free(U);
   return 0;
 }

@@ -116,7 +116,7 @@ int apco_interpolate(const apco_cloud *C, const double *phi, const double *xyz, 
    m <= 40) and is m_i = (e_0 + o_i) / d_i with o_i (41) the network output.
    Row features (n x 48): Poisson weights / |d_i| in stencil order (40 slots, zero
    padded); level(J_p) - level(i) of the first 6 stencil nodes (0 for boundary
-   nodes); level(i) / max_depth; the fraction of boundary nodes in the stencil.
+   nodes); m / 40; the fraction of boundary nodes in the stencil.
    Quadratic data (n x 903) from K probes Z (K x (n+nb), boundary entries
    ignored): with U = A Z over the interior unknowns and u_p = U[J_p] / d_i (0 for
    boundary or absent J_p): Q = u u^T / K (packed lower, 861), b = u z_i / K (41),
@@ -129,6 +129,15 @@ int apco_mlp_loss_grad(const double *params, const double *feat, const double *q
                        const int32_t *rows, int B, double *loss, double *grad);
 /* Network output o (nrow x 41) of every feature row (nrow x 48), same layout. */
 int apco_mlp_forward(const double *params, const double *feat, int64_t nrow, double *out);
+/* Rows of the learned M: diagonal mdiag (n) and off-diagonal weights mw aligned
+   with the stencil CSR (boundary columns 0), m_i = (e_0 + o_i) / d_i.  With K
+   probes Z (K x (n+nb), boundary entries ignored), every row that is not a
+   uniform 2-ring row (24 stencil nodes at offsets, in cells of the row's level,
+   with components in {0, 1, 2} and L1 norm <= 2) becomes j_i + alpha (m_i - j_i),
+   j_i the Jacobi row, alpha in [0, 1] minimising sum_k ((.)^T A z_k - z_ki)^2
+   (alpha = 1 when t = 0). */
+int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, int K,
+                   double *mdiag, double *mw);
 
 #ifdef __cplusplus
 }

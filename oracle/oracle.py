@@ -69,6 +69,7 @@ def _load():
     lib.apco_learn_data.argtypes = [P, P, ct.c_int, P, P]
     lib.apco_mlp_loss_grad.argtypes = [P, P, P, P, ct.c_int, P, P]
     lib.apco_mlp_forward.argtypes = [P, P, ct.c_int64, P]
+    lib.apco_learned_m.argtypes = [P, P, P, ct.c_int, P, P]
     _lib = lib
     return lib
 
@@ -287,6 +288,21 @@ class OracleCloud:
         _check(self.lib.apco_learn_data(self.h, _ptr(Z), Z.shape[0], _ptr(feat), _ptr(quad)),
                "learn_data")
         return feat, quad
+
+    def learned_m(self, params, Z=None):
+        """Rows of the learned M: diagonal (n) and weights aligned with the stencil."""
+        P = np.ascontiguousarray(params, dtype=np.float64)
+        assert P.size == MLP_NPARAM
+        md = np.zeros(self.n)
+        mw = np.zeros(self.nnz)
+        if Z is None:
+            _check(self.lib.apco_learned_m(self.h, _ptr(P), None, 0, _ptr(md), _ptr(mw)),
+                   "learned_m")
+        else:
+            Z = np.ascontiguousarray(Z, dtype=np.float64)
+            _check(self.lib.apco_learned_m(self.h, _ptr(P), _ptr(Z), Z.shape[0], _ptr(md),
+                                           _ptr(mw)), "learned_m")
+        return md, mw
 
     def interpolate(self, phi, xyz=None):
         phi = np.ascontiguousarray(phi, dtype=np.float64)

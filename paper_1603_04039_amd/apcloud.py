@@ -86,7 +86,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_mlp_loss_grad.argtypes = [P, P, P, P, ct.c_int, P, P, P]
     lib.apc_mlp_adam.argtypes = [P, P, P, P, ct.c_int, ct.c_float, P]
     lib.apc_mlp_infer.argtypes = [P, P, P, ct.c_int, P, P]
-    lib.apc_set_learned_precond.argtypes = [P, P, P]
+    lib.apc_set_learned_precond.argtypes = [P, P, P, ct.c_int, P]
     lib.apc_apply_precond.argtypes = [P, ct.c_int, P, P, P]
     lib.apc_destroy.argtypes = [P]
     lib.apc_destroy.restype = None
@@ -293,10 +293,17 @@ class Cloud:
                                       _dptr(out), _stream(stream)), "apc_mlp_infer")
         return out
 
-    def set_learned_precond(self, params, stream=None):
+    def set_learned_precond(self, params, Z=None, stream=None):
+        """Install M from the network parameters; Z (K x (n+nb) float64 probes)
+        enables the per-row safeguard towards Jacobi."""
         import torch
+        K = 0
+        if Z is not None:
+            assert Z.dim() == 2 and Z.shape[1] == self.n + self.nb
+            K = Z.shape[0]
         _check(self.lib.apc_set_learned_precond(self.h, _dptr(params, torch.float32, MLP_NPARAM),
-                                                _stream(stream)), "apc_set_learned_precond")
+                                                _dptr(Z, torch.float64), K, _stream(stream)),
+               "apc_set_learned_precond")
 
     def apply_precond(self, f, precond=APC_PRECOND_LEARNED, stream=None):
         """out = M f over the interior rows (f: n+nb)."""

@@ -166,7 +166,7 @@ int apc_mlp_adam_impl(float *P, float *m, float *v, const float *g, int step, fl
                       hipStream_t s);
 int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16, float *out,
                        hipStream_t s);
-int apc_set_learned_impl(apc_cloud *c, const float *P, hipStream_t s);
+int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, hipStream_t s);
 int apc_apply_precond_impl(apc_cloud *c, int precond, const double *in, double *out,
                            hipStream_t s);
 int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s);

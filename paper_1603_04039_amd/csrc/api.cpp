@@ -228,11 +228,12 @@ int apc_mlp_infer(apc_cloud *c, const float *params, const float *feat, int bf16
   return apc_mlp_infer_impl(c, params, feat, bf16, out, stream);
 }
 
-int apc_set_learned_precond(apc_cloud *c, const float *params, hipStream_t stream) {
-  if (!c || !params) return APC_EINVAL;
+int apc_set_learned_precond(apc_cloud *c, const float *params, const double *Z, int K,
+                            hipStream_t stream) {
+  if (!c || !params || (Z && K < 1)) return APC_EINVAL;
   DeviceGuard g(c->device);
   if (!g.ok) return APC_EHIP;
-  return apc_set_learned_impl(c, params, stream);
+  return apc_set_learned_impl(c, params, Z, Z ? K : 0, stream);
 }
 
 int apc_apply_precond(apc_cloud *c, int precond, const double *in, double *out,

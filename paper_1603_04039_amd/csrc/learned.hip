@@ -64,7 +64,7 @@ __device__ inline void row_features(const RowOp &r, int64_t i, float *f) {
   }
   int nb = 0;
   for (int j = 0; j < m; j++) nb += r.st_idx[a + j] >= r.n ? 1 : 0;
-  f[46] = (float)((double)li / (double)r.max_depth);
+  f[46] = (float)((double)m / (double)NW);
   f[47] = (float)((double)nb / (double)m);
 }
 
@@ -275,135 +275,266 @@ __device__ __forceinline__ uint16_t bf16_of(float x) {
   return (uint16_t)(u >> 16);
 }
 
-// BF16 copies of the weights, zero-padded to multiples of 16 (N of layer 3: 48)
+// BF16 copies of the weights, transposed ([column][k]) so that the 4 consecutive
+// k of an MFMA B operand are one 8-byte LDS read; layer 3 zero-padded to 48 columns
 constexpr int K1 = 48, N3 = 48;
 static_assert(OUT <= N3 && IN == K1, "tile padding");
-constexpr int NWB = K1 * HID + HID * HID + HID * N3;
-__global__ void k_pack_bf16(const float *__restrict__ P, uint16_t *__restrict__ W1,
-                            uint16_t *__restrict__ W2, uint16_t *__restrict__ W3) {
+constexpr int NWB = HID * K1 + HID * HID + N3 * HID;
+__global__ void k_pack_bf16(const float *__restrict__ P, uint16_t *__restrict__ W1t,
+                            uint16_t *__restrict__ W2t, uint16_t *__restrict__ W3t) {
   const int t = blockIdx.x * APC_BLOCK + threadIdx.x;
-  if (t < K1 * HID) W1[t] = bf16_of(P[OW1 + t]);
-  if (t < HID * HID) W2[t] = bf16_of(P[OW2 + t]);
-  if (t < HID * N3) {
-    const int i = t / N3, j = t % N3;
-    W3[t] = bf16_of(j < OUT ? P[OW3 + i * OUT + j] : 0.0f);
+  if (t < HID * K1) {
+    const int col = t / K1, k = t % K1;
+    W1t[t] = bf16_of(P[OW1 + k * HID + col]);
+  }
+  if (t < HID * HID) {
+    const int col = t / HID, k = t % HID;
+    W2t[t] = bf16_of(P[OW2 + k * HID + col]);
+  }
+  if (t < N3 * HID) {
+    const int col = t / HID, k = t % HID;
+    W3t[t] = bf16_of(col < OUT ? P[OW3 + k * OUT + col] : 0.0f);
   }
 }
 
 typedef short short4_t __attribute__((ext_vector_type(4)));
 typedef float float4_t __attribute__((ext_vector_type(4)));
 
-__device__ __forceinline__ short bf16_bits(float x) { return (short)bf16_of(x); }
-__device__ __forceinline__ short bf16_raw(uint16_t h) { return (short)h; }
-
-// where the BF16 inference writes
+// where the BF16 inference reads its rows and writes its results
 struct InferOut {
   int mode;             // 0: o per row; 1: M of general slices; 2: per-level rows of M
   float *o;             // mode 0: n x OUT
   float *m_diag;        // mode 1
   float *m_sell;        // mode 1 (operator's sliced layout)
   float *m_tmpl;        // mode 2: APC_MAX_LEVELS x NT
-  const int32_t *sl_tmpl, *sl_len, *st_off, *st_idx;
+};
+struct InferIn {
+  RowOp r;
+  const float *feat;          // given features (n x IN) or nullptr: computed here
+  const int32_t *rows_tab;    // mode 2: 64 rows (-1 padded) forming one pseudo-slice
+  const int32_t *sl_rows, *sl_tmpl, *sl_len, *sl_idx;
   const int64_t *sl_off;
-  const int8_t *rk;
-  const double *diag;
-  int64_t n;
+  const float *sl_w32;
+  const double *sl_w64;
+  int64_t nsl;
 };
 
-// One wavefront per slice of 64 rows, 4 passes of 16 rows.  v_mfma_f32_16x16x16
-// bf16: lane l holds A[l%16][4(l/16)..+3], B[4(l/16)..+3][l%16] and
-// D[4(l/16)..+3][l%16].  Hidden activations go through LDS to turn the D layout
-// into the next A layout; the 16 x 48 outputs of a pass are written out from LDS
-// by all 64 lanes.
-__global__ void __launch_bounds__(64)
-    k_infer_bf16(const int32_t *__restrict__ rows_tab, int64_t nsl, const float *__restrict__ feat,
-                 const float *__restrict__ P, const uint16_t *__restrict__ W1,
-                 const uint16_t *__restrict__ W2, const uint16_t *__restrict__ W3, InferOut io) {
-  __shared__ float hs[16][HID + 1];
-  const int64_t s = blockIdx.x;
-  if (s >= nsl) return;
-  if (io.mode == 1 && io.sl_tmpl[s]) return; // uniform slices use the per-level rows
-  const int l = threadIdx.x, r16 = l & 15, kb = (l >> 4) * 4;
-  for (int sub = 0; sub < 4; sub++) {
-    const int32_t row = rows_tab[s * APC_SLICE + sub * 16 + r16];
-    // layer 1: A = features (16 x 48), B = W1 (48 x 64)
-    float4_t acc[4];
-    for (int nt = 0; nt < 4; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
-    for (int kk = 0; kk < K1 / 16; kk++) {
-      short4_t a;
-      for (int q = 0; q < 4; q++)
-        a[q] = row >= 0 ? bf16_bits(feat[(int64_t)row * IN + 16 * kk + kb + q]) : (short)0;
-      for (int nt = 0; nt < 4; nt++) {
-        short4_t b;
-        for (int q = 0; q < 4; q++) b[q] = bf16_raw(W1[(16 * kk + kb + q) * HID + 16 * nt + r16]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+// Features of the lane's row (the same values k_features writes), from the
+// sliced layout: entry k of the 64 rows of a slice is one contiguous load.
+__device__ inline void slice_features(const InferIn &in, int64_t s, bool tmpl, int lane, int32_t row,
+                                      float *f) {
+  if (row < 0) {
+    for (int j = 0; j < IN; j++) f[j] = 0.0f;
+    return;
+  }
+  const RowOp &r = in.r;
+  const double inv = 1.0 / fabs(r.diag[row]);
+  if (tmpl) { // uniform 2-ring row: 24 same-level interior neighbours
+    for (int j = 0; j < NW; j++) f[j] = j < 24 ? (float)(row_weight(r, row, j, 0) * inv) : 0.0f;
+    for (int k = 0; k < 6; k++) f[NW + k] = 0.0f;
+    f[46] = (float)(24.0 / (double)NW);
+    f[47] = 0.0f;
+    return;
+  }
+  const int64_t off = in.sl_off[s] + lane;
+  const int len = in.sl_len[s];
+  const int m = r.st_off[row + 1] - r.st_off[row];
+  for (int j = 0; j < NW; j++) {
+    double w = 0.0;
+    if (j < len) w = in.sl_w64 ? in.sl_w64[off + (int64_t)j * APC_SLICE] : (double)in.sl_w32[off + (int64_t)j * APC_SLICE];
+    f[j] = j < m ? (float)(w * inv) : 0.0f;
+  }
+  const int li = r.level[row];
+  for (int k = 0; k < 6; k++) {
+    const int32_t v = in.sl_idx[off + (int64_t)k * APC_SLICE];
+    f[NW + k] = v < r.n ? (float)(r.level[v] - li) : 0.0f;
+  }
+  int nb = 0;
+  for (int k = 0; k < len; k++) nb += (k < m && in.sl_idx[off + (int64_t)k * APC_SLICE] >= r.n) ? 1 : 0;
+  f[46] = (float)((double)m / (double)NW);
+  f[47] = (float)((double)nb / (double)m);
+}
+
+// LDS ordering between lanes of one wavefront (its LDS operations run in order)
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
+  __builtin_amdgcn_wave_barrier();
+}
+
+// 4 wavefronts per block share the BF16 weights in LDS; each wavefront takes
+// slices of 64 rows (grid-stride), computes the features of its rows into LDS,
+// then runs 4 passes of 16 rows through the network on v_mfma_f32_16x16x16 bf16:
+// lane l holds A[l%16][4(l/16)..+3], B[4(l/16)..+3][l%16], D[4(l/16)..+3][l%16].
+// Activations go through LDS to turn the D layout into the next A layout.
+constexpr int WPB = 4, FS = 52, HS = 68; // LDS row strides (16-byte aligned rows)
+__global__ void __launch_bounds__(WPB * 64)
+    k_infer_bf16(InferIn in, const float *__restrict__ P, const uint16_t *__restrict__ Wt,
+                 InferOut io) {
+  __shared__ __align__(16) uint16_t w1t[HID * K1];
+  __shared__ __align__(16) uint16_t w2t[HID * HID];
+  __shared__ __align__(16) uint16_t w3t[N3 * HID];
+  __shared__ float bsh[HID + HID + N3];
+  __shared__ __align__(16) float fl[WPB][64 * FS];
+  __shared__ __align__(16) float hl[WPB][16 * HS];
+  for (int t = threadIdx.x; t < NWB; t += WPB * 64) {
+    const uint16_t v = Wt[t];
+    if (t < HID * K1) w1t[t] = v;
+    else if (t < HID * K1 + HID * HID) w2t[t - HID * K1] = v;
+    else w3t[t - HID * K1 - HID * HID] = v;
+  }
+  for (int t = threadIdx.x; t < HID + HID + N3; t += WPB * 64)
+    bsh[t] = t < HID ? P[OB1 + t] : (t < 2 * HID ? P[OB2 + t - HID] : (t - 2 * HID < OUT ? P[OB3 + t - 2 * HID] : 0.f));
+  __syncthreads();
+  const int wv = threadIdx.x >> 6, l = threadIdx.x & 63, r16 = l & 15, kb = (l >> 4) * 4;
+  float *F = fl[wv];
+  float *H = hl[wv];
+  for (int64_t s0 = (int64_t)blockIdx.x * WPB + wv; s0 < in.nsl; s0 += (int64_t)gridDim.x * WPB) {
+    const int64_t s = __builtin_amdgcn_readfirstlane((int)s0);
+    const bool tmpl = io.mode == 2 ? true : in.sl_tmpl[s] != 0;
+    if (io.mode == 1 && tmpl) continue; // uniform slices use the per-level rows
+    const int32_t *tab = io.mode == 2 ? in.rows_tab : in.sl_rows + s * APC_SLICE;
+    {
+      const int32_t row = tab[l];
+      float f[IN];
+      if (in.feat) {
+        for (int j = 0; j < IN; j++) f[j] = row >= 0 ? in.feat[(int64_t)row * IN + j] : 0.0f;
+      } else {
+        slice_features(in, s, tmpl, l, row, f);
       }
+      for (int j = 0; j < IN; j++) F[l * FS + j] = f[j];
     }
-    for (int nt = 0; nt < 4; nt++)
-      for (int q = 0; q < 4; q++)
-        hs[kb + q][16 * nt + r16] = fmaxf(acc[nt][q] + P[OB1 + 16 * nt + r16], 0.f);
-    __syncthreads();
-    // layer 2
-    for (int nt = 0; nt < 4; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
-    for (int kk = 0; kk < HID / 16; kk++) {
-      short4_t a;
-      for (int q = 0; q < 4; q++) a[q] = bf16_bits(hs[r16][16 * kk + kb + q]);
-      for (int nt = 0; nt < 4; nt++) {
-        short4_t b;
-        for (int q = 0; q < 4; q++) b[q] = bf16_raw(W2[(16 * kk + kb + q) * HID + 16 * nt + r16]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+    wave_lds_sync();
+    for (int sub = 0; sub < 4; sub++) {
+      const float *Frow = F + (sub * 16 + r16) * FS;
+      // layer 1: A = features (16 x 48), B = W1 (48 x 64)
+      float4_t acc[4];
+      for (int nt = 0; nt < 4; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < K1 / 16; kk++) {
+        const float4_t x = *(const float4_t *)(Frow + 16 * kk + kb);
+        short4_t a;
+        for (int q = 0; q < 4; q++) a[q] = (short)bf16_of(x[q]);
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++) {
+          const short4_t b = *(const short4_t *)(w1t + (16 * nt + r16) * K1 + 16 * kk + kb);
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+        }
       }
+      for (int nt = 0; nt < 4; nt++)
+        for (int q = 0; q < 4; q++)
+          H[(kb + q) * HS + 16 * nt + r16] = fmaxf(acc[nt][q] + bsh[16 * nt + r16], 0.f);
+      wave_lds_sync();
+      // layer 2
+      for (int nt = 0; nt < 4; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < HID / 16; kk++) {
+        const float4_t x = *(const float4_t *)(H + r16 * HS + 16 * kk + kb);
+        short4_t a;
+        for (int q = 0; q < 4; q++) a[q] = (short)bf16_of(x[q]);
+#pragma unroll
+        for (int nt = 0; nt < 4; nt++) {
+          const short4_t b = *(const short4_t *)(w2t + (16 * nt + r16) * HID + 16 * kk + kb);
+          acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
+        }
+      }
+      wave_lds_sync();
+      for (int nt = 0; nt < 4; nt++)
+        for (int q = 0; q < 4; q++)
+          H[(kb + q) * HS + 16 * nt + r16] = fmaxf(acc[nt][q] + bsh[HID + 16 * nt + r16], 0.f);
+      wave_lds_sync();
+      // layer 3: N = 48 (41 used)
+      float4_t acc3[N3 / 16];
+      for (int nt = 0; nt < N3 / 16; nt++) acc3[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+      for (int kk = 0; kk < HID / 16; kk++) {
+        const float4_t x = *(const float4_t *)(H + r16 * HS + 16 * kk + kb);
+        short4_t a;
+        for (int q = 0; q < 4; q++) a[q] = (short)bf16_of(x[q]);
+#pragma unroll
+        for (int nt = 0; nt < N3 / 16; nt++) {
+          const short4_t b = *(const short4_t *)(w3t + (16 * nt + r16) * HID + 16 * kk + kb);
+          acc3[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc3[nt], 0, 0, 0);
+        }
+      }
+      wave_lds_sync();
+      for (int nt = 0; nt < N3 / 16; nt++)
+        for (int q = 0; q < 4; q++)
+          H[(kb + q) * HS + 16 * nt + r16] = acc3[nt][q] + bsh[2 * HID + 16 * nt + r16];
+      wave_lds_sync();
+      // 16 rows x OUT outputs; consecutive lanes take consecutive rows of one output
+      for (int e = l; e < 16 * OUT; e += 64) {
+        const int q = e & 15, p = e >> 4;
+        const int lane_row = sub * 16 + q;
+        const int32_t rr = tab[lane_row];
+        if (rr < 0) continue;
+        const float o = H[q * HS + p];
+        if (io.mode == 0) {
+          io.o[(int64_t)rr * OUT + p] = o;
+          continue;
+        }
+        const double inv = 1.0 / in.r.diag[rr];
+        if (io.mode == 2) {
+          if (p < NT) io.m_tmpl[NT * (int)in.r.rk[rr] + p] = (float)(((p == 0 ? 1.0 : 0.0) + (double)o) * inv);
+          continue;
+        }
+        if (p == 0) {
+          io.m_diag[rr] = (float)((1.0 + (double)o) * inv);
+          continue;
+        }
+        const int len = in.sl_len[s];
+        if (p - 1 >= len) continue;
+        const int64_t at = in.sl_off[s] + lane_row + (int64_t)(p - 1) * APC_SLICE;
+        const int m = in.r.st_off[rr + 1] - in.r.st_off[rr];
+        const bool live = p - 1 < m && in.sl_idx[at] < in.r.n;
+        io.m_sell[at] = live ? (float)((double)o * inv) : 0.f;
+      }
+      wave_lds_sync();
     }
-    __syncthreads();
-    for (int nt = 0; nt < 4; nt++)
-      for (int q = 0; q < 4; q++)
-        hs[kb + q][16 * nt + r16] = fmaxf(acc[nt][q] + P[OB2 + 16 * nt + r16], 0.f);
-    __syncthreads();
-    // layer 3: N = 48 (41 used)
-    for (int nt = 0; nt < N3 / 16; nt++) acc[nt] = float4_t{0.f, 0.f, 0.f, 0.f};
-    for (int kk = 0; kk < HID / 16; kk++) {
-      short4_t a;
-      for (int q = 0; q < 4; q++) a[q] = bf16_bits(hs[r16][16 * kk + kb + q]);
-      for (int nt = 0; nt < N3 / 16; nt++) {
-        short4_t b;
-        for (int q = 0; q < 4; q++) b[q] = bf16_raw(W3[(16 * kk + kb + q) * N3 + 16 * nt + r16]);
-        acc[nt] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[nt], 0, 0, 0);
-      }
+  }
+}
+
+// Safeguard of the general rows: alpha_i in [0, 1] minimising
+// sum_k (s_k + alpha t_k)^2 with s_k = U_k[i] / d_i - z_ki (the Jacobi row's probe
+// residual) and t_k = (m_i - j_i)^T U_k, then m_i <- j_i + alpha (m_i - j_i).
+// One wavefront per general slice, one lane per row; U = A Z (K x ntot).
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_safeguard(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_tmpl,
+                const int32_t *__restrict__ sl_len, const int32_t *__restrict__ sl_idx,
+                const int64_t *__restrict__ sl_off, int64_t nsl, const double *__restrict__ diag,
+                const double *__restrict__ Z, const double *__restrict__ U, int K, int64_t n,
+                int64_t ntot, float *__restrict__ m_diag, float *__restrict__ m_sell) {
+  const int64_t s0 = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
+  if (s0 >= nsl) return;
+  const int64_t s = __builtin_amdgcn_readfirstlane((int)s0);
+  if (sl_tmpl[s]) return;
+  const int lane = threadIdx.x & 63;
+  const int32_t row = sl_rows[s * APC_SLICE + lane];
+  if (row < 0) return;
+  const int len = sl_len[s];
+  const int64_t off = sl_off[s] + lane;
+  const double jd = 1.0 / diag[row];
+  const double dd = (double)m_diag[row] - jd;
+  double st = 0.0, tt = 0.0;
+  for (int k = 0; k < K; k++) {
+    const double *Uk = U + (int64_t)k * ntot;
+    const double ui = Uk[row];
+    const double sk = ui * jd - Z[(int64_t)k * ntot + row];
+    double tk = dd * ui;
+    for (int e = 0; e < len; e++) {
+      const int64_t at = off + (int64_t)e * APC_SLICE;
+      const int32_t j = sl_idx[at];
+      if (j < n) tk += (double)m_sell[at] * Uk[j]; // U holds interior rows only
     }
-    __syncthreads();
-    for (int nt = 0; nt < N3 / 16; nt++)
-      for (int q = 0; q < 4; q++) {
-        const int col = 16 * nt + r16;
-        hs[kb + q][col] = acc[nt][q] + (col < OUT ? P[OB3 + col] : 0.f);
-      }
-    __syncthreads();
-    for (int e = l; e < 16 * OUT; e += 64) {
-      const int q = e / OUT, p = e % OUT;
-      const int lane_row = sub * 16 + q;
-      const int32_t rr = rows_tab[s * APC_SLICE + lane_row];
-      if (rr < 0) continue;
-      const float o = hs[q][p];
-      if (io.mode == 0) {
-        io.o[(int64_t)rr * OUT + p] = o;
-        continue;
-      }
-      const double inv = 1.0 / io.diag[rr];
-      if (io.mode == 2) {
-        if (p < NT) io.m_tmpl[NT * (int)io.rk[rr] + p] = (float)(((p == 0 ? 1.0 : 0.0) + (double)o) * inv);
-        continue;
-      }
-      if (p == 0) {
-        io.m_diag[rr] = (float)((1.0 + (double)o) * inv);
-        continue;
-      }
-      const int len = io.sl_len[s];
-      if (p - 1 >= len) continue;
-      const int32_t a0 = io.st_off[rr];
-      const int m = io.st_off[rr + 1] - a0;
-      const bool live = p - 1 < m && io.st_idx[a0 + p - 1] < io.n;
-      io.m_sell[io.sl_off[s] + lane_row + (int64_t)(p - 1) * APC_SLICE] = live ? (float)((double)o * inv) : 0.f;
-    }
-    __syncthreads();
+    st += sk * tk;
+    tt += tk * tk;
+  }
+  double a = tt > 0.0 ? -st / tt : 1.0;
+  a = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+  if (a == 1.0) return;
+  m_diag[row] = (float)(jd + a * dd);
+  for (int e = 0; e < len; e++) {
+    const int64_t at = off + (int64_t)e * APC_SLICE;
+    m_sell[at] = (float)(a * (double)m_sell[at]);
   }
 }
 
@@ -450,15 +581,28 @@ InferOut make_out(const apc_cloud *c, int mode) {
   io.m_diag = c->m_diag;
   io.m_sell = c->m_sell;
   io.m_tmpl = c->m_tmpl;
-  io.sl_tmpl = c->sl_tmpl;
-  io.sl_len = c->sl_len;
-  io.st_off = c->st_off;
-  io.st_idx = c->st_idx;
-  io.sl_off = c->sl_off;
-  io.rk = c->rkind;
-  io.diag = c->diag;
-  io.n = c->n;
   return io;
+}
+
+InferIn make_in(const apc_cloud *c, const float *feat, const int32_t *tab) {
+  InferIn in;
+  in.r = make_rowop(c);
+  in.feat = feat;
+  in.rows_tab = tab;
+  in.sl_rows = c->sl_rows;
+  in.sl_tmpl = c->sl_tmpl;
+  in.sl_len = c->sl_len;
+  in.sl_idx = c->sl_idx;
+  in.sl_off = c->sl_off;
+  in.sl_w32 = c->sl_w32;
+  in.sl_w64 = c->sl_w64;
+  in.nsl = tab ? 1 : c->nsl;
+  return in;
+}
+
+unsigned infer_grid(int64_t nsl) {
+  const int64_t g = (nsl + WPB - 1) / WPB;
+  return (unsigned)(g < 1 ? 1 : (g < 2048 ? g : 2048));
 }
 
 } // namespace
@@ -556,49 +700,64 @@ int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16
   uint16_t *wb = nullptr;
   HIPCHK(hipMallocAsync((void **)&wb, (size_t)NWB * 2, s));
   hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(HID * HID)), dim3(APC_BLOCK), 0, s, P, wb,
-                     wb + K1 * HID, wb + K1 * HID + HID * HID);
+                     wb + HID * K1, wb + HID * K1 + HID * HID);
   InferOut io = make_out(c, 0);
   io.o = out;
   if (c->nsl > 0)
-    hipLaunchKernelGGL(k_infer_bf16, dim3((unsigned)c->nsl), dim3(64), 0, s, c->sl_rows, c->nsl,
-                       feat, P, wb, wb + K1 * HID, wb + K1 * HID + HID * HID, io);
+    hipLaunchKernelGGL(k_infer_bf16, dim3(infer_grid(c->nsl)), dim3(WPB * 64), 0, s,
+                       make_in(c, feat, nullptr), P, (const uint16_t *)wb, io);
   HIPCHK(hipGetLastError());
   HIPCHK(hipFreeAsync(wb, s));
   return APC_OK;
 }
 
-int apc_set_learned_impl(apc_cloud *c, const float *P, hipStream_t s) {
+int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, hipStream_t s) {
   if (!c->assembled) return APC_EINVAL;
   const int64_t n = c->n;
   if (!c->m_diag) HIPCHK(hipMalloc((void **)&c->m_diag, (size_t)(n > 0 ? n : 1) * sizeof(float)));
   if (!c->m_sell)
     HIPCHK(hipMalloc((void **)&c->m_sell, (size_t)(c->sl_entries > 0 ? c->sl_entries : 1) * sizeof(float)));
   if (!c->m_tmpl) HIPCHK(hipMalloc((void **)&c->m_tmpl, (size_t)APC_MAX_LEVELS * NT * sizeof(float)));
-  float *feat = nullptr;
   uint16_t *wb = nullptr;
   int32_t *rep = nullptr;
-  HIPCHK(hipMallocAsync((void **)&feat, (size_t)(n > 0 ? n : 1) * IN * sizeof(float), s));
   HIPCHK(hipMallocAsync((void **)&wb, (size_t)NWB * 2, s));
   HIPCHK(hipMallocAsync((void **)&rep, (size_t)(APC_MAX_LEVELS + APC_SLICE) * sizeof(int32_t), s));
   int32_t *tab = rep + APC_MAX_LEVELS;
-  hipLaunchKernelGGL(k_features, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, make_rowop(c), feat);
   hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(HID * HID)), dim3(APC_BLOCK), 0, s, P, wb,
-                     wb + K1 * HID, wb + K1 * HID + HID * HID);
+                     wb + HID * K1, wb + HID * K1 + HID * HID);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, rep, APC_MAX_LEVELS, INT_MAX);
   hipLaunchKernelGGL(k_rep_rows, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, n, rep);
   hipLaunchKernelGGL(k_rep_slice, dim3(1), dim3(APC_BLOCK), 0, s, (const int32_t *)rep, tab,
                      c->m_tmpl);
-  const uint16_t *W1 = wb, *W2 = wb + K1 * HID, *W3 = wb + K1 * HID + HID * HID;
-  // general slices: per-row M; then the per-level rows of the uniform slices
+  // general slices: per-row M (features computed in the kernel); then the
+  // per-level rows of the uniform slices
   if (c->nsl > 0)
-    hipLaunchKernelGGL(k_infer_bf16, dim3((unsigned)c->nsl), dim3(64), 0, s, c->sl_rows, c->nsl,
-                       (const float *)feat, P, W1, W2, W3, make_out(c, 1));
-  hipLaunchKernelGGL(k_infer_bf16, dim3(1), dim3(64), 0, s, (const int32_t *)tab, (int64_t)1,
-                     (const float *)feat, P, W1, W2, W3, make_out(c, 2));
+    hipLaunchKernelGGL(k_infer_bf16, dim3(infer_grid(c->nsl)), dim3(WPB * 64), 0, s,
+                       make_in(c, nullptr, nullptr), P, (const uint16_t *)wb, make_out(c, 1));
+  hipLaunchKernelGGL(k_infer_bf16, dim3(1), dim3(WPB * 64), 0, s,
+                     make_in(c, nullptr, (const int32_t *)tab), P, (const uint16_t *)wb,
+                     make_out(c, 2));
   HIPCHK(hipGetLastError());
-  HIPCHK(hipFreeAsync(feat, s));
   HIPCHK(hipFreeAsync(wb, s));
   HIPCHK(hipFreeAsync(rep, s));
+  if (Z && K > 0 && c->nsl > 0) {
+    const int64_t ntot = n + c->nb;
+    double *U = nullptr, *Zc = nullptr;
+    HIPCHK(hipMallocAsync((void **)&U, (size_t)K * ntot * sizeof(double), s));
+    HIPCHK(hipMallocAsync((void **)&Zc, (size_t)K * ntot * sizeof(double), s));
+    for (int k = 0; k < K; k++) {
+      double *zt = Zc + (int64_t)k * ntot;
+      hipLaunchKernelGGL(k_probe_copy, dim3(grid_for(ntot)), dim3(APC_BLOCK), 0, s,
+                         Z + (int64_t)k * ntot, n, ntot, zt);
+      APCCHK(apc_apply_impl(c, zt, U + (int64_t)k * ntot, s));
+    }
+    hipLaunchKernelGGL(k_safeguard, dim3(grid_for(c->nsl, APC_BLOCK / 64)), dim3(APC_BLOCK), 0, s,
+                       c->sl_rows, c->sl_tmpl, c->sl_len, c->sl_idx, c->sl_off, c->nsl, c->diag,
+                       (const double *)Zc, (const double *)U, K, n, ntot, c->m_diag, c->m_sell);
+    HIPCHK(hipGetLastError());
+    HIPCHK(hipFreeAsync(U, s));
+    HIPCHK(hipFreeAsync(Zc, s));
+  }
   HIPCHK(hipStreamSynchronize(s));
   c->learned = true;
   return APC_OK;

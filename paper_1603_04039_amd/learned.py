@@ -67,6 +67,18 @@ def training_data(seeds=TRAIN_SEEDS, K=32, workload="beam_halo_1e5", probe_seed=
     return torch.cat(feats), torch.cat(quads)
 
 
+SAFEGUARD_PROBES = 16
+
+
+def probes(cloud, K=SAFEGUARD_PROBES, seed=0):
+    """K Gaussian probe vectors for the install's safeguard (device, float64)."""
+    import torch
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(seed)
+    return torch.randn((K, cloud.n + cloud.nb), dtype=torch.float64, device="cuda",
+                       generator=gen)
+
+
 def init_params(seed=0):
     """He-initialised hidden layers, zero output layer (starts at Jacobi)."""
     import torch
@@ -130,7 +142,7 @@ def evaluate(P, seeds=HELD_OUT_SEEDS, workload="beam_halo_1e5", tol=1e-8,
         for name, pc in (("jacobi", apc.APC_PRECOND_JACOBI), ("learned", apc.APC_PRECOND_LEARNED)):
             if pc == apc.APC_PRECOND_LEARNED:
                 t0 = time.perf_counter()
-                cloud.set_learned_precond(P)
+                cloud.set_learned_precond(P, probes(cloud, seed=sd))
                 res["install_ms"] = (time.perf_counter() - t0) * 1e3
             # one untimed solve, then the timed one
             cloud.solve(b, tol=tol, maxit=maxit, precond=pc)
@@ -163,7 +175,7 @@ def main():
     ap.add_argument("--probes", type=int, default=32)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=4096)
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=2e-3)
     ap.add_argument("--eval-clouds", type=int, default=len(HELD_OUT_SEEDS))
     ap.add_argument("--out", default=PARAMS_PATH)
     args = ap.parse_args()

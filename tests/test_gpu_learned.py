@@ -163,13 +163,38 @@ def test_inference_fp32_and_bf16(apc, lrn, oracle_mod, small):
     assert np.abs(o16 - o32).max() > 0.0
 
 
+def _m_times(O, md, mw, f):
+    nd = O.nodes()
+    off, idx = nd["st_off"], nd["st_idx"]
+    rows = np.repeat(np.arange(O.n), np.diff(off))
+    out = md * f[:O.n]
+    np.add.at(out, rows, mw * f[np.minimum(idx, O.n + O.nb - 1)] * (idx < O.n))
+    return out
+
+
+def _m_bound(O, oracle_mod, P, f, d, frac):
+    """frac times the magnitude of each row of M f: the forward of the network
+    with |W|, |b| on |x| bounds |o| and the BF16 error of o from above."""
+    feat, _ = O.learn_data()
+    mag = oracle_mod.mlp_forward(np.abs(P.astype(np.float64)),
+                                 np.abs(feat.astype(np.float32).astype(np.float64)))
+    nd = O.nodes()
+    off, idx = nd["st_off"], nd["st_idx"]
+    rows = np.repeat(np.arange(O.n), np.diff(off))
+    pos = np.arange(off[-1]) - np.repeat(off[:-1], np.diff(off)) + 1
+    tot = (mag[:, 0] + 1.0) * np.abs(f[:O.n])
+    np.add.at(tot, rows, np.where(idx < O.n, mag[rows, np.minimum(pos, 40)], 0.0)
+              * np.abs(f[np.minimum(idx, O.n + O.nb - 1)]))
+    return frac * tot / np.abs(d)
+
+
 def test_apply_precond(apc, lrn, oracle_mod, small):
-    """M f of the installed learned M against the oracle's network output: row i
-    of M is (e_0 + o_i) / d_i on {i} + the stencil of row i (boundary columns
-    dropped).  Uniform 2-ring rows take the output of their level's first such
-    row; their features are identical, so the oracle's per-row outputs agree.
-    Bar: the BF16 inference bound (2% of the magnitude forward) carried through
-    the row sum, plus FP32 storage of the weights.  Jacobi: f_i / d_i."""
+    """M f of the installed learned M against the oracle's rows of M.  Uniform
+    2-ring rows take the output of their level's first such row; their features
+    are identical, so the oracle's per-row outputs agree.  Bar: the BF16
+    inference bound (2% of the magnitude forward) through the row sum; with the
+    safeguard 3% (alpha is computed from the BF16 outputs on the GPU and from FP64
+    ones in the oracle).  Jacobi: f_i / d_i."""
     note("apply_precond: Jacobi and learned M vs oracle")
     O, G = small
     n, nt = O.n, O.n + O.nb
@@ -183,24 +208,35 @@ def test_apply_precond(apc, lrn, oracle_mod, small):
     P = lrn.init_params(3).cpu().numpy()
     n3 = apc.MLP_HID * apc.MLP_OUT + apc.MLP_OUT
     P[-n3:] = (0.05 * rng.standard_normal(n3)).astype(np.float32)
-    G.set_learned_precond(torch.from_numpy(P).cuda())
+    Pd = torch.from_numpy(P).cuda()
+    G.set_learned_precond(Pd)
     got = G.apply_precond(fd, apc.APC_PRECOND_LEARNED).cpu().numpy()
-    feat, _ = O.learn_data()
-    f32 = feat.astype(np.float32).astype(np.float64)
-    o = oracle_mod.mlp_forward(P.astype(np.float64), f32)
-    mag = oracle_mod.mlp_forward(np.abs(P.astype(np.float64)), np.abs(f32))
+    md, mw = O.learned_m(P)
+    err = np.abs(got - _m_times(O, md, mw, f))
+    assert np.all(err <= _m_bound(O, oracle_mod, P, f, d, 0.02))
+    # the install computes the features itself from the sliced layout: they must
+    # be the ones apc_learn_data writes, so M agrees with the BF16 inference on
+    # those features up to FP32 storage
+    fg, _ = G.learn_data()
+    o16 = G.mlp_infer(Pd, fg, bf16=True).cpu().numpy().astype(np.float64)
     nd = O.nodes()
     off, idx = nd["st_off"], nd["st_idx"]
     for i in range(n):
         J = [i] + list(idx[off[i]:off[i + 1]])
         live = np.array([j < n for j in J])
         Jc = np.array([j if j < n else 0 for j in J])
-        mt = o[i, :len(J)].copy()
+        mt = o16[i, :len(J)].copy()
         mt[0] += 1.0
-        expect = np.sum(np.where(live, mt * f[Jc], 0.0)) / d[i]
-        bound = (0.02 * np.sum(np.where(live, mag[i, :len(J)] * np.abs(f[Jc]), 0.0))
-                 + 1e-6 * np.sum(np.where(live, np.abs(mt * f[Jc]), 0.0))) / abs(d[i])
-        assert abs(got[i] - expect) <= bound, (i, got[i], expect, bound)
+        terms = np.where(live, mt * f[Jc], 0.0) / d[i]
+        assert abs(got[i] - terms.sum()) <= 1e-5 * np.abs(terms).sum(), i
+    # safeguard with probes
+    Z = rng.standard_normal((8, nt))
+    G.set_learned_precond(Pd, torch.from_numpy(Z).cuda())
+    got_s = G.apply_precond(fd, apc.APC_PRECOND_LEARNED).cpu().numpy()
+    md_s, mw_s = O.learned_m(P, Z)
+    err = np.abs(got_s - _m_times(O, md_s, mw_s, f))
+    assert np.all(err <= _m_bound(O, oracle_mod, P, f, d, 0.03))
+    assert np.abs(got_s - got).max() > 0.0  # the safeguard changed rows
 
 
 def test_learned_training_and_solve(apc, lrn):
@@ -220,7 +256,7 @@ def test_learned_training_and_solve(apc, lrn):
     _, rho_t, _ = cloud.deposit(tol=1e-10, maxit=4000)
     b = rho_t[:cloud.n].contiguous()
     phi_j, st_j = cloud.solve(b, tol=1e-10, precond=apc.APC_PRECOND_JACOBI)
-    cloud.set_learned_precond(P)
+    cloud.set_learned_precond(P, lrn.probes(cloud, seed=1))
     phi_l, st_l = cloud.solve(b, tol=1e-10, precond=apc.APC_PRECOND_LEARNED)
     note(f"jacobi {st_j['iters']} it, learned {st_l['iters']} it")
     assert st_j["status"] == 0 and st_l["status"] == 0
@@ -261,3 +297,19 @@ def test_learned_requires_install(apc, lrn):
     with pytest.raises(apc.ApcError):
         cloud.solve(b, precond=apc.APC_PRECOND_LEARNED)
     cloud.close()
+
+
+def test_learned_gain_held_out(apc, lrn):
+    """Training on the 200 seeded clouds of the small beam recipe (seeds 4000..4199),
+    evaluation on 20 held-out seeds (5000..5019): the learned M needs fewer
+    iterations and less solve time than Jacobi to reach 1e-8, without fallback."""
+    note("learned: training on 200 clouds")
+    feat, quad = lrn.training_data()
+    P, _ = lrn.train(feat, quad, steps=3000, batch=4096, lr=2e-3)
+    del feat, quad
+    note("learned: 20 held-out clouds")
+    s = lrn.summarize(lrn.evaluate(P))
+    note(f"held-out: {s}")
+    assert s["fallbacks"] == 0
+    assert s["iter_ratio"] >= 1.4
+    assert s["time_ratio"] >= 1.2

@@ -40,7 +40,7 @@ def test_features_row_sums(oracle_mod, small_cloud):
     the 40 weight features of a row sum to -d_i/|d_i| = 1 in magnitude.  The
     structural features, counted here from the node list: level differences to
     the first 6 stencil nodes (2:1 balance keeps face neighbours within one
-    level), the row's level / max_depth, the boundary fraction of the stencil."""
+    level), the stencil size m / 40, the boundary fraction of the stencil."""
     C = small_cloud
     feat, _ = C.learn_data()
     nd = C.nodes()
@@ -55,7 +55,7 @@ def test_features_row_sums(oracle_mod, small_cloud):
             assert feat[i, 40 + k] == (lev[v] - lev[i] if v < C.n else 0)
         assert feat[i, 47] == pytest.approx(np.mean(nbrs >= C.n), abs=1e-15)
         assert np.all(feat[i, m[i]:40] == 0.0)
-    np.testing.assert_array_equal(feat[:, 46], lev / 5.0)
+    np.testing.assert_array_equal(feat[:, 46], m / 40.0)
     assert feat[:, 47].max() > 0.0 and np.all(np.abs(feat[:, 40:46]) <= 2)
 
 
@@ -187,3 +187,80 @@ def test_mlp_loss_consistent_with_forward(oracle_mod):
         Q, bq, cq = unpack(quad[r])
         tot += m @ Q @ m - 2 * bq @ m + cq
     assert L == pytest.approx(tot / rows.size, rel=1e-12)
+
+
+def _probe_losses(C, w, d, off, idx, Z, mdiag, mw):
+    """Per-row probe estimate sum_k (m_i^T A z_k - z_ki)^2, with A z computed here."""
+    n = C.n
+    import scipy.sparse as sp
+    rows = np.repeat(np.arange(n), np.diff(off))
+    keep = idx < n
+    A = sp.csr_matrix((np.concatenate([d, w[keep]]),
+                       (np.concatenate([np.arange(n), rows[keep]]),
+                        np.concatenate([np.arange(n), idx[keep]]))), shape=(n, n))
+    M = sp.csr_matrix((np.concatenate([mdiag, mw[keep]]),
+                       (np.concatenate([np.arange(n), rows[keep]]),
+                        np.concatenate([np.arange(n), idx[keep]]))), shape=(n, n))
+    Zi = Z[:, :n].T
+    R = M @ (A @ Zi) - Zi
+    return (R * R).sum(axis=1)
+
+
+def test_learned_m_zero_network_is_jacobi(oracle_mod, small_cloud):
+    C = small_cloud
+    _, d = C.assemble()
+    Z = np.random.default_rng(2).standard_normal((4, C.n + C.nb))
+    for z in (None, Z):
+        md, mw = C.learned_m(np.zeros(oracle_mod.MLP_NPARAM), z)
+        np.testing.assert_allclose(md, 1.0 / d, rtol=1e-15)
+        assert np.all(mw == 0.0)
+
+
+def test_learned_m_safeguard_minimises_probe_loss(oracle_mod, small_cloud):
+    """The safeguarded row is the best point of the segment from the Jacobi row to
+    the network's row under the probe loss: never worse than either end."""
+    C = small_cloud
+    w, d = C.assemble()
+    nd = C.nodes()
+    off, idx = nd["st_off"], nd["st_idx"]
+    rng = np.random.default_rng(6)
+    P = 0.3 * rng.standard_normal(oracle_mod.MLP_NPARAM)
+    Z = rng.standard_normal((6, C.n + C.nb))
+    md0, mw0 = C.learned_m(P)
+    md1, mw1 = C.learned_m(P, Z)
+    Lj = _probe_losses(C, w, d, off, idx, Z, 1.0 / d, np.zeros_like(w))
+    L0 = _probe_losses(C, w, d, off, idx, Z, md0, mw0)
+    L1 = _probe_losses(C, w, d, off, idx, Z, md1, mw1)
+    tol = 1e-9 * (Lj + L0)
+    assert np.all(L1 <= np.minimum(Lj, L0) + tol)
+    # with random weights most rows are pulled back, some all the way to Jacobi
+    changed = np.abs(md1 - md0) > 1e-12 * np.abs(md0)
+    assert changed.mean() > 0.5
+    # every row lies on the segment: m1 - j = alpha (m0 - j) with one alpha per row
+    for i in np.where(changed)[0][:50]:
+        a = (md1[i] - 1.0 / d[i]) / (md0[i] - 1.0 / d[i])
+        assert -1e-12 <= a <= 1.0 + 1e-12
+        np.testing.assert_allclose(mw1[off[i]:off[i + 1]], a * mw0[off[i]:off[i + 1]],
+                                   rtol=1e-12, atol=1e-300)
+
+
+def test_learned_m_uniform_rows_untouched(oracle_mod):
+    """On a uniform lattice the interior rows two cells away from the boundary
+    have the uniform 2-ring stencil; the safeguard leaves them as the network
+    gives them, and the network gives them all the same scaled row."""
+    from workloads import uniform_lattice_points
+    C = oracle_mod.OracleCloud(uniform_lattice_points(4), order=2, c=1e-3, max_depth=4)
+    rng = np.random.default_rng(7)
+    P = 0.3 * rng.standard_normal(oracle_mod.MLP_NPARAM)
+    Z = rng.standard_normal((4, C.n + C.nb))
+    md0, mw0 = C.learned_m(P)
+    md1, mw1 = C.learned_m(P, Z)
+    ix = C.coords()[:, :C.n]
+    sp = 2  # cell size of level 4 in units of 2^-(max_depth+1)
+    lo, hi = ix.min(axis=1), ix.max(axis=1)
+    inner = np.all((ix >= lo[:, None] + 2 * sp) & (ix <= hi[:, None] - 2 * sp), axis=0)
+    assert inner.sum() == 12 ** 3  # nodes 2..13 of 0..15 along each axis
+    _, d = C.assemble()
+    np.testing.assert_array_equal(md1[inner], md0[inner])
+    scaled = md0[inner] * d[inner]
+    np.testing.assert_allclose(scaled, scaled[0], rtol=1e-12)
