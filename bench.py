@@ -144,6 +144,70 @@ def spmv_roofline(torch, cloud, reps, mixed):
                 uniform_rows=oi["n_uniform"], sell_entries=oi["sell_entries"])
 
 
+def batch_bench(apc, torch, steps, tol):
+    """The 64-cloud workload: one batch (union of the clouds, batched BiCGSTAB
+    replayed from HIP graphs, autotuned) against the same clouds solved one after
+    the other through the single-cloud path.  nodes/s = total interior nodes /
+    (assembly + Poisson solve), HIP events on the stream."""
+    from workloads import BATCH, batch_specs, beam_halo
+    specs = batch_specs(master_seed=BATCH["master_seed"], count=BATCH["count"])
+    xs = [torch.from_numpy(beam_halo(sp["N"], seed=sp["seed"], sigma=sp["sigma"],
+                                     halo_frac=sp["halo_frac"])).cuda() for sp in specs]
+    kw = dict(order=BATCH["order"], c=BATCH["c"], max_depth=BATCH["max_depth"],
+              precision=apc.APC_MIXED)
+    stream = torch.cuda.current_stream()
+    B = apc.Batch(xs, **kw)
+    B.assemble_gfd()
+    div, chunk = B.tune(tol=tol)
+    _, rho_t, _ = B.deposit(tol=1e-10, maxit=4000)
+    times = []
+    iters = None
+    for it in range(steps + 1):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        B.assemble_gfd()
+        e1.record(stream)
+        phi, st = B.solve(rho_t, tol=tol, maxit=20000, precond=apc.APC_PRECOND_JACOBI)
+        e2.record(stream)
+        e2.synchronize()
+        if any(x["status"] != 0 for x in st):
+            raise RuntimeError("batch solve did not converge")
+        iters = [x["iters"] for x in st]
+        if it > 0:
+            times.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+    t_asm = sum(t[0] for t in times) / len(times)
+    t_sol = sum(t[1] for t in times) / len(times)
+    n_tot = B.n
+    # the same clouds through the single-cloud path, one after the other
+    seq = 0.0
+    singles = [apc.Cloud(x, **kw) for x in xs]
+    for S, c in zip(singles, range(len(singles))):
+        S.assemble_gfd()
+        idx = torch.from_numpy(B.node_index(c)).cuda()
+        rt = rho_t[idx][:S.n].contiguous()
+        S.solve(rt, tol=tol)  # warm
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        S.assemble_gfd()
+        e1.record(stream)
+        S.solve(rt, tol=tol)
+        e2.record(stream)
+        e2.synchronize()
+        seq += e0.elapsed_time(e2)
+        S.close()
+    out = dict(workload=f"beam_halo_batch{BATCH['count']}", clouds=B.count,
+               particles=int(B.N), nodes=int(n_tot),
+               nodes_per_s=round(n_tot / ((t_asm + t_sol) * 1e-3), 1),
+               assemble_ms=round(t_asm, 3), solve_ms=round(t_sol, 3),
+               iters_min=min(iters), iters_max=max(iters),
+               sequential_nodes_per_s=round(n_tot / (seq * 1e-3), 1),
+               speedup_vs_sequential=round(seq / (t_asm + t_sol), 3),
+               tuned=dict(spmv_div=div, chunk=chunk, spmv_blocks=B.info["spmv_blocks"],
+                          use_graph=B.info["use_graph"]))
+    B.close()
+    return out
+
+
 def cpu_baseline(xyz, cfg, iters_full, n_sample_iters=20):
     """The oracle (plain serial C, FP64) on the same cloud: assembly of all nodes
     plus `n_sample_iters` BiCGSTAB iterations, the solve time scaled to the
@@ -181,6 +245,7 @@ def main():
     ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batch")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
@@ -258,6 +323,12 @@ def main():
             if pcn == "learned":
                 variants[key]["install_ms"] = round(msv["install"], 3)
 
+    batch = None
+    if not args.no_batch:
+        log("64-cloud batch")
+        batch = batch_bench(apc, torch, max(2, args.steps // 2), args.tol)
+        log(f"batch: {batch}")
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -287,6 +358,8 @@ def main():
         "roofline": roof,
         "cpu_baseline": cpu,
     }
+    if batch is not None:
+        out["batch"] = batch
     if roof_m is not None:
         out["roofline_precond"] = roof_m
         out["learned_params"] = params_src

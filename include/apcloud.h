@@ -251,6 +251,59 @@ int apc_set_learned_precond(apc_cloud *c, const float *params, const double *Z, 
 int apc_apply_precond(apc_cloud *c, int precond, const double *in, double *out,
                       hipStream_t stream);
 
+/* ---- batches of independent clouds (a grown form beside the paper's method) ----
+   count clouds built with the same parameters are held as one union: node
+   vectors of the batch (n_total + nb_total) carry the interior nodes of cloud 0,
+   1, ... first (cloud c at [ibase_c, ibase_c + n_c), ibase_c = sum of n before c,
+   its nodes in the order of a single cloud), then the boundary nodes in the same
+   cloud order; particle arrays (N_total) carry cloud c's particles, in the
+   caller's order, at [pbase_c, pbase_c + N_c).  Assembly, deposit, right-hand
+   sides, operator applies and interpolation run as single launches over all
+   clouds; every cloud keeps its own BiCGSTAB (own scalars and convergence test,
+   so its iterates are those of a single-cloud solve up to rounding), replayed
+   from a HIP graph of `chunk` iterations until every cloud has stopped. */
+typedef struct apc_batch apc_batch;
+typedef struct {
+  int64_t count, N, n, nb, nnz, nsl; /* clouds; totals over the batch; slices */
+  int use_graph, chunk;               /* solver replay: HIP graph on/off, iterations per replay */
+  int spmv_blocks, pad;               /* workgroups of the batched SpMV */
+} apc_batch_info_t;
+
+/* Build count clouds (xyz[c]: device pointer of cloud c's 3 x N[c] SoA particles;
+   xyz and N are host arrays), then their union.  Same errors as
+   apc_build_cloud, for the first cloud that fails.  Synchronises. */
+int apc_build_batch(const apc_params *p, int count, const double *const *xyz, const int64_t *N,
+                    hipStream_t stream, apc_batch **out);
+/* Totals and launch shape; per-cloud sizes into host arrays (each may be NULL). */
+int apc_batch_info(const apc_batch *b, apc_batch_info_t *info, int64_t *cloud_N,
+                   int64_t *cloud_n, int64_t *cloud_nb);
+/* Solver launch shape: use_graph 0/1 (-1 keeps), chunk iterations per replay
+   (<= 0 keeps), SpMV workgroup divisor 1, 2, 4 or 8 (<= 0 keeps). */
+int apc_batch_configure(apc_batch *b, int use_graph, int chunk, int spmv_div);
+/* Autotuner: times the batched SpMV for each workgroup divisor and whole Jacobi
+   solves (to tol, right-hand side from the batch's own deposit) for chunk 4, 8,
+   16 and 32; keeps the fastest of each and returns them (host ints, may be
+   NULL).  Requires apc_batch_assemble.  Synchronises. */
+int apc_batch_tune(apc_batch *b, double tol, int *spmv_div, int *chunk, hipStream_t stream);
+/* The operator of every cloud (apc_assemble_gfd on each), one launch. */
+int apc_batch_assemble(apc_batch *b, hipStream_t stream);
+/* apc_deposit for every cloud: q (N_total, or NULL for 1/N_c per particle of
+   cloud c), rho_M (may be NULL) and rho_t (n_total + nb_total); st: count
+   host records (may be NULL; ms is the batch's time).  Synchronises. */
+int apc_batch_deposit(apc_batch *b, const double *q, double *rho_M, double *rho_t, double tol,
+                      int maxit, apc_stats *st, hipStream_t stream);
+/* apc_solve for every cloud: rho_t (n_total, or longer), g (nb_total or NULL),
+   phi (n_total + nb_total), precond APC_PRECOND_NONE or APC_PRECOND_JACOBI; st:
+   count host records (may be NULL).  Returns APC_ENOCONV if any cloud did not
+   converge (see its record).  Synchronises. */
+int apc_batch_solve(apc_batch *b, const double *rho_t, const double *g, double *phi, double tol,
+                    int maxit, int precond, apc_stats *st, hipStream_t stream);
+/* apc_interpolate_force for every cloud: phi (n_total + nb_total), phi_p
+   (N_total), grad_p (3 x N_total SoA).  Does not synchronise. */
+int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, double *grad_p,
+                                hipStream_t stream);
+void apc_batch_destroy(apc_batch *b);
+
 void apc_destroy(apc_cloud *c);
 const char *apc_strerror(int code);
 /* Text of the last HIP error seen by the calling thread (empty if none). */

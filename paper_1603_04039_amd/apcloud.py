@@ -28,7 +28,9 @@ EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_n
            "apc_assemble_gfd", "apc_get_operator", "apc_operator_info", "apc_deposit", "apc_density_solve",
            "apc_solve", "apc_interpolate_force", "apc_node_derivs", "apc_apply_operator",
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
-           "apc_set_learned_precond", "apc_apply_precond", "apc_destroy", "apc_strerror", "apc_last_error"]
+           "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
+           "apc_batch_configure", "apc_batch_tune", "apc_batch_assemble", "apc_batch_deposit",
+           "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_destroy", "apc_destroy", "apc_strerror", "apc_last_error"]
 
 
 class ApcError(RuntimeError):
@@ -52,6 +54,12 @@ class Stats(ct.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class BatchInfo(ct.Structure):
+    _fields_ = [("count", ct.c_int64), ("N", ct.c_int64), ("n", ct.c_int64), ("nb", ct.c_int64),
+                ("nnz", ct.c_int64), ("nsl", ct.c_int64), ("use_graph", ct.c_int),
+                ("chunk", ct.c_int), ("spmv_blocks", ct.c_int), ("pad", ct.c_int)]
 
 
 _lib = None
@@ -88,6 +96,16 @@ def load_library(path: str = LIB_PATH):
     lib.apc_mlp_infer.argtypes = [P, P, P, ct.c_int, P, P]
     lib.apc_set_learned_precond.argtypes = [P, P, P, ct.c_int, P]
     lib.apc_apply_precond.argtypes = [P, ct.c_int, P, P, P]
+    lib.apc_build_batch.argtypes = [ct.POINTER(Params), ct.c_int, P, P, P, ct.POINTER(P)]
+    lib.apc_batch_info.argtypes = [P, ct.POINTER(BatchInfo), P, P, P]
+    lib.apc_batch_configure.argtypes = [P, ct.c_int, ct.c_int, ct.c_int]
+    lib.apc_batch_tune.argtypes = [P, ct.c_double, ct.POINTER(ct.c_int), ct.POINTER(ct.c_int), P]
+    lib.apc_batch_assemble.argtypes = [P, P]
+    lib.apc_batch_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, P, P]
+    lib.apc_batch_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, P, P]
+    lib.apc_batch_interpolate_force.argtypes = [P, P, P, P, P]
+    lib.apc_batch_destroy.argtypes = [P]
+    lib.apc_batch_destroy.restype = None
     lib.apc_destroy.argtypes = [P]
     lib.apc_destroy.restype = None
     lib.apc_strerror.argtypes = [ct.c_int]
@@ -344,6 +362,102 @@ def mlp_adam(params, m, v, grad, step, lr, stream=None):
     _check(lib.apc_mlp_adam(_dptr(params, f32, MLP_NPARAM), _dptr(m, f32, MLP_NPARAM),
                             _dptr(v, f32, MLP_NPARAM), _dptr(grad, f32, MLP_NPARAM), int(step),
                             float(lr), _stream(stream)), "apc_mlp_adam")
+
+
+class Batch:
+    """count clouds (list of 3 x N_c float64 CUDA tensors) built with one set of
+    parameters and held as one union (see apc_build_batch)."""
+
+    def __init__(self, xyz_list, stream=None, **params):
+        import torch
+        self.lib = load_library()
+        self.params = make_params(**params)
+        self.xyz = list(xyz_list)
+        self.count = len(self.xyz)
+        ptrs = (ct.c_void_p * self.count)(*[_dptr(x, torch.float64).value for x in self.xyz])
+        Ns = (ct.c_int64 * self.count)(*[x.shape[1] for x in self.xyz])
+        h = ct.c_void_p()
+        _check(self.lib.apc_build_batch(ct.byref(self.params), self.count, ptrs, Ns,
+                                        _stream(stream), ct.byref(h)), "apc_build_batch")
+        self.h = h
+        self.refresh()
+
+    def refresh(self):
+        info = BatchInfo()
+        cN, cn, cnb = [np.zeros(self.count, np.int64) for _ in range(3)]
+        _check(self.lib.apc_batch_info(self.h, ct.byref(info), cN.ctypes.data_as(ct.c_void_p),
+                                       cn.ctypes.data_as(ct.c_void_p),
+                                       cnb.ctypes.data_as(ct.c_void_p)), "apc_batch_info")
+        self.info = {k: getattr(info, k) for k, _ in BatchInfo._fields_ if k != "pad"}
+        self.N, self.n, self.nb = int(info.N), int(info.n), int(info.nb)
+        self.cloud_N, self.cloud_n, self.cloud_nb = cN, cn, cnb
+        self.pbase = np.concatenate([[0], np.cumsum(cN)[:-1]])
+        self.ibase = np.concatenate([[0], np.cumsum(cn)[:-1]])
+        self.bbase = np.concatenate([[0], np.cumsum(cnb)[:-1]])
+
+    def node_index(self, c):
+        """Batch positions of cloud c's n_c + nb_c nodes, in single-cloud order."""
+        return np.concatenate([self.ibase[c] + np.arange(self.cloud_n[c]),
+                               self.n + self.bbase[c] + np.arange(self.cloud_nb[c])])
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.apc_batch_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def configure(self, use_graph=-1, chunk=0, spmv_div=0):
+        _check(self.lib.apc_batch_configure(self.h, int(use_graph), int(chunk), int(spmv_div)),
+               "apc_batch_configure")
+        self.refresh()
+
+    def tune(self, tol=1e-8, stream=None):
+        d, c = ct.c_int(), ct.c_int()
+        _check(self.lib.apc_batch_tune(self.h, tol, ct.byref(d), ct.byref(c), _stream(stream)),
+               "apc_batch_tune")
+        self.refresh()
+        return d.value, c.value
+
+    def assemble_gfd(self, stream=None):
+        _check(self.lib.apc_batch_assemble(self.h, _stream(stream)), "apc_batch_assemble")
+
+    def _stats(self):
+        return (Stats * self.count)()
+
+    def deposit(self, q=None, tol=1e-12, maxit=1000, stream=None):
+        import torch
+        nt = self.n + self.nb
+        rho_M = torch.empty(nt, dtype=torch.float64, device="cuda")
+        rho_t = torch.empty(nt, dtype=torch.float64, device="cuda")
+        st = self._stats()
+        rc = _check(self.lib.apc_batch_deposit(self.h, _dptr(q, torch.float64, self.N),
+                                               _dptr(rho_M), _dptr(rho_t), tol, maxit,
+                                               ct.cast(st, ct.c_void_p), _stream(stream)),
+                    "apc_batch_deposit")
+        return rho_M, rho_t, [dict(x.as_dict(), rc=rc) for x in st]
+
+    def solve(self, rho_t, g=None, tol=1e-8, maxit=20000, precond=APC_PRECOND_JACOBI,
+              stream=None):
+        import torch
+        nt = self.n + self.nb
+        phi = torch.empty(nt, dtype=torch.float64, device="cuda")
+        st = self._stats()
+        rc = _check(self.lib.apc_batch_solve(self.h, _dptr(rho_t, torch.float64, self.n),
+                                             _dptr(g, torch.float64, self.nb), _dptr(phi), tol,
+                                             maxit, precond, ct.cast(st, ct.c_void_p),
+                                             _stream(stream)), "apc_batch_solve")
+        return phi, [dict(x.as_dict(), rc=rc) for x in st]
+
+    def interpolate_force(self, phi, stream=None):
+        import torch
+        phi_p = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        grad_p = torch.empty((3, self.N), dtype=torch.float64, device="cuda")
+        _check(self.lib.apc_batch_interpolate_force(
+            self.h, _dptr(phi, torch.float64, self.n + self.nb), _dptr(phi_p), _dptr(grad_p),
+            _stream(stream)), "apc_batch_interpolate_force")
+        return phi_p, grad_p
 
 
 # C-ABI names as free functions

@@ -8,12 +8,14 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libapcloud.so")
-SOURCES = ["primitives.hip", "build.hip", "gfd.hip", "sell.hip", "solve.hip", "learned.hip", "api.cpp"]
+SOURCES = ["primitives.hip", "build.hip", "gfd.hip", "sell.hip", "solve.hip", "learned.hip",
+           "batch.hip", "api.cpp"]
 
 
-def build_library(verbose: bool = False) -> str:
+def build_library(verbose: bool = False, jobs: int = 0) -> str:
+    from concurrent.futures import ThreadPoolExecutor
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    objs = []
+    cmds, objs = [], []
     for src in SOURCES:
         obj = os.path.join(CSRC, src + ".o")
         # -packed-fp32-ops: no packed-FP32 instructions anywhere in the device code
@@ -24,8 +26,12 @@ def build_library(verbose: bool = False) -> str:
                "-o", obj, os.path.join(CSRC, src)]
         if verbose:
             print(" ".join(cmd), flush=True)
-        subprocess.run(cmd, check=True)
+        cmds.append(cmd)
         objs.append(obj)
+    jobs = jobs or min(len(cmds), os.cpu_count() or 1, 8)
+    with ThreadPoolExecutor(jobs) as ex:
+        for r in list(ex.map(lambda c: subprocess.run(c, check=True), cmds)):
+            pass
     tmp = LIB + ".tmp"
     cmd = [hipcc, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp, *objs]
     subprocess.run(cmd, check=True)

@@ -178,6 +178,20 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
 int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *phi,
                    double tol, int maxit, int precond, apc_stats *st, hipStream_t s);
 int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s);
+
+// batches (batch.hip)
+int apc_build_batch_impl(const apc_params *P, int count, const double *const *xyz,
+                         const int64_t *N, hipStream_t s, apc_batch **out);
+void apc_destroy_batch_impl(apc_batch *B);
+apc_cloud *apc_batch_union(apc_batch *B);
+int apc_batch_info_impl(const apc_batch *B, apc_batch_info_t *info, int64_t *cN, int64_t *cn,
+                        int64_t *cnb);
+int apc_batch_configure_impl(apc_batch *B, int use_graph, int chunk, int spmv_div);
+int apc_batch_deposit_impl(apc_batch *B, const double *q, double *rho_M, double *rho_t, double tol,
+                           int maxit, apc_stats *st, hipStream_t s);
+int apc_batch_solve_impl(apc_batch *B, const double *rho_t, const double *g, double *phi,
+                         double tol, int maxit, int precond, apc_stats *st, hipStream_t s);
+int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, hipStream_t s);
 void apc_free_solver(apc_cloud *c);
 int apc_build_sell(apc_cloud *c, hipStream_t s);
 void apc_free_sell(apc_cloud *c);

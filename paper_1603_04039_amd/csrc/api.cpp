@@ -244,6 +244,71 @@ int apc_apply_precond(apc_cloud *c, int precond, const double *in, double *out,
   return apc_apply_precond_impl(c, precond, in, out, stream);
 }
 
+int apc_build_batch(const apc_params *p, int count, const double *const *xyz, const int64_t *N,
+                    hipStream_t stream, apc_batch **out) {
+  if (!p || count < 1 || !xyz || !N || !out) return APC_EINVAL;
+  *out = nullptr;
+  for (int c = 0; c < count; c++)
+    if (!xyz[c] || N[c] < 1) return APC_EINVAL;
+  return apc_build_batch_impl(p, count, xyz, N, stream, out);
+}
+
+int apc_batch_info(const apc_batch *b, apc_batch_info_t *info, int64_t *cloud_N,
+                   int64_t *cloud_n, int64_t *cloud_nb) {
+  if (!b) return APC_EINVAL;
+  return apc_batch_info_impl(b, info, cloud_N, cloud_n, cloud_nb);
+}
+
+int apc_batch_configure(apc_batch *b, int use_graph, int chunk, int spmv_div) {
+  if (!b || use_graph > 1 || chunk > 256 ||
+      !(spmv_div <= 0 || spmv_div == 1 || spmv_div == 2 || spmv_div == 4 || spmv_div == 8))
+    return APC_EINVAL;
+  return apc_batch_configure_impl(b, use_graph, chunk, spmv_div);
+}
+
+int apc_batch_tune(apc_batch *b, double tol, int *spmv_div, int *chunk, hipStream_t stream) {
+  if (!b || !(tol > 0.0)) return APC_EINVAL;
+  return apc_batch_tune_impl(b, tol, spmv_div, chunk, stream);
+}
+
+int apc_batch_assemble(apc_batch *b, hipStream_t stream) {
+  if (!b) return APC_EINVAL;
+  return apc_assemble_gfd(apc_batch_union(b), stream);
+}
+
+int apc_batch_deposit(apc_batch *b, const double *q, double *rho_M, double *rho_t, double tol,
+                      int maxit, apc_stats *st, hipStream_t stream) {
+  if (!b || !rho_t || !(tol > 0.0) || maxit < 1) return APC_EINVAL;
+  apc_cloud *u = apc_batch_union(b);
+  DeviceGuard g(u->device);
+  if (!g.ok) return APC_EHIP;
+  double *rm = rho_M;
+  if (!rm) HIPCHK(hipMallocAsync((void **)&rm, (size_t)(u->n + u->nb) * sizeof(double), stream));
+  const int rc = apc_batch_deposit_impl(b, q, rm, rho_t, tol, maxit, st, stream);
+  if (!rho_M) HIPCHK(hipFreeAsync(rm, stream));
+  return rc;
+}
+
+int apc_batch_solve(apc_batch *b, const double *rho_t, const double *g, double *phi, double tol,
+                    int maxit, int precond, apc_stats *st, hipStream_t stream) {
+  if (!b || !rho_t || !phi || !(tol > 0.0) || maxit < 1) return APC_EINVAL;
+  DeviceGuard gd(apc_batch_union(b)->device);
+  if (!gd.ok) return APC_EHIP;
+  return apc_batch_solve_impl(b, rho_t, g, phi, tol, maxit, precond, st, stream);
+}
+
+int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, double *grad_p,
+                                hipStream_t stream) {
+  if (!b) return APC_EINVAL;
+  return apc_interpolate_force(apc_batch_union(b), phi, phi_p, grad_p, stream);
+}
+
+void apc_batch_destroy(apc_batch *b) {
+  if (!b) return;
+  DeviceGuard g(apc_batch_union(b)->device);
+  apc_destroy_batch_impl(b);
+}
+
 void apc_destroy(apc_cloud *c) {
   if (!c) return;
   DeviceGuard g(c->device);

@@ -19,10 +19,9 @@
 #include <cstring>
 
 #include "apc_internal.h"
+#include "spmv_core.h"
 
 namespace {
-
-enum { V64 = 0, V32A32 = 1, V32A64 = 2 }; // value type / arithmetic of the SpMV
 
 struct Scal {
   double rho, alpha, omega, beta;
@@ -31,31 +30,6 @@ struct Scal {
   double tol;
   int it, maxit, done, pad;
 };
-
-struct Op {
-  const int32_t *off;
-  const int32_t *idx;
-  const double *w64;
-  const float *w32;
-  const double *hs; // nullptr => Laplacian
-  const int8_t *rk; // level of a uniform 2-ring row, -1 for a general row
-  double tc[3];     // shell weights of the uniform 2-ring at h_c = 1
-  double invL2;     // 1 / L^2: a level-l row scales tc by 4^l / L^2
-  int64_t n;
-  // sliced-ELL copy (the SpMV reads only this)
-  const int32_t *sl_rows, *sl_len, *sl_idx, *sl_tmpl;
-  const int64_t *sl_off;
-  const double *sl_w64;
-  const float *sl_w32;
-  int64_t cs[9];
-};
-
-
-__device__ __forceinline__ double wave_sum(double v) {
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-  return v;
-}
 
 // Reductions: kernels that produce dot products run on a capped grid of GRED
 // blocks (grid-stride) and store one partial per block; a one-block finalize
@@ -115,107 +89,9 @@ __device__ __forceinline__ void fin_sum(const double *part, unsigned G, double (
   }
 }
 
-// Slices (64 rows, one per wavefront) are grouped in 8 contiguous row chunks, one
-// per XCD (workgroups are dealt round-robin over the 8 XCDs): block b works on
-// chunk b mod 8, so neighbour gathers reuse that XCD's own L2.  Within a chunk
-// the XCD's wavefronts stride over its slices.  The slice index is made
-// wave-uniform (readfirstlane) so that the slice's offset, kind and length come
-// from scalar loads and its column-index loads issue at once.
-constexpr int SL = APC_SLICE;
-constexpr unsigned GSPMV = 4096; // <= 4 FIN_T (one load batch per finalize thread)
-struct SlIter {
-  int s, end, step;
-};
-__device__ __forceinline__ SlIter sl_iter(const Op &op) {
-  const int xcd = blockIdx.x & 7u, j = blockIdx.x >> 3;
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  SlIter it;
-  it.s = (int)op.cs[xcd] + j * (APC_BLOCK / 64) + wv;
-  it.end = (int)op.cs[xcd + 1];
-  it.step = (int)(gridDim.x >> 3) * (APC_BLOCK / 64);
-  return it;
-}
-static inline unsigned spmv_grid(const apc_cloud *c) {
-  int64_t mx = 0;
-  for (int k = 0; k < 8; k++) mx = (c->sl_cs[k + 1] - c->sl_cs[k]) > mx ? (c->sl_cs[k + 1] - c->sl_cs[k]) : mx;
-  int64_t per = (mx + (APC_BLOCK / 64) - 1) / (APC_BLOCK / 64);
-  if (per < 1) per = 1;
-  const int64_t g = 8 * per;
-  return (unsigned)(g < (int64_t)GSPMV ? g : (int64_t)GSPMV);
-}
 static inline unsigned vec_grid(int64_t n) {
   const unsigned g = grid_for(n);
   return g < GRED ? g : GRED;
-}
-
-// (A x)_row for the lane's row of slice s (row = -1 on padding lanes, result 0).
-// Uniform 2-ring slices hold 24 entries ordered by shell (6 at r = 1 cell, 12 at
-// sqrt 2, 6 at 2) and no weights: their index loads go out before the row id.
-// General slices run their entry loop unrolled by 8 so that 8 index/weight loads
-// and then 8 gathers are in flight together.
-template <int MODE>
-__device__ __forceinline__ double sell_apply(const Op &op, const double *__restrict__ x, int s_in,
-                                             int32_t &row) {
-  const int s = __builtin_amdgcn_readfirstlane(s_in);
-  const int lane = threadIdx.x & 63;
-  const int64_t off = op.sl_off[s] + lane;
-  const int32_t *__restrict__ ix = op.sl_idx + off;
-  double acc;
-  double xi;
-  if (op.sl_tmpl[s]) {
-    int32_t jj[24];
-#pragma unroll
-    for (int k = 0; k < 24; k++) jj[k] = ix[k * SL];
-    row = op.sl_rows[(int64_t)s * SL + lane];
-    if (row < 0) return 0.0;
-    xi = x[row];
-    const double scale = ldexp(op.invL2, 2 * (int)op.rk[row]);
-    if (MODE == V32A32) {
-      float a0 = 0.f, a1 = 0.f, a2 = 0.f;
-#pragma unroll
-      for (int k = 0; k < 24; k++) {
-        const float d = (float)(x[jj[k]] - xi);
-        if (k < 6) a0 += d; else if (k < 18) a1 += d; else a2 += d;
-      }
-      acc = (double)((float)op.tc[0] * a0 + (float)op.tc[1] * a1 + (float)op.tc[2] * a2) * scale;
-    } else {
-      double a0 = 0.0, a1 = 0.0, a2 = 0.0;
-#pragma unroll
-      for (int k = 0; k < 24; k++) {
-        const double d = x[jj[k]] - xi;
-        if (k < 6) a0 += d; else if (k < 18) a1 += d; else a2 += d;
-      }
-      const double c0 = MODE == V64 ? op.tc[0] : (double)(float)op.tc[0];
-      const double c1 = MODE == V64 ? op.tc[1] : (double)(float)op.tc[1];
-      const double c2 = MODE == V64 ? op.tc[2] : (double)(float)op.tc[2];
-      acc = (c0 * a0 + c1 * a1 + c2 * a2) * scale;
-    }
-  } else {
-    const int len = op.sl_len[s];
-    row = op.sl_rows[(int64_t)s * SL + lane];
-    if (row < 0) return 0.0;
-    xi = x[row];
-    if (MODE == V32A32) {
-      const float *__restrict__ wv = op.sl_w32 + off;
-      float af = 0.f;
-#pragma unroll 8
-      for (int k = 0; k < len; k++) af += wv[k * SL] * (float)(x[ix[k * SL]] - xi);
-      acc = (double)af;
-    } else if (MODE == V64) {
-      const double *__restrict__ wv = op.sl_w64 + off;
-      double ad = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < len; k++) ad += wv[k * SL] * (x[ix[k * SL]] - xi);
-      acc = ad;
-    } else {
-      const float *__restrict__ wv = op.sl_w32 + off;
-      double ad = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (x[ix[k * SL]] - xi);
-      acc = ad;
-    }
-  }
-  return op.hs ? xi + op.hs[row] * acc : acc;
 }
 
 // ---------------------------------------------------------------- BiCGSTAB kernels
@@ -554,28 +430,6 @@ static int ensure_ws(apc_cloud *c) {
   HIPCHK(hipEventCreate(&w->e0));
   HIPCHK(hipEventCreate(&w->e1));
   return APC_OK;
-}
-
-static Op make_op(const apc_cloud *c, bool density) {
-  Op op;
-  op.off = c->st_off;
-  op.idx = c->st_idx;
-  op.w64 = c->w64;
-  op.w32 = c->w32;
-  op.hs = density ? c->hscale : nullptr;
-  op.rk = c->rkind;
-  for (int k = 0; k < 3; k++) op.tc[k] = c->tmpl[k];
-  op.invL2 = 1.0 / (c->P.L * c->P.L);
-  op.n = c->n;
-  op.sl_rows = c->sl_rows;
-  op.sl_len = c->sl_len;
-  op.sl_idx = c->sl_idx;
-  op.sl_tmpl = c->sl_tmpl;
-  op.sl_off = c->sl_off;
-  op.sl_w64 = c->sl_w64;
-  op.sl_w32 = c->sl_w32;
-  for (int k = 0; k < 9; k++) op.cs[k] = c->sl_cs[k];
-  return op;
 }
 
 static int read_sc(apc_solver_ws *w, hipStream_t s) {

@@ -26,6 +26,11 @@ CONFIGS = {
 }
 
 
+# many clouds of uneven size: batch_specs(master_seed, count) gives each cloud's
+# N, sigma and halo fraction; all share the tree and fit parameters below
+BATCH = dict(master_seed=3, count=64, max_depth=8, order=2, c=0.35)
+
+
 def _core(rng: np.random.Generator, n: int, sigma) -> np.ndarray:
     sig = np.asarray(sigma, dtype=np.float64).reshape(3, 1)
     cen = np.asarray(CENTRE, dtype=np.float64).reshape(3, 1)
