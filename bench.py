@@ -84,6 +84,29 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="ja
     return ms, info, t_wall * 1000.0 / steps, last, phi
 
 
+def stream_probe(torch, mib=1024, reps=10):
+    """Device copy of `mib` MiB (torch's copy kernel): the bandwidth a plain
+    streaming kernel reaches here, and a kernel of known traffic (read + write
+    of `mib` MiB each) against which the HBM byte counters are scaled."""
+    n = mib * (1 << 20) // 8
+    src = torch.ones(n, dtype=torch.float64, device="cuda")
+    dst = torch.empty_like(src)
+    for _ in range(2):
+        dst.copy_(src)
+    stream = torch.cuda.current_stream()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        dst.copy_(src)
+    e1.record(stream)
+    e1.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del src, dst
+    return dict(bytes=2 * n * 8, avg_us=round(ms * 1e3, 2),
+                GBs=round(2 * n * 8 / (ms * 1e-3) / 1e9, 1))
+
+
 def precond_roofline(torch, cloud, reps):
     """Average duration of the learned M apply (k_prec_apply), same method."""
     stream = torch.cuda.current_stream()
@@ -113,6 +136,30 @@ def precond_roofline(torch, cloud, reps):
                 bytes_per_launch=int(byts))
 
 
+def counted_traffic(name="k_apply_beam_halo_1e7_hbm_counters.md"):
+    """HBM bytes per launch of the SpMV from the committed rocprofv3 --pmc summary
+    (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel factor), or None when
+    the summary is missing or the SpMV's sources changed since it was taken."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", name)
+    if not os.path.exists(path):
+        return None
+    kv = {}
+    for line in open(path):
+        if ":" in line and not line.startswith(("#", "|", "`")):
+            k, v = line.split(":", 1)
+            kv[k.strip()] = v.strip()
+    try:
+        h = hashlib.sha256()
+        for src in kv["sources"].split():
+            h.update(open(os.path.join(ROOT, src), "rb").read())
+        if h.hexdigest()[:16] != kv["source_sha256_16"]:
+            return None
+        return float(kv["traffic_bytes_per_launch"])
+    except (KeyError, OSError, ValueError):
+        return None
+
+
 def spmv_roofline(torch, cloud, reps, mixed):
     """Average duration of the operator SpMV (the solver's dominant kernel) over
     `reps` back-to-back launches, HIP events on the library's stream."""
@@ -137,8 +184,10 @@ def spmv_roofline(torch, cloud, reps, mixed):
     byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["nnz_general"] * (4 + vbytes)
             + n * (4 + 8 + 8))
     gbs = byts / (ms * 1e-3) / 1e9
+    traffic = counted_traffic() if mixed else None
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
+                frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=None if traffic is None else round(traffic), traffic_unit="bytes/launch",
                 kernel="k_apply<%s> (sliced-ELL operator SpMV)" % ("V32A64" if mixed else "V64"),
                 avg_us=round(ms * 1e3, 2), bytes_per_launch=int(byts),
                 uniform_rows=oi["n_uniform"], sell_entries=oi["sell_entries"])
@@ -289,6 +338,7 @@ def main():
     value = info["n"] / t_metric
     log(f"{args.precision}/{args.precond}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
     roof = spmv_roofline(torch, cloud, args.spmv_reps, prec != apc.APC_FP64)
+    roof["stream_copy"] = stream_probe(torch)
     log(f"spmv roofline: {roof}")
     roof_m = None
     if args.precond == "learned":

@@ -538,11 +538,19 @@ __global__ void __launch_bounds__(APC_BLOCK)
   }
 }
 
-// smallest uniform 2-ring row of each level
+// smallest uniform 2-ring row of each level: minimum per block in LDS, then one
+// global atomic per level and block (all rows of a level would otherwise contend
+// for one address)
 __global__ void __launch_bounds__(APC_BLOCK)
     k_rep_rows(const int8_t *__restrict__ rk, int64_t n, int32_t *__restrict__ rep) {
+  __shared__ int32_t bmin[APC_MAX_LEVELS];
+  if (threadIdx.x < APC_MAX_LEVELS) bmin[threadIdx.x] = INT_MAX;
+  __syncthreads();
   const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
-  if (i < n && rk[i] >= 0) atomicMin(&rep[rk[i]], (int32_t)i);
+  if (i < n && rk[i] >= 0) atomicMin(&bmin[rk[i]], (int32_t)i);
+  __syncthreads();
+  if (threadIdx.x < APC_MAX_LEVELS && bmin[threadIdx.x] != INT_MAX)
+    atomicMin(&rep[threadIdx.x], bmin[threadIdx.x]);
 }
 
 // rep (APC_MAX_LEVELS, INT_MAX = none) -> one slice of rows (-1 padded); template rows zeroed
