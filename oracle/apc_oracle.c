@@ -212,6 +212,7 @@ struct apco_cloud {
   int32_t *bidx; /* 6*n: boundary node index of (node, face) or -1 */
   int32_t *r1off, *r1;
   int32_t *st_off, *st, *st_ring;
+  int8_t *node_order; /* GFD order of each node's row: the cloud's k, or 2 (fallback) */
 };
 
 static uint64_t morton(uint64_t x, uint64_t y, uint64_t z, int bits) {
@@ -350,14 +351,18 @@ static int in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
 
 /* Stencil choice from a candidate ring sorted by (r^2, index) -- the quadrant
    criterion of Sec. 3.1 read for 3-D octants: first the two nearest candidates of
-   every closed octant, then the nearest remaining candidates, until
+   every closed octant, then (order 4 only) for each axis in turn the nearest
+   candidates with a new offset along that axis until the axis has 5 distinct
+   offsets counting the centre's 0 (on fewer planes a degree-4 polynomial
+   vanishes on the whole stencil), then the nearest remaining candidates, until
    min(count, m_cap) nodes are chosen; the chosen set is kept in candidate order.
    It is accepted when (i) every closed octant holds at least one chosen node,
    (ii) m >= p + 1 and (iii) the weighted V0 has full column rank:
    min|R_ii| / max|R_ii| >= 1e-6.  Returns m (>0) on acceptance, 0 otherwise; the
    chosen candidates are compacted to the front of cd. */
 #define TAU_RANK 1e-6
-static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cnt, int m_cap) {
+static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cnt, int m_cap,
+                          int order) {
   const int32_t *c0 = &C->crd[3 * y];
   int64_t want = cnt < m_cap ? cnt : m_cap;
   static unsigned char pick[1 << 20];
@@ -376,6 +381,32 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
       }
     }
   }
+  for (int d = 0; order == 4 && d < 3; d++) {
+    for (;;) {
+      int64_t vals[MAXM + 1];
+      int nv = 1;
+      vals[0] = 0;
+      for (int64_t j = 0; j < cnt; j++) {
+        if (!pick[j]) continue;
+        int64_t o = (int64_t)C->crd[3 * cd[j].idx + d] - c0[d];
+        int seen = 0;
+        for (int q = 0; q < nv; q++) seen |= vals[q] == o;
+        if (!seen && nv <= MAXM) vals[nv++] = o;
+      }
+      if (nv >= 5 || got >= want) break;
+      int64_t add = -1;
+      for (int64_t j = 0; j < cnt && add < 0; j++) {
+        if (pick[j]) continue;
+        int64_t o = (int64_t)C->crd[3 * cd[j].idx + d] - c0[d];
+        int seen = 0;
+        for (int q = 0; q < nv; q++) seen |= vals[q] == o;
+        if (!seen) add = j;
+      }
+      if (add < 0) break;
+      pick[add] = 1;
+      got++;
+    }
+  }
   for (int64_t j = 0; j < cnt && got < want; j++)
     if (!pick[j]) {
       pick[j] = 1;
@@ -384,7 +415,7 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
   int m = 0;
   for (int64_t j = 0; j < cnt; j++)
     if (pick[j]) cd[m++] = cd[j];
-  if (m < C->p + 1 || m > MAXM) return 0;
+  if (m < apco_num_unknowns(order) + 1 || m > MAXM) return 0;
   int oct[8] = {0};
   double dx[MAXM], dy[MAXM], dz[MAXM];
   for (int j = 0; j < m; j++) {
@@ -399,7 +430,7 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
     if (oct[o] < 1) return 0;
   static double X[MAXP * MAXM];
   double h, ratio;
-  wls_core(C->P.order, m, dx, dy, dz, X, &h, &ratio);
+  wls_core(order, m, dx, dy, dz, X, &h, &ratio);
   return ratio >= TAU_RANK ? m : 0;
 }
 
@@ -419,6 +450,7 @@ void apco_destroy(apco_cloud *C) {
   free(C->st_off);
   free(C->st);
   free(C->st_ring);
+  free(C->node_order);
   free(C);
 }
 
@@ -641,17 +673,20 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
 
   /* Stencils (Sec. 4.3): the R-ring = nodes within R face-adjacency steps
      (boundary nodes hang off their owner), sorted by (integer squared distance,
-     node index); a stencil is chosen from ring_min upward until one is accepted;
-     past ring_max the build fails. */
+     node index); a stencil is chosen from ring_min upward until one is accepted.
+     Order fallback (k = 4 only): a node with no acceptable order-4 stencil up to
+     ring_max takes an order-2 row, chosen by the order-2 rule from ring 2 with
+     m_cap 40.  Past ring_max at order 2 the build fails. */
   int64_t ntot = n + nb;
   int32_t *stamp = malloc((size_t)ntot * sizeof(int32_t));
   int32_t *front = malloc((size_t)ntot * sizeof(int32_t));
   cand_t *cand = malloc((size_t)ntot * sizeof(cand_t));
   C->st_off = malloc((size_t)(n + 1) * sizeof(int32_t));
   C->st_ring = malloc((size_t)(n + 1) * sizeof(int32_t));
+  C->node_order = malloc((size_t)(n + 1));
   int64_t stcap = n * 32 + 64;
   C->st = malloc((size_t)stcap * sizeof(int32_t));
-  if (!stamp || !front || !cand || !C->st_off || !C->st_ring || !C->st) {
+  if (!stamp || !front || !cand || !C->st_off || !C->st_ring || !C->st || !C->node_order) {
     free(stamp);
     free(front);
     free(cand);
@@ -664,7 +699,11 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
   for (int64_t y = 0; y < n && !rc; y++) {
     C->st_off[y] = (int32_t)ne;
     int done = 0;
-    for (int R = P->ring_min; R <= P->ring_max && !done; R++) {
+    for (int att = 0; att < 2 && !done; att++) {
+    const int ko = att == 0 ? P->order : 2;
+    if (att == 1 && P->order != 4) break;
+    const int rmin = att == 0 ? P->ring_min : 2, mcap = att == 0 ? P->m_cap : 40;
+    for (int R = rmin; R <= P->ring_max && !done; R++) {
       /* depth-limited BFS */
       int64_t nf = 0, cnt = 0;
       stamp[y] = (int32_t)y;
@@ -704,7 +743,7 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
       /* reset stamps for the next ring size of this node */
       for (int64_t t = 0; t < nf; t++) stamp[front[t]] = -1;
       qsort(cand, (size_t)cnt, sizeof(cand_t), cmp_cand);
-      int m = choose_stencil(C, (int32_t)y, cand, cnt, P->m_cap);
+      int m = choose_stencil(C, (int32_t)y, cand, cnt, mcap, ko);
       if (m > 0) {
         if (ne + m > stcap) {
           stcap = 2 * stcap + m;
@@ -717,8 +756,10 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
         }
         for (int j = 0; j < m; j++) C->st[ne++] = cand[j].idx;
         C->st_ring[y] = R;
+        C->node_order[y] = (int8_t)ko;
         done = 1;
       }
+    }
     }
     if (!done && !rc) rc = APCO_ESTENCIL;
   }
@@ -798,7 +839,7 @@ int apco_ring1(const apco_cloud *C, int32_t *off, int32_t *idx, int64_t cap) {
 
 /* ------------------------------------------------------------------ */
 /* Per-node fit on the cloud's stencil, in integer units. */
-static int node_fit(const apco_cloud *C, int64_t y, double *X, int *m, double *hphys) {
+static int node_fit(const apco_cloud *C, int64_t y, double *X, int *m, double *hphys, int *pk) {
   int32_t a = C->st_off[y], b = C->st_off[y + 1];
   *m = b - a;
   double dx[MAXM], dy[MAXM], dz[MAXM];
@@ -809,7 +850,9 @@ static int node_fit(const apco_cloud *C, int64_t y, double *X, int *m, double *h
     dz[j] = (double)(C->crd[3 * v + 2] - C->crd[3 * y + 2]);
   }
   double h, ratio;
-  int rc = wls_core(C->P.order, *m, dx, dy, dz, X, &h, &ratio);
+  const int ko = C->node_order[y];
+  *pk = apco_num_unknowns(ko);
+  int rc = wls_core(ko, *m, dx, dy, dz, X, &h, &ratio);
   if (rc) return rc;
   if (ratio < TAU_RANK) return APCO_ESTENCIL;
   *hphys = h * C->unit;
@@ -832,9 +875,9 @@ int apco_assemble(const apco_cloud *C, double *w, double *diag) {
       izz = find_alpha(al, p, 0, 0, 2);
   static double X[MAXP * MAXM];
   for (int64_t y = 0; y < C->n; y++) {
-    int m;
+    int m, pk;
     double hp;
-    int rc = node_fit(C, y, X, &m, &hp);
+    int rc = node_fit(C, y, X, &m, &hp, &pk);
     if (rc) return rc;
     double s = 0.0;
     int32_t a = C->st_off[y];
@@ -859,14 +902,15 @@ int apco_density_rows(const apco_cloud *C, double *bw, double *bdiag) {
   int32_t al[3 * MAXP];
   apco_monomials(C->P.order, al);
   static double X[MAXP * MAXM];
+  (void)p;
   for (int64_t y = 0; y < C->n; y++) {
-    int m;
+    int m, pk;
     double hp;
-    int rc = node_fit(C, y, X, &m, &hp);
+    int rc = node_fit(C, y, X, &m, &hp, &pk);
     if (rc) return rc;
     double hc = C->P.L / ldexp(1.0, C->cells[C->node_cell[y]].level);
     double coef[MAXP];
-    for (int i = 0; i < p; i++) {
+    for (int i = 0; i < pk; i++) {
       const int32_t *a = &al[3 * i];
       coef[i] = 0.0;
       if ((a[0] | a[1] | a[2]) & 1) continue;
@@ -878,7 +922,7 @@ int apco_density_rows(const apco_cloud *C, double *bw, double *bdiag) {
     int32_t a0 = C->st_off[y];
     for (int j = 0; j < m; j++) {
       double v = 0.0;
-      for (int i = 0; i < p; i++) v += coef[i] * X[i * m + j];
+      for (int i = 0; i < pk; i++) v += coef[i] * X[i * m + j];
       bw[a0 + j] = v;
       s += v;
     }
@@ -1149,12 +1193,13 @@ int apco_node_derivs(const apco_cloud *C, const double *f, double *Dout) {
   apco_monomials(C->P.order, al);
   static double X[MAXP * MAXM];
   for (int64_t y = 0; y < C->n; y++) {
-    int m;
+    int m, pk;
     double hp;
-    int rc = node_fit(C, y, X, &m, &hp);
+    int rc = node_fit(C, y, X, &m, &hp, &pk);
     if (rc) return rc;
     int32_t a = C->st_off[y];
-    for (int i = 0; i < p; i++) {
+    for (int i = pk; i < p; i++) Dout[y * p + i] = 0.0; /* order-2 fallback rows */
+    for (int i = 0; i < pk; i++) {
       double s = 0.0;
       for (int j = 0; j < m; j++) s += X[i * m + j] * (f[C->st[a + j]] - f[y]);
       Dout[y * p + i] = s / ipow(hp, al[3 * i] + al[3 * i + 1] + al[3 * i + 2]);
@@ -1451,5 +1496,10 @@ int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, i
     for (int p = 1; p <= m; p++) mw[a + p - 1] *= al;
   }
   free(w); free(d); free(feat); free(o); free(ixyz); free(U);
+  return 0;
+}
+
+int apco_node_orders(const apco_cloud *C, int8_t *ord) {
+  memcpy(ord, C->node_order, (size_t)C->n);
   return 0;
 }

@@ -69,6 +69,9 @@ int apco_info(const apco_cloud *C, int64_t *n, int64_t *nb, int64_t *nnz, int64_
 int apco_get_nodes(const apco_cloud *C, int64_t *perm, uint64_t *code, int32_t *level,
                    int64_t *first, int64_t *count, int32_t *bowner, int32_t *bface,
                    int32_t *st_off, int32_t *st_idx, int32_t *st_ring);
+/* GFD order of each interior node's row (n int8): the cloud's k, or 2 where a
+   k = 4 cloud found no acceptable order-4 stencil (order fallback). */
+int apco_node_orders(const apco_cloud *C, int8_t *ord);
 /* Integer coordinates of all n+nb nodes, 3 x (n+nb) SoA. */
 int apco_node_coords(const apco_cloud *C, int32_t *ixyz);
 /* All cells of the queue Q in creation order: level, integer index (3), particle count,

@@ -49,6 +49,7 @@ def _load():
     lib.apco_info.argtypes = [P] + [ct.POINTER(ct.c_int64)] * 5
     lib.apco_get_nodes.argtypes = [P] * 11
     lib.apco_node_coords.argtypes = [P, P]
+    lib.apco_node_orders.argtypes = [P, P]
     lib.apco_get_cells.argtypes = [P] * 5
     lib.apco_ring1.argtypes = [P, P, P, ct.c_int64]
     lib.apco_wls_fit.argtypes = [ct.c_int, ct.c_int, P, P, P, P]
@@ -197,6 +198,11 @@ class OracleCloud:
                                           ["perm", "code", "level", "first", "count", "bowner",
                                            "bface", "st_off", "st_idx", "st_ring"]])
         return out
+
+    def node_orders(self) -> np.ndarray:
+        o = np.zeros(self.n, np.int8)
+        _check(self.lib.apco_node_orders(self.h, _ptr(o)), "node_orders")
+        return o
 
     def coords(self) -> np.ndarray:
         a = np.zeros((3, self.n + self.nb), np.int32)

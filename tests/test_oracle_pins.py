@@ -544,3 +544,37 @@ def test_direct_summation_far_field(oracle_mod):
     ex = direct(pos[:, :C.n][:, far])
     rel = np.linalg.norm(phi[:C.n][far] - ex) / np.linalg.norm(ex)
     assert rel < 0.03, rel
+
+
+def test_k4_adaptive_cloud_rows(oracle_mod):
+    """k = 4 on an adaptive beam cloud (Sec. 3.1, Sec. 4.3): every row of order 4
+    is exact on quartics, every order-2 fallback row on quadratics; order-4
+    stencils span 5 distinct offsets along each axis (the centre's 0 included);
+    the fallback stays rare."""
+    rng = np.random.default_rng(12)
+    xyz = beam_halo(50000, seed=32)
+    C = oracle_mod.OracleCloud(xyz, order=4, c=0.05, max_depth=6)
+    orders = C.node_orders()
+    assert set(np.unique(orders)) <= {2, 4}
+    n2 = int((orders == 2).sum())
+    assert n2 <= C.n // 1000 + 1
+    nd = C.nodes()
+    off, idx = nd["st_off"], nd["st_idx"]
+    crd = C.coords()
+    for i in np.where(orders == 4)[0][:: max(1, C.n // 2000)]:
+        d = crd[:, idx[off[i]:off[i + 1]]] - crd[:, [i]]
+        for ax in range(3):
+            assert len(set(d[ax].tolist()) | {0}) >= 5
+    pos = C.positions()
+    for deg, sel in ((4, orders == 4), (2, orders == 2)):
+        if not sel.any():
+            continue
+        P = rand_poly(rng, deg)
+        f = poly_eval(P, *pos)
+        lap = {}
+        for a in ((2, 0, 0), (0, 2, 0), (0, 0, 2)):
+            for b, v in poly_deriv(P, a).items():
+                lap[b] = lap.get(b, 0.0) + v
+        want = poly_eval(lap, *pos[:, :C.n])[sel]
+        got = C.apply_laplacian(f)[sel]
+        assert np.abs(got - want).max() <= 1e-7 * max(1.0, np.abs(want).max())
