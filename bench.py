@@ -136,12 +136,12 @@ def precond_roofline(torch, cloud, reps):
                 bytes_per_launch=int(byts))
 
 
-def counted_traffic(name="k_apply_beam_halo_1e7_hbm_counters.md"):
+def counted_traffic(workload):
     """HBM bytes per launch of the SpMV from the committed rocprofv3 --pmc summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel factor), or None when
     the summary is missing or the SpMV's sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", name)
+    path = os.path.join(ROOT, "profiles", f"k_apply_{workload}_hbm_counters.md")
     if not os.path.exists(path):
         return None
     kv = {}
@@ -160,7 +160,7 @@ def counted_traffic(name="k_apply_beam_halo_1e7_hbm_counters.md"):
         return None
 
 
-def spmv_roofline(torch, cloud, reps, mixed):
+def spmv_roofline(torch, cloud, reps, mixed, workload):
     """Average duration of the operator SpMV (the solver's dominant kernel) over
     `reps` back-to-back launches, HIP events on the library's stream."""
     stream = torch.cuda.current_stream()
@@ -184,7 +184,7 @@ def spmv_roofline(torch, cloud, reps, mixed):
     byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["nnz_general"] * (4 + vbytes)
             + n * (4 + 8 + 8))
     gbs = byts / (ms * 1e-3) / 1e9
-    traffic = counted_traffic() if mixed else None
+    traffic = counted_traffic(workload) if mixed else None
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
                 frac=round(gbs / HBM_PEAK_GBS, 4),
                 traffic=None if traffic is None else round(traffic), traffic_unit="bytes/launch",
@@ -337,7 +337,7 @@ def main():
     t_metric = (ms["assemble"] + ms["install"] + ms["solve"]) * 1e-3
     value = info["n"] / t_metric
     log(f"{args.precision}/{args.precond}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
-    roof = spmv_roofline(torch, cloud, args.spmv_reps, prec != apc.APC_FP64)
+    roof = spmv_roofline(torch, cloud, args.spmv_reps, prec != apc.APC_FP64, args.workload)
     roof["stream_copy"] = stream_probe(torch)
     log(f"spmv roofline: {roof}")
     roof_m = None

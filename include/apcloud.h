@@ -187,6 +187,11 @@ int apc_node_derivs(apc_cloud *c, const double *f, double *D, hipStream_t stream
 /* Apply the assembled operator: out[i] = (L f)_i for interior i; f: n+nb. */
 int apc_apply_operator(apc_cloud *c, const double *f, double *out, hipStream_t stream);
 
+/* GFD order of every interior node's row into host memory (n int8): the cloud's
+   k, or 2 where a k = 4 cloud found no acceptable order-4 stencil up to ring_max
+   and the node took an order-2 row instead (order fallback, Sec. 4.3 reading). */
+int apc_get_node_orders(const apc_cloud *c, int8_t *order_host);
+
 /* ---- learned preconditioner (a grown form beside the paper's method) ----
    Row i of M has the pattern of row i of the Poisson operator: J_0 = i and J_p the
    p-th stencil node (p = 1..m, m <= 40; boundary nodes carry weight 0), and is

@@ -357,10 +357,12 @@ static int in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
    vanishes on the whole stencil), then the nearest remaining candidates, until
    min(count, m_cap) nodes are chosen; the chosen set is kept in candidate order.
    It is accepted when (i) every closed octant holds at least one chosen node,
-   (ii) m >= p + 1 and (iii) the weighted V0 has full column rank:
-   min|R_ii| / max|R_ii| >= 1e-6.  Returns m (>0) on acceptance, 0 otherwise; the
-   chosen candidates are compacted to the front of cd. */
+   (ii) m >= p + 1, (iii) the weighted V0 has full column rank:
+   min|R_ii| / max|R_ii| >= 1e-6, and (iv, order 4) its Laplacian row has a
+   negative diagonal d and sum |w_j| <= 10 |d|.  Returns m (>0) on acceptance, 0
+   otherwise; the chosen candidates are compacted to the front of cd. */
 #define TAU_RANK 1e-6
+#define TAU_DOM 10.0
 static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cnt, int m_cap,
                           int order) {
   const int32_t *c0 = &C->crd[3 * y];
@@ -431,7 +433,20 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
   static double X[MAXP * MAXM];
   double h, ratio;
   wls_core(order, m, dx, dy, dz, X, &h, &ratio);
-  return ratio >= TAU_RANK ? m : 0;
+  if (!(ratio >= TAU_RANK)) return 0;
+  if (order == 4) {
+    /* stability of the order-4 Laplacian row: a negative diagonal and off-diagonal
+       weights of total magnitude at most TAU_DOM times the diagonal's (scale-free:
+       h cancels); otherwise the node falls back to an order-2 row */
+    double s = 0.0, sa = 0.0;
+    for (int j = 0; j < m; j++) {
+      double v = X[3 * m + j] + X[6 * m + j] + X[8 * m + j];
+      s += v;
+      sa += fabs(v);
+    }
+    if (!(s > 0.0 && sa <= TAU_DOM * s)) return 0;
+  }
+  return m;
 }
 
 void apco_destroy(apco_cloud *C) {

@@ -25,7 +25,7 @@ LEARN_QUAD = MLP_OUT * (MLP_OUT + 1) // 2 + MLP_OUT + 1
 
 # every symbol declared in include/apcloud.h
 EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_nodes",
-           "apc_assemble_gfd", "apc_get_operator", "apc_operator_info", "apc_deposit", "apc_density_solve",
+           "apc_assemble_gfd", "apc_get_operator", "apc_get_node_orders", "apc_operator_info", "apc_deposit", "apc_density_solve",
            "apc_solve", "apc_interpolate_force", "apc_node_derivs", "apc_apply_operator",
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
@@ -84,6 +84,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_assemble_gfd.argtypes = [P, P]
     lib.apc_get_operator.argtypes = [P, P, P]
     lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 3
+    lib.apc_get_node_orders.argtypes = [P, P]
     lib.apc_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, ct.POINTER(Stats), P]
@@ -188,6 +189,7 @@ class Cloud:
         self.L = self.params.L
         self.lo = np.array(self.params.lo[:])
         self.max_depth = self.params.max_depth
+        self.p = 9 if self.params.order == 2 else 34
         self.unit = self.L / 2.0 ** (self.max_depth + 1)
         self.assembled = False
 
@@ -212,6 +214,12 @@ class Cloud:
                  "st_idx", "ixyz"]]
         _check(self.lib.apc_get_nodes(self.h, *ptrs), "apc_get_nodes")
         return out
+
+    def node_orders(self):
+        o = np.zeros(self.n, np.int8)
+        _check(self.lib.apc_get_node_orders(self.h, o.ctypes.data_as(ct.c_void_p)),
+               "apc_get_node_orders")
+        return o
 
     def positions(self):
         return self.lo[:, None] + self.unit * self.nodes()["ixyz"].astype(np.float64)
@@ -281,7 +289,7 @@ class Cloud:
 
     def node_derivs(self, f, stream=None):
         import torch
-        D = torch.empty((self.n, 9), dtype=torch.float64, device="cuda")
+        D = torch.empty((self.n, self.p), dtype=torch.float64, device="cuda")
         _check(self.lib.apc_node_derivs(self.h, _dptr(f, torch.float64, self.n + self.nb),
                                         _dptr(D), _stream(stream)), "apc_node_derivs")
         return D

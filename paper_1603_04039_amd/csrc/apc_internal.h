@@ -11,6 +11,7 @@
 #define APC_MAXM 64      // hard stencil cap: one wavefront
 #define APC_RING_CAP 2048 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
+#define APC_TAU_DOM 10.0  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
 #define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
 #define APC_TAU_FP32 0.1
 #define APC_MAX_LEVELS 24 // > max_depth (<= 20): per-level tables  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
@@ -115,12 +116,16 @@ struct apc_cloud {
   int32_t *crd = nullptr; // 3 x (n+nb) SoA integer coordinates
   int32_t *bowner = nullptr, *bface = nullptr;
   int32_t *st_off = nullptr, *st_idx = nullptr; // stencil CSR
+  int8_t *rorder = nullptr; // n: GFD order of each row (k, or 2 for a k = 4 fallback row)
   // operator
   bool assembled = false;
   double *w64 = nullptr; // nnz (APC_FP64)
   float *w32 = nullptr;  // nnz (APC_MIXED)
   double *diag = nullptr, *inv_diag = nullptr; // n
-  double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator)
+  double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator, k = 2)
+  // k = 4: density operator rows (B has its own weights; row sums are 1)
+  double *bw64 = nullptr, *sl_bw64 = nullptr;
+  float *bw32 = nullptr, *sl_bw32 = nullptr;
   uint8_t *fp64row = nullptr;                  // n (APC_MIXED): refitted in FP64
   int64_t n_fp64_rows = 0;
   apc_asm_scratch *scratch = nullptr;
@@ -170,6 +175,12 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
 int apc_apply_precond_impl(apc_cloud *c, int precond, const double *in, double *out,
                            hipStream_t s);
 int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s);
+// k = 4 (gfd4.hip)
+int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t np,
+                    const int32_t *cand, int32_t *m, hipStream_t s);
+int apc_assemble4(apc_cloud *c, hipStream_t s);
+int apc_node_derivs4(apc_cloud *c, const double *f, double *D, hipStream_t s);
+int apc_interp4(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, hipStream_t s);
 int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
                     hipStream_t s);
 int apc_deposit_impl(apc_cloud *c, const double *q, double *rho_M, hipStream_t s);
@@ -196,5 +207,5 @@ void apc_free_solver(apc_cloud *c);
 int apc_build_sell(apc_cloud *c, hipStream_t s);
 void apc_free_sell(apc_cloud *c);
 // stencil rank test of pending nodes (k = 2); clears m[y] of rejected nodes
-int apc_rank_check(const apc_cloud *c, const int32_t *pending, int64_t np, const int32_t *cand,
-                   int32_t *m, hipStream_t s);
+int apc_rank_check(const apc_cloud *c, int order, const int32_t *pending, int64_t np,
+                   const int32_t *cand, int32_t *m, hipStream_t s);

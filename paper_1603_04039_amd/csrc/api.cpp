@@ -139,6 +139,14 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host) {
   return APC_OK;
 }
 
+int apc_get_node_orders(const apc_cloud *c, int8_t *order_host) {
+  if (!c || !order_host) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  if (c->n > 0) HIPCHK(hipMemcpy(order_host, c->rorder, (size_t)c->n, hipMemcpyDeviceToHost));
+  return APC_OK;
+}
+
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
                       int64_t *sell_entries) {
   if (!c || !c->assembled) return APC_EINVAL;
@@ -248,6 +256,7 @@ int apc_build_batch(const apc_params *p, int count, const double *const *xyz, co
                     hipStream_t stream, apc_batch **out) {
   if (!p || count < 1 || !xyz || !N || !out) return APC_EINVAL;
   *out = nullptr;
+  if (p->order != 2) return APC_EINVAL; // the union carries k = 2 operators only
   for (int c = 0; c < count; c++)
     if (!xyz[c] || N[c] < 1) return APC_EINVAL;
   return apc_build_batch_impl(p, count, xyz, N, stream, out);

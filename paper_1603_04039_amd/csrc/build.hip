@@ -275,13 +275,15 @@ __device__ inline bool in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
 
 // Stencil of node y from its R-ring (nodes within R face-adjacency steps, boundary
 // nodes hanging off their owner): candidates sorted by (squared integer distance,
-// node index); the two nearest of every closed octant are chosen first, then the
-// nearest remaining ones up to min(count, m_cap).  Accepted (m > 0) when every
-// closed octant holds a chosen node and m >= p + 1; the rank test follows in a
-// separate kernel.  One thread per pending node; the ring lives in a per-thread
-// slice of global scratch.
+// node index); the two nearest of every closed octant are chosen first; for an
+// order-4 row then, axis by axis, the nearest candidates with a new offset along
+// the axis until it spans 5 distinct offsets (the centre's 0 included; on fewer
+// planes a quartic vanishes on the whole stencil); then the nearest remaining ones
+// up to min(count, m_cap).  Accepted (m > 0) when every closed octant holds a
+// chosen node and m >= p + 1; the rank test follows in a separate kernel.  One
+// thread per pending node; the ring lives in a per-thread slice of global scratch.
 __global__ void __launch_bounds__(APC_BLOCK)
-    k_stencil(const int32_t *__restrict__ pending, int64_t np, int R, int m_cap, int p,
+    k_stencil(const int32_t *__restrict__ pending, int64_t np, int R, int m_cap, int p, int order,
               const int32_t *__restrict__ crd, int64_t ntot, int64_t n,
               const int32_t *__restrict__ r1cnt, const int32_t *__restrict__ r1,
               const int32_t *__restrict__ bowner, int32_t *__restrict__ lst_all,
@@ -368,6 +370,34 @@ __global__ void __launch_bounds__(APC_BLOCK)
       }
     }
   }
+  for (int d = 0; order == 4 && d < 3; d++) {
+    const int32_t *cd = crd + (int64_t)d * ntot;
+    const int64_t c0 = d == 0 ? cy0 : (d == 1 ? cy1 : cy2);
+    for (;;) {
+      int64_t vals[5];
+      int nv = 1;
+      vals[0] = 0;
+      for (int j = 1; j < cnt && nv < 5; j++) {
+        if (lst[j] >= 0) continue;
+        const int64_t o = cd[-lst[j] - 1] - c0;
+        bool seen = false;
+        for (int q = 0; q < nv; q++) seen = seen || vals[q] == o;
+        if (!seen) vals[nv++] = o;
+      }
+      if (nv >= 5 || got >= want) break;
+      int add = -1;
+      for (int j = 1; j < cnt && add < 0; j++) {
+        if (lst[j] < 0) continue;
+        const int64_t o = cd[lst[j]] - c0;
+        bool seen = false;
+        for (int q = 0; q < nv; q++) seen = seen || vals[q] == o;
+        if (!seen) add = j;
+      }
+      if (add < 0) break;
+      lst[add] = -lst[add] - 1;
+      got++;
+    }
+  }
   for (int j = 1; j < cnt && got < want; j++)
     if (lst[j] >= 0) {
       lst[j] = -lst[j] - 1;
@@ -392,7 +422,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
 __global__ void __launch_bounds__(APC_BLOCK)
     k_accept(const int32_t *__restrict__ pending, int64_t np, const int32_t *__restrict__ cand,
              const int32_t *__restrict__ m, int32_t *__restrict__ stbuf,
-             int32_t *__restrict__ mnode, int32_t *__restrict__ still) {
+             int32_t *__restrict__ mnode, int32_t *__restrict__ still, int order,
+             int8_t *__restrict__ rorder) {
   int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (t >= np) return;
   const int32_t y = pending[t];
@@ -400,6 +431,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   still[t] = mm > 0 ? 0 : 1;
   if (mm <= 0) return;
   mnode[y] = mm;
+  rorder[y] = (int8_t)order;
   for (int j = 0; j < mm; j++) stbuf[(int64_t)y * APC_MAXM + j] = cand[t * APC_MAXM + j];
 }
 
@@ -505,7 +537,8 @@ void apc_free_cloud(apc_cloud *c) {
   apc_free_sell(c);
   free_cloud_arrays(c);
   void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row, c->rkind, c->scratch,
-                 c->m_diag, c->m_sell, c->m_tmpl};
+                 c->m_diag, c->m_sell, c->m_tmpl, c->bw64, c->bw32, c->sl_bw64, c->sl_bw32,
+                 c->rorder};
   for (void *q : ops)
     if (q) (void)hipFree(q);
   delete c;
@@ -658,17 +691,25 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   APCCHK(dalloc(&still, n, s));
   APCCHK(dalloc(&soff, n, s));
   APCCHK(dalloc(&npend, n, s));
-  for (int R = P.ring_min; R <= P.ring_max && np > 0; R++) {
+  // order fallback (k = 4): nodes with no acceptable order-4 stencil up to ring_max
+  // take an order-2 row, chosen by the order-2 rule from ring 2 with cap 40
+  HIPCHK(hipMalloc((void **)&c->rorder, (size_t)(n > 0 ? n : 1)));
+  for (int att = 0; att < 2 && np > 0; att++) {
+  if (att == 1 && P.order != 4) break;
+  const int ko = att == 0 ? P.order : 2;
+  const int pk = ko == 2 ? 9 : 34;
+  const int rmin = att == 0 ? P.ring_min : 2, mcap = att == 0 ? P.m_cap : 40;
+  for (int R = rmin; R <= P.ring_max && np > 0; R++) {
     HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
     for (int64_t c0 = 0; c0 < np; c0 += CH) {
       const int64_t cn = (np - c0) < CH ? (np - c0) : CH;
       hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, R,
-                         P.m_cap, c->p, c->crd, ntot, n, r1cnt, r1, c->bowner, lst, key, cand, mch,
+                         mcap, pk, ko, c->crd, ntot, n, r1cnt, r1, c->bowner, lst, key, cand, mch,
                          err);
       HIPCHK(hipGetLastError());
-      APCCHK(apc_rank_check(c, pending + c0, cn, cand, mch, s));
+      APCCHK(apc_rank_check(c, ko, pending + c0, cn, cand, mch, s));
       hipLaunchKernelGGL(k_accept, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, cand,
-                         mch, stbuf, mnode, still + c0);
+                         mch, stbuf, mnode, still + c0, ko, c->rorder);
       HIPCHK(hipGetLastError());
     }
     APCCHK(read_err(err, s, &herr));
@@ -683,6 +724,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     pending = npend;
     npend = tmp;
     np = left;
+  }
   }
   APCCHK(dfree(lst, s));
   APCCHK(dfree(key, s));
@@ -732,7 +774,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
                    apc_cloud **out) {
   *out = nullptr;
   if (!p || !xyz || N < 1 || N > INT32_MAX) return APC_EINVAL;
-  if (p->order != 2) return APC_EINVAL;
+  if (p->order != 2 && p->order != 4) return APC_EINVAL;
   if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
       p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
@@ -742,7 +784,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   c->P = *p;
   HIPCHK(hipGetDevice(&c->device));
   c->N = N;
-  c->p = 9;
+  c->p = p->order == 2 ? 9 : 34;
   c->unit = p->L / ldexp(1.0, p->max_depth + 1);
   // T_l = t^(2k-2), t = (c 2^l) / L, by repeated multiplication from 1.0
   for (int l = 0; l < 24; l++) {

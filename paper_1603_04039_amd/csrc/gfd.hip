@@ -395,8 +395,12 @@ __global__ void __launch_bounds__(APC_BLOCK)
 
 } // namespace
 
-int apc_rank_check(const apc_cloud *c, const int32_t *pending, int64_t np, const int32_t *cand,
-                   int32_t *m, hipStream_t s) {
+// Rank test of candidate stencils: k = 2 clouds by the per-thread Cholesky of the
+// 9x9 normal equations; k = 4 clouds (order-4 rows and their order-2 fallback
+// rows) by the wavefront Householder QR, the oracle's algorithm.
+int apc_rank_check(const apc_cloud *c, int order, const int32_t *pending, int64_t np,
+                   const int32_t *cand, int32_t *m, hipStream_t s) {
+  if (c->P.order == 4) return apc_rank_check4(c, order == 4 ? 34 : 9, pending, np, cand, m, s);
   hipLaunchKernelGGL(k_rank9, dim3(grid_for(np)), dim3(APC_BLOCK), 0, s, pending, np, cand, m,
                      c->crd, c->n + c->nb);
   HIPCHK(hipGetLastError());
@@ -417,10 +421,27 @@ int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
     HIPCHK(hipMalloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
   else
     HIPCHK(hipMalloc((void **)&c->w64, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
-  hipLaunchKernelGGL(k_classify, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off, c->st_idx,
-                     c->crd, ntot, c->level, c->P.max_depth, c->rkind);
-  HIPCHK(hipGetLastError());
+  if (c->P.order == 2) {
+    hipLaunchKernelGGL(k_classify, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
+                       c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->rkind);
+    HIPCHK(hipGetLastError());
+  } else {
+    // k = 4: every row is fitted and stored (no uniform-row sharing)
+    HIPCHK(hipMemsetAsync(c->rkind, 0xff, (size_t)(n > 0 ? n : 1), s));
+  }
   APCCHK(apc_build_sell(c, s));
+  if (c->P.order == 4) {
+    const size_t nz = (size_t)(c->nnz > 0 ? c->nnz : 1), ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 1);
+    if (mixed) {
+      HIPCHK(hipMalloc((void **)&c->bw32, nz * sizeof(float)));
+      HIPCHK(hipMalloc((void **)&c->sl_bw32, ne * sizeof(float)));
+      HIPCHK(hipMemsetAsync(c->sl_bw32, 0, ne * sizeof(float), s));
+    } else {
+      HIPCHK(hipMalloc((void **)&c->bw64, nz * sizeof(double)));
+      HIPCHK(hipMalloc((void **)&c->sl_bw64, ne * sizeof(double)));
+      HIPCHK(hipMemsetAsync(c->sl_bw64, 0, ne * sizeof(double), s));
+    }
+  }
   // canonical uniform 2-ring (spacing 1) around (4,4,4), sorted by r^2
   int32_t hcrd[3 * 25];
   int k = 1;
@@ -452,6 +473,11 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
   const bool mixed = c->P.precision != APC_FP64;
   const unsigned gsl = (unsigned)((c->nsl + (APC_BLOCK / 64) - 1) / (APC_BLOCK / 64));
   c->learned = false; // M depends on the assembled rows: install it again
+  if (c->P.order == 4) {
+    APCCHK(apc_assemble4(c, s));
+    c->assembled = true;
+    return APC_OK;
+  }
   HIPCHK(hipMemsetAsync(&c->scratch->nfp64, 0, sizeof(unsigned long long), s));
   if (c->nsl > 0) {
     if (mixed)
@@ -473,6 +499,7 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
 }
 
 int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s) {
+  if (c->P.order == 4) return apc_node_derivs4(c, f, D, s);
   hipLaunchKernelGGL(k_node_derivs, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->st_off,
                      c->st_idx, c->crd, c->n + c->nb, c->unit, f, D);
   HIPCHK(hipGetLastError());
@@ -481,6 +508,7 @@ int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s
 
 int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
                     hipStream_t s) {
+  if (c->P.order == 4) return apc_interp4(c, phi, phi_p, grad_p, s);
   double *D = nullptr;
   HIPCHK(hipMallocAsync((void **)&D, (size_t)c->n * P9 * sizeof(double), s));
   APCCHK(apc_node_derivs_impl(c, phi, D, s));

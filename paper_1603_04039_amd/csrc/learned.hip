@@ -617,7 +617,7 @@ unsigned infer_grid(int64_t nsl) {
 
 int apc_learn_data_impl(apc_cloud *c, const double *Z, int K, float *feat, float *quad,
                         hipStream_t s) {
-  if (!c->assembled) return APC_EINVAL;
+  if (!c->assembled || c->P.order != 2) return APC_EINVAL;
   const int64_t n = c->n, ntot = c->n + c->nb;
   const RowOp r = make_rowop(c);
   hipLaunchKernelGGL(k_features, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, r, feat);
@@ -700,6 +700,7 @@ int apc_mlp_adam_impl(float *P, float *m, float *v, const float *g, int step, fl
 
 int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16, float *out,
                        hipStream_t s) {
+  if (c->P.order != 2) return APC_EINVAL;
   if (!bf16) {
     hipLaunchKernelGGL(k_infer_f32, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, P, feat, c->n, out);
     HIPCHK(hipGetLastError());
@@ -720,7 +721,7 @@ int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16
 }
 
 int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, hipStream_t s) {
-  if (!c->assembled) return APC_EINVAL;
+  if (!c->assembled || c->P.order != 2) return APC_EINVAL;
   const int64_t n = c->n;
   if (!c->m_diag) HIPCHK(hipMalloc((void **)&c->m_diag, (size_t)(n > 0 ? n : 1) * sizeof(float)));
   if (!c->m_sell)

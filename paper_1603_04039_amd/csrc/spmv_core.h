@@ -16,7 +16,8 @@ struct Op {
   const int32_t *idx;
   const double *w64;
   const float *w32;
-  const double *hs; // nullptr => Laplacian
+  const double *hs; // k = 2 density operator: x_i + hs_i (L x)_i
+  int unit_diag;    // k = 4 density operator: x_i + (sum_j b_ij (x_j - x_i)) with its own weights
   const int8_t *rk; // level of a uniform 2-ring row, -1 for a general row
   double tc[3];     // shell weights of the uniform 2-ring at h_c = 1
   double invL2;     // 1 / L^2: a level-l row scales tc by 4^l / L^2
@@ -131,16 +132,18 @@ __device__ __forceinline__ double sell_apply(const Op &op, const double *__restr
       acc = ad;
     }
   }
-  return op.hs ? xi + op.hs[row] * acc : acc;
+  return op.hs ? xi + op.hs[row] * acc : (op.unit_diag ? xi + acc : acc);
 }
 
 static inline Op make_op(const apc_cloud *c, bool density) {
   Op op;
   op.off = c->st_off;
   op.idx = c->st_idx;
-  op.w64 = c->w64;
-  op.w32 = c->w32;
-  op.hs = density ? c->hscale : nullptr;
+  const bool b4 = density && c->P.order == 4;
+  op.w64 = b4 ? c->bw64 : c->w64;
+  op.w32 = b4 ? c->bw32 : c->w32;
+  op.hs = (density && !b4) ? c->hscale : nullptr;
+  op.unit_diag = b4 ? 1 : 0;
   op.rk = c->rkind;
   for (int k = 0; k < 3; k++) op.tc[k] = c->tmpl[k];
   op.invL2 = 1.0 / (c->P.L * c->P.L);
@@ -150,8 +153,8 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   op.sl_idx = c->sl_idx;
   op.sl_tmpl = c->sl_tmpl;
   op.sl_off = c->sl_off;
-  op.sl_w64 = c->sl_w64;
-  op.sl_w32 = c->sl_w32;
+  op.sl_w64 = b4 ? c->sl_bw64 : c->sl_w64;
+  op.sl_w32 = b4 ? c->sl_bw32 : c->sl_w32;
   for (int k = 0; k < 9; k++) op.cs[k] = c->sl_cs[k];
   return op;
 }

@@ -549,15 +549,21 @@ def test_direct_summation_far_field(oracle_mod):
 def test_k4_adaptive_cloud_rows(oracle_mod):
     """k = 4 on an adaptive beam cloud (Sec. 3.1, Sec. 4.3): every row of order 4
     is exact on quartics, every order-2 fallback row on quadratics; order-4
-    stencils span 5 distinct offsets along each axis (the centre's 0 included);
-    the fallback stays rare."""
+    stencils span 5 distinct offsets along each axis (the centre's 0 included)
+    and their rows are stable (negative diagonal, off-diagonal mass at most 10
+    times it); the fallback stays a few percent of the rows."""
     rng = np.random.default_rng(12)
     xyz = beam_halo(50000, seed=32)
     C = oracle_mod.OracleCloud(xyz, order=4, c=0.05, max_depth=6)
     orders = C.node_orders()
     assert set(np.unique(orders)) <= {2, 4}
     n2 = int((orders == 2).sum())
-    assert n2 <= C.n // 1000 + 1
+    assert 0 < n2 <= 0.05 * C.n
+    # order-4 rows are stable: negative diagonal, off-diagonal mass <= 10 |diag|
+    w, dg = C.assemble()
+    aw = np.add.reduceat(np.abs(w), C.nodes()["st_off"][:-1])
+    assert np.all(dg[orders == 4] < 0)
+    assert np.all(aw[orders == 4] <= 10.0 * np.abs(dg[orders == 4]) * (1 + 1e-12))
     nd = C.nodes()
     off, idx = nd["st_off"], nd["st_idx"]
     crd = C.coords()
