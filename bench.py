@@ -58,7 +58,7 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="ja
             from paper_1603_04039_amd import learned
             cloud.set_learned_precond(params, learned.probes(cloud, seed=it))
         ev[3].record(stream)
-        rho_M, rho_t, std = cloud.deposit(tol=1e-10, maxit=2000)
+        rho_M, rho_t, std = cloud.deposit(tol=1e-10, maxit=20000)
         ev[4].record(stream)
         phi, st = cloud.solve(rho_t[:cloud.n], tol=tol, maxit=20000, precond=pc)
         ev[5].record(stream)
@@ -67,11 +67,16 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="ja
         ev[6].synchronize()
         if st["status"] != 0:
             raise RuntimeError(f"solve did not converge: {st}")
+        if std["status"] != 0:
+            raise RuntimeError(f"density solve did not converge: {std}")
         if st["precond_used"] != pc:
             raise RuntimeError(f"learned preconditioner fell back to Jacobi: {st}")
         if timed:
             for k, name in enumerate(names):
                 acc[name] += ev[k].elapsed_time(ev[k + 1])
+        log(f"step {it} ({'timed' if timed else 'warmup'}): n={cloud.n} iters={st['iters']} "
+            f"phases(ms)=" + ", ".join(f"{k} {ev[q].elapsed_time(ev[q + 1]):.2f}"
+                                         for q, k in enumerate(names)))
         info = dict(n=cloud.n, nb=cloud.nb, nnz=cloud.nnz, iters=st["iters"],
                     sweeps=st["sweeps"], rel_resid_true=st["rel_resid_true"],
                     density_iters=std["iters"])
@@ -295,6 +300,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batch")
+    ap.add_argument("--no-k4", action="store_true",
+                    help="skip the 1e8-particle fourth-order workload (about 90 s)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
@@ -379,6 +386,29 @@ def main():
         batch = batch_bench(apc, torch, max(2, args.steps // 2), args.tol)
         log(f"batch: {batch}")
 
+    k4 = None
+    if not args.no_k4 and args.workload != "beam_halo_1e8_k4":
+        log("fourth-order workload beam_halo_1e8_k4 (one timed step)")
+        try:
+            c4 = CONFIGS["beam_halo_1e8_k4"]
+            x4 = torch.from_numpy(beam_halo(c4["N"], seed=c4["seed"], sigma=c4["sigma"],
+                                            halo_frac=c4["halo_frac"])).cuda()
+            ms4, info4, _, cl4, _ = run_steps(apc, torch, x4, c4, apc.APC_MIXED, 1, 0, args.tol)
+            r4 = spmv_roofline(torch, cl4, 10, True, "beam_halo_1e8_k4")
+            cl4.close()
+            del x4
+            k4 = dict(workload="beam_halo_1e8_k4", particles=c4["N"], nodes=info4["n"],
+                      nnz=info4["nnz"], order=4, max_depth=c4["max_depth"], c=c4["c"],
+                      nodes_per_s=round(info4["n"] / ((ms4["assemble"] + ms4["solve"]) * 1e-3), 1),
+                      phases_ms={k: round(v, 1) for k, v in ms4.items()}, iters=info4["iters"],
+                      density_iters=info4["density_iters"],
+                      rel_resid_true=info4["rel_resid_true"],
+                      spmv=dict(avg_us=r4["avg_us"], GBs=r4["achieved"], frac=r4["frac"]))
+        except Exception as e:  # reported, never hides the headline
+            k4 = dict(workload="beam_halo_1e8_k4", error=str(e)[:300])
+        log(f"k4: {k4}")
+        torch.cuda.empty_cache()
+
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
@@ -410,6 +440,8 @@ def main():
     }
     if batch is not None:
         out["batch"] = batch
+    if k4 is not None:
+        out["k4"] = k4
     if roof_m is not None:
         out["roofline_precond"] = roof_m
         out["learned_params"] = params_src

@@ -9,7 +9,7 @@
 
 #define APC_BLOCK 256
 #define APC_MAXM 64      // hard stencil cap: one wavefront
-#define APC_RING_CAP 2048 // per-node candidate capacity of the ring search
+#define APC_RING_CAP 16384 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
 #define APC_TAU_DOM 10.0  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
 #define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
@@ -154,6 +154,8 @@ struct apc_cloud {
 };
 
 // ---------------------------------------------------------------- host utilities
+// text returned by apc_last_error for the calling thread
+void apc_set_error_msg(const char *msg);
 int apc_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);  // exclusive
 int apc_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);  // exclusive
 int apc_sum_i32(const int32_t *in, int64_t n, int64_t *host_out, hipStream_t s);

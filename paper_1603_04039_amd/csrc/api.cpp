@@ -33,6 +33,8 @@ struct DeviceGuard {
 };
 } // namespace
 
+void apc_set_error_msg(const char *msg) { snprintf(g_err, sizeof(g_err), "%s", msg); }
+
 extern "C" {
 
 void apc_default_params(apc_params *p, int order) {

@@ -565,8 +565,14 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   HIPCHK(hipGetLastError());
   int herr = 0;
   APCCHK(read_err(err, s, &herr));
-  if (herr & 1) return APC_EINVAL;
-  if (herr & 2) return APC_EDOMAIN;
+  if (herr & 1) {
+    apc_set_error_msg("non-finite particle coordinate");
+    return APC_EINVAL;
+  }
+  if (herr & 2) {
+    apc_set_error_msg("particle outside the domain");
+    return APC_EDOMAIN;
+  }
   APCCHK(apc_radix_sort(keys, c->perm, N, 3 * D, s));
 
   // criterion phase, one level per pass
@@ -651,7 +657,10 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
                      n, D, r1cnt, r1, err);
   HIPCHK(hipGetLastError());
   APCCHK(read_err(err, s, &herr));
-  if (herr) return APC_EINVAL; // an unbalanced face: cannot happen after the balance phase
+  if (herr) { // an unbalanced face: cannot happen after the balance phase
+    apc_set_error_msg("2:1 balance violated after the balance phase");
+    return APC_EINVAL;
+  }
   APCCHK(dfree(bcnt, s));
   APCCHK(dfree(bstart, s));
   APCCHK(dfree(mc, s));
@@ -680,7 +689,9 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     APCCHK(dfree(offs, s));
   }
   int64_t np = n;
-  const int64_t CH = 32768; // nodes per ring-search chunk (scratch ~ CH * 24 KB)
+  // nodes per ring-search chunk: enough threads to keep the GPU busy, scratch of
+  // CH * APC_RING_CAP * 12 B (6.4 GB at the largest chunk)
+  const int64_t CH = np < 32768 ? (np > 0 ? np : 1) : 32768;
   int32_t *lst = nullptr, *cand = nullptr, *mch = nullptr, *still = nullptr, *soff = nullptr,
           *npend = nullptr;
   int64_t *key = nullptr;
@@ -713,7 +724,10 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
       HIPCHK(hipGetLastError());
     }
     APCCHK(read_err(err, s, &herr));
-    if (herr) return APC_EINVAL; // ring larger than the search capacity
+    if (herr) {
+      apc_set_error_msg("ring larger than the search capacity (16384 candidates)");
+      return APC_EINVAL;
+    }
     APCCHK(apc_scan_i32(still, soff, np, s));
     int64_t left = 0;
     APCCHK(apc_sum_i32(still, np, &left, s));
