@@ -89,6 +89,25 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="ja
     return ms, info, t_wall * 1000.0 / steps, last, phi
 
 
+def load_params(apc, torch, order):
+    """Learned-preconditioner parameters of the GFD order (committed file, or
+    trained here on the order's 200 training clouds when it is missing)."""
+    import numpy as np
+    from paper_1603_04039_amd import learned
+    path = learned.params_path(order)
+    if os.path.exists(path):
+        params, src = torch.from_numpy(np.load(path)).cuda(), os.path.basename(path)
+    else:
+        rec = learned.RECIPES[order]
+        log(f"training the learned preconditioner for k = {order} (no {os.path.basename(path)})")
+        feat, quad = learned.training_data(rec["train"], workload=rec["workload"])
+        params, _ = learned.train(feat, quad, steps=3000, batch=4096, lr=2e-3)
+        del feat, quad
+        src = "trained in this run (200 clouds, 3000 Adam steps)"
+    assert params.numel() == apc.MLP_NPARAM
+    return params, src
+
+
 def stream_probe(torch, mib=1024, reps=10):
     """Device copy of `mib` MiB (torch's copy kernel): the bandwidth a plain
     streaming kernel reaches here, and a kernel of known traffic (read + write
@@ -127,12 +146,12 @@ def precond_roofline(torch, cloud, reps):
     e1.record(stream)
     e1.synchronize()
     ms = e0.elapsed_time(e1) / reps
-    oi = cloud.operator_info()
+    oi = cloud.operator_info(m_entries=True)
     n_gen = cloud.n - oi["n_uniform"]
     # uniform rows: 24 indices + level byte (per-level M rows stay in cache);
-    # general rows: index + FP32 weight per entry and an FP32 diagonal; every
-    # row: row id, in_i, out_i
-    byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["nnz_general"] * 8 + n_gen * 4
+    # general rows: index + FP32 weight per stored entry of M (the first 40
+    # stencil entries) and an FP32 diagonal; every row: row id, in_i, out_i
+    byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["m_entries"] * 8 + n_gen * 4
             + cloud.n * (4 + 8 + 8))
     gbs = byts / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -327,17 +346,7 @@ def main():
     params = None
     params_src = None
     if args.precond == "learned" or not args.no_plain:
-        from paper_1603_04039_amd import learned
-        if os.path.exists(learned.PARAMS_PATH):
-            params = torch.from_numpy(np.load(learned.PARAMS_PATH)).cuda()
-            params_src = "learned_params.npy"
-        else:
-            log("training the learned preconditioner (no learned_params.npy)")
-            feat, quad = learned.training_data()
-            params, _ = learned.train(feat, quad, steps=3000, batch=4096, lr=2e-3)
-            del feat, quad
-            params_src = "trained in this run (200 clouds, 3000 Adam steps)"
-        assert params.numel() == apc.MLP_NPARAM
+        params, params_src = load_params(apc, torch, cfg["order"])
     log(f"timed steps ({args.precision}, {args.precond}): warmup={args.warmup} steps={args.steps}")
     ms, info, ms_step, cloud, phi = run_steps(apc, torch, xyz_d, cfg, prec, args.steps,
                                               args.warmup, args.tol, args.precond, params)
@@ -396,14 +405,31 @@ def main():
             ms4, info4, _, cl4, _ = run_steps(apc, torch, x4, c4, apc.APC_MIXED, 1, 0, args.tol)
             r4 = spmv_roofline(torch, cl4, 10, True, "beam_halo_1e8_k4")
             cl4.close()
-            del x4
+
+            def leg(ms, info):
+                t = (ms["assemble"] + ms["install"] + ms["solve"]) * 1e-3
+                return dict(nodes_per_s=round(info["n"] / t, 1),
+                            phases_ms={k: round(v, 1) for k, v in ms.items()},
+                            iters=info["iters"], sweeps=info["sweeps"],
+                            density_iters=info["density_iters"],
+                            rel_resid_true=info["rel_resid_true"])
             k4 = dict(workload="beam_halo_1e8_k4", particles=c4["N"], nodes=info4["n"],
                       nnz=info4["nnz"], order=4, max_depth=c4["max_depth"], c=c4["c"],
-                      nodes_per_s=round(info4["n"] / ((ms4["assemble"] + ms4["solve"]) * 1e-3), 1),
-                      phases_ms={k: round(v, 1) for k, v in ms4.items()}, iters=info4["iters"],
-                      density_iters=info4["density_iters"],
-                      rel_resid_true=info4["rel_resid_true"],
+                      precision="mixed", jacobi=leg(ms4, info4),
                       spmv=dict(avg_us=r4["avg_us"], GBs=r4["achieved"], frac=r4["frac"]))
+            log(f"k4 jacobi: {k4['jacobi']}")
+            p4, p4src = load_params(apc, torch, 4)
+            ms4l, info4l, _, cl4, _ = run_steps(apc, torch, x4, c4, apc.APC_MIXED, 1, 0, args.tol,
+                                                "learned", p4)
+            r4m = precond_roofline(torch, cl4, 10)
+            cl4.close()
+            del x4
+            k4["learned"] = leg(ms4l, info4l)
+            k4["learned"]["params"] = p4src
+            k4["learned"]["m_apply"] = dict(avg_us=r4m["avg_us"], GBs=r4m["achieved"],
+                                            frac=r4m["frac"])
+            k4["speedup_learned_vs_jacobi"] = round(
+                k4["learned"]["nodes_per_s"] / k4["jacobi"]["nodes_per_s"], 3)
         except Exception as e:  # reported, never hides the headline
             k4 = dict(workload="beam_halo_1e8_k4", error=str(e)[:300])
         log(f"k4: {k4}")

@@ -141,17 +141,23 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host);
 /* Layout of the assembled operator as the solver streams it: n_uniform rows have
    the uniform 24-node 2-ring stencil of their own level (their weights are the
    shared shell constants and are not read), nnz_general entries belong to the
-   other rows, sell_entries is the padded entry count of the sliced layout. */
+   other rows, sell_entries is the padded entry count of the sliced layout,
+   m_entries the off-diagonal entries the learned M stores for the other rows
+   (min(m, APC_MLP_OUT - 1) per row).  Any output may be NULL; m_entries copies
+   the stencil offsets to the host (n+1 int32) and synchronises the device. */
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
-                      int64_t *sell_entries);
+                      int64_t *sell_entries, int64_t *m_entries);
 
 /* WLS charge assignment (Sec. 3.2 step 1): rho_M_j = (1/h_j^3) sum_{i in cell j} q_i
    (NGP kernel: the node's own octree cell, edge h_j), then B rho~ = rho_M with
-   B = I + diag(h_j^2 / 24) L for k = 2 (kernel moments of the cell), boundary
-   nodes carrying their owner's rho_M.  q: N charges in the caller's particle
-   order, or NULL for 1/N each (total charge 1, Sec. 2).  rho_M (may be NULL)
-   and rho_t: n+nb.  Requires apc_assemble_gfd.  BiCGSTAB to relative residual
-   tol (maxit iterations).  Synchronises the stream. */
+   B = I + sum_alpha a_alpha D^alpha over the even derivatives up to order k (eq.
+   density_linear_system; a_alpha the kernel moments of the cell): for k = 2
+   B = I + diag(h_j^2 / 24) L, for k = 4 B has rows of its own from the same
+   fit.  Boundary nodes carry their owner's rho_M.  q: N charges in the
+   caller's particle order, or NULL for 1/N each (total charge 1, Sec. 2).
+   rho_M (may be NULL) and rho_t: n+nb.  Requires apc_assemble_gfd.  BiCGSTAB to
+   relative residual tol (maxit iterations), no preconditioner.  Synchronises
+   the stream. */
 int apc_deposit(apc_cloud *c, const double *q, double *rho_M, double *rho_t, double tol,
                 int maxit, apc_stats *st, hipStream_t stream);
 
@@ -194,9 +200,11 @@ int apc_get_node_orders(const apc_cloud *c, int8_t *order_host);
 
 /* ---- learned preconditioner (a grown form beside the paper's method) ----
    Row i of M has the pattern of row i of the Poisson operator: J_0 = i and J_p the
-   p-th stencil node (p = 1..m, m <= 40; boundary nodes carry weight 0), and is
+   p-th stencil node (p = 1..min(m, 40); boundary nodes carry weight 0), and is
    written as m_i = (e_0 + o_i) / d_i, d_i the operator's diagonal: o_i = 0 is
-   Jacobi.  The network maps row features to o_i (APC_MLP_OUT entries, those
+   Jacobi.  k = 2 stencils hold at most 40 nodes, so M has the whole pattern of
+   the row; k = 4 rows (up to 64 nodes) keep their 40 nearest.  One parameter
+   set serves one order: the operators of k = 2 and k = 4 differ in kind.  The network maps row features to o_i (APC_MLP_OUT entries, those
    beyond m unused).  Training minimises the left approximate-inverse loss
    ||m_i^T A - e_i^T||^2 per row, estimated with K probe vectors z ~ N(0, I):
    E (m_i^T A z - z_i)^2.  Per row this is the quadratic
@@ -205,9 +213,9 @@ int apc_get_node_orders(const apc_cloud *c, int8_t *order_host);
    Features and quadratic data of every interior row for K probes Z (K x (n+nb)
    float64, boundary entries ignored): feat n x APC_MLP_IN float32, quad
    n x APC_LEARN_QUAD float32 (Q packed lower row-major, then b, then c).
-   Features: the row's Poisson weights divided by |d_i| in stencil order (40
-   slots, zero padded); level(J_p) - level(i) of the first 6 stencil nodes (0 for
-   boundary nodes); m / 40; the fraction of boundary nodes in the stencil.  All
+   Features: the row's Poisson weights divided by |d_i| in stencil order (the
+   first 40, zero padded); level(J_p) - level(i) of the first 6 stencil nodes (0
+   for boundary nodes); m / 40; the fraction of boundary nodes in the stencil.  All
    are scale-free, so clouds of any depth share one network.  Z may be NULL (K
    ignored, quad untouched): features only.  Requires
    apc_assemble_gfd.  Does not synchronise. */

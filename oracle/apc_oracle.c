@@ -1439,8 +1439,9 @@ int apco_mlp_forward(const double *P, const double *feat, int64_t nrow, double *
 /* Rows of M: the network output on every row (m_i = (e_0 + o_i) / d_i on the
    operator's pattern, boundary columns 0), then, with probes, the safeguard
    m_i <- j_i + alpha_i (m_i - j_i) on every row that is not a uniform 2-ring
-   row (24 stencil nodes at offsets, in cells of the row's level, with
-   components in {0, 1, 2} and L1 norm <= 2). */
+   row of a second-order cloud (24 stencil nodes at offsets, in cells of the
+   row's level, with components in {0, 1, 2} and L1 norm <= 2).  Rows longer
+   than 40 stencil nodes (fourth order) keep their first 40, the nearest. */
 int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, int K,
                    double *mdiag, double *mw) {
   int64_t n = C->n, ntot = C->n + C->nb, nnz = C->st_off[n];
@@ -1480,7 +1481,8 @@ int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, i
   for (int64_t i = 0; U && i < n; i++) {
     int32_t a = C->st_off[i];
     int m = C->st_off[i + 1] - a;
-    int uniform = m == 24;
+    /* per-level shared rows exist only in second-order clouds */
+    int uniform = C->P.order == 2 && m == 24;
     int lv = C->cells[C->node_cell[i]].level;
     int32_t sp = 1 << (C->P.max_depth - lv + 1);
     for (int j = 0; j < m && uniform; j++) {

@@ -83,7 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_get_nodes.argtypes = [P] * 11
     lib.apc_assemble_gfd.argtypes = [P, P]
     lib.apc_get_operator.argtypes = [P, P, P]
-    lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 3
+    lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 4
     lib.apc_get_node_orders.argtypes = [P, P]
     lib.apc_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
@@ -236,10 +236,14 @@ class Cloud:
                                          d.ctypes.data_as(ct.c_void_p)), "apc_get_operator")
         return w, d
 
-    def operator_info(self):
-        v = [ct.c_int64() for _ in range(3)]
-        _check(self.lib.apc_operator_info(self.h, *[ct.byref(x) for x in v]), "apc_operator_info")
-        return dict(n_uniform=v[0].value, nnz_general=v[1].value, sell_entries=v[2].value)
+    def operator_info(self, m_entries=False):
+        v = [ct.c_int64() for _ in range(4)]
+        refs = [ct.byref(x) for x in v[:3]] + [ct.byref(v[3]) if m_entries else None]
+        _check(self.lib.apc_operator_info(self.h, *refs), "apc_operator_info")
+        out = dict(n_uniform=v[0].value, nnz_general=v[1].value, sell_entries=v[2].value)
+        if m_entries:
+            out["m_entries"] = v[3].value
+        return out
 
     def deposit(self, q=None, tol=1e-12, maxit=1000, stream=None, rho_M=None, rho_t=None):
         import torch

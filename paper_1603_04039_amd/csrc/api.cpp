@@ -1,8 +1,10 @@
 // C ABI of the gfx950 AP-Cloud library (declared in include/apcloud.h).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
+#include <vector>
 
 #include "apc_internal.h"
 
@@ -150,11 +152,24 @@ int apc_get_node_orders(const apc_cloud *c, int8_t *order_host) {
 }
 
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
-                      int64_t *sell_entries) {
+                      int64_t *sell_entries, int64_t *m_entries) {
   if (!c || !c->assembled) return APC_EINVAL;
   if (n_uniform) *n_uniform = c->n_template;
   if (nnz_general) *nnz_general = c->nnz - 24 * c->n_template;
   if (sell_entries) *sell_entries = c->sl_entries;
+  if (m_entries) {
+    DeviceGuard g(c->device);
+    if (!g.ok) return APC_EHIP;
+    std::vector<int32_t> off((size_t)c->n + 1);
+    HIPCHK(hipMemcpy(off.data(), c->st_off, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+    std::vector<int8_t> rk((size_t)(c->n > 0 ? c->n : 1));
+    if (c->n > 0)
+      HIPCHK(hipMemcpy(rk.data(), c->rkind, (size_t)c->n, hipMemcpyDeviceToHost));
+    int64_t tot = 0;
+    for (int64_t i = 0; i < c->n; i++)
+      if (rk[i] < 0) tot += std::min<int64_t>(off[i + 1] - off[i], APC_MLP_OUT - 1);
+    *m_entries = tot;
+  }
   return APC_OK;
 }
 

@@ -2,7 +2,8 @@
 // (forward, backward, Adam), FP32 reference inference and BF16 MFMA inference.
 //
 // Row i of M has the pattern of row i of the operator (J_0 = i, J_p the p-th
-// stencil node) and is written as m_i = (e_0 + o_i) / d_i (o = 0 is Jacobi).  The
+// stencil node; the first 40 stencil nodes, the nearest, of the longer
+// fourth-order rows) and is written as m_i = (e_0 + o_i) / d_i (o = 0 is Jacobi).  The
 // network maps 48 row features to o_i (41 entries).  The training loss of a row
 // is the left approximate-inverse residual ||m_i^T A - e_i^T||^2 estimated with
 // K probes z ~ N(0, I): with U = A Z and u_p = U[J_p] / d_i, Q = u u^T / K,
@@ -510,7 +511,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int lane = threadIdx.x & 63;
   const int32_t row = sl_rows[s * APC_SLICE + lane];
   if (row < 0) return;
-  const int len = sl_len[s];
+  const int len = min(sl_len[s], NW); // M holds the first NW stencil entries
   const int64_t off = sl_off[s] + lane;
   const double jd = 1.0 / diag[row];
   const double dd = (double)m_diag[row] - jd;
@@ -617,7 +618,7 @@ unsigned infer_grid(int64_t nsl) {
 
 int apc_learn_data_impl(apc_cloud *c, const double *Z, int K, float *feat, float *quad,
                         hipStream_t s) {
-  if (!c->assembled || c->P.order != 2) return APC_EINVAL;
+  if (!c->assembled) return APC_EINVAL;
   const int64_t n = c->n, ntot = c->n + c->nb;
   const RowOp r = make_rowop(c);
   hipLaunchKernelGGL(k_features, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, r, feat);
@@ -700,7 +701,6 @@ int apc_mlp_adam_impl(float *P, float *m, float *v, const float *g, int step, fl
 
 int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16, float *out,
                        hipStream_t s) {
-  if (c->P.order != 2) return APC_EINVAL;
   if (!bf16) {
     hipLaunchKernelGGL(k_infer_f32, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, P, feat, c->n, out);
     HIPCHK(hipGetLastError());
@@ -721,7 +721,7 @@ int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16
 }
 
 int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, hipStream_t s) {
-  if (!c->assembled || c->P.order != 2) return APC_EINVAL;
+  if (!c->assembled) return APC_EINVAL;
   const int64_t n = c->n;
   if (!c->m_diag) HIPCHK(hipMalloc((void **)&c->m_diag, (size_t)(n > 0 ? n : 1) * sizeof(float)));
   if (!c->m_sell)

@@ -216,7 +216,9 @@ __global__ void __launch_bounds__(APC_BLOCK)
       for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * in[jj[k]];
       out[row] = acc;
     } else {
-      const int len = op.sl_len[s];
+      // M holds the first APC_MLP_OUT - 1 stencil entries of a row (all of them
+      // for k = 2; the nearest 40 of the up to 64 of k = 4)
+      const int len = min(op.sl_len[s], APC_MLP_OUT - 1);
       const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
       if (row < 0) continue;
       const float *__restrict__ wv = M.sell + off;
@@ -487,8 +489,8 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
 // tol, the iteration restarts from it.  With FP32 iteration arithmetic and FP64
 // true residuals this restart is the iterative refinement of the mixed mode.
 template <int MODE, int TMODE>
-static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, double tol, int maxit,
-                    int prec, apc_stats *st, hipStream_t s) {
+static int bicgstab(apc_cloud *c, const Op &op, const double *invd, const double *b, double *x,
+                    double tol, int maxit, int prec, apc_stats *st, hipStream_t s) {
   apc_solver_ws *w = c->ws;
   const int64_t n = w->n;
   const unsigned gs = spmv_grid(c);
@@ -502,7 +504,7 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
   int chunk = 8, nrest = 0, status = APC_ENOCONV;
   for (;;) {
     for (int k = 0; k < chunk; k++)
-      launch_iteration<MODE>(w, op, x, c->inv_diag, MOp{c->m_diag, c->m_sell, c->m_tmpl}, prec,
+      launch_iteration<MODE>(w, op, x, invd, MOp{c->m_diag, c->m_sell, c->m_tmpl}, prec,
                              gs, s);
     HIPCHK(hipGetLastError());
     APCCHK(read_sc(w, s));
@@ -540,13 +542,13 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *b, double *x, doub
 // true residuals deciding convergence.  Mixed with FP32 accumulation: FP32 SpMV
 // arithmetic in the iteration, the FP64 true residual restarting it (iterative
 // refinement) until it meets tol.
-static int run_once(apc_cloud *c, const Op &op, const double *b, double *x, double tol, int maxit,
-                    int prec, apc_stats *st, hipStream_t s) {
+static int run_once(apc_cloud *c, const Op &op, const double *invd, const double *b, double *x,
+                    double tol, int maxit, int prec, apc_stats *st, hipStream_t s) {
   if (c->P.precision == APC_MIXED_F32ACC)
-    return bicgstab<V32A32, V32A64>(c, op, b, x, tol, maxit, prec, st, s);
+    return bicgstab<V32A32, V32A64>(c, op, invd, b, x, tol, maxit, prec, st, s);
   if (c->P.precision == APC_MIXED)
-    return bicgstab<V32A64, V32A64>(c, op, b, x, tol, maxit, prec, st, s);
-  return bicgstab<V64, V64>(c, op, b, x, tol, maxit, prec, st, s);
+    return bicgstab<V32A64, V32A64>(c, op, invd, b, x, tol, maxit, prec, st, s);
+  return bicgstab<V64, V64>(c, op, invd, b, x, tol, maxit, prec, st, s);
 }
 
 // The learned preconditioner only changes the iteration; the true residual decides.
@@ -554,10 +556,11 @@ static int run_once(apc_cloud *c, const Op &op, const double *b, double *x, doub
 static int run_solve(apc_cloud *c, bool density, const double *b, double *x, double tol, int maxit,
                      int prec, apc_stats *st, hipStream_t s) {
   const Op op = make_op(c, density);
-  int rc = run_once(c, op, b, x, tol, maxit, prec, st, s);
+  const double *invd = density ? nullptr : c->inv_diag; // the density solve is plain
+  int rc = run_once(c, op, invd, b, x, tol, maxit, prec, st, s);
   if (rc == APC_ENOCONV && prec == APC_PRECOND_LEARNED) {
     const int it = st ? st->iters : 0;
-    rc = run_once(c, op, b, x, tol, maxit, APC_PRECOND_JACOBI, st, s);
+    rc = run_once(c, op, invd, b, x, tol, maxit, APC_PRECOND_JACOBI, st, s);
     if (st) st->iters += it;
   }
   return rc;
@@ -587,6 +590,11 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
     hipLaunchKernelGGL(k_rhs<V64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_M,
                        1.0, rho_M + c->n, w->b);
   HIPCHK(hipGetLastError());
+  // plain BiCGSTAB: B is the identity plus a local perturbation.  (For k = 4
+  // the rows of coarse nodes beside finer ones have diagonals far from 1, of
+  // either sign; right Jacobi scaling of the other rows changed the iteration
+  // count at 8.8e6 nodes by -17% to +18% depending on the cut-off, and scaling
+  // all rows stalled.)
   int rc = run_solve(c, true, w->b, w->x, tol, maxit, APC_PRECOND_NONE, st, s);
   if (rc < 0) return rc;
   hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,

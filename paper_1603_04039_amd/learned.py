@@ -7,10 +7,11 @@ draws the seeded clouds and probe vectors and sequences the calls.
 
 The network maps 48 features of a row of the assembled Poisson operator to the
 41 weights of row i of M (the pattern of row i of the operator: the diagonal and
-up to 40 stencil nodes) as m_i = (e_0 + o_i) / d_i, so an all-zero output layer
-is Jacobi.  The loss is the
+up to 40 stencil nodes, the nearest 40 of a fourth-order row) as
+m_i = (e_0 + o_i) / d_i, so an all-zero output layer is Jacobi.  The loss is the
 left approximate-inverse residual ||m_i^T A - e_i^T||^2 estimated with Gaussian
-probe vectors.
+probe vectors.  Second- and fourth-order operators get a network each, trained
+on clouds of their own order.
 """
 from __future__ import annotations
 
@@ -26,7 +27,21 @@ from . import apcloud as apc
 
 TRAIN_SEEDS = tuple(range(4000, 4200))
 HELD_OUT_SEEDS = tuple(range(5000, 5020))
-PARAMS_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "learned_params.npy")
+_HERE = os.path.dirname(os.path.abspath(__file__))
+PARAMS_PATH = os.path.join(_HERE, "learned_params.npy")
+
+# per GFD order: the cloud recipe, training and held-out seeds, parameter file
+RECIPES = {
+    2: dict(workload="beam_halo_1e5", train=TRAIN_SEEDS, held_out=HELD_OUT_SEEDS,
+            params=PARAMS_PATH),
+    4: dict(workload="beam_halo_k4_3e4", train=tuple(range(6000, 6200)),
+            held_out=tuple(range(7000, 7020)),
+            params=os.path.join(_HERE, "learned_params_k4.npy")),
+}
+
+
+def params_path(order: int) -> str:
+    return RECIPES[order]["params"]
 
 
 def _workload(name):
@@ -49,13 +64,15 @@ def make_cloud(seed, workload="beam_halo_1e5", precision=apc.APC_MIXED):
 
 
 def training_data(seeds=TRAIN_SEEDS, K=32, workload="beam_halo_1e5", probe_seed=7,
-                  precision=apc.APC_MIXED):
+                  precision=apc.APC_MIXED, log=None):
     """Features and quadratic loss data of every interior row of the clouds."""
     import torch
     gen = torch.Generator(device="cuda")
     gen.manual_seed(probe_seed)
     feats, quads = [], []
-    for sd in seeds:
+    for k, sd in enumerate(seeds):
+        if log and k % 50 == 0:
+            log(f"training data: cloud {k} of {len(seeds)}")
         cloud = make_cloud(sd, workload, precision)
         Z = torch.randn((K, cloud.n + cloud.nb), dtype=torch.float64, device="cuda",
                         generator=gen)
@@ -171,14 +188,17 @@ def summarize(results):
 
 def main():
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
-    ap.add_argument("--train-clouds", type=int, default=len(TRAIN_SEEDS))
+    ap.add_argument("--order", type=int, default=2, choices=sorted(RECIPES))
+    ap.add_argument("--train-clouds", type=int, default=200)
     ap.add_argument("--probes", type=int, default=32)
     ap.add_argument("--steps", type=int, default=3000)
     ap.add_argument("--batch", type=int, default=4096)
     ap.add_argument("--lr", type=float, default=2e-3)
-    ap.add_argument("--eval-clouds", type=int, default=len(HELD_OUT_SEEDS))
-    ap.add_argument("--out", default=PARAMS_PATH)
+    ap.add_argument("--eval-clouds", type=int, default=20)
+    ap.add_argument("--out", default=None)
     args = ap.parse_args()
+    rec = RECIPES[args.order]
+    out_path = args.out or rec["params"]
     import torch
 
     def log(msg):
@@ -187,7 +207,8 @@ def main():
     apc.load_library()
     torch.cuda.set_device(0)
     t0 = time.perf_counter()
-    feat, quad = training_data(TRAIN_SEEDS[:args.train_clouds], K=args.probes)
+    feat, quad = training_data(rec["train"][:args.train_clouds], K=args.probes,
+                               workload=rec["workload"], log=log)
     log(f"training data: {feat.shape[0]} rows from {args.train_clouds} clouds "
         f"({time.perf_counter() - t0:.1f} s)")
     P0 = init_params(0)
@@ -198,10 +219,11 @@ def main():
     t_train = time.perf_counter() - t0
     l1 = full_loss(P, feat, quad)
     log(f"loss {l0:.5f} (Jacobi) -> {l1:.5f} in {t_train:.1f} s")
-    np.save(args.out, P.cpu().numpy())
-    res = evaluate(P, HELD_OUT_SEEDS[:args.eval_clouds])
+    np.save(out_path, P.cpu().numpy())
+    res = evaluate(P, rec["held_out"][:args.eval_clouds], workload=rec["workload"])
     s = summarize(res)
-    s.update(loss_jacobi=l0, loss_trained=l1, train_s=t_train, train_rows=int(feat.shape[0]))
+    s.update(order=args.order, loss_jacobi=l0, loss_trained=l1, train_s=t_train,
+             train_rows=int(feat.shape[0]))
     print(json.dumps(s), flush=True)
 
 

@@ -160,13 +160,8 @@ def test_k4_lattice_stencils(apc, oracle_mod):
     G.close()
 
 
-def test_k4_rejections(apc):
-    """The learned preconditioner and batches carry k = 2 operators only."""
+def test_k4_batch_rejected(apc):
+    """Batches carry k = 2 operators only."""
     xyz = beam_halo(20000, seed=31)
-    G = gcloud(apc, xyz, precision=apc.APC_MIXED, **K4A)
-    G.assemble_gfd()
-    with pytest.raises(apc.ApcError):
-        G.learn_data()
     with pytest.raises(apc.ApcError):
         apc.Batch([torch.from_numpy(xyz).cuda()], **K4A)
-    G.close()

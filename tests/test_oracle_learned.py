@@ -264,3 +264,77 @@ def test_learned_m_uniform_rows_untouched(oracle_mod):
     np.testing.assert_array_equal(md1[inner], md0[inner])
     scaled = md0[inner] * d[inner]
     np.testing.assert_allclose(scaled, scaled[0], rtol=1e-12)
+
+
+# ---------------------------------------------------------------- k = 4
+@pytest.fixture(scope="module")
+def small_cloud4(oracle_mod):
+    xyz = beam_halo(3000, seed=21)
+    C = oracle_mod.OracleCloud(xyz, order=4, c=0.05, max_depth=4)
+    assert np.diff(C.nodes()["st_off"]).max() > 40
+    return C
+
+
+def test_k4_features_first_40_weights(oracle_mod, small_cloud4):
+    """Fourth-order rows hold up to 64 stencil nodes; the weight features are the
+    first 40 (the nearest) over |d_i|, the size feature is m / 40 (> 1 here)."""
+    C = small_cloud4
+    feat, _ = C.learn_data()
+    w, d = C.assemble()
+    off = C.nodes()["st_off"]
+    m = np.diff(off)
+    for i in range(C.n):
+        k = min(m[i], 40)
+        np.testing.assert_allclose(feat[i, :k], w[off[i]:off[i] + k] / abs(d[i]), rtol=1e-15)
+        assert np.all(feat[i, k:40] == 0.0)
+    np.testing.assert_array_equal(feat[:, 46], m / 40.0)
+    assert feat[:, 46].max() > 1.0
+
+
+def test_k4_quadratic_data_with_identity_probes(oracle_mod, small_cloud4):
+    """With the n unit vectors as probes, the per-row quadratic of a fourth-order
+    row equals ||m_i^T A - e_i^T||^2 / n exactly for m_i on {i} and the first 40
+    stencil nodes; stencil nodes beyond the 40th are not part of M."""
+    C = small_cloud4
+    n, ntot = C.n, C.n + C.nb
+    Z = np.zeros((n, ntot))
+    Z[np.arange(n), np.arange(n)] = 1.0
+    _, quad = C.learn_data(Z)
+    A, w, d, off, idx = _dense_interior(C)
+    rng = np.random.default_rng(8)
+    long_rows = np.where(np.diff(off) > 40)[0]
+    for i in rng.choice(long_rows, size=20, replace=False):
+        J = [i] + list(idx[off[i]:off[i] + 40])
+        mt = 0.3 * rng.standard_normal(NOUT)
+        mt[0] += 1.0
+        mvec = np.zeros(n)
+        for p, j in enumerate(J):
+            if j < n:
+                mvec[j] += mt[p] / d[i]
+        r = mvec @ A
+        r[i] -= 1.0
+        Q, bq, cq = unpack(quad[i])
+        assert mt @ Q @ mt - 2 * bq @ mt + cq == pytest.approx(r @ r / n, rel=1e-10, abs=1e-14)
+
+
+def test_k4_learned_m_pattern_and_safeguard(oracle_mod, small_cloud4):
+    """Rows of M carry weights on their first 40 stencil nodes only, and the
+    safeguard is never worse than either end of its segment (every fourth-order
+    row is safeguarded)."""
+    C = small_cloud4
+    w, d = C.assemble()
+    nd = C.nodes()
+    off, idx = nd["st_off"], nd["st_idx"]
+    rng = np.random.default_rng(9)
+    P = 0.3 * rng.standard_normal(oracle_mod.MLP_NPARAM)
+    Z = rng.standard_normal((6, C.n + C.nb))
+    md0, mw0 = C.learned_m(P)
+    pos = np.arange(off[-1]) - np.repeat(off[:-1], np.diff(off))
+    assert np.all(mw0[pos >= 40] == 0.0)
+    assert np.any(mw0[(pos < 40) & (idx < C.n)] != 0.0)
+    md1, mw1 = C.learned_m(P, Z)
+    Lj = _probe_losses(C, w, d, off, idx, Z, 1.0 / d, np.zeros_like(w))
+    L0 = _probe_losses(C, w, d, off, idx, Z, md0, mw0)
+    L1 = _probe_losses(C, w, d, off, idx, Z, md1, mw1)
+    assert np.all(L1 <= np.minimum(Lj, L0) + 1e-9 * (Lj + L0))
+    assert (np.abs(md1 - md0) > 1e-12 * np.abs(md0)).mean() > 0.5

@@ -23,6 +23,10 @@ CONFIGS = {
                           max_depth=10, order=2, c=0.04),
     "beam_halo_1e8_k4": dict(N=100_000_000, seed=5, sigma=(0.05, 0.05, 0.2), halo_frac=0.03,
                              max_depth=12, order=4, c=0.007),
+    # the anisotropic recipe at 3e4 particles (about 3.4e4 nodes): the clouds the
+    # fourth-order learned preconditioner is trained and evaluated on
+    "beam_halo_k4_3e4": dict(N=30_000, seed=6, sigma=(0.05, 0.05, 0.2), halo_frac=0.03,
+                             max_depth=6, order=4, c=0.004),
 }
 
 
