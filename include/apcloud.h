@@ -203,7 +203,7 @@ int apc_get_node_orders(const apc_cloud *c, int8_t *order_host);
    p-th stencil node (p = 1..min(m, 40); boundary nodes carry weight 0), and is
    written as m_i = (e_0 + o_i) / d_i, d_i the operator's diagonal: o_i = 0 is
    Jacobi.  k = 2 stencils hold at most 40 nodes, so M has the whole pattern of
-   the row; k = 4 rows (up to 64 nodes) keep their 40 nearest.  One parameter
+   the row; k = 4 rows (up to 56 nodes) keep their 40 nearest.  One parameter
    set serves one order: the operators of k = 2 and k = 4 differ in kind.  The network maps row features to o_i (APC_MLP_OUT entries, those
    beyond m unused).  Training minimises the left approximate-inverse loss
    ||m_i^T A - e_i^T||^2 per row, estimated with K probe vectors z ~ N(0, I):

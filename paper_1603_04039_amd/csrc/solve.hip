@@ -217,7 +217,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
       out[row] = acc;
     } else {
       // M holds the first APC_MLP_OUT - 1 stencil entries of a row (all of them
-      // for k = 2; the nearest 40 of the up to 64 of k = 4)
+      // for k = 2; the nearest 40 of the up to 56 of k = 4)
       const int len = min(op.sl_len[s], APC_MLP_OUT - 1);
       const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
       if (row < 0) continue;

@@ -276,7 +276,7 @@ def small_cloud4(oracle_mod):
 
 
 def test_k4_features_first_40_weights(oracle_mod, small_cloud4):
-    """Fourth-order rows hold up to 64 stencil nodes; the weight features are the
+    """Fourth-order rows hold up to 56 stencil nodes; the weight features are the
     first 40 (the nearest) over |d_i|, the size feature is m / 40 (> 1 here)."""
     C = small_cloud4
     feat, _ = C.learn_data()
