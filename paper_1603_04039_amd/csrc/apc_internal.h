@@ -11,7 +11,12 @@
 #define APC_MAXM 64      // hard stencil cap: one wavefront
 #define APC_RING_CAP 16384 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
-#define APC_TAU_DOM 10.0  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
+#define APC_TAU_DOM 10.0
+// window of the length sort of general rows in the sliced layout (SELL-C-sigma;
+// a multiple of the 64-row slice, 64 = no sort)
+#ifndef APC_SELL_SIGMA
+#define APC_SELL_SIGMA 256
+#endif  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
 #define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
 #define APC_TAU_FP32 0.1
 #define APC_MAX_LEVELS 24 // > max_depth (<= 20): per-level tables  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this

@@ -45,6 +45,24 @@ __device__ __forceinline__ int wave_max_i(int v) {
   return v;
 }
 
+// SELL-C-sigma: the general rows of each chunk are sorted by descending stencil
+// length (stably) within windows of APC_SELL_SIGMA consecutive rows, so that the
+// 64 rows of a slice have nearly equal lengths and padding stays small, while a
+// window keeps the Morton locality of its rows.  Key: chunk (3 bits) | window |
+// 255 - m (8 bits); the radix sort permutes srow_g in place.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_sigma_keys(Groups G, const int32_t *__restrict__ srow_g, const int32_t *__restrict__ st_off,
+                 int64_t ng, uint64_t *__restrict__ key) {
+  const int64_t q = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (q >= ng) return;
+  int c = 7;
+  while (c > 0 && q < G.r0[2 * c + 1]) c--;
+  const int64_t win = (q - G.r0[2 * c + 1]) / APC_SELL_SIGMA;
+  const int32_t row = srow_g[q];
+  const int m = min(st_off[row + 1] - st_off[row], 255);
+  key[q] = ((uint64_t)c << 33) | ((uint64_t)win << 8) | (uint64_t)(255 - m);
+}
+
 // one 64-thread block per slice
 __global__ void __launch_bounds__(SL)
     k_slices(Groups G, const int32_t *__restrict__ srow_t, const int32_t *__restrict__ srow_g,
@@ -132,6 +150,16 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   }
   c->sl_cs[8] = ns;
   c->nsl = ns;
+  const int64_t ng = n - T[8];
+  if (APC_SELL_SIGMA > SL && ng > 1) {
+    uint64_t *key = nullptr;
+    HIPCHK(hipMallocAsync((void **)&key, (size_t)ng * sizeof(uint64_t), s));
+    hipLaunchKernelGGL(k_sigma_keys, dim3(grid_for(ng)), dim3(APC_BLOCK), 0, s, G, srow_g, c->st_off,
+                       ng, key);
+    HIPCHK(hipGetLastError());
+    APCCHK(apc_radix_sort(key, srow_g, ng, 36, s));
+    HIPCHK(hipFreeAsync(key, s));
+  }
   const size_t nsz = (size_t)(ns > 0 ? ns : 1);
   HIPCHK(hipMalloc((void **)&c->sl_rows, nsz * SL * sizeof(int32_t)));
   HIPCHK(hipMalloc((void **)&c->sl_len, nsz * sizeof(int32_t)));
