@@ -6,6 +6,7 @@ so the bars are rounding-order bounds: operator rows within 1e-9 of the row's
 node cloud, stencils and the order-2 fallback decisions bit-exact, Krylov
 solutions within kappa (tol_gpu + tol_oracle).
 """
+import math
 import sys
 
 import numpy as np
@@ -165,3 +166,92 @@ def test_k4_batch_rejected(apc):
     xyz = beam_halo(20000, seed=31)
     with pytest.raises(apc.ApcError):
         apc.Batch([torch.from_numpy(xyz).cuda()], **K4A)
+
+
+# ---------------------------------------------------------------- full size
+@pytest.mark.slow
+@pytest.mark.timeout(900)
+def test_k4_full_size_sampled(apc, oracle_mod):
+    """beam_halo_1e8_k4 at full size (1e8 particles, ~8.8e6 nodes), mixed precision
+    with the learned M, as the bench runs it.  The oracle cannot build a cloud
+    this size, so it checks sampled outputs one node at a time: operator rows
+    (the oracle's WLS fit on the GPU's stencil, at the row's order; stencil
+    selection is bit-exact at the smaller sizes above), the deposit, and the
+    Taylor interpolation of sampled particles from the GPU potential.  The solve
+    must reach the 1e-8 true residual with the learned M and no fallback."""
+    from paper_1603_04039_amd import learned as lrn
+    from workloads import CONFIGS
+    cfg = CONFIGS["beam_halo_1e8_k4"]
+    note("k = 4 full size: generating 1e8 particles")
+    xyz = beam_halo(cfg["N"], seed=cfg["seed"], sigma=cfg["sigma"], halo_frac=cfg["halo_frac"])
+    kw = dict(order=4, c=cfg["c"], max_depth=cfg["max_depth"])
+    note("k = 4 full size: GPU build and assembly")
+    G = gcloud(apc, xyz, precision=apc.APC_MIXED, **kw)
+    G.assemble_gfd()
+    n, nb, N = G.n, G.nb, G.N
+    nd = G.nodes()
+    off, idx, lev = nd["st_off"], nd["st_idx"], nd["level"]
+    pos = G.lo[:, None] + G.unit * nd["ixyz"].astype(np.float64)
+    orders = G.node_orders()
+    note(f"k = 4 full size: n={n} nb={nb} nnz={G.nnz} order-2 rows={int((orders == 2).sum())}")
+    assert int(nd["count"].astype(np.int64).sum()) == N
+    assert np.all(np.diff(off) >= np.where(orders == 4, 35, 10))
+    w, d = G.operator()
+    rng = np.random.default_rng(11)
+    sample = rng.choice(n, 400, replace=False)
+    worst = 0.0
+    for i in sample:
+        nbr = idx[off[i]:off[i + 1]]
+        X, h, ratio = oracle_mod.wls_fit(int(orders[i]), (pos[:, nbr] - pos[:, [i]]).T)
+        assert ratio >= 1e-6
+        wl = (X[3] + X[6] + X[8]) / h ** 2
+        err = np.abs(w[off[i]:off[i + 1]] - wl).max() / abs(d[i])
+        worst = max(worst, err)
+        assert abs(d[i] + wl.sum()) <= 1e-6 * abs(d[i])
+    note(f"k = 4 full size: 400 sampled rows, max |w_gpu - w_oracle| / |diag| = {worst:.2e}")
+    assert worst <= 1e-6  # FP32 weights of the FP64 fit
+    del w
+    note("k = 4 full size: deposit")
+    rho_M, rho_t, std = G.deposit(tol=1e-10, maxit=20000)
+    assert std["status"] == 0
+    rM = rho_M.cpu().numpy()
+    hc = G.L / 2.0 ** lev[sample]
+    np.testing.assert_allclose(rM[sample], nd["count"][sample] / N / hc ** 3, rtol=1e-13)
+    note("k = 4 full size: learned M install and solve")
+    P = torch.from_numpy(np.load(lrn.params_path(4))).cuda()
+    G.set_learned_precond(P, lrn.probes(G, seed=0))
+    phi, st = G.solve(rho_t[:n].contiguous(), tol=1e-8, maxit=20000,
+                      precond=apc.APC_PRECOND_LEARNED)
+    note(f"k = 4 full size: {st['iters']} iterations, true residual {st['rel_resid_true']:.2e}")
+    assert st["status"] == 0 and st["rel_resid_true"] <= 1e-8
+    assert st["precond_used"] == apc.APC_PRECOND_LEARNED
+    note("k = 4 full size: interpolation of sampled particles")
+    phi_p, grad_p = G.interpolate_force(phi)
+    ph = phi.cpu().numpy()
+    pp, gp = phi_p.cpu().numpy(), grad_p.cpu().numpy()
+    alphas = oracle_mod.monomials(4)
+    fact = np.array([np.prod([math.factorial(int(e)) for e in a]) for a in alphas], dtype=float)
+    perm, first, count = nd["perm"], nd["first"], nd["count"]
+    occupied = sample[count[sample] > 0][:200]
+    assert occupied.size >= 50
+    for i in occupied:
+        p = int(perm[first[i]])
+        nbr = idx[off[i]:off[i + 1]]
+        X, h, _ = oracle_mod.wls_fit(int(orders[i]), (pos[:, nbr] - pos[:, [i]]).T)
+        a = alphas[:X.shape[0]]
+        df = ph[nbr] - ph[i]
+        hk = h ** a.sum(axis=1)
+        D = X @ df / hk
+        Dm = np.abs(X) @ np.abs(df) / hk  # magnitude behind each derivative
+        dl = xyz[:, p] - pos[:, i]
+        mono = np.prod(dl[None, :] ** a, axis=1) / fact[:len(a)]
+        # the value and the gradient of the Taylor polynomial at the particle; bars
+        # relative to the magnitudes that enter them (kappa eps of the two fits)
+        assert abs(pp[p] - (ph[i] + D @ mono)) <= 1e-9 * (abs(ph[i]) + Dm @ np.abs(mono)), i
+        for c in range(3):
+            ok = a[:, c] > 0
+            da = a[ok].copy()
+            da[:, c] -= 1
+            dm = a[ok, c] * np.prod(dl[None, :] ** da, axis=1) / fact[:len(a)][ok]
+            assert abs(gp[c, p] - D[ok] @ dm) <= 1e-9 * (Dm[ok] @ np.abs(dm)), (i, c)
+    G.close()
