@@ -3,20 +3,31 @@
 // which are the order-2 unknowns in the same order.
 //
 // A 34-unknown fit does not fit one thread's registers, so every k = 4 kernel
-// here runs one wavefront per node: lane j holds row j of W V0 (the stencil has
-// at most 64 nodes; lanes beyond it hold zero rows), the matrix lives in LDS as
-// 34 columns of 64 doubles, and the Householder QR of W V0 reduces each column
-// product across the wavefront.  This is the oracle's algorithm (Householder QR,
-// rank ratio min|R_ii| / max|R_ii|), so both sides take the same rank decisions.
-// The fit stays in FP64 in every precision mode (k = 4 systems are less well
+// here runs one wavefront per node (the stencil has at most 64 nodes).  Lane j
+// builds row j of W V0 and stores it into LDS column-major; then lane c takes
+// column c into registers and the Householder QR runs column-parallel: at step
+// k lane k forms the reflector of its column and publishes it in LDS, and every
+// lane c > k applies it to its own column with a lane-local dot product, so the
+// factorisation needs no cross-lane reduction.  This is the oracle's algorithm
+// (Householder QR, rank ratio min|R_ii| / max|R_ii|), so both sides take the
+// same rank decisions; the lane-local sums run as four interleaved partial sums
+// to shorten the FP64 dependency chains.  The fit
+// stays in FP64 in every precision mode (k = 4 systems are less well
 // conditioned); the mixed modes store FP32 weights.
 //
-// From one factorisation W V0 = Q R:
-//   Laplacian row   w_j = W_j (Q R^-T c)_j / h^2,  c = e_xx + e_yy + e_zz
-//   density row     b_j = W_j (Q R^-T c_B)_j,       c_B = cell moments a_alpha / h^|alpha|
+// From one factorisation W V0 = Q R and u = R^-1 R^-T c (two triangular solves,
+// one lane per unknown, each solved value broadcast with readlane):
+//   Laplacian row   w_j = W_j (W V0 u)_j / h^2 = W_j (Q R^-T c)_j / h^2,
+//                   c = e_xx + e_yy + e_zz
+//   density row     b_j = W_j (W V0 u_B)_j,  c_B = cell moments a_alpha / h^|alpha|
 //                   (eq. density_linear_system; B row sums are 1, so the diagonal
 //                   is 1 - sum b and B is applied in difference form)
-//   derivatives     h^|alpha| d^alpha f = R^-1 Q^T (W (f_j - f_0))
+//   derivatives     h^|alpha| d^alpha f = R^-1 Q^T (W (f_j - f_0)): the vector
+//                   W (f_j - f_0) rides along as one more column of the QR and
+//                   comes out multiplied by Q^T.
+// (W V0) R^-1 is Q, so the rows need no reflector after the factorisation; the
+// triangular solves are backward stable, which keeps the rows within
+// kappa(W V0) eps of the Q form.
 #include <hip/hip_runtime.h>
 
 #include <cmath>
@@ -26,15 +37,21 @@
 namespace {
 
 constexpr int P4 = 34;
-constexpr int WPB4 = 4; // wavefronts per block
-constexpr int LCOL = 64; // LDS column length (one entry per lane)
+constexpr int WPB4 = 4;      // wavefronts per block; the kernels ask for 2 blocks per CU
+                             // (2 waves per SIMD, as the LDS allows): measured on the
+                             // 8.8e6-node assembly, 0.58 s against 0.81 s at the
+                             // register count the compiler picks alone
+constexpr int MR = APC_MAXM; // rows of a column held per lane (the stencil cap)
+constexpr int LD = 66;       // LDS column stride in doubles (16-byte aligned columns)
+constexpr int RC = 8;        // rows per LDS read chunk in the QR update
+constexpr int RLD = P4 + 1;  // row stride of R in LDS (odd: conflict-free both ways)
 
 struct Wave4 {
-  double A[P4 * LCOL]; // column-major: A[c * 64 + j]; after QR: R on and above the
-                       // diagonal, reflector entries below it
-  double vd[P4];       // diagonal entries of the reflectors
-  double beta[P4];
-  double y[P4];
+  double A[(P4 + 1) * LD]; // the rows of W V0 column-major (and one extra column)
+                           // for the column loads; then R row-major (stride RLD)
+  double v[MR];            // the current step's reflector
+  double u[2 * P4];        // two solved vectors, broadcast to every lane
+  double beta;
 };
 
 __device__ __forceinline__ double wsum(double v) {
@@ -62,6 +79,13 @@ __device__ __forceinline__ void wsync() {
   __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "workgroup");
   __builtin_amdgcn_wave_barrier();
 }
+// x of lane l, in every lane (l is the same in all lanes)
+__device__ __forceinline__ double rdlane(double x, int l) {
+  const unsigned long long b = (unsigned long long)__double_as_longlong(x);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)b, l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(unsigned)(b >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
 
 // multi-index of unknown k in the oracle's order: degree 1..4, then the x power
 // descending, then the y power descending
@@ -87,30 +111,39 @@ __device__ __forceinline__ double fact(int a) {
   return f;
 }
 
-// xi^alpha / alpha! for the 34 unknowns into column-major LDS (row `lane`), times W
-__device__ inline void fill_row(double *A, int lane, double x, double y, double z, double W) {
+// xi^alpha / alpha! of the 34 unknowns, in the order of alpha4
+__device__ __forceinline__ void monos(double x, double y, double z, double (&mo)[P4]) {
   double px[5], py[5], pz[5];
   px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
   for (int e = 1; e <= 4; e++) {
     px[e] = px[e - 1] * x;
     py[e] = py[e - 1] * y;
     pz[e] = pz[e - 1] * z;
   }
   int k = 0;
+#pragma unroll
   for (int d = 1; d <= 4; d++)
+#pragma unroll
     for (int a = d; a >= 0; a--)
+#pragma unroll
       for (int b = d - a; b >= 0; b--) {
         const int c = d - a - b;
-        A[k * LCOL + lane] = W * (px[a] / fact(a) * py[b] / fact(b) * pz[c] / fact(c));
-        k++;
+        mo[k++] = px[a] / fact(a) * py[b] / fact(b) * pz[c] / fact(c);
       }
 }
 
-// Geometry of node y's stencil (lane j < m: neighbour j), rows of W V0 into LDS.
-// Returns h (integer units); W of the lane's row in *Wl (0 beyond the stencil).
-__device__ inline int stencil_rows(Wave4 &S, int lane, const int32_t *nb, int m,
-                                   const int32_t *__restrict__ crd, int64_t ntot, int64_t y,
-                                   double *Wl) {
+// Geometry of the lane's stencil node: offset scaled by h, WLS weight W (0 beyond
+// the stencil), h in integer units
+struct Geo {
+  double x, y, z, W;
+  int h;
+};
+
+// Node y's stencil (lane j < m: neighbour j): rows of W V0 into LDS columns 0..33
+// (zero rows beyond the stencil).  The caller synchronises.
+__device__ __forceinline__ Geo stencil_rows(Wave4 &S, int lane, const int32_t *nb, int m,
+                                   const int32_t *__restrict__ crd, int64_t ntot, int64_t y) {
   int32_t d0 = 0, d1 = 0, d2 = 0;
   if (lane < m) {
     const int32_t v = nb[lane];
@@ -118,125 +151,196 @@ __device__ inline int stencil_rows(Wave4 &S, int lane, const int32_t *nb, int m,
     d1 = crd[ntot + v] - crd[ntot + y];
     d2 = crd[2 * ntot + v] - crd[2 * ntot + y];
   }
-  const int h = wmax_i(max(abs(d0), max(abs(d1), abs(d2))));
+  Geo g;
+  g.h = wmax_i(max(abs(d0), max(abs(d1), abs(d2))));
   const double r2 = (double)((int64_t)d0 * d0 + (int64_t)d1 * d1 + (int64_t)d2 * d2);
   const double r2max = wmax_d(r2);
-  double W = 0.0;
+  g.W = 0.0;
   if (lane < m) {
     const double e4 = exp(-4.0);
-    W = (exp(-r2 / r2max) - e4) / (1.0 - e4);
+    g.W = (exp(-r2 / r2max) - e4) / (1.0 - e4);
   }
-  *Wl = W;
-  const double hd = (double)h;
-  if (lane < m)
-    fill_row(S.A, lane, (double)d0 / hd, (double)d1 / hd, (double)d2 / hd, W);
-  else
-    for (int k = 0; k < P4; k++) S.A[k * LCOL + lane] = 0.0;
-  wsync();
-  return h;
+  const double hd = (double)g.h;
+  g.x = (double)d0 / hd;
+  g.y = (double)d1 / hd;
+  g.z = (double)d2 / hd;
+  double mo[P4];
+  monos(g.x, g.y, g.z, mo);
+#pragma unroll
+  for (int k = 0; k < P4; k++) S.A[k * LD + lane] = lane < m ? g.W * mo[k] : 0.0;
+  return g;
 }
 
-// Householder QR of the first pc columns (34, or 9 for an order-2 row) of the
-// 64 x 34 matrix in S.A; returns min|R_ii| / max|R_ii|
-__device__ inline double wave_qr(Wave4 &S, int lane, int pc) {
-  double rmin = INFINITY, rmax = 0.0;
-  for (int c = 0; c < pc; c++) {
-    double *col = S.A + c * LCOL;
-    const double x = lane >= c ? col[lane] : 0.0;
-    const double nrm = sqrt(wsum(x * x));
-    const double acc = __shfl(x, c, 64);
-    double alpha = 0.0, bt = 0.0, v = 0.0;
-    if (nrm > 0.0) {
-      alpha = acc >= 0.0 ? -nrm : nrm;
-      v = lane == c ? x - alpha : x;
-      const double vn2 = wsum(v * v);
-      bt = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-      for (int c2 = c + 1; c2 < pc; c2++) {
-        double *cc = S.A + c2 * LCOL;
-        const double s = wsum(v * cc[lane]) * bt;
-        if (lane >= c) cc[lane] -= s * v;
+// Column-parallel Householder QR of the first pc columns in LDS (column-major,
+// stride LD), with columns pc..ncol-1 carried along (they receive Q^T).  Lane
+// c < ncol holds column c; after step k it drops the finished row k, so a[0] is
+// always the pivot row and no step needs a row predicate.  On return R is in LDS
+// row-major with stride RLD (R_ij at A[i * RLD + j], i <= j < pc) and row i of
+// Q^T times the extra column c at A[i * RLD + c].  Returns min|R_ii| / max|R_ii|.
+__device__ __forceinline__ double col_qr(Wave4 &S, int lane, int pc, int ncol) {
+  double a[MR];
+#pragma unroll
+  for (int r = 0; r < MR; r++) a[r] = lane < ncol ? S.A[lane * LD + r] : 0.0;
+  wsync(); // every column is in registers before R reuses the buffer
+  double rd = 0.0;
+  for (int k = 0; k < pc; k++) {
+    // a[] = rows k..k+MR-1 of the lane's column (zeros past the stencil); lane
+    // k's reflector: v = a - alpha e_0, alpha = -sign(a_0) ||a||
+    double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r = 0; r < MR; r++) q[r & 3] += a[r] * a[r];
+    if (lane == k) {
+      const double nrm = sqrt((q[0] + q[1]) + (q[2] + q[3]));
+      double alpha = 0.0, bt = 0.0;
+      if (nrm > 0.0) {
+        alpha = a[0] >= 0.0 ? -nrm : nrm;
+        double e[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int r = 0; r < MR; r++) {
+          const double v = r == 0 ? a[0] - alpha : a[r];
+          e[r & 3] += v * v;
+          S.v[r] = v;
+        }
+        const double vn2 = (e[0] + e[1]) + (e[2] + e[3]);
+        bt = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+      } else {
+#pragma unroll
+        for (int r = 0; r < MR; r++) S.v[r] = 0.0;
       }
+      S.beta = bt;
+      S.A[k * RLD + k] = alpha;
+      rd = alpha;
     }
-    if (lane == c) {
-      col[lane] = alpha;
-      S.vd[c] = v;
-      S.beta[c] = bt;
-    } else if (lane > c) {
-      col[lane] = v;
-    }
-    rmin = fmin(rmin, fabs(alpha));
-    rmax = fmax(rmax, fabs(alpha));
     wsync();
+    // every later column: a -= beta (v . a) v; its new pivot entry is R_k,lane
+    if (lane > k && lane < ncol) {
+      double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r0 = 0; r0 < MR; r0 += RC) {
+#pragma unroll
+        for (int r = r0; r < r0 + RC; r++) d[r & 3] += S.v[r] * a[r];
+        __asm__ volatile("" ::: "memory");
+      }
+      const double sc = ((d[0] + d[1]) + (d[2] + d[3])) * S.beta;
+#pragma unroll
+      for (int r0 = 0; r0 < MR; r0 += RC) {
+#pragma unroll
+        for (int r = r0; r < r0 + RC; r++) a[r] -= sc * S.v[r];
+        __asm__ volatile("" ::: "memory");
+      }
+      S.A[k * RLD + lane] = a[0];
+    }
+#pragma unroll
+    for (int r = 0; r < MR - 1; r++) a[r] = a[r + 1];
+    a[MR - 1] = 0.0;
+    wsync(); // the reflector reads are done before the next step rewrites it
   }
+  const double rmin = wmin_d(lane < pc ? fabs(rd) : INFINITY);
+  const double rmax = wmax_d(lane < pc ? fabs(rd) : 0.0);
   return rmax > 0.0 ? rmin / rmax : 0.0;
 }
 
-// reflector c's entry for this lane
-__device__ __forceinline__ double refl(const Wave4 &S, int c, int lane) {
-  return lane == c ? S.vd[c] : (lane > c ? S.A[c * LCOL + lane] : 0.0);
+// u = R^-1 R^-T rhs for two right-hand sides (lane i < pc holds rhs_i); R in LDS
+// row-major.  Returns u_i in lane i (0 in lanes >= pc).
+__device__ __forceinline__ void solve_rrt(const Wave4 &S, int lane, int pc, double r1, double r2,
+                                          double &u1, double &u2) {
+  const double rinv = lane < pc ? 1.0 / S.A[lane * RLD + lane] : 1.0;
+  double a1 = r1, a2 = r2, y1 = 0.0, y2 = 0.0;
+  // R^T y = rhs: y_i = (rhs_i - sum_{k<i} R_ki y_k) / R_ii
+  for (int i = 0; i < pc; i++) {
+    const double d = rdlane(rinv, i);
+    const double t1 = rdlane(a1, i) * d, t2 = rdlane(a2, i) * d;
+    if (lane == i) {
+      y1 = t1;
+      y2 = t2;
+    }
+    if (lane > i && lane < pc) {
+      const double rij = S.A[i * RLD + lane];
+      a1 -= rij * t1;
+      a2 -= rij * t2;
+    }
+  }
+  // R u = y: u_j = (y_j - sum_{k>j} R_jk u_k) / R_jj
+  a1 = y1;
+  a2 = y2;
+  u1 = u2 = 0.0;
+  for (int j = pc - 1; j >= 0; j--) {
+    const double d = rdlane(rinv, j);
+    const double t1 = rdlane(a1, j) * d, t2 = rdlane(a2, j) * d;
+    if (lane == j) {
+      u1 = t1;
+      u2 = t2;
+    }
+    if (lane < j) {
+      const double rij = S.A[lane * RLD + j];
+      a1 -= rij * t1;
+      a2 -= rij * t2;
+    }
+  }
 }
 
-// u <- Q^T u (forward order of the reflectors); u held one entry per lane
-__device__ inline double apply_qt(const Wave4 &S, int lane, int pc, double u) {
-  for (int c = 0; c < pc; c++) {
-    const double v = refl(S, c, lane);
-    const double s = wsum(v * u) * S.beta[c];
-    u -= s * v;
+// R u = g (lane i < pc holds g_i); returns u_i in lane i
+__device__ __forceinline__ double solve_r(const Wave4 &S, int lane, int pc, double g) {
+  const double rinv = lane < pc ? 1.0 / S.A[lane * RLD + lane] : 1.0;
+  double a = g, u = 0.0;
+  for (int j = pc - 1; j >= 0; j--) {
+    const double t = rdlane(a, j) * rdlane(rinv, j);
+    if (lane == j) u = t;
+    if (lane < j) a -= S.A[lane * RLD + j] * t;
   }
   return u;
 }
-// z <- Q z (reverse order)
-__device__ inline double apply_q(const Wave4 &S, int lane, int pc, double z) {
-  for (int c = pc - 1; c >= 0; c--) {
-    const double v = refl(S, c, lane);
-    const double s = wsum(v * z) * S.beta[c];
-    z -= s * v;
-  }
-  return z;
-}
 
-// solve R^T y = rhs (lane i < pc holds rhs_i); returns y_i in lane i
-__device__ inline double solve_rt(const Wave4 &S, int lane, int pc, double rhs) {
-  double ym = 0.0;
-  for (int i = 0; i < pc; i++) {
-    // R_ki = A[i * 64 + k] for k < i, held in column i
-    const double t = wsum(lane < i ? S.A[i * LCOL + lane] * ym : 0.0);
-    if (lane == i) ym = (rhs - t) / S.A[i * LCOL + i];
+// (W V0 u)_j of the lane's row j for two vectors u (u_c in lane c < pc), the
+// u broadcast through LDS
+__device__ __forceinline__ void wv0_times(Wave4 &S, const Geo &g, int lane, int pc, double u1,
+                                          double u2, double &z1, double &z2) {
+  if (lane < pc) {
+    S.u[lane] = u1;
+    S.u[P4 + lane] = u2;
   }
-  return ym;
-}
-// solve R a = u (lane i < pc holds u_i); returns a_i in lane i
-__device__ inline double solve_r(const Wave4 &S, int lane, int pc, double u) {
-  double am = 0.0;
-  for (int i = pc - 1; i >= 0; i--) {
-    // R_ik = A[k * 64 + i] for k > i, held in column k
-    const double t = wsum((lane > i && lane < pc) ? S.A[lane * LCOL + i] * am : 0.0);
-    if (lane == i) am = (u - t) / S.A[i * LCOL + i];
-  }
-  return am;
+  wsync();
+  // recompute the monomials here rather than keep the 34 values of the row build
+  // live across the factorisation (the asm statements hide that they are equal)
+  double x = g.x, y = g.y, z = g.z;
+  __asm__ volatile("" : "+v"(x), "+v"(y), "+v"(z));
+  double mo[P4];
+  monos(x, y, z, mo);
+  double s1 = 0.0, s2 = 0.0;
+#pragma unroll
+  for (int c = 0; c < P4; c++)
+    if (c < pc) {
+      const double a0 = g.W * mo[c];
+      s1 += a0 * S.u[c];
+      s2 += a0 * S.u[P4 + c];
+    }
+  z1 = s1;
+  z2 = s2;
 }
 
 // ---------------------------------------------------------------- rank test (build)
-__global__ void __launch_bounds__(WPB4 * 64)
+__global__ void __launch_bounds__(WPB4 * 64, 2)
     k_rank_qr(int pc, const int32_t *__restrict__ pending, int64_t np, const int32_t *__restrict__ cand,
               int32_t *__restrict__ m, const int32_t *__restrict__ crd, int64_t ntot) {
   __shared__ Wave4 SH[WPB4];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * WPB4 + wv;
   if (t >= np) return;
   const int mm = m[t];
   if (mm <= 0) return;
-  double W;
-  stencil_rows(SH[wv], lane, cand + t * APC_MAXM, mm, crd, ntot, pending[t], &W);
-  const double ratio = wave_qr(SH[wv], lane, pc);
+  Wave4 &S = SH[wv];
+  const Geo g = stencil_rows(S, lane, cand + t * APC_MAXM, mm, crd, ntot, pending[t]);
+  wsync();
+  const double ratio = col_qr(S, lane, pc, pc);
   bool ok = ratio >= APC_TAU_RANK;
   if (ok && pc == P4) {
     // stability of the order-4 Laplacian row: negative diagonal and off-diagonal
     // weights of total magnitude <= APC_TAU_DOM times it (scale-free, h cancels)
     const double cl = (lane == 3 || lane == 6 || lane == 8) ? 1.0 : 0.0;
-    const double yl = solve_rt(SH[wv], lane, pc, cl);
-    const double zl = apply_q(SH[wv], lane, pc, lane < pc ? yl : 0.0);
-    const double sv = lane < mm ? W * zl : 0.0;
+    double u1, u2, z1, z2;
+    solve_rrt(S, lane, pc, cl, 0.0, u1, u2);
+    wv0_times(S, g, lane, pc, u1, u2, z1, z2);
+    const double sv = lane < mm ? g.W * z1 : 0.0;
     const double s1 = wsum(sv), s2 = wsum(fabs(sv));
     ok = s1 > 0.0 && s2 <= APC_TAU_DOM * s1;
   }
@@ -246,7 +350,7 @@ __global__ void __launch_bounds__(WPB4 * 64)
 // ---------------------------------------------------------------- assembly
 // Laplacian and density rows of every node (CSR order); one wavefront per node
 template <bool MIXED>
-__global__ void __launch_bounds__(WPB4 * 64)
+__global__ void __launch_bounds__(WPB4 * 64, 2)
     k_fit4(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
            const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
            const int8_t *__restrict__ rorder, double unit, double L, double *__restrict__ w64,
@@ -254,21 +358,21 @@ __global__ void __launch_bounds__(WPB4 * 64)
            double *__restrict__ bw64, float *__restrict__ bw32, double *__restrict__ diag,
            double *__restrict__ inv_diag, double *__restrict__ hscale, int *__restrict__ err) {
   __shared__ Wave4 SH[WPB4];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t y = (int64_t)blockIdx.x * WPB4 + wv;
   if (y >= n) return;
   Wave4 &S = SH[wv];
   const int32_t a0 = st_off[y];
   const int m = st_off[y + 1] - a0;
-  double W;
   const int pc = rorder[y] == 4 ? P4 : 9;
-  const int h = stencil_rows(S, lane, st_idx + a0, m, crd, ntot, y, &W);
-  const double ratio = wave_qr(S, lane, pc);
+  const Geo g = stencil_rows(S, lane, st_idx + a0, m, crd, ntot, y);
+  wsync();
+  const double ratio = col_qr(S, lane, pc, pc);
   if (!(ratio >= APC_TAU_RANK)) {
     if (lane == 0) *err = 1;
     return;
   }
-  const double hp = (double)h * unit;
+  const double hp = (double)g.h * unit;
   const double hc = L / (double)(1 << level[y]);
   // right-hand sides: Laplacian (unknowns xx = 3, yy = 6, zz = 8) and the cell moments
   double cl = 0.0, cb = 0.0;
@@ -289,12 +393,11 @@ __global__ void __launch_bounds__(WPB4 * 64)
       cb = mom / hk;
     }
   }
-  const double yl = solve_rt(S, lane, pc, cl);
-  const double zl = apply_q(S, lane, pc, lane < pc ? yl : 0.0);
-  const double yb = solve_rt(S, lane, pc, cb);
-  const double zb = apply_q(S, lane, pc, lane < pc ? yb : 0.0);
-  const double wl = lane < m ? W * zl / (hp * hp) : 0.0;
-  const double wb = lane < m ? W * zb : 0.0;
+  double ul, ub, zl, zb;
+  solve_rrt(S, lane, pc, cl, cb, ul, ub);
+  wv0_times(S, g, lane, pc, ul, ub, zl, zb);
+  const double wl = lane < m ? g.W * zl / (hp * hp) : 0.0;
+  const double wb = lane < m ? g.W * zb : 0.0;
   const double sw = wsum(wl);
   if (lane < m) {
     if (MIXED) {
@@ -330,31 +433,31 @@ __global__ void __launch_bounds__(APC_BLOCK)
 }
 
 // ---------------------------------------------------------------- derivatives
-__global__ void __launch_bounds__(WPB4 * 64)
+__global__ void __launch_bounds__(WPB4 * 64, 2)
     k_node_derivs4(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
                    const int32_t *__restrict__ crd, int64_t ntot, const int8_t *__restrict__ rorder,
                    double unit,
                    const double *__restrict__ f, double *__restrict__ D) {
   __shared__ Wave4 SH[WPB4];
-  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t y = (int64_t)blockIdx.x * WPB4 + wv;
   if (y >= n) return;
   Wave4 &S = SH[wv];
   const int32_t a0 = st_off[y];
   const int m = st_off[y + 1] - a0;
-  double W;
   const int pc = rorder[y] == 4 ? P4 : 9;
-  const int h = stencil_rows(S, lane, st_idx + a0, m, crd, ntot, y, &W);
-  wave_qr(S, lane, pc);
-  const double u = lane < m ? W * (f[st_idx[a0 + lane]] - f[y]) : 0.0;
-  const double qu = apply_qt(S, lane, pc, u);
-  const double ai = solve_r(S, lane, pc, lane < pc ? qu : 0.0);
+  const Geo g = stencil_rows(S, lane, st_idx + a0, m, crd, ntot, y);
+  // W (f_j - f_0) as column pc, transformed by the QR into Q^T W (f_j - f_0)
+  S.A[pc * LD + lane] = lane < m ? g.W * (f[st_idx[a0 + lane]] - f[y]) : 0.0;
+  wsync();
+  col_qr(S, lane, pc, pc + 1);
+  const double ai = solve_r(S, lane, pc, lane < pc ? S.A[lane * RLD + pc] : 0.0);
   if (lane >= pc && lane < P4) D[y * P4 + lane] = 0.0; // order-2 fallback row
   if (lane < pc) {
     int ax, ay, az;
     alpha4(lane, ax, ay, az);
     double hk = 1.0;
-    const double hp = (double)h * unit;
+    const double hp = (double)g.h * unit;
     for (int q = 0; q < ax + ay + az; q++) hk *= hp;
     D[y * P4 + lane] = ai / hk;
   }
