@@ -151,7 +151,8 @@ def precond_roofline(torch, cloud, reps):
     # uniform rows: 24 indices + level byte (per-level M rows stay in cache);
     # general rows: index + FP32 weight per stored entry of M (the first 40
     # stencil entries) and an FP32 diagonal; every row: row id, in_i, out_i
-    byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["m_entries"] * 8 + n_gen * 4
+    ib = index_bytes(cloud)
+    byts = (oi["n_uniform"] * (24 * ib + 1) + oi["m_entries"] * (ib + 4) + n_gen * 4
             + cloud.n * (4 + 8 + 8))
     gbs = byts / (ms * 1e-3) / 1e9
     return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
@@ -184,6 +185,12 @@ def counted_traffic(workload):
         return None
 
 
+def index_bytes(cloud):
+    """Bytes per column index the operator kernels read: 3 (a 16-bit and an 8-bit
+    part), 4 for clouds of 2^24 nodes or more."""
+    return 4 if cloud.n + cloud.nb >= 1 << 24 else 3
+
+
 def spmv_roofline(torch, cloud, reps, mixed, workload):
     """Average duration of the operator SpMV (the solver's dominant kernel) over
     `reps` back-to-back launches, HIP events on the library's stream."""
@@ -202,10 +209,11 @@ def spmv_roofline(torch, cloud, reps, mixed, workload):
     n = cloud.n
     oi = cloud.operator_info()
     vbytes = 4 if mixed else 8
+    ib = index_bytes(cloud)
     # algorithmic bytes (padding excluded): uniform 2-ring rows read 24 column
     # indices and their level, other rows column index + weight per entry; every
     # row reads its row id, x_i and writes y_i (x_j gathers counted once, in x_i)
-    byts = (oi["n_uniform"] * (24 * 4 + 1) + oi["nnz_general"] * (4 + vbytes)
+    byts = (oi["n_uniform"] * (24 * ib + 1) + oi["nnz_general"] * (ib + vbytes)
             + n * (4 + 8 + 8))
     gbs = byts / (ms * 1e-3) / 1e9
     traffic = counted_traffic(workload) if mixed else None

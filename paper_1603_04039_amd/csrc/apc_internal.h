@@ -151,8 +151,14 @@ struct apc_cloud {
   int32_t *sl_rows = nullptr;  // nsl * 64 row ids (-1 = padding lane)
   int32_t *sl_len = nullptr;   // entries per row in the slice
   int32_t *sl_tmpl = nullptr;  // 1: uniform 2-ring slice (no weights); 32-bit: scalar loads
-  int64_t *sl_off = nullptr;   // first entry of the slice
+  int64_t *sl_off = nullptr;   // first entry of the slice (a multiple of 4 x 64: slices
+                               // hold a multiple of 4 entries per row)
   int32_t *sl_idx = nullptr;   // column indices, entry-major within a slice
+  // compact copy of sl_idx read by the operator kernels: low 16 bits two entries per
+  // word, bits 16..23 four entries per word, bits 24..31 likewise (only when the
+  // cloud has 2^24 nodes or more); entry k of lane r of the slice at entry offset o
+  // is in word o/2 + 64 (k/2) + r (low) and o/4 + 64 (k/4) + r (high, top)
+  uint32_t *sl_lo2 = nullptr, *sl_hi4 = nullptr, *sl_top4 = nullptr;
   double *sl_w64 = nullptr;    // weights (general slices), APC_FP64
   float *sl_w32 = nullptr;     // weights (general slices), mixed modes
   apc_solver_ws *ws = nullptr;
@@ -212,6 +218,8 @@ int apc_batch_solve_impl(apc_batch *B, const double *rho_t, const double *g, dou
 int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, hipStream_t s);
 void apc_free_solver(apc_cloud *c);
 int apc_build_sell(apc_cloud *c, hipStream_t s);
+// (re)build sl_lo2 / sl_hi4 / sl_top4 from sl_idx (allocates them)
+int apc_pack_sell_idx(apc_cloud *c, hipStream_t s);
 void apc_free_sell(apc_cloud *c);
 // stencil rank test of pending nodes (k = 2); clears m[y] of rejected nodes
 int apc_rank_check(const apc_cloud *c, int order, const int32_t *pending, int64_t np,

@@ -565,6 +565,7 @@ int merge(apc_batch *B, std::vector<apc_cloud *> &cl, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(u->st_off + nall, &nnz32, 4, hipMemcpyHostToDevice, s));
   if (u->sl_w32) HIPCHK(hipMemsetAsync(u->sl_w32, 0, (size_t)(entall > 0 ? entall : 1) * 4, s));
   if (u->sl_w64) HIPCHK(hipMemsetAsync(u->sl_w64, 0, (size_t)(entall > 0 ? entall : 1) * 8, s));
+  APCCHK(apc_pack_sell_idx(u, s)); // the operator kernels' copy of the union's column indices
   // 8 contiguous slice ranges, one per XCD, balanced by slice count
   for (int k = 0; k <= 8; k++) u->sl_cs[k] = (int64_t)k * nslall / 8;
   // row blocks of the vector kernels: each inside one cloud

@@ -84,12 +84,12 @@ __global__ void __launch_bounds__(SL)
   if (lane == 0) {
     sl_len[s] = len;
     sl_tmpl[s] = type == 0 ? 1 : 0;
-    sl_ent[s] = (int64_t)len * SL;
+    sl_ent[s] = (int64_t)((len + 3) & ~3) * SL; // storage padded to a multiple of 4 entries
   }
 }
 
-// column indices of every slice (structure only); weights start at 0 so that
-// padding entries contribute nothing
+// column indices of every slice (structure only), storage padding included;
+// weights start at 0 so that padding entries contribute nothing
 __global__ void __launch_bounds__(SL)
     k_sell_idx(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
                const int64_t *__restrict__ sl_off, const int32_t *__restrict__ st_off,
@@ -101,7 +101,34 @@ __global__ void __launch_bounds__(SL)
   const int64_t off = sl_off[s] + lane;
   const int32_t a = row >= 0 ? st_off[row] : 0;
   const int m = row >= 0 ? st_off[row + 1] - a : 0;
-  for (int k = 0; k < len; k++) idx[off + (int64_t)k * SL] = k < m ? st_idx[a + k] : (row >= 0 ? row : 0);
+  const int len4 = (len + 3) & ~3;
+  for (int k = 0; k < len4; k++) idx[off + (int64_t)k * SL] = k < m ? st_idx[a + k] : (row >= 0 ? row : 0);
+}
+
+// the compact copy of the column indices (layout in apc_cloud::sl_lo2)
+__global__ void __launch_bounds__(SL)
+    k_pack_idx(const int32_t *__restrict__ sl_len, const int64_t *__restrict__ sl_off,
+               const int32_t *__restrict__ idx, uint32_t *__restrict__ lo2,
+               uint32_t *__restrict__ hi4, uint32_t *__restrict__ top4) {
+  const int64_t s = blockIdx.x;
+  const int lane = threadIdx.x;
+  const int len4 = (sl_len[s] + 3) & ~3;
+  const int64_t o = sl_off[s];
+  for (int k = 0; k < len4; k += 4) {
+    uint32_t v[4];
+#pragma unroll
+    for (int q = 0; q < 4; q++) v[q] = (uint32_t)idx[o + (int64_t)(k + q) * SL + lane];
+    lo2[o / 2 + (int64_t)SL * (k / 2) + lane] = (v[0] & 0xffffu) | (v[1] << 16);
+    lo2[o / 2 + (int64_t)SL * (k / 2 + 1) + lane] = (v[2] & 0xffffu) | (v[3] << 16);
+    uint32_t h = 0, t = 0;
+#pragma unroll
+    for (int q = 0; q < 4; q++) {
+      h |= ((v[q] >> 16) & 0xffu) << (8 * q);
+      t |= (v[q] >> 24) << (8 * q);
+    }
+    hi4[o / 4 + (int64_t)SL * (k / 4) + lane] = h;
+    if (top4) top4[o / 4 + (int64_t)SL * (k / 4) + lane] = t;
+  }
 }
 
 } // namespace
@@ -191,6 +218,7 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   }
   if (c->sl_w64) HIPCHK(hipMemsetAsync(c->sl_w64, 0, ne * sizeof(double), s));
   if (c->sl_w32) HIPCHK(hipMemsetAsync(c->sl_w32, 0, ne * sizeof(float), s));
+  APCCHK(apc_pack_sell_idx(c, s));
   HIPCHK(hipFreeAsync(ent, s));
   HIPCHK(hipFreeAsync(tf, s));
   HIPCHK(hipFreeAsync(tpos, s));
@@ -199,10 +227,30 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   return APC_OK;
 }
 
+int apc_pack_sell_idx(apc_cloud *c, hipStream_t s) {
+  const size_t ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 4);
+  uint32_t *old[] = {c->sl_lo2, c->sl_hi4, c->sl_top4};
+  for (uint32_t *q : old)
+    if (q) HIPCHK(hipFree(q));
+  c->sl_lo2 = c->sl_hi4 = c->sl_top4 = nullptr;
+  HIPCHK(hipMalloc((void **)&c->sl_lo2, ne / 2 * sizeof(uint32_t)));
+  HIPCHK(hipMalloc((void **)&c->sl_hi4, ne / 4 * sizeof(uint32_t)));
+  if (c->n + c->nb >= ((int64_t)1 << 24))
+    HIPCHK(hipMalloc((void **)&c->sl_top4, ne / 4 * sizeof(uint32_t)));
+  if (c->nsl > 0) {
+    hipLaunchKernelGGL(k_pack_idx, dim3((unsigned)c->nsl), dim3(SL), 0, s, c->sl_len, c->sl_off,
+                       c->sl_idx, c->sl_lo2, c->sl_hi4, c->sl_top4);
+    HIPCHK(hipGetLastError());
+  }
+  return APC_OK;
+}
+
 void apc_free_sell(apc_cloud *c) {
-  void *ptrs[] = {c->sl_rows, c->sl_len, c->sl_tmpl, c->sl_off, c->sl_idx, c->sl_w64, c->sl_w32};
+  void *ptrs[] = {c->sl_rows, c->sl_len, c->sl_tmpl, c->sl_off, c->sl_idx, c->sl_w64, c->sl_w32,
+                  c->sl_lo2, c->sl_hi4, c->sl_top4};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
+  c->sl_lo2 = c->sl_hi4 = c->sl_top4 = nullptr;
   c->sl_rows = c->sl_len = c->sl_idx = c->sl_tmpl = nullptr;
   c->sl_off = nullptr;
   c->sl_w64 = nullptr;

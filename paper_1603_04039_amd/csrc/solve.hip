@@ -195,38 +195,48 @@ __global__ void __launch_bounds__(APC_BLOCK)
 struct MOp {
   const float *diag, *sell, *tmpl;
 };
+template <bool TOP>
+__device__ __forceinline__ void prec_slice(const Op &op, const MOp &M, const double *__restrict__ in,
+                                           double *__restrict__ out, int s) {
+  const int lane = threadIdx.x & 63;
+  const int64_t o = op.sl_off[s];
+  const int64_t off = o + lane, lb = (o >> 1) + lane, hb = (o >> 2) + lane;
+  if (op.sl_tmpl[s]) {
+    int32_t jj[24];
+#pragma unroll
+    for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP>(op, lb, hb, k);
+    const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
+    if (row < 0) return;
+    const float *__restrict__ T = M.tmpl + 25 * (int)op.rk[row];
+    double acc = (double)T[0] * in[row];
+#pragma unroll
+    for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * in[jj[k]];
+    out[row] = acc;
+  } else {
+    // M holds the first APC_MLP_OUT - 1 stencil entries of a row (all of them
+    // for k = 2; the nearest 40 of the up to 56 of k = 4)
+    const int len = min(op.sl_len[s], APC_MLP_OUT - 1);
+    const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
+    if (row < 0) return;
+    const float *__restrict__ wv = M.sell + off;
+    double acc = (double)M.diag[row] * in[row];
+#pragma unroll 8
+    for (int k = 0; k < len; k++) acc += (double)wv[k * SL] * in[sl_col<TOP>(op, lb, hb, k)];
+    out[row] = acc;
+  }
+}
+
+// out = M in over the rows of every slice (the learned preconditioner)
 __global__ void __launch_bounds__(APC_BLOCK)
     k_prec_apply(Op op, MOp M, const double *__restrict__ in, double *__restrict__ out,
                  const Scal *sc) {
   if (sc && sc->done) return;
-  const int lane = threadIdx.x & 63;
   for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
     const int s = __builtin_amdgcn_readfirstlane(it.s);
-    const int64_t off = op.sl_off[s] + lane;
-    const int32_t *__restrict__ ix = op.sl_idx + off;
-    if (op.sl_tmpl[s]) {
-      int32_t jj[24];
-#pragma unroll
-      for (int k = 0; k < 24; k++) jj[k] = ix[k * SL];
-      const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
-      if (row < 0) continue;
-      const float *__restrict__ T = M.tmpl + 25 * (int)op.rk[row];
-      double acc = (double)T[0] * in[row];
-#pragma unroll
-      for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * in[jj[k]];
-      out[row] = acc;
-    } else {
-      // M holds the first APC_MLP_OUT - 1 stencil entries of a row (all of them
-      // for k = 2; the nearest 40 of the up to 56 of k = 4)
-      const int len = min(op.sl_len[s], APC_MLP_OUT - 1);
-      const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
-      if (row < 0) continue;
-      const float *__restrict__ wv = M.sell + off;
-      double acc = (double)M.diag[row] * in[row];
-#pragma unroll 8
-      for (int k = 0; k < len; k++) acc += (double)wv[k * SL] * in[ix[k * SL]];
-      out[row] = acc;
-    }
+    if (op.sl_top4)
+      prec_slice<true>(op, M, in, out, s);
+    else
+      prec_slice<false>(op, M, in, out, s);
   }
 }
 

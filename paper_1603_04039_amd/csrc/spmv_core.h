@@ -22,8 +22,10 @@ struct Op {
   double tc[3];     // shell weights of the uniform 2-ring at h_c = 1
   double invL2;     // 1 / L^2: a level-l row scales tc by 4^l / L^2
   int64_t n;
-  // sliced-ELL copy (the SpMV reads only this)
-  const int32_t *sl_rows, *sl_len, *sl_idx, *sl_tmpl;
+  // sliced-ELL copy (the SpMV reads only this); column indices from the compact
+  // 24-bit copy (plus the top byte for clouds of 2^24 nodes or more)
+  const int32_t *sl_rows, *sl_len, *sl_tmpl;
+  const uint32_t *sl_lo2, *sl_hi4, *sl_top4;
   const int64_t *sl_off;
   const double *sl_w64;
   const float *sl_w32;
@@ -65,24 +67,36 @@ static inline unsigned spmv_grid(const apc_cloud *c) {
   const int64_t g = 8 * per;
   return (unsigned)(g < (int64_t)GSPMV ? g : (int64_t)GSPMV);
 }
+// Column index of entry k of the lane's row: lb = o/2 + lane and hb = o/4 + lane
+// for the slice at entry offset o.  Three bytes per entry (four with TOP): two
+// 32-bit loads cover two and four entries, so a uniform row's 24 indices take 18
+// loads instead of 24.
+template <bool TOP>
+__device__ __forceinline__ int32_t sl_col(const Op &op, int64_t lb, int64_t hb, int k) {
+  const uint32_t lo = (op.sl_lo2[lb + (int64_t)SL * (k >> 1)] >> (16 * (k & 1))) & 0xffffu;
+  const uint32_t hi = (op.sl_hi4[hb + (int64_t)SL * (k >> 2)] >> (8 * (k & 3))) & 0xffu;
+  uint32_t j = lo | (hi << 16);
+  if (TOP) j |= ((op.sl_top4[hb + (int64_t)SL * (k >> 2)] >> (8 * (k & 3))) & 0xffu) << 24;
+  return (int32_t)j;
+}
+
 // (A x)_row for the lane's row of slice s (row = -1 on padding lanes, result 0).
 // Uniform 2-ring slices hold 24 entries ordered by shell (6 at r = 1 cell, 12 at
 // sqrt 2, 6 at 2) and no weights: their index loads go out before the row id.
 // General slices run their entry loop unrolled by 8 so that 8 index/weight loads
 // and then 8 gathers are in flight together.
-template <int MODE>
-__device__ __forceinline__ double sell_apply(const Op &op, const double *__restrict__ x, int s_in,
-                                             int32_t &row) {
-  const int s = __builtin_amdgcn_readfirstlane(s_in);
+template <int MODE, bool TOP>
+__device__ __forceinline__ double sell_apply_t(const Op &op, const double *__restrict__ x, int s,
+                                               int32_t &row) {
   const int lane = threadIdx.x & 63;
-  const int64_t off = op.sl_off[s] + lane;
-  const int32_t *__restrict__ ix = op.sl_idx + off;
+  const int64_t o = op.sl_off[s];
+  const int64_t off = o + lane, lb = (o >> 1) + lane, hb = (o >> 2) + lane;
   double acc;
   double xi;
   if (op.sl_tmpl[s]) {
     int32_t jj[24];
 #pragma unroll
-    for (int k = 0; k < 24; k++) jj[k] = ix[k * SL];
+    for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP>(op, lb, hb, k);
     row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return 0.0;
     xi = x[row];
@@ -116,23 +130,29 @@ __device__ __forceinline__ double sell_apply(const Op &op, const double *__restr
       const float *__restrict__ wv = op.sl_w32 + off;
       float af = 0.f;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) af += wv[k * SL] * (float)(x[ix[k * SL]] - xi);
+      for (int k = 0; k < len; k++) af += wv[k * SL] * (float)(x[sl_col<TOP>(op, lb, hb, k)] - xi);
       acc = (double)af;
     } else if (MODE == V64) {
       const double *__restrict__ wv = op.sl_w64 + off;
       double ad = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) ad += wv[k * SL] * (x[ix[k * SL]] - xi);
+      for (int k = 0; k < len; k++) ad += wv[k * SL] * (x[sl_col<TOP>(op, lb, hb, k)] - xi);
       acc = ad;
     } else {
       const float *__restrict__ wv = op.sl_w32 + off;
       double ad = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (x[ix[k * SL]] - xi);
+      for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (x[sl_col<TOP>(op, lb, hb, k)] - xi);
       acc = ad;
     }
   }
   return op.hs ? xi + op.hs[row] * acc : (op.unit_diag ? xi + acc : acc);
+}
+template <int MODE>
+__device__ __forceinline__ double sell_apply(const Op &op, const double *__restrict__ x, int s_in,
+                                             int32_t &row) {
+  const int s = __builtin_amdgcn_readfirstlane(s_in);
+  return op.sl_top4 ? sell_apply_t<MODE, true>(op, x, s, row) : sell_apply_t<MODE, false>(op, x, s, row);
 }
 
 static inline Op make_op(const apc_cloud *c, bool density) {
@@ -150,7 +170,9 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   op.n = c->n;
   op.sl_rows = c->sl_rows;
   op.sl_len = c->sl_len;
-  op.sl_idx = c->sl_idx;
+  op.sl_lo2 = c->sl_lo2;
+  op.sl_hi4 = c->sl_hi4;
+  op.sl_top4 = c->sl_top4;
   op.sl_tmpl = c->sl_tmpl;
   op.sl_off = c->sl_off;
   op.sl_w64 = b4 ? c->sl_bw64 : c->sl_w64;

@@ -329,3 +329,25 @@ def test_full_size_beam_halo_1e7(apc, oracle_mod):
     rt_g = rho_t.cpu().numpy()
     res = O.apply_laplacian(phi_g) - rt_g[:O.n]
     assert np.linalg.norm(res) <= 1.01e-8 * np.linalg.norm(rt_g[:O.n])
+
+
+@pytest.mark.slow
+def test_column_index_top_byte(apc):
+    """The operator kernels read column indices as 24-bit values plus a top byte
+    once the cloud has 2^24 nodes or more.  A uniform 256^3 lattice has 2^24
+    interior nodes, so every boundary column needs the top byte.  Its rows are
+    exact on quadratics (Sec. 3.1), so L f must equal the Laplacian of f at every
+    interior node, including the rows next to the boundary."""
+    note("index top byte: 256^3 lattice (2^24 interior nodes)")
+    xyz = uniform_lattice_points(8)
+    G = gcloud(apc, xyz, order=2, c=1e-3, max_depth=8, precision=apc.APC_FP64)
+    assert G.n == 1 << 24 and G.n + G.nb >= 1 << 24
+    G.assemble_gfd()
+    ix = G.nodes()["ixyz"].astype(np.float64)
+    x, y, z = (G.lo[:, None] + G.unit * ix)
+    f = x * x + 2.0 * y * y - z * z + 0.5 * x - y + 0.25 * z
+    out = G.apply_operator(torch.from_numpy(f).cuda()).cpu().numpy()
+    err = np.abs(out - 4.0)
+    note(f"index top byte: max |L f - 4| = {err.max():.2e} over {G.n} rows")
+    assert err.max() <= 1e-6
+    G.close()
