@@ -131,7 +131,6 @@ struct apc_cloud {
   // k = 4: density operator rows (B has its own weights; row sums are 1)
   double *bw64 = nullptr, *sl_bw64 = nullptr;
   float *bw32 = nullptr, *sl_bw32 = nullptr;
-  uint8_t *fp64row = nullptr;                  // n (APC_MIXED): refitted in FP64
   int64_t n_fp64_rows = 0;
   apc_asm_scratch *scratch = nullptr;
   // learned preconditioner M: diagonal per row, off-diagonal weights in the

@@ -536,7 +536,7 @@ void apc_free_cloud(apc_cloud *c) {
   apc_free_solver(c);
   apc_free_sell(c);
   free_cloud_arrays(c);
-  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->fp64row, c->rkind, c->scratch,
+  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, c->scratch,
                  c->m_diag, c->m_sell, c->m_tmpl, c->bw64, c->bw32, c->sl_bw64, c->sl_bw32,
                  c->rorder};
   for (void *q : ops)

@@ -49,6 +49,9 @@ __device__ inline NodeGeom node_geom(const int32_t *nb, int m, const int32_t *__
   g.c2 = crd[2 * ntot + y];
   int32_t h = 0;
   int64_t r2max = 0;
+  // loops over the stencil are unrolled by 4 so that four neighbours' coordinate
+  // gathers are in flight together (the loads of a neighbour depend on its index)
+#pragma unroll 4
   for (int j = 0; j < m; j++) {
     const int32_t v = nb[j];
     const int32_t d0 = crd[v] - g.c0, d1 = crd[ntot + v] - g.c1, d2 = crd[2 * ntot + v] - g.c2;
@@ -79,6 +82,7 @@ __device__ inline void gram(const int32_t *nb, int m, const NodeGeom &g,
                             const int32_t *__restrict__ crd, int64_t ntot, T G[G45]) {
 #pragma unroll
   for (int k = 0; k < G45; k++) G[k] = T(0);
+#pragma unroll 4
   for (int j = 0; j < m; j++) {
     T vv[P9];
     const T w2 = row_w2<T>(g, crd, ntot, nb[j], vv);
@@ -230,12 +234,58 @@ __global__ void __launch_bounds__(APC_BLOCK)
   rkind[y] = tmpl ? (int8_t)l : (int8_t)-1;
 }
 
+// FP64 fit of a general row: weights into the CSR copy and the slice (FP32 storage
+// in the mixed modes), diagonal; returns the R-diagonal ratio.
+template <bool MIXED>
+__device__ inline double fit64_row(int32_t row, int64_t off, const int32_t *__restrict__ st_off,
+                                   const int32_t *__restrict__ st_idx, const int32_t *__restrict__ crd,
+                                   int64_t ntot, double unit, double *__restrict__ w64,
+                                   float *__restrict__ w32, double *__restrict__ sw64,
+                                   float *__restrict__ sw32, double *__restrict__ diag,
+                                   double *__restrict__ inv_diag) {
+  const int32_t a = st_off[row];
+  const int m = st_off[row + 1] - a;
+  const int32_t *nb = st_idx + a;
+  const NodeGeom g = node_geom(nb, m, crd, ntot, row);
+  const double hp = (double)g.h * unit;
+  const double inv_h2 = 1.0 / (hp * hp);
+  double z[P9];
+  const double ratio = lap_fit<double>(nb, m, g, crd, ntot, z);
+  double sum = 0.0;
+#pragma unroll 4
+  for (int j = 0; j < m; j++) {
+    double vv[P9];
+    const double w2 = row_w2<double>(g, crd, ntot, nb[j], vv);
+    double dotv = 0.0;
+#pragma unroll
+    for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
+    const double w = w2 * dotv * inv_h2;
+    const int64_t e = off + (int64_t)j * APC_SLICE;
+    if (MIXED) {
+      const float wf = (float)w;
+      w32[a + j] = wf;
+      sw32[e] = wf;
+      sum += (double)wf;
+    } else {
+      w64[a + j] = w;
+      sw64[e] = w;
+      sum += w;
+    }
+  }
+  diag[row] = -sum;
+  inv_diag[row] = -1.0 / sum;
+  return ratio;
+}
+
 // One wavefront per slice of the sliced layout (indices were laid out at build).
 // Uniform slices: the rows' diagonal from the canonical shell constants (their
 // CSR weights are implied by rkind and are not stored).  General slices: fit
-// each row (FP64, or FP32 in the mixed modes with an FP64 refit when
-// min|R_ii|/max|R_ii| < APC_TAU_FP32), write its weights to the CSR copy and to
-// the slice (entry-major, coalesced); padding entries keep weight 0.
+// each row (FP64, or FP32 in the mixed modes), write its weights to the CSR copy
+// and to the slice (entry-major, coalesced); padding entries keep weight 0.  In
+// the mixed modes a row whose FP32 Cholesky gives min|R_ii|/max|R_ii| <
+// APC_TAU_FP32 is refitted in FP64 right away, while its neighbours'
+// coordinates are still in cache (a separate refit kernel over a list of such
+// rows measured slower: 339 against 284 us on 1.01e6 nodes).
 template <bool MIXED>
 __global__ void __launch_bounds__(APC_BLOCK)
     k_fit_sell(int64_t nsl, const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
@@ -252,7 +302,6 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int32_t row = sl_rows[s * APC_SLICE + lane];
   if (row < 0) return;
   const int64_t off = sl_off[s] + lane;
-  const int len = sl_len[s];
   const double hc = L / (double)(1 << level[row]);
   hscale[row] = hc * hc / 24.0;
   if (sl_tmpl[s]) {
@@ -267,59 +316,40 @@ __global__ void __launch_bounds__(APC_BLOCK)
     inv_diag[row] = -1.0 / sum;
     return;
   }
+  if (!MIXED) {
+    const double ratio = fit64_row<false>(row, off, st_off, st_idx, crd, ntot, unit, w64, w32,
+                                          sw64, sw32, diag, inv_diag);
+    if (!(ratio >= APC_TAU_RANK)) atomicOr(err, 1);
+    return;
+  }
   const int32_t a = st_off[row];
   const int m = st_off[row + 1] - a;
   const int32_t *nb = st_idx + a;
   const NodeGeom g = node_geom(nb, m, crd, ntot, row);
   const double hp = (double)g.h * unit;
   const double inv_h2 = 1.0 / (hp * hp);
+  float z[P9];
+  const float ratio = lap_fit<float>(nb, m, g, crd, ntot, z);
+  if (!(ratio >= (float)APC_TAU_FP32)) {
+    atomicAdd(nfp64, 1ull);
+    const double r64 = fit64_row<true>(row, off, st_off, st_idx, crd, ntot, unit, w64, w32, sw64,
+                                       sw32, diag, inv_diag);
+    if (!(r64 >= APC_TAU_RANK)) atomicOr(err, 1);
+    return;
+  }
   double sum = 0.0;
-  bool done = false;
-  if (MIXED) {
-    float z[P9];
-    const float ratio = lap_fit<float>(nb, m, g, crd, ntot, z);
-    if (ratio >= (float)APC_TAU_FP32) {
-      for (int j = 0; j < m; j++) {
-        float vv[P9];
-        const float w2 = row_w2<float>(g, crd, ntot, nb[j], vv);
-        float dotv = 0.f;
+#pragma unroll 4
+  for (int j = 0; j < m; j++) {
+    float vv[P9];
+    const float w2 = row_w2<float>(g, crd, ntot, nb[j], vv);
+    float dotv = 0.f;
 #pragma unroll
-        for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
-        const float wf = (float)((double)(w2 * dotv) * inv_h2);
-        w32[a + j] = wf;
-        sw32[off + (int64_t)j * APC_SLICE] = wf;
-        sum += (double)wf;
-      }
-      done = true;
-    } else {
-      atomicAdd(nfp64, 1ull);
-    }
+    for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
+    const float wf = (float)((double)(w2 * dotv) * inv_h2);
+    w32[a + j] = wf;
+    sw32[off + (int64_t)j * APC_SLICE] = wf;
+    sum += (double)wf;
   }
-  if (!done) {
-    double z[P9];
-    const double ratio = lap_fit<double>(nb, m, g, crd, ntot, z);
-    if (!(ratio >= APC_TAU_RANK)) atomicOr(err, 1);
-    for (int j = 0; j < m; j++) {
-      double vv[P9];
-      const double w2 = row_w2<double>(g, crd, ntot, nb[j], vv);
-      double dotv = 0.0;
-#pragma unroll
-      for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
-      const double w = w2 * dotv * inv_h2;
-      const int64_t e = off + (int64_t)j * APC_SLICE;
-      if (MIXED) {
-        const float wf = (float)w;
-        w32[a + j] = wf;
-        sw32[e] = wf;
-        sum += (double)wf;
-      } else {
-        w64[a + j] = w;
-        sw64[e] = w;
-        sum += w;
-      }
-    }
-  }
-  (void)len;
   diag[row] = -sum;
   inv_diag[row] = -1.0 / sum;
 }
@@ -480,18 +510,19 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
   }
   HIPCHK(hipMemsetAsync(&c->scratch->nfp64, 0, sizeof(unsigned long long), s));
   if (c->nsl > 0) {
-    if (mixed)
+    if (mixed) {
       hipLaunchKernelGGL(k_fit_sell<true>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,
                          c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
                          c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
                          c->inv_diag, c->hscale, c->sl_w64, c->sl_w32, &c->scratch->err,
                          &c->scratch->nfp64);
-    else
+    } else {
       hipLaunchKernelGGL(k_fit_sell<false>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,
                          c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
                          c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
                          c->inv_diag, c->hscale, c->sl_w64, c->sl_w32, &c->scratch->err,
                          &c->scratch->nfp64);
+    }
     HIPCHK(hipGetLastError());
   }
   c->assembled = true;
