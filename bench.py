@@ -131,6 +131,48 @@ def stream_probe(torch, mib=1024, reps=10):
                 GBs=round(2 * n * 8 / (ms * 1e-3) / 1e9, 1))
 
 
+def assembly_roofline(torch, cloud, reps, mixed):
+    """Average duration of apc_assemble_gfd (HIP events, reps back-to-back calls)
+    with its algorithmic bytes and flops, as fractions of the HBM peak and of the
+    vector peak of the fit's precision.  k = 2 counts the general rows' FP32 (mixed)
+    or FP64 normal-equation fits: per stencil entry ~160 flop (monomials, Gaussian
+    weight, 45 Gram FMAs, weight pass), per row ~650 (9 x 9 Cholesky and solves);
+    bytes: CSR indices and the two weight copies per entry, the coordinate array
+    once, per-row metadata.  k = 4 counts the FP64 Householder QR of the 56 x 34
+    systems, 2 m p^2 - 2 p^3 / 3 + 4 m p per node."""
+    stream = torch.cuda.current_stream()
+    for _ in range(2):
+        cloud.assemble_gfd()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    for _ in range(reps):
+        cloud.assemble_gfd()
+    e1.record(stream)
+    e1.synchronize()
+    us = e0.elapsed_time(e1) / reps * 1e3
+    oi = cloud.operator_info()
+    n, ntot = cloud.n, cloud.n + cloud.nb
+    wb = 4 if mixed else 8
+    if cloud.p == 9:
+        n_u, nnz_g = oi["n_uniform"], oi["nnz_general"]
+        n_g = n - n_u
+        byts = n_u * 32 + n_g * 52 + nnz_g * (4 + 2 * wb) + ntot * 12
+        flops = nnz_g * 160 + n_g * 650
+        peak = 157300.0 if mixed else 78600.0
+    else:
+        p, nnz = 34, cloud.nnz
+        byts = nnz * (4 + 2 * wb) + n * 44 + ntot * 12
+        flops = 2 * p * p * nnz - (2.0 / 3.0) * p ** 3 * n + 4 * p * nnz
+        peak = 78600.0
+    gbs = byts / (us * 1e-6) / 1e9
+    gfl = flops / (us * 1e-6) / 1e9
+    return dict(avg_us=round(us, 1), bytes_per_launch=int(byts), GBs=round(gbs, 1),
+                hbm_frac=round(gbs / HBM_PEAK_GBS, 4), gflop_per_launch=round(flops / 1e9, 3),
+                GFLOPs=round(gfl, 1), valu_peak_GFLOPs=peak, valu_frac=round(gfl / peak, 4),
+                bound="latency of the per-row neighbour gathers (neither HBM nor VALU)")
+
+
 def precond_roofline(torch, cloud, reps):
     """Average duration of the learned M apply (k_prec_apply), same method."""
     stream = torch.cuda.current_stream()
@@ -368,6 +410,10 @@ def main():
     if args.precond == "learned":
         roof_m = precond_roofline(torch, cloud, args.spmv_reps)
         log(f"precond roofline: {roof_m}")
+    # last: re-assembly drops the learned M
+    roof_a = assembly_roofline(torch, cloud, 10 if cloud.n < 5_000_000 else 3,
+                               prec != apc.APC_FP64)
+    log(f"assembly roofline: {roof_a}")
     cloud.close()
 
     plain = None
@@ -412,6 +458,7 @@ def main():
                                             halo_frac=c4["halo_frac"])).cuda()
             ms4, info4, _, cl4, _ = run_steps(apc, torch, x4, c4, apc.APC_MIXED, 1, 0, args.tol)
             r4 = spmv_roofline(torch, cl4, 10, True, "beam_halo_1e8_k4")
+            a4 = assembly_roofline(torch, cl4, 2, True)
             cl4.close()
 
             def leg(ms, info):
@@ -424,7 +471,8 @@ def main():
             k4 = dict(workload="beam_halo_1e8_k4", particles=c4["N"], nodes=info4["n"],
                       nnz=info4["nnz"], order=4, max_depth=c4["max_depth"], c=c4["c"],
                       precision="mixed", jacobi=leg(ms4, info4),
-                      spmv=dict(avg_us=r4["avg_us"], GBs=r4["achieved"], frac=r4["frac"]))
+                      spmv=dict(avg_us=r4["avg_us"], GBs=r4["achieved"], frac=r4["frac"]),
+                      assembly=a4)
             log(f"k4 jacobi: {k4['jacobi']}")
             p4, p4src = load_params(apc, torch, 4)
             ms4l, info4l, _, cl4, _ = run_steps(apc, torch, x4, c4, apc.APC_MIXED, 1, 0, args.tol,
@@ -470,6 +518,7 @@ def main():
                   "rel_resid_true": info["rel_resid_true"],
                   "density_iters": info["density_iters"]},
         "roofline": roof,
+        "roofline_assembly": roof_a,
         "cpu_baseline": cpu,
     }
     if batch is not None:
