@@ -102,8 +102,16 @@ void apc_default_params(apc_params *p, int order);
    particles, the error-balance criterion opening cells with N' >= T_l where
    T_l = t^(2k-2), t = (c 2^l) / L evaluated in FP64 by repeated multiplication,
    level-by-level 2:1 face balance to the unique minimal balanced refinement,
-   boundary face nodes, and per-node GFD stencils from the k-ring (Sec. 3.1
-   octant rule; see the library documentation for the exact acceptance test).
+   boundary face nodes, and per-node GFD stencils from the R-ring (Sec. 3.1,
+   4.3).  Stencil rule: the ring's nodes sorted by (squared distance, index); the
+   two nearest of every closed octant (a zero offset counts on both sides), for
+   k = 4 then per axis the nearest with a new offset until the axis has 5
+   distinct offsets, then the nearest remaining, up to m_cap nodes.  Accepted when
+   every closed octant holds a chosen node, m >= p + 1, the weighted V0 has
+   min|R_ii| / max|R_ii| >= 1e-6, and (k = 4) the Laplacian row has a negative
+   diagonal d with sum |w_j| <= 10 |d|; otherwise R grows from ring_min to
+   ring_max.  A k = 4 node with no acceptable stencil takes an order-2 row (ring
+   2, m_cap 40); past ring_max at order 2 the build fails (APC_ESTENCIL).
    xyz: 3 x N float64, read during the call and copied (sorted) into the
    handle.  Errors: APC_EINVAL (parameters, NaN), APC_EDOMAIN (a particle outside
    Omega), APC_ESTENCIL, APC_ENOMEM, APC_EHIP.  Synchronises the stream. */
@@ -130,8 +138,11 @@ int apc_get_nodes(const apc_cloud *c, int32_t *perm_host, uint64_t *code_host,
 /* Assemble the GFD Poisson operator (Sec. 3.1, 3.2 step 2): per node the weighted
    least-squares fit of the scaled Taylor Vandermonde V0 over its stencil
    (h = max |delta|, Gaussian weight with c = 4), giving the off-diagonal weights
-   w_ij of Delta at node i; the diagonal is -sum_j w_ij.  Must follow
-   apc_build_cloud.  Does not synchronise. */
+   w_ij of Delta at node i; the diagonal is -sum_j w_ij.  k = 2: normal equations
+   and Cholesky per node (FP32 with an FP64 refit of ill-conditioned rows in the
+   mixed modes, FP64 otherwise).  k = 4: Householder QR in FP64 in every mode,
+   also giving the rows of the density operator B.  Must follow apc_build_cloud.
+   Does not synchronise. */
 int apc_assemble_gfd(apc_cloud *c, hipStream_t stream);
 
 /* Host copy of the assembled operator: w_host[nnz] aligned with the stencil

@@ -427,7 +427,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
 
 // Rank test of candidate stencils: k = 2 clouds by the per-thread Cholesky of the
 // 9x9 normal equations; k = 4 clouds (order-4 rows and their order-2 fallback
-// rows) by the wavefront Householder QR, the oracle's algorithm.
+// rows) by the column-parallel Householder QR (one wavefront per candidate
+// stencil), the oracle's algorithm.
 int apc_rank_check(const apc_cloud *c, int order, const int32_t *pending, int64_t np,
                    const int32_t *cand, int32_t *m, hipStream_t s) {
   if (c->P.order == 4) return apc_rank_check4(c, order == 4 ? 34 : 9, pending, np, cand, m, s);
