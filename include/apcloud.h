@@ -71,7 +71,7 @@ typedef struct apc_cloud apc_cloud;
 typedef struct {
   double lo[3];     /* domain Omega = [lo, lo + L]^3 */
   double L;         /* domain edge, > 0 */
-  int order;        /* GFD order k (Sec. 3.1): 2 */
+  int order;        /* GFD order k (Sec. 3.1): 2 or 4 */
   double c;         /* error-balance constant (Sec. 4.3, eq. errorbalance_implementation), > 0 */
   int max_depth;    /* deepest octree level, 1..20 */
   int ring_min;     /* first k-ring searched for a stencil (Sec. 4.3); 2 for k = 2 */
@@ -79,6 +79,10 @@ typedef struct {
   int m_cap;        /* stencil size cap (<= 64); 40 for k = 2 */
   double poisson_c; /* c in Delta phi = c rho (eq. Poisson); 1 */
   int precision;    /* APC_FP64, APC_MIXED or APC_MIXED_F32ACC, fixed at build time */
+  int stage_cap;    /* operator kernels: a 64-row slice with at most this many distinct
+                       neighbour columns gathers them once into LDS (performance only,
+                       same results bit for bit); 0 = default (1008, also the maximum),
+                       -1 = never */
 } apc_params;
 
 typedef struct {
@@ -154,10 +158,15 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host);
    shared shell constants and are not read), nnz_general entries belong to the
    other rows, sell_entries is the padded entry count of the sliced layout,
    m_entries the off-diagonal entries the learned M stores for the other rows
-   (min(m, APC_MLP_OUT - 1) per row).  Any output may be NULL; m_entries copies
-   the stencil offsets to the host (n+1 int32) and synchronises the device. */
+   (min(m, APC_MLP_OUT - 1) per row).  staged[4], if not NULL, receives the
+   neighbour staging of the operator kernels: the number of 64-row slices whose
+   distinct neighbour columns are gathered once into LDS, the sum of those
+   distinct-column counts, the entries those slices read (row length x 64 each),
+   and the LDS tile in doubles per wavefront (0: no slice staged).  Any output may
+   be NULL; m_entries and staged copy device arrays to the host and synchronise
+   the device. */
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
-                      int64_t *sell_entries, int64_t *m_entries);
+                      int64_t *sell_entries, int64_t *m_entries, int64_t *staged);
 
 /* WLS charge assignment (Sec. 3.2 step 1): rho_M_j = (1/h_j^3) sum_{i in cell j} q_i
    (NGP kernel: the node's own octree cell, edge h_j), then B rho~ = rho_M with

@@ -43,7 +43,7 @@ class Params(ct.Structure):
     _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
-                ("precision", ct.c_int)]
+                ("precision", ct.c_int), ("stage_cap", ct.c_int)]
 
 
 class Stats(ct.Structure):
@@ -83,7 +83,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_get_nodes.argtypes = [P] * 11
     lib.apc_assemble_gfd.argtypes = [P, P]
     lib.apc_get_operator.argtypes = [P, P, P]
-    lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 4
+    lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 5
     lib.apc_get_node_orders.argtypes = [P, P]
     lib.apc_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
@@ -132,7 +132,8 @@ def _check(rc, what):
 
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
-                ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64) -> Params:
+                ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64,
+                stage_cap=0) -> Params:
     p = Params()
     load_library().apc_default_params(ct.byref(p), order)
     p.lo[:] = lo
@@ -146,6 +147,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
         p.m_cap = m_cap
     p.poisson_c = poisson_c
     p.precision = precision
+    p.stage_cap = stage_cap
     return p
 
 
@@ -236,13 +238,18 @@ class Cloud:
                                          d.ctypes.data_as(ct.c_void_p)), "apc_get_operator")
         return w, d
 
-    def operator_info(self, m_entries=False):
+    def operator_info(self, m_entries=False, staged=False):
         v = [ct.c_int64() for _ in range(4)]
-        refs = [ct.byref(x) for x in v[:3]] + [ct.byref(v[3]) if m_entries else None]
+        st = (ct.c_int64 * 4)()
+        refs = ([ct.byref(x) for x in v[:3]] + [ct.byref(v[3]) if m_entries else None]
+                + [ct.cast(st, ct.POINTER(ct.c_int64)) if staged else None])
         _check(self.lib.apc_operator_info(self.h, *refs), "apc_operator_info")
         out = dict(n_uniform=v[0].value, nnz_general=v[1].value, sell_entries=v[2].value)
         if m_entries:
             out["m_entries"] = v[3].value
+        if staged:
+            out.update(staged_slices=st[0], staged_distinct=st[1], staged_entries=st[2],
+                       stage_tile=st[3])
         return out
 
     def deposit(self, q=None, tol=1e-12, maxit=1000, stream=None, rho_M=None, rho_t=None):

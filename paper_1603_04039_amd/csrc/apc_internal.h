@@ -11,15 +11,21 @@
 #define APC_MAXM 64      // hard stencil cap: one wavefront
 #define APC_RING_CAP 16384 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
-#define APC_TAU_DOM 10.0
+#define APC_TAU_DOM 10.0  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
 // window of the length sort of general rows in the sliced layout (SELL-C-sigma;
 // a multiple of the 64-row slice, 64 = no sort)
 #ifndef APC_SELL_SIGMA
 #define APC_SELL_SIGMA 256
-#endif  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
+#endif
+// most distinct neighbour columns of a slice staged in LDS (per wavefront; a
+// slice with more gathers directly).  1008 doubles a wave keep a 256-thread
+// block at 32,256 bytes, five blocks per 160 KB compute unit.
+#ifndef APC_UCAP_MAX
+#define APC_UCAP_MAX 1008
+#endif
 #define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
-#define APC_TAU_FP32 0.1
-#define APC_MAX_LEVELS 24 // > max_depth (<= 20): per-level tables  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
+#define APC_TAU_FP32 0.1  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
+#define APC_MAX_LEVELS 24 // > max_depth (<= 20): per-level tables
 
 void apc_set_hip_error(hipError_t e, const char *what, const char *file, int line);
 
@@ -158,6 +164,15 @@ struct apc_cloud {
   // cloud has 2^24 nodes or more); entry k of lane r of the slice at entry offset o
   // is in word o/2 + 64 (k/2) + r (low) and o/4 + 64 (k/4) + r (high, top)
   uint32_t *sl_lo2 = nullptr, *sl_hi4 = nullptr, *sl_top4 = nullptr;
+  // neighbour staging: slice s with sl_un[s] > 0 first gathers its sl_un[s]
+  // distinct columns, listed ascending in sl_uq[sl_off[s] ..], into an LDS tile of
+  // ucap doubles per wavefront; entry k of lane r then reads tile slot
+  // (sl_lx2[o/2 + 64 (k/2) + r] >> 16 (k%2)) & 0xffff.  sl_un[s] = 0: the slice
+  // gathers through sl_lo2 / sl_hi4 / sl_top4.  ucap = 0: no slice is staged.
+  int32_t *sl_un = nullptr;
+  int32_t *sl_uq = nullptr;
+  uint32_t *sl_lx2 = nullptr;
+  int ucap = 0;
   double *sl_w64 = nullptr;    // weights (general slices), APC_FP64
   float *sl_w32 = nullptr;     // weights (general slices), mixed modes
   apc_solver_ws *ws = nullptr;
@@ -217,7 +232,8 @@ int apc_batch_solve_impl(apc_batch *B, const double *rho_t, const double *g, dou
 int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, hipStream_t s);
 void apc_free_solver(apc_cloud *c);
 int apc_build_sell(apc_cloud *c, hipStream_t s);
-// (re)build sl_lo2 / sl_hi4 / sl_top4 from sl_idx (allocates them)
+// (re)build sl_lo2 / sl_hi4 / sl_top4 and the neighbour staging from sl_idx
+// (allocates them)
 int apc_pack_sell_idx(apc_cloud *c, hipStream_t s);
 void apc_free_sell(apc_cloud *c);
 // stencil rank test of pending nodes (k = 2); clears m[y] of rejected nodes

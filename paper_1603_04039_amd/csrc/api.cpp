@@ -152,7 +152,7 @@ int apc_get_node_orders(const apc_cloud *c, int8_t *order_host) {
 }
 
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
-                      int64_t *sell_entries, int64_t *m_entries) {
+                      int64_t *sell_entries, int64_t *m_entries, int64_t *staged) {
   if (!c || !c->assembled) return APC_EINVAL;
   if (n_uniform) *n_uniform = c->n_template;
   if (nnz_general) *nnz_general = c->nnz - 24 * c->n_template;
@@ -169,6 +169,23 @@ int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_gener
     for (int64_t i = 0; i < c->n; i++)
       if (rk[i] < 0) tot += std::min<int64_t>(off[i + 1] - off[i], APC_MLP_OUT - 1);
     *m_entries = tot;
+  }
+  if (staged) {
+    staged[0] = staged[1] = staged[2] = 0;
+    staged[3] = c->ucap;
+    if (c->ucap > 0 && c->nsl > 0) {
+      DeviceGuard g(c->device);
+      if (!g.ok) return APC_EHIP;
+      std::vector<int32_t> un((size_t)c->nsl), len((size_t)c->nsl);
+      HIPCHK(hipMemcpy(un.data(), c->sl_un, un.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(len.data(), c->sl_len, len.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
+      for (int64_t s = 0; s < c->nsl; s++)
+        if (un[s] > 0) {
+          staged[0] += 1;
+          staged[1] += un[s];
+          staged[2] += (int64_t)len[s] * APC_SLICE;
+        }
+    }
   }
   return APC_OK;
 }

@@ -619,7 +619,7 @@ int ensure_bws(apc_batch *B) {
 template <int MODE>
 void launch_restart(apc_batch *B, const Op &op, const BDesc &D, int first, hipStream_t s) {
   const unsigned g = batch_spmv_grid(B);
-  hipLaunchKernelGGL(kb_restart<MODE>, dim3(g), dim3(APC_BLOCK), 0, s, op, D, (const BScal *)B->sc,
+  hipLaunchKernelGGL(kb_restart<MODE>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, D, (const BScal *)B->sc,
                      (const double *)B->b, (const double *)B->x, B->r, B->rh, B->p, B->v, B->part_sl,
                      first);
   hipLaunchKernelGGL(kb_fin_restart, dim3(B->count), dim3(FB), 0, s, D, (const double *)B->part_sl,
@@ -635,13 +635,13 @@ void launch_iteration(apc_batch *B, const Op &op, const BDesc &D, const double *
   double *sh = JAC ? B->sh : B->s;
   hipLaunchKernelGGL(kb_upd_p<JAC>, dim3(gr), dim3(RB), 0, s, D, sc, (const double *)B->r, B->p,
                      (const double *)B->v, ph, invd);
-  hipLaunchKernelGGL(kb_spmv_v<MODE>, dim3(g), dim3(APC_BLOCK), 0, s, op, D, sc, (const double *)ph,
+  hipLaunchKernelGGL(kb_spmv_v<MODE>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, D, sc, (const double *)ph,
                      B->v, (const double *)B->rh, B->part_sl);
   hipLaunchKernelGGL(kb_fin_alpha, dim3(B->count), dim3(FB), 0, s, D, (const double *)B->part_sl,
                      B->sc);
   hipLaunchKernelGGL(kb_upd_s<JAC>, dim3(gr), dim3(RB), 0, s, D, sc, (const double *)B->r,
                      (const double *)B->v, B->s, sh, invd);
-  hipLaunchKernelGGL(kb_spmv_t<MODE>, dim3(g), dim3(APC_BLOCK), 0, s, op, D, sc, (const double *)sh,
+  hipLaunchKernelGGL(kb_spmv_t<MODE>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, D, sc, (const double *)sh,
                      (const double *)B->s, B->t, B->part_sl);
   hipLaunchKernelGGL(kb_fin_omega, dim3(B->count), dim3(FB), 0, s, D, (const double *)B->part_sl,
                      B->sc);
@@ -957,15 +957,15 @@ int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, 
     const unsigned g = batch_spmv_grid(B);
     for (int rep = 0; rep < 3; rep++)
       if (B->P.precision == APC_FP64)
-        hipLaunchKernelGGL(k_apply_batch<V64>, dim3(g), dim3(APC_BLOCK), 0, s, op, (const double *)f, y);
+        hipLaunchKernelGGL(k_apply_batch<V64>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, (const double *)f, y);
       else
-        hipLaunchKernelGGL(k_apply_batch<V32A64>, dim3(g), dim3(APC_BLOCK), 0, s, op, (const double *)f, y);
+        hipLaunchKernelGGL(k_apply_batch<V32A64>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, (const double *)f, y);
     HIPCHK(hipEventRecord(B->e0, s));
     for (int rep = 0; rep < 20; rep++)
       if (B->P.precision == APC_FP64)
-        hipLaunchKernelGGL(k_apply_batch<V64>, dim3(g), dim3(APC_BLOCK), 0, s, op, (const double *)f, y);
+        hipLaunchKernelGGL(k_apply_batch<V64>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, (const double *)f, y);
       else
-        hipLaunchKernelGGL(k_apply_batch<V32A64>, dim3(g), dim3(APC_BLOCK), 0, s, op, (const double *)f, y);
+        hipLaunchKernelGGL(k_apply_batch<V32A64>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, (const double *)f, y);
     HIPCHK(hipEventRecord(B->e1, s));
     HIPCHK(hipEventSynchronize(B->e1));
     float ms = 0.f;

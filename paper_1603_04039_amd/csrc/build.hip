@@ -790,7 +790,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   if (!p || !xyz || N < 1 || N > INT32_MAX) return APC_EINVAL;
   if (p->order != 2 && p->order != 4) return APC_EINVAL;
   if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
-      p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 ||
+      p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 || p->stage_cap < -1 ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
         p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c))
     return APC_EINVAL;

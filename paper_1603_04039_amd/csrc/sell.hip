@@ -13,6 +13,9 @@
 // are written by the assembly (k_fit_sell).
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+#include <vector>
+
 #include "apc_internal.h"
 
 namespace {
@@ -131,6 +134,89 @@ __global__ void __launch_bounds__(SL)
   }
 }
 
+// Distinct neighbour columns of one slice (one 256-thread block per slice): the
+// entries the operator kernels read (k < len on lanes with a row) are sorted in
+// LDS as (column << 12 | entry) keys (bitonic sort, at most 4096 entries), the
+// first entry of every run of equal columns starts a new tile slot, and every
+// entry gets the slot of its column.  Writes the count (un), the columns in
+// ascending order at the slice's entry offset (uq) and the 16-bit slots (lx2, as
+// uint16: entry k of lane r at 2 (o/2 + 64 (k/2) + r) + k%2).
+constexpr int UQ_T = 256, UQ_MAX = 4096;
+__global__ void __launch_bounds__(UQ_T)
+    k_uniq(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
+           const int64_t *__restrict__ sl_off, const int32_t *__restrict__ idx,
+           int32_t *__restrict__ un, int32_t *__restrict__ uq, uint16_t *__restrict__ lx) {
+  __shared__ uint64_t key[UQ_MAX];
+  __shared__ int32_t cnt[UQ_T];
+  const int64_t s = blockIdx.x;
+  const int t = threadIdx.x;
+  const int len = sl_len[s];
+  const int ne = len * SL;
+  if (ne > UQ_MAX || ne <= 0) {
+    if (t == 0) un[s] = 0;
+    return;
+  }
+  const int64_t o = sl_off[s];
+  int np = SL;
+  while (np < ne) np <<= 1;
+  for (int e = t; e < np; e += UQ_T) {
+    uint64_t kv = ~0ull;
+    if (e < ne && sl_rows[s * SL + (e & (SL - 1))] >= 0)
+      kv = ((uint64_t)(uint32_t)idx[o + e] << 12) | (uint64_t)e;
+    key[e] = kv;
+  }
+  __syncthreads();
+  for (int kk = 2; kk <= np; kk <<= 1)
+    for (int j = kk >> 1; j > 0; j >>= 1) {
+      for (int e = t; e < np; e += UQ_T) {
+        const int p = e ^ j;
+        if (p > e) {
+          const uint64_t a = key[e], b = key[p];
+          if ((a > b) == ((e & kk) == 0)) {
+            key[e] = b;
+            key[p] = a;
+          }
+        }
+      }
+      __syncthreads();
+    }
+  // thread t owns sorted positions [t per, (t+1) per)
+  const int per = np / UQ_T > 0 ? np / UQ_T : 1;
+  const int e0 = t * per, e1 = min(e0 + per, np);
+  int c = 0;
+  for (int e = e0; e < e1; e++) {
+    const uint64_t kv = key[e];
+    c += kv != ~0ull && (e == 0 || (kv >> 12) != (key[e - 1] >> 12));
+  }
+  cnt[t] = c;
+  __syncthreads();
+  for (int d = 1; d < UQ_T; d <<= 1) { // inclusive scan
+    const int v = t >= d ? cnt[t - d] : 0;
+    __syncthreads();
+    cnt[t] += v;
+    __syncthreads();
+  }
+  int r = cnt[t] - c - 1; // slot of the run that precedes this thread's first start
+  for (int e = e0; e < e1; e++) {
+    const uint64_t kv = key[e];
+    if (kv == ~0ull) break;
+    const int32_t col = (int32_t)(kv >> 12);
+    if (e == 0 || (kv >> 12) != (key[e - 1] >> 12)) {
+      r++;
+      uq[o + r] = col;
+    }
+    const int en = (int)(kv & 4095u), k = en >> 6, lane = en & (SL - 1);
+    lx[2 * ((o >> 1) + (int64_t)SL * (k >> 1) + lane) + (k & 1)] = (uint16_t)r;
+  }
+  if (t == UQ_T - 1) un[s] = cnt[UQ_T - 1];
+}
+
+// slices with more distinct columns than the tile holds gather directly
+__global__ void __launch_bounds__(APC_BLOCK) k_cap_un(int32_t *un, int64_t ns, int cap) {
+  const int64_t s = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (s < ns && un[s] > cap) un[s] = 0;
+}
+
 } // namespace
 
 int apc_build_sell(apc_cloud *c, hipStream_t s) {
@@ -227,12 +313,43 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   return APC_OK;
 }
 
+// Neighbour staging (layout in apc_cloud::sl_un): the distinct columns of every
+// slice, then the tile size ucap = the largest count, rounded up to 16 and capped
+// at the cloud's stage_cap (APC_UCAP_MAX at most); slices above the cap keep the
+// direct gathers.
+static int build_staging(apc_cloud *c, hipStream_t s) {
+  const size_t ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 4);
+  const size_t nsz = (size_t)(c->nsl > 0 ? c->nsl : 1);
+  const int cap = c->P.stage_cap == 0 ? APC_UCAP_MAX : std::min(c->P.stage_cap, APC_UCAP_MAX);
+  c->ucap = 0;
+  if (cap <= 0) return APC_OK;
+  HIPCHK(hipMalloc((void **)&c->sl_un, nsz * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->sl_uq, ne * sizeof(int32_t)));
+  HIPCHK(hipMalloc((void **)&c->sl_lx2, ne / 2 * sizeof(uint32_t)));
+  HIPCHK(hipMemsetAsync(c->sl_lx2, 0, ne / 2 * sizeof(uint32_t), s));
+  if (c->nsl <= 0) return APC_OK;
+  hipLaunchKernelGGL(k_uniq, dim3((unsigned)c->nsl), dim3(UQ_T), 0, s, c->sl_rows, c->sl_len,
+                     c->sl_off, c->sl_idx, c->sl_un, c->sl_uq, (uint16_t *)c->sl_lx2);
+  HIPCHK(hipGetLastError());
+  std::vector<int32_t> un((size_t)c->nsl);
+  HIPCHK(hipMemcpyAsync(un.data(), c->sl_un, un.size() * sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  int mx = 0;
+  for (int32_t v : un) mx = v > mx ? v : mx;
+  c->ucap = std::min((mx + 15) & ~15, cap);
+  hipLaunchKernelGGL(k_cap_un, dim3(grid_for(c->nsl)), dim3(APC_BLOCK), 0, s, c->sl_un, c->nsl,
+                     c->ucap);
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
 int apc_pack_sell_idx(apc_cloud *c, hipStream_t s) {
   const size_t ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 4);
-  uint32_t *old[] = {c->sl_lo2, c->sl_hi4, c->sl_top4};
-  for (uint32_t *q : old)
+  void *old[] = {c->sl_lo2, c->sl_hi4, c->sl_top4, c->sl_un, c->sl_uq, c->sl_lx2};
+  for (void *q : old)
     if (q) HIPCHK(hipFree(q));
-  c->sl_lo2 = c->sl_hi4 = c->sl_top4 = nullptr;
+  c->sl_lo2 = c->sl_hi4 = c->sl_top4 = c->sl_lx2 = nullptr;
+  c->sl_un = c->sl_uq = nullptr;
   HIPCHK(hipMalloc((void **)&c->sl_lo2, ne / 2 * sizeof(uint32_t)));
   HIPCHK(hipMalloc((void **)&c->sl_hi4, ne / 4 * sizeof(uint32_t)));
   if (c->n + c->nb >= ((int64_t)1 << 24))
@@ -242,15 +359,17 @@ int apc_pack_sell_idx(apc_cloud *c, hipStream_t s) {
                        c->sl_idx, c->sl_lo2, c->sl_hi4, c->sl_top4);
     HIPCHK(hipGetLastError());
   }
-  return APC_OK;
+  return build_staging(c, s);
 }
 
 void apc_free_sell(apc_cloud *c) {
   void *ptrs[] = {c->sl_rows, c->sl_len, c->sl_tmpl, c->sl_off, c->sl_idx, c->sl_w64, c->sl_w32,
-                  c->sl_lo2, c->sl_hi4, c->sl_top4};
+                  c->sl_lo2, c->sl_hi4, c->sl_top4, c->sl_un, c->sl_uq, c->sl_lx2};
   for (void *q : ptrs)
     if (q) (void)hipFree(q);
-  c->sl_lo2 = c->sl_hi4 = c->sl_top4 = nullptr;
+  c->sl_lo2 = c->sl_hi4 = c->sl_top4 = c->sl_lx2 = nullptr;
+  c->sl_un = c->sl_uq = nullptr;
+  c->ucap = 0;
   c->sl_rows = c->sl_len = c->sl_idx = c->sl_tmpl = nullptr;
   c->sl_off = nullptr;
   c->sl_w64 = nullptr;

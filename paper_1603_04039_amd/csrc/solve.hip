@@ -34,8 +34,10 @@ struct Scal {
 // Reductions: kernels that produce dot products run on a capped grid of GRED
 // blocks (grid-stride) and store one partial per block; a one-block finalize
 // kernel sums the partials in a fixed order and updates the solver scalars.  No
-// atomics or device-scope fences inside kernels (the 8 XCD L2s are not coherent
-// with each other within a kernel); kernel boundaries order everything.
+// atomics or device-scope fences inside kernels: kernel boundaries order
+// everything.  (Finalizing in the last block to finish, behind a device-scope
+// release fence in every block, was measured: the fence writes back the XCD's L2
+// each time and the iteration ran 3x slower.)
 constexpr unsigned GRED = 2048;
 
 template <int NV>
@@ -195,48 +197,64 @@ __global__ void __launch_bounds__(APC_BLOCK)
 struct MOp {
   const float *diag, *sell, *tmpl;
 };
-template <bool TOP>
+template <bool TOP, bool STG>
 __device__ __forceinline__ void prec_slice(const Op &op, const MOp &M, const double *__restrict__ in,
-                                           double *__restrict__ out, int s) {
+                                           double *__restrict__ out, int s, int u) {
   const int lane = threadIdx.x & 63;
   const int64_t o = op.sl_off[s];
   const int64_t off = o + lane, lb = (o >> 1) + lane, hb = (o >> 2) + lane;
+  double *tile = STG ? stage_tile(op) : nullptr;
   if (op.sl_tmpl[s]) {
     int32_t jj[24];
+    if (STG) {
+      uint32_t wq[12];
 #pragma unroll
-    for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP>(op, lb, hb, k);
+      for (int k = 0; k < 12; k++) wq[k] = op.sl_lx2[lb + (int64_t)SL * k];
+      stage_fill(tile, op.sl_uq + o, u, in);
+#pragma unroll
+      for (int k = 0; k < 24; k++) jj[k] = (int32_t)((wq[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP>(op, lb, hb, k);
+    }
     const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return;
     const float *__restrict__ T = M.tmpl + 25 * (int)op.rk[row];
     double acc = (double)T[0] * in[row];
 #pragma unroll
-    for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * in[jj[k]];
+    for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * (STG ? tile[jj[k]] : in[jj[k]]);
     out[row] = acc;
   } else {
     // M holds the first APC_MLP_OUT - 1 stencil entries of a row (all of them
     // for k = 2; the nearest 40 of the up to 56 of k = 4)
     const int len = min(op.sl_len[s], APC_MLP_OUT - 1);
+    if (STG) stage_fill(tile, op.sl_uq + o, u, in);
     const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return;
     const float *__restrict__ wv = M.sell + off;
     double acc = (double)M.diag[row] * in[row];
 #pragma unroll 8
-    for (int k = 0; k < len; k++) acc += (double)wv[k * SL] * in[sl_col<TOP>(op, lb, hb, k)];
+    for (int k = 0; k < len; k++)
+      acc += (double)wv[k * SL] * (STG ? tile[stage_slot(op, lb, k)] : in[sl_col<TOP>(op, lb, hb, k)]);
     out[row] = acc;
   }
 }
 
-// out = M in over the rows of every slice (the learned preconditioner)
+// out = M in over the rows of every slice (the learned preconditioner); launched
+// with op_lds(op) bytes of dynamic LDS
 __global__ void __launch_bounds__(APC_BLOCK)
     k_prec_apply(Op op, MOp M, const double *__restrict__ in, double *__restrict__ out,
                  const Scal *sc) {
   if (sc && sc->done) return;
   for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
     const int s = __builtin_amdgcn_readfirstlane(it.s);
-    if (op.sl_top4)
-      prec_slice<true>(op, M, in, out, s);
+    const int u = op.sl_un ? op.sl_un[s] : 0;
+    if (u > 0)
+      prec_slice<false, true>(op, M, in, out, s, u);
+    else if (op.sl_top4)
+      prec_slice<true, false>(op, M, in, out, s, 0);
     else
-      prec_slice<false>(op, M, in, out, s);
+      prec_slice<false, false>(op, M, in, out, s, 0);
   }
 }
 
@@ -453,7 +471,7 @@ static int read_sc(apc_solver_ws *w, hipStream_t s) {
 template <int MODE>
 static int launch_restart(apc_solver_ws *w, const Op &op, const double *b, const double *x,
                           int first, unsigned g, hipStream_t s) {
-  hipLaunchKernelGGL(k_restart<MODE>, dim3(g), dim3(APC_BLOCK), 0, s, op, b, x, w->r, w->rh, w->p,
+  hipLaunchKernelGGL(k_restart<MODE>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, b, x, w->r, w->rh, w->p,
                      w->v, w->part, first);
   hipLaunchKernelGGL(k_fin_restart, dim3(1), dim3(FIN_T), 0, s, w->part, g, w->sc, first);
   HIPCHK(hipGetLastError());
@@ -474,8 +492,8 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
   else
     hipLaunchKernelGGL(k_upd_p<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->p, w->v, ph,
                        invd, w->sc);
-  if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), 0, s, op, mw, w->p, ph, w->sc);
-  hipLaunchKernelGGL(k_spmv_v<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, ph, w->v, w->rh, w->part,
+  if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, mw, w->p, ph, w->sc);
+  hipLaunchKernelGGL(k_spmv_v<MODE>, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, ph, w->v, w->rh, w->part,
                      w->sc);
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
   if (jac)
@@ -484,8 +502,8 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
   else
     hipLaunchKernelGGL(k_upd_s<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->v, w->s, sh,
                        invd, w->sc);
-  if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), 0, s, op, mw, w->s, sh, w->sc);
-  hipLaunchKernelGGL(k_spmv_t<MODE>, dim3(gs), dim3(APC_BLOCK), 0, s, op, sh, w->s, w->t, w->part,
+  if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, mw, w->s, sh, w->sc);
+  hipLaunchKernelGGL(k_spmv_t<MODE>, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, sh, w->s, w->t, w->part,
                      w->sc);
   hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
   hipLaunchKernelGGL(k_upd_xr, dim3(gr), dim3(APC_BLOCK), 0, s, n, x, ph, sh, w->s, w->t, w->r,
@@ -666,9 +684,9 @@ int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s) {
   const Op op = make_op(c, false);
   // f has n+nb entries: boundary values take part as given (no zero tail here)
   if (c->P.precision != APC_FP64)
-    hipLaunchKernelGGL(k_apply<V32A64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, op, f, out);
+    hipLaunchKernelGGL(k_apply<V32A64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), op_lds(op), s, op, f, out);
   else
-    hipLaunchKernelGGL(k_apply<V64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, op, f, out);
+    hipLaunchKernelGGL(k_apply<V64>, dim3(spmv_grid(c)), dim3(APC_BLOCK), op_lds(op), s, op, f, out);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
@@ -678,9 +696,11 @@ int apc_apply_precond_impl(apc_cloud *c, int precond, const double *in, double *
   if (!c->assembled) return APC_EINVAL;
   if (precond == APC_PRECOND_LEARNED) {
     if (!c->learned) return APC_EINVAL;
-    if (c->nsl > 0)
-      hipLaunchKernelGGL(k_prec_apply, dim3(spmv_grid(c)), dim3(APC_BLOCK), 0, s, make_op(c, false),
+    if (c->nsl > 0) {
+      const Op op = make_op(c, false);
+      hipLaunchKernelGGL(k_prec_apply, dim3(spmv_grid(c)), dim3(APC_BLOCK), op_lds(op), s, op,
                          MOp{c->m_diag, c->m_sell, c->m_tmpl}, in, out, (const Scal *)nullptr);
+    }
   } else if (precond == APC_PRECOND_JACOBI || precond == APC_PRECOND_NONE) {
     hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, in,
                        precond == APC_PRECOND_JACOBI ? (const double *)c->inv_diag : nullptr, out);

@@ -29,8 +29,18 @@ struct Op {
   const int64_t *sl_off;
   const double *sl_w64;
   const float *sl_w32;
+  // neighbour staging (null / 0 when no slice is staged)
+  const int32_t *sl_un, *sl_uq;
+  const uint32_t *sl_lx2;
+  int ucap;
   int64_t cs[9];
 };
+
+// Dynamic LDS of a kernel that applies the operator through sell_apply or
+// prec_slice: one tile of ucap doubles per wavefront of the block.
+static inline size_t op_lds(const Op &op) {
+  return op.sl_un ? (size_t)(APC_BLOCK / 64) * (size_t)op.ucap * sizeof(double) : 0;
+}
 
 
 __device__ __forceinline__ double wave_sum(double v) {
@@ -80,23 +90,76 @@ __device__ __forceinline__ int32_t sl_col(const Op &op, int64_t lb, int64_t hb, 
   return (int32_t)j;
 }
 
+// Tile of the calling wavefront in the block's dynamic LDS.
+__device__ __forceinline__ double *stage_tile(const Op &op) {
+  extern __shared__ double apc_stage_lds[];
+  return apc_stage_lds + (threadIdx.x >> 6) * op.ucap;
+}
+
+// Orders the wavefront's LDS accesses before and after this point (the lanes of
+// one wavefront read what other lanes wrote).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Gathers x at the slice's u distinct columns (ascending, so that neighbouring
+// lanes read neighbouring addresses) into the tile: four loads a lane in flight.
+// Every lane of the wavefront takes part.
+__device__ __forceinline__ void stage_fill(double *tile, const int32_t *__restrict__ uq, int u,
+                                           const double *__restrict__ x) {
+  const int lane = threadIdx.x & 63;
+  wave_lds_sync();
+  for (int b = 0; b < u; b += 4 * SL) {
+    int32_t q[4];
+    double v[4];
+#pragma unroll
+    for (int h = 0; h < 4; h++) q[h] = b + SL * h + lane < u ? uq[b + SL * h + lane] : -1;
+#pragma unroll
+    for (int h = 0; h < 4; h++) v[h] = q[h] >= 0 ? x[q[h]] : 0.0;
+#pragma unroll
+    for (int h = 0; h < 4; h++)
+      if (q[h] >= 0) tile[b + SL * h + lane] = v[h];
+  }
+  wave_lds_sync();
+}
+
+// tile slot of entry k of the lane (lb = o/2 + lane)
+__device__ __forceinline__ int stage_slot(const Op &op, int64_t lb, int k) {
+  return (int)((op.sl_lx2[lb + (int64_t)SL * (k >> 1)] >> (16 * (k & 1))) & 0xffffu);
+}
+
 // (A x)_row for the lane's row of slice s (row = -1 on padding lanes, result 0).
 // Uniform 2-ring slices hold 24 entries ordered by shell (6 at r = 1 cell, 12 at
 // sqrt 2, 6 at 2) and no weights: their index loads go out before the row id.
 // General slices run their entry loop unrolled by 8 so that 8 index/weight loads
-// and then 8 gathers are in flight together.
-template <int MODE, bool TOP>
+// and then 8 gathers are in flight together.  STG: the slice's u distinct
+// neighbour values are staged in the wavefront's LDS tile first, and each entry
+// reads its slot there (same values, same arithmetic, so the result is the same
+// bit for bit); otherwise every entry gathers from x.
+template <int MODE, bool TOP, bool STG>
 __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__restrict__ x, int s,
-                                               int32_t &row) {
+                                               int u, int32_t &row) {
   const int lane = threadIdx.x & 63;
   const int64_t o = op.sl_off[s];
   const int64_t off = o + lane, lb = (o >> 1) + lane, hb = (o >> 2) + lane;
+  double *tile = STG ? stage_tile(op) : nullptr;
   double acc;
   double xi;
   if (op.sl_tmpl[s]) {
     int32_t jj[24];
+    if (STG) {
+      uint32_t wq[12];
 #pragma unroll
-    for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP>(op, lb, hb, k);
+      for (int k = 0; k < 12; k++) wq[k] = op.sl_lx2[lb + (int64_t)SL * k];
+      stage_fill(tile, op.sl_uq + o, u, x);
+#pragma unroll
+      for (int k = 0; k < 24; k++) jj[k] = (int32_t)((wq[k >> 1] >> (16 * (k & 1))) & 0xffffu);
+    } else {
+#pragma unroll
+      for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP>(op, lb, hb, k);
+    }
     row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return 0.0;
     xi = x[row];
@@ -105,7 +168,7 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
       float a0 = 0.f, a1 = 0.f, a2 = 0.f;
 #pragma unroll
       for (int k = 0; k < 24; k++) {
-        const float d = (float)(x[jj[k]] - xi);
+        const float d = (float)((STG ? tile[jj[k]] : x[jj[k]]) - xi);
         if (k < 6) a0 += d; else if (k < 18) a1 += d; else a2 += d;
       }
       acc = (double)((float)op.tc[0] * a0 + (float)op.tc[1] * a1 + (float)op.tc[2] * a2) * scale;
@@ -113,7 +176,7 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
       double a0 = 0.0, a1 = 0.0, a2 = 0.0;
 #pragma unroll
       for (int k = 0; k < 24; k++) {
-        const double d = x[jj[k]] - xi;
+        const double d = (STG ? tile[jj[k]] : x[jj[k]]) - xi;
         if (k < 6) a0 += d; else if (k < 18) a1 += d; else a2 += d;
       }
       const double c0 = MODE == V64 ? op.tc[0] : (double)(float)op.tc[0];
@@ -123,36 +186,43 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
     }
   } else {
     const int len = op.sl_len[s];
+    if (STG) stage_fill(tile, op.sl_uq + o, u, x);
     row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return 0.0;
     xi = x[row];
+#define APC_NB(k) (STG ? tile[stage_slot(op, lb, k)] : x[sl_col<TOP>(op, lb, hb, k)])
     if (MODE == V32A32) {
       const float *__restrict__ wv = op.sl_w32 + off;
       float af = 0.f;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) af += wv[k * SL] * (float)(x[sl_col<TOP>(op, lb, hb, k)] - xi);
+      for (int k = 0; k < len; k++) af += wv[k * SL] * (float)(APC_NB(k) - xi);
       acc = (double)af;
     } else if (MODE == V64) {
       const double *__restrict__ wv = op.sl_w64 + off;
       double ad = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) ad += wv[k * SL] * (x[sl_col<TOP>(op, lb, hb, k)] - xi);
+      for (int k = 0; k < len; k++) ad += wv[k * SL] * (APC_NB(k) - xi);
       acc = ad;
     } else {
       const float *__restrict__ wv = op.sl_w32 + off;
       double ad = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (x[sl_col<TOP>(op, lb, hb, k)] - xi);
+      for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (APC_NB(k) - xi);
       acc = ad;
     }
+#undef APC_NB
   }
   return op.hs ? xi + op.hs[row] * acc : (op.unit_diag ? xi + acc : acc);
 }
+// Kernels that call this are launched with op_lds(op) bytes of dynamic LDS.
 template <int MODE>
 __device__ __forceinline__ double sell_apply(const Op &op, const double *__restrict__ x, int s_in,
                                              int32_t &row) {
   const int s = __builtin_amdgcn_readfirstlane(s_in);
-  return op.sl_top4 ? sell_apply_t<MODE, true>(op, x, s, row) : sell_apply_t<MODE, false>(op, x, s, row);
+  const int u = op.sl_un ? op.sl_un[s] : 0;
+  if (u > 0) return sell_apply_t<MODE, false, true>(op, x, s, u, row);
+  return op.sl_top4 ? sell_apply_t<MODE, true, false>(op, x, s, 0, row)
+                    : sell_apply_t<MODE, false, false>(op, x, s, 0, row);
 }
 
 static inline Op make_op(const apc_cloud *c, bool density) {
@@ -177,6 +247,10 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   op.sl_off = c->sl_off;
   op.sl_w64 = b4 ? c->sl_bw64 : c->sl_w64;
   op.sl_w32 = b4 ? c->sl_bw32 : c->sl_w32;
+  op.ucap = c->ucap;
+  op.sl_un = c->ucap > 0 ? c->sl_un : nullptr;
+  op.sl_uq = c->sl_uq;
+  op.sl_lx2 = c->sl_lx2;
   for (int k = 0; k < 9; k++) op.cs[k] = c->sl_cs[k];
   return op;
 }
