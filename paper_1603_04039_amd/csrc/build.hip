@@ -5,6 +5,7 @@
 // independent of evaluation order.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 #include <cstring>
@@ -280,76 +281,117 @@ __device__ inline bool in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
 // the axis until it spans 5 distinct offsets (the centre's 0 included; on fewer
 // planes a quartic vanishes on the whole stencil); then the nearest remaining ones
 // up to min(count, m_cap).  Accepted (m > 0) when every closed octant holds a
-// chosen node and m >= p + 1; the rank test follows in a separate kernel.  One
-// thread per pending node; the ring lives in a per-thread slice of global scratch.
+// chosen node and m >= p + 1; the rank test follows in a separate kernel.
+//
+// One thread per pending node (thread t works on position pos = tmap ? tmap[t] : t
+// of the chunk and writes mout[pos], cand[pos]).  The ring lives in per-thread
+// global scratch laid out element-major (element k of thread t at k * stride + t,
+// so that the lanes of a wavefront walking their lists in step touch neighbouring
+// words): the BFS list (node ids), the sort keys, and an open-addressing hash set
+// of the nodes seen (entries gen << 32 | node; an entry of another generation is
+// empty, so the table is never cleared).  The list holds at most cap nodes: past
+// that the thread reports -1 (the host reruns it with the full APC_RING_CAP), or,
+// when cap is already APC_RING_CAP (full), flags error 8.  The result does not
+// depend on cap.
+__device__ __forceinline__ uint32_t ring_hash(int32_t v, uint32_t mask) {
+  return ((uint32_t)v * 2654435761u) & mask;
+}
+
 __global__ void __launch_bounds__(APC_BLOCK)
-    k_stencil(const int32_t *__restrict__ pending, int64_t np, int R, int m_cap, int p, int order,
-              const int32_t *__restrict__ crd, int64_t ntot, int64_t n,
-              const int32_t *__restrict__ r1cnt, const int32_t *__restrict__ r1,
-              const int32_t *__restrict__ bowner, int32_t *__restrict__ lst_all,
-              int64_t *__restrict__ key_all, int32_t *__restrict__ cand, int32_t *__restrict__ mout,
-              int *__restrict__ err) {
-  int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+    k_stencil(const int32_t *__restrict__ pending, const int32_t *__restrict__ tmap, int64_t np,
+              int R, int m_cap, int p, int order, const int32_t *__restrict__ crd, int64_t ntot,
+              int64_t n, const int32_t *__restrict__ r1cnt, const int32_t *__restrict__ r1,
+              const int32_t *__restrict__ bowner, int cap, int64_t stride, uint32_t hmask,
+              uint32_t gen, int32_t *__restrict__ lst_all, int64_t *__restrict__ key_all,
+              uint64_t *__restrict__ hash_all, int full, int32_t *__restrict__ cand,
+              int32_t *__restrict__ mout, int *__restrict__ err) {
+  const int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (t >= np) return;
-  const int32_t y = pending[t];
-  int32_t *lst = lst_all + t * APC_RING_CAP;
-  int64_t *key = key_all + t * APC_RING_CAP;
+  const int64_t pos = tmap ? tmap[t] : t;
+  const int32_t y = pending[pos];
+  int32_t *lst = lst_all + t;
+  int64_t *key = key_all + t;
+  uint64_t *tab = hash_all + t;
+#define LST(k) lst[(int64_t)(k) * stride]
+#define KEY(k) key[(int64_t)(k) * stride]
+  const uint64_t g = (uint64_t)gen << 32;
+  // true when v was not in the set (and is now)
+  auto insert = [&](int32_t v) -> bool {
+    uint32_t h = ring_hash(v, hmask);
+    for (;;) {
+      const uint64_t e = tab[(int64_t)h * stride];
+      if ((e & 0xffffffff00000000ull) != g) {
+        tab[(int64_t)h * stride] = g | (uint32_t)v;
+        return true;
+      }
+      if ((int32_t)(uint32_t)e == v) return false;
+      h = (h + 1) & hmask;
+    }
+  };
   int cnt = 0;
-  lst[cnt++] = y;
+  LST(cnt++) = y;
+  insert(y);
   int lo = 0;
   bool overflow = false;
   for (int depth = 1; depth <= R && !overflow; depth++) {
     const int hi = cnt;
     for (int q = lo; q < hi && !overflow; q++) {
-      const int32_t u = lst[q];
-      int na;
-      const int32_t *adj;
-      int32_t own;
-      if (u >= n) {
-        own = bowner[u - n];
-        adj = &own;
-        na = 1;
-      } else {
-        adj = r1 + (int64_t)u * 24;
-        na = r1cnt[u];
-      }
+      const int32_t u = LST(q);
+      const bool bnd = u >= n; // a boundary node's only neighbour is its owner
+      const int na = bnd ? 1 : r1cnt[u];
       for (int a = 0; a < na; a++) {
-        const int32_t v = adj[a];
-        bool seen = false;
-        for (int s = 0; s < cnt; s++)
-          if (lst[s] == v) {
-            seen = true;
-            break;
-          }
-        if (seen) continue;
-        if (cnt == APC_RING_CAP) {
+        const int32_t v = bnd ? bowner[u - n] : r1[(int64_t)u * 24 + a];
+        if (!insert(v)) continue;
+        if (cnt == cap) {
           overflow = true;
           break;
         }
-        lst[cnt++] = v;
+        LST(cnt++) = v;
       }
     }
     lo = hi;
   }
   if (overflow) {
-    atomicOr(err, 8);
-    mout[t] = 0;
+    if (full) atomicOr(err, 8);
+    mout[pos] = full ? 0 : -1;
     return;
   }
   const int32_t cy0 = crd[y], cy1 = crd[ntot + y], cy2 = crd[2 * ntot + y];
-  // candidates = lst[1..cnt); insertion sort by (r2, index)
+  // candidates = list positions 1 .. cnt-1, heap-sorted by (r2, index)
   for (int j = 1; j < cnt; j++) {
-    const int32_t v = lst[j];
+    const int32_t v = LST(j);
     const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
-    const int64_t k = d0 * d0 + d1 * d1 + d2 * d2;
-    int s = j - 1;
-    while (s >= 1 && (key[s] > k || (key[s] == k && lst[s] > v))) {
-      key[s + 1] = key[s];
-      lst[s + 1] = lst[s];
-      s--;
+    KEY(j) = d0 * d0 + d1 * d1 + d2 * d2;
+  }
+  {
+    const int m = cnt - 1;
+    auto less = [&](int a, int b) -> bool { // heap positions 0..m-1 = list positions 1..m
+      const int64_t ka = KEY(a + 1), kb = KEY(b + 1);
+      return ka < kb || (ka == kb && LST(a + 1) < LST(b + 1));
+    };
+    auto swp = [&](int a, int b) {
+      const int64_t k = KEY(a + 1);
+      KEY(a + 1) = KEY(b + 1);
+      KEY(b + 1) = k;
+      const int32_t v = LST(a + 1);
+      LST(a + 1) = LST(b + 1);
+      LST(b + 1) = v;
+    };
+    auto sift = [&](int root, int end) {
+      for (;;) {
+        int c = 2 * root + 1;
+        if (c >= end) break;
+        if (c + 1 < end && less(c, c + 1)) c++;
+        if (!less(root, c)) break;
+        swp(root, c);
+        root = c;
+      }
+    };
+    for (int st = m / 2 - 1; st >= 0; st--) sift(st, m);
+    for (int e = m - 1; e > 0; e--) {
+      swp(0, e);
+      sift(0, e);
     }
-    key[s + 1] = k;
-    lst[s + 1] = v;
   }
   const int nc = cnt - 1;
   const int want = nc < m_cap ? nc : m_cap;
@@ -358,14 +400,14 @@ __global__ void __launch_bounds__(APC_BLOCK)
   for (int o = 0; o < 8; o++) {
     int taken = 0;
     for (int j = 1; j < cnt && taken < 2; j++) {
-      int32_t v = lst[j];
+      int32_t v = LST(j);
       const bool picked = v < 0;
       if (picked) v = -v - 1;
       const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
       if (!in_octant(o, d0, d1, d2)) continue;
       taken++;
       if (!picked && got < want) {
-        lst[j] = -v - 1;
+        LST(j) = -v - 1;
         got++;
       }
     }
@@ -378,8 +420,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
       int nv = 1;
       vals[0] = 0;
       for (int j = 1; j < cnt && nv < 5; j++) {
-        if (lst[j] >= 0) continue;
-        const int64_t o = cd[-lst[j] - 1] - c0;
+        if (LST(j) >= 0) continue;
+        const int64_t o = cd[-LST(j) - 1] - c0;
         bool seen = false;
         for (int q = 0; q < nv; q++) seen = seen || vals[q] == o;
         if (!seen) vals[nv++] = o;
@@ -387,36 +429,44 @@ __global__ void __launch_bounds__(APC_BLOCK)
       if (nv >= 5 || got >= want) break;
       int add = -1;
       for (int j = 1; j < cnt && add < 0; j++) {
-        if (lst[j] < 0) continue;
-        const int64_t o = cd[lst[j]] - c0;
+        if (LST(j) < 0) continue;
+        const int64_t o = cd[LST(j)] - c0;
         bool seen = false;
         for (int q = 0; q < nv; q++) seen = seen || vals[q] == o;
         if (!seen) add = j;
       }
       if (add < 0) break;
-      lst[add] = -lst[add] - 1;
+      LST(add) = -LST(add) - 1;
       got++;
     }
   }
   for (int j = 1; j < cnt && got < want; j++)
-    if (lst[j] >= 0) {
-      lst[j] = -lst[j] - 1;
+    if (LST(j) >= 0) {
+      LST(j) = -LST(j) - 1;
       got++;
     }
   int m = 0;
   int oct[8] = {0, 0, 0, 0, 0, 0, 0, 0};
-  int32_t *out = cand + t * APC_MAXM;
+  int32_t *out = cand + pos * APC_MAXM;
   for (int j = 1; j < cnt; j++) {
-    if (lst[j] >= 0) continue;
-    const int32_t v = -lst[j] - 1;
+    if (LST(j) >= 0) continue;
+    const int32_t v = -LST(j) - 1;
     if (m < APC_MAXM) out[m] = v;
     m++;
     const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
     for (int o = 0; o < 8; o++) oct[o] += in_octant(o, d0, d1, d2);
   }
+#undef LST
+#undef KEY
   bool ok = m >= p + 1 && m <= APC_MAXM;
   for (int o = 0; o < 8; o++) ok = ok && oct[o] >= 1;
-  mout[t] = ok ? m : 0;
+  mout[pos] = ok ? m : 0;
+}
+
+// 1 where the first pass ran out of ring capacity
+__global__ void __launch_bounds__(APC_BLOCK) k_retry_flag(const int32_t *m, int64_t n, int32_t *f) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) f[i] = m[i] < 0 ? 1 : 0;
 }
 
 __global__ void __launch_bounds__(APC_BLOCK)
@@ -689,19 +739,67 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     APCCHK(dfree(offs, s));
   }
   int64_t np = n;
-  // nodes per ring-search chunk: enough threads to keep the GPU busy, scratch of
-  // CH * APC_RING_CAP * 12 B (6.4 GB at the largest chunk)
-  const int64_t CH = np < 32768 ? (np > 0 ? np : 1) : 32768;
-  int32_t *lst = nullptr, *cand = nullptr, *mch = nullptr, *still = nullptr, *soff = nullptr,
-          *npend = nullptr;
-  int64_t *key = nullptr;
-  APCCHK(dalloc(&lst, CH * APC_RING_CAP, s));
-  APCCHK(dalloc(&key, CH * APC_RING_CAP, s));
-  APCCHK(dalloc(&cand, CH * APC_MAXM, s));
-  APCCHK(dalloc(&mch, CH, s));
+  // Ring-search scratch of k_stencil, per node of a chunk (element-major): a list
+  // of cap nodes, their sort keys and a hash set of 2^k >= 2 cap entries.  First
+  // pass with cap = 2 (2R+1)^3 (twice the R-ring of a uniform region) on chunks
+  // of up to 8 GiB of scratch; nodes whose ring is larger are rerun with the full
+  // APC_RING_CAP in sub-chunks of up to 1 GiB.
+  auto ring_cap = [](int R) {
+    const int64_t w = 2 * (int64_t)R + 1;
+    return (int)std::min<int64_t>(APC_RING_CAP, 2 * w * w * w);
+  };
+  auto hash_size = [](int cap) {
+    int h = 1;
+    while (h < 2 * cap) h <<= 1;
+    return h;
+  };
+  auto node_words = [&](int cap) { // 8-byte words per node
+    return ((int64_t)cap * 4 + 7) / 8 + (int64_t)cap + (int64_t)hash_size(cap);
+  };
+  const int64_t W1 = ((int64_t)8 << 30) / 8, W2 = ((int64_t)1 << 30) / 8;
+  auto chunk_nodes = [&](int cap, int64_t words) {
+    return std::max<int64_t>(1, std::min<int64_t>(np, words / node_words(cap)));
+  };
+  int64_t CHmax = 1, words1 = 1;
+  for (int R = 1; R <= P.ring_max; R++) {
+    const int64_t ch = chunk_nodes(ring_cap(R), W1);
+    CHmax = std::max(CHmax, ch);
+    words1 = std::max(words1, ch * node_words(ring_cap(R)));
+  }
+  const int64_t CH2 = chunk_nodes(APC_RING_CAP, W2);
+  const int64_t words2 = CH2 * node_words(APC_RING_CAP);
+  uint64_t *scr1 = nullptr, *scr2 = nullptr;
+  int32_t *cand = nullptr, *mch = nullptr, *still = nullptr, *soff = nullptr, *npend = nullptr,
+          *rflag = nullptr, *roff = nullptr, *rlist = nullptr;
+  APCCHK(dalloc(&scr1, words1, s));
+  APCCHK(dalloc(&scr2, words2, s));
+  // hash entries carry the launch's generation: zero once, never cleared again
+  HIPCHK(hipMemsetAsync(scr1, 0, (size_t)words1 * 8, s));
+  HIPCHK(hipMemsetAsync(scr2, 0, (size_t)words2 * 8, s));
+  uint32_t gen = 0;
+  APCCHK(dalloc(&cand, CHmax * APC_MAXM, s));
+  APCCHK(dalloc(&mch, CHmax, s));
+  APCCHK(dalloc(&rflag, CHmax, s));
+  APCCHK(dalloc(&roff, CHmax, s));
+  APCCHK(dalloc(&rlist, CHmax, s));
   APCCHK(dalloc(&still, n, s));
   APCCHK(dalloc(&soff, n, s));
   APCCHK(dalloc(&npend, n, s));
+  struct Scr {
+    int32_t *lst;
+    int64_t *key;
+    uint64_t *tab;
+    uint32_t mask;
+  };
+  auto carve = [&](uint64_t *base, int cap, int64_t ch) {
+    Scr r;
+    r.lst = (int32_t *)base;
+    r.key = (int64_t *)(base + (ch * cap * 4 + 7) / 8);
+    r.tab = (uint64_t *)(r.key + ch * cap);
+    r.mask = (uint32_t)hash_size(cap) - 1u;
+    return r;
+  };
+  const Scr S2 = carve(scr2, APC_RING_CAP, CH2);
   // order fallback (k = 4): nodes with no acceptable order-4 stencil up to ring_max
   // take an order-2 row, chosen by the order-2 rule from ring 2 with cap 40
   HIPCHK(hipMalloc((void **)&c->rorder, (size_t)(n > 0 ? n : 1)));
@@ -712,12 +810,35 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   const int rmin = att == 0 ? P.ring_min : 2, mcap = att == 0 ? P.m_cap : 40;
   for (int R = rmin; R <= P.ring_max && np > 0; R++) {
     HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
+    const int cap1 = ring_cap(R);
+    const int64_t CH = chunk_nodes(cap1, W1);
+    const Scr S1 = carve(scr1, cap1, CH);
     for (int64_t c0 = 0; c0 < np; c0 += CH) {
       const int64_t cn = (np - c0) < CH ? (np - c0) : CH;
-      hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, R,
-                         mcap, pk, ko, c->crd, ntot, n, r1cnt, r1, c->bowner, lst, key, cand, mch,
+      hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0,
+                         (const int32_t *)nullptr, cn, R, mcap, pk, ko, c->crd, ntot, n, r1cnt, r1,
+                         c->bowner, cap1, CH, S1.mask, ++gen, S1.lst, S1.key, S1.tab, 0, cand, mch,
                          err);
       HIPCHK(hipGetLastError());
+      // rerun the nodes whose ring outgrew cap1 with the full capacity
+      hipLaunchKernelGGL(k_retry_flag, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, mch, cn, rflag);
+      HIPCHK(hipGetLastError());
+      int64_t nr = 0;
+      APCCHK(apc_sum_i32(rflag, cn, &nr, s));
+      if (nr > 0) {
+        APCCHK(apc_scan_i32(rflag, roff, cn, s));
+        hipLaunchKernelGGL(k_compact_idx, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, rflag, roff,
+                           (const int32_t *)nullptr, cn, rlist);
+        HIPCHK(hipGetLastError());
+        for (int64_t r0 = 0; r0 < nr; r0 += CH2) {
+          const int64_t rn = (nr - r0) < CH2 ? (nr - r0) : CH2;
+          hipLaunchKernelGGL(k_stencil, dim3(grid_for(rn)), dim3(APC_BLOCK), 0, s, pending + c0,
+                             (const int32_t *)(rlist + r0), rn, R, mcap, pk, ko, c->crd, ntot, n,
+                             r1cnt, r1, c->bowner, APC_RING_CAP, CH2, S2.mask, ++gen, S2.lst,
+                             S2.key, S2.tab, 1, cand, mch, err);
+          HIPCHK(hipGetLastError());
+        }
+      }
       APCCHK(apc_rank_check(c, ko, pending + c0, cn, cand, mch, s));
       hipLaunchKernelGGL(k_accept, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, cand,
                          mch, stbuf, mnode, still + c0, ko, c->rorder);
@@ -740,8 +861,11 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     np = left;
   }
   }
-  APCCHK(dfree(lst, s));
-  APCCHK(dfree(key, s));
+  APCCHK(dfree(scr1, s));
+  APCCHK(dfree(scr2, s));
+  APCCHK(dfree(rflag, s));
+  APCCHK(dfree(roff, s));
+  APCCHK(dfree(rlist, s));
   APCCHK(dfree(cand, s));
   APCCHK(dfree(mch, s));
   APCCHK(dfree(still, s));
