@@ -463,6 +463,12 @@ __global__ void __launch_bounds__(APC_BLOCK)
   mout[pos] = ok ? m : 0;
 }
 
+// first-pass ring capacity of the stencil search; 0: 2 (2R+1)^3 for ring R (a
+// smaller value sends more nodes to the full-capacity rerun, same stencils)
+#ifndef APC_RING_FIRST_CAP
+#define APC_RING_FIRST_CAP 0
+#endif
+
 // 1 where the first pass ran out of ring capacity
 __global__ void __launch_bounds__(APC_BLOCK) k_retry_flag(const int32_t *m, int64_t n, int32_t *f) {
   const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
@@ -741,12 +747,14 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   int64_t np = n;
   // Ring-search scratch of k_stencil, per node of a chunk (element-major): a list
   // of cap nodes, their sort keys and a hash set of 2^k >= 2 cap entries.  First
-  // pass with cap = 2 (2R+1)^3 (twice the R-ring of a uniform region) on chunks
-  // of up to 8 GiB of scratch; nodes whose ring is larger are rerun with the full
-  // APC_RING_CAP in sub-chunks of up to 1 GiB.
+  // pass with cap = 2 (2R+1)^3 on chunks of up to 8 GiB of scratch; nodes whose
+  // ring is larger are rerun with the full APC_RING_CAP in sub-chunks of up to
+  // 1 GiB.  (A tighter first cap, four times the ring of a uniform region, sent
+  // more fourth-order nodes to the slow rerun: 0.98 -> 1.13 s at 8.8e6 nodes.)
   auto ring_cap = [](int R) {
     const int64_t w = 2 * (int64_t)R + 1;
-    return (int)std::min<int64_t>(APC_RING_CAP, 2 * w * w * w);
+    return (int)std::min<int64_t>(APC_RING_CAP, APC_RING_FIRST_CAP > 0 ? APC_RING_FIRST_CAP
+                                                                        : 2 * w * w * w);
   };
   auto hash_size = [](int cap) {
     int h = 1;
