@@ -405,6 +405,10 @@ def main():
     log(f"{args.precision}/{args.precond}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
     roof = spmv_roofline(torch, cloud, args.spmv_reps, prec != apc.APC_FP64, args.workload)
     roof["stream_copy"] = stream_probe(torch)
+    if roof["traffic"] is not None:
+        # the counted HBM bytes per launch over the launch time, against the copy probe
+        roof["traffic_GBs"] = round(roof["traffic"] / (roof["avg_us"] * 1e-6) / 1e9, 1)
+        roof["traffic_vs_copy"] = round(roof["traffic_GBs"] / roof["stream_copy"]["GBs"], 3)
     log(f"spmv roofline: {roof}")
     roof_m = None
     if args.precond == "learned":
