@@ -185,6 +185,13 @@ int apc_scan_i32(const int32_t *in, int32_t *out, int64_t n, hipStream_t s);  //
 int apc_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s);  // exclusive
 int apc_sum_i32(const int32_t *in, int64_t n, int64_t *host_out, hipStream_t s);
 int apc_radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream_t s);
+// Stream-ordered temporaries through a cache: a block freed on stream s goes to
+// a free list of (device, s) and serves the next allocation of a fitting size on
+// that same stream (stream order makes the reuse safe) without a HIP call; the
+// HIP stream-ordered allocator is called only on a miss, and blocks beyond a
+// 16 GiB cache go back to it.  Same signatures as hipMallocAsync / hipFreeAsync.
+hipError_t apc_malloc_async(void **p, size_t bytes, hipStream_t s);
+hipError_t apc_free_async(void *p, hipStream_t s);
 
 int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_t s,
                    apc_cloud **out);

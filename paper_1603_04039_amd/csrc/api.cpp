@@ -197,10 +197,10 @@ int apc_deposit(apc_cloud *c, const double *q, double *rho_M, double *rho_t, dou
   if (!g.ok) return APC_EHIP;
   if (!c->assembled) return APC_EINVAL;
   double *rm = rho_M;
-  if (!rm) HIPCHK(hipMallocAsync((void **)&rm, (size_t)(c->n + c->nb) * sizeof(double), stream));
+  if (!rm) HIPCHK(apc_malloc_async((void **)&rm, (size_t)(c->n + c->nb) * sizeof(double), stream));
   int rc = apc_deposit_impl(c, q, rm, stream);
   if (rc == APC_OK) rc = apc_density_solve_impl(c, rm, rho_t, tol, maxit, st, stream);
-  if (!rho_M) HIPCHK(hipFreeAsync(rm, stream));
+  if (!rho_M) HIPCHK(apc_free_async(rm, stream));
   return rc;
 }
 
@@ -326,9 +326,9 @@ int apc_batch_deposit(apc_batch *b, const double *q, double *rho_M, double *rho_
   DeviceGuard g(u->device);
   if (!g.ok) return APC_EHIP;
   double *rm = rho_M;
-  if (!rm) HIPCHK(hipMallocAsync((void **)&rm, (size_t)(u->n + u->nb) * sizeof(double), stream));
+  if (!rm) HIPCHK(apc_malloc_async((void **)&rm, (size_t)(u->n + u->nb) * sizeof(double), stream));
   const int rc = apc_batch_deposit_impl(b, q, rm, rho_t, tol, maxit, st, stream);
-  if (!rho_M) HIPCHK(hipFreeAsync(rm, stream));
+  if (!rho_M) HIPCHK(apc_free_async(rm, stream));
   return rc;
 }
 

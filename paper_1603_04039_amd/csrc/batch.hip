@@ -943,11 +943,11 @@ int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, 
   APCCHK(ensure_bws(B));
   const int64_t ntot = B->u->n + B->u->nb;
   double *f = nullptr, *y = nullptr, *rhoM = nullptr, *rhot = nullptr, *phi = nullptr;
-  HIPCHK(hipMallocAsync((void **)&f, (size_t)ntot * 8, s));
-  HIPCHK(hipMallocAsync((void **)&y, (size_t)ntot * 8, s));
-  HIPCHK(hipMallocAsync((void **)&rhoM, (size_t)ntot * 8, s));
-  HIPCHK(hipMallocAsync((void **)&rhot, (size_t)ntot * 8, s));
-  HIPCHK(hipMallocAsync((void **)&phi, (size_t)ntot * 8, s));
+  HIPCHK(apc_malloc_async((void **)&f, (size_t)ntot * 8, s));
+  HIPCHK(apc_malloc_async((void **)&y, (size_t)ntot * 8, s));
+  HIPCHK(apc_malloc_async((void **)&rhoM, (size_t)ntot * 8, s));
+  HIPCHK(apc_malloc_async((void **)&rhot, (size_t)ntot * 8, s));
+  HIPCHK(apc_malloc_async((void **)&phi, (size_t)ntot * 8, s));
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(ntot)), dim3(APC_BLOCK), 0, s, f, ntot, 1.0);
   const Op op = make_op(B->u, false);
   float best = 1e30f;
@@ -995,11 +995,11 @@ int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, 
     }
   }
   B->chunk = best_chunk;
-  HIPCHK(hipFreeAsync(f, s));
-  HIPCHK(hipFreeAsync(y, s));
-  HIPCHK(hipFreeAsync(rhoM, s));
-  HIPCHK(hipFreeAsync(rhot, s));
-  HIPCHK(hipFreeAsync(phi, s));
+  HIPCHK(apc_free_async(f, s));
+  HIPCHK(apc_free_async(y, s));
+  HIPCHK(apc_free_async(rhoM, s));
+  HIPCHK(apc_free_async(rhot, s));
+  HIPCHK(apc_free_async(phi, s));
   HIPCHK(hipStreamSynchronize(s));
   if (out_div) *out_div = B->spmv_div;
   if (out_chunk) *out_chunk = B->chunk;

@@ -66,19 +66,19 @@ struct Cells {
 int cells_alloc(Cells &c, int64_t n, hipStream_t s) {
   c.n = n;
   size_t m = (size_t)(n > 0 ? n : 1);
-  HIPCHK(hipMallocAsync((void **)&c.pre, m * sizeof(uint64_t), s));
-  HIPCHK(hipMallocAsync((void **)&c.lev, m * sizeof(int32_t), s));
-  HIPCHK(hipMallocAsync((void **)&c.fst, m * sizeof(int32_t), s));
-  HIPCHK(hipMallocAsync((void **)&c.cnt, m * sizeof(int32_t), s));
-  HIPCHK(hipMallocAsync((void **)&c.flag, m * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&c.pre, m * sizeof(uint64_t), s));
+  HIPCHK(apc_malloc_async((void **)&c.lev, m * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&c.fst, m * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&c.cnt, m * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&c.flag, m * sizeof(int32_t), s));
   return APC_OK;
 }
 int cells_free(Cells &c, hipStream_t s) {
-  if (c.pre) HIPCHK(hipFreeAsync(c.pre, s));
-  if (c.lev) HIPCHK(hipFreeAsync(c.lev, s));
-  if (c.fst) HIPCHK(hipFreeAsync(c.fst, s));
-  if (c.cnt) HIPCHK(hipFreeAsync(c.cnt, s));
-  if (c.flag) HIPCHK(hipFreeAsync(c.flag, s));
+  if (c.pre) HIPCHK(apc_free_async(c.pre, s));
+  if (c.lev) HIPCHK(apc_free_async(c.lev, s));
+  if (c.fst) HIPCHK(apc_free_async(c.fst, s));
+  if (c.cnt) HIPCHK(apc_free_async(c.cnt, s));
+  if (c.flag) HIPCHK(apc_free_async(c.flag, s));
   c = Cells();
   return APC_OK;
 }
@@ -536,12 +536,12 @@ __global__ void __launch_bounds__(APC_BLOCK)
 
 template <typename T>
 int dalloc(T **p, int64_t n, hipStream_t s) {
-  HIPCHK(hipMallocAsync((void **)p, (size_t)(n > 0 ? n : 1) * sizeof(T), s));
+  HIPCHK(apc_malloc_async((void **)p, (size_t)(n > 0 ? n : 1) * sizeof(T), s));
   return APC_OK;
 }
 template <typename T>
 int dfree(T *&p, hipStream_t s) {
-  if (p) HIPCHK(hipFreeAsync(p, s));
+  if (p) HIPCHK(apc_free_async(p, s));
   p = nullptr;
   return APC_OK;
 }

@@ -542,12 +542,12 @@ int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad
                     hipStream_t s) {
   if (c->P.order == 4) return apc_interp4(c, phi, phi_p, grad_p, s);
   double *D = nullptr;
-  HIPCHK(hipMallocAsync((void **)&D, (size_t)c->n * P9 * sizeof(double), s));
+  HIPCHK(apc_malloc_async((void **)&D, (size_t)c->n * P9 * sizeof(double), s));
   APCCHK(apc_node_derivs_impl(c, phi, D, s));
   hipLaunchKernelGGL(k_interp, dim3(grid_for(c->N)), dim3(APC_BLOCK), 0, s, c->N, c->sxyz, c->perm,
                      c->pnode, c->crd, c->n + c->nb, c->P.lo[0], c->P.lo[1], c->P.lo[2], c->unit,
                      phi, D, phi_p, grad_p);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipFreeAsync(D, s));
+  HIPCHK(apc_free_async(D, s));
   return APC_OK;
 }

@@ -625,8 +625,8 @@ int apc_learn_data_impl(apc_cloud *c, const double *Z, int K, float *feat, float
   HIPCHK(hipGetLastError());
   if (!Z || K < 1 || n == 0) return APC_OK;
   double *U = nullptr, *Zc = nullptr;
-  HIPCHK(hipMallocAsync((void **)&U, (size_t)K * ntot * sizeof(double), s));
-  HIPCHK(hipMallocAsync((void **)&Zc, (size_t)K * ntot * sizeof(double), s));
+  HIPCHK(apc_malloc_async((void **)&U, (size_t)K * ntot * sizeof(double), s));
+  HIPCHK(apc_malloc_async((void **)&Zc, (size_t)K * ntot * sizeof(double), s));
   for (int k = 0; k < K; k++) {
     double *zt = Zc + (int64_t)k * ntot;
     hipLaunchKernelGGL(k_probe_copy, dim3(grid_for(ntot)), dim3(APC_BLOCK), 0, s,
@@ -636,8 +636,8 @@ int apc_learn_data_impl(apc_cloud *c, const double *Z, int K, float *feat, float
   hipLaunchKernelGGL(k_learn_quad, dim3(grid_for(n * NQ)), dim3(APC_BLOCK), 0, s, r,
                      (const double *)Zc, (const double *)U, K, ntot, quad);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipFreeAsync(U, s));
-  HIPCHK(hipFreeAsync(Zc, s));
+  HIPCHK(apc_free_async(U, s));
+  HIPCHK(apc_free_async(Zc, s));
   return APC_OK;
 }
 
@@ -647,14 +647,14 @@ int apc_mlp_loss_grad_impl(const float *P, const float *feat, const float *quad,
   float *H1 = nullptr, *H2 = nullptr, *O = nullptr, *dO = nullptr, *dH2 = nullptr, *dH1 = nullptr,
         *lrow = nullptr, *part = nullptr;
   const int nch = (B + CH - 1) / CH;
-  HIPCHK(hipMallocAsync((void **)&H1, (size_t)B * HID * 4, s));
-  HIPCHK(hipMallocAsync((void **)&H2, (size_t)B * HID * 4, s));
-  HIPCHK(hipMallocAsync((void **)&O, (size_t)B * OUT * 4, s));
-  HIPCHK(hipMallocAsync((void **)&dO, (size_t)B * OUT * 4, s));
-  HIPCHK(hipMallocAsync((void **)&dH2, (size_t)B * HID * 4, s));
-  HIPCHK(hipMallocAsync((void **)&dH1, (size_t)B * HID * 4, s));
-  HIPCHK(hipMallocAsync((void **)&lrow, (size_t)B * 4, s));
-  HIPCHK(hipMallocAsync((void **)&part, (size_t)nch * (HID + 1) * HID * 4, s));
+  HIPCHK(apc_malloc_async((void **)&H1, (size_t)B * HID * 4, s));
+  HIPCHK(apc_malloc_async((void **)&H2, (size_t)B * HID * 4, s));
+  HIPCHK(apc_malloc_async((void **)&O, (size_t)B * OUT * 4, s));
+  HIPCHK(apc_malloc_async((void **)&dO, (size_t)B * OUT * 4, s));
+  HIPCHK(apc_malloc_async((void **)&dH2, (size_t)B * HID * 4, s));
+  HIPCHK(apc_malloc_async((void **)&dH1, (size_t)B * HID * 4, s));
+  HIPCHK(apc_malloc_async((void **)&lrow, (size_t)B * 4, s));
+  HIPCHK(apc_malloc_async((void **)&part, (size_t)nch * (HID + 1) * HID * 4, s));
   auto g = [](int64_t t) { return dim3(grid_for(t)); };
   hipLaunchKernelGGL(k_dense_fwd, g((int64_t)B * HID), dim3(APC_BLOCK), 0, s, feat, rows, B, IN, HID,
                      P + OW1, P + OB1, 1, H1);
@@ -685,7 +685,7 @@ int apc_mlp_loss_grad_impl(const float *P, const float *feat, const float *quad,
                      grad + OW1, grad + OB1);
   HIPCHK(hipGetLastError());
   float *bufs[] = {H1, H2, O, dO, dH2, dH1, lrow, part};
-  for (float *b : bufs) HIPCHK(hipFreeAsync(b, s));
+  for (float *b : bufs) HIPCHK(apc_free_async(b, s));
   return APC_OK;
 }
 
@@ -707,7 +707,7 @@ int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16
     return APC_OK;
   }
   uint16_t *wb = nullptr;
-  HIPCHK(hipMallocAsync((void **)&wb, (size_t)NWB * 2, s));
+  HIPCHK(apc_malloc_async((void **)&wb, (size_t)NWB * 2, s));
   hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(HID * HID)), dim3(APC_BLOCK), 0, s, P, wb,
                      wb + HID * K1, wb + HID * K1 + HID * HID);
   InferOut io = make_out(c, 0);
@@ -716,7 +716,7 @@ int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16
     hipLaunchKernelGGL(k_infer_bf16, dim3(infer_grid(c->nsl)), dim3(WPB * 64), 0, s,
                        make_in(c, feat, nullptr), P, (const uint16_t *)wb, io);
   HIPCHK(hipGetLastError());
-  HIPCHK(hipFreeAsync(wb, s));
+  HIPCHK(apc_free_async(wb, s));
   return APC_OK;
 }
 
@@ -729,8 +729,8 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
   if (!c->m_tmpl) HIPCHK(hipMalloc((void **)&c->m_tmpl, (size_t)APC_MAX_LEVELS * NT * sizeof(float)));
   uint16_t *wb = nullptr;
   int32_t *rep = nullptr;
-  HIPCHK(hipMallocAsync((void **)&wb, (size_t)NWB * 2, s));
-  HIPCHK(hipMallocAsync((void **)&rep, (size_t)(APC_MAX_LEVELS + APC_SLICE) * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&wb, (size_t)NWB * 2, s));
+  HIPCHK(apc_malloc_async((void **)&rep, (size_t)(APC_MAX_LEVELS + APC_SLICE) * sizeof(int32_t), s));
   int32_t *tab = rep + APC_MAX_LEVELS;
   hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(HID * HID)), dim3(APC_BLOCK), 0, s, P, wb,
                      wb + HID * K1, wb + HID * K1 + HID * HID);
@@ -747,13 +747,13 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
                      make_in(c, nullptr, (const int32_t *)tab), P, (const uint16_t *)wb,
                      make_out(c, 2));
   HIPCHK(hipGetLastError());
-  HIPCHK(hipFreeAsync(wb, s));
-  HIPCHK(hipFreeAsync(rep, s));
+  HIPCHK(apc_free_async(wb, s));
+  HIPCHK(apc_free_async(rep, s));
   if (Z && K > 0 && c->nsl > 0) {
     const int64_t ntot = n + c->nb;
     double *U = nullptr, *Zc = nullptr;
-    HIPCHK(hipMallocAsync((void **)&U, (size_t)K * ntot * sizeof(double), s));
-    HIPCHK(hipMallocAsync((void **)&Zc, (size_t)K * ntot * sizeof(double), s));
+    HIPCHK(apc_malloc_async((void **)&U, (size_t)K * ntot * sizeof(double), s));
+    HIPCHK(apc_malloc_async((void **)&Zc, (size_t)K * ntot * sizeof(double), s));
     for (int k = 0; k < K; k++) {
       double *zt = Zc + (int64_t)k * ntot;
       hipLaunchKernelGGL(k_probe_copy, dim3(grid_for(ntot)), dim3(APC_BLOCK), 0, s,
@@ -764,8 +764,8 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
                        c->sl_rows, c->sl_tmpl, c->sl_len, c->sl_idx, c->sl_off, c->nsl, c->diag,
                        (const double *)Zc, (const double *)U, K, n, ntot, c->m_diag, c->m_sell);
     HIPCHK(hipGetLastError());
-    HIPCHK(hipFreeAsync(U, s));
-    HIPCHK(hipFreeAsync(Zc, s));
+    HIPCHK(apc_free_async(U, s));
+    HIPCHK(apc_free_async(Zc, s));
   }
   HIPCHK(hipStreamSynchronize(s));
   c->learned = true;

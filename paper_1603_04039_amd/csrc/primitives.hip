@@ -2,6 +2,11 @@
 // a stable LSD radix sort of (64-bit key, 32-bit value) pairs.
 #include <hip/hip_runtime.h>
 
+#include <map>
+#include <mutex>
+#include <unordered_map>
+#include <utility>
+
 #include "apc_internal.h"
 
 namespace {
@@ -59,7 +64,7 @@ int scan_rec(const T *in, T *out, int64_t n, hipStream_t s) {
   if (n <= 0) return APC_OK;
   const int64_t nb = (n + SCAN_TILE - 1) / SCAN_TILE;
   T *bsum = nullptr;
-  HIPCHK(hipMallocAsync((void **)&bsum, (size_t)nb * sizeof(T), s));
+  HIPCHK(apc_malloc_async((void **)&bsum, (size_t)nb * sizeof(T), s));
   hipLaunchKernelGGL(k_scan_tile<T>, dim3((unsigned)nb), dim3(APC_BLOCK), 0, s, in, out, bsum, n);
   HIPCHK(hipGetLastError());
   if (nb > 1) {
@@ -68,7 +73,7 @@ int scan_rec(const T *in, T *out, int64_t n, hipStream_t s) {
     hipLaunchKernelGGL(k_scan_add<T>, dim3((unsigned)nb), dim3(APC_BLOCK), 0, s, out, bsum, n);
     HIPCHK(hipGetLastError());
   }
-  HIPCHK(hipFreeAsync(bsum, s));
+  HIPCHK(apc_free_async(bsum, s));
   return APC_OK;
 }
 
@@ -155,7 +160,7 @@ int apc_scan_i64(const int64_t *in, int64_t *out, int64_t n, hipStream_t s) {
 
 int apc_sum_i32(const int32_t *in, int64_t n, int64_t *host_out, hipStream_t s) {
   unsigned long long *acc = nullptr;
-  HIPCHK(hipMallocAsync((void **)&acc, sizeof(unsigned long long), s));
+  HIPCHK(apc_malloc_async((void **)&acc, sizeof(unsigned long long), s));
   HIPCHK(hipMemsetAsync(acc, 0, sizeof(unsigned long long), s));
   unsigned g = grid_for(n);
   if (g > 4096) g = 4096;
@@ -164,7 +169,7 @@ int apc_sum_i32(const int32_t *in, int64_t n, int64_t *host_out, hipStream_t s) 
   unsigned long long h = 0;
   HIPCHK(hipMemcpyAsync(&h, acc, sizeof(h), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipFreeAsync(acc, s));
+  HIPCHK(apc_free_async(acc, s));
   *host_out = (int64_t)h;
   return APC_OK;
 }
@@ -175,9 +180,9 @@ int apc_radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream
   const unsigned nblk = (unsigned)((ntiles + RS_WAVES - 1) / RS_WAVES);
   uint64_t *k2 = nullptr;
   int32_t *v2 = nullptr, *hist = nullptr;
-  HIPCHK(hipMallocAsync((void **)&k2, (size_t)n * sizeof(uint64_t), s));
-  HIPCHK(hipMallocAsync((void **)&v2, (size_t)n * sizeof(int32_t), s));
-  HIPCHK(hipMallocAsync((void **)&hist, (size_t)ntiles * 256 * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&k2, (size_t)n * sizeof(uint64_t), s));
+  HIPCHK(apc_malloc_async((void **)&v2, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&hist, (size_t)ntiles * 256 * sizeof(int32_t), s));
   uint64_t *ka = keys, *kb = k2;
   int32_t *va = vals, *vb = v2;
   for (int shift = 0; shift < bits; shift += 8) {
@@ -199,8 +204,95 @@ int apc_radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream
     HIPCHK(hipMemcpyAsync(keys, ka, (size_t)n * sizeof(uint64_t), hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(vals, va, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
   }
-  HIPCHK(hipFreeAsync(k2, s));
-  HIPCHK(hipFreeAsync(v2, s));
-  HIPCHK(hipFreeAsync(hist, s));
+  HIPCHK(apc_free_async(k2, s));
+  HIPCHK(apc_free_async(v2, s));
+  HIPCHK(apc_free_async(hist, s));
   return APC_OK;
+}
+
+// ---------------------------------------------------------------- temporaries
+namespace {
+struct TmpCache {
+  std::mutex mu;
+  // (device, stream) -> size class -> free blocks
+  std::map<std::pair<int, hipStream_t>, std::multimap<size_t, void *>> free;
+  std::unordered_map<void *, size_t> live; // block -> size class
+  size_t cached = 0;
+};
+TmpCache &tmp_cache() {
+  static TmpCache *c = new TmpCache(); // never destroyed: blocks live until process exit
+  return *c;
+}
+constexpr size_t TMP_CACHE_MAX = (size_t)16 << 30;
+// sizes round up to a power of two below 2 MiB and to 2 MiB steps above
+size_t tmp_class(size_t b) {
+  if (b <= 256) return 256;
+  if (b < ((size_t)2 << 20)) {
+    size_t c = 512;
+    while (c < b) c <<= 1;
+    return c;
+  }
+  const size_t g = (size_t)2 << 20;
+  return (b + g - 1) / g * g;
+}
+} // namespace
+
+hipError_t apc_malloc_async(void **p, size_t bytes, hipStream_t s) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t cls = tmp_class(bytes);
+  TmpCache &C = tmp_cache();
+  {
+    std::lock_guard<std::mutex> lock(C.mu);
+    auto f = C.free.find({dev, s});
+    if (f != C.free.end()) {
+      auto it = f->second.lower_bound(cls);
+      // a cached block at most twice the request
+      if (it != f->second.end() && it->first <= 2 * cls) {
+        *p = it->second;
+        C.live[it->second] = it->first;
+        C.cached -= it->first;
+        f->second.erase(it);
+        return hipSuccess;
+      }
+    }
+  }
+  e = hipMallocAsync(p, cls, s);
+  if (e == hipErrorOutOfMemory) {
+    // give this device's cached blocks back, then try once more
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lock(C.mu);
+    for (auto &kv : C.free) {
+      if (kv.first.first != dev) continue;
+      for (auto &b : kv.second) {
+        (void)hipFreeAsync(b.second, kv.first.second);
+        C.cached -= b.first;
+      }
+      kv.second.clear();
+    }
+    (void)hipDeviceSynchronize();
+    e = hipMallocAsync(p, cls, s);
+  }
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(C.mu);
+  C.live[*p] = cls;
+  return hipSuccess;
+}
+
+hipError_t apc_free_async(void *p, hipStream_t s) {
+  if (!p) return hipSuccess;
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  TmpCache &C = tmp_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  auto it = C.live.find(p);
+  if (it == C.live.end()) return hipFreeAsync(p, s); // not from apc_malloc_async
+  const size_t cls = it->second;
+  C.live.erase(it);
+  if (C.cached + cls > TMP_CACHE_MAX) return hipFreeAsync(p, s);
+  C.free[{dev, s}].insert({cls, p});
+  C.cached += cls;
+  return hipSuccess;
 }

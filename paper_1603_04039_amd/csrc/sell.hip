@@ -222,10 +222,10 @@ __global__ void __launch_bounds__(APC_BLOCK) k_cap_un(int32_t *un, int64_t ns, i
 int apc_build_sell(apc_cloud *c, hipStream_t s) {
   const int64_t n = c->n;
   int32_t *tf = nullptr, *tpos = nullptr, *srow_t = nullptr, *srow_g = nullptr;
-  HIPCHK(hipMallocAsync((void **)&tf, (size_t)n * sizeof(int32_t), s));
-  HIPCHK(hipMallocAsync((void **)&tpos, (size_t)(n + 1) * sizeof(int32_t), s));
-  HIPCHK(hipMallocAsync((void **)&srow_t, (size_t)n * sizeof(int32_t), s));
-  HIPCHK(hipMallocAsync((void **)&srow_g, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&tf, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&tpos, (size_t)(n + 1) * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&srow_t, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&srow_g, (size_t)n * sizeof(int32_t), s));
   hipLaunchKernelGGL(k_tflag, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, n, tf);
   APCCHK(apc_scan_i32(tf, tpos, n, s));
   hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, tpos, n, srow_t,
@@ -266,12 +266,12 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   const int64_t ng = n - T[8];
   if (APC_SELL_SIGMA > SL && ng > 1) {
     uint64_t *key = nullptr;
-    HIPCHK(hipMallocAsync((void **)&key, (size_t)ng * sizeof(uint64_t), s));
+    HIPCHK(apc_malloc_async((void **)&key, (size_t)ng * sizeof(uint64_t), s));
     hipLaunchKernelGGL(k_sigma_keys, dim3(grid_for(ng)), dim3(APC_BLOCK), 0, s, G, srow_g, c->st_off,
                        ng, key);
     HIPCHK(hipGetLastError());
     APCCHK(apc_radix_sort(key, srow_g, ng, 36, s));
-    HIPCHK(hipFreeAsync(key, s));
+    HIPCHK(apc_free_async(key, s));
   }
   const size_t nsz = (size_t)(ns > 0 ? ns : 1);
   HIPCHK(hipMalloc((void **)&c->sl_rows, nsz * SL * sizeof(int32_t)));
@@ -279,7 +279,7 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   HIPCHK(hipMalloc((void **)&c->sl_tmpl, nsz * sizeof(int32_t)));
   HIPCHK(hipMalloc((void **)&c->sl_off, nsz * sizeof(int64_t)));
   int64_t *ent = nullptr;
-  HIPCHK(hipMallocAsync((void **)&ent, nsz * sizeof(int64_t), s));
+  HIPCHK(apc_malloc_async((void **)&ent, nsz * sizeof(int64_t), s));
   if (ns > 0) {
     hipLaunchKernelGGL(k_slices, dim3((unsigned)ns), dim3(SL), 0, s, G, srow_t, srow_g, c->st_off,
                        c->sl_rows, c->sl_len, c->sl_tmpl, ent);
@@ -305,11 +305,11 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   if (c->sl_w64) HIPCHK(hipMemsetAsync(c->sl_w64, 0, ne * sizeof(double), s));
   if (c->sl_w32) HIPCHK(hipMemsetAsync(c->sl_w32, 0, ne * sizeof(float), s));
   APCCHK(apc_pack_sell_idx(c, s));
-  HIPCHK(hipFreeAsync(ent, s));
-  HIPCHK(hipFreeAsync(tf, s));
-  HIPCHK(hipFreeAsync(tpos, s));
-  HIPCHK(hipFreeAsync(srow_t, s));
-  HIPCHK(hipFreeAsync(srow_g, s));
+  HIPCHK(apc_free_async(ent, s));
+  HIPCHK(apc_free_async(tf, s));
+  HIPCHK(apc_free_async(tpos, s));
+  HIPCHK(apc_free_async(srow_t, s));
+  HIPCHK(apc_free_async(srow_g, s));
   return APC_OK;
 }
 
