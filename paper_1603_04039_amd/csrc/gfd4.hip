@@ -171,70 +171,87 @@ __device__ __forceinline__ Geo stencil_rows(Wave4 &S, int lane, const int32_t *n
   return g;
 }
 
+// One Householder step of col_qr on the first LEN rows of the lane's column: the
+// rows below are zero after the earlier steps' shifts, so the sums skip exact
+// zeros only and the arithmetic (the partial sum of row r is r % 4) is that of a
+// step over all rows.
+template <int MR, int LEN>
+__device__ __forceinline__ void qr_step(Wave4 &S, int lane, int k, int ncol, double (&a)[MR],
+                                        double &rd) {
+  // a[] = rows k..k+LEN-1 of the lane's column; lane k's reflector:
+  // v = a - alpha e_0, alpha = -sign(a_0) ||a||
+  double q[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+  for (int r = 0; r < LEN; r++) q[r & 3] += a[r] * a[r];
+  if (lane == k) {
+    const double nrm = sqrt((q[0] + q[1]) + (q[2] + q[3]));
+    double alpha = 0.0, bt = 0.0;
+    if (nrm > 0.0) {
+      alpha = a[0] >= 0.0 ? -nrm : nrm;
+      double e[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+      for (int r = 0; r < LEN; r++) {
+        const double v = r == 0 ? a[0] - alpha : a[r];
+        e[r & 3] += v * v;
+        S.v[r] = v;
+      }
+      const double vn2 = (e[0] + e[1]) + (e[2] + e[3]);
+      bt = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
+    } else {
+#pragma unroll
+      for (int r = 0; r < LEN; r++) S.v[r] = 0.0;
+    }
+    S.beta = bt;
+    S.A[k * RLD + k] = alpha;
+    rd = alpha;
+  }
+  wsync();
+  // every later column: a -= beta (v . a) v; its new pivot entry is R_k,lane
+  if (lane > k && lane < ncol) {
+    double d[4] = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int r0 = 0; r0 < LEN; r0 += RC) {
+#pragma unroll
+      for (int r = r0; r < r0 + RC; r++) d[r & 3] += S.v[r] * a[r];
+      __asm__ volatile("" ::: "memory");
+    }
+    const double sc = ((d[0] + d[1]) + (d[2] + d[3])) * S.beta;
+#pragma unroll
+    for (int r0 = 0; r0 < LEN; r0 += RC) {
+#pragma unroll
+      for (int r = r0; r < r0 + RC; r++) a[r] -= sc * S.v[r];
+      __asm__ volatile("" ::: "memory");
+    }
+    S.A[k * RLD + lane] = a[0];
+  }
+#pragma unroll
+  for (int r = 0; r < LEN - 1; r++) a[r] = a[r + 1];
+  a[LEN - 1] = 0.0;
+  wsync(); // the reflector reads are done before the next step rewrites it
+}
+
 // Column-parallel Householder QR of the first pc columns in LDS (column-major,
 // stride LD), with columns pc..ncol-1 carried along (they receive Q^T).  Lane
-// c < ncol holds column c; after step k it drops the finished row k, so a[0] is
-// always the pivot row and no step needs a row predicate.  On return R is in LDS
-// row-major with stride RLD (R_ij at A[i * RLD + j], i <= j < pc) and row i of
-// Q^T times the extra column c at A[i * RLD + c].  Returns min|R_ii| / max|R_ii|.
+// c < ncol holds column c (its first MR rows: MR >= the stencil size); after step
+// k it drops the finished row k, so a[0] is always the pivot row and no step needs
+// a row predicate, and steps 8p .. 8p+7 work on the first MR - 8p rows only (the
+// rest are zero).  On return R is in LDS row-major with stride RLD (R_ij at
+// A[i * RLD + j], i <= j < pc) and row i of Q^T times the extra column c at
+// A[i * RLD + c].  Returns min|R_ii| / max|R_ii|.
+template <int MR>
 __device__ __forceinline__ double col_qr(Wave4 &S, int lane, int pc, int ncol) {
+  static_assert(MR % RC == 0 && MR - 32 >= RC, "row chunks");
   double a[MR];
 #pragma unroll
   for (int r = 0; r < MR; r++) a[r] = lane < ncol ? S.A[lane * LD + r] : 0.0;
   wsync(); // every column is in registers before R reuses the buffer
   double rd = 0.0;
-  for (int k = 0; k < pc; k++) {
-    // a[] = rows k..k+MR-1 of the lane's column (zeros past the stencil); lane
-    // k's reflector: v = a - alpha e_0, alpha = -sign(a_0) ||a||
-    double q[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-    for (int r = 0; r < MR; r++) q[r & 3] += a[r] * a[r];
-    if (lane == k) {
-      const double nrm = sqrt((q[0] + q[1]) + (q[2] + q[3]));
-      double alpha = 0.0, bt = 0.0;
-      if (nrm > 0.0) {
-        alpha = a[0] >= 0.0 ? -nrm : nrm;
-        double e[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int r = 0; r < MR; r++) {
-          const double v = r == 0 ? a[0] - alpha : a[r];
-          e[r & 3] += v * v;
-          S.v[r] = v;
-        }
-        const double vn2 = (e[0] + e[1]) + (e[2] + e[3]);
-        bt = vn2 > 0.0 ? 2.0 / vn2 : 0.0;
-      } else {
-#pragma unroll
-        for (int r = 0; r < MR; r++) S.v[r] = 0.0;
-      }
-      S.beta = bt;
-      S.A[k * RLD + k] = alpha;
-      rd = alpha;
-    }
-    wsync();
-    // every later column: a -= beta (v . a) v; its new pivot entry is R_k,lane
-    if (lane > k && lane < ncol) {
-      double d[4] = {0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-      for (int r0 = 0; r0 < MR; r0 += RC) {
-#pragma unroll
-        for (int r = r0; r < r0 + RC; r++) d[r & 3] += S.v[r] * a[r];
-        __asm__ volatile("" ::: "memory");
-      }
-      const double sc = ((d[0] + d[1]) + (d[2] + d[3])) * S.beta;
-#pragma unroll
-      for (int r0 = 0; r0 < MR; r0 += RC) {
-#pragma unroll
-        for (int r = r0; r < r0 + RC; r++) a[r] -= sc * S.v[r];
-        __asm__ volatile("" ::: "memory");
-      }
-      S.A[k * RLD + lane] = a[0];
-    }
-#pragma unroll
-    for (int r = 0; r < MR - 1; r++) a[r] = a[r + 1];
-    a[MR - 1] = 0.0;
-    wsync(); // the reflector reads are done before the next step rewrites it
-  }
+  int k = 0;
+  for (; k < pc && k < 8; k++) qr_step<MR, MR>(S, lane, k, ncol, a, rd);
+  for (; k < pc && k < 16; k++) qr_step<MR, MR - 8>(S, lane, k, ncol, a, rd);
+  for (; k < pc && k < 24; k++) qr_step<MR, MR - 16>(S, lane, k, ncol, a, rd);
+  for (; k < pc && k < 32; k++) qr_step<MR, MR - 24>(S, lane, k, ncol, a, rd);
+  for (; k < pc; k++) qr_step<MR, MR - 32>(S, lane, k, ncol, a, rd);
   const double rmin = wmin_d(lane < pc ? fabs(rd) : INFINITY);
   const double rmax = wmax_d(lane < pc ? fabs(rd) : 0.0);
   return rmax > 0.0 ? rmin / rmax : 0.0;
@@ -319,6 +336,7 @@ __device__ __forceinline__ void wv0_times(Wave4 &S, const Geo &g, int lane, int 
 }
 
 // ---------------------------------------------------------------- rank test (build)
+template <int MR>
 __global__ void __launch_bounds__(WPB4 * 64, 2)
     k_rank_qr(int pc, const int32_t *__restrict__ pending, int64_t np, const int32_t *__restrict__ cand,
               int32_t *__restrict__ m, const int32_t *__restrict__ crd, int64_t ntot) {
@@ -331,7 +349,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
   Wave4 &S = SH[wv];
   const Geo g = stencil_rows(S, lane, cand + t * APC_MAXM, mm, crd, ntot, pending[t]);
   wsync();
-  const double ratio = col_qr(S, lane, pc, pc);
+  const double ratio = col_qr<MR>(S, lane, pc, pc);
   bool ok = ratio >= APC_TAU_RANK;
   if (ok && pc == P4) {
     // stability of the order-4 Laplacian row: negative diagonal and off-diagonal
@@ -349,7 +367,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
 
 // ---------------------------------------------------------------- assembly
 // Laplacian and density rows of every node (CSR order); one wavefront per node
-template <bool MIXED>
+template <bool MIXED, int MR>
 __global__ void __launch_bounds__(WPB4 * 64, 2)
     k_fit4(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
            const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
@@ -367,7 +385,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
   const int pc = rorder[y] == 4 ? P4 : 9;
   const Geo g = stencil_rows(S, lane, st_idx + a0, m, crd, ntot, y);
   wsync();
-  const double ratio = col_qr(S, lane, pc, pc);
+  const double ratio = col_qr<MR>(S, lane, pc, pc);
   if (!(ratio >= APC_TAU_RANK)) {
     if (lane == 0) *err = 1;
     return;
@@ -433,6 +451,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 }
 
 // ---------------------------------------------------------------- derivatives
+template <int MR>
 __global__ void __launch_bounds__(WPB4 * 64, 2)
     k_node_derivs4(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
                    const int32_t *__restrict__ crd, int64_t ntot, const int8_t *__restrict__ rorder,
@@ -450,7 +469,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
   // W (f_j - f_0) as column pc, transformed by the QR into Q^T W (f_j - f_0)
   S.A[pc * LD + lane] = lane < m ? g.W * (f[st_idx[a0 + lane]] - f[y]) : 0.0;
   wsync();
-  col_qr(S, lane, pc, pc + 1);
+  col_qr<MR>(S, lane, pc, pc + 1);
   const double ai = solve_r(S, lane, pc, lane < pc ? S.A[lane * RLD + pc] : 0.0);
   if (lane >= pc && lane < P4) D[y * P4 + lane] = 0.0; // order-2 fallback row
   if (lane < pc) {
@@ -515,8 +534,13 @@ inline unsigned grid4(int64_t count) {
 int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t np,
                     const int32_t *cand, int32_t *m, hipStream_t s) {
   if (np <= 0) return APC_OK;
-  hipLaunchKernelGGL(k_rank_qr, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, pending, np, cand, m,
-                     c->crd, c->n + c->nb);
+  // stencils hold at most m_cap rows (order-2 fallback: 40): QR over 56 or 64 rows
+  if (c->P.m_cap <= 56)
+    hipLaunchKernelGGL(k_rank_qr<56>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, pending, np,
+                       cand, m, c->crd, c->n + c->nb);
+  else
+    hipLaunchKernelGGL(k_rank_qr<APC_MAXM>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, pending,
+                       np, cand, m, c->crd, c->n + c->nb);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
@@ -527,14 +551,20 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
   HIPCHK(hipMemsetAsync(&c->scratch->err, 0, sizeof(int), s));
   HIPCHK(hipMemsetAsync(&c->scratch->nfp64, 0, sizeof(unsigned long long), s));
   if (n > 0) {
-    if (mixed)
-      hipLaunchKernelGGL(k_fit4<true>, dim3(grid4(n)), dim3(WPB4 * 64), 0, s, n, c->st_off, c->st_idx,
-                         c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, c->w64, c->w32, c->bw64, c->bw32,
-                         c->diag, c->inv_diag, c->hscale, &c->scratch->err);
+    const bool m56 = c->P.m_cap <= 56;
+#define APC_FIT4(MX, R)                                                                        \
+  hipLaunchKernelGGL((k_fit4<MX, R>), dim3(grid4(n)), dim3(WPB4 * 64), 0, s, n, c->st_off,     \
+                     c->st_idx, c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, c->w64,    \
+                     c->w32, c->bw64, c->bw32, c->diag, c->inv_diag, c->hscale, &c->scratch->err)
+    if (mixed && m56)
+      APC_FIT4(true, 56);
+    else if (mixed)
+      APC_FIT4(true, APC_MAXM);
+    else if (m56)
+      APC_FIT4(false, 56);
     else
-      hipLaunchKernelGGL(k_fit4<false>, dim3(grid4(n)), dim3(WPB4 * 64), 0, s, n, c->st_off, c->st_idx,
-                         c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, c->w64, c->w32, c->bw64, c->bw32,
-                         c->diag, c->inv_diag, c->hscale, &c->scratch->err);
+      APC_FIT4(false, APC_MAXM);
+#undef APC_FIT4
     HIPCHK(hipGetLastError());
   }
   if (c->nsl > 0) {
@@ -556,9 +586,14 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
 }
 
 int apc_node_derivs4(apc_cloud *c, const double *f, double *D, hipStream_t s) {
-  if (c->n > 0)
-    hipLaunchKernelGGL(k_node_derivs4, dim3(grid4(c->n)), dim3(WPB4 * 64), 0, s, c->n, c->st_off,
-                       c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder, c->unit, f, D);
+  if (c->n > 0 && c->P.m_cap <= 56)
+    hipLaunchKernelGGL(k_node_derivs4<56>, dim3(grid4(c->n)), dim3(WPB4 * 64), 0, s, c->n,
+                       c->st_off, c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder,
+                       c->unit, f, D);
+  else if (c->n > 0)
+    hipLaunchKernelGGL(k_node_derivs4<APC_MAXM>, dim3(grid4(c->n)), dim3(WPB4 * 64), 0, s, c->n,
+                       c->st_off, c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder,
+                       c->unit, f, D);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
