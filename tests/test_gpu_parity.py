@@ -63,6 +63,35 @@ def test_cloud_bit_exact(c1):
     assert G.n == 1 + 7 * G.n_opened
 
 
+def test_repeated_builds_reuse_temporaries(apc, c1):
+    """Temporaries come from a per-stream cache of freed blocks: builds, solves and
+    interpolations repeated on one stream, between clouds of other sizes (blocks
+    of other size classes in the cache), give the same results bit for bit."""
+    note("repeated builds through the temporary cache")
+    xyz, O, G = c1
+    small = beam_halo(20_000, seed=9)
+
+    def run(points):
+        cl = gcloud(apc, points, **P1)
+        cl.assemble_gfd()
+        _, rho_t, _ = cl.deposit(tol=1e-12)
+        phi, _ = cl.solve(rho_t[:cl.n].contiguous(), tol=1e-10)
+        pp, gp = cl.interpolate_force(phi)
+        torch.cuda.synchronize()
+        out = dict(st_idx=cl.nodes()["st_idx"], phi=phi.cpu().numpy(), pp=pp.cpu().numpy(),
+                   gp=gp.cpu().numpy())
+        cl.close()
+        return out
+
+    first = run(xyz)
+    for pts in (small, xyz, small, xyz):
+        again = run(pts)
+        if pts is xyz:
+            for k, v in first.items():
+                np.testing.assert_array_equal(again[k], v, err_msg=k)
+    np.testing.assert_array_equal(first["st_idx"], O.nodes()["st_idx"])
+
+
 def test_operator_rows(c1):
     note("operator parity beam_halo_1e5")
     _, O, G = c1
