@@ -1520,3 +1520,41 @@ int apco_node_orders(const apco_cloud *C, int8_t *ord) {
   memcpy(ord, C->node_order, (size_t)C->n);
   return 0;
 }
+
+/* ------------------------------------------------------------------ */
+/* Particle push of the Vlasov-Poisson time loop (Sec. 1: particles move in the
+   field that the three steps of Sec. 3.2 compute from their own positions).  The
+   paper does not name its time integrator; the reading here is the leapfrog
+   scheme in kick-drift form, velocities staggered half a step behind positions:
+       v <- v + kick * grad phi(x),     x <- x + dt * v,
+   kick being dt times the caller's charge-to-mass coupling.  Every product and
+   every sum is rounded on its own (the library is built without contraction).
+   Walls: a particle that ends outside Omega is reflected specularly.  Per axis,
+   u = (x - lo) / L is outside [0, 1]; with f = floor(u) whole lengths and
+   r = u - f, the position after f wall crossings is r (f even) or 1 - r (f odd),
+   x = lo + u L, and the velocity component flips sign when f is odd.  A particle
+   inside Omega keeps x + dt v as computed. */
+int apco_push(const apco_params *P, int64_t N, double *xyz, double *vel, const double *grad,
+              double kick, double dt) {
+  if (!P || N < 0 || !(P->L > 0.0) || !isfinite(kick) || !isfinite(dt)) return APCO_EINVAL;
+  if (N > 0 && (!xyz || !vel || !grad)) return APCO_EINVAL;
+  for (int d = 0; d < 3; d++) {
+    const double lo = P->lo[d], hi = P->lo[d] + P->L;
+    for (int64_t i = 0; i < N; i++) {
+      double v = vel[d * N + i] + kick * grad[d * N + i];
+      double x = xyz[d * N + i] + dt * v;
+      if (x < lo || x > hi) {
+        double u = (x - lo) / P->L;
+        const double f = floor(u);
+        const double r = u - f;
+        const int odd = fmod(f, 2.0) != 0.0;
+        u = odd ? 1.0 - r : r;
+        if (odd) v = -v;
+        x = lo + u * P->L;
+      }
+      xyz[d * N + i] = x;
+      vel[d * N + i] = v;
+    }
+  }
+  return 0;
+}

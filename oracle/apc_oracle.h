@@ -114,6 +114,13 @@ int apco_node_derivs(const apco_cloud *C, const double *f, double *D);
 int apco_interpolate(const apco_cloud *C, const double *phi, const double *xyz, double *phi_p,
                      double *grad_p);
 
+/* Leapfrog push of the Vlasov-Poisson loop: per particle and axis
+   v <- v + kick grad, then x <- x + dt v (each product and sum rounded on its own),
+   and a particle that leaves Omega is reflected specularly at its faces (velocity
+   component negated once per wall crossing).  xyz, vel: 3 x N in/out; grad: 3 x N. */
+int apco_push(const apco_params *P, int64_t N, double *xyz, double *vel, const double *grad,
+              double kick, double dt);
+
 /* ---- learned preconditioner (checks of the training data and gradients) ----
    Row i of M has the pattern J_0 = i, J_p = the p-th stencil node (p = 1..m,
    m <= 40) and is m_i = (e_0 + o_i) / d_i with o_i (41) the network output.

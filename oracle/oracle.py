@@ -71,6 +71,8 @@ def _load():
     lib.apco_mlp_loss_grad.argtypes = [P, P, P, P, ct.c_int, P, P]
     lib.apco_mlp_forward.argtypes = [P, P, ct.c_int64, P]
     lib.apco_learned_m.argtypes = [P, P, P, ct.c_int, P, P]
+    lib.apco_push.argtypes = [ct.POINTER(_Params), ct.c_int64, P, P, P, ct.c_double,
+                              ct.c_double]
     _lib = lib
     return lib
 
@@ -98,6 +100,19 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     P.m_cap = m_cap if m_cap is not None else (40 if order == 2 else 56)
     P.poisson_c = poisson_c
     return P
+
+
+def push(xyz, vel, grad, kick, dt, lo=(0.0, 0.0, 0.0), L=1.0):
+    """Leapfrog kick-drift push with specular walls (apco_push).  xyz, vel: 3 x N
+    float64, updated copies are returned; grad: 3 x N."""
+    x = np.array(xyz, dtype=np.float64, order="C", copy=True)
+    v = np.array(vel, dtype=np.float64, order="C", copy=True)
+    g = np.ascontiguousarray(grad, dtype=np.float64)
+    assert x.shape == v.shape == g.shape and x.shape[0] == 3
+    P = make_params(lo=lo, L=L)
+    _check(_load().apco_push(ct.byref(P), x.shape[1], _ptr(x), _ptr(v), _ptr(g), kick, dt),
+           "push")
+    return x, v
 
 
 def num_unknowns(order: int) -> int:
