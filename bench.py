@@ -331,6 +331,43 @@ def batch_bench(apc, torch, steps, tol):
     return out
 
 
+def vlasov_bench(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, dt=1e-3):
+    """Time steps of the Vlasov-Poisson loop (apc_step) on the workload's particles,
+    starting at rest with unit coupling (kick = dt): every step re-selects the node
+    cloud from the current positions, assembles, deposits (density solve to 1e-10),
+    solves (Jacobi, tol), interpolates and pushes.  The push streams 120 B per
+    particle (per axis x, v, grad read and x, v written, float64)."""
+    x = xyz_d.clone()
+    v = torch.zeros_like(x)
+    N = x.shape[1]
+    pp = torch.empty(N, dtype=torch.float64, device="cuda")
+    gp = torch.empty((3, N), dtype=torch.float64, device="cuda")
+    kw = dict(order=cfg["order"], c=cfg["c"], max_depth=cfg["max_depth"], precision=precision)
+    acc = None
+    for it in range(warmup + steps):
+        if it == warmup:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+        _, _, st = apc.step(x, v, dt, dt, tol_density=1e-10, tol=tol, maxit=20000,
+                            phi_p=pp, grad_p=gp, **kw)
+        if st["status"] != 0:
+            raise RuntimeError(f"time step did not converge: {st}")
+        log(f"vlasov step {it}: n={st['n']} iters={st['iters']} ms={st['ms']}")
+        if it >= warmup:
+            acc = dict(st["ms"]) if acc is None else {k: acc[k] + st["ms"][k] for k in acc}
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    ms = {k: round(t / steps, 3) for k, t in acc.items()}
+    push_bytes = 120 * N
+    push_gbs = push_bytes / (ms["push"] * 1e-3) / 1e9 if ms["push"] > 0 else 0.0
+    return dict(workload=f"{cfg['N']} particles of the headline beam, {steps} steps of dt {dt}",
+                particles=N, steps=steps, ms_per_step=round(wall * 1e3, 3),
+                particle_steps_per_s=round(N / wall, 1), phases_ms=ms, nodes=st["n"],
+                iters=st["iters"], density_iters=st["density_iters"],
+                push=dict(bytes_per_launch=push_bytes, GBs=round(push_gbs, 1),
+                          frac=round(push_gbs / HBM_PEAK_GBS, 4)))
+
+
 def cpu_baseline(xyz, cfg, iters_full, n_sample_iters=20):
     """The oracle (plain serial C, FP64) on the same cloud: assembly of all nodes
     plus `n_sample_iters` BiCGSTAB iterations, the solve time scaled to the
@@ -369,6 +406,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batch")
+    ap.add_argument("--no-vlasov", action="store_true",
+                    help="skip the Vlasov-Poisson time steps (apc_step)")
     ap.add_argument("--no-k4", action="store_true",
                     help="skip the 1e8-particle fourth-order workload (about 90 s)")
     args = ap.parse_args()
@@ -453,6 +492,12 @@ def main():
         batch = batch_bench(apc, torch, max(2, args.steps // 2), args.tol)
         log(f"batch: {batch}")
 
+    vlasov = None
+    if not args.no_vlasov:
+        log("Vlasov-Poisson time steps")
+        vlasov = vlasov_bench(apc, torch, xyz_d, cfg, prec, max(2, args.steps), 1, args.tol)
+        log(f"vlasov: {vlasov}")
+
     k4 = None
     if not args.no_k4 and args.workload != "beam_halo_1e8_k4":
         log("fourth-order workload beam_halo_1e8_k4 (one timed step)")
@@ -527,6 +572,8 @@ def main():
     }
     if batch is not None:
         out["batch"] = batch
+    if vlasov is not None:
+        out["vlasov"] = vlasov
     if k4 is not None:
         out["k4"] = k4
     if roof_m is not None:

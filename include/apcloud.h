@@ -337,6 +337,52 @@ int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, 
                                 hipStream_t stream);
 void apc_batch_destroy(apc_batch *b);
 
+/* ---- Vlasov-Poisson time loop (Sec. 1) ----
+   The particles move in the field the three steps of Sec. 3.2 compute from their
+   own positions; the node cloud is re-selected from the current positions every
+   step (Sec. 4).  The paper leaves the time integrator open: this is the
+   leapfrog scheme in kick-drift form, velocities half a step behind positions. */
+
+/* Particle push: per particle and axis v <- v + kick grad, then x <- x + dt v,
+   each product and sum rounded on its own (no fused multiply-add).  kick is dt
+   times the caller's charge-to-mass coupling (its sign is the caller's: grad is
+   grad phi); kick = coupling dt / 2 on the first step staggers the velocities.
+   A particle that ends outside Omega = [p->lo, p->lo + p->L]^3 is reflected
+   specularly: per axis u = (x - lo) / L, f = floor(u) wall crossings,
+   r = u - f, u <- r (f even) or 1 - r (f odd), x = lo + u L, and the velocity
+   component changes sign for odd f; a particle inside keeps x + dt v.  Only
+   p->lo and p->L are read.  xyz, vel: 3 x N float64, updated in place; grad:
+   3 x N (as apc_interpolate_force writes it).  Errors: APC_EINVAL (N < 0,
+   L <= 0, a non-finite lo, L, kick or dt, NULL arrays with N > 0).  Does not
+   synchronise. */
+int apc_push(const apc_params *p, int64_t N, double *xyz, double *vel, const double *grad,
+             double kick, double dt, hipStream_t stream);
+
+typedef struct {
+  int64_t n, nb, nnz;    /* the step's node cloud */
+  int density_iters;     /* BiCGSTAB iterations of the density solve */
+  int iters;             /* BiCGSTAB iterations of the Poisson solve */
+  int status;            /* APC_OK, or APC_ENOCONV if a solve stopped at maxit */
+  int pad;
+  double rel_resid_true; /* Poisson solve: ||b - A x|| / ||b|| */
+  double ms[6];          /* device time of build, assemble, deposit (with the density
+                            solve), Poisson solve, interpolation, push */
+} apc_step_stats;
+
+/* One time step: apc_build_cloud(p, xyz), apc_assemble_gfd, apc_deposit(q,
+   tol_density), apc_solve (phi = 0 on the boundary, tol, precond
+   APC_PRECOND_NONE or APC_PRECOND_JACOBI), apc_interpolate_force into phi_p[N]
+   and grad_p[3 x N] (the field at the positions the step started from), then
+   apc_push(kick, dt) of xyz and vel.  maxit bounds both solves.  The node cloud
+   and its buffers live for the call only.  st_host (may be NULL) receives the
+   cloud's sizes, iteration counts and per-phase device times.  Returns APC_OK,
+   APC_ENOCONV when a solve stopped at maxit (the step still completes with the
+   last iterate), or the first error of a phase (xyz and vel are then unchanged
+   unless the push itself ran).  Synchronises the stream. */
+int apc_step(const apc_params *p, double *xyz, double *vel, const double *q, int64_t N,
+             double kick, double dt, double tol_density, double tol, int maxit, int precond,
+             double *phi_p, double *grad_p, apc_step_stats *st_host, hipStream_t stream);
+
 void apc_destroy(apc_cloud *c);
 const char *apc_strerror(int code);
 /* Text of the last HIP error seen by the calling thread (empty if none). */

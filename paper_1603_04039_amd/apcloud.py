@@ -30,7 +30,8 @@ EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_n
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
            "apc_batch_configure", "apc_batch_tune", "apc_batch_assemble", "apc_batch_deposit",
-           "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_destroy", "apc_destroy", "apc_strerror", "apc_last_error"]
+           "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_destroy", "apc_push",
+           "apc_step", "apc_destroy", "apc_strerror", "apc_last_error"]
 
 
 class ApcError(RuntimeError):
@@ -54,6 +55,19 @@ class Stats(ct.Structure):
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
+
+
+class StepStats(ct.Structure):
+    _fields_ = [("n", ct.c_int64), ("nb", ct.c_int64), ("nnz", ct.c_int64),
+                ("density_iters", ct.c_int), ("iters", ct.c_int), ("status", ct.c_int),
+                ("pad", ct.c_int), ("rel_resid_true", ct.c_double), ("ms", ct.c_double * 6)]
+
+    PHASES = ("build", "assemble", "deposit", "solve", "interpolate", "push")
+
+    def as_dict(self):
+        out = {k: getattr(self, k) for k, _ in self._fields_ if k not in ("pad", "ms")}
+        out["ms"] = dict(zip(self.PHASES, self.ms[:]))
+        return out
 
 
 class BatchInfo(ct.Structure):
@@ -107,6 +121,10 @@ def load_library(path: str = LIB_PATH):
     lib.apc_batch_interpolate_force.argtypes = [P, P, P, P, P]
     lib.apc_batch_destroy.argtypes = [P]
     lib.apc_batch_destroy.restype = None
+    lib.apc_push.argtypes = [ct.POINTER(Params), I64, P, P, P, ct.c_double, ct.c_double, P]
+    lib.apc_step.argtypes = [ct.POINTER(Params), P, P, P, I64, ct.c_double, ct.c_double,
+                             ct.c_double, ct.c_double, ct.c_int, ct.c_int, P, P,
+                             ct.POINTER(StepStats), P]
     lib.apc_destroy.argtypes = [P]
     lib.apc_destroy.restype = None
     lib.apc_strerror.argtypes = [ct.c_int]
@@ -357,6 +375,46 @@ class Cloud:
         _check(self.lib.apc_apply_operator(self.h, _dptr(f, torch.float64, self.n + self.nb),
                                            _dptr(out), _stream(stream)), "apc_apply_operator")
         return out
+
+
+def _particles(t, N=None):
+    import torch
+    if not (isinstance(t, torch.Tensor) and t.dim() == 2 and t.shape[0] == 3):
+        raise ValueError("expected a 3 x N tensor")
+    if N is not None and t.shape[1] != N:
+        raise ValueError(f"expected 3 x {N}, got {tuple(t.shape)}")
+    return _dptr(t, torch.float64)
+
+
+def push(xyz, vel, grad, kick, dt, stream=None, **params):
+    """Leapfrog kick-drift push with specular walls (apc_push), in place on the
+    3 x N float64 CUDA tensors xyz and vel; grad: 3 x N.  params: the domain
+    (lo, L) as for Cloud."""
+    p = make_params(**params)
+    N = xyz.shape[1]
+    _check(load_library().apc_push(ct.byref(p), N, _particles(xyz), _particles(vel, N),
+                                   _particles(grad, N), kick, dt, _stream(stream)), "apc_push")
+    return xyz, vel
+
+
+def step(xyz, vel, kick, dt, q=None, tol_density=1e-12, tol=1e-8, maxit=20000,
+         precond=APC_PRECOND_JACOBI, stream=None, phi_p=None, grad_p=None, **params):
+    """One Vlasov-Poisson time step (apc_step): cloud from xyz, field, push of xyz
+    and vel in place.  Returns (phi_p, grad_p, stats) -- the potential and its
+    gradient at the positions the step started from."""
+    import torch
+    p = make_params(**params)
+    N = xyz.shape[1]
+    phi_p = phi_p if phi_p is not None else torch.empty(N, dtype=torch.float64, device="cuda")
+    grad_p = grad_p if grad_p is not None else torch.empty((3, N), dtype=torch.float64,
+                                                           device="cuda")
+    st = StepStats()
+    rc = _check(load_library().apc_step(ct.byref(p), _particles(xyz), _particles(vel, N),
+                                        _dptr(q, torch.float64, N), N, kick, dt, tol_density,
+                                        tol, maxit, precond, _dptr(phi_p, torch.float64, N),
+                                        _particles(grad_p, N), ct.byref(st), _stream(stream)),
+                "apc_step")
+    return phi_p, grad_p, dict(st.as_dict(), rc=rc)
 
 
 def mlp_loss_grad(params, feat, quad, rows, stream=None, grad=None, loss=None):

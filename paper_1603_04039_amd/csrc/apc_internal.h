@@ -223,6 +223,12 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
 int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *phi,
                    double tol, int maxit, int precond, apc_stats *st, hipStream_t s);
 int apc_apply_impl(apc_cloud *c, const double *f, double *out, hipStream_t s);
+// time loop (push.hip)
+int apc_push_impl(const apc_params *p, int64_t N, double *xyz, double *vel, const double *grad,
+                  double kick, double dt, hipStream_t s);
+int apc_step_impl(const apc_params *p, double *xyz, double *vel, const double *q, int64_t N,
+                  double kick, double dt, double tol_density, double tol, int maxit, int precond,
+                  double *phi_p, double *grad_p, apc_step_stats *st, hipStream_t s);
 
 // batches (batch.hip)
 int apc_build_batch_impl(const apc_params *P, int count, const double *const *xyz,

@@ -286,6 +286,20 @@ int apc_apply_precond(apc_cloud *c, int precond, const double *in, double *out,
   return apc_apply_precond_impl(c, precond, in, out, stream);
 }
 
+int apc_push(const apc_params *p, int64_t N, double *xyz, double *vel, const double *grad,
+             double kick, double dt, hipStream_t stream) {
+  g_err[0] = 0;
+  return apc_push_impl(p, N, xyz, vel, grad, kick, dt, stream);
+}
+
+int apc_step(const apc_params *p, double *xyz, double *vel, const double *q, int64_t N,
+             double kick, double dt, double tol_density, double tol, int maxit, int precond,
+             double *phi_p, double *grad_p, apc_step_stats *st_host, hipStream_t stream) {
+  g_err[0] = 0;
+  return apc_step_impl(p, xyz, vel, q, N, kick, dt, tol_density, tol, maxit, precond, phi_p,
+                       grad_p, st_host, stream);
+}
+
 int apc_build_batch(const apc_params *p, int count, const double *const *xyz, const int64_t *N,
                     hipStream_t stream, apc_batch **out) {
   if (!p || count < 1 || !xyz || !N || !out) return APC_EINVAL;

@@ -90,3 +90,20 @@ def uniform_lattice_points(depth: int) -> np.ndarray:
     g = (np.arange(m, dtype=np.float64) + 0.5) / m
     x, y, z = np.meshgrid(g, g, g, indexing="ij")
     return np.ascontiguousarray(np.stack([x.ravel(), y.ravel(), z.ravel()]))
+
+
+def gaussian_blob(M: int, seed: int, sigma: float = 0.03, centre=(0.40, 0.5, 0.5),
+                  velocity=(1.0, 0.0, 0.0), v_spread: float = 0.05):
+    """The test particle of the single-particle self-force test (Sec. 5): a sharp
+    Gaussian cloud of M points, N(centre, sigma^2 I) re-drawn until inside
+    [0,1)^3, moving with a common velocity plus N(0, v_spread^2) per component.
+    Returns (xyz, vel), each (3, M) float64.  Draw order: positions, velocities."""
+    rng = np.random.default_rng(seed)
+    c = np.asarray(centre, dtype=np.float64)[:, None]
+    xyz = c + sigma * rng.standard_normal((3, M))
+    bad = np.any((xyz < 0.0) | (xyz >= 1.0), axis=0)
+    while bad.any():
+        xyz[:, bad] = c + sigma * rng.standard_normal((3, int(bad.sum())))
+        bad = np.any((xyz < 0.0) | (xyz >= 1.0), axis=0)
+    vel = np.asarray(velocity, dtype=np.float64)[:, None] + v_spread * rng.standard_normal((3, M))
+    return np.ascontiguousarray(xyz), np.ascontiguousarray(vel)
