@@ -314,7 +314,12 @@ __global__ void __launch_bounds__(APC_BLOCK)
   uint64_t *tab = hash_all + t;
 #define LST(k) lst[(int64_t)(k) * stride]
 #define KEY(k) key[(int64_t)(k) * stride]
-  const uint64_t g = (uint64_t)gen << 32;
+  // Tag of this launch: bit 31 set, so no stale word of the scratch can match
+  // it.  The same scratch is carved anew for each ring radius, so a hash slot may
+  // hold words of an earlier launch's list or keys: pairs of node ids (below 2^31,
+  // or -(v+1) for a picked node, at least 2^32 - ntot as unsigned) and squared
+  // distances (below 2^46); the host keeps gen < 2^16 and ntot <= 2^31 - 2^16.
+  const uint64_t g = (uint64_t)(gen | 0x80000000u) << 32;
   // true when v was not in the set (and is now)
   auto insert = [&](int32_t v) -> bool {
     uint32_t h = ring_hash(v, hmask);
@@ -784,7 +789,11 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   // hash entries carry the launch's generation: zero once, never cleared again
   HIPCHK(hipMemsetAsync(scr1, 0, (size_t)words1 * 8, s));
   HIPCHK(hipMemsetAsync(scr2, 0, (size_t)words2 * 8, s));
-  uint32_t gen = 0;
+  uint32_t gen = 0; // launch tag of the hash entries; stays below 2^16 (see k_stencil)
+  if (ntot > ((int64_t)1 << 31) - ((int64_t)1 << 16)) {
+    apc_set_error_msg("too many nodes for the ring search");
+    return APC_EINVAL;
+  }
   APCCHK(dalloc(&cand, CHmax * APC_MAXM, s));
   APCCHK(dalloc(&mch, CHmax, s));
   APCCHK(dalloc(&rflag, CHmax, s));
@@ -823,6 +832,10 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     const Scr S1 = carve(scr1, cap1, CH);
     for (int64_t c0 = 0; c0 < np; c0 += CH) {
       const int64_t cn = (np - c0) < CH ? (np - c0) : CH;
+      if (gen + 1 + (cn + CH2 - 1) / CH2 >= 0xffffu) {
+        apc_set_error_msg("ring search: too many launches for the hash tags");
+        return APC_EINVAL;
+      }
       hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0,
                          (const int32_t *)nullptr, cn, R, mcap, pk, ko, c->crd, ntot, n, r1cnt, r1,
                          c->bowner, cap1, CH, S1.mask, ++gen, S1.lst, S1.key, S1.tab, 0, cand, mch,
