@@ -4,8 +4,8 @@ This package holds only random-number draws and array shapes.  It contains none 
 the method's arithmetic (no keys, no tree, no stencils), so it may be imported by
 both sides without coupling them.
 """
-from .beam_halo import (beam_halo, batch_specs, uniform_lattice_points, gaussian_blob, CONFIGS,
-                        BATCH)
+from .beam_halo import (beam_halo, batch_specs, uniform_lattice_points, gaussian_blob,
+                        paper_beam_3d, BEAM3D, CONFIGS, BATCH)
 
-__all__ = ["beam_halo", "batch_specs", "uniform_lattice_points", "gaussian_blob", "CONFIGS",
-           "BATCH"]
+__all__ = ["beam_halo", "batch_specs", "uniform_lattice_points", "gaussian_blob", "paper_beam_3d",
+           "BEAM3D", "CONFIGS", "BATCH"]

@@ -107,3 +107,34 @@ def gaussian_blob(M: int, seed: int, sigma: float = 0.03, centre=(0.40, 0.5, 0.5
         bad = np.any((xyz < 0.0) | (xyz >= 1.0), axis=0)
     vel = np.asarray(velocity, dtype=np.float64)[:, None] + v_spread * rng.standard_normal((3, M))
     return np.ascontiguousarray(xyz), np.ascontiguousarray(vel)
+
+
+# The 3-D Gaussian beam with halo of Sec. 5.2 (eq. GaussianDist, read with 2 tau^2 in
+# the exponents): rho = a1 [exp(-|x|^2 / (2 tau1^2)) + a2 exp(-|x|^2 / (2 tau2^2))] on
+# Omega = [-1, 1]^3, a1 normalising the charge in Omega to 1.
+BEAM3D = dict(tau1=0.02, tau2=0.3, a2=1e-5, lo=(-1.0, -1.0, -1.0), L=2.0)
+
+
+def paper_beam_3d(N: int, seed: int):
+    """N particles of the 3-D beam with halo, (3, N) float64: each particle is drawn
+    from the halo with the halo's share of the charge in Omega (binomial count),
+    else from the core, each an isotropic Gaussian truncated to Omega by
+    re-drawing.  Draw order: the halo count, the core block, the halo block."""
+    import math
+    t1, t2, a2 = BEAM3D["tau1"], BEAM3D["tau2"], BEAM3D["a2"]
+
+    def mass(t):  # integral of exp(-|x|^2 / (2 t^2)) over [-1, 1]^3
+        return (math.sqrt(2 * math.pi) * t * math.erf(1 / (math.sqrt(2) * t))) ** 3
+
+    rng = np.random.default_rng(seed)
+    p_halo = a2 * mass(t2) / (mass(t1) + a2 * mass(t2))
+    nh = int(rng.binomial(N, p_halo))
+
+    def truncated(n, t):
+        out = np.empty((3, 0))
+        while out.shape[1] < n:
+            x = t * rng.standard_normal((3, 2 * (n - out.shape[1]) + 16))
+            out = np.concatenate([out, x[:, np.all(np.abs(x) <= 1.0, axis=0)]], axis=1)
+        return out[:, :n]
+
+    return np.ascontiguousarray(np.concatenate([truncated(N - nh, t1), truncated(nh, t2)], axis=1))
