@@ -250,11 +250,13 @@ int apco_thresholds(const apco_params *P, double *T) {
   /* T_l = t^(2k-2), t = c 2^l / L: the criterion h < c N'^(-1/(2k-2)) with
      h = L 2^-l (cell edge, as in the worked example of Sec. 4.3) is N' < T_l;
      a cell is opened when N' >= T_l.  Evaluated as t = (c * 2^l) / L and then
-     repeated multiplication from 1.0. */
+     repeated multiplication from 1.0.  For k = 2 the supraconvergent bound of
+     Sec. 3.3 balances with h ~ N'^(-1/4) instead: exponent 4 (criterion_pow). */
+  const int pw = P->criterion_pow > 0 ? P->criterion_pow : 2 * P->order - 2;
   for (int l = 0; l <= P->max_depth; l++) {
     double t = (P->c * ldexp(1.0, l)) / P->L;
     double v = 1.0;
-    for (int e = 0; e < 2 * P->order - 2; e++) v *= t;
+    for (int e = 0; e < pw; e++) v *= t;
     T[l] = v;
   }
   return 0;
@@ -482,7 +484,8 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
   int p = apco_num_unknowns(P->order);
   if (!(P->order == 2 || P->order == 4) || P->max_depth < 1 || P->max_depth > 20 ||
       !(P->L > 0.0) || !(P->c > 0.0) || P->ring_min < 1 || P->ring_max < P->ring_min ||
-      P->m_cap > MAXM || P->m_cap < p + 1 || N < 1)
+      P->m_cap > MAXM || P->m_cap < p + 1 || N < 1 || P->criterion_pow < 0 ||
+      P->criterion_pow > 16)
     return APCO_EINVAL;
   apco_cloud *C = calloc(1, sizeof(apco_cloud));
   if (!C) return APCO_ENOMEM;

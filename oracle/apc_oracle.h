@@ -40,6 +40,10 @@ typedef struct {
   int ring_max;   /* last ring searched (5, Sec. 4.3) */
   int m_cap;      /* stencil size cap (40 for k=2, 56 for k=4); hard cap 64 */
   double poisson_c; /* Delta phi = c rho (eq. Poisson) */
+  int criterion_pow; /* exponent e of T_l = (c 2^l / L)^e: 0 = 2k - 2 (eq.
+                        errorbalance_implementation); 4 with k = 2 is the balance
+                        of the supraconvergent second-order error bound (Sec. 3.3),
+                        h = c N'^(-1/4) */
 } apco_params;
 
 typedef struct {
@@ -55,7 +59,7 @@ typedef struct apco_cloud apco_cloud;
 int apco_num_unknowns(int order);
 /* Multi-index table of the fitted unknowns in column order (p x 3 ints). */
 int apco_monomials(int order, int32_t *alpha);
-/* Refinement thresholds T_l = (c 2^l / L)^(2k-2), l = 0..max_depth. */
+/* Refinement thresholds T_l = (c 2^l / L)^e, l = 0..max_depth, e = 2k-2 or criterion_pow. */
 int apco_thresholds(const apco_params *P, double *T);
 
 /* Build octree, node set, boundary nodes and GFD stencils from N particles

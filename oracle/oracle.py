@@ -27,7 +27,8 @@ def build_oracle_lib() -> str:
 class _Params(ct.Structure):
     _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
-                ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double)]
+                ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
+                ("criterion_pow", ct.c_int)]
 
 
 class _Stats(ct.Structure):
@@ -88,7 +89,7 @@ def _check(rc, what):
 
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
-                ring_max=5, m_cap=None, poisson_c=1.0):
+                ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0):
     P = _Params()
     P.lo[:] = lo
     P.L = L
@@ -99,6 +100,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     P.ring_max = ring_max
     P.m_cap = m_cap if m_cap is not None else (40 if order == 2 else 56)
     P.poisson_c = poisson_c
+    P.criterion_pow = criterion_pow
     return P
 
 
