@@ -83,6 +83,11 @@ typedef struct {
                        neighbour columns gathers them once into LDS (performance only,
                        same results bit for bit); 0 = default (1008, also the maximum),
                        -1 = never */
+  int criterion_pow; /* exponent e of the criterion thresholds T_l = (c 2^l / L)^e:
+                        0 = 2k - 2 (eq. errorbalance_implementation, the default);
+                        4 with k = 2 is the balance of the supraconvergent
+                        second-order error bound (Sec. 3.3), h = c N'^(-1/4);
+                        1..16 accepted */
 } apc_params;
 
 typedef struct {
@@ -104,7 +109,8 @@ void apc_default_params(apc_params *p, int order);
 
 /* Build the node cloud (Sec. 4): Morton keys and a stable radix sort of the
    particles, the error-balance criterion opening cells with N' >= T_l where
-   T_l = t^(2k-2), t = (c 2^l) / L evaluated in FP64 by repeated multiplication,
+   T_l = t^(2k-2) (or t^criterion_pow), t = (c 2^l) / L evaluated in FP64 by
+   repeated multiplication,
    level-by-level 2:1 face balance to the unique minimal balanced refinement,
    boundary face nodes, and per-node GFD stencils from the R-ring (Sec. 3.1,
    4.3).  Stencil rule: the ring's nodes sorted by (squared distance, index); the

@@ -936,6 +936,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   if (p->order != 2 && p->order != 4) return APC_EINVAL;
   if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
       p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 || p->stage_cap < -1 ||
+      p->criterion_pow < 0 || p->criterion_pow > 16 ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
         p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c))
     return APC_EINVAL;
@@ -945,11 +946,13 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   c->N = N;
   c->p = p->order == 2 ? 9 : 34;
   c->unit = p->L / ldexp(1.0, p->max_depth + 1);
-  // T_l = t^(2k-2), t = (c 2^l) / L, by repeated multiplication from 1.0
+  // T_l = t^e, t = (c 2^l) / L, by repeated multiplication from 1.0; e = 2k-2,
+  // or the caller's exponent (4 for the supraconvergent k = 2 balance)
+  const int pw = p->criterion_pow > 0 ? p->criterion_pow : 2 * p->order - 2;
   for (int l = 0; l < 24; l++) {
     double t = (p->c * ldexp(1.0, l)) / p->L;
     double v = 1.0;
-    for (int e = 0; e < 2 * p->order - 2; e++) v *= t;
+    for (int e = 0; e < pw; e++) v *= t;
     c->T[l] = v;
   }
   int rc = build_body(c, xyz, s);

@@ -63,6 +63,26 @@ def test_cloud_bit_exact(c1):
     assert G.n == 1 + 7 * G.n_opened
 
 
+@pytest.mark.parametrize("case", ["beam_halo_1e5", "lattice6"])
+def test_supraconvergent_criterion_cloud(apc, oracle_mod, case):
+    """Criterion exponent 4 (the supraconvergent k = 2 balance, h = c N'^(-1/4)):
+    the same cloud as the oracle's, bit for bit, and fewer nodes than exponent 2."""
+    note(f"criterion exponent 4: {case}")
+    if case == "lattice6":
+        xyz, kw = uniform_lattice_points(6), dict(order=2, c=1.0, max_depth=8)
+    else:
+        xyz, kw = beam_halo(100_000, seed=1), dict(P1, c=0.2)
+    O = oracle_mod.OracleCloud(xyz, criterion_pow=4, **kw)
+    G = gcloud(apc, xyz, criterion_pow=4, **kw)
+    assert_same_cloud(O, G)
+    if case == "lattice6":
+        assert G.n == 8 ** 3
+    G2 = gcloud(apc, xyz, **kw)
+    assert G.n < G2.n
+    G.close()
+    G2.close()
+
+
 def test_repeated_builds_reuse_temporaries(apc, c1):
     """Temporaries come from a per-stream cache of freed blocks: builds, solves and
     interpolations repeated on one stream, between clouds of other sizes (blocks

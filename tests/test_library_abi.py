@@ -44,8 +44,10 @@ def test_error_strings_and_defaults(apc):
 
 
 def test_struct_layouts_match_header(apc):
-    # apc_params: lo[3], L, order, c, max_depth, ring_min, ring_max, m_cap, poisson_c, precision
-    assert ct.sizeof(apc.Params) == 3 * 8 + 8 + 8 + 8 + 4 * 4 + 8 + 8
+    # apc_params: lo[3], L, order (+pad), c, max_depth, ring_min, ring_max, m_cap, poisson_c,
+    # precision, stage_cap, criterion_pow (+pad)
+    assert ct.sizeof(apc.Params) == 3 * 8 + 8 + 8 + 8 + 4 * 4 + 8 + 8 + 8
+    assert apc.Params.criterion_pow.offset == 80
     assert ct.sizeof(apc.Stats) == 4 * 4 + 8 + 8 + 8 + 8 + 4 + 4
 
 
