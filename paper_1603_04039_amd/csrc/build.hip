@@ -269,11 +269,6 @@ __global__ void __launch_bounds__(APC_BLOCK)
   r1cnt[y] = k;
 }
 
-__device__ inline bool in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
-  const int64_t sx = (o & 4) ? 1 : -1, sy = (o & 2) ? 1 : -1, sz = (o & 1) ? 1 : -1;
-  return sx * d0 >= 0 && sy * d1 >= 0 && sz * d2 >= 0;
-}
-
 // Stencil of node y from its R-ring (nodes within R face-adjacency steps, boundary
 // nodes hanging off their owner): candidates sorted by (squared integer distance,
 // node index); the two nearest of every closed octant are chosen first; for an
@@ -293,6 +288,8 @@ __device__ inline bool in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
 // that the thread reports -1 (the host reruns it with the full APC_RING_CAP), or,
 // when cap is already APC_RING_CAP (full), flags error 8.  The result does not
 // depend on cap.
+constexpr int64_t KEY_R2 = ((int64_t)1 << 56) - 1; // r2 bits of a ring-search sort key
+
 __device__ __forceinline__ uint32_t ring_hash(int32_t v, uint32_t mask) {
   return ((uint32_t)v * 2654435761u) & mask;
 }
@@ -362,16 +359,22 @@ __global__ void __launch_bounds__(APC_BLOCK)
     return;
   }
   const int32_t cy0 = crd[y], cy1 = crd[ntot + y], cy2 = crd[2 * ntot + y];
-  // candidates = list positions 1 .. cnt-1, heap-sorted by (r2, index)
+  // candidates = list positions 1 .. cnt-1, heap-sorted by (r2, index).  Each key
+  // carries the candidate's closed-octant mask in bits 56-63 (bit o: the offset lies
+  // in octant o, a zero component counting on both sides); r2 < 2^46 below them.
   for (int j = 1; j < cnt; j++) {
     const int32_t v = LST(j);
     const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
-    KEY(j) = d0 * d0 + d1 * d1 + d2 * d2;
+    const uint32_t mx = (d0 >= 0 ? 0xF0u : 0u) | (d0 <= 0 ? 0x0Fu : 0u);
+    const uint32_t my = (d1 >= 0 ? 0xCCu : 0u) | (d1 <= 0 ? 0x33u : 0u);
+    const uint32_t mz = (d2 >= 0 ? 0xAAu : 0u) | (d2 <= 0 ? 0x55u : 0u);
+    KEY(j) = (int64_t)((uint64_t)(d0 * d0 + d1 * d1 + d2 * d2) |
+                       ((uint64_t)(mx & my & mz) << 56));
   }
   {
     const int m = cnt - 1;
     auto less = [&](int a, int b) -> bool { // heap positions 0..m-1 = list positions 1..m
-      const int64_t ka = KEY(a + 1), kb = KEY(b + 1);
+      const int64_t ka = KEY(a + 1) & KEY_R2, kb = KEY(b + 1) & KEY_R2;
       return ka < kb || (ka == kb && LST(a + 1) < LST(b + 1));
     };
     auto swp = [&](int a, int b) {
@@ -401,21 +404,36 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int nc = cnt - 1;
   const int want = nc < m_cap ? nc : m_cap;
   int got = 0;
-  // picked candidates are marked by storing -(v+1)
-  for (int o = 0; o < 8; o++) {
-    int taken = 0;
-    for (int j = 1; j < cnt && taken < 2; j++) {
-      int32_t v = LST(j);
-      const bool picked = v < 0;
-      if (picked) v = -v - 1;
-      const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
-      if (!in_octant(o, d0, d1, d2)) continue;
-      taken++;
-      if (!picked && got < want) {
-        LST(j) = -v - 1;
-        got++;
-      }
+  // picked candidates are marked by storing -(v+1).  Octant by octant, the two
+  // nearest candidates in the octant are taken and picked unless picked already:
+  // one pass over the sorted list finds each octant's two nearest.
+  {
+    int f0[8], f1[8], nf[8];
+#pragma unroll
+    for (int o = 0; o < 8; o++) nf[o] = 0, f0[o] = f1[o] = 0;
+    uint32_t open = 0xFFu; // octants still short of two
+    for (int j = 1; j < cnt && open; j++) {
+      const uint32_t msk = (uint32_t)((uint64_t)KEY(j) >> 56) & open;
+#pragma unroll
+      for (int o = 0; o < 8; o++)
+        if ((msk >> o) & 1u) {
+          if (nf[o] == 0) f0[o] = j;
+          else f1[o] = j;
+          if (++nf[o] == 2) open &= ~(1u << o);
+        }
     }
+#pragma unroll
+    for (int o = 0; o < 8; o++)
+#pragma unroll
+      for (int t = 0; t < 2; t++) {
+        if (t >= nf[o]) continue;
+        const int j = t == 0 ? f0[o] : f1[o];
+        const int32_t v = LST(j);
+        if (v >= 0 && got < want) {
+          LST(j) = -v - 1;
+          got++;
+        }
+      }
   }
   for (int d = 0; order == 4 && d < 3; d++) {
     const int32_t *cd = crd + (int64_t)d * ntot;
@@ -458,8 +476,9 @@ __global__ void __launch_bounds__(APC_BLOCK)
     const int32_t v = -LST(j) - 1;
     if (m < APC_MAXM) out[m] = v;
     m++;
-    const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
-    for (int o = 0; o < 8; o++) oct[o] += in_octant(o, d0, d1, d2);
+    const uint32_t msk = (uint32_t)((uint64_t)KEY(j) >> 56);
+#pragma unroll
+    for (int o = 0; o < 8; o++) oct[o] += (msk >> o) & 1u;
   }
 #undef LST
 #undef KEY
