@@ -487,6 +487,148 @@ __global__ void __launch_bounds__(APC_BLOCK)
   mout[pos] = ok ? m : 0;
 }
 
+__device__ __forceinline__ void wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// The order-2 stencil search of k_stencil with one wavefront per node, for rings
+// of at most 63 candidates (the node itself and 63 others fill the 64 lanes).
+// Lanes expand the BFS frontier in parallel (lane q takes frontier node q and its
+// up to 24 face neighbours) into a hash set in LDS; the members, in any order,
+// are then sorted across the lanes by (r2, index) with a bitonic network, so lane
+// j holds the j-th nearest candidate; the selection of k_stencil (per octant the
+// two nearest, then the nearest remaining up to m_cap) runs on lane masks.  The
+// set, the order and so the stencil are those of k_stencil.  A larger ring gets
+// m = -1 and is searched again by k_stencil.
+constexpr int WV_HASH = 256; // > 2 x 128: at most 64 + 64 members before the overflow test
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_stencil_wave(const int32_t *__restrict__ pending, int64_t np, int R, int m_cap, int p,
+                   const int32_t *__restrict__ crd, int64_t ntot, int64_t n,
+                   const int32_t *__restrict__ r1cnt, const int32_t *__restrict__ r1,
+                   const int32_t *__restrict__ bowner, int32_t *__restrict__ cand,
+                   int32_t *__restrict__ mout) {
+  __shared__ int32_t sh_h[APC_BLOCK / 64][WV_HASH];
+  __shared__ int32_t sh_l[APC_BLOCK / 64][64];
+  __shared__ int32_t sh_c[APC_BLOCK / 64];
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t pos = (int64_t)blockIdx.x * (APC_BLOCK / 64) + w;
+  if (pos >= np) return; // whole wavefronts
+  int32_t *H = sh_h[w], *Ls = sh_l[w];
+  int32_t *cnt = &sh_c[w];
+  for (int k = lane; k < WV_HASH; k += 64) H[k] = -1;
+  if (lane == 0) *cnt = 0;
+  const int32_t y = pending[pos];
+  wave_sync();
+  auto insert = [&](int32_t v) {
+    uint32_t h = ring_hash(v, WV_HASH - 1);
+    for (;;) {
+      const int32_t old = atomicCAS(&H[h], -1, v);
+      if (old == -1) {
+        const int slot = atomicAdd(cnt, 1);
+        if (slot < 64) Ls[slot] = v;
+        return;
+      }
+      if (old == v) return;
+      h = (h + 1) & (WV_HASH - 1);
+    }
+  };
+  if (lane == 0) insert(y);
+  wave_sync();
+  int lo = 0, hi = 1;
+  bool ovf = false;
+  for (int depth = 1; depth <= R && !ovf; depth++) {
+    const int q = lo + lane;
+    int32_t nb[24];
+    int na = 0;
+    if (q < hi) {
+      const int32_t u = Ls[q];
+      if (u >= n) { // a boundary node's only neighbour is its owner
+        na = 1;
+        nb[0] = bowner[u - n];
+      } else {
+        na = r1cnt[u];
+#pragma unroll
+        for (int a = 0; a < 24; a++) nb[a] = a < na ? r1[(int64_t)u * 24 + a] : -1;
+      }
+    }
+#pragma unroll
+    for (int a = 0; a < 24; a++) {
+      if (a < na) insert(nb[a]);
+      wave_sync();
+      if (*cnt > 64) {
+        ovf = true;
+        break;
+      }
+    }
+    lo = hi;
+    hi = *cnt;
+  }
+  const int total = *cnt;
+  if (ovf || total > 64) {
+    if (lane == 0) mout[pos] = -1;
+    return;
+  }
+  const int nc = total - 1; // candidates: the members other than y
+  int32_t v = 0x7fffffff;
+  int64_t r2 = INT64_MAX;
+  uint32_t msk = 0;
+  if (lane < nc) {
+    const int32_t cy0 = crd[y], cy1 = crd[ntot + y], cy2 = crd[2 * ntot + y];
+    v = Ls[lane + 1]; // slot 0 holds y
+    const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
+    r2 = d0 * d0 + d1 * d1 + d2 * d2;
+    const uint32_t mx = (d0 >= 0 ? 0xF0u : 0u) | (d0 <= 0 ? 0x0Fu : 0u);
+    const uint32_t my = (d1 >= 0 ? 0xCCu : 0u) | (d1 <= 0 ? 0x33u : 0u);
+    const uint32_t mz = (d2 >= 0 ? 0xAAu : 0u) | (d2 <= 0 ? 0x55u : 0u);
+    msk = mx & my & mz;
+  }
+  // bitonic sort of (r2, v) ascending over the 64 lanes; idle lanes hold the maximum
+  for (int k = 2; k <= 64; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int64_t r2o = __shfl_xor(r2, j);
+      const int32_t vo = __shfl_xor(v, j);
+      const uint32_t mo = (uint32_t)__shfl_xor((int)msk, j);
+      const bool lower = (lane & j) == 0, up = (lane & k) == 0;
+      const bool o_less = r2o < r2 || (r2o == r2 && vo < v);
+      const bool o_more = r2o > r2 || (r2o == r2 && vo > v);
+      if (up == lower ? o_less : o_more) {
+        r2 = r2o;
+        v = vo;
+        msk = mo;
+      }
+    }
+  const int want = nc < m_cap ? nc : m_cap;
+  uint64_t inO[8];
+#pragma unroll
+  for (int o = 0; o < 8; o++) inO[o] = __ballot(lane < nc && ((msk >> o) & 1u));
+  uint64_t P = 0;
+#pragma unroll
+  for (int o = 0; o < 8; o++) {
+    uint64_t b = inO[o];
+#pragma unroll
+    for (int t = 0; t < 2; t++) {
+      if (!b) break;
+      const uint64_t low = b & (~b + 1ull);
+      b &= b - 1ull;
+      if (!(P & low) && __popcll(P) < want) P |= low;
+    }
+  }
+  uint64_t rem = (nc >= 64 ? ~0ull : ((1ull << nc) - 1ull)) & ~P;
+  while (__popcll(P) < want && rem) {
+    P |= rem & (~rem + 1ull);
+    rem &= rem - 1ull;
+  }
+  const int m = __popcll(P);
+  bool ok = m >= p + 1 && m <= APC_MAXM;
+#pragma unroll
+  for (int o = 0; o < 8; o++) ok = ok && (P & inO[o]) != 0;
+  if ((P >> lane) & 1ull)
+    cand[pos * APC_MAXM + __popcll(P & ((1ull << lane) - 1ull))] = v;
+  if (lane == 0) mout[pos] = ok ? m : 0;
+}
+
 // first-pass ring capacity of the stencil search; 0: 2 (2R+1)^3 for ring R (a
 // smaller value sends more nodes to the full-capacity rerun, same stencils)
 #ifndef APC_RING_FIRST_CAP
@@ -851,34 +993,49 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     const Scr S1 = carve(scr1, cap1, CH);
     for (int64_t c0 = 0; c0 < np; c0 += CH) {
       const int64_t cn = (np - c0) < CH ? (np - c0) : CH;
-      if (gen + 1 + (cn + CH2 - 1) / CH2 >= 0xffffu) {
+      if (gen + 2 + (cn + CH2 - 1) / CH2 >= 0xffffu) {
         apc_set_error_msg("ring search: too many launches for the hash tags");
         return APC_EINVAL;
       }
-      hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0,
-                         (const int32_t *)nullptr, cn, R, mcap, pk, ko, c->crd, ntot, n, r1cnt, r1,
-                         c->bowner, cap1, CH, S1.mask, ++gen, S1.lst, S1.key, S1.tab, 0, cand, mch,
-                         err);
-      HIPCHK(hipGetLastError());
-      // rerun the nodes whose ring outgrew cap1 with the full capacity
-      hipLaunchKernelGGL(k_retry_flag, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, mch, cn, rflag);
-      HIPCHK(hipGetLastError());
-      int64_t nr = 0;
-      APCCHK(apc_sum_i32(rflag, cn, &nr, s));
-      if (nr > 0) {
+      // the chunk's nodes whose stencil is still open (m < 0) are searched again by
+      // k_stencil with capacity capx, in launches of at most per nodes
+      auto rerun = [&](int capx, const Scr &S, int64_t stride, int64_t per, int full) -> int {
+        hipLaunchKernelGGL(k_retry_flag, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, mch, cn, rflag);
+        HIPCHK(hipGetLastError());
+        int64_t nr = 0;
+        APCCHK(apc_sum_i32(rflag, cn, &nr, s));
+        if (nr == 0) return APC_OK;
         APCCHK(apc_scan_i32(rflag, roff, cn, s));
         hipLaunchKernelGGL(k_compact_idx, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, rflag, roff,
                            (const int32_t *)nullptr, cn, rlist);
         HIPCHK(hipGetLastError());
-        for (int64_t r0 = 0; r0 < nr; r0 += CH2) {
-          const int64_t rn = (nr - r0) < CH2 ? (nr - r0) : CH2;
+        for (int64_t r0 = 0; r0 < nr; r0 += per) {
+          const int64_t rn = (nr - r0) < per ? (nr - r0) : per;
           hipLaunchKernelGGL(k_stencil, dim3(grid_for(rn)), dim3(APC_BLOCK), 0, s, pending + c0,
                              (const int32_t *)(rlist + r0), rn, R, mcap, pk, ko, c->crd, ntot, n,
-                             r1cnt, r1, c->bowner, APC_RING_CAP, CH2, S2.mask, ++gen, S2.lst,
-                             S2.key, S2.tab, 1, cand, mch, err);
+                             r1cnt, r1, c->bowner, capx, stride, S.mask, ++gen, S.lst, S.key,
+                             S.tab, full, cand, mch, err);
           HIPCHK(hipGetLastError());
         }
+        return APC_OK;
+      };
+      if (ko == 2) {
+        // rings of up to 63 candidates: one wavefront per node; the rest by
+        // k_stencil at capacity cap1
+        hipLaunchKernelGGL(k_stencil_wave, dim3(grid_for(cn, APC_BLOCK / 64)), dim3(APC_BLOCK), 0,
+                           s, pending + c0, cn, R, mcap, pk, c->crd, ntot, n, r1cnt, r1,
+                           c->bowner, cand, mch);
+        HIPCHK(hipGetLastError());
+        APCCHK(rerun(cap1, S1, CH, CH, 0));
+      } else {
+        hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0,
+                           (const int32_t *)nullptr, cn, R, mcap, pk, ko, c->crd, ntot, n, r1cnt,
+                           r1, c->bowner, cap1, CH, S1.mask, ++gen, S1.lst, S1.key, S1.tab, 0,
+                           cand, mch, err);
+        HIPCHK(hipGetLastError());
       }
+      // rerun the nodes whose ring outgrew cap1 with the full capacity
+      APCCHK(rerun(APC_RING_CAP, S2, CH2, CH2, 1));
       APCCHK(apc_rank_check(c, ko, pending + c0, cn, cand, mch, s));
       hipLaunchKernelGGL(k_accept, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, cand,
                          mch, stbuf, mnode, still + c0, ko, c->rorder);
