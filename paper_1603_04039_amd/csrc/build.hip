@@ -629,6 +629,176 @@ __global__ void __launch_bounds__(APC_BLOCK)
   if (lane == 0) mout[pos] = ok ? m : 0;
 }
 
+// The same search with one block per node for rings of 64 to 255 candidates
+// (the rings k_stencil_wave leaves open): threads expand the frontier into an LDS
+// hash set, a bitonic network in LDS sorts the members by (r2, index), and thread
+// 0 runs the selection on the 256-bit masks of the four wavefronts' ballots.
+// Larger rings keep m = -1 and go to k_stencil.  tmap lists the chunk positions
+// of the nodes to search (one block each).
+constexpr int BK_HASH = 1024; // > 2 x 512: at most 256 + 256 members before the overflow test
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_stencil_block(const int32_t *__restrict__ pending, const int32_t *__restrict__ tmap,
+                    int64_t np, int R, int m_cap, int p, const int32_t *__restrict__ crd,
+                    int64_t ntot, int64_t n, const int32_t *__restrict__ r1cnt,
+                    const int32_t *__restrict__ r1, const int32_t *__restrict__ bowner,
+                    int32_t *__restrict__ cand, int32_t *__restrict__ mout) {
+  __shared__ int32_t H[BK_HASH];
+  __shared__ int32_t Ls[APC_BLOCK];
+  __shared__ int64_t Kr[APC_BLOCK];
+  __shared__ int32_t Kv[APC_BLOCK];
+  __shared__ uint32_t Km[APC_BLOCK];
+  __shared__ uint64_t inO[8][APC_BLOCK / 64];
+  __shared__ uint64_t Pm[APC_BLOCK / 64];
+  __shared__ int32_t cnt, mres;
+  const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+  const int64_t t = blockIdx.x;
+  if (t >= np) return; // whole blocks
+  const int64_t pos = tmap[t];
+  const int32_t y = pending[pos];
+  for (int k = tid; k < BK_HASH; k += APC_BLOCK) H[k] = -1;
+  if (tid == 0) cnt = 0;
+  __syncthreads();
+  auto insert = [&](int32_t v) {
+    uint32_t h = ring_hash(v, BK_HASH - 1);
+    for (;;) {
+      const int32_t old = atomicCAS(&H[h], -1, v);
+      if (old == -1) {
+        const int slot = atomicAdd(&cnt, 1);
+        if (slot < APC_BLOCK) Ls[slot] = v;
+        return;
+      }
+      if (old == v) return;
+      h = (h + 1) & (BK_HASH - 1);
+    }
+  };
+  if (tid == 0) insert(y);
+  __syncthreads();
+  int lo = 0, hi = 1;
+  bool ovf = false;
+  for (int depth = 1; depth <= R && !ovf; depth++) {
+    const int q = lo + tid;
+    int32_t u = -1;
+    int na = 0;
+    if (q < hi) {
+      u = Ls[q];
+      na = u >= n ? 1 : r1cnt[u];
+    }
+    for (int a = 0; a < 24; a++) {
+      if (a < na) insert(u >= n ? bowner[u - n] : r1[(int64_t)u * 24 + a]);
+      __syncthreads();
+      const int c_now = cnt;
+      __syncthreads(); // every thread has read cnt before the next round changes it
+      if (c_now > APC_BLOCK) {
+        ovf = true;
+        break;
+      }
+    }
+    lo = hi;
+    hi = cnt;
+    __syncthreads();
+  }
+  const int total = cnt;
+  if (ovf || total > APC_BLOCK) {
+    if (tid == 0) mout[pos] = -1;
+    return;
+  }
+  const int nc = total - 1;
+  {
+    int32_t v = 0x7fffffff;
+    int64_t r2 = INT64_MAX;
+    uint32_t msk = 0;
+    if (tid < nc) {
+      v = Ls[tid + 1]; // slot 0 holds y
+      const int64_t d0 = crd[v] - crd[y], d1 = crd[ntot + v] - crd[ntot + y],
+                    d2 = crd[2 * ntot + v] - crd[2 * ntot + y];
+      r2 = d0 * d0 + d1 * d1 + d2 * d2;
+      const uint32_t mx = (d0 >= 0 ? 0xF0u : 0u) | (d0 <= 0 ? 0x0Fu : 0u);
+      const uint32_t my = (d1 >= 0 ? 0xCCu : 0u) | (d1 <= 0 ? 0x33u : 0u);
+      const uint32_t mz = (d2 >= 0 ? 0xAAu : 0u) | (d2 <= 0 ? 0x55u : 0u);
+      msk = mx & my & mz;
+    }
+    Kr[tid] = r2;
+    Kv[tid] = v;
+    Km[tid] = msk;
+  }
+  __syncthreads();
+  // bitonic sort of (r2, v) ascending over the block
+  for (int k = 2; k <= APC_BLOCK; k <<= 1)
+    for (int j = k >> 1; j > 0; j >>= 1) {
+      const int o = tid ^ j;
+      int64_t r2 = Kr[tid];
+      int32_t v = Kv[tid];
+      uint32_t msk = Km[tid];
+      const int64_t r2o = Kr[o];
+      const int32_t vo = Kv[o];
+      const uint32_t mo = Km[o];
+      const bool lower = (tid & j) == 0, up = (tid & k) == 0;
+      const bool o_less = r2o < r2 || (r2o == r2 && vo < v);
+      const bool o_more = r2o > r2 || (r2o == r2 && vo > v);
+      const bool take = up == lower ? o_less : o_more;
+      __syncthreads();
+      if (take) {
+        Kr[tid] = r2o;
+        Kv[tid] = vo;
+        Km[tid] = mo;
+      }
+      __syncthreads();
+    }
+  const uint32_t msk = Km[tid];
+#pragma unroll
+  for (int o = 0; o < 8; o++) {
+    const uint64_t b = __ballot(tid < nc && ((msk >> o) & 1u));
+    if (lane == 0) inO[o][w] = b;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    const int want = nc < m_cap ? nc : m_cap;
+    uint64_t P[APC_BLOCK / 64] = {0, 0, 0, 0};
+    int got = 0;
+    for (int o = 0; o < 8; o++) {
+      int taken = 0;
+      for (int q = 0; q < APC_BLOCK / 64 && taken < 2; q++) {
+        uint64_t b = inO[o][q];
+        while (b && taken < 2) {
+          const uint64_t low = b & (~b + 1ull);
+          b &= b - 1ull;
+          taken++;
+          if (!(P[q] & low) && got < want) {
+            P[q] |= low;
+            got++;
+          }
+        }
+      }
+    }
+    for (int q = 0; q < APC_BLOCK / 64 && got < want; q++) {
+      const int base = 64 * q;
+      const int lim = nc - base;
+      if (lim <= 0) break;
+      uint64_t rem = (lim >= 64 ? ~0ull : ((1ull << lim) - 1ull)) & ~P[q];
+      while (got < want && rem) {
+        P[q] |= rem & (~rem + 1ull);
+        rem &= rem - 1ull;
+        got++;
+      }
+    }
+    bool ok = got >= p + 1 && got <= APC_MAXM;
+    for (int o = 0; o < 8; o++) {
+      bool any = false;
+      for (int q = 0; q < APC_BLOCK / 64; q++) any = any || (P[q] & inO[o][q]) != 0;
+      ok = ok && any;
+    }
+    for (int q = 0; q < APC_BLOCK / 64; q++) Pm[q] = P[q];
+    mres = ok ? got : 0;
+  }
+  __syncthreads();
+  if ((Pm[w] >> lane) & 1ull) {
+    int idx = __popcll(Pm[w] & ((1ull << lane) - 1ull));
+    for (int q = 0; q < w; q++) idx += __popcll(Pm[q]);
+    cand[pos * APC_MAXM + idx] = Kv[tid];
+  }
+  if (tid == 0) mout[pos] = mres;
+}
+
 // first-pass ring capacity of the stencil search; 0: 2 (2R+1)^3 for ring R (a
 // smaller value sends more nodes to the full-capacity rerun, same stencils)
 #ifndef APC_RING_FIRST_CAP
@@ -999,16 +1169,22 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
       }
       // the chunk's nodes whose stencil is still open (m < 0) are searched again by
       // k_stencil with capacity capx, in launches of at most per nodes
-      auto rerun = [&](int capx, const Scr &S, int64_t stride, int64_t per, int full) -> int {
+      // chunk positions with m < 0 into rlist, their count into *nr
+      auto compact_open = [&](int64_t *nr) -> int {
         hipLaunchKernelGGL(k_retry_flag, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, mch, cn, rflag);
         HIPCHK(hipGetLastError());
-        int64_t nr = 0;
-        APCCHK(apc_sum_i32(rflag, cn, &nr, s));
-        if (nr == 0) return APC_OK;
+        *nr = 0;
+        APCCHK(apc_sum_i32(rflag, cn, nr, s));
+        if (*nr == 0) return APC_OK;
         APCCHK(apc_scan_i32(rflag, roff, cn, s));
         hipLaunchKernelGGL(k_compact_idx, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, rflag, roff,
                            (const int32_t *)nullptr, cn, rlist);
         HIPCHK(hipGetLastError());
+        return APC_OK;
+      };
+      auto rerun = [&](int capx, const Scr &S, int64_t stride, int64_t per, int full) -> int {
+        int64_t nr = 0;
+        APCCHK(compact_open(&nr));
         for (int64_t r0 = 0; r0 < nr; r0 += per) {
           const int64_t rn = (nr - r0) < per ? (nr - r0) : per;
           hipLaunchKernelGGL(k_stencil, dim3(grid_for(rn)), dim3(APC_BLOCK), 0, s, pending + c0,
@@ -1020,12 +1196,20 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
         return APC_OK;
       };
       if (ko == 2) {
-        // rings of up to 63 candidates: one wavefront per node; the rest by
-        // k_stencil at capacity cap1
+        // rings of up to 63 candidates: one wavefront per node; up to 255: one
+        // block per node; the rest by k_stencil at capacity cap1
         hipLaunchKernelGGL(k_stencil_wave, dim3(grid_for(cn, APC_BLOCK / 64)), dim3(APC_BLOCK), 0,
                            s, pending + c0, cn, R, mcap, pk, c->crd, ntot, n, r1cnt, r1,
                            c->bowner, cand, mch);
         HIPCHK(hipGetLastError());
+        int64_t nb = 0;
+        APCCHK(compact_open(&nb));
+        if (nb > 0) {
+          hipLaunchKernelGGL(k_stencil_block, dim3((unsigned)nb), dim3(APC_BLOCK), 0, s,
+                             pending + c0, (const int32_t *)rlist, nb, R, mcap, pk, c->crd, ntot,
+                             n, r1cnt, r1, c->bowner, cand, mch);
+          HIPCHK(hipGetLastError());
+        }
         APCCHK(rerun(cap1, S1, CH, CH, 0));
       } else {
         hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0,
