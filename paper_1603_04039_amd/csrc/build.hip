@@ -1115,11 +1115,17 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   uint64_t *scr1 = nullptr, *scr2 = nullptr;
   int32_t *cand = nullptr, *mch = nullptr, *still = nullptr, *soff = nullptr, *npend = nullptr,
           *rflag = nullptr, *roff = nullptr, *rlist = nullptr;
-  APCCHK(dalloc(&scr1, words1, s));
-  APCCHK(dalloc(&scr2, words2, s));
-  // hash entries carry the launch's generation: zero once, never cleared again
-  HIPCHK(hipMemsetAsync(scr1, 0, (size_t)words1 * 8, s));
-  HIPCHK(hipMemsetAsync(scr2, 0, (size_t)words2 * 8, s));
+  // scratch of the per-thread search (k_stencil), allocated on its first use: the
+  // wavefront and block searches keep their rings in LDS
+  auto scratch = [&]() -> int {
+    if (scr1) return APC_OK;
+    APCCHK(dalloc(&scr1, words1, s));
+    APCCHK(dalloc(&scr2, words2, s));
+    // hash entries carry the launch's tag: zero once, never cleared again
+    HIPCHK(hipMemsetAsync(scr1, 0, (size_t)words1 * 8, s));
+    HIPCHK(hipMemsetAsync(scr2, 0, (size_t)words2 * 8, s));
+    return APC_OK;
+  };
   uint32_t gen = 0; // launch tag of the hash entries; stays below 2^16 (see k_stencil)
   if (ntot > ((int64_t)1 << 31) - ((int64_t)1 << 16)) {
     apc_set_error_msg("too many nodes for the ring search");
@@ -1147,7 +1153,6 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     r.mask = (uint32_t)hash_size(cap) - 1u;
     return r;
   };
-  const Scr S2 = carve(scr2, APC_RING_CAP, CH2);
   // order fallback (k = 4): nodes with no acceptable order-4 stencil up to ring_max
   // take an order-2 row, chosen by the order-2 rule from ring 2 with cap 40
   HIPCHK(hipMalloc((void **)&c->rorder, (size_t)(n > 0 ? n : 1)));
@@ -1160,7 +1165,6 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
     const int cap1 = ring_cap(R);
     const int64_t CH = chunk_nodes(cap1, W1);
-    const Scr S1 = carve(scr1, cap1, CH);
     for (int64_t c0 = 0; c0 < np; c0 += CH) {
       const int64_t cn = (np - c0) < CH ? (np - c0) : CH;
       if (gen + 2 + (cn + CH2 - 1) / CH2 >= 0xffffu) {
@@ -1182,9 +1186,13 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
         HIPCHK(hipGetLastError());
         return APC_OK;
       };
-      auto rerun = [&](int capx, const Scr &S, int64_t stride, int64_t per, int full) -> int {
+      // (scratch 1: capacity cap1, stride CH; scratch 2: the full capacity, stride CH2)
+      auto rerun = [&](int capx, int which, int64_t stride, int64_t per, int full) -> int {
         int64_t nr = 0;
         APCCHK(compact_open(&nr));
+        if (nr == 0) return APC_OK;
+        APCCHK(scratch());
+        const Scr S = carve(which == 1 ? scr1 : scr2, capx, stride);
         for (int64_t r0 = 0; r0 < nr; r0 += per) {
           const int64_t rn = (nr - r0) < per ? (nr - r0) : per;
           hipLaunchKernelGGL(k_stencil, dim3(grid_for(rn)), dim3(APC_BLOCK), 0, s, pending + c0,
@@ -1210,8 +1218,10 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
                              n, r1cnt, r1, c->bowner, cand, mch);
           HIPCHK(hipGetLastError());
         }
-        APCCHK(rerun(cap1, S1, CH, CH, 0));
+        APCCHK(rerun(cap1, 1, CH, CH, 0));
       } else {
+        APCCHK(scratch());
+        const Scr S1 = carve(scr1, cap1, CH);
         hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0,
                            (const int32_t *)nullptr, cn, R, mcap, pk, ko, c->crd, ntot, n, r1cnt,
                            r1, c->bowner, cap1, CH, S1.mask, ++gen, S1.lst, S1.key, S1.tab, 0,
@@ -1219,7 +1229,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
         HIPCHK(hipGetLastError());
       }
       // rerun the nodes whose ring outgrew cap1 with the full capacity
-      APCCHK(rerun(APC_RING_CAP, S2, CH2, CH2, 1));
+      APCCHK(rerun(APC_RING_CAP, 2, CH2, CH2, 1));
       APCCHK(apc_rank_check(c, ko, pending + c0, cn, cand, mch, s));
       hipLaunchKernelGGL(k_accept, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, cand,
                          mch, stbuf, mnode, still + c0, ko, c->rorder);
