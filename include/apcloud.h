@@ -88,6 +88,11 @@ typedef struct {
                         4 with k = 2 is the balance of the supraconvergent
                         second-order error bound (Sec. 3.3), h = c N'^(-1/4);
                         1..16 accepted */
+  int ring_lds;      /* order-2 stencil search (performance only, same stencils bit
+                        for bit): 0 = default, rings of up to 63 candidates with one
+                        wavefront per node and up to 255 with one block per node,
+                        both in LDS, the rest per thread; 1 = the wavefront tier
+                        only; -1 = every ring per thread */
 } apc_params;
 
 typedef struct {

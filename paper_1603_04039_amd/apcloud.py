@@ -44,7 +44,8 @@ class Params(ct.Structure):
     _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
-                ("precision", ct.c_int), ("stage_cap", ct.c_int), ("criterion_pow", ct.c_int)]
+                ("precision", ct.c_int), ("stage_cap", ct.c_int), ("criterion_pow", ct.c_int),
+                ("ring_lds", ct.c_int)]
 
 
 class Stats(ct.Structure):
@@ -151,7 +152,7 @@ def _check(rc, what):
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
                 ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64,
-                stage_cap=0, criterion_pow=0) -> Params:
+                stage_cap=0, criterion_pow=0, ring_lds=0) -> Params:
     p = Params()
     load_library().apc_default_params(ct.byref(p), order)
     p.lo[:] = lo
@@ -167,6 +168,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     p.precision = precision
     p.stage_cap = stage_cap
     p.criterion_pow = criterion_pow
+    p.ring_lds = ring_lds
     return p
 
 

@@ -1203,7 +1203,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
         }
         return APC_OK;
       };
-      if (ko == 2) {
+      if (ko == 2 && P.ring_lds >= 0) {
         // rings of up to 63 candidates: one wavefront per node; up to 255: one
         // block per node; the rest by k_stencil at capacity cap1
         hipLaunchKernelGGL(k_stencil_wave, dim3(grid_for(cn, APC_BLOCK / 64)), dim3(APC_BLOCK), 0,
@@ -1211,7 +1211,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
                            c->bowner, cand, mch);
         HIPCHK(hipGetLastError());
         int64_t nb = 0;
-        APCCHK(compact_open(&nb));
+        if (P.ring_lds == 0) APCCHK(compact_open(&nb));
         if (nb > 0) {
           hipLaunchKernelGGL(k_stencil_block, dim3((unsigned)nb), dim3(APC_BLOCK), 0, s,
                              pending + c0, (const int32_t *)rlist, nb, R, mcap, pk, c->crd, ntot,
@@ -1306,7 +1306,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   if (p->order != 2 && p->order != 4) return APC_EINVAL;
   if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
       p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 || p->stage_cap < -1 ||
-      p->criterion_pow < 0 || p->criterion_pow > 16 ||
+      p->criterion_pow < 0 || p->criterion_pow > 16 || p->ring_lds < -1 || p->ring_lds > 1 ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
         p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c))
     return APC_EINVAL;
