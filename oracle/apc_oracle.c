@@ -18,6 +18,8 @@
  *               Poisson rows, Taylor interpolation of phi and grad phi
  *   Sec. 5      BiCGSTAB (the paper leaves the sparse solver open) and a dense
  *               LU cross-check
+ *   Sec. 1      leapfrog particle push of the Vlasov-Poisson loop, with
+ *               specular walls (the paper leaves the integrator open)
  *
  * Readings of points the paper leaves open are stated where they are used.
  */
