@@ -816,15 +816,21 @@ __global__ void __launch_bounds__(APC_BLOCK)
              const int32_t *__restrict__ m, int32_t *__restrict__ stbuf,
              int32_t *__restrict__ mnode, int32_t *__restrict__ still, int order,
              int8_t *__restrict__ rorder) {
-  int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  // one thread per (node, slot): a wavefront copies one node's row of APC_MAXM slots
+  const int64_t e = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  const int64_t t = e / APC_MAXM;
+  const int j = (int)(e % APC_MAXM);
   if (t >= np) return;
   const int32_t y = pending[t];
   const int mm = m[t];
-  still[t] = mm > 0 ? 0 : 1;
-  if (mm <= 0) return;
-  mnode[y] = mm;
-  rorder[y] = (int8_t)order;
-  for (int j = 0; j < mm; j++) stbuf[(int64_t)y * APC_MAXM + j] = cand[t * APC_MAXM + j];
+  if (j == 0) {
+    still[t] = mm > 0 ? 0 : 1;
+    if (mm > 0) {
+      mnode[y] = mm;
+      rorder[y] = (int8_t)order;
+    }
+  }
+  if (j < mm) stbuf[(int64_t)y * APC_MAXM + j] = cand[t * APC_MAXM + j];
 }
 
 __global__ void __launch_bounds__(APC_BLOCK)
@@ -1231,7 +1237,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
       // rerun the nodes whose ring outgrew cap1 with the full capacity
       APCCHK(rerun(APC_RING_CAP, 2, CH2, CH2, 1));
       APCCHK(apc_rank_check(c, ko, pending + c0, cn, cand, mch, s));
-      hipLaunchKernelGGL(k_accept, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0, cn, cand,
+      hipLaunchKernelGGL(k_accept, dim3(grid_for(cn * APC_MAXM)), dim3(APC_BLOCK), 0, s, pending + c0, cn, cand,
                          mch, stbuf, mnode, still + c0, ko, c->rorder);
       HIPCHK(hipGetLastError());
     }
