@@ -192,6 +192,10 @@ int apc_radix_sort(uint64_t *keys, int32_t *vals, int64_t n, int bits, hipStream
 // 16 GiB cache go back to it.  Same signatures as hipMallocAsync / hipFreeAsync.
 hipError_t apc_malloc_async(void **p, size_t bytes, hipStream_t s);
 hipError_t apc_free_async(void *p, hipStream_t s);
+// Arrays a cloud keeps for its lifetime: a device-wide cache of freed blocks of
+// the same size classes; apc_dev_free requires that no queued work uses the block.
+hipError_t apc_dev_alloc(void **p, size_t bytes);
+hipError_t apc_dev_free(void *p);
 
 int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_t s,
                    apc_cloud **out);

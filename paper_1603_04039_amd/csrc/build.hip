@@ -924,13 +924,15 @@ void free_cloud_arrays(apc_cloud *c) {
   void *ptrs[] = {c->perm, c->sxyz, c->pnode, c->code, c->level, c->first, c->count, c->crd,
                   c->bowner, c->bface, c->st_off, c->st_idx};
   for (void *q : ptrs)
-    if (q) (void)hipFree(q);
+    if (q) (void)apc_dev_free(q);
 }
 
 } // namespace
 
 void apc_free_cloud(apc_cloud *c) {
   if (!c) return;
+  // once for all arrays: queued work on any stream may still use them
+  (void)hipDeviceSynchronize();
   apc_free_solver(c);
   apc_free_sell(c);
   free_cloud_arrays(c);
@@ -938,7 +940,7 @@ void apc_free_cloud(apc_cloud *c) {
                  c->m_diag, c->m_sell, c->m_tmpl, c->bw64, c->bw32, c->sl_bw64, c->sl_bw32,
                  c->rorder};
   for (void *q : ops)
-    if (q) (void)hipFree(q);
+    if (q) (void)apc_dev_free(q);
   delete c;
 }
 
@@ -954,7 +956,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   uint64_t *keys = nullptr;
   int *err = nullptr;
   APCCHK(dalloc(&keys, N, s));
-  HIPCHK(hipMalloc((void **)&c->perm, (size_t)N * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->perm, (size_t)N * sizeof(int32_t)));
   APCCHK(dalloc(&err, 1, s));
   HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
   const double scale = ldexp(1.0, D) / P.L;
@@ -1017,10 +1019,10 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   c->n_opened = opened;
 
   // leaves
-  HIPCHK(hipMalloc((void **)&c->code, (size_t)n * sizeof(uint64_t)));
-  HIPCHK(hipMalloc((void **)&c->level, (size_t)n * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->first, (size_t)n * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->count, (size_t)n * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->code, (size_t)n * sizeof(uint64_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->level, (size_t)n * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->first, (size_t)n * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->count, (size_t)n * sizeof(int32_t)));
   hipLaunchKernelGGL(k_leaf_out, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, mc, cl.lev, n, c->code,
                      c->level);
   HIPCHK(hipMemcpyAsync(c->first, cl.fst, (size_t)n * sizeof(int32_t), hipMemcpyDeviceToDevice, s));
@@ -1039,9 +1041,9 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   const int64_t nb = (int64_t)last[0] + last[1];
   c->nb = nb;
   const int64_t ntot = n + nb;
-  HIPCHK(hipMalloc((void **)&c->crd, (size_t)3 * ntot * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->bowner, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->bface, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->crd, (size_t)3 * ntot * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->bowner, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->bface, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
   hipLaunchKernelGGL(k_nodes, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, bstart, n,
                      ntot, D, c->crd, c->bowner, c->bface);
   HIPCHK(hipGetLastError());
@@ -1161,7 +1163,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   };
   // order fallback (k = 4): nodes with no acceptable order-4 stencil up to ring_max
   // take an order-2 row, chosen by the order-2 rule from ring 2 with cap 40
-  HIPCHK(hipMalloc((void **)&c->rorder, (size_t)(n > 0 ? n : 1)));
+  HIPCHK(apc_dev_alloc((void **)&c->rorder, (size_t)(n > 0 ? n : 1)));
   for (int att = 0; att < 2 && np > 0; att++) {
   if (att == 1 && P.order != 4) break;
   const int ko = att == 0 ? P.order : 2;
@@ -1274,7 +1276,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   if (np > 0) return APC_ESTENCIL;
 
   // stencil CSR
-  HIPCHK(hipMalloc((void **)&c->st_off, (size_t)(n + 1) * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->st_off, (size_t)(n + 1) * sizeof(int32_t)));
   APCCHK(apc_scan_i32(mnode, c->st_off, n, s));
   int32_t lastm[2];
   HIPCHK(hipMemcpyAsync(&lastm[0], c->st_off + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1284,7 +1286,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   c->nnz = nnz;
   const int32_t nnz32 = (int32_t)nnz;
   HIPCHK(hipMemcpyAsync(c->st_off + n, &nnz32, sizeof(int32_t), hipMemcpyHostToDevice, s));
-  HIPCHK(hipMalloc((void **)&c->st_idx, (size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->st_idx, (size_t)(nnz > 0 ? nnz : 1) * sizeof(int32_t)));
   hipLaunchKernelGGL(k_csr_fill, dim3(grid_for(n * APC_MAXM)), dim3(APC_BLOCK), 0, s, stbuf,
                      c->st_off, n, c->st_idx);
   HIPCHK(hipGetLastError());
@@ -1292,8 +1294,8 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   APCCHK(dfree(mnode, s));
 
   // particles: leaf of each sorted particle, sorted positions
-  HIPCHK(hipMalloc((void **)&c->pnode, (size_t)N * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->sxyz, (size_t)3 * N * sizeof(double)));
+  HIPCHK(apc_dev_alloc((void **)&c->pnode, (size_t)N * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sxyz, (size_t)3 * N * sizeof(double)));
   hipLaunchKernelGGL(k_pnode, dim3(grid_for(N)), dim3(APC_BLOCK), 0, s, c->first, n, N, c->pnode);
   hipLaunchKernelGGL(k_gather_xyz, dim3(grid_for(N)), dim3(APC_BLOCK), 0, s, xyz, c->perm, N,
                      c->sxyz);

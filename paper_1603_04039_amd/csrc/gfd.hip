@@ -444,14 +444,14 @@ int apc_rank_check(const apc_cloud *c, int order, const int32_t *pending, int64_
 int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
   const int64_t n = c->n, ntot = c->n + c->nb;
   const bool mixed = c->P.precision != APC_FP64;
-  HIPCHK(hipMalloc((void **)&c->diag, (size_t)n * sizeof(double)));
-  HIPCHK(hipMalloc((void **)&c->inv_diag, (size_t)n * sizeof(double)));
-  HIPCHK(hipMalloc((void **)&c->hscale, (size_t)n * sizeof(double)));
-  HIPCHK(hipMalloc((void **)&c->rkind, (size_t)n * sizeof(int8_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->diag, (size_t)n * sizeof(double)));
+  HIPCHK(apc_dev_alloc((void **)&c->inv_diag, (size_t)n * sizeof(double)));
+  HIPCHK(apc_dev_alloc((void **)&c->hscale, (size_t)n * sizeof(double)));
+  HIPCHK(apc_dev_alloc((void **)&c->rkind, (size_t)n * sizeof(int8_t)));
   if (mixed)
-    HIPCHK(hipMalloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
+    HIPCHK(apc_dev_alloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
   else
-    HIPCHK(hipMalloc((void **)&c->w64, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
+    HIPCHK(apc_dev_alloc((void **)&c->w64, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
   if (c->P.order == 2) {
     hipLaunchKernelGGL(k_classify, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
                        c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->rkind);
@@ -464,12 +464,12 @@ int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
   if (c->P.order == 4) {
     const size_t nz = (size_t)(c->nnz > 0 ? c->nnz : 1), ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 1);
     if (mixed) {
-      HIPCHK(hipMalloc((void **)&c->bw32, nz * sizeof(float)));
-      HIPCHK(hipMalloc((void **)&c->sl_bw32, ne * sizeof(float)));
+      HIPCHK(apc_dev_alloc((void **)&c->bw32, nz * sizeof(float)));
+      HIPCHK(apc_dev_alloc((void **)&c->sl_bw32, ne * sizeof(float)));
       HIPCHK(hipMemsetAsync(c->sl_bw32, 0, ne * sizeof(float), s));
     } else {
-      HIPCHK(hipMalloc((void **)&c->bw64, nz * sizeof(double)));
-      HIPCHK(hipMalloc((void **)&c->sl_bw64, ne * sizeof(double)));
+      HIPCHK(apc_dev_alloc((void **)&c->bw64, nz * sizeof(double)));
+      HIPCHK(apc_dev_alloc((void **)&c->sl_bw64, ne * sizeof(double)));
       HIPCHK(hipMemsetAsync(c->sl_bw64, 0, ne * sizeof(double), s));
     }
   }
@@ -488,7 +488,7 @@ int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
           hcrd[50 + k] = 4 + dz;
           k++;
         }
-  HIPCHK(hipMalloc((void **)&c->scratch, sizeof(apc_asm_scratch)));
+  HIPCHK(apc_dev_alloc((void **)&c->scratch, sizeof(apc_asm_scratch)));
   HIPCHK(hipMemsetAsync(c->scratch, 0, sizeof(apc_asm_scratch), s));
   HIPCHK(hipMemcpyAsync(c->scratch->crd, hcrd, sizeof(hcrd), hipMemcpyHostToDevice, s));
   hipLaunchKernelGGL(k_canon24, dim3(1), dim3(64), 0, s, c->scratch->crd, c->scratch->tc);

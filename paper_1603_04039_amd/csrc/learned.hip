@@ -723,10 +723,10 @@ int apc_mlp_infer_impl(apc_cloud *c, const float *P, const float *feat, int bf16
 int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, hipStream_t s) {
   if (!c->assembled) return APC_EINVAL;
   const int64_t n = c->n;
-  if (!c->m_diag) HIPCHK(hipMalloc((void **)&c->m_diag, (size_t)(n > 0 ? n : 1) * sizeof(float)));
+  if (!c->m_diag) HIPCHK(apc_dev_alloc((void **)&c->m_diag, (size_t)(n > 0 ? n : 1) * sizeof(float)));
   if (!c->m_sell)
-    HIPCHK(hipMalloc((void **)&c->m_sell, (size_t)(c->sl_entries > 0 ? c->sl_entries : 1) * sizeof(float)));
-  if (!c->m_tmpl) HIPCHK(hipMalloc((void **)&c->m_tmpl, (size_t)APC_MAX_LEVELS * NT * sizeof(float)));
+    HIPCHK(apc_dev_alloc((void **)&c->m_sell, (size_t)(c->sl_entries > 0 ? c->sl_entries : 1) * sizeof(float)));
+  if (!c->m_tmpl) HIPCHK(apc_dev_alloc((void **)&c->m_tmpl, (size_t)APC_MAX_LEVELS * NT * sizeof(float)));
   uint16_t *wb = nullptr;
   int32_t *rep = nullptr;
   HIPCHK(apc_malloc_async((void **)&wb, (size_t)NWB * 2, s));

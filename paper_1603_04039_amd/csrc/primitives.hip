@@ -296,3 +296,80 @@ hipError_t apc_free_async(void *p, hipStream_t s) {
   C.cached += cls;
   return hipSuccess;
 }
+
+// ---------------------------------------------------------------- persistent arrays
+// The arrays a cloud keeps (its structure, operators and solver workspace) come
+// from a device-wide cache of freed blocks: apc_dev_free keeps a block for the next
+// apc_dev_alloc of its size class on that device instead of calling hipFree, which
+// waits for the whole device on every call.  The caller of apc_dev_free guarantees
+// that no queued work still uses the block (apc_destroy synchronises the device
+// once, then frees every array).  Blocks not from apc_dev_alloc go to hipFree.
+namespace {
+struct DevCache {
+  std::mutex mu;
+  std::map<int, std::multimap<size_t, void *>> free;       // device -> size class -> blocks
+  std::unordered_map<void *, std::pair<int, size_t>> live; // block -> (device, size class)
+  size_t cached = 0;
+};
+DevCache &dev_cache() {
+  static DevCache *c = new DevCache(); // never destroyed: blocks live until process exit
+  return *c;
+}
+constexpr size_t DEV_CACHE_MAX = (size_t)32 << 30;
+} // namespace
+
+hipError_t apc_dev_alloc(void **p, size_t bytes) {
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  const size_t cls = tmp_class(bytes);
+  DevCache &C = dev_cache();
+  {
+    std::lock_guard<std::mutex> lock(C.mu);
+    auto f = C.free.find(dev);
+    if (f != C.free.end()) {
+      auto it = f->second.lower_bound(cls);
+      if (it != f->second.end() && it->first <= 2 * cls) {
+        *p = it->second;
+        C.live[it->second] = {dev, it->first};
+        C.cached -= it->first;
+        f->second.erase(it);
+        return hipSuccess;
+      }
+    }
+  }
+  e = hipMalloc(p, cls);
+  if (e == hipErrorOutOfMemory) {
+    // give this device's cached blocks back, then try once more
+    (void)hipGetLastError();
+    std::lock_guard<std::mutex> lock(C.mu);
+    auto f = C.free.find(dev);
+    if (f != C.free.end()) {
+      for (auto &b : f->second) {
+        (void)hipFree(b.second);
+        C.cached -= b.first;
+      }
+      f->second.clear();
+    }
+    e = hipMalloc(p, cls);
+  }
+  if (e != hipSuccess) return e;
+  std::lock_guard<std::mutex> lock(C.mu);
+  C.live[*p] = {dev, cls};
+  return hipSuccess;
+}
+
+hipError_t apc_dev_free(void *p) {
+  if (!p) return hipSuccess;
+  DevCache &C = dev_cache();
+  std::lock_guard<std::mutex> lock(C.mu);
+  auto it = C.live.find(p);
+  if (it == C.live.end()) return hipFree(p); // not from apc_dev_alloc
+  const int dev = it->second.first;
+  const size_t cls = it->second.second;
+  C.live.erase(it);
+  if (C.cached + cls > DEV_CACHE_MAX) return hipFree(p);
+  C.free[dev].insert({cls, p});
+  C.cached += cls;
+  return hipSuccess;
+}

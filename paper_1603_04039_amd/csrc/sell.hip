@@ -274,10 +274,10 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
     HIPCHK(apc_free_async(key, s));
   }
   const size_t nsz = (size_t)(ns > 0 ? ns : 1);
-  HIPCHK(hipMalloc((void **)&c->sl_rows, nsz * SL * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->sl_len, nsz * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->sl_tmpl, nsz * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->sl_off, nsz * sizeof(int64_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_rows, nsz * SL * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_len, nsz * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_tmpl, nsz * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_off, nsz * sizeof(int64_t)));
   int64_t *ent = nullptr;
   HIPCHK(apc_malloc_async((void **)&ent, nsz * sizeof(int64_t), s));
   if (ns > 0) {
@@ -292,11 +292,11 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
     c->sl_entries = lasto + laste;
   }
   const size_t ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 1);
-  HIPCHK(hipMalloc((void **)&c->sl_idx, ne * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_idx, ne * sizeof(int32_t)));
   if (c->P.precision == APC_FP64)
-    HIPCHK(hipMalloc((void **)&c->sl_w64, ne * sizeof(double)));
+    HIPCHK(apc_dev_alloc((void **)&c->sl_w64, ne * sizeof(double)));
   else
-    HIPCHK(hipMalloc((void **)&c->sl_w32, ne * sizeof(float)));
+    HIPCHK(apc_dev_alloc((void **)&c->sl_w32, ne * sizeof(float)));
   if (ns > 0) {
     hipLaunchKernelGGL(k_sell_idx, dim3((unsigned)ns), dim3(SL), 0, s, c->sl_rows, c->sl_len,
                        c->sl_off, c->st_off, c->st_idx, c->sl_idx);
@@ -323,9 +323,9 @@ static int build_staging(apc_cloud *c, hipStream_t s) {
   const int cap = c->P.stage_cap == 0 ? APC_UCAP_MAX : std::min(c->P.stage_cap, APC_UCAP_MAX);
   c->ucap = 0;
   if (cap <= 0) return APC_OK;
-  HIPCHK(hipMalloc((void **)&c->sl_un, nsz * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->sl_uq, ne * sizeof(int32_t)));
-  HIPCHK(hipMalloc((void **)&c->sl_lx2, ne / 2 * sizeof(uint32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_un, nsz * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_uq, ne * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_lx2, ne / 2 * sizeof(uint32_t)));
   HIPCHK(hipMemsetAsync(c->sl_lx2, 0, ne / 2 * sizeof(uint32_t), s));
   if (c->nsl <= 0) return APC_OK;
   hipLaunchKernelGGL(k_uniq, dim3((unsigned)c->nsl), dim3(UQ_T), 0, s, c->sl_rows, c->sl_len,
@@ -346,14 +346,17 @@ static int build_staging(apc_cloud *c, hipStream_t s) {
 int apc_pack_sell_idx(apc_cloud *c, hipStream_t s) {
   const size_t ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 4);
   void *old[] = {c->sl_lo2, c->sl_hi4, c->sl_top4, c->sl_un, c->sl_uq, c->sl_lx2};
+  bool any = false;
+  for (void *q : old) any = any || q;
+  if (any) HIPCHK(hipDeviceSynchronize()); // queued work may still read the old arrays
   for (void *q : old)
-    if (q) HIPCHK(hipFree(q));
+    if (q) HIPCHK(apc_dev_free(q));
   c->sl_lo2 = c->sl_hi4 = c->sl_top4 = c->sl_lx2 = nullptr;
   c->sl_un = c->sl_uq = nullptr;
-  HIPCHK(hipMalloc((void **)&c->sl_lo2, ne / 2 * sizeof(uint32_t)));
-  HIPCHK(hipMalloc((void **)&c->sl_hi4, ne / 4 * sizeof(uint32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_lo2, ne / 2 * sizeof(uint32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->sl_hi4, ne / 4 * sizeof(uint32_t)));
   if (c->n + c->nb >= ((int64_t)1 << 24))
-    HIPCHK(hipMalloc((void **)&c->sl_top4, ne / 4 * sizeof(uint32_t)));
+    HIPCHK(apc_dev_alloc((void **)&c->sl_top4, ne / 4 * sizeof(uint32_t)));
   if (c->nsl > 0) {
     hipLaunchKernelGGL(k_pack_idx, dim3((unsigned)c->nsl), dim3(SL), 0, s, c->sl_len, c->sl_off,
                        c->sl_idx, c->sl_lo2, c->sl_hi4, c->sl_top4);
@@ -366,7 +369,7 @@ void apc_free_sell(apc_cloud *c) {
   void *ptrs[] = {c->sl_rows, c->sl_len, c->sl_tmpl, c->sl_off, c->sl_idx, c->sl_w64, c->sl_w32,
                   c->sl_lo2, c->sl_hi4, c->sl_top4, c->sl_un, c->sl_uq, c->sl_lx2};
   for (void *q : ptrs)
-    if (q) (void)hipFree(q);
+    if (q) (void)apc_dev_free(q);
   c->sl_lo2 = c->sl_hi4 = c->sl_top4 = c->sl_lx2 = nullptr;
   c->sl_un = c->sl_uq = nullptr;
   c->ucap = 0;

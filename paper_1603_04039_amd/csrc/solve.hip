@@ -432,8 +432,8 @@ void apc_free_solver(apc_cloud *c) {
   if (!w) return;
   double *vs[] = {w->x, w->r, w->rh, w->p, w->v, w->s, w->t, w->ph, w->sh, w->b, w->part};
   for (double *q : vs)
-    if (q) (void)hipFree(q);
-  if (w->sc) (void)hipFree(w->sc);
+    if (q) (void)apc_dev_free(q);
+  if (w->sc) (void)apc_dev_free(w->sc);
   if (w->sc_host) (void)hipHostFree(w->sc_host);
   if (w->e0) (void)hipEventDestroy(w->e0);
   if (w->e1) (void)hipEventDestroy(w->e1);
@@ -450,11 +450,11 @@ static int ensure_ws(apc_cloud *c) {
   const size_t bytes = (size_t)w->ntot * sizeof(double);
   double **vs[] = {&w->x, &w->r, &w->rh, &w->p, &w->v, &w->s, &w->t, &w->ph, &w->sh, &w->b};
   for (double **q : vs) {
-    HIPCHK(hipMalloc((void **)q, bytes));
+    HIPCHK(apc_dev_alloc((void **)q, bytes));
     HIPCHK(hipMemset(*q, 0, bytes)); // boundary tails stay zero for good
   }
-  HIPCHK(hipMalloc((void **)&w->part, 2 * (size_t)GSPMV * sizeof(double)));
-  HIPCHK(hipMalloc((void **)&w->sc, sizeof(Scal)));
+  HIPCHK(apc_dev_alloc((void **)&w->part, 2 * (size_t)GSPMV * sizeof(double)));
+  HIPCHK(apc_dev_alloc((void **)&w->sc, sizeof(Scal)));
   HIPCHK(hipMemset(w->sc, 0, sizeof(Scal)));
   HIPCHK(hipHostMalloc((void **)&w->sc_host, sizeof(Scal), hipHostMallocDefault));
   HIPCHK(hipEventCreate(&w->e0));
