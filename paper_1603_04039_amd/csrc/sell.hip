@@ -141,13 +141,18 @@ __global__ void __launch_bounds__(SL)
 // entry gets the slot of its column.  Writes the count (un), the columns in
 // ascending order at the slice's entry offset (uq) and the 16-bit slots (lx2, as
 // uint16: entry k of lane r at 2 (o/2 + 64 (k/2) + r) + k%2).
-constexpr int UQ_T = 256, UQ_MAX = 4096;
+constexpr int UQ_T = 256, UQ_MAX = 4096, UQ_HASH = 8192; // hash at most half full
+// The distinct columns of one slice, ascending, and each entry's slot among them:
+// the valid entries' columns go into an LDS hash set (each new column appended to
+// a list), only the distinct columns are sorted (bitonic), and every entry finds
+// its slot by binary search in the sorted list.  Entries of padding rows keep slot 0.
 __global__ void __launch_bounds__(UQ_T)
     k_uniq(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
            const int64_t *__restrict__ sl_off, const int32_t *__restrict__ idx,
            int32_t *__restrict__ un, int32_t *__restrict__ uq, uint16_t *__restrict__ lx) {
-  __shared__ uint64_t key[UQ_MAX];
-  __shared__ int32_t cnt[UQ_T];
+  __shared__ int32_t hk[UQ_HASH];
+  __shared__ int32_t lst[UQ_MAX];
+  __shared__ int32_t nd;
   const int64_t s = blockIdx.x;
   const int t = threadIdx.x;
   const int len = sl_len[s];
@@ -157,58 +162,57 @@ __global__ void __launch_bounds__(UQ_T)
     return;
   }
   const int64_t o = sl_off[s];
-  int np = SL;
-  while (np < ne) np <<= 1;
-  for (int e = t; e < np; e += UQ_T) {
-    uint64_t kv = ~0ull;
-    if (e < ne && sl_rows[s * SL + (e & (SL - 1))] >= 0)
-      kv = ((uint64_t)(uint32_t)idx[o + e] << 12) | (uint64_t)e;
-    key[e] = kv;
+  for (int k = t; k < UQ_HASH; k += UQ_T) hk[k] = -1;
+  if (t == 0) nd = 0;
+  __syncthreads();
+  for (int e = t; e < ne; e += UQ_T) {
+    if (sl_rows[s * SL + (e & (SL - 1))] < 0) continue;
+    const int32_t col = idx[o + e];
+    uint32_t h = ((uint32_t)col * 2654435761u) & (UQ_HASH - 1);
+    for (;;) {
+      const int32_t old = atomicCAS(&hk[h], -1, col);
+      if (old == -1) {
+        lst[atomicAdd(&nd, 1)] = col;
+        break;
+      }
+      if (old == col) break;
+      h = (h + 1) & (UQ_HASH - 1);
+    }
   }
+  __syncthreads();
+  const int n_d = nd;
+  int np = 1;
+  while (np < n_d) np <<= 1;
+  for (int k = n_d + t; k < np; k += UQ_T) lst[k] = 0x7fffffff;
   __syncthreads();
   for (int kk = 2; kk <= np; kk <<= 1)
     for (int j = kk >> 1; j > 0; j >>= 1) {
       for (int e = t; e < np; e += UQ_T) {
-        const int p = e ^ j;
-        if (p > e) {
-          const uint64_t a = key[e], b = key[p];
+        const int q = e ^ j;
+        if (q > e) {
+          const int32_t a = lst[e], b = lst[q];
           if ((a > b) == ((e & kk) == 0)) {
-            key[e] = b;
-            key[p] = a;
+            lst[e] = b;
+            lst[q] = a;
           }
         }
       }
       __syncthreads();
     }
-  // thread t owns sorted positions [t per, (t+1) per)
-  const int per = np / UQ_T > 0 ? np / UQ_T : 1;
-  const int e0 = t * per, e1 = min(e0 + per, np);
-  int c = 0;
-  for (int e = e0; e < e1; e++) {
-    const uint64_t kv = key[e];
-    c += kv != ~0ull && (e == 0 || (kv >> 12) != (key[e - 1] >> 12));
-  }
-  cnt[t] = c;
-  __syncthreads();
-  for (int d = 1; d < UQ_T; d <<= 1) { // inclusive scan
-    const int v = t >= d ? cnt[t - d] : 0;
-    __syncthreads();
-    cnt[t] += v;
-    __syncthreads();
-  }
-  int r = cnt[t] - c - 1; // slot of the run that precedes this thread's first start
-  for (int e = e0; e < e1; e++) {
-    const uint64_t kv = key[e];
-    if (kv == ~0ull) break;
-    const int32_t col = (int32_t)(kv >> 12);
-    if (e == 0 || (kv >> 12) != (key[e - 1] >> 12)) {
-      r++;
-      uq[o + r] = col;
+  for (int r = t; r < n_d; r += UQ_T) uq[o + r] = lst[r];
+  for (int e = t; e < ne; e += UQ_T) {
+    if (sl_rows[s * SL + (e & (SL - 1))] < 0) continue;
+    const int32_t col = idx[o + e];
+    int lo = 0, hi = n_d; // first position with lst[pos] >= col
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (lst[mid] < col) lo = mid + 1;
+      else hi = mid;
     }
-    const int en = (int)(kv & 4095u), k = en >> 6, lane = en & (SL - 1);
-    lx[2 * ((o >> 1) + (int64_t)SL * (k >> 1) + lane) + (k & 1)] = (uint16_t)r;
+    const int k = e >> 6, lane = e & (SL - 1);
+    lx[2 * ((o >> 1) + (int64_t)SL * (k >> 1) + lane) + (k & 1)] = (uint16_t)lo;
   }
-  if (t == UQ_T - 1) un[s] = cnt[UQ_T - 1];
+  if (t == 0) un[s] = n_d;
 }
 
 // slices with more distinct columns than the tile holds gather directly
