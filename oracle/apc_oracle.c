@@ -916,39 +916,108 @@ int apco_assemble(const apco_cloud *C, double *w, double *diag) {
    characteristic function of the node's own cell, edge h_c).  Reading: the
    Taylor terms carry 1/alpha!, so a^T d rho~ is the cell average of the Taylor
    polynomial; odd moments vanish and a_alpha = prod_d mu(alpha_d) / alpha! with
-   mu(e) = (h_c/2)^e / (e + 1). */
-int apco_density_rows(const apco_cloud *C, double *bw, double *bdiag) {
-  int p = C->p;
+   mu(e) = (h_c/2)^e / (e + 1).  The row is b_j = sum_alpha a_alpha X_alpha,j / h^|alpha|
+   over the unknowns of the fit of order ko (moments of order <= ko); the
+   diagonal is 1 - sum_j b_j (the row reproduces constants). */
+static void density_row(const double *X, int m, int ko, double hc, double hp, double *b,
+                        double *bdiag) {
   int32_t al[3 * MAXP];
-  apco_monomials(C->P.order, al);
+  int pk = apco_num_unknowns(ko);
+  apco_monomials(ko, al);
+  double coef[MAXP];
+  for (int i = 0; i < pk; i++) {
+    const int32_t *a = &al[3 * i];
+    coef[i] = 0.0;
+    if ((a[0] | a[1] | a[2]) & 1) continue;
+    double mom = 1.0;
+    for (int d = 0; d < 3; d++) mom *= ipow(hc / 2.0, a[d]) / (double)(a[d] + 1) / factorial(a[d]);
+    coef[i] = mom / ipow(hp, a[0] + a[1] + a[2]);
+  }
+  double s = 0.0;
+  for (int j = 0; j < m; j++) {
+    double v = 0.0;
+    for (int i = 0; i < pk; i++) v += coef[i] * X[i * m + j];
+    b[j] = v;
+    s += v;
+  }
+  *bdiag = 1.0 - s;
+}
+
+/* Stability bound of a density row (reading; the paper states none): the row is
+   strictly diagonally dominant with sum_j |b_j| <= THETA_B * b_ii.  Then B has
+   a positive diagonal and the Jacobi iteration matrix of B has infinity norm at
+   most THETA_B, so the density solve converges at a rate independent of n. */
+#define THETA_B 0.5
+static int density_row_ok(const double *b, int m, double bdiag) {
+  double sa = 0.0;
+  for (int j = 0; j < m; j++) sa += fabs(b[j]);
+  return sa <= THETA_B * bdiag;
+}
+
+/* Density rows of every interior node, with the stability rule (reading): the
+   row of the node's own fit order k_y is kept when it meets the bound; else, for
+   an order-4 row, the order-2 row of the same stencil (the fit restricted to the
+   9 unknowns of order 1 and 2, moments a_{2 e_d} only); else the identity row
+   (rho~ = rho_M at that node: the cell average read as the centre value, which
+   the vanishing odd moments make second-order accurate).  ord (may be NULL)
+   receives the order of each row kept: k_y, 2 or 0. */
+static int density_rows_ord(const apco_cloud *C, double *bw, double *bdiag, int8_t *ord) {
   static double X[MAXP * MAXM];
-  (void)p;
+  double b[MAXM];
   for (int64_t y = 0; y < C->n; y++) {
     int m, pk;
     double hp;
     int rc = node_fit(C, y, X, &m, &hp, &pk);
     if (rc) return rc;
     double hc = C->P.L / ldexp(1.0, C->cells[C->node_cell[y]].level);
-    double coef[MAXP];
-    for (int i = 0; i < pk; i++) {
-      const int32_t *a = &al[3 * i];
-      coef[i] = 0.0;
-      if ((a[0] | a[1] | a[2]) & 1) continue;
-      double mom = 1.0;
-      for (int d = 0; d < 3; d++) mom *= ipow(hc / 2.0, a[d]) / (double)(a[d] + 1) / factorial(a[d]);
-      coef[i] = mom / ipow(hp, a[0] + a[1] + a[2]);
+    int ko = C->node_order[y];
+    double bd;
+    density_row(X, m, ko, hc, hp, b, &bd);
+    if (!density_row_ok(b, m, bd) && ko == 4) {
+      /* the order-2 fit of the same stencil */
+      int32_t a = C->st_off[y];
+      double dx[MAXM], dy[MAXM], dz[MAXM], h2, ratio2;
+      for (int j = 0; j < m; j++) {
+        int32_t v = C->st[a + j];
+        dx[j] = (double)(C->crd[3 * v] - C->crd[3 * y]);
+        dy[j] = (double)(C->crd[3 * v + 1] - C->crd[3 * y + 1]);
+        dz[j] = (double)(C->crd[3 * v + 2] - C->crd[3 * y + 2]);
+      }
+      rc = wls_core(2, m, dx, dy, dz, X, &h2, &ratio2);
+      if (rc) return rc;
+      ko = 2;
+      density_row(X, m, 2, hc, hp, b, &bd);
     }
-    double s = 0.0;
+    if (!density_row_ok(b, m, bd)) {
+      ko = 0;
+      for (int j = 0; j < m; j++) b[j] = 0.0;
+      bd = 1.0;
+    }
     int32_t a0 = C->st_off[y];
-    for (int j = 0; j < m; j++) {
-      double v = 0.0;
-      for (int i = 0; i < pk; i++) v += coef[i] * X[i * m + j];
-      bw[a0 + j] = v;
-      s += v;
-    }
-    bdiag[y] = 1.0 - s;
+    for (int j = 0; j < m; j++) bw[a0 + j] = b[j];
+    bdiag[y] = bd;
+    if (ord) ord[y] = (int8_t)ko;
   }
   return 0;
+}
+
+int apco_density_rows(const apco_cloud *C, double *bw, double *bdiag) {
+  return density_rows_ord(C, bw, bdiag, NULL);
+}
+
+int apco_density_orders(const apco_cloud *C, int8_t *ord) {
+  int64_t nnz = C->st_off[C->n];
+  double *bw = malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+  double *bd = malloc(sizeof(double) * (size_t)(C->n > 0 ? C->n : 1));
+  if (!bw || !bd) {
+    free(bw);
+    free(bd);
+    return APCO_ENOMEM;
+  }
+  int rc = density_rows_ord(C, bw, bd, ord);
+  free(bw);
+  free(bd);
+  return rc;
 }
 
 /* rho_M(y_j) = (1/h_c^3) sum_{particles in cell j} q_i (eq. density_apcloud with

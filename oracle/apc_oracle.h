@@ -94,8 +94,14 @@ int apco_wls_fit(int order, int m, const double *delta, double *X, double *h, do
 /* Poisson rows: off-diagonal weights w (nnz, aligned with the stencil CSR) and the
    diagonal (n), so that (L f)_i = diag_i f_i + sum_j w_ij f_j. */
 int apco_assemble(const apco_cloud *C, double *w, double *diag);
-/* Density rows B (eq. density_linear_system), same layout. */
+/* Density rows B (eq. density_linear_system), same layout, with the stability
+   rule: a row is kept when sum_j |b_j| <= 0.5 b_ii; an order-4 row that fails
+   is replaced by the order-2 row of the same stencil, and a row that still fails
+   by the identity row. */
 int apco_density_rows(const apco_cloud *C, double *bw, double *bdiag);
+/* Order of every interior node's density row (n int8): the node's fit order, 2
+   (order-4 row replaced by the order-2 row of the same stencil) or 0 (identity). */
+int apco_density_orders(const apco_cloud *C, int8_t *ord);
 /* NGP deposit (Sec. 5.1 kernel choice): rho_M for all n+nb nodes (boundary node takes
    its owner's value).  q may be NULL: every particle then carries 1/N. */
 int apco_deposit(const apco_cloud *C, const double *q, double *rho_M);

@@ -51,6 +51,7 @@ def _load():
     lib.apco_get_nodes.argtypes = [P] * 11
     lib.apco_node_coords.argtypes = [P, P]
     lib.apco_node_orders.argtypes = [P, P]
+    lib.apco_density_orders.argtypes = [P, P]
     lib.apco_get_cells.argtypes = [P] * 5
     lib.apco_ring1.argtypes = [P, P, P, ct.c_int64]
     lib.apco_wls_fit.argtypes = [ct.c_int, ct.c_int, P, P, P, P]
@@ -219,6 +220,11 @@ class OracleCloud:
     def node_orders(self) -> np.ndarray:
         o = np.zeros(self.n, np.int8)
         _check(self.lib.apco_node_orders(self.h, _ptr(o)), "node_orders")
+        return o
+
+    def density_orders(self) -> np.ndarray:
+        o = np.zeros(self.n, np.int8)
+        _check(self.lib.apco_density_orders(self.h, _ptr(o)), "density_orders")
         return o
 
     def coords(self) -> np.ndarray:
