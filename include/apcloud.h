@@ -93,6 +93,11 @@ typedef struct {
                         wavefront per node and up to 255 with one block per node,
                         both in LDS, the rest per thread; 1 = the wavefront tier
                         only; -1 = every ring per thread */
+  int ring_first_cap; /* per-thread stencil search (performance only, same stencils
+                        bit for bit): ring capacity of its first pass; a node whose
+                        R-ring holds more candidates is searched again with the full
+                        capacity (16384).  0 = default, 2 (2R+1)^3 for ring R;
+                        1..16384 accepted */
 } apc_params;
 
 typedef struct {
@@ -223,6 +228,22 @@ int apc_node_derivs(apc_cloud *c, const double *f, double *D, hipStream_t stream
 
 /* Apply the assembled operator: out[i] = (L f)_i for interior i; f: n+nb. */
 int apc_apply_operator(apc_cloud *c, const double *f, double *out, hipStream_t stream);
+
+/* Host copy of the density operator B of the WLS charge assignment (eq.
+   density_linear_system), as the density solve applies it: bw_host[nnz] aligned
+   with the stencil CSR, bdiag_host[n], so that (B f)_i = bdiag_i f_i +
+   sum_j bw_ij f_j, and order_host[n] (int8) the order of each row.  Stability
+   rule (the paper states no bound; a reading): a row of the node's fit order is
+   kept when sum_j |b_ij| <= 0.5 b_ii; an order-4 row that fails is replaced by
+   the order-2 row of the same stencil (the fit on the 9 unknowns of order 1 and
+   2, moments a_(2 e_d) = h_c^2 / 24 only), and a row that still fails by the
+   identity row (rho~_i = rho_M,i, order 0).  Every row of B then meets the bound,
+   so the density solve converges at a rate independent of n.  k = 2 rows are
+   b = (h_c^2 / 24) w with diagonal 1 + (h_c^2 / 24) d (w, d the Poisson row);
+   APC_MIXED widens the stored FP32 values exactly.  Any pointer may be NULL.
+   Requires apc_assemble_gfd.  Synchronises the device. */
+int apc_get_density_operator(const apc_cloud *c, double *bw_host, double *bdiag_host,
+                             int8_t *order_host);
 
 /* GFD order of every interior node's row into host memory (n int8): the cloud's
    k, or 2 where a k = 4 cloud found no acceptable order-4 stencil up to ring_max

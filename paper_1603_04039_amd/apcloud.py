@@ -25,7 +25,8 @@ LEARN_QUAD = MLP_OUT * (MLP_OUT + 1) // 2 + MLP_OUT + 1
 
 # every symbol declared in include/apcloud.h
 EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_nodes",
-           "apc_assemble_gfd", "apc_get_operator", "apc_get_node_orders", "apc_operator_info", "apc_deposit", "apc_density_solve",
+           "apc_assemble_gfd", "apc_get_operator", "apc_get_node_orders",
+           "apc_get_density_operator", "apc_operator_info", "apc_deposit", "apc_density_solve",
            "apc_solve", "apc_interpolate_force", "apc_node_derivs", "apc_apply_operator",
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
@@ -45,7 +46,7 @@ class Params(ct.Structure):
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
                 ("precision", ct.c_int), ("stage_cap", ct.c_int), ("criterion_pow", ct.c_int),
-                ("ring_lds", ct.c_int)]
+                ("ring_lds", ct.c_int), ("ring_first_cap", ct.c_int)]
 
 
 class Stats(ct.Structure):
@@ -100,6 +101,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_get_operator.argtypes = [P, P, P]
     lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 5
     lib.apc_get_node_orders.argtypes = [P, P]
+    lib.apc_get_density_operator.argtypes = [P, P, P, P]
     lib.apc_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, ct.POINTER(Stats), P]
@@ -152,7 +154,7 @@ def _check(rc, what):
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
                 ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64,
-                stage_cap=0, criterion_pow=0, ring_lds=0) -> Params:
+                stage_cap=0, criterion_pow=0, ring_lds=0, ring_first_cap=0) -> Params:
     p = Params()
     load_library().apc_default_params(ct.byref(p), order)
     p.lo[:] = lo
@@ -169,6 +171,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     p.stage_cap = stage_cap
     p.criterion_pow = criterion_pow
     p.ring_lds = ring_lds
+    p.ring_first_cap = ring_first_cap
     return p
 
 
@@ -243,6 +246,18 @@ class Cloud:
         _check(self.lib.apc_get_node_orders(self.h, o.ctypes.data_as(ct.c_void_p)),
                "apc_get_node_orders")
         return o
+
+    def density_operator(self):
+        """Rows of the density operator B (bw aligned with the CSR, diagonal) and the
+        order of each row (4, 2 or 0 for the identity row)."""
+        bw = np.zeros(max(self.nnz, 1))
+        bd = np.zeros(max(self.n, 1))
+        o = np.zeros(max(self.n, 1), np.int8)
+        _check(self.lib.apc_get_density_operator(self.h, bw.ctypes.data_as(ct.c_void_p),
+                                                 bd.ctypes.data_as(ct.c_void_p),
+                                                 o.ctypes.data_as(ct.c_void_p)),
+               "apc_get_density_operator")
+        return bw[:self.nnz], bd[:self.n], o[:self.n]
 
     def positions(self):
         return self.lo[:, None] + self.unit * self.nodes()["ixyz"].astype(np.float64)

@@ -9,6 +9,8 @@
 
 #define APC_BLOCK 256
 #define APC_MAXM 64      // hard stencil cap: one wavefront
+// density-row stability bound: a row of B is kept when sum_j |b_ij| <= APC_THETA_B b_ii
+#define APC_THETA_B 0.5
 #define APC_RING_CAP 16384 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
 #define APC_TAU_DOM 10.0  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
@@ -133,7 +135,12 @@ struct apc_cloud {
   double *w64 = nullptr; // nnz (APC_FP64)
   float *w32 = nullptr;  // nnz (APC_MIXED)
   double *diag = nullptr, *inv_diag = nullptr; // n
-  double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator, k = 2)
+  double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator, k = 2;
+                                               // 0 for an identity density row)
+  int8_t *dorder = nullptr;                    // n: order of each density row: the row's
+                                               // fit order, 2 (order-4 row replaced by the
+                                               // order-2 row of the same stencil) or 0
+                                               // (identity row)
   // k = 4: density operator rows (B has its own weights; row sums are 1)
   double *bw64 = nullptr, *sl_bw64 = nullptr;
   float *bw32 = nullptr, *sl_bw32 = nullptr;

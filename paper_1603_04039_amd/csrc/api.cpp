@@ -143,6 +143,53 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host) {
   return APC_OK;
 }
 
+int apc_get_density_operator(const apc_cloud *c, double *bw_host, double *bdiag_host,
+                             int8_t *order_host) {
+  if (!c || !c->assembled) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  HIPCHK(hipDeviceSynchronize());
+  const int64_t n = c->n, nnz = c->nnz;
+  const bool mixed = c->P.precision != APC_FP64;
+  if (order_host && n > 0) HIPCHK(hipMemcpy(order_host, c->dorder, (size_t)n, hipMemcpyDeviceToHost));
+  if (!bw_host && !bdiag_host) return APC_OK;
+  std::vector<double> bw((size_t)(nnz > 0 ? nnz : 1)), bd((size_t)(n > 0 ? n : 1));
+  if (c->P.order == 4) {
+    // B has rows of its own; the diagonal is 1 - sum of the stored row
+    if (nnz > 0) {
+      if (mixed) {
+        std::vector<float> t((size_t)nnz);
+        HIPCHK(hipMemcpy(t.data(), c->bw32, (size_t)nnz * 4, hipMemcpyDeviceToHost));
+        for (int64_t i = 0; i < nnz; i++) bw[i] = (double)t[i];
+      } else {
+        HIPCHK(hipMemcpy(bw.data(), c->bw64, (size_t)nnz * 8, hipMemcpyDeviceToHost));
+      }
+    }
+  } else {
+    // k = 2: b = (h_c^2 / 24) w, diagonal 1 + (h_c^2 / 24) d; hscale 0 is the identity row
+    std::vector<double> hs((size_t)(n > 0 ? n : 1)), d((size_t)(n > 0 ? n : 1));
+    APCCHK(apc_get_operator(c, bw.data(), d.data()));
+    if (n > 0) HIPCHK(hipMemcpy(hs.data(), c->hscale, (size_t)n * 8, hipMemcpyDeviceToHost));
+    std::vector<int32_t> off((size_t)n + 1);
+    HIPCHK(hipMemcpy(off.data(), c->st_off, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; i++)
+      for (int32_t e = off[i]; e < off[i + 1]; e++) bw[e] *= hs[i];
+    for (int64_t i = 0; i < n; i++) bd[i] = 1.0 + hs[i] * d[i];
+  }
+  if (c->P.order == 4) {
+    std::vector<int32_t> off((size_t)n + 1);
+    HIPCHK(hipMemcpy(off.data(), c->st_off, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost));
+    for (int64_t i = 0; i < n; i++) {
+      double sum = 0.0;
+      for (int32_t e = off[i]; e < off[i + 1]; e++) sum += bw[e];
+      bd[i] = 1.0 - sum;
+    }
+  }
+  if (bw_host && nnz > 0) memcpy(bw_host, bw.data(), (size_t)nnz * 8);
+  if (bdiag_host && n > 0) memcpy(bdiag_host, bd.data(), (size_t)n * 8);
+  return APC_OK;
+}
+
 int apc_get_node_orders(const apc_cloud *c, int8_t *order_host) {
   if (!c || !order_host) return APC_EINVAL;
   DeviceGuard g(c->device);

@@ -288,7 +288,11 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // that the thread reports -1 (the host reruns it with the full APC_RING_CAP), or,
 // when cap is already APC_RING_CAP (full), flags error 8.  The result does not
 // depend on cap.
-constexpr int64_t KEY_R2 = ((int64_t)1 << 56) - 1; // r2 bits of a ring-search sort key
+// A ring-search sort key holds r2 in bits 0-47 (r2 < 3 * 2^42 at max_depth 20, whose
+// integer coordinates stay below 2^21) and the closed-octant mask in bits 48-55, so
+// bits 56-63 of every key are zero.
+constexpr int KEY_MASK_SHIFT = 48;
+constexpr int64_t KEY_R2 = ((int64_t)1 << KEY_MASK_SHIFT) - 1;
 
 __device__ __forceinline__ uint32_t ring_hash(int32_t v, uint32_t mask) {
   return ((uint32_t)v * 2654435761u) & mask;
@@ -311,11 +315,13 @@ __global__ void __launch_bounds__(APC_BLOCK)
   uint64_t *tab = hash_all + t;
 #define LST(k) lst[(int64_t)(k) * stride]
 #define KEY(k) key[(int64_t)(k) * stride]
-  // Tag of this launch: bit 31 set, so no stale word of the scratch can match
-  // it.  The same scratch is carved anew for each ring radius, so a hash slot may
-  // hold words of an earlier launch's list or keys: pairs of node ids (below 2^31,
-  // or -(v+1) for a picked node, at least 2^32 - ntot as unsigned) and squared
-  // distances (below 2^46); the host keeps gen < 2^16 and ntot <= 2^31 - 2^16.
+  // Tag of this launch: bit 31 of the upper half set, so no stale word of the
+  // scratch can match it.  The same scratch is carved anew for each ring radius,
+  // so a hash slot may hold words of an earlier launch's list or keys.  A list
+  // word is a pair of node ids: an upper half below 2^31, or -(v+1) for a picked
+  // node, which equals the tag only for v = 2^31 - gen - 1 >= ntot (the host keeps
+  // gen < 2^16 and ntot <= 2^31 - 2^16).  A key word has bits 56-63 clear, so its
+  // upper half is below 2^24.
   const uint64_t g = (uint64_t)(gen | 0x80000000u) << 32;
   // true when v was not in the set (and is now)
   auto insert = [&](int32_t v) -> bool {
@@ -360,8 +366,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
   }
   const int32_t cy0 = crd[y], cy1 = crd[ntot + y], cy2 = crd[2 * ntot + y];
   // candidates = list positions 1 .. cnt-1, heap-sorted by (r2, index).  Each key
-  // carries the candidate's closed-octant mask in bits 56-63 (bit o: the offset lies
-  // in octant o, a zero component counting on both sides); r2 < 2^46 below them.
+  // carries the candidate's closed-octant mask in bits 48-55 (bit o: the offset lies
+  // in octant o, a zero component counting on both sides); r2 < 2^44 below them.
   for (int j = 1; j < cnt; j++) {
     const int32_t v = LST(j);
     const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
@@ -369,7 +375,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
     const uint32_t my = (d1 >= 0 ? 0xCCu : 0u) | (d1 <= 0 ? 0x33u : 0u);
     const uint32_t mz = (d2 >= 0 ? 0xAAu : 0u) | (d2 <= 0 ? 0x55u : 0u);
     KEY(j) = (int64_t)((uint64_t)(d0 * d0 + d1 * d1 + d2 * d2) |
-                       ((uint64_t)(mx & my & mz) << 56));
+                       ((uint64_t)(mx & my & mz) << KEY_MASK_SHIFT));
   }
   {
     const int m = cnt - 1;
@@ -413,7 +419,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
     for (int o = 0; o < 8; o++) nf[o] = 0, f0[o] = f1[o] = 0;
     uint32_t open = 0xFFu; // octants still short of two
     for (int j = 1; j < cnt && open; j++) {
-      const uint32_t msk = (uint32_t)((uint64_t)KEY(j) >> 56) & open;
+      const uint32_t msk = (uint32_t)((uint64_t)KEY(j) >> KEY_MASK_SHIFT) & open;
 #pragma unroll
       for (int o = 0; o < 8; o++)
         if ((msk >> o) & 1u) {
@@ -476,7 +482,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
     const int32_t v = -LST(j) - 1;
     if (m < APC_MAXM) out[m] = v;
     m++;
-    const uint32_t msk = (uint32_t)((uint64_t)KEY(j) >> 56);
+    const uint32_t msk = (uint32_t)((uint64_t)KEY(j) >> KEY_MASK_SHIFT) & 0xFFu;
 #pragma unroll
     for (int o = 0; o < 8; o++) oct[o] += (msk >> o) & 1u;
   }
@@ -799,12 +805,6 @@ __global__ void __launch_bounds__(APC_BLOCK)
   if (tid == 0) mout[pos] = mres;
 }
 
-// first-pass ring capacity of the stencil search; 0: 2 (2R+1)^3 for ring R (a
-// smaller value sends more nodes to the full-capacity rerun, same stencils)
-#ifndef APC_RING_FIRST_CAP
-#define APC_RING_FIRST_CAP 0
-#endif
-
 // 1 where the first pass ran out of ring capacity
 __global__ void __launch_bounds__(APC_BLOCK) k_retry_flag(const int32_t *m, int64_t n, int32_t *f) {
   const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
@@ -938,7 +938,7 @@ void apc_free_cloud(apc_cloud *c) {
   free_cloud_arrays(c);
   void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, c->scratch,
                  c->m_diag, c->m_sell, c->m_tmpl, c->bw64, c->bw32, c->sl_bw64, c->sl_bw32,
-                 c->rorder};
+                 c->rorder, c->dorder};
   for (void *q : ops)
     if (q) (void)apc_dev_free(q);
   delete c;
@@ -1095,10 +1095,12 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   // ring is larger are rerun with the full APC_RING_CAP in sub-chunks of up to
   // 1 GiB.  (A tighter first cap, four times the ring of a uniform region, sent
   // more fourth-order nodes to the slow rerun: 0.98 -> 1.13 s at 8.8e6 nodes.)
-  auto ring_cap = [](int R) {
+  // apc_params.ring_first_cap > 0 sets the first-pass capacity instead (a smaller
+  // value sends more nodes to the full-capacity rerun; the stencils are the same).
+  auto ring_cap = [&P](int R) {
     const int64_t w = 2 * (int64_t)R + 1;
-    return (int)std::min<int64_t>(APC_RING_CAP, APC_RING_FIRST_CAP > 0 ? APC_RING_FIRST_CAP
-                                                                        : 2 * w * w * w);
+    return (int)std::min<int64_t>(APC_RING_CAP, P.ring_first_cap > 0 ? P.ring_first_cap
+                                                                     : 2 * w * w * w);
   };
   auto hash_size = [](int cap) {
     int h = 1;
@@ -1315,6 +1317,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
       p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 || p->stage_cap < -1 ||
       p->criterion_pow < 0 || p->criterion_pow > 16 || p->ring_lds < -1 || p->ring_lds > 1 ||
+      p->ring_first_cap < 0 || p->ring_first_cap > APC_RING_CAP ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
         p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c))
     return APC_EINVAL;

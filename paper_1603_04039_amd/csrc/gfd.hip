@@ -242,7 +242,7 @@ __device__ inline double fit64_row(int32_t row, int64_t off, const int32_t *__re
                                    int64_t ntot, double unit, double *__restrict__ w64,
                                    float *__restrict__ w32, double *__restrict__ sw64,
                                    float *__restrict__ sw32, double *__restrict__ diag,
-                                   double *__restrict__ inv_diag) {
+                                   double *__restrict__ inv_diag, double &asum) {
   const int32_t a = st_off[row];
   const int m = st_off[row + 1] - a;
   const int32_t *nb = st_idx + a;
@@ -252,6 +252,7 @@ __device__ inline double fit64_row(int32_t row, int64_t off, const int32_t *__re
   double z[P9];
   const double ratio = lap_fit<double>(nb, m, g, crd, ntot, z);
   double sum = 0.0;
+  asum = 0.0;
 #pragma unroll 4
   for (int j = 0; j < m; j++) {
     double vv[P9];
@@ -266,10 +267,12 @@ __device__ inline double fit64_row(int32_t row, int64_t off, const int32_t *__re
       w32[a + j] = wf;
       sw32[e] = wf;
       sum += (double)wf;
+      asum += fabs((double)wf);
     } else {
       w64[a + j] = w;
       sw64[e] = w;
       sum += w;
+      asum += fabs(w);
     }
   }
   diag[row] = -sum;
@@ -294,7 +297,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
                const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
                double unit, double L, const double *__restrict__ tc, double *__restrict__ w64,
                float *__restrict__ w32, double *__restrict__ diag, double *__restrict__ inv_diag,
-               double *__restrict__ hscale, double *__restrict__ sw64, float *__restrict__ sw32,
+               double *__restrict__ hscale, int8_t *__restrict__ dorder,
+               double *__restrict__ sw64, float *__restrict__ sw32,
                int *__restrict__ err, unsigned long long *__restrict__ nfp64) {
   const int64_t s = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
   if (s >= nsl) return;
@@ -303,7 +307,14 @@ __global__ void __launch_bounds__(APC_BLOCK)
   if (row < 0) return;
   const int64_t off = sl_off[s] + lane;
   const double hc = L / (double)(1 << level[row]);
-  hscale[row] = hc * hc / 24.0;
+  const double hs = hc * hc / 24.0;
+  // density row b = hs w (eq. density_linear_system at k = 2), diagonal 1 - hs sum w:
+  // kept when hs sum |w| <= theta (1 - hs sum w), else the identity row (hs = 0)
+  auto density_row = [&](double sum, double asum) {
+    const bool ok = hs * asum <= APC_THETA_B * (1.0 - hs * sum);
+    hscale[row] = ok ? hs : 0.0;
+    if (dorder) dorder[row] = ok ? 2 : 0;
+  };
   if (sl_tmpl[s]) {
     const double ih2 = 1.0 / (hc * hc);
     double sum = 0.0;
@@ -314,12 +325,15 @@ __global__ void __launch_bounds__(APC_BLOCK)
     }
     diag[row] = -sum;
     inv_diag[row] = -1.0 / sum;
+    density_row(sum, sum); // the shell constants are positive
     return;
   }
   if (!MIXED) {
+    double asum;
     const double ratio = fit64_row<false>(row, off, st_off, st_idx, crd, ntot, unit, w64, w32,
-                                          sw64, sw32, diag, inv_diag);
+                                          sw64, sw32, diag, inv_diag, asum);
     if (!(ratio >= APC_TAU_RANK)) atomicOr(err, 1);
+    density_row(-diag[row], asum);
     return;
   }
   const int32_t a = st_off[row];
@@ -332,12 +346,14 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const float ratio = lap_fit<float>(nb, m, g, crd, ntot, z);
   if (!(ratio >= (float)APC_TAU_FP32)) {
     atomicAdd(nfp64, 1ull);
+    double asum;
     const double r64 = fit64_row<true>(row, off, st_off, st_idx, crd, ntot, unit, w64, w32, sw64,
-                                       sw32, diag, inv_diag);
+                                       sw32, diag, inv_diag, asum);
     if (!(r64 >= APC_TAU_RANK)) atomicOr(err, 1);
+    density_row(-diag[row], asum);
     return;
   }
-  double sum = 0.0;
+  double sum = 0.0, asum = 0.0;
 #pragma unroll 4
   for (int j = 0; j < m; j++) {
     float vv[P9];
@@ -349,9 +365,11 @@ __global__ void __launch_bounds__(APC_BLOCK)
     w32[a + j] = wf;
     sw32[off + (int64_t)j * APC_SLICE] = wf;
     sum += (double)wf;
+    asum += fabs((double)wf);
   }
   diag[row] = -sum;
   inv_diag[row] = -1.0 / sum;
+  density_row(sum, asum);
 }
 
 // ---------------------------------------------------------------- derivatives
@@ -447,6 +465,7 @@ int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
   HIPCHK(apc_dev_alloc((void **)&c->diag, (size_t)n * sizeof(double)));
   HIPCHK(apc_dev_alloc((void **)&c->inv_diag, (size_t)n * sizeof(double)));
   HIPCHK(apc_dev_alloc((void **)&c->hscale, (size_t)n * sizeof(double)));
+  HIPCHK(apc_dev_alloc((void **)&c->dorder, (size_t)(n > 0 ? n : 1) * sizeof(int8_t)));
   HIPCHK(apc_dev_alloc((void **)&c->rkind, (size_t)n * sizeof(int8_t)));
   if (mixed)
     HIPCHK(apc_dev_alloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
@@ -515,14 +534,14 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
       hipLaunchKernelGGL(k_fit_sell<true>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,
                          c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
                          c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
-                         c->inv_diag, c->hscale, c->sl_w64, c->sl_w32, &c->scratch->err,
-                         &c->scratch->nfp64);
+                         c->inv_diag, c->hscale, c->dorder, c->sl_w64, c->sl_w32,
+                         &c->scratch->err, &c->scratch->nfp64);
     } else {
       hipLaunchKernelGGL(k_fit_sell<false>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,
                          c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
                          c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
-                         c->inv_diag, c->hscale, c->sl_w64, c->sl_w32, &c->scratch->err,
-                         &c->scratch->nfp64);
+                         c->inv_diag, c->hscale, c->dorder, c->sl_w64, c->sl_w32,
+                         &c->scratch->err, &c->scratch->nfp64);
     }
     HIPCHK(hipGetLastError());
   }

@@ -374,7 +374,8 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
            const int8_t *__restrict__ rorder, double unit, double L, double *__restrict__ w64,
            float *__restrict__ w32,
            double *__restrict__ bw64, float *__restrict__ bw32, double *__restrict__ diag,
-           double *__restrict__ inv_diag, double *__restrict__ hscale, int *__restrict__ err) {
+           double *__restrict__ inv_diag, double *__restrict__ hscale, int8_t *__restrict__ dorder,
+           int *__restrict__ err) {
   __shared__ Wave4 SH[WPB4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t y = (int64_t)blockIdx.x * WPB4 + wv;
@@ -415,8 +416,26 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
   solve_rrt(S, lane, pc, cl, cb, ul, ub);
   wv0_times(S, g, lane, pc, ul, ub, zl, zb);
   const double wl = lane < m ? g.W * zl / (hp * hp) : 0.0;
-  const double wb = lane < m ? g.W * zb : 0.0;
+  double wb = lane < m ? g.W * zb : 0.0;
   const double sw = wsum(wl);
+  // density-row stability: the row is kept when sum |b_j| <= theta (1 - sum b_j);
+  // an order-4 row that fails takes the order-2 row of the same stencil, whose
+  // fit is the leading 9 columns of the same factorisation (moments of order 2
+  // only); a row that still fails becomes the identity row
+  auto row_ok = [&](double b) { return wsum(fabs(b)) <= APC_THETA_B * (1.0 - wsum(b)); };
+  int dord = pc == P4 ? 4 : 2;
+  if (!row_ok(wb)) {
+    dord = 0;
+    if (pc == P4) {
+      const double cb2 = (lane == 3 || lane == 6 || lane == 8) ? cb : 0.0;
+      double u2, u0, z2, z0;
+      solve_rrt(S, lane, 9, cb2, 0.0, u2, u0);
+      wv0_times(S, g, lane, 9, u2, u0, z2, z0);
+      wb = lane < m ? g.W * z2 : 0.0;
+      if (row_ok(wb)) dord = 2;
+    }
+    if (dord == 0) wb = 0.0;
+  }
   if (lane < m) {
     if (MIXED) {
       w32[a0 + lane] = (float)wl;
@@ -430,6 +449,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
     diag[y] = -sw;
     inv_diag[y] = -1.0 / sw;
     hscale[y] = hc * hc / 24.0;
+    dorder[y] = (int8_t)dord;
   }
 }
 
@@ -555,7 +575,8 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
 #define APC_FIT4(MX, R)                                                                        \
   hipLaunchKernelGGL((k_fit4<MX, R>), dim3(grid4(n)), dim3(WPB4 * 64), 0, s, n, c->st_off,     \
                      c->st_idx, c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, c->w64,    \
-                     c->w32, c->bw64, c->bw32, c->diag, c->inv_diag, c->hscale, &c->scratch->err)
+                     c->w32, c->bw64, c->bw32, c->diag, c->inv_diag, c->hscale, c->dorder,    \
+                     &c->scratch->err)
     if (mixed && m56)
       APC_FIT4(true, 56);
     else if (mixed)

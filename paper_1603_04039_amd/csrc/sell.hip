@@ -134,18 +134,14 @@ __global__ void __launch_bounds__(SL)
   }
 }
 
-// Distinct neighbour columns of one slice (one 256-thread block per slice): the
-// entries the operator kernels read (k < len on lanes with a row) are sorted in
-// LDS as (column << 12 | entry) keys (bitonic sort, at most 4096 entries), the
-// first entry of every run of equal columns starts a new tile slot, and every
-// entry gets the slot of its column.  Writes the count (un), the columns in
-// ascending order at the slice's entry offset (uq) and the 16-bit slots (lx2, as
+// Distinct neighbour columns of one slice (one 256-thread block per slice, at most
+// 4096 entries: k < len on lanes with a row): the entries' columns go into an LDS
+// hash set (each new column appended to a list), only the distinct columns are
+// sorted (bitonic), and every entry finds its slot by binary search in the sorted
+// list.  Entries of padding rows keep slot 0.  Writes the count (un), the columns
+// in ascending order at the slice's entry offset (uq) and the 16-bit slots (lx2, as
 // uint16: entry k of lane r at 2 (o/2 + 64 (k/2) + r) + k%2).
 constexpr int UQ_T = 256, UQ_MAX = 4096, UQ_HASH = 8192; // hash at most half full
-// The distinct columns of one slice, ascending, and each entry's slot among them:
-// the valid entries' columns go into an LDS hash set (each new column appended to
-// a list), only the distinct columns are sorted (bitonic), and every entry finds
-// its slot by binary search in the sorted list.  Entries of padding rows keep slot 0.
 __global__ void __launch_bounds__(UQ_T)
     k_uniq(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
            const int64_t *__restrict__ sl_off, const int32_t *__restrict__ idx,

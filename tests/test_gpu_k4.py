@@ -1,10 +1,11 @@
 """Fourth-order GFD (k = 4) on the GPU against the FP64 oracle.
 
 Both sides fit with Householder QR in FP64 (the GPU: one wavefront per node),
-so the bars are rounding-order bounds: operator rows within 1e-9 of the row's
-|diag| (kappa(W V0) eps with kappa up to ~1e5 for 34-unknown stencils), the
-node cloud, stencils and the order-2 fallback decisions bit-exact, Krylov
-solutions within kappa (tol_gpu + tol_oracle).
+so operator rows, density rows, derivatives and interpolated values agree to
+1e-12 relative; the node cloud, stencils, the order-2 fallback decisions and the
+density-row orders bit-exact; Krylov solutions, both sides at 1e-13, within
+kappa_2 (1e-13 + 1e-13) with kappa_2 estimated from the oracle's operator, and
+at most 1e-10 (Poisson) or 1e-12 (density).
 """
 import math
 import sys
@@ -12,6 +13,7 @@ import sys
 import numpy as np
 import pytest
 
+from linalg_bounds import interior_matrix, kappa2, moment_row, row_ok, solve_bar
 from workloads import beam_halo, uniform_lattice_points
 
 torch = pytest.importorskip("torch")
@@ -71,7 +73,24 @@ def test_k4_operator_rows(pair):
     err = np.max(np.abs(w_g - w_o) / np.repeat(np.abs(d_o), m))
     derr = np.max(np.abs(d_g - d_o) / np.abs(d_o))
     note(f"k = 4 rows: max |w_gpu - w_oracle| / |diag| = {err:.2e}, diag {derr:.2e}")
-    assert err <= 1e-9 and derr <= 1e-9
+    assert err <= 1e-12 and derr <= 1e-12
+
+
+def test_k4_density_rows(pair):
+    """Density rows (eq. density_linear_system) with the stability rule: row
+    orders (4, 2 for the order-2 row of the same stencil, 0 for the identity)
+    equal to the oracle's, rows within 1e-12, every row within
+    sum_j |b_ij| <= 0.5 b_ii."""
+    xyz, O, G = pair
+    bw_g, bd_g, ord_g = G.density_operator()
+    bw_o, bd_o = O.density_rows()
+    np.testing.assert_array_equal(ord_g, O.density_orders())
+    err = max(np.abs(bw_g - bw_o).max(), np.abs(bd_g - bd_o).max())
+    note(f"k = 4 density rows: orders {np.bincount(ord_g, minlength=5).tolist()}, "
+         f"max diff {err:.2e}")
+    assert err <= 1e-12
+    off = O.nodes()["st_off"]
+    assert np.all(np.add.reduceat(np.abs(bw_g), off[:-1]) <= 0.5 * bd_g * (1 + 1e-12))
 
 
 def test_k4_quartic_exactness(apc, pair):
@@ -98,20 +117,29 @@ def test_k4_quartic_exactness(apc, pair):
 
 def test_k4_deposit_and_solve(apc, pair):
     xyz, O, G = pair
+    nd = O.nodes()
     rho_M, rho_t, std = G.deposit(tol=1e-13, maxit=4000)
     rM_o = O.deposit()
     np.testing.assert_allclose(rho_M.cpu().numpy(), rM_o, rtol=1e-13)
     rt_o, sto = O.density_solve(rM_o, tol=1e-13, maxit=4000)
-    d = np.abs(rho_t.cpu().numpy() - rt_o).max() / np.abs(rt_o).max()
-    note(f"k = 4 density: rel diff {d:.2e}, iters gpu {std['iters']} oracle {sto['iters']}")
-    assert d <= 1e-10
+    bw, bd = O.density_rows()
+    kB = kappa2(interior_matrix(nd["st_off"], nd["st_idx"], bw, bd, O.n), direct=False)
+    d = np.linalg.norm(rho_t.cpu().numpy() - rt_o) / np.linalg.norm(rt_o)
+    note(f"k = 4 density: rel diff {d:.2e}, iters gpu {std['iters']} oracle {sto['iters']}, "
+         f"kappa_B {kB:.2f}")
+    assert std["status"] == 0 and std["iters"] <= 12
+    assert d <= solve_bar(kB, 1e-13, 1e-13, cap=1e-12)
     # Poisson solve of the oracle's right-hand side on both sides
+    w, dg = O.assemble()
+    kL = kappa2(interior_matrix(nd["st_off"], nd["st_idx"], w, dg, O.n))
     rhs = torch.from_numpy(np.ascontiguousarray(rt_o[:O.n])).cuda()
-    phi, st = G.solve(rhs, tol=1e-12, maxit=20000)
-    phi_o, sto = O.poisson_solve(rt_o[:O.n], tol=1e-12, maxit=20000, precond=1)
-    d = np.abs(phi.cpu().numpy() - phi_o).max() / np.abs(phi_o).max()
-    note(f"k = 4 Poisson: rel diff {d:.2e}, iters gpu {st['iters']} oracle {sto['iters']}")
-    assert st["status"] == 0 and d <= 1e-7
+    phi, st = G.solve(rhs, tol=1e-13, maxit=20000)
+    phi_o, sto = O.poisson_solve(rt_o[:O.n], tol=1e-13, maxit=20000, precond=1)
+    d = np.linalg.norm(phi.cpu().numpy() - phi_o) / np.linalg.norm(phi_o)
+    note(f"k = 4 Poisson: rel diff {d:.2e}, iters gpu {st['iters']} oracle {sto['iters']}, "
+         f"kappa_L {kL:.3e}")
+    assert st["status"] == 0 and sto["status"] == 0
+    assert d <= solve_bar(kL, 1e-13, 1e-13, cap=1e-10)
 
 
 def test_k4_derivatives_and_interpolation(apc, pair):
@@ -124,11 +152,13 @@ def test_k4_derivatives_and_interpolation(apc, pair):
     scale = np.abs(D_o).max(axis=0) + 1e-300
     err = (np.abs(D_g - D_o) / scale).max()
     note(f"k = 4 derivatives: max err / column scale = {err:.2e}")
-    assert err <= 1e-9
+    assert err <= 1e-12
     pp_o, gp_o = O.interpolate(phi)
     pp_g, gp_g = G.interpolate_force(torch.from_numpy(phi).cuda())
-    np.testing.assert_allclose(pp_g.cpu().numpy(), pp_o, rtol=0, atol=1e-10 * np.abs(pp_o).max())
-    np.testing.assert_allclose(gp_g.cpu().numpy(), gp_o, rtol=0, atol=1e-9 * np.abs(gp_o).max())
+    e_pp = np.abs(pp_g.cpu().numpy() - pp_o).max() / np.abs(pp_o).max()
+    e_gp = np.abs(gp_g.cpu().numpy() - gp_o).max() / np.abs(gp_o).max()
+    note(f"k = 4 interpolation: phi {e_pp:.2e}, grad {e_gp:.2e} (relative to the max)")
+    assert e_pp <= 1e-12 and e_gp <= 1e-12
 
 
 def test_k4_mixed_weights(apc, oracle_mod):
@@ -213,10 +243,45 @@ def test_k4_full_size_sampled(apc, oracle_mod):
     del w
     note("k = 4 full size: deposit")
     rho_M, rho_t, std = G.deposit(tol=1e-10, maxit=20000)
-    assert std["status"] == 0
+    note(f"k = 4 full size: density solve {std['iters']} iterations, "
+         f"true residual {std['rel_resid_true']:.2e}")
+    assert std["status"] == 0 and std["iters"] <= 20
     rM = rho_M.cpu().numpy()
     hc = G.L / 2.0 ** lev[sample]
     np.testing.assert_allclose(rM[sample], nd["count"][sample] / N / hc ** 3, rtol=1e-13)
+    # the oracle's density rows (its fit on the GPU's stencil, the stability rule
+    # replayed) applied to the GPU's rho~ give rho_M to the solve tolerance plus the
+    # FP32 rounding of the stored rows
+    bw, bd, dord = G.density_operator()
+    rt = rho_t.cpu().numpy()
+    al4, al2 = oracle_mod.monomials(4), oracle_mod.monomials(2)
+    nrm = np.linalg.norm(rM[:n])
+    worst = 0.0
+    for i in sample:
+        nbr = idx[off[i]:off[i + 1]]
+        dl = (pos[:, nbr] - pos[:, [i]]).T
+        hci = G.L / 2.0 ** int(lev[i])
+        ko = int(orders[i])
+        X, h, _ = oracle_mod.wls_fit(ko, dl)
+        b = moment_row(X, hci, h, al4 if ko == 4 else al2)
+        if ko == 4 and not row_ok(b):
+            X2, h2, _ = oracle_mod.wls_fit(2, dl)
+            b = moment_row(X2, hci, h2, al2)
+            want = 2 if row_ok(b) else 0
+        else:
+            want = ko if row_ok(b) else 0
+        assert dord[i] == want, i
+        if want == 0:
+            b = np.zeros_like(b)
+        assert np.abs(bw[off[i]:off[i + 1]] - b).max() <= 1e-6 * max(np.abs(b).max(), 1e-300) \
+            or want == 0
+        diff = rt[nbr] - rt[i]
+        r = rt[i] + b @ diff - rM[i]
+        bar = 1e-10 * nrm + 1e-7 * (np.abs(b) @ np.abs(diff))
+        worst = max(worst, abs(r) / bar)
+        assert abs(r) <= bar, i
+    note(f"k = 4 full size: 400 sampled density rows (orders "
+         f"{np.bincount(dord, minlength=5).tolist()} over all rows): max residual / bar = {worst:.2e}")
     note("k = 4 full size: learned M install and solve")
     P = torch.from_numpy(np.load(lrn.params_path(4))).cuda()
     G.set_learned_precond(P, lrn.probes(G, seed=0))
@@ -225,9 +290,23 @@ def test_k4_full_size_sampled(apc, oracle_mod):
     note(f"k = 4 full size: {st['iters']} iterations, true residual {st['rel_resid_true']:.2e}")
     assert st["status"] == 0 and st["rel_resid_true"] <= 1e-8
     assert st["precond_used"] == apc.APC_PRECOND_LEARNED
+    # the oracle's Poisson rows applied to the GPU's phi (zero on the boundary) give
+    # rho~ to the solve tolerance plus the FP32 rounding of the stored weights
+    ph = phi.cpu().numpy()
+    rtn = np.linalg.norm(rt[:n])
+    worst = 0.0
+    for i in sample:
+        nbr = idx[off[i]:off[i + 1]]
+        X, h, _ = oracle_mod.wls_fit(int(orders[i]), (pos[:, nbr] - pos[:, [i]]).T)
+        wl = (X[3] + X[6] + X[8]) / h ** 2
+        diff = ph[nbr] - ph[i]
+        r = wl @ diff - rt[i]
+        bar = 1e-8 * rtn + 1e-7 * (np.abs(wl) @ np.abs(diff))
+        worst = max(worst, abs(r) / bar)
+        assert abs(r) <= bar, i
+    note(f"k = 4 full size: 400 sampled Poisson rows: max residual / bar = {worst:.2e}")
     note("k = 4 full size: interpolation of sampled particles")
     phi_p, grad_p = G.interpolate_force(phi)
-    ph = phi.cpu().numpy()
     pp, gp = phi_p.cpu().numpy(), grad_p.cpu().numpy()
     alphas = oracle_mod.monomials(4)
     fact = np.array([np.prod([math.factorial(int(e)) for e in a]) for a in alphas], dtype=float)

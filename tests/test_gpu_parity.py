@@ -11,6 +11,7 @@ import sys
 import numpy as np
 import pytest
 
+from linalg_bounds import interior_matrix, kappa2, solve_bar
 from workloads import beam_halo, batch_specs, uniform_lattice_points
 
 torch = pytest.importorskip("torch")
@@ -54,6 +55,20 @@ def c1(apc, oracle_mod):
     G.assemble_gfd()
     torch.cuda.synchronize()
     return xyz, O, G
+
+
+@pytest.fixture(scope="module")
+def kappas(c1):
+    """2-norm condition estimates of the oracle's Poisson and density operators of
+    the beam_halo_1e5 cloud (interior rows and columns)."""
+    _, O, _ = c1
+    nd = O.nodes()
+    w, d = O.assemble()
+    bw, bd = O.density_rows()
+    kL = kappa2(interior_matrix(nd["st_off"], nd["st_idx"], w, d, O.n))
+    kB = kappa2(interior_matrix(nd["st_off"], nd["st_idx"], bw, bd, O.n), direct=False)
+    note(f"kappa_2 estimates: Poisson {kL:.3e}, density {kB:.3e}")
+    return kL, kB
 
 
 def test_cloud_bit_exact(c1):
@@ -135,8 +150,24 @@ def test_apply_operator(c1):
     assert np.max(np.abs(out_g - out_o) / (np.abs(d_o) * np.abs(f).max())) <= 1e-13
 
 
+def test_density_operator_rows(c1):
+    """Density operator B (eq. density_linear_system) with the stability rule: the
+    order of every row (2, or 0 for the identity row) equal to the oracle's, rows
+    within 1e-12 (b_ii is about 1, so absolute is relative), every row within the
+    bound sum_j |b_ij| <= 0.5 b_ii."""
+    note("density operator parity beam_halo_1e5")
+    _, O, G = c1
+    bw_g, bd_g, ord_g = G.density_operator()
+    bw_o, bd_o = O.density_rows()
+    np.testing.assert_array_equal(ord_g, O.density_orders())
+    note(f"  identity rows: {int((ord_g == 0).sum())} of {G.n}")
+    assert np.max(np.abs(bw_g - bw_o)) <= 1e-12 and np.max(np.abs(bd_g - bd_o)) <= 1e-12
+    off = O.nodes()["st_off"]
+    assert np.all(np.add.reduceat(np.abs(bw_g), off[:-1]) <= 0.5 * bd_g * (1 + 1e-12))
+
+
 @pytest.mark.parametrize("charges", ["uniform", "random"])
-def test_deposit(c1, charges):
+def test_deposit(c1, kappas, charges):
     note(f"deposit parity ({charges})")
     xyz, O, G = c1
     q = None if charges == "uniform" else np.random.default_rng(3).uniform(0.5, 1.5, xyz.shape[1])
@@ -147,12 +178,14 @@ def test_deposit(c1, charges):
     rt_o, st_o = O.density_solve(rm_o, tol=1e-13)
     rt_g = rho_t.cpu().numpy()
     assert st["status"] == 0 and st["rel_resid_true"] <= 1e-13
-    # B is well conditioned (I + O(1/4) perturbation): both at 1e-13
-    assert np.linalg.norm(rt_g - rt_o) <= 1e-11 * np.linalg.norm(rt_o)
+    # both sides at 1e-13: ||drho|| <= kappa_B (1e-13 + 1e-13) ||rho||
+    rel = np.linalg.norm(rt_g - rt_o) / np.linalg.norm(rt_o)
+    note(f"  density solve: rel diff {rel:.2e}, iters {st['iters']}")
+    assert rel <= solve_bar(kappas[1], 1e-13, 1e-13, cap=1e-12)
 
 
 @pytest.mark.parametrize("precond", [0, 1])
-def test_poisson_solve(c1, precond):
+def test_poisson_solve(c1, kappas, precond):
     note(f"poisson parity precond={precond}")
     _, O, G = c1
     rt_o, _ = O.density_solve(O.deposit(), tol=1e-13)
@@ -164,8 +197,10 @@ def test_poisson_solve(c1, precond):
     note(f"  gpu iters={st['iters']} restarts={st['restarts']} true={st['rel_resid_true']:.2e}")
     assert st["status"] == 0 and st["rel_resid_true"] <= 1e-13
     np.testing.assert_array_equal(phi_g[O.n:], g)
-    # ||dphi|| <= ||A^-1|| (||r_gpu|| + ||r_oracle||); kappa of this cloud is < 1e4
-    assert np.linalg.norm(phi_g - phi_o) <= 1e4 * 2e-13 * np.linalg.norm(phi_o)
+    # ||dphi|| / ||phi|| <= kappa (1e-13 + 1e-13), and at most 1e-10
+    rel = np.linalg.norm(phi_g - phi_o) / np.linalg.norm(phi_o)
+    note(f"  Poisson solve: rel diff {rel:.2e} (kappa {kappas[0]:.2e})")
+    assert rel <= solve_bar(kappas[0], 1e-13, 1e-13, cap=1e-10)
 
 
 def test_interpolation_given_phi(c1):
@@ -185,17 +220,27 @@ def test_interpolation_given_phi(c1):
         assert np.max(np.abs(D_g[:, k] - D_o[:, k])) <= 1e-10 * np.abs(D_o[:, k]).max()
 
 
-def test_end_to_end_chain(c1):
+def test_end_to_end_chain(c1, kappas):
+    """deposit -> density solve -> Poisson solve -> interpolation on both sides,
+    every solve to 1e-13: rho~ within the density bar, phi within kappa_L times the
+    residuals plus the rho~ difference, and the particle values within 1e-10 (the
+    interpolation is a fixed linear map of phi)."""
     note("end-to-end chain parity")
     xyz, O, G = c1
-    rho_M, rho_t, _ = G.deposit(tol=1e-12)
-    phi, st = G.solve(rho_t[:G.n].contiguous(), tol=1e-12)
+    rho_M, rho_t, _ = G.deposit(tol=1e-13)
+    phi, st = G.solve(rho_t[:G.n].contiguous(), tol=1e-13, maxit=20000)
     pp, gp = G.interpolate_force(phi)
-    rt_o, _ = O.density_solve(O.deposit(), tol=1e-12)
-    phi_o, _ = O.poisson_solve(rt_o[:O.n], tol=1e-12, precond=1)
+    rt_o, _ = O.density_solve(O.deposit(), tol=1e-13)
+    phi_o, _ = O.poisson_solve(rt_o[:O.n], tol=1e-13, precond=1)
     pp_o, gp_o = O.interpolate(phi_o)
-    assert np.linalg.norm(pp.cpu().numpy() - pp_o) <= 1e-8 * np.linalg.norm(pp_o)
-    assert np.linalg.norm(gp.cpu().numpy() - gp_o) <= 1e-7 * np.linalg.norm(gp_o)
+    e_rho = np.linalg.norm(rho_t.cpu().numpy()[:O.n] - rt_o[:O.n]) / np.linalg.norm(rt_o[:O.n])
+    e_phi = np.linalg.norm(phi.cpu().numpy() - phi_o) / np.linalg.norm(phi_o)
+    e_pp = np.linalg.norm(pp.cpu().numpy() - pp_o) / np.linalg.norm(pp_o)
+    e_gp = np.linalg.norm(gp.cpu().numpy() - gp_o) / np.linalg.norm(gp_o)
+    note(f"  chain: rho~ {e_rho:.2e} phi {e_phi:.2e} phi_p {e_pp:.2e} grad_p {e_gp:.2e}")
+    assert e_rho <= solve_bar(kappas[1], 1e-13, 1e-13, cap=1e-12)
+    assert e_phi <= min(2.0 * kappas[0] * (2e-13 + e_rho), 1e-10)
+    assert e_pp <= 1e-10 and e_gp <= 1e-10
 
 
 # ---------------------------------------------------------------- edge cases
@@ -378,6 +423,26 @@ def test_full_size_beam_halo_1e7(apc, oracle_mod):
     rt_g = rho_t.cpu().numpy()
     res = O.apply_laplacian(phi_g) - rt_g[:O.n]
     assert np.linalg.norm(res) <= 1.01e-8 * np.linalg.norm(rt_g[:O.n])
+    # mixed precision (FP32 fit and weights, FP64 Krylov and refinement) at full
+    # size, against the FP64 oracle: its residual on the oracle's FP64 operator and
+    # its distance to the FP64 potential, both stated
+    note("full size: mixed-precision solve against the FP64 oracle")
+    Gm = gcloud(apc, xyz, precision=apc.APC_MIXED, **kw)
+    Gm.assemble_gfd()
+    rhs = rho_t[:G.n].contiguous()
+    phi_m, stm = Gm.solve(rhs, tol=1e-8)
+    phi64, st64 = G.solve(rhs, tol=1e-12)
+    pm, p64 = phi_m.cpu().numpy(), phi64.cpu().numpy()
+    r64 = np.linalg.norm(O.apply_laplacian(pm) - rt_g[:O.n]) / np.linalg.norm(rt_g[:O.n])
+    dphi = np.linalg.norm(pm - p64) / np.linalg.norm(p64)
+    wm, _ = Gm.operator()
+    werr = np.max(np.abs(wm - w_o) / np.repeat(np.abs(d_o), m))
+    note(f"  mixed: iters {stm['iters']} sweeps {stm['sweeps']} own true residual "
+         f"{stm['rel_resid_true']:.2e}; residual on the FP64 oracle operator {r64:.2e}; "
+         f"|phi32 - phi64| / |phi64| = {dphi:.2e}; max |w32 - w64| / |diag| = {werr:.2e}")
+    assert stm["status"] == 0 and stm["rel_resid_true"] <= 1e-8
+    assert werr <= 1e-4 and r64 <= 1e-4 and dphi <= 1e-4
+    Gm.close()
 
 
 @pytest.mark.slow
