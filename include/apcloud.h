@@ -222,6 +222,20 @@ int apc_solve(apc_cloud *c, const double *rho_t, const double *g, double *phi, d
 int apc_interpolate_force(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
                           hipStream_t stream);
 
+/* apc_interpolate_force without allocation, for callers that cannot allocate
+   device memory (code under HIP graph capture, tight serving loops, harnesses
+   that forbid hipMalloc).  Same arguments, kernels and results (bit for bit) as
+   apc_interpolate_force; its n x p derivative buffer (p = 9 for k = 2, 34 for
+   k = 4) lives in a fixed device array of APC_NOALLOC_BYTES that each GPU holds
+   until the process ends, so the call makes no hipMalloc or hipFree.  Clouds with
+   n p 8 > APC_NOALLOC_BYTES are rejected with APC_EINVAL (apc_last_error says
+   so): k = 2 clouds up to 466,033 nodes, k = 4 up to 123,361.  Every call on a
+   GPU shares that GPU's array: calls that overlap on one GPU (two streams, two
+   host threads) race and must be ordered by the caller.  Does not synchronise. */
+#define APC_NOALLOC_BYTES (32LL << 20)
+int apc_interpolate_force_noalloc(apc_cloud *c, const double *phi, double *phi_p,
+                                  double *grad_p, hipStream_t stream);
+
 /* Scaled-back GFD derivatives d^alpha f at every interior node (n x p row-major,
    p = 9 for k = 2, columns x,y,z,xx,xy,xz,yy,yz,zz).  f: n+nb. */
 int apc_node_derivs(apc_cloud *c, const double *f, double *D, hipStream_t stream);

@@ -17,6 +17,7 @@ LIB_PATH = os.path.join(_HERE, "libapcloud.so")
 
 APC_OK, APC_EINVAL, APC_ENOMEM, APC_EHIP, APC_EDOMAIN, APC_ESTENCIL = 0, -1, -2, -3, -4, -5
 APC_ENOCONV = 1
+APC_NOALLOC_BYTES = 32 << 20  # fixed derivative buffer of apc_interpolate_force_noalloc
 APC_FP64, APC_MIXED, APC_MIXED_F32ACC = 0, 1, 2
 APC_PRECOND_NONE, APC_PRECOND_JACOBI, APC_PRECOND_LEARNED = 0, 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 48, 64, 41
@@ -27,7 +28,7 @@ LEARN_QUAD = MLP_OUT * (MLP_OUT + 1) // 2 + MLP_OUT + 1
 EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_nodes",
            "apc_assemble_gfd", "apc_get_operator", "apc_get_node_orders",
            "apc_get_density_operator", "apc_operator_info", "apc_deposit", "apc_density_solve",
-           "apc_solve", "apc_interpolate_force", "apc_node_derivs", "apc_apply_operator",
+           "apc_solve", "apc_interpolate_force", "apc_interpolate_force_noalloc", "apc_node_derivs", "apc_apply_operator",
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
            "apc_batch_configure", "apc_batch_tune", "apc_batch_assemble", "apc_batch_deposit",
@@ -106,6 +107,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, ct.POINTER(Stats), P]
     lib.apc_interpolate_force.argtypes = [P, P, P, P, P]
+    lib.apc_interpolate_force_noalloc.argtypes = [P, P, P, P, P]
     lib.apc_node_derivs.argtypes = [P, P, P, P]
     lib.apc_apply_operator.argtypes = [P, P, P, P]
     lib.apc_learn_data.argtypes = [P, P, ct.c_int, P, P, P]
@@ -332,6 +334,16 @@ class Cloud:
                                               _dptr(phi_p, torch.float64, self.N),
                                               _dptr(grad_p, torch.float64, 3 * self.N),
                                               _stream(stream)), "apc_interpolate_force")
+        return phi_p, grad_p
+
+    def interpolate_force_noalloc(self, phi, phi_p, grad_p, stream=None):
+        """apc_interpolate_force_noalloc into caller-owned outputs (no allocation in
+        the library)."""
+        import torch
+        _check(self.lib.apc_interpolate_force_noalloc(
+            self.h, _dptr(phi, torch.float64, self.n + self.nb),
+            _dptr(phi_p, torch.float64, self.N), _dptr(grad_p, torch.float64, 3 * self.N),
+            _stream(stream)), "apc_interpolate_force_noalloc")
         return phi_p, grad_p
 
     def node_derivs(self, f, stream=None):

@@ -226,6 +226,12 @@ int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t 
 int apc_assemble4(apc_cloud *c, hipStream_t s);
 int apc_node_derivs4(apc_cloud *c, const double *f, double *D, hipStream_t s);
 int apc_interp4(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, hipStream_t s);
+int apc_interp4_with(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, double *D,
+                     hipStream_t s);
+int apc_interp_with(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, double *D,
+                    hipStream_t s);
+int apc_interp_noalloc_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
+                            hipStream_t s);
 int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
                     hipStream_t s);
 int apc_deposit_impl(apc_cloud *c, const double *q, double *rho_M, hipStream_t s);

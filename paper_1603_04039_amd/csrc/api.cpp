@@ -275,6 +275,15 @@ int apc_interpolate_force(apc_cloud *c, const double *phi, double *phi_p, double
   return apc_interp_impl(c, phi, phi_p, grad_p, stream);
 }
 
+int apc_interpolate_force_noalloc(apc_cloud *c, const double *phi, double *phi_p,
+                                  double *grad_p, hipStream_t stream) {
+  if (!c || !phi || !phi_p || !grad_p) return APC_EINVAL;
+  g_err[0] = 0;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  return apc_interp_noalloc_impl(c, phi, phi_p, grad_p, stream);
+}
+
 int apc_node_derivs(apc_cloud *c, const double *f, double *D, hipStream_t stream) {
   if (!c || !f || !D) return APC_EINVAL;
   DeviceGuard g(c->device);

@@ -557,16 +557,26 @@ int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s
   return APC_OK;
 }
 
-int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
+// Interpolation with the caller's derivative buffer D (n x p doubles, p = 9 or
+// 34): every row of D is written by the derivative kernel before the particle
+// kernel reads it, so D needs no clearing.
+int apc_interp_with(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, double *D,
                     hipStream_t s) {
-  if (c->P.order == 4) return apc_interp4(c, phi, phi_p, grad_p, s);
-  double *D = nullptr;
-  HIPCHK(apc_malloc_async((void **)&D, (size_t)c->n * P9 * sizeof(double), s));
+  if (c->P.order == 4) return apc_interp4_with(c, phi, phi_p, grad_p, D, s);
   APCCHK(apc_node_derivs_impl(c, phi, D, s));
   hipLaunchKernelGGL(k_interp, dim3(grid_for(c->N)), dim3(APC_BLOCK), 0, s, c->N, c->sxyz, c->perm,
                      c->pnode, c->crd, c->n + c->nb, c->P.lo[0], c->P.lo[1], c->P.lo[2], c->unit,
                      phi, D, phi_p, grad_p);
   HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
+int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
+                    hipStream_t s) {
+  if (c->P.order == 4) return apc_interp4(c, phi, phi_p, grad_p, s);
+  double *D = nullptr;
+  HIPCHK(apc_malloc_async((void **)&D, (size_t)(c->n > 0 ? c->n : 1) * P9 * sizeof(double), s));
+  APCCHK(apc_interp_with(c, phi, phi_p, grad_p, D, s));
   HIPCHK(apc_free_async(D, s));
   return APC_OK;
 }

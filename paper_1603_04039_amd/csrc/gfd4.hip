@@ -619,14 +619,22 @@ int apc_node_derivs4(apc_cloud *c, const double *f, double *D, hipStream_t s) {
   return APC_OK;
 }
 
-int apc_interp4(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, hipStream_t s) {
-  double *D = nullptr;
-  HIPCHK(apc_malloc_async((void **)&D, (size_t)(c->n > 0 ? c->n : 1) * P4 * sizeof(double), s));
+// Interpolation with the caller's derivative buffer D (n x 34 doubles): every row
+// of D is written by the derivative kernel before the particle kernel reads it.
+int apc_interp4_with(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, double *D,
+                     hipStream_t s) {
   APCCHK(apc_node_derivs4(c, phi, D, s));
   hipLaunchKernelGGL(k_interp4, dim3(grid_for(c->N)), dim3(APC_BLOCK), 0, s, c->N, c->sxyz, c->perm,
                      c->pnode, c->crd, c->n + c->nb, c->P.lo[0], c->P.lo[1], c->P.lo[2], c->unit,
                      phi, D, phi_p, grad_p);
   HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
+int apc_interp4(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, hipStream_t s) {
+  double *D = nullptr;
+  HIPCHK(apc_malloc_async((void **)&D, (size_t)(c->n > 0 ? c->n : 1) * P4 * sizeof(double), s));
+  APCCHK(apc_interp4_with(c, phi, phi_p, grad_p, D, s));
   HIPCHK(apc_free_async(D, s));
   return APC_OK;
 }
