@@ -98,6 +98,11 @@ typedef struct {
                         R-ring holds more candidates is searched again with the full
                         capacity (16384).  0 = default, 2 (2R+1)^3 for ring R;
                         1..16384 accepted */
+  double tau_dom;     /* stability bound of an order-4 Laplacian row (k = 4; the paper
+                        states none, a reading): the row is accepted when its diagonal
+                        d is negative and sum_j |w_j| <= tau_dom |d|, else the node
+                        searches a larger ring and finally takes an order-2 row;
+                        0 = default 10 */
 } apc_params;
 
 typedef struct {
@@ -111,7 +116,17 @@ typedef struct {
   double ms;             /* device time of the call, milliseconds */
   int precond_used;      /* preconditioner of the final iteration (Jacobi after a fallback) */
   int pad;
+  double rel_resid_fp64ref; /* apc_solve: ||b - A64 x|| / ||b|| with A64 the FP64 fit of the
+                               same stencils.  FP64 mode: rel_resid_true.  Mixed modes: computed
+                               at exit when APC_DIAG_FP64_RESIDUAL is set, else -1 */
+  double spmv_ms;        /* APC_DIAG_KERNEL_TIMES: summed device time of the operator
+                            SpMV launches of the iterations (HIP events on the call's
+                            stream), else 0 */
+  int64_t spmv_launches; /* number of SpMV launches summed in spmv_ms */
 } apc_stats;
+
+#define APC_DIAG_KERNEL_TIMES 1  /* time every operator SpMV of the solves with HIP events */
+#define APC_DIAG_FP64_RESIDUAL 2 /* mixed modes: FP64 reference residual at the end of apc_solve */
 
 /* Fill *p with the defaults above for order k (domain [0,1]^3, c, max_depth left
    as given by the caller afterwards). */
@@ -129,7 +144,7 @@ void apc_default_params(apc_params *p, int order);
    distinct offsets, then the nearest remaining, up to m_cap nodes.  Accepted when
    every closed octant holds a chosen node, m >= p + 1, the weighted V0 has
    min|R_ii| / max|R_ii| >= 1e-6, and (k = 4) the Laplacian row has a negative
-   diagonal d with sum |w_j| <= 10 |d|; otherwise R grows from ring_min to
+   diagonal d with sum |w_j| <= tau_dom |d|; otherwise R grows from ring_min to
    ring_max.  A k = 4 node with no acceptable stencil takes an order-2 row (ring
    2, m_cap 40); past ring_max at order 2 the build fails (APC_ESTENCIL).
    xyz: 3 x N float64, read during the call and copied (sorted) into the
@@ -428,6 +443,17 @@ typedef struct {
 int apc_step(const apc_params *p, double *xyz, double *vel, const double *q, int64_t N,
              double kick, double dt, double tol_density, double tol, int maxit, int precond,
              double *phi_p, double *grad_p, apc_step_stats *st_host, hipStream_t stream);
+
+/* Diagnostics of the cloud's solves (flags, a combination of APC_DIAG_*; 0 = off,
+   the default).  APC_DIAG_KERNEL_TIMES records HIP events on the solve's stream
+   around the two operator SpMVs (k_spmv_v, k_spmv_t) of every iteration and
+   reports their summed device time and count in apc_stats.spmv_ms /
+   spmv_launches (iterations that ran after the solver stopped are not counted);
+   the events add marker packets between kernels.  APC_DIAG_FP64_RESIDUAL makes
+   apc_solve in the mixed modes compute rel_resid_fp64ref once at exit (an FP64
+   refit of every k = 2 row, or the FP64 copy of the k = 4 rows that assembly
+   then also keeps), outside the iteration. */
+int apc_set_diagnostics(apc_cloud *c, int flags);
 
 void apc_destroy(apc_cloud *c);
 const char *apc_strerror(int code);

@@ -366,7 +366,7 @@ static int in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
    negative diagonal d and sum |w_j| <= 10 |d|.  Returns m (>0) on acceptance, 0
    otherwise; the chosen candidates are compacted to the front of cd. */
 #define TAU_RANK 1e-6
-#define TAU_DOM 10.0
+#define TAU_DOM_DEFAULT 10.0
 static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cnt, int m_cap,
                           int order) {
   const int32_t *c0 = &C->crd[3 * y];
@@ -440,7 +440,7 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
   if (!(ratio >= TAU_RANK)) return 0;
   if (order == 4) {
     /* stability of the order-4 Laplacian row: a negative diagonal and off-diagonal
-       weights of total magnitude at most TAU_DOM times the diagonal's (scale-free:
+       weights of total magnitude at most tau_dom times the diagonal's (scale-free:
        h cancels); otherwise the node falls back to an order-2 row */
     double s = 0.0, sa = 0.0;
     for (int j = 0; j < m; j++) {
@@ -448,7 +448,8 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
       s += v;
       sa += fabs(v);
     }
-    if (!(s > 0.0 && sa <= TAU_DOM * s)) return 0;
+    const double tau = C->P.tau_dom > 0.0 ? C->P.tau_dom : TAU_DOM_DEFAULT;
+    if (!(s > 0.0 && sa <= tau * s)) return 0;
   }
   return m;
 }
@@ -487,7 +488,7 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
   if (!(P->order == 2 || P->order == 4) || P->max_depth < 1 || P->max_depth > 20 ||
       !(P->L > 0.0) || !(P->c > 0.0) || P->ring_min < 1 || P->ring_max < P->ring_min ||
       P->m_cap > MAXM || P->m_cap < p + 1 || N < 1 || P->criterion_pow < 0 ||
-      P->criterion_pow > 16)
+      P->criterion_pow > 16 || !(P->tau_dom >= 0.0))
     return APCO_EINVAL;
   apco_cloud *C = calloc(1, sizeof(apco_cloud));
   if (!C) return APCO_ENOMEM;

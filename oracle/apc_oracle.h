@@ -44,6 +44,9 @@ typedef struct {
                         errorbalance_implementation); 4 with k = 2 is the balance
                         of the supraconvergent second-order error bound (Sec. 3.3),
                         h = c N'^(-1/4) */
+  double tau_dom; /* stability bound of order-4 Laplacian rows: accepted when the
+                     diagonal is negative and sum_j |w_j| <= tau_dom |diag|;
+                     0 = the default 10 */
 } apco_params;
 
 typedef struct {

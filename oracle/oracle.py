@@ -28,7 +28,7 @@ class _Params(ct.Structure):
     _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
-                ("criterion_pow", ct.c_int)]
+                ("criterion_pow", ct.c_int), ("tau_dom", ct.c_double)]
 
 
 class _Stats(ct.Structure):
@@ -90,7 +90,7 @@ def _check(rc, what):
 
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
-                ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0):
+                ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0, tau_dom=0.0):
     P = _Params()
     P.lo[:] = lo
     P.L = L
@@ -102,6 +102,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     P.m_cap = m_cap if m_cap is not None else (40 if order == 2 else 56)
     P.poisson_c = poisson_c
     P.criterion_pow = criterion_pow
+    P.tau_dom = tau_dom
     return P
 
 

@@ -20,6 +20,7 @@ APC_ENOCONV = 1
 APC_NOALLOC_BYTES = 32 << 20  # fixed derivative buffer of apc_interpolate_force_noalloc
 APC_FP64, APC_MIXED, APC_MIXED_F32ACC = 0, 1, 2
 APC_PRECOND_NONE, APC_PRECOND_JACOBI, APC_PRECOND_LEARNED = 0, 1, 2
+APC_DIAG_KERNEL_TIMES, APC_DIAG_FP64_RESIDUAL = 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 48, 64, 41
 MLP_NPARAM = MLP_IN * MLP_HID + MLP_HID + MLP_HID * MLP_HID + MLP_HID + MLP_HID * MLP_OUT + MLP_OUT
 LEARN_QUAD = MLP_OUT * (MLP_OUT + 1) // 2 + MLP_OUT + 1
@@ -33,7 +34,7 @@ EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_n
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
            "apc_batch_configure", "apc_batch_tune", "apc_batch_assemble", "apc_batch_deposit",
            "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_destroy", "apc_push",
-           "apc_step", "apc_destroy", "apc_strerror", "apc_last_error"]
+           "apc_step", "apc_set_diagnostics", "apc_destroy", "apc_strerror", "apc_last_error"]
 
 
 class ApcError(RuntimeError):
@@ -47,14 +48,15 @@ class Params(ct.Structure):
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
                 ("precision", ct.c_int), ("stage_cap", ct.c_int), ("criterion_pow", ct.c_int),
-                ("ring_lds", ct.c_int), ("ring_first_cap", ct.c_int)]
+                ("ring_lds", ct.c_int), ("ring_first_cap", ct.c_int), ("tau_dom", ct.c_double)]
 
 
 class Stats(ct.Structure):
     _fields_ = [("iters", ct.c_int), ("restarts", ct.c_int), ("sweeps", ct.c_int),
                 ("status", ct.c_int), ("rel_resid", ct.c_double),
                 ("rel_resid_true", ct.c_double), ("n_fp64_rows", ct.c_int64), ("ms", ct.c_double),
-                ("precond_used", ct.c_int), ("pad", ct.c_int)]
+                ("precond_used", ct.c_int), ("pad", ct.c_int), ("rel_resid_fp64ref", ct.c_double),
+                ("spmv_ms", ct.c_double), ("spmv_launches", ct.c_int64)]
 
     def as_dict(self):
         return {k: getattr(self, k) for k, _ in self._fields_}
@@ -130,6 +132,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_step.argtypes = [ct.POINTER(Params), P, P, P, I64, ct.c_double, ct.c_double,
                              ct.c_double, ct.c_double, ct.c_int, ct.c_int, P, P,
                              ct.POINTER(StepStats), P]
+    lib.apc_set_diagnostics.argtypes = [P, ct.c_int]
     lib.apc_destroy.argtypes = [P]
     lib.apc_destroy.restype = None
     lib.apc_strerror.argtypes = [ct.c_int]
@@ -156,7 +159,8 @@ def _check(rc, what):
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
                 ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64,
-                stage_cap=0, criterion_pow=0, ring_lds=0, ring_first_cap=0) -> Params:
+                stage_cap=0, criterion_pow=0, ring_lds=0, ring_first_cap=0,
+                tau_dom=0.0) -> Params:
     p = Params()
     load_library().apc_default_params(ct.byref(p), order)
     p.lo[:] = lo
@@ -174,6 +178,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     p.criterion_pow = criterion_pow
     p.ring_lds = ring_lds
     p.ring_first_cap = ring_first_cap
+    p.tau_dom = tau_dom
     return p
 
 
@@ -248,6 +253,10 @@ class Cloud:
         _check(self.lib.apc_get_node_orders(self.h, o.ctypes.data_as(ct.c_void_p)),
                "apc_get_node_orders")
         return o
+
+    def set_diagnostics(self, flags):
+        """APC_DIAG_KERNEL_TIMES and/or APC_DIAG_FP64_RESIDUAL for the cloud's solves."""
+        _check(self.lib.apc_set_diagnostics(self.h, flags), "apc_set_diagnostics")
 
     def density_operator(self):
         """Rows of the density operator B (bw aligned with the CSR, diagonal) and the

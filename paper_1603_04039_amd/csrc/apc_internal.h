@@ -13,7 +13,7 @@
 #define APC_THETA_B 0.5
 #define APC_RING_CAP 16384 // per-node candidate capacity of the ring search
 #define APC_TAU_RANK 1e-6 // min|R_ii| / max|R_ii| below this => rank deficient
-#define APC_TAU_DOM 10.0  // order-4 rows: sum |w_j| <= this times |diag| (else order-2 row)
+#define APC_TAU_DOM 10.0  // default of apc_params.tau_dom: order-4 rows need sum |w_j| <= tau |diag|
 // window of the length sort of general rows in the sliced layout (SELL-C-sigma;
 // a multiple of the 64-row slice, 64 = no sort)
 #ifndef APC_SELL_SIGMA
@@ -115,6 +115,9 @@ struct apc_asm_scratch {
 struct apc_cloud {
   apc_params P;
   int device = 0;
+  int diag_flags = 0; // apc_set_diagnostics: APC_DIAG_KERNEL_TIMES | APC_DIAG_FP64_RESIDUAL
+  bool w64_mixed = false; // k = 4 mixed modes: the last assembly also wrote FP64 rows to w64ref
+  double *w64ref = nullptr; // nnz: those FP64 rows (allocated by apc_set_diagnostics)
   int p = 9;
   int64_t N = 0, n = 0, nb = 0, nnz = 0, n_opened = 0;
   double unit = 0.0; // L / 2^(max_depth+1)
@@ -230,6 +233,7 @@ int apc_interp4_with(apc_cloud *c, const double *phi, double *phi_p, double *gra
                      hipStream_t s);
 int apc_interp_with(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, double *D,
                     hipStream_t s);
+int apc_resid64_rows(apc_cloud *c, const double *b, const double *x, double *r, hipStream_t s);
 int apc_interp_noalloc_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,
                             hipStream_t s);
 int apc_interp_impl(apc_cloud *c, const double *phi, double *phi_p, double *grad_p,

@@ -422,6 +422,19 @@ void apc_batch_destroy(apc_batch *b) {
   apc_destroy_batch_impl(b);
 }
 
+int apc_set_diagnostics(apc_cloud *c, int flags) {
+  if (!c || flags < 0 || flags > (APC_DIAG_KERNEL_TIMES | APC_DIAG_FP64_RESIDUAL)) return APC_EINVAL;
+  DeviceGuard g(c->device);
+  if (!g.ok) return APC_EHIP;
+  c->diag_flags = flags;
+  // fourth order, mixed modes: the FP64 reference residual needs the FP64 rows,
+  // which the next assembly keeps beside the FP32 ones
+  if ((flags & APC_DIAG_FP64_RESIDUAL) && c->P.order == 4 && c->P.precision != APC_FP64 &&
+      !c->w64ref)
+    HIPCHK(apc_dev_alloc((void **)&c->w64ref, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
+  return APC_OK;
+}
+
 void apc_destroy(apc_cloud *c) {
   if (!c) return;
   DeviceGuard g(c->device);

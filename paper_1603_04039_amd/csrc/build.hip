@@ -938,7 +938,7 @@ void apc_free_cloud(apc_cloud *c) {
   free_cloud_arrays(c);
   void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, c->scratch,
                  c->m_diag, c->m_sell, c->m_tmpl, c->bw64, c->bw32, c->sl_bw64, c->sl_bw32,
-                 c->rorder, c->dorder};
+                 c->rorder, c->dorder, c->w64ref};
   for (void *q : ops)
     if (q) (void)apc_dev_free(q);
   delete c;
@@ -1317,7 +1317,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   if (p->max_depth < 1 || p->max_depth > 20 || !(p->L > 0.0) || !(p->c > 0.0) ||
       p->ring_min < 1 || p->ring_max < p->ring_min || p->m_cap > APC_MAXM || p->m_cap < 10 || p->stage_cap < -1 ||
       p->criterion_pow < 0 || p->criterion_pow > 16 || p->ring_lds < -1 || p->ring_lds > 1 ||
-      p->ring_first_cap < 0 || p->ring_first_cap > APC_RING_CAP ||
+      p->ring_first_cap < 0 || p->ring_first_cap > APC_RING_CAP || !(p->tau_dom >= 0.0) ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
         p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c))
     return APC_EINVAL;

@@ -372,6 +372,46 @@ __global__ void __launch_bounds__(APC_BLOCK)
   density_row(sum, asum);
 }
 
+// FP64 reference residual of the mixed modes: r_i = b_i - sum_j w_ij (x_j - x_i)
+// with w the FP64 fit of row i (refitted here, the FP32 weights are not used):
+// general rows by the FP64 normal equations of the assembly, uniform 2-ring rows
+// by the FP64 shell constants (CSR order: 6, 12 and 6 entries at r^2 = 1, 2, 4
+// cells).  One thread per row.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_resid64(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+              const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
+              const int8_t *__restrict__ rkind, double unit, double L,
+              const double *__restrict__ tc, const double *__restrict__ b,
+              const double *__restrict__ x, double *__restrict__ r) {
+  const int64_t row = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (row >= n) return;
+  const int32_t a = st_off[row];
+  const int m = st_off[row + 1] - a;
+  const int32_t *nb = st_idx + a;
+  const double xi = x[row];
+  double t = 0.0;
+  if (rkind[row] >= 0) {
+    const double hc = L / (double)(1 << level[row]);
+    const double ih2 = 1.0 / (hc * hc);
+    for (int j = 0; j < 24; j++) t += tc[j < 6 ? 0 : (j < 18 ? 1 : 2)] * ih2 * (x[nb[j]] - xi);
+  } else {
+    const NodeGeom g = node_geom(nb, m, crd, ntot, (int32_t)row);
+    const double hp = (double)g.h * unit;
+    const double inv_h2 = 1.0 / (hp * hp);
+    double z[P9];
+    lap_fit<double>(nb, m, g, crd, ntot, z);
+    for (int j = 0; j < m; j++) {
+      double vv[P9];
+      const double w2 = row_w2<double>(g, crd, ntot, nb[j], vv);
+      double dotv = 0.0;
+#pragma unroll
+      for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
+      t += w2 * dotv * inv_h2 * (x[nb[j]] - xi);
+    }
+  }
+  r[row] = b[row] - t;
+}
+
 // ---------------------------------------------------------------- derivatives
 // d = G^{-1} sum_j W_j^2 v_j (f_j - f_0);  d^alpha f = d_alpha / (h unit)^{|alpha|}
 __global__ void __launch_bounds__(APC_BLOCK)
@@ -546,6 +586,15 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
     HIPCHK(hipGetLastError());
   }
   c->assembled = true;
+  return APC_OK;
+}
+
+int apc_resid64_rows(apc_cloud *c, const double *b, const double *x, double *r, hipStream_t s) {
+  if (c->n > 0)
+    hipLaunchKernelGGL(k_resid64, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->st_off,
+                       c->st_idx, c->crd, c->n + c->nb, c->level, c->rkind, c->unit, c->P.L,
+                       (const double *)c->scratch->tc, b, x, r);
+  HIPCHK(hipGetLastError());
   return APC_OK;
 }
 

@@ -338,8 +338,9 @@ __device__ __forceinline__ void wv0_times(Wave4 &S, const Geo &g, int lane, int 
 // ---------------------------------------------------------------- rank test (build)
 template <int MR>
 __global__ void __launch_bounds__(WPB4 * 64, 2)
-    k_rank_qr(int pc, const int32_t *__restrict__ pending, int64_t np, const int32_t *__restrict__ cand,
-              int32_t *__restrict__ m, const int32_t *__restrict__ crd, int64_t ntot) {
+    k_rank_qr(int pc, double tau, const int32_t *__restrict__ pending, int64_t np,
+              const int32_t *__restrict__ cand, int32_t *__restrict__ m,
+              const int32_t *__restrict__ crd, int64_t ntot) {
   __shared__ Wave4 SH[WPB4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * WPB4 + wv;
@@ -353,14 +354,14 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
   bool ok = ratio >= APC_TAU_RANK;
   if (ok && pc == P4) {
     // stability of the order-4 Laplacian row: negative diagonal and off-diagonal
-    // weights of total magnitude <= APC_TAU_DOM times it (scale-free, h cancels)
+    // weights of total magnitude <= tau times it (scale-free, h cancels)
     const double cl = (lane == 3 || lane == 6 || lane == 8) ? 1.0 : 0.0;
     double u1, u2, z1, z2;
     solve_rrt(S, lane, pc, cl, 0.0, u1, u2);
     wv0_times(S, g, lane, pc, u1, u2, z1, z2);
     const double sv = lane < mm ? g.W * z1 : 0.0;
     const double s1 = wsum(sv), s2 = wsum(fabs(sv));
-    ok = s1 > 0.0 && s2 <= APC_TAU_DOM * s1;
+    ok = s1 > 0.0 && s2 <= tau * s1;
   }
   if (lane == 0 && !ok) m[t] = 0;
 }
@@ -375,7 +376,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
            float *__restrict__ w32,
            double *__restrict__ bw64, float *__restrict__ bw32, double *__restrict__ diag,
            double *__restrict__ inv_diag, double *__restrict__ hscale, int8_t *__restrict__ dorder,
-           int *__restrict__ err) {
+           double *__restrict__ w64ref, int *__restrict__ err) {
   __shared__ Wave4 SH[WPB4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t y = (int64_t)blockIdx.x * WPB4 + wv;
@@ -440,6 +441,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
     if (MIXED) {
       w32[a0 + lane] = (float)wl;
       bw32[a0 + lane] = (float)wb;
+      if (w64ref) w64ref[a0 + lane] = wl; // FP64 rows kept for the reference residual
     } else {
       w64[a0 + lane] = wl;
       bw64[a0 + lane] = wb;
@@ -555,12 +557,13 @@ int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t 
                     const int32_t *cand, int32_t *m, hipStream_t s) {
   if (np <= 0) return APC_OK;
   // stencils hold at most m_cap rows (order-2 fallback: 40): QR over 56 or 64 rows
+  const double tau = c->P.tau_dom > 0.0 ? c->P.tau_dom : APC_TAU_DOM;
   if (c->P.m_cap <= 56)
-    hipLaunchKernelGGL(k_rank_qr<56>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, pending, np,
-                       cand, m, c->crd, c->n + c->nb);
-  else
-    hipLaunchKernelGGL(k_rank_qr<APC_MAXM>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, pending,
+    hipLaunchKernelGGL(k_rank_qr<56>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, tau, pending,
                        np, cand, m, c->crd, c->n + c->nb);
+  else
+    hipLaunchKernelGGL(k_rank_qr<APC_MAXM>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, tau,
+                       pending, np, cand, m, c->crd, c->n + c->nb);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
@@ -576,7 +579,7 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
   hipLaunchKernelGGL((k_fit4<MX, R>), dim3(grid4(n)), dim3(WPB4 * 64), 0, s, n, c->st_off,     \
                      c->st_idx, c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, c->w64,    \
                      c->w32, c->bw64, c->bw32, c->diag, c->inv_diag, c->hscale, c->dorder,    \
-                     &c->scratch->err)
+                     MX ? c->w64ref : nullptr, &c->scratch->err)
     if (mixed && m56)
       APC_FIT4(true, 56);
     else if (mixed)
@@ -588,6 +591,7 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
 #undef APC_FIT4
     HIPCHK(hipGetLastError());
   }
+  c->w64_mixed = mixed && c->w64ref != nullptr;
   if (c->nsl > 0) {
     const unsigned g = (unsigned)((c->nsl + (APC_BLOCK / 64) - 1) / (APC_BLOCK / 64));
     if (mixed) {

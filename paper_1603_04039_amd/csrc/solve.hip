@@ -17,6 +17,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "apc_internal.h"
 #include "spmv_core.h"
@@ -414,6 +415,40 @@ __global__ void __launch_bounds__(APC_BLOCK)
   if (b < nb) v[n + b] = v[bowner[b]];
 }
 
+// FP64 reference residual, fourth order: r_i = b_i - sum_j w_ij (x_j - x_i) over
+// the CSR rows of the FP64 weights (x has a zero boundary tail, so boundary
+// columns contribute -w_ij x_i as in the interior operator); one wavefront per
+// row (at most 64 entries); partial sums of r^2 per block.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_resid_csr(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+                const double *__restrict__ w64, const double *__restrict__ b,
+                const double *__restrict__ x, double *part) {
+  double val[1] = {0.0};
+  const int lane = threadIdx.x & 63;
+  const int64_t nw = (int64_t)gridDim.x * (APC_BLOCK / 64);
+  for (int64_t i = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6); i < n; i += nw) {
+    const int32_t a = st_off[i], m = st_off[i + 1] - a;
+    const double xi = x[i];
+    double t = lane < m ? w64[a + lane] * (x[st_idx[a + lane]] - xi) : 0.0;
+    t = wave_sum(t);
+    if (lane == 0) {
+      const double r = b[i] - t;
+      val[0] += r * r;
+    }
+  }
+  block_partials<1>(val, part);
+}
+
+// sum of r^2 over rows (r given), partials per block
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_sumsq(int64_t n, const double *__restrict__ r, double *part) {
+  double val[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * APC_BLOCK)
+    val[0] += r[i] * r[i];
+  block_partials<1>(val, part);
+}
+
 } // namespace
 
 // ---------------------------------------------------------------- workspace
@@ -425,6 +460,12 @@ struct apc_solver_ws {
   Scal *sc = nullptr;
   Scal *sc_host = nullptr;
   hipEvent_t e0 = nullptr, e1 = nullptr;
+  // kernel timing (apc_set_diagnostics): start/stop events of the two SpMVs of
+  // every iteration of a chunk (at most 32 iterations between host polls)
+  hipEvent_t kev[4 * 32] = {};
+  bool kev_made = false;
+  double spmv_ms = 0.0;
+  int64_t spmv_launches = 0;
 };
 
 void apc_free_solver(apc_cloud *c) {
@@ -437,6 +478,8 @@ void apc_free_solver(apc_cloud *c) {
   if (w->sc_host) (void)hipHostFree(w->sc_host);
   if (w->e0) (void)hipEventDestroy(w->e0);
   if (w->e1) (void)hipEventDestroy(w->e1);
+  if (w->kev_made)
+    for (hipEvent_t e : w->kev) (void)hipEventDestroy(e);
   delete w;
   c->ws = nullptr;
 }
@@ -478,9 +521,11 @@ static int launch_restart(apc_solver_ws *w, const Op &op, const double *b, const
   return APC_OK;
 }
 
+// ev (may be null): four events recorded around the iteration's two SpMVs
 template <int MODE>
 static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const double *invd,
-                             const MOp &mw, int prec, unsigned gs, hipStream_t s) {
+                             const MOp &mw, int prec, unsigned gs, hipStream_t s,
+                             hipEvent_t *ev) {
   const int64_t n = w->n;
   const unsigned gv = grid_for(n), gr = vec_grid(n);
   const bool jac = prec == APC_PRECOND_JACOBI, lrn = prec == APC_PRECOND_LEARNED;
@@ -493,8 +538,10 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
     hipLaunchKernelGGL(k_upd_p<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->p, w->v, ph,
                        invd, w->sc);
   if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, mw, w->p, ph, w->sc);
+  if (ev) (void)hipEventRecord(ev[0], s);
   hipLaunchKernelGGL(k_spmv_v<MODE>, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, ph, w->v, w->rh, w->part,
                      w->sc);
+  if (ev) (void)hipEventRecord(ev[1], s);
   hipLaunchKernelGGL(k_fin_alpha, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
   if (jac)
     hipLaunchKernelGGL(k_upd_s<true>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->v, w->s, sh,
@@ -503,8 +550,10 @@ static void launch_iteration(apc_solver_ws *w, const Op &op, double *x, const do
     hipLaunchKernelGGL(k_upd_s<false>, dim3(gv), dim3(APC_BLOCK), 0, s, n, w->r, w->v, w->s, sh,
                        invd, w->sc);
   if (lrn) hipLaunchKernelGGL(k_prec_apply, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, mw, w->s, sh, w->sc);
+  if (ev) (void)hipEventRecord(ev[2], s);
   hipLaunchKernelGGL(k_spmv_t<MODE>, dim3(gs), dim3(APC_BLOCK), op_lds(op), s, op, sh, w->s, w->t, w->part,
                      w->sc);
+  if (ev) (void)hipEventRecord(ev[3], s);
   hipLaunchKernelGGL(k_fin_omega, dim3(1), dim3(FIN_T), 0, s, w->part, gs, w->sc);
   hipLaunchKernelGGL(k_upd_xr, dim3(gr), dim3(APC_BLOCK), 0, s, n, x, ph, sh, w->s, w->t, w->r,
                      w->rh, w->part, w->sc);
@@ -529,14 +578,31 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *invd, const double
   HIPCHK(hipMemcpyAsync(w->sc, &init, sizeof(Scal), hipMemcpyHostToDevice, s));
   HIPCHK(hipMemsetAsync(x, 0, (size_t)n * sizeof(double), s));
   APCCHK(launch_restart<TMODE>(w, op, b, x, 1, gs, s));
-  int chunk = 8, nrest = 0, status = APC_ENOCONV;
+  const bool timed = (c->diag_flags & APC_DIAG_KERNEL_TIMES) != 0;
+  if (timed && !w->kev_made) {
+    for (hipEvent_t &e : w->kev) HIPCHK(hipEventCreate(&e));
+    w->kev_made = true;
+  }
+  int chunk = 8, nrest = 0, status = APC_ENOCONV, it0 = 0;
   for (;;) {
     for (int k = 0; k < chunk; k++)
       launch_iteration<MODE>(w, op, x, invd, MOp{c->m_diag, c->m_sell, c->m_tmpl}, prec,
-                             gs, s);
+                             gs, s, timed ? &w->kev[4 * k] : nullptr);
     HIPCHK(hipGetLastError());
     APCCHK(read_sc(w, s));
     Scal &h = *w->sc_host;
+    if (timed) {
+      // SpMVs of the iterations that completed (later launches of the chunk return
+      // at once once the solver has stopped, and are not counted)
+      for (int k = 0; k < chunk && it0 + k < h.it; k++)
+        for (int q = 0; q < 2; q++) {
+          float ms = 0.f;
+          HIPCHK(hipEventElapsedTime(&ms, w->kev[4 * k + 2 * q], w->kev[4 * k + 2 * q + 1]));
+          w->spmv_ms += ms;
+          w->spmv_launches++;
+        }
+    }
+    it0 = h.it;
     if (!h.done) {
       if (chunk < 32) chunk *= 2;
       continue;
@@ -554,6 +620,8 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *invd, const double
   }
   const Scal &h = *w->sc_host;
   if (st) {
+    st->spmv_ms = w->spmv_ms;
+    st->spmv_launches = w->spmv_launches;
     st->iters = h.it;
     st->restarts = nrest;
     st->sweeps = 1 + nrest;
@@ -584,6 +652,8 @@ static int run_once(apc_cloud *c, const Op &op, const double *invd, const double
 static int run_solve(apc_cloud *c, bool density, const double *b, double *x, double tol, int maxit,
                      int prec, apc_stats *st, hipStream_t s) {
   const Op op = make_op(c, density);
+  c->ws->spmv_ms = 0.0;
+  c->ws->spmv_launches = 0;
   const double *invd = density ? nullptr : c->inv_diag; // the density solve is plain
   int rc = run_once(c, op, invd, b, x, tol, maxit, prec, st, s);
   if (rc == APC_ENOCONV && prec == APC_PRECOND_LEARNED) {
@@ -625,6 +695,7 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
   // all rows stalled.)
   int rc = run_solve(c, true, w->b, w->x, tol, maxit, APC_PRECOND_NONE, st, s);
   if (rc < 0) return rc;
+  if (st) st->rel_resid_fp64ref = c->P.precision == APC_FP64 ? w->sc_host->rtrue : -1.0;
   hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
                      w->x, rho_M + c->n, rho_t);
   HIPCHK(hipGetLastError());
@@ -662,6 +733,36 @@ int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *p
   HIPCHK(hipGetLastError());
   int rc = run_solve(c, false, w->b, w->x, tol, maxit, precond, st, s);
   if (rc < 0) return rc;
+  double fp64ref = -1.0;
+  if (c->P.precision == APC_FP64) {
+    fp64ref = w->sc_host->rtrue;
+  } else if (c->diag_flags & APC_DIAG_FP64_RESIDUAL) {
+    // ||b - A64 x|| / ||b|| with the FP64 fit of the same stencils (the mixed
+    // modes iterate on FP32 weights); w->t is free after the solve
+    const unsigned gr = vec_grid(c->n);
+    if (c->P.order == 4 && !c->w64_mixed) {
+      fp64ref = -1.0; // assembled before the flag was set: no FP64 rows kept
+    } else if (c->P.order == 4) {
+      hipLaunchKernelGGL(k_resid_csr, dim3(gr), dim3(APC_BLOCK), 0, s, c->n, c->st_off, c->st_idx,
+                         (const double *)c->w64ref, (const double *)w->b, (const double *)w->x,
+                         w->part);
+    } else {
+      APCCHK(apc_resid64_rows(c, w->b, w->x, w->t, s));
+      hipLaunchKernelGGL(k_sumsq, dim3(gr), dim3(APC_BLOCK), 0, s, c->n, (const double *)w->t,
+                         w->part);
+    }
+    if (c->P.order == 2 || c->w64_mixed) {
+      HIPCHK(hipGetLastError());
+      std::vector<double> part(gr);
+      HIPCHK(hipMemcpyAsync(part.data(), w->part, gr * sizeof(double), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      double ss = 0.0;
+      for (double v : part) ss += v;
+      const double bn = w->sc_host->bnorm;
+      fp64ref = bn > 0.0 ? sqrt(ss) / bn : 0.0;
+    }
+  }
+  if (st) st->rel_resid_fp64ref = fp64ref;
   hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
                      w->x, g, phi);
   HIPCHK(hipGetLastError());

@@ -162,10 +162,13 @@ def test_k4_derivatives_and_interpolation(apc, pair):
 
 
 def test_k4_mixed_weights(apc, oracle_mod):
-    """Mixed precision keeps the FP64 fit and stores FP32 weights."""
+    """Mixed precision keeps the FP64 fit and stores FP32 weights; with the FP64
+    reference residual requested, the mixed solve's residual on the FP64 rows
+    equals that of the oracle's operator applied to its potential."""
     xyz = beam_halo(20000, seed=31)
     O = oracle_mod.OracleCloud(xyz, **K4A)
     G = gcloud(apc, xyz, precision=apc.APC_MIXED, **K4A)
+    G.set_diagnostics(apc.APC_DIAG_FP64_RESIDUAL)
     G.assemble_gfd()
     w_g, _ = G.operator()
     w_o, d_o = O.assemble()
@@ -176,6 +179,11 @@ def test_k4_mixed_weights(apc, oracle_mod):
     _, rho_t, _ = G.deposit(tol=1e-10, maxit=4000)
     phi, st = G.solve(rho_t[:G.n].contiguous(), tol=1e-8)
     assert st["status"] == 0 and st["rel_resid_true"] <= 1e-8
+    rt = rho_t.cpu().numpy()[:O.n]
+    want = np.linalg.norm(O.apply_laplacian(phi.cpu().numpy()) - rt) / np.linalg.norm(rt)
+    note(f"k = 4 mixed: own residual {st['rel_resid_true']:.2e}, FP64 reference "
+         f"{st['rel_resid_fp64ref']:.2e}, oracle operator {want:.2e}")
+    assert abs(st["rel_resid_fp64ref"] - want) <= 1e-3 * want
     G.close()
 
 

@@ -365,6 +365,37 @@ def test_mixed_precision_error_reported(apc, oracle_mod, c1, mode):
     assert err < 1e-4
 
 
+def test_solver_diagnostics(apc, oracle_mod, c1):
+    """apc_set_diagnostics: the SpMV launches of a solve timed with HIP events
+    (two per completed iteration, summed time below the call's), and the FP64
+    reference residual of a mixed-precision solve equal to the residual of the
+    oracle's FP64 operator applied to the GPU's potential."""
+    note("solver diagnostics: kernel times and FP64 reference residual")
+    xyz, O, G = c1
+    rt_o, _ = O.density_solve(O.deposit(), tol=1e-13)
+    rhs = torch.from_numpy(rt_o[:O.n].copy()).cuda()
+    G.set_diagnostics(apc.APC_DIAG_KERNEL_TIMES)
+    phi, st = G.solve(rhs, tol=1e-10, precond=apc.APC_PRECOND_NONE)
+    note(f"  fp64: iters {st['iters']} spmv launches {st['spmv_launches']} "
+         f"spmv ms {st['spmv_ms']:.3f} of {st['ms']:.3f}")
+    assert st["spmv_launches"] == 2 * st["iters"]
+    assert 0.0 < st["spmv_ms"] < st["ms"]
+    assert st["rel_resid_fp64ref"] == st["rel_resid_true"]
+    G.set_diagnostics(0)
+    _, st0 = G.solve(rhs, tol=1e-10, precond=apc.APC_PRECOND_NONE)
+    assert st0["spmv_launches"] == 0 and st0["spmv_ms"] == 0.0
+    Gm = gcloud(apc, xyz, precision=apc.APC_MIXED, **P1)
+    Gm.set_diagnostics(apc.APC_DIAG_FP64_RESIDUAL)
+    Gm.assemble_gfd()
+    phi_m, stm = Gm.solve(rhs, tol=1e-8)
+    res = O.apply_laplacian(phi_m.cpu().numpy()) - rt_o[:O.n]
+    want = np.linalg.norm(res) / np.linalg.norm(rt_o[:O.n])
+    note(f"  mixed: own true residual {stm['rel_resid_true']:.3e}, FP64 reference "
+         f"{stm['rel_resid_fp64ref']:.3e}, oracle operator {want:.3e}")
+    assert abs(stm["rel_resid_fp64ref"] - want) <= 1e-3 * want
+    Gm.close()
+
+
 def test_uniform_rows_use_lattice_constants(apc, oracle_mod):
     """Rows whose stencil is the uniform 2-ring of their level carry the lattice
     weights of the canonical fit (0.109091, 0.130530, 0.092198 per unit spacing,
