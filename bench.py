@@ -1,16 +1,24 @@
 #!/usr/bin/env python3
 """Benchmark of the AP-Cloud field-solve hot path on one MI355X.
 
-A step is one pass of the whole path over the synthetic beam-with-halo cloud:
-build_cloud -> assemble_gfd (+ install of the learned preconditioner) -> deposit
-(NGP + density solve) -> solve (Poisson, BiCGSTAB to relative residual 1e-8) ->
-interpolate_force.  The reported value is nodes / (assembly + preconditioner
-install + Poisson solve time), from HIP events on the stream the library runs
-on, averaged over the timed steps.  Inputs are resident in HBM before the timed
-region starts.  The learned preconditioner's parameters come from
-paper_1603_04039_amd/learned_params.npy (written by `python -m
-paper_1603_04039_amd.learned`); without that file they are trained here, on the
-GPU, before the timed region.
+Headline workload: beam_halo_1e8_k4 (1e8 particles of the anisotropic
+beam-with-halo recipe, octree depth 12, fourth-order GFD, ~8.8e6 nodes), the
+largest configuration, in the plain method: FP64 throughout and BiCGSTAB without a
+preconditioner (the oracle's solver) to relative residual 1e-8.
+
+A step is one pass of the whole path: build_cloud -> assemble_gfd -> deposit (NGP +
+density solve) -> solve (Poisson, BiCGSTAB to 1e-8) -> interpolate_force.  The
+reported value is nodes / (assembly + Poisson solve time), from HIP events on the
+stream the library runs on, averaged over the timed steps; inputs are resident in
+HBM before the timed region starts.  During the timed steps the library also
+times every operator SpMV of the solves with HIP events on its stream
+(apc_set_diagnostics), which gives the roofline figure of the dominant kernel.
+
+Beside the headline: the grown forms on the same workload (mixed precision; mixed
+precision with the learned preconditioner; Jacobi), the 1e7-particle second-order
+workload in its five variants, the 64-cloud batch, the Vlasov-Poisson time loop,
+the paper's 3-D beam, memory-bandwidth probes, and the oracle timed on a bounded
+sample of the headline recipe on the host cores.
 
 Prints one JSON line.  `--gpus N` with N > 1 is not supported (single-GPU build).
 """
@@ -19,6 +27,7 @@ from __future__ import annotations
 import argparse
 import json
 import os
+import platform
 import sys
 import time
 
@@ -27,31 +36,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "nodes/s for GFD assembly+solve to 1e-8 resid; learned/mixed vs plain speedup"
 HBM_PEAK_GBS = 8000.0
+FP64_PEAK_GFLOPS = 78600.0
+FP32_PEAK_GFLOPS = 157300.0
+PRECOND = {"none": 0, "jacobi": 1, "learned": 2}
 
 
 def log(msg):
     print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
 
-def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="jacobi",
-              params=None):
-    """Run warmup + timed steps; returns per-phase mean ms and the last cloud."""
+def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="none",
+              params=None, timing=True, keep_last=False):
+    """warmup + timed steps of the whole path; per-phase mean device ms over the
+    timed steps, and the SpMV launch times the library recorded during them."""
     stream = torch.cuda.current_stream()
     names = ["build", "assemble", "install", "deposit", "solve", "interpolate"]
-    pc = apc.APC_PRECOND_LEARNED if precond == "learned" else apc.APC_PRECOND_JACOBI
+    pc = PRECOND[precond]
     acc = {k: 0.0 for k in names}
-    info = {}
-    t_wall = 0.0
+    spmv_ms, spmv_n = 0.0, 0
+    info, last = {}, None
     kw = dict(order=cfg["order"], c=cfg["c"], max_depth=cfg["max_depth"], precision=precision)
+    t0 = None
     for it in range(warmup + steps):
         timed = it >= warmup
-        if timed and it == warmup:
+        if timed and t0 is None:
             torch.cuda.synchronize()
             t0 = time.perf_counter()
         ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
         ev[0].record(stream)
         cloud = apc.Cloud(xyz_d, **kw)
         ev[1].record(stream)
+        if timing:
+            cloud.set_diagnostics(apc.APC_DIAG_KERNEL_TIMES)
         cloud.assemble_gfd()
         ev[2].record(stream)
         if pc == apc.APC_PRECOND_LEARNED:
@@ -74,19 +90,49 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="ja
         if timed:
             for k, name in enumerate(names):
                 acc[name] += ev[k].elapsed_time(ev[k + 1])
+            spmv_ms += st["spmv_ms"]
+            spmv_n += st["spmv_launches"]
         log(f"step {it} ({'timed' if timed else 'warmup'}): n={cloud.n} iters={st['iters']} "
-            f"phases(ms)=" + ", ".join(f"{k} {ev[q].elapsed_time(ev[q + 1]):.2f}"
-                                         for q, k in enumerate(names)))
+            f"density_iters={std['iters']} phases(ms)=" +
+            ", ".join(f"{k} {ev[q].elapsed_time(ev[q + 1]):.2f}" for q, k in enumerate(names)))
         info = dict(n=cloud.n, nb=cloud.nb, nnz=cloud.nnz, iters=st["iters"],
                     sweeps=st["sweeps"], rel_resid_true=st["rel_resid_true"],
-                    density_iters=std["iters"])
-        last = cloud if it == warmup + steps - 1 else None
-        if last is None:
+                    rel_resid_fp64ref=st["rel_resid_fp64ref"], density_iters=std["iters"])
+        if keep_last and it == warmup + steps - 1:
+            last = (cloud, rho_t)
+        else:
             cloud.close()
     torch.cuda.synchronize()
-    t_wall = time.perf_counter() - t0
+    wall = (time.perf_counter() - t0) * 1000.0 / steps
     ms = {k: v / steps for k, v in acc.items()}
-    return ms, info, t_wall * 1000.0 / steps, last, phi
+    info["spmv_avg_us"] = spmv_ms / spmv_n * 1e3 if spmv_n else None
+    info["spmv_launches_per_step"] = spmv_n // steps
+    return ms, info, wall, last
+
+
+def nodes_per_s(ms, info):
+    return info["n"] / ((ms["assemble"] + ms["install"] + ms["solve"]) * 1e-3)
+
+
+def leg(ms, info, wall=None):
+    out = dict(nodes_per_s=round(nodes_per_s(ms, info), 1),
+               phases_ms={k: round(v, 3) for k, v in ms.items()},
+               iters=info["iters"], sweeps=info["sweeps"], density_iters=info["density_iters"],
+               rel_resid_true=info["rel_resid_true"])
+    if info.get("spmv_avg_us") is not None:
+        out["spmv_avg_us"] = round(info["spmv_avg_us"], 2)
+    if wall is not None:
+        out["ms_per_step"] = round(wall, 3)
+    return out
+
+
+def fp64_reference_residual(apc, torch, cloud, rho_t, tol):
+    """A25: a mixed-precision solve's residual on the FP64 fit of the same stencils
+    (assembled again with the FP64 rows kept, solved again; untimed)."""
+    cloud.set_diagnostics(apc.APC_DIAG_FP64_RESIDUAL)
+    cloud.assemble_gfd()
+    _, st = cloud.solve(rho_t[:cloud.n], tol=tol, maxit=20000, precond=apc.APC_PRECOND_NONE)
+    return st["rel_resid_fp64ref"], st["rel_resid_true"]
 
 
 def load_params(apc, torch, order):
@@ -108,18 +154,16 @@ def load_params(apc, torch, order):
     return params, src
 
 
-def stream_probe(torch, mib=1024, reps=10):
-    """Device copy of `mib` MiB (torch's copy kernel): the bandwidth a plain
-    streaming kernel reaches here, and a kernel of known traffic (read + write
-    of `mib` MiB each) against which the HBM byte counters are scaled."""
+def copy_probe(torch, mib=1024, reps=10):
+    """Device copy of `mib` MiB (torch's copy kernel): read + write of mib MiB each;
+    the kernel of known traffic against which the HBM byte counters are scaled."""
     n = mib * (1 << 20) // 8
     src = torch.ones(n, dtype=torch.float64, device="cuda")
     dst = torch.empty_like(src)
     for _ in range(2):
         dst.copy_(src)
     stream = torch.cuda.current_stream()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
         dst.copy_(src)
@@ -131,84 +175,37 @@ def stream_probe(torch, mib=1024, reps=10):
                 GBs=round(2 * n * 8 / (ms * 1e-3) / 1e9, 1))
 
 
-def assembly_roofline(torch, cloud, reps, mixed):
-    """Average duration of apc_assemble_gfd (HIP events, reps back-to-back calls)
-    with its algorithmic bytes and flops, as fractions of the HBM peak and of the
-    vector peak of the fit's precision.  k = 2 counts the general rows' FP32 (mixed)
-    or FP64 normal-equation fits: per stencil entry ~160 flop (monomials, Gaussian
-    weight, 45 Gram FMAs, weight pass), per row ~650 (9 x 9 Cholesky and solves);
-    bytes: CSR indices and the two weight copies per entry, the coordinate array
-    once, per-row metadata.  k = 4 counts the FP64 Householder QR of the 56 x 34
-    systems, 2 m p^2 - 2 p^3 / 3 + 4 m p per node."""
+def read_probe(torch, sizes_mib=(64, 128, 192, 256, 512, 2048, 8192)):
+    """Read-dominated streams (torch's sum over a float64 array, repeated
+    back-to-back) at several footprints: footprints that fit the 256 MB Infinity
+    Cache (MALL) read faster than HBM allows when the cache serves them; large
+    footprints read at the HBM rate."""
+    out = {}
     stream = torch.cuda.current_stream()
-    for _ in range(2):
-        cloud.assemble_gfd()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        cloud.assemble_gfd()
-    e1.record(stream)
-    e1.synchronize()
-    us = e0.elapsed_time(e1) / reps * 1e3
-    oi = cloud.operator_info()
-    n, ntot = cloud.n, cloud.n + cloud.nb
-    wb = 4 if mixed else 8
-    if cloud.p == 9:
-        n_u, nnz_g = oi["n_uniform"], oi["nnz_general"]
-        n_g = n - n_u
-        byts = n_u * 32 + n_g * 52 + nnz_g * (4 + 2 * wb) + ntot * 12
-        flops = nnz_g * 160 + n_g * 650
-        peak = 157300.0 if mixed else 78600.0
-    else:
-        p, nnz = 34, cloud.nnz
-        byts = nnz * (4 + 2 * wb) + n * 44 + ntot * 12
-        flops = 2 * p * p * nnz - (2.0 / 3.0) * p ** 3 * n + 4 * p * nnz
-        peak = 78600.0
-    gbs = byts / (us * 1e-6) / 1e9
-    gfl = flops / (us * 1e-6) / 1e9
-    return dict(avg_us=round(us, 1), bytes_per_launch=int(byts), GBs=round(gbs, 1),
-                hbm_frac=round(gbs / HBM_PEAK_GBS, 4), gflop_per_launch=round(flops / 1e9, 3),
-                GFLOPs=round(gfl, 1), valu_peak_GFLOPs=peak, valu_frac=round(gfl / peak, 4),
-                bound="latency of the per-row neighbour gathers (neither HBM nor VALU)")
+    for mib in sizes_mib:
+        n = mib * (1 << 20) // 8
+        a = torch.ones(n, dtype=torch.float64, device="cuda")
+        reps = max(5, min(200, (16 << 10) // mib))
+        for _ in range(3):
+            a.sum()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            a.sum()
+        e1.record(stream)
+        e1.synchronize()
+        ms = e0.elapsed_time(e1) / reps
+        out[f"{mib}MiB"] = round(n * 8 / (ms * 1e-3) / 1e9, 1)
+        del a
+    return dict(kernel="torch sum (read-only stream), GB/s by footprint", GBs=out)
 
 
-def precond_roofline(torch, cloud, reps):
-    """Average duration of the learned M apply (k_prec_apply), same method."""
-    stream = torch.cuda.current_stream()
-    f = torch.rand(cloud.n + cloud.nb, dtype=torch.float64, device="cuda")
-    from paper_1603_04039_amd import apcloud as apc
-    for _ in range(5):
-        cloud.apply_precond(f, apc.APC_PRECOND_LEARNED)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
-    e0.record(stream)
-    for _ in range(reps):
-        cloud.apply_precond(f, apc.APC_PRECOND_LEARNED)
-    e1.record(stream)
-    e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    oi = cloud.operator_info(m_entries=True)
-    n_gen = cloud.n - oi["n_uniform"]
-    # uniform rows: 24 indices + level byte (per-level M rows stay in cache);
-    # general rows: index + FP32 weight per stored entry of M (the first 40
-    # stencil entries) and an FP32 diagonal; every row: row id, in_i, out_i
-    ib = index_bytes(cloud)
-    byts = (oi["n_uniform"] * (24 * ib + 1) + oi["m_entries"] * (ib + 4) + n_gen * 4
-            + cloud.n * (4 + 8 + 8))
-    gbs = byts / (ms * 1e-3) / 1e9
-    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4), traffic=None,
-                kernel="k_prec_apply (learned M, sliced layout)", avg_us=round(ms * 1e3, 2),
-                bytes_per_launch=int(byts))
-
-
-def counted_traffic(workload):
-    """HBM bytes per launch of the SpMV from the committed rocprofv3 --pmc summary
+def counted_traffic(name):
+    """HBM bytes per launch of a kernel from a committed rocprofv3 --pmc summary
     (FETCH_SIZE + WRITE_SIZE, each scaled by its copy-kernel factor), or None when
-    the summary is missing or the SpMV's sources changed since it was taken."""
+    the summary is missing or the kernel's sources changed since it was taken."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", f"k_apply_{workload}_hbm_counters.md")
+    path = os.path.join(ROOT, "profiles", name)
     if not os.path.exists(path):
         return None
     kv = {}
@@ -227,44 +224,68 @@ def counted_traffic(workload):
         return None
 
 
+def spmv_bytes(cloud, info, value_bytes, index_bytes_layout):
+    """Bytes per operator SpMV launch.  survey: the algorithmic count per row of the
+    hot-path table, (m_i + 1) (value + 4 B index) + 8 B y_i + 4 B row pointer + 8 B
+    x_i, i.e. (value + 4) (nnz + n) + 20 n.  layout: what the sliced layout has to
+    move: per stored entry its index (3 B) and weight, nothing for uniform 2-ring
+    rows but 24 indices and a level byte, per row a 4 B row id, x_i and y_i (the
+    diagonal is implied by the zero row sums)."""
+    n, nnz = info["n"], info["nnz"]
+    oi = cloud.operator_info()
+    survey = (value_bytes + 4) * (nnz + n) + 20 * n
+    ib = index_bytes_layout
+    layout = oi["n_uniform"] * (24 * ib + 1) + oi["nnz_general"] * (ib + value_bytes) + n * 20
+    return int(survey), int(layout)
+
+
 def index_bytes(cloud):
     """Bytes per column index the operator kernels read: 3 (a 16-bit and an 8-bit
     part), 4 for clouds of 2^24 nodes or more."""
     return 4 if cloud.n + cloud.nb >= 1 << 24 else 3
 
 
-def spmv_roofline(torch, cloud, reps, mixed, workload):
-    """Average duration of the operator SpMV (the solver's dominant kernel) over
-    `reps` back-to-back launches, HIP events on the library's stream."""
+def assembly_roofline(torch, cloud, reps, mixed):
+    """Average duration of apc_assemble_gfd (HIP events, reps back-to-back calls)
+    with its algorithmic bytes and flops.  k = 2 counts the general rows' FP32
+    (mixed) or FP64 normal-equation fits: per stencil entry ~160 flop (monomials,
+    Gaussian weight, 45 Gram FMAs, weight pass), per row ~650 (9 x 9 Cholesky and
+    solves); bytes: CSR indices and the two weight copies per entry, the
+    coordinate array once, per-row metadata.  k = 4 counts the FP64 Householder QR
+    of the m x 34 systems, 2 m p^2 - 2 p^3 / 3 + 4 m p per node (FP64 in every
+    precision mode)."""
     stream = torch.cuda.current_stream()
-    f = torch.rand(cloud.n + cloud.nb, dtype=torch.float64, device="cuda")
-    for _ in range(5):
-        cloud.apply_operator(f)
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
+    for _ in range(2):
+        cloud.assemble_gfd()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
     e0.record(stream)
     for _ in range(reps):
-        cloud.apply_operator(f)
+        cloud.assemble_gfd()
     e1.record(stream)
     e1.synchronize()
-    ms = e0.elapsed_time(e1) / reps
-    n = cloud.n
+    us = e0.elapsed_time(e1) / reps * 1e3
     oi = cloud.operator_info()
-    vbytes = 4 if mixed else 8
-    ib = index_bytes(cloud)
-    # algorithmic bytes (padding excluded): uniform 2-ring rows read 24 column
-    # indices and their level, other rows column index + weight per entry; every
-    # row reads its row id, x_i and writes y_i (x_j gathers counted once, in x_i)
-    byts = (oi["n_uniform"] * (24 * ib + 1) + oi["nnz_general"] * (ib + vbytes)
-            + n * (4 + 8 + 8))
-    gbs = byts / (ms * 1e-3) / 1e9
-    traffic = counted_traffic(workload) if mixed else None
-    return dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
-                frac=round(gbs / HBM_PEAK_GBS, 4),
-                traffic=None if traffic is None else round(traffic), traffic_unit="bytes/launch",
-                kernel="k_apply<%s> (sliced-ELL operator SpMV)" % ("V32A64" if mixed else "V64"),
-                avg_us=round(ms * 1e3, 2), bytes_per_launch=int(byts),
-                uniform_rows=oi["n_uniform"], sell_entries=oi["sell_entries"])
+    n, ntot = cloud.n, cloud.n + cloud.nb
+    wb = 4 if mixed else 8
+    if cloud.p == 9:
+        n_u, nnz_g = oi["n_uniform"], oi["nnz_general"]
+        n_g = n - n_u
+        byts = n_u * 32 + n_g * 52 + nnz_g * (4 + 2 * wb) + ntot * 12
+        flops = nnz_g * 160 + n_g * 650
+        peak = FP32_PEAK_GFLOPS if mixed else FP64_PEAK_GFLOPS
+        kernel = "k_fit_sell"
+    else:
+        p, nnz = 34, cloud.nnz
+        byts = nnz * (4 + 2 * wb) + n * 44 + ntot * 12
+        flops = 2 * p * p * nnz - (2.0 / 3.0) * p ** 3 * n + 4 * p * nnz
+        peak = FP64_PEAK_GFLOPS
+        kernel = "k_fit4"
+    gbs = byts / (us * 1e-6) / 1e9
+    gfl = flops / (us * 1e-6) / 1e9
+    return dict(kernel=kernel, avg_us=round(us, 1), bytes_per_launch=int(byts),
+                GBs=round(gbs, 1), hbm_frac=round(gbs / HBM_PEAK_GBS, 4),
+                gflop_per_launch=round(flops / 1e9, 3), GFLOPs=round(gfl, 1),
+                peak_GFLOPs=peak, flop_frac=round(gfl / peak, 4))
 
 
 def batch_bench(apc, torch, steps, tol):
@@ -301,7 +322,6 @@ def batch_bench(apc, torch, steps, tol):
     t_asm = sum(t[0] for t in times) / len(times)
     t_sol = sum(t[1] for t in times) / len(times)
     n_tot = B.n
-    # the same clouds through the single-cloud path, one after the other
     seq = 0.0
     singles = [apc.Cloud(x, **kw) for x in xs]
     for S, c in zip(singles, range(len(singles))):
@@ -344,6 +364,7 @@ def vlasov_bench(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, dt=1e-3)
     gp = torch.empty((3, N), dtype=torch.float64, device="cuda")
     kw = dict(order=cfg["order"], c=cfg["c"], max_depth=cfg["max_depth"], precision=precision)
     acc = None
+    t0 = None
     for it in range(warmup + steps):
         if it == warmup:
             torch.cuda.synchronize()
@@ -352,7 +373,6 @@ def vlasov_bench(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, dt=1e-3)
                             phi_p=pp, grad_p=gp, **kw)
         if st["status"] != 0:
             raise RuntimeError(f"time step did not converge: {st}")
-        log(f"vlasov step {it}: n={st['n']} iters={st['iters']} ms={st['ms']}")
         if it >= warmup:
             acc = dict(st["ms"]) if acc is None else {k: acc[k] + st["ms"][k] for k in acc}
     torch.cuda.synchronize()
@@ -360,7 +380,7 @@ def vlasov_bench(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, dt=1e-3)
     ms = {k: round(t / steps, 3) for k, t in acc.items()}
     push_bytes = 120 * N
     push_gbs = push_bytes / (ms["push"] * 1e-3) / 1e9 if ms["push"] > 0 else 0.0
-    return dict(workload=f"{cfg['N']} particles of the headline beam, {steps} steps of dt {dt}",
+    return dict(workload=f"{N} particles of beam_halo_1e7, {steps} steps of dt {dt}",
                 particles=N, steps=steps, ms_per_step=round(wall * 1e3, 3),
                 particle_steps_per_s=round(N / wall, 1), phases_ms=ms, nodes=st["n"],
                 iters=st["iters"], density_iters=st["density_iters"],
@@ -376,9 +396,7 @@ def paper_beam_bench(apc, torch, cs=(1.0, 0.3, 0.1)):
     """The paper's 3-D beam with halo (1e6 particles in [-1, 1]^3) timed end to end
     (build, assembly, deposit with density solve to 1e-12, Poisson solve to 1e-10
     with Jacobi, interpolation) in FP64 through apc_step with a zero push, at
-    criterion constants giving clouds of about the table's sizes.  The boundary
-    data are zero here (the field's values do not change the work); the accuracy
-    against the benchmark solution is a test."""
+    criterion constants giving clouds of about the table's sizes."""
     from workloads import BEAM3D, paper_beam_3d
     x = torch.from_numpy(paper_beam_3d(1_000_000, seed=1)).cuda()
     v = torch.zeros_like(x)
@@ -397,34 +415,51 @@ def paper_beam_bench(apc, torch, cs=(1.0, 0.3, 0.1)):
         out.append(dict(c=c, nodes=n, iters=st["iters"], density_iters=st["density_iters"],
                         phases_ms=ms, step_ms=round(sum(ms.values()), 3),
                         wall_ms=round(wall, 3), paper_nearest=dict(nodes=near[0], s=near[1])))
-        log(f"paper beam c={c}: {out[-1]}")
     return dict(workload="3-D Gaussian beam with halo of Sec. 5.2, 1e6 particles, FP64",
                 clouds=out)
 
 
-def cpu_baseline(xyz, cfg, iters_full, n_sample_iters=20):
-    """The oracle (plain serial C, FP64) on the same cloud: assembly of all nodes
-    plus `n_sample_iters` BiCGSTAB iterations, the solve time scaled to the
-    iteration count of the plain FP64 GPU solve (same algorithm and matrix)."""
-    import numpy as np
+def cpu_model():
+    try:
+        for line in open("/proc/cpuinfo"):
+            if line.startswith("model name"):
+                return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return platform.processor() or "unknown"
+
+
+def cpu_baseline(cfg, n_full, iters_full, N_sample=1_000_000, depth_sample=5, n_iters=200):
+    """The oracle (plain serial C, FP64, one thread) on a bounded sample of the
+    headline recipe: the same particle recipe, GFD order, criterion constant and
+    stencil rule at octree depth `depth_sample` instead of the full depth, from
+    N_sample of its particles.  Timed: the assembly of every node, and n_iters
+    iterations of the oracle's BiCGSTAB (no preconditioner, as the headline) on
+    the assembled rows.  Per-node costs scale to the headline:
+    nodes/s = 1 / (t_asm / n + iters_full t_it / n)."""
     from oracle.oracle import OracleCloud
+    from workloads import beam_halo
+    xyz = beam_halo(N_sample, seed=cfg["seed"], sigma=cfg["sigma"], halo_frac=cfg["halo_frac"])
     t = time.perf_counter()
-    O = OracleCloud(xyz, order=cfg["order"], c=cfg["c"], max_depth=cfg["max_depth"])
+    O = OracleCloud(xyz, order=cfg["order"], c=cfg["c"], max_depth=depth_sample)
     t_build = time.perf_counter() - t
     t = time.perf_counter()
     w, d = O.assemble()
     t_asm = time.perf_counter() - t
-    rt = O.deposit()  # rho_M stands in for rho~ (same magnitude; only timing matters)
+    rt = O.deposit()  # rho_M stands in for the right-hand side (only timing matters)
     t = time.perf_counter()
-    _, st = O.poisson_solve(rt[:O.n], tol=1e-30, maxit=n_sample_iters, precond=1)
+    _, st = O.bicgstab_rows(w, d, rt[:O.n], tol=1e-30, maxit=n_iters, precond=0)
     t_it = (time.perf_counter() - t) / max(1, st["iters"])
-    t_solve = t_it * iters_full
-    val = O.n / (t_asm + t_solve)
-    return dict(value=round(val, 1), unit="nodes/s", cores=1, kind="oracle",
-                sample=(f"oracle on the same {O.n}-node cloud: assembly of all nodes "
-                        f"({t_asm:.2f} s) + {st['iters']} Jacobi-BiCGSTAB iterations "
-                        f"({t_it * 1e3:.1f} ms each) scaled to {iters_full} iterations; "
-                        f"oracle build {t_build:.1f} s not counted"))
+    per_node = t_asm / O.n + iters_full * t_it / O.n
+    return dict(value=round(1.0 / per_node, 1), unit="nodes/s", cores=1, kind="oracle",
+                nproc=os.cpu_count(), cpu_model=cpu_model(),
+                sample=(f"oracle (serial C, 1 thread) on the headline recipe at depth "
+                        f"{depth_sample} from {N_sample} of its particles: {O.n} nodes; "
+                        f"assembly {t_asm:.2f} s ({t_asm / O.n * 1e6:.1f} us/node), "
+                        f"BiCGSTAB {t_it * 1e3:.2f} ms per iteration "
+                        f"({t_it / O.n * 1e9:.1f} ns/node); scaled to the headline's "
+                        f"{iters_full} iterations per node (n = {n_full}); oracle build "
+                        f"{t_build:.1f} s not counted"))
 
 
 def main():
@@ -432,100 +467,159 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="beam_halo_1e7")
-    ap.add_argument("--precision", default="mixed", choices=["mixed", "fp64", "mixed_f32acc"])
-    ap.add_argument("--precond", default="jacobi", choices=["learned", "jacobi"])
+    ap.add_argument("--workload", default="beam_halo_1e8_k4")
+    ap.add_argument("--precision", default="fp64", choices=["mixed", "fp64", "mixed_f32acc"])
+    ap.add_argument("--precond", default="none", choices=["none", "jacobi", "learned"])
     ap.add_argument("--tol", type=float, default=1e-8)
-    ap.add_argument("--spmv-reps", type=int, default=50)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--no-plain", action="store_true", help="skip the plain FP64 comparison")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the grown forms on the headline workload")
+    ap.add_argument("--no-k2", action="store_true", help="skip the 1e7-particle k = 2 legs")
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-cloud batch")
     ap.add_argument("--no-paper-beam", action="store_true",
                     help="skip the paper's 3-D beam timings")
     ap.add_argument("--no-vlasov", action="store_true",
                     help="skip the Vlasov-Poisson time steps (apc_step)")
-    ap.add_argument("--no-k4", action="store_true",
-                    help="skip the 1e8-particle fourth-order workload (about 90 s)")
+    ap.add_argument("--no-probes", action="store_true", help="skip the bandwidth probes")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
               "the multi-GPU sharding is a design, not an implementation", file=sys.stderr)
         sys.exit(2)
 
-    import numpy as np
     import torch
 
     from paper_1603_04039_amd import apcloud as apc
     from workloads import CONFIGS, beam_halo
 
     apc.load_library()
-    cfg = CONFIGS[args.workload]
     torch.cuda.set_device(0)
-    log(f"generating {args.workload}: N={cfg['N']}")
-    xyz = beam_halo(cfg["N"], seed=cfg["seed"], sigma=cfg["sigma"], halo_frac=cfg["halo_frac"])
-    xyz_d = torch.from_numpy(xyz).cuda()
-    torch.cuda.synchronize()
-
     PREC = {"fp64": apc.APC_FP64, "mixed": apc.APC_MIXED, "mixed_f32acc": apc.APC_MIXED_F32ACC}
+    cfg = CONFIGS[args.workload]
+    log(f"generating {args.workload}: N={cfg['N']}")
+    xyz_d = torch.from_numpy(beam_halo(cfg["N"], seed=cfg["seed"], sigma=cfg["sigma"],
+                                       halo_frac=cfg["halo_frac"])).cuda()
+    torch.cuda.synchronize()
     prec = PREC[args.precision]
-    params = None
-    params_src = None
-    if args.precond == "learned" or not args.no_plain:
-        params, params_src = load_params(apc, torch, cfg["order"])
-    log(f"timed steps ({args.precision}, {args.precond}): warmup={args.warmup} steps={args.steps}")
-    ms, info, ms_step, cloud, phi = run_steps(apc, torch, xyz_d, cfg, prec, args.steps,
-                                              args.warmup, args.tol, args.precond, params)
-    t_metric = (ms["assemble"] + ms["install"] + ms["solve"]) * 1e-3
-    value = info["n"] / t_metric
-    log(f"{args.precision}/{args.precond}: n={info['n']} iters={info['iters']} phases(ms)={ms}")
-    roof = spmv_roofline(torch, cloud, args.spmv_reps, prec != apc.APC_FP64, args.workload)
-    roof["stream_copy"] = stream_probe(torch)
-    if roof["traffic"] is not None:
-        # the counted HBM bytes per launch over the launch time, against the copy probe
-        roof["traffic_GBs"] = round(roof["traffic"] / (roof["avg_us"] * 1e-6) / 1e9, 1)
-        roof["traffic_vs_copy"] = round(roof["traffic_GBs"] / roof["stream_copy"]["GBs"], 3)
-    log(f"spmv roofline: {roof}")
-    roof_m = None
-    if args.precond == "learned":
-        roof_m = precond_roofline(torch, cloud, args.spmv_reps)
-        log(f"precond roofline: {roof_m}")
-    # last: re-assembly drops the learned M
-    roof_a = assembly_roofline(torch, cloud, 10 if cloud.n < 5_000_000 else 3,
-                               prec != apc.APC_FP64)
-    log(f"assembly roofline: {roof_a}")
-    cloud.close()
+    params = {}
 
-    plain = None
-    jac = None
+    def params_for(order):
+        if order not in params:
+            params[order] = load_params(apc, torch, order)
+        return params[order][0]
+
+    # ---- headline
+    log(f"timed steps ({args.precision}, {args.precond}): warmup={args.warmup} steps={args.steps}")
+    ms, info, wall, last = run_steps(
+        apc, torch, xyz_d, cfg, prec, args.steps, args.warmup, args.tol, args.precond,
+        params_for(cfg["order"]) if args.precond == "learned" else None, keep_last=True)
+    value = nodes_per_s(ms, info)
+    log(f"headline: {value:.4g} nodes/s, phases {ms}, iters {info['iters']}")
+    cloud, _ = last
+    vb = 8 if prec == apc.APC_FP64 else 4
+    b_survey, b_layout = spmv_bytes(cloud, info, vb, index_bytes(cloud))
+    avg_us = info["spmv_avg_us"]
+    gbs = b_survey / (avg_us * 1e-6) / 1e9
+    pmc_name = f"k_spmv_{args.workload}_{args.precision}_hbm_counters.md"
+    traffic = counted_traffic(pmc_name)
+    mode = {"fp64": "V64", "mixed": "V32A64", "mixed_f32acc": "V32A32"}[args.precision]
+    roof = dict(bound="hbm", achieved=round(gbs, 1), peak=HBM_PEAK_GBS, unit="GB/s",
+                frac=round(gbs / HBM_PEAK_GBS, 4),
+                traffic=None if traffic is None else int(traffic),
+                kernel=f"k_spmv_v<{mode}> and k_spmv_t<{mode}> (BiCGSTAB operator SpMVs, "
+                       "sliced layout)",
+                avg_us=round(avg_us, 2), launches_per_step=info["spmv_launches_per_step"],
+                bytes_per_launch=b_survey, layout_bytes_per_launch=b_layout,
+                layout_GBs=round(b_layout / (avg_us * 1e-6) / 1e9, 1),
+                timing="HIP events around every SpMV launch of the timed solves, on the "
+                       "library's stream")
+    if traffic is not None:
+        roof["traffic_GBs"] = round(traffic / (avg_us * 1e-6) / 1e9, 1)
+    log(f"roofline: {roof}")
+    roof_a = assembly_roofline(torch, cloud, 2 if cloud.n > 2_000_000 else 10,
+                               prec != apc.APC_FP64)
+    log(f"assembly: {roof_a}")
+    t_build_inc = (ms["build"] + ms["assemble"] + ms["install"] + ms["solve"]) * 1e-3
+    cloud.close()
+    del last, cloud
+
+    # ---- grown forms on the headline workload (one timed step each; the kernels
+    # are warm from the headline steps)
     variants = {}
-    iters_fp64 = info["iters"]
-    if not args.no_plain:
-        todo = [("fp64", "jacobi"), ("mixed", "jacobi"), ("mixed", "learned"),
-                ("mixed_f32acc", "jacobi")]
+    if not args.no_variants:
+        todo = [("mixed", "none"), ("mixed", "learned"), ("mixed", "jacobi"), ("fp64", "jacobi")]
         for name, pcn in todo:
             if (PREC[name], pcn) == (prec, args.precond):
                 continue
-            log(f"comparison variant {name}/{pcn}")
-            msv, infov, _, cv, _ = run_steps(apc, torch, xyz_d, cfg, PREC[name],
-                                             max(2, args.steps // 2), 1, args.tol, pcn, params)
-            cv.close()
-            vv = infov["n"] / ((msv["assemble"] + msv["install"] + msv["solve"]) * 1e-3)
-            key = f"{name}_{pcn}"
-            variants[key] = dict(nodes_per_s=round(vv, 1), iters=infov["iters"],
-                                 sweeps=infov["sweeps"], assemble_ms=round(msv["assemble"], 3),
-                                 solve_ms=round(msv["solve"], 3))
-            if key == "fp64_jacobi":
-                plain = variants[key]
-                iters_fp64 = infov["iters"]
-            if key == f"{args.precision}_jacobi":
-                jac = variants[key]
-            if pcn == "learned":
-                variants[key]["install_ms"] = round(msv["install"], 3)
+            log(f"variant {name}/{pcn}")
+            msv, infov, wallv, lastv = run_steps(
+                apc, torch, xyz_d, cfg, PREC[name], 1, 0, args.tol, pcn,
+                params_for(cfg["order"]) if pcn == "learned" else None,
+                keep_last=(name, pcn) == ("mixed", "none"))
+            variants[f"{name}_{pcn}"] = leg(msv, infov, wallv)
+            if lastv is not None:
+                r64, rown = fp64_reference_residual(apc, torch, lastv[0], lastv[1], args.tol)
+                variants[f"{name}_{pcn}"]["rel_resid_fp64ref"] = r64
+                lastv[0].close()
+            log(f"variant {name}/{pcn}: {variants[f'{name}_{pcn}']}")
+    plain = value if (args.precision, args.precond) == ("fp64", "none") else None
+
+    def speedup(key):
+        v = variants.get(key)
+        return None if v is None or plain is None else round(v["nodes_per_s"] / plain, 3)
+    del xyz_d
+    torch.cuda.empty_cache()
+
+    # ---- second-order workload at 1e7 particles (five variants)
+    k2 = None
+    if not args.no_k2 and args.workload != "beam_halo_1e7":
+        c2 = CONFIGS["beam_halo_1e7"]
+        log("beam_halo_1e7 legs")
+        x2 = torch.from_numpy(beam_halo(c2["N"], seed=c2["seed"], sigma=c2["sigma"],
+                                        halo_frac=c2["halo_frac"])).cuda()
+        k2 = dict(workload="beam_halo_1e7", particles=c2["N"], order=2,
+                  max_depth=c2["max_depth"], c=c2["c"])
+        for name, pcn in (("fp64", "none"), ("fp64", "jacobi"), ("mixed", "none"),
+                          ("mixed", "jacobi"), ("mixed", "learned")):
+            ms2, info2, wall2, last2 = run_steps(
+                apc, torch, x2, c2, PREC[name], 5, 2, args.tol, pcn,
+                params_for(2) if pcn == "learned" else None, keep_last=True)
+            k2[f"{name}_{pcn}"] = leg(ms2, info2, wall2)
+            cl2, rt2 = last2
+            k2["nodes"], k2["nnz"] = info2["n"], info2["nnz"]
+            if (name, pcn) == ("mixed", "jacobi"):
+                sb, lb = spmv_bytes(cl2, info2, 4, index_bytes(cl2))
+                au = info2["spmv_avg_us"]
+                k2["spmv_mixed"] = dict(avg_us=round(au, 2), bytes_per_launch=sb,
+                                        GBs=round(sb / (au * 1e-6) / 1e9, 1),
+                                        frac=round(sb / (au * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                                        layout_bytes_per_launch=lb,
+                                        layout_GBs=round(lb / (au * 1e-6) / 1e9, 1))
+                k2["assembly_mixed"] = assembly_roofline(torch, cl2, 10, True)
+            if (name, pcn) == ("mixed", "none"):
+                r64, _ = fp64_reference_residual(apc, torch, cl2, rt2, args.tol)
+                k2[f"{name}_{pcn}"]["rel_resid_fp64ref"] = r64
+            cl2.close()
+            log(f"k2 {name}/{pcn}: {k2[f'{name}_{pcn}']}")
+        base = k2["fp64_none"]["nodes_per_s"]
+        k2["speedup_mixed_vs_plain"] = round(k2["mixed_none"]["nodes_per_s"] / base, 3)
+        k2["speedup_mixed_learned_vs_plain"] = round(k2["mixed_learned"]["nodes_per_s"] / base, 3)
+        k2["speedup_learned_vs_jacobi"] = round(
+            k2["mixed_learned"]["nodes_per_s"] / k2["mixed_jacobi"]["nodes_per_s"], 3)
+        vlasov = None
+        if not args.no_vlasov:
+            log("Vlasov-Poisson time steps")
+            vlasov = vlasov_bench(apc, torch, x2, c2, apc.APC_MIXED, 5, 1, args.tol)
+            log(f"vlasov: {vlasov}")
+        del x2
+        torch.cuda.empty_cache()
+    else:
+        vlasov = None
 
     batch = None
     if not args.no_batch:
         log("64-cloud batch")
-        batch = batch_bench(apc, torch, max(2, args.steps // 2), args.tol)
+        batch = batch_bench(apc, torch, 3, args.tol)
         log(f"batch: {batch}")
 
     pbeam = None
@@ -533,58 +627,16 @@ def main():
         log("paper's 3-D beam with halo")
         pbeam = paper_beam_bench(apc, torch)
 
-    vlasov = None
-    if not args.no_vlasov:
-        log("Vlasov-Poisson time steps")
-        vlasov = vlasov_bench(apc, torch, xyz_d, cfg, prec, max(2, args.steps), 1, args.tol)
-        log(f"vlasov: {vlasov}")
-
-    k4 = None
-    if not args.no_k4 and args.workload != "beam_halo_1e8_k4":
-        log("fourth-order workload beam_halo_1e8_k4 (one timed step)")
-        try:
-            c4 = CONFIGS["beam_halo_1e8_k4"]
-            x4 = torch.from_numpy(beam_halo(c4["N"], seed=c4["seed"], sigma=c4["sigma"],
-                                            halo_frac=c4["halo_frac"])).cuda()
-            ms4, info4, _, cl4, _ = run_steps(apc, torch, x4, c4, apc.APC_MIXED, 1, 0, args.tol)
-            r4 = spmv_roofline(torch, cl4, 10, True, "beam_halo_1e8_k4")
-            a4 = assembly_roofline(torch, cl4, 2, True)
-            cl4.close()
-
-            def leg(ms, info):
-                t = (ms["assemble"] + ms["install"] + ms["solve"]) * 1e-3
-                return dict(nodes_per_s=round(info["n"] / t, 1),
-                            phases_ms={k: round(v, 1) for k, v in ms.items()},
-                            iters=info["iters"], sweeps=info["sweeps"],
-                            density_iters=info["density_iters"],
-                            rel_resid_true=info["rel_resid_true"])
-            k4 = dict(workload="beam_halo_1e8_k4", particles=c4["N"], nodes=info4["n"],
-                      nnz=info4["nnz"], order=4, max_depth=c4["max_depth"], c=c4["c"],
-                      precision="mixed", jacobi=leg(ms4, info4),
-                      spmv=dict(avg_us=r4["avg_us"], GBs=r4["achieved"], frac=r4["frac"]),
-                      assembly=a4)
-            log(f"k4 jacobi: {k4['jacobi']}")
-            p4, p4src = load_params(apc, torch, 4)
-            ms4l, info4l, _, cl4, _ = run_steps(apc, torch, x4, c4, apc.APC_MIXED, 1, 0, args.tol,
-                                                "learned", p4)
-            r4m = precond_roofline(torch, cl4, 10)
-            cl4.close()
-            del x4
-            k4["learned"] = leg(ms4l, info4l)
-            k4["learned"]["params"] = p4src
-            k4["learned"]["m_apply"] = dict(avg_us=r4m["avg_us"], GBs=r4m["achieved"],
-                                            frac=r4m["frac"])
-            k4["speedup_learned_vs_jacobi"] = round(
-                k4["learned"]["nodes_per_s"] / k4["jacobi"]["nodes_per_s"], 3)
-        except Exception as e:  # reported, never hides the headline
-            k4 = dict(workload="beam_halo_1e8_k4", error=str(e)[:300])
-        log(f"k4: {k4}")
-        torch.cuda.empty_cache()
+    probes = None
+    if not args.no_probes:
+        probes = dict(copy_1GiB=copy_probe(torch), read=read_probe(torch))
+        log(f"probes: {probes}")
 
     cpu = None
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle)")
-        cpu = cpu_baseline(xyz, cfg, iters_fp64)
+        cpu = cpu_baseline(cfg, info["n"], info["iters"])
+        log(f"cpu baseline: {cpu}")
 
     out = {
         "metric": METRIC,
@@ -593,7 +645,7 @@ def main():
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": round(ms_step, 3),
+        "ms_per_step": round(wall, 3),
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
@@ -606,31 +658,32 @@ def main():
         "phases_ms": {k: round(v, 3) for k, v in ms.items()},
         "solve": {"iters": info["iters"], "sweeps": info["sweeps"],
                   "rel_resid_true": info["rel_resid_true"],
+                  "rel_resid_fp64ref": info["rel_resid_fp64ref"],
                   "density_iters": info["density_iters"]},
+        "nodes_per_s_incl_build": round(info["n"] / t_build_inc, 1),
         "roofline": roof,
         "roofline_assembly": roof_a,
         "cpu_baseline": cpu,
     }
-    if batch is not None:
-        out["batch"] = batch
-    if vlasov is not None:
-        out["vlasov"] = vlasov
-    if pbeam is not None:
-        out["paper_beam3d"] = pbeam
-    if k4 is not None:
-        out["k4"] = k4
-    if roof_m is not None:
-        out["roofline_precond"] = roof_m
-        out["learned_params"] = params_src
     if variants:
         out["variants"] = variants
-    if plain is not None:
-        out["speedup_vs_plain_fp64_jacobi"] = round(value / plain["nodes_per_s"], 3)
-    if jac is not None:
-        out["speedup_learned_vs_jacobi"] = round(value / jac["nodes_per_s"], 3)
-    lv = variants.get(f"{args.precision}_learned")
-    if lv is not None and args.precond == "jacobi":
-        out["speedup_learned_vs_jacobi"] = round(lv["nodes_per_s"] / value, 3)
+        out["speedup_mixed_vs_plain"] = speedup("mixed_none")
+        out["speedup_mixed_learned_vs_plain"] = speedup("mixed_learned")
+        if "mixed_learned" in variants and "mixed_jacobi" in variants:
+            out["speedup_learned_vs_jacobi"] = round(
+                variants["mixed_learned"]["nodes_per_s"] / variants["mixed_jacobi"]["nodes_per_s"],
+                3)
+        out["learned_params"] = {o: p[1] for o, p in params.items()}
+    if k2 is not None:
+        out["k2"] = k2
+    if vlasov is not None:
+        out["vlasov"] = vlasov
+    if batch is not None:
+        out["batch"] = batch
+    if pbeam is not None:
+        out["paper_beam3d"] = pbeam
+    if probes is not None:
+        out["probes"] = probes
     print(json.dumps(out), flush=True)
 
 

@@ -1208,6 +1208,15 @@ int apco_poisson_solve(const apco_cloud *C, const double *rho_t, const double *g
   return rc;
 }
 
+/* BiCGSTAB on rows the caller assembled (apco_assemble or apco_density_rows) and
+   an interior right-hand side: the solver of apco_poisson_solve without the
+   assembly, so that the two can be timed apart. */
+int apco_bicgstab_rows(const apco_cloud *C, const double *w, const double *diag,
+                       const double *rhs, double *x, double tol, int maxit, int precond,
+                       apco_stats *st) {
+  return bicgstab(C, diag, w, rhs, x, tol, maxit, precond, st);
+}
+
 int apco_poisson_lu(const apco_cloud *C, const double *rho_t, const double *g, double *phi) {
   int64_t n = C->n;
   double *w = NULL, *diag = NULL, *rhs = NULL;

@@ -97,6 +97,11 @@ int apco_wls_fit(int order, int m, const double *delta, double *X, double *h, do
 /* Poisson rows: off-diagonal weights w (nnz, aligned with the stencil CSR) and the
    diagonal (n), so that (L f)_i = diag_i f_i + sum_j w_ij f_j. */
 int apco_assemble(const apco_cloud *C, double *w, double *diag);
+/* BiCGSTAB (the solver of apco_poisson_solve) on caller-assembled rows w/diag and
+   an interior right-hand side rhs (n); x (n) receives the solution. */
+int apco_bicgstab_rows(const apco_cloud *C, const double *w, const double *diag,
+                       const double *rhs, double *x, double tol, int maxit, int precond,
+                       apco_stats *st);
 /* Density rows B (eq. density_linear_system), same layout, with the stability
    rule: a row is kept when sum_j |b_j| <= 0.5 b_ii; an order-4 row that fails
    is replaced by the order-2 row of the same stencil, and a row that still fails

@@ -63,6 +63,8 @@ def _load():
     lib.apco_poisson_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int,
                                        ct.POINTER(_Stats)]
     lib.apco_poisson_lu.argtypes = [P, P, P, P]
+    lib.apco_bicgstab_rows.argtypes = [P, P, P, P, P, ct.c_double, ct.c_int, ct.c_int,
+                                       ct.POINTER(_Stats)]
     lib.apco_apply_laplacian.argtypes = [P, P, P]
     lib.apco_node_derivs.argtypes = [P, P, P]
     lib.apco_interpolate.argtypes = [P, P, P, P, P]
@@ -287,6 +289,18 @@ class OracleCloud:
                                            precond, ct.byref(st)), "poisson_solve")
         return out, dict(iters=st.iters, status=st.status, rel_resid=st.rel_resid,
                          rel_resid_true=st.rel_resid_true)
+
+    def bicgstab_rows(self, w, diag, rhs, tol=1e-12, maxit=20000, precond=0):
+        """The oracle's BiCGSTAB on rows assembled beforehand (no assembly inside)."""
+        w = np.ascontiguousarray(w, dtype=np.float64)
+        diag = np.ascontiguousarray(diag, dtype=np.float64)
+        rhs = np.ascontiguousarray(rhs, dtype=np.float64)
+        x = np.zeros(self.n)
+        st = _Stats()
+        _check(self.lib.apco_bicgstab_rows(self.h, _ptr(w), _ptr(diag), _ptr(rhs), _ptr(x), tol,
+                                           maxit, precond, ct.byref(st)), "bicgstab_rows")
+        return x, dict(iters=st.iters, status=st.status, rel_resid=st.rel_resid,
+                       rel_resid_true=st.rel_resid_true)
 
     def poisson_lu(self, rho_t, g=None):
         rho_t = np.ascontiguousarray(rho_t, dtype=np.float64)
