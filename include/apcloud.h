@@ -327,9 +327,10 @@ int apc_mlp_infer(apc_cloud *c, const float *params, const float *feat, int bf16
    inference with FP32 accumulation, then M stored in the solver's sliced layout
    (FP32).  Rows whose stencil is the uniform same-level 2-ring have identical
    features at a given level; M keeps one row per level for them (the network's
-   output for the first such row of that level).
+   output for the first such row of that level) and each such row's safeguard
+   weight alpha_i below.
    Safeguard (Z != NULL): K probe vectors Z (K x (n+nb) float64, boundary
-   entries ignored).  Every other row becomes m_i = j_i + alpha_i (m_i - j_i),
+   entries ignored).  Every row becomes m_i = j_i + alpha_i (m_i - j_i),
    j_i the Jacobi row, with alpha_i in [0, 1] minimising the probe estimate
    sum_k ((j_i + alpha (m_i - j_i))^T A z_k - z_ki)^2 (alpha_i = 1 when the two
    rows agree), so that rows the network does not know fall back towards

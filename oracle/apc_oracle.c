@@ -1522,10 +1522,9 @@ int apco_mlp_forward(const double *P, const double *feat, int64_t nrow, double *
 
 /* Rows of M: the network output on every row (m_i = (e_0 + o_i) / d_i on the
    operator's pattern, boundary columns 0), then, with probes, the safeguard
-   m_i <- j_i + alpha_i (m_i - j_i) on every row that is not a uniform 2-ring
-   row of a second-order cloud (24 stencil nodes at offsets, in cells of the
-   row's level, with components in {0, 1, 2} and L1 norm <= 2).  Rows longer
-   than 40 stencil nodes (fourth order) keep their first 40, the nearest. */
+   m_i <- j_i + alpha_i (m_i - j_i) on every row, alpha_i in [0, 1] minimising the
+   row's probe loss.  Rows longer than 40 stencil nodes (fourth order) keep their
+   first 40, the nearest. */
 int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, int K,
                    double *mdiag, double *mw) {
   int64_t n = C->n, ntot = C->n + C->nb, nnz = C->st_off[n];
@@ -1533,15 +1532,13 @@ int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, i
   double *d = malloc((size_t)(n + 1) * sizeof(double));
   double *feat = malloc((size_t)(n + 1) * LIN * sizeof(double));
   double *o = malloc((size_t)(n + 1) * LOUT * sizeof(double));
-  int32_t *ixyz = malloc((size_t)(3 * ntot + 1) * sizeof(int32_t));
   double *U = (Z && K > 0) ? malloc((size_t)K * n * sizeof(double)) : NULL;
-  int rc = (!w || !d || !feat || !o || !ixyz || (Z && K > 0 && !U)) ? APCO_ENOMEM : 0;
+  int rc = (!w || !d || !feat || !o || (Z && K > 0 && !U)) ? APCO_ENOMEM : 0;
   if (!rc) rc = apco_assemble(C, w, d);
   if (!rc) rc = apco_learn_data(C, NULL, 0, feat, NULL);
   if (!rc) rc = apco_mlp_forward(params, feat, n, o);
-  if (!rc) rc = apco_node_coords(C, ixyz);
   if (rc) {
-    free(w); free(d); free(feat); free(o); free(ixyz); free(U);
+    free(w); free(d); free(feat); free(o); free(U);
     return rc;
   }
   for (int64_t i = 0; i < n; i++) {
@@ -1565,20 +1562,6 @@ int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, i
   for (int64_t i = 0; U && i < n; i++) {
     int32_t a = C->st_off[i];
     int m = C->st_off[i + 1] - a;
-    /* per-level shared rows exist only in second-order clouds */
-    int uniform = C->P.order == 2 && m == 24;
-    int lv = C->cells[C->node_cell[i]].level;
-    int32_t sp = 1 << (C->P.max_depth - lv + 1);
-    for (int j = 0; j < m && uniform; j++) {
-      int32_t v = C->st[a + j], l1 = 0;
-      for (int c = 0; c < 3; c++) {
-        int32_t dd = abs(ixyz[c * ntot + v] - ixyz[c * ntot + i]);
-        uniform = uniform && (dd == 0 || dd == sp || dd == 2 * sp);
-        l1 += dd;
-      }
-      uniform = uniform && l1 <= 2 * sp;
-    }
-    if (uniform) continue;
     double jd = 1.0 / d[i], st = 0.0, tt = 0.0;
     for (int k = 0; k < K; k++) {
       const double *Uk = U + (int64_t)k * n;
@@ -1596,7 +1579,7 @@ int apco_learned_m(const apco_cloud *C, const double *params, const double *Z, i
     mdiag[i] = jd + al * (mdiag[i] - jd);
     for (int p = 1; p <= m; p++) mw[a + p - 1] *= al;
   }
-  free(w); free(d); free(feat); free(o); free(ixyz); free(U);
+  free(w); free(d); free(feat); free(o); free(U);
   return 0;
 }
 

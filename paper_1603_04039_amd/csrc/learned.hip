@@ -24,7 +24,8 @@ constexpr int NQ = APC_LEARN_QUAD;
 static_assert(NQ == NQQ + OUT + 1, "quadratic data layout");
 constexpr int NW = 40; // stencil-weight feature slots (= OUT - 1)
 static_assert(NW == OUT - 1, "pattern");
-constexpr int NT = 25; // per-level row of M for uniform 2-ring rows
+constexpr int NT = 26; // per-level row of M for uniform 2-ring rows: the diagonal, the 24
+                       // stencil entries, and 1 / d (the level's Jacobi row, for the safeguard)
 // parameter offsets
 constexpr int OW1 = 0, OB1 = OW1 + IN * HID, OW2 = OB1 + HID, OB2 = OW2 + HID * HID,
               OW3 = OB2 + HID, OB3 = OW3 + HID * OUT, NPAR = OB3 + OUT;
@@ -392,7 +393,13 @@ __global__ void __launch_bounds__(WPB * 64)
   for (int64_t s0 = (int64_t)blockIdx.x * WPB + wv; s0 < in.nsl; s0 += (int64_t)gridDim.x * WPB) {
     const int64_t s = __builtin_amdgcn_readfirstlane((int)s0);
     const bool tmpl = io.mode == 2 ? true : in.sl_tmpl[s] != 0;
-    if (io.mode == 1 && tmpl) continue; // uniform slices use the per-level rows
+    if (io.mode == 1 && tmpl) {
+      // uniform slices use the per-level rows; m_diag holds each row's safeguard
+      // weight alpha (1: the network's row)
+      const int32_t row = in.sl_rows[s * APC_SLICE + l];
+      if (row >= 0) io.m_diag[row] = 1.0f;
+      continue;
+    }
     const int32_t *tab = io.mode == 2 ? in.rows_tab : in.sl_rows + s * APC_SLICE;
     {
       const int32_t row = tab[l];
@@ -475,7 +482,8 @@ __global__ void __launch_bounds__(WPB * 64)
         }
         const double inv = 1.0 / in.r.diag[rr];
         if (io.mode == 2) {
-          if (p < NT) io.m_tmpl[NT * (int)in.r.rk[rr] + p] = (float)(((p == 0 ? 1.0 : 0.0) + (double)o) * inv);
+          if (p < NT - 1) io.m_tmpl[NT * (int)in.r.rk[rr] + p] = (float)(((p == 0 ? 1.0 : 0.0) + (double)o) * inv);
+          if (p == NT - 1) io.m_tmpl[NT * (int)in.r.rk[rr] + p] = (float)inv;
           continue;
         }
         if (p == 0) {
@@ -494,23 +502,46 @@ __global__ void __launch_bounds__(WPB * 64)
   }
 }
 
-// Safeguard of the general rows: alpha_i in [0, 1] minimising
+// Safeguard of every row: alpha_i in [0, 1] minimising
 // sum_k (s_k + alpha t_k)^2 with s_k = U_k[i] / d_i - z_ki (the Jacobi row's probe
 // residual) and t_k = (m_i - j_i)^T U_k, then m_i <- j_i + alpha (m_i - j_i).
-// One wavefront per general slice, one lane per row; U = A Z (K x ntot).
+// One wavefront per slice, one lane per row; U = A Z (K x ntot).  General rows
+// are scaled in place; a uniform 2-ring row keeps its level's row T of M and
+// stores alpha in m_diag (the apply forms alpha T + (1 - alpha) j_i).
 __global__ void __launch_bounds__(APC_BLOCK)
     k_safeguard(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_tmpl,
                 const int32_t *__restrict__ sl_len, const int32_t *__restrict__ sl_idx,
                 const int64_t *__restrict__ sl_off, int64_t nsl, const double *__restrict__ diag,
+                const int8_t *__restrict__ rk, const float *__restrict__ m_tmpl,
                 const double *__restrict__ Z, const double *__restrict__ U, int K, int64_t n,
                 int64_t ntot, float *__restrict__ m_diag, float *__restrict__ m_sell) {
   const int64_t s0 = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
   if (s0 >= nsl) return;
   const int64_t s = __builtin_amdgcn_readfirstlane((int)s0);
-  if (sl_tmpl[s]) return;
   const int lane = threadIdx.x & 63;
   const int32_t row = sl_rows[s * APC_SLICE + lane];
   if (row < 0) return;
+  if (sl_tmpl[s]) {
+    const float *T = m_tmpl + NT * (int)rk[row];
+    const int64_t off = sl_off[s] + lane;
+    const double jd = 1.0 / diag[row];
+    const double dd = (double)T[0] - jd;
+    double st = 0.0, tt = 0.0;
+    for (int k = 0; k < K; k++) {
+      const double *Uk = U + (int64_t)k * ntot;
+      const double ui = Uk[row];
+      const double sk = ui * jd - Z[(int64_t)k * ntot + row];
+      double tk = dd * ui;
+      for (int e = 0; e < 24; e++) // the 24 neighbours are interior nodes
+        tk += (double)T[e + 1] * Uk[sl_idx[off + (int64_t)e * APC_SLICE]];
+      st += sk * tk;
+      tt += tk * tk;
+    }
+    double a = tt > 0.0 ? -st / tt : 1.0;
+    a = a < 0.0 ? 0.0 : (a > 1.0 ? 1.0 : a);
+    m_diag[row] = (float)a;
+    return;
+  }
   const int len = min(sl_len[s], NW); // M holds the first NW stencil entries
   const int64_t off = sl_off[s] + lane;
   const double jd = 1.0 / diag[row];
@@ -762,7 +793,8 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
     }
     hipLaunchKernelGGL(k_safeguard, dim3(grid_for(c->nsl, APC_BLOCK / 64)), dim3(APC_BLOCK), 0, s,
                        c->sl_rows, c->sl_tmpl, c->sl_len, c->sl_idx, c->sl_off, c->nsl, c->diag,
-                       (const double *)Zc, (const double *)U, K, n, ntot, c->m_diag, c->m_sell);
+                       (const int8_t *)c->rkind, (const float *)c->m_tmpl, (const double *)Zc,
+                       (const double *)U, K, n, ntot, c->m_diag, c->m_sell);
     HIPCHK(hipGetLastError());
     HIPCHK(apc_free_async(U, s));
     HIPCHK(apc_free_async(Zc, s));

@@ -220,11 +220,14 @@ __device__ __forceinline__ void prec_slice(const Op &op, const MOp &M, const dou
     }
     const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return;
-    const float *__restrict__ T = M.tmpl + 25 * (int)op.rk[row];
+    // the level's row T of M (diagonal, 24 entries, then 1 / d) and the row's
+    // safeguard weight alpha: M_i = alpha T + (1 - alpha) e_i / d
+    const float *__restrict__ T = M.tmpl + 26 * (int)op.rk[row];
     double acc = (double)T[0] * in[row];
 #pragma unroll
     for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * (STG ? tile[jj[k]] : in[jj[k]]);
-    out[row] = acc;
+    const float a = M.diag[row];
+    out[row] = a == 1.0f ? acc : (double)a * acc + (1.0 - (double)a) * ((double)T[25] * in[row]);
   } else {
     // M holds the first APC_MLP_OUT - 1 stencil entries of a row (all of them
     // for k = 2; the nearest 40 of the up to 56 of k = 4)

@@ -244,10 +244,12 @@ def test_learned_m_safeguard_minimises_probe_loss(oracle_mod, small_cloud):
                                    rtol=1e-12, atol=1e-300)
 
 
-def test_learned_m_uniform_rows_untouched(oracle_mod):
+def test_learned_m_uniform_rows(oracle_mod):
     """On a uniform lattice the interior rows two cells away from the boundary
-    have the uniform 2-ring stencil; the safeguard leaves them as the network
-    gives them, and the network gives them all the same scaled row."""
+    have the uniform 2-ring stencil and identical features: the network gives
+    them all the same scaled row.  The safeguard treats them like every other
+    row: each moves along its own segment towards the Jacobi row, never worse
+    than either end under its probe loss."""
     from workloads import uniform_lattice_points
     C = oracle_mod.OracleCloud(uniform_lattice_points(4), order=2, c=1e-3, max_depth=4)
     rng = np.random.default_rng(7)
@@ -260,10 +262,18 @@ def test_learned_m_uniform_rows_untouched(oracle_mod):
     lo, hi = ix.min(axis=1), ix.max(axis=1)
     inner = np.all((ix >= lo[:, None] + 2 * sp) & (ix <= hi[:, None] - 2 * sp), axis=0)
     assert inner.sum() == 12 ** 3  # nodes 2..13 of 0..15 along each axis
-    _, d = C.assemble()
-    np.testing.assert_array_equal(md1[inner], md0[inner])
+    w, d = C.assemble()
     scaled = md0[inner] * d[inner]
     np.testing.assert_allclose(scaled, scaled[0], rtol=1e-12)
+    nd = C.nodes()
+    off, idx = nd["st_off"], nd["st_idx"]
+    Lj = _probe_losses(C, w, d, off, idx, Z, 1.0 / d, np.zeros_like(w))
+    L0 = _probe_losses(C, w, d, off, idx, Z, md0, mw0)
+    L1 = _probe_losses(C, w, d, off, idx, Z, md1, mw1)
+    assert np.all(L1[inner] <= np.minimum(Lj, L0)[inner] + 1e-9 * (Lj + L0)[inner])
+    a = (md1 - 1.0 / d) / (md0 - 1.0 / d)
+    assert np.all((a[inner] >= -1e-12) & (a[inner] <= 1.0 + 1e-12))
+    assert np.unique(np.round(a[inner], 12)).size > 1  # alpha is per row
 
 
 # ---------------------------------------------------------------- k = 4
