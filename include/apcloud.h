@@ -112,7 +112,9 @@ typedef struct {
   int status;            /* APC_OK or APC_ENOCONV */
   double rel_resid;      /* recursive ||r|| / ||b|| at exit */
   double rel_resid_true; /* ||b - A x|| / ||b|| recomputed in FP64 at exit */
-  int64_t n_fp64_rows;   /* APC_MIXED: stencils refitted in FP64 (R-diagonal test) */
+  int64_t n_fp64_rows;   /* k = 2, APC_MIXED: stencils refitted in FP64 (R-diagonal test);
+                            k = 4: nodes whose normal-equation fit was handed to the
+                            Householder QR */
   double ms;             /* device time of the call, milliseconds */
   int precond_used;      /* preconditioner of the final iteration (Jacobi after a fallback) */
   int pad;

@@ -108,7 +108,7 @@ struct apc_asm_scratch {
   int32_t crd[3 * 25];
   double tc[3];
   int err;
-  int pad;
+  unsigned fb_count; // k = 4 assembly: nodes handed from the normal equations to the QR
   unsigned long long nfp64;
 };
 
@@ -140,6 +140,7 @@ struct apc_cloud {
   double *diag = nullptr, *inv_diag = nullptr; // n
   double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator, k = 2;
                                                // 0 for an identity density row)
+  int32_t *fb_list = nullptr;                  // n (k = 4): nodes the assembly refits by QR
   int8_t *dorder = nullptr;                    // n: order of each density row: the row's
                                                // fit order, 2 (order-4 row replaced by the
                                                // order-2 row of the same stencil) or 0

@@ -521,6 +521,7 @@ int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
   }
   APCCHK(apc_build_sell(c, s));
   if (c->P.order == 4) {
+    HIPCHK(apc_dev_alloc((void **)&c->fb_list, (size_t)(n > 0 ? n : 1) * sizeof(int32_t)));
     const size_t nz = (size_t)(c->nnz > 0 ? c->nnz : 1), ne = (size_t)(c->sl_entries > 0 ? c->sl_entries : 1);
     if (mixed) {
       HIPCHK(apc_dev_alloc((void **)&c->bw32, nz * sizeof(float)));

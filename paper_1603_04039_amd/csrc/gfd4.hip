@@ -367,35 +367,12 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
 }
 
 // ---------------------------------------------------------------- assembly
-// Laplacian and density rows of every node (CSR order); one wavefront per node
-template <bool MIXED, int MR>
-__global__ void __launch_bounds__(WPB4 * 64, 2)
-    k_fit4(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
-           const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
-           const int8_t *__restrict__ rorder, double unit, double L, double *__restrict__ w64,
-           float *__restrict__ w32,
-           double *__restrict__ bw64, float *__restrict__ bw32, double *__restrict__ diag,
-           double *__restrict__ inv_diag, double *__restrict__ hscale, int8_t *__restrict__ dorder,
-           double *__restrict__ w64ref, int *__restrict__ err) {
-  __shared__ Wave4 SH[WPB4];
-  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int64_t y = (int64_t)blockIdx.x * WPB4 + wv;
-  if (y >= n) return;
-  Wave4 &S = SH[wv];
-  const int32_t a0 = st_off[y];
-  const int m = st_off[y + 1] - a0;
-  const int pc = rorder[y] == 4 ? P4 : 9;
-  const Geo g = stencil_rows(S, lane, st_idx + a0, m, crd, ntot, y);
-  wsync();
-  const double ratio = col_qr<MR>(S, lane, pc, pc);
-  if (!(ratio >= APC_TAU_RANK)) {
-    if (lane == 0) *err = 1;
-    return;
-  }
-  const double hp = (double)g.h * unit;
-  const double hc = L / (double)(1 << level[y]);
-  // right-hand sides: Laplacian (unknowns xx = 3, yy = 6, zz = 8) and the cell moments
-  double cl = 0.0, cb = 0.0;
+// Moments of the cell (eq. density_linear_system) over h^|alpha| for unknown `lane`,
+// and the Laplacian's right-hand side (unknowns xx = 3, yy = 6, zz = 8)
+__device__ __forceinline__ void fit_rhs(int lane, int pc, double hc, double hp, double &cl,
+                                        double &cb) {
+  cl = 0.0;
+  cb = 0.0;
   if (lane < pc) {
     int ax, ay, az;
     alpha4(lane, ax, ay, az);
@@ -413,26 +390,27 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
       cb = mom / hk;
     }
   }
-  double ul, ub, zl, zb;
-  solve_rrt(S, lane, pc, cl, cb, ul, ub);
-  wv0_times(S, g, lane, pc, ul, ub, zl, zb);
-  const double wl = lane < m ? g.W * zl / (hp * hp) : 0.0;
-  double wb = lane < m ? g.W * zb : 0.0;
+}
+
+// Writes one node's Laplacian and density rows (lane j: stencil entry j) and its
+// diagonal; the density row goes through the stability rule: kept when
+// sum |b_j| <= theta (1 - sum b_j), else the order-2 row of the same stencil
+// (computed by order2(), which returns it per lane), else the identity row.
+template <bool MIXED, typename Order2>
+__device__ __forceinline__ void write_rows(int lane, int64_t y, int32_t a0, int m, int pc,
+                                           double wl, double wb, double hc, Order2 order2,
+                                           double *__restrict__ w64, float *__restrict__ w32,
+                                           double *__restrict__ bw64, float *__restrict__ bw32,
+                                           double *__restrict__ diag, double *__restrict__ inv_diag,
+                                           double *__restrict__ hscale, int8_t *__restrict__ dorder,
+                                           double *__restrict__ w64ref) {
   const double sw = wsum(wl);
-  // density-row stability: the row is kept when sum |b_j| <= theta (1 - sum b_j);
-  // an order-4 row that fails takes the order-2 row of the same stencil, whose
-  // fit is the leading 9 columns of the same factorisation (moments of order 2
-  // only); a row that still fails becomes the identity row
-  auto row_ok = [&](double b) { return wsum(fabs(b)) <= APC_THETA_B * (1.0 - wsum(b)); };
+  auto row_ok = [&](double v) { return wsum(fabs(v)) <= APC_THETA_B * (1.0 - wsum(v)); };
   int dord = pc == P4 ? 4 : 2;
   if (!row_ok(wb)) {
     dord = 0;
     if (pc == P4) {
-      const double cb2 = (lane == 3 || lane == 6 || lane == 8) ? cb : 0.0;
-      double u2, u0, z2, z0;
-      solve_rrt(S, lane, 9, cb2, 0.0, u2, u0);
-      wv0_times(S, g, lane, 9, u2, u0, z2, z0);
-      wb = lane < m ? g.W * z2 : 0.0;
+      wb = order2();
       if (row_ok(wb)) dord = 2;
     }
     if (dord == 0) wb = 0.0;
@@ -453,6 +431,412 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
     hscale[y] = hc * hc / 24.0;
     dorder[y] = (int8_t)dord;
   }
+}
+
+// Laplacian and density rows by Householder QR (the oracle's algorithm); one
+// wavefront per node.  Runs over the nodes listed in list[0 .. *cnt) (the nodes
+// whose normal-equation fit did not converge, see k_fit4n), grid-stride.
+template <bool MIXED, int MR>
+__global__ void __launch_bounds__(WPB4 * 64, 2)
+    k_fit4(const int32_t *__restrict__ list, const unsigned *__restrict__ cnt,
+           const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+           const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
+           const int8_t *__restrict__ rorder, double unit, double L, double *__restrict__ w64,
+           float *__restrict__ w32,
+           double *__restrict__ bw64, float *__restrict__ bw32, double *__restrict__ diag,
+           double *__restrict__ inv_diag, double *__restrict__ hscale, int8_t *__restrict__ dorder,
+           double *__restrict__ w64ref, int *__restrict__ err) {
+  __shared__ Wave4 SH[WPB4];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  Wave4 &S = SH[wv];
+  const int64_t total = *cnt;
+  for (int64_t t = (int64_t)blockIdx.x * WPB4 + wv; t < total; t += (int64_t)gridDim.x * WPB4) {
+    const int64_t y = list[t];
+    const int32_t a0 = st_off[y];
+    const int m = st_off[y + 1] - a0;
+    const int pc = rorder[y] == 4 ? P4 : 9;
+    const Geo g = stencil_rows(S, lane, st_idx + a0, m, crd, ntot, y);
+    wsync();
+    const double ratio = col_qr<MR>(S, lane, pc, pc);
+    if (!(ratio >= APC_TAU_RANK)) {
+      if (lane == 0) *err = 1;
+      continue;
+    }
+    const double hp = (double)g.h * unit;
+    const double hc = L / (double)(1 << level[y]);
+    double cl, cb;
+    fit_rhs(lane, pc, hc, hp, cl, cb);
+    double ul, ub, zl, zb;
+    solve_rrt(S, lane, pc, cl, cb, ul, ub);
+    wv0_times(S, g, lane, pc, ul, ub, zl, zb);
+    const double wl = lane < m ? g.W * zl / (hp * hp) : 0.0;
+    const double wb = lane < m ? g.W * zb : 0.0;
+    // the order-2 row of the same stencil: the leading 9 columns of the same
+    // factorisation, moments of order 2 only
+    auto order2 = [&]() {
+      const double cb2 = (lane == 3 || lane == 6 || lane == 8) ? cb : 0.0;
+      double u2, u0, z2, z0;
+      solve_rrt(S, lane, 9, cb2, 0.0, u2, u0);
+      wv0_times(S, g, lane, 9, u2, u0, z2, z0);
+      return lane < m ? g.W * z2 : 0.0;
+    };
+    write_rows<MIXED>(lane, y, a0, m, pc, wl, wb, hc, order2, w64, w32, bw64, bw32, diag,
+                      inv_diag, hscale, dorder, w64ref);
+    wsync(); // the next node's rows reuse the LDS
+  }
+}
+
+// the count of nodes refitted by the QR, as the assembly's n_fp64_rows
+__global__ void k_fb_report(const unsigned *cnt, unsigned long long *nfp64) {
+  if (threadIdx.x == 0) *nfp64 = *cnt;
+}
+
+// ---------------------------------------------------------------- normal equations on MFMA
+// The same rows from the normal equations G z = c, G = (W V0)^T (W V0), with
+// iterative refinement: A = W V0 (m x pc, one stencil row per lane) is staged in
+// LDS column-major; G is formed on the matrix cores (v_mfma_f64_16x16x4f64, 16 x 16
+// blocks of G, 4 stencil rows per step; lane l of a block product holds entries
+// ((l >> 4) + 4 e, l & 15), e < 4); G = L L^T by Cholesky with one row of G per lane;
+// z = G^-1 c, then twice r = c - A^T (A z) (the product A^T y again on the matrix
+// cores) and z += G^-1 r.  The rows are w_j = W_j (A z)_j, as from the QR, since
+// A G^-1 = Q R^-T.  The normal equations square the condition number of A, the
+// refinement brings the rows back to the accuracy of the QR (their error is that
+// of the residual, kappa(A) eps); a node whose last correction is not below 1e-13
+// of the solution, or whose Cholesky meets a pivot that is not positive, is
+// listed for the Householder kernel above instead.
+typedef double v4d __attribute__((ext_vector_type(4)));
+// wavefronts per block: as many as the 160 KB of LDS per compute unit hold (7 x 21.7 KB
+// for stencils of up to 56 nodes, 6 x 24.5 KB up to 64)
+template <int MR> constexpr int wpbn() { return MR <= 56 ? 7 : 6; }
+constexpr int NREF = 1; // refinement steps
+
+template <int MR>
+struct WaveN {
+  static constexpr int LDA = MR + 1; // column stride of A (odd: spreads the banks)
+  double A[P4 * LDA];                // W V0 column-major; rows m .. MR-1 are zero
+  double L[P4 * (P4 + 1) / 2];       // G, then its Cholesky factor: packed lower, row-major
+  double y[2 * MR];                  // two stencil-row vectors
+  double z[2 * P4];                  // two unknown-space vectors
+  double cb[64];                     // one column of L, broadcast
+};
+
+__device__ __forceinline__ int tri(int i, int j) { return i * (i + 1) / 2 + j; }
+
+// xi^alpha / alpha! of the 34 unknowns (the order of alpha4), with the factorials
+// as constant reciprocals
+__device__ __forceinline__ void monos_n(double x, double y, double z, double (&mo)[P4]) {
+  constexpr double rf[5] = {1.0, 1.0, 0.5, 1.0 / 6.0, 1.0 / 24.0};
+  double px[5], py[5], pz[5];
+  px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+  for (int e = 1; e <= 4; e++) {
+    px[e] = px[e - 1] * x;
+    py[e] = py[e - 1] * y;
+    pz[e] = pz[e - 1] * z;
+  }
+#pragma unroll
+  for (int e = 2; e <= 4; e++) {
+    px[e] *= rf[e];
+    py[e] *= rf[e];
+    pz[e] *= rf[e];
+  }
+  int k = 0;
+#pragma unroll
+  for (int d = 1; d <= 4; d++)
+#pragma unroll
+    for (int a = d; a >= 0; a--)
+#pragma unroll
+      for (int b = d - a; b >= 0; b--)
+        mo[k++] = px[a] * py[b] * pz[d - a - b];
+}
+
+// Node y's stencil: rows of W V0 into S.A (lanes < MR)
+template <int MR>
+__device__ __forceinline__ Geo stencil_rows_n(WaveN<MR> &S, int lane, const int32_t *nb, int m,
+                                              const int32_t *__restrict__ crd, int64_t ntot,
+                                              int64_t y) {
+  int32_t d0 = 0, d1 = 0, d2 = 0;
+  if (lane < m) {
+    const int32_t v = nb[lane];
+    d0 = crd[v] - crd[y];
+    d1 = crd[ntot + v] - crd[ntot + y];
+    d2 = crd[2 * ntot + v] - crd[2 * ntot + y];
+  }
+  Geo g;
+  g.h = wmax_i(max(abs(d0), max(abs(d1), abs(d2))));
+  const double r2 = (double)((int64_t)d0 * d0 + (int64_t)d1 * d1 + (int64_t)d2 * d2);
+  const double r2max = wmax_d(r2);
+  g.W = 0.0;
+  if (lane < m) {
+    const double e4 = exp(-4.0);
+    g.W = (exp(-r2 / r2max) - e4) / (1.0 - e4);
+  }
+  const double hd = (double)g.h;
+  g.x = (double)d0 / hd;
+  g.y = (double)d1 / hd;
+  g.z = (double)d2 / hd;
+  double mo[P4];
+  monos_n(g.x, g.y, g.z, mo);
+  if (lane < MR) {
+#pragma unroll
+    for (int k = 0; k < P4; k++) S.A[k * WaveN<MR>::LDA + lane] = lane < m ? g.W * mo[k] : 0.0;
+  }
+  return g;
+}
+
+// G = A^T A over the first PC columns into S.L (packed lower)
+template <int MR, int PC>
+__device__ __forceinline__ void gram_mfma(WaveN<MR> &S, int lane) {
+  constexpr int NB = (PC + 15) / 16, NP = NB * (NB + 1) / 2, LDA = WaveN<MR>::LDA;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  v4d acc[NP];
+#pragma unroll
+  for (int q = 0; q < NP; q++) acc[q] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int r0 = 0; r0 < MR; r0 += 4) {
+    double a[NB];
+#pragma unroll
+    for (int I = 0; I < NB; I++) {
+      const int col = 16 * I + i16;
+      a[I] = col < PC ? S.A[col * LDA + r0 + k4] : 0.0;
+    }
+    int q = 0;
+#pragma unroll
+    for (int I = 0; I < NB; I++)
+#pragma unroll
+      for (int J = I; J < NB; J++, q++)
+        acc[q] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[I], a[J], acc[q], 0, 0, 0);
+  }
+  int q = 0;
+#pragma unroll
+  for (int I = 0; I < NB; I++)
+#pragma unroll
+    for (int J = I; J < NB; J++, q++)
+#pragma unroll
+      for (int e = 0; e < 4; e++) {
+        const int row = 16 * I + k4 + 4 * e, col = 16 * J + i16; // entry (row, col) of G
+        if (row < PC && col < PC && col >= row) S.L[tri(col, row)] = acc[q][e];
+      }
+}
+
+// Cholesky G = L L^T with row `lane` of G in g (lanes < PC); on return g holds row
+// `lane` of L, rd = 1 / L_lane,lane, S.L the packed factor.  False when a pivot is
+// not positive.
+template <int MR, int PC>
+__device__ __forceinline__ bool cholesky_n(WaveN<MR> &S, int lane, double (&g)[P4], double &rd) {
+#pragma unroll
+  for (int j = 0; j < P4; j++) g[j] = (j < PC && lane < PC && j <= lane) ? S.L[tri(lane, j)] : 0.0;
+  bool ok = true;
+  rd = 1.0;
+#pragma unroll
+  for (int k = 0; k < PC; k++) {
+    const double pk = rdlane(g[k], k);
+    ok = ok && pk > 0.0;
+    const double d = sqrt(pk), inv = 1.0 / d;
+    if (lane == k) {
+      g[k] = d;
+      rd = inv;
+    } else if (lane > k) {
+      g[k] *= inv;
+    }
+    S.cb[lane] = g[k];
+    wsync();
+#pragma unroll
+    for (int j = k + 1; j < PC; j++)
+      if (lane >= j) g[j] -= g[k] * S.cb[j];
+    wsync();
+  }
+  if (lane < PC)
+#pragma unroll
+    for (int j = 0; j < PC; j++)
+      if (j <= lane) S.L[tri(lane, j)] = g[j];
+  wsync();
+  return ok;
+}
+
+// G z = c for two right-hand sides (lane i < PC holds c0_i, c1_i); returns z in place
+template <int MR, int PC>
+__device__ __forceinline__ void chol_solve_n(const WaveN<MR> &S, int lane, const double (&g)[P4],
+                                             double rd, double &c0, double &c1) {
+  // L y = c (columns of L in the lanes' rows)
+#pragma unroll
+  for (int k = 0; k < PC; k++) {
+    const double ik = rdlane(rd, k);
+    const double y0 = rdlane(c0, k) * ik, y1 = rdlane(c1, k) * ik;
+    if (lane == k) {
+      c0 = y0;
+      c1 = y1;
+    } else if (lane > k) {
+      c0 -= g[k] * y0;
+      c1 -= g[k] * y1;
+    }
+  }
+  // L^T z = y (row k of L from LDS)
+#pragma unroll
+  for (int k = PC - 1; k >= 0; k--) {
+    const double ik = rdlane(rd, k);
+    const double z0 = rdlane(c0, k) * ik, z1 = rdlane(c1, k) * ik;
+    if (lane == k) {
+      c0 = z0;
+      c1 = z1;
+    } else if (lane < k) {
+      const double lki = S.L[tri(k, lane)];
+      c0 -= lki * z0;
+      c1 -= lki * z1;
+    }
+  }
+}
+
+// y = A z for two vectors (z in lanes < PC); y into S.y and returned in the lanes
+template <int MR, int PC>
+__device__ __forceinline__ void a_times_n(WaveN<MR> &S, int lane, double z0, double z1,
+                                          double &y0, double &y1) {
+  constexpr int LDA = WaveN<MR>::LDA;
+  if (lane < PC) {
+    S.z[lane] = z0;
+    S.z[P4 + lane] = z1;
+  }
+  wsync();
+  double s0 = 0.0, s1 = 0.0;
+  if (lane < MR) {
+#pragma unroll
+    for (int c = 0; c < PC; c++) {
+      const double a = S.A[c * LDA + lane];
+      s0 += a * S.z[c];
+      s1 += a * S.z[P4 + c];
+    }
+    S.y[lane] = s0;
+    S.y[MR + lane] = s1;
+  }
+  y0 = s0;
+  y1 = s1;
+  wsync();
+}
+
+// A^T y for the two vectors in S.y, on the matrix cores; returned in lanes < PC
+template <int MR, int PC>
+__device__ __forceinline__ void at_times_n(WaveN<MR> &S, int lane, double &t0, double &t1) {
+  constexpr int NB = (PC + 15) / 16, LDA = WaveN<MR>::LDA;
+  const int i16 = lane & 15, k4 = lane >> 4;
+  v4d acc[NB];
+#pragma unroll
+  for (int I = 0; I < NB; I++) acc[I] = v4d{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int r0 = 0; r0 < MR; r0 += 4) {
+    const double b = i16 < 2 ? S.y[i16 * MR + r0 + k4] : 0.0;
+#pragma unroll
+    for (int I = 0; I < NB; I++) {
+      const int col = 16 * I + i16;
+      const double a = col < PC ? S.A[col * LDA + r0 + k4] : 0.0;
+      acc[I] = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc[I], 0, 0, 0);
+    }
+  }
+#pragma unroll
+  for (int I = 0; I < NB; I++)
+#pragma unroll
+    for (int e = 0; e < 4; e++) {
+      const int row = 16 * I + k4 + 4 * e; // unknown; the column i16 is the vector
+      if (i16 < 2 && row < PC) S.z[i16 * P4 + row] = acc[I][e];
+    }
+  wsync();
+  t0 = lane < PC ? S.z[lane] : 0.0;
+  t1 = lane < PC ? S.z[P4 + lane] : 0.0;
+  wsync();
+}
+
+// z = G^-1 c with NREF refinement steps.  Refinement contracts the error by about
+// rho = kappa(G) eps per step, and the last correction d estimates the error it
+// removed, so the error left is about rho |d| with rho ~ |d| / |z|: the solve is
+// accepted (true) when |d| <= 1e-7 |z| for each right-hand side, which leaves an
+// error of at most about 1e-14 |z|.
+template <int MR, int PC>
+__device__ __forceinline__ bool solve_refined(WaveN<MR> &S, int lane, const double (&g)[P4],
+                                              double rd, double c0, double c1, double &z0,
+                                              double &z1) {
+  z0 = c0;
+  z1 = c1;
+  chol_solve_n<MR, PC>(S, lane, g, rd, z0, z1);
+  bool ok = true;
+  for (int it = 0; it < NREF; it++) {
+    double y0, y1, t0, t1;
+    a_times_n<MR, PC>(S, lane, z0, z1, y0, y1);
+    at_times_n<MR, PC>(S, lane, t0, t1);
+    double r0 = lane < PC ? c0 - t0 : 0.0, r1 = lane < PC ? c1 - t1 : 0.0;
+    chol_solve_n<MR, PC>(S, lane, g, rd, r0, r1);
+    if (lane < PC) {
+      z0 += r0;
+      z1 += r1;
+    }
+    if (it == NREF - 1) {
+      const double d0 = wmax_d(fabs(r0)), d1 = wmax_d(fabs(r1));
+      const double m0 = wmax_d(lane < PC ? fabs(z0) : 0.0), m1 = wmax_d(lane < PC ? fabs(z1) : 0.0);
+      ok = d0 <= 1e-7 * m0 && d1 <= 1e-7 * m1;
+    }
+  }
+  return ok;
+}
+
+template <bool MIXED, int MR>
+__global__ void __launch_bounds__(wpbn<MR>() * 64)
+    k_fit4n(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+            const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
+            const int8_t *__restrict__ rorder, double unit, double L, double *__restrict__ w64,
+            float *__restrict__ w32, double *__restrict__ bw64, float *__restrict__ bw32,
+            double *__restrict__ diag, double *__restrict__ inv_diag, double *__restrict__ hscale,
+            int8_t *__restrict__ dorder, double *__restrict__ w64ref, int32_t *__restrict__ fb_list,
+            unsigned *__restrict__ fb_cnt) {
+  constexpr int WPB = wpbn<MR>();
+  __shared__ WaveN<MR> SH[WPB];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t y = (int64_t)blockIdx.x * WPB + wv;
+  if (y >= n) return;
+  WaveN<MR> &S = SH[wv];
+  const int32_t a0 = st_off[y];
+  const int m = st_off[y + 1] - a0;
+  const int pc = rorder[y] == 4 ? P4 : 9;
+  const Geo g = stencil_rows_n<MR>(S, lane, st_idx + a0, m, crd, ntot, y);
+  wsync();
+  const double hp = (double)g.h * unit;
+  const double hc = L / (double)(1 << level[y]);
+  double cl, cb;
+  fit_rhs(lane, pc, hc, hp, cl, cb);
+  double lrow[P4], rd, zl, zb;
+  bool ok;
+  if (pc == P4) {
+    gram_mfma<MR, P4>(S, lane);
+    wsync();
+    ok = cholesky_n<MR, P4>(S, lane, lrow, rd);
+    if (ok) ok = solve_refined<MR, P4>(S, lane, lrow, rd, cl, cb, zl, zb);
+  } else {
+    gram_mfma<MR, 9>(S, lane);
+    wsync();
+    ok = cholesky_n<MR, 9>(S, lane, lrow, rd);
+    if (ok) ok = solve_refined<MR, 9>(S, lane, lrow, rd, cl, cb, zl, zb);
+  }
+  if (!ok) { // the Householder kernel takes this node
+    if (lane == 0) fb_list[atomicAdd(fb_cnt, 1u)] = (int32_t)y;
+    return;
+  }
+  double yl, yb;
+  if (pc == P4)
+    a_times_n<MR, P4>(S, lane, zl, zb, yl, yb);
+  else
+    a_times_n<MR, 9>(S, lane, zl, zb, yl, yb);
+  const double wl = lane < m ? g.W * yl / (hp * hp) : 0.0;
+  const double wb = lane < m ? g.W * yb : 0.0;
+  // the order-2 row of the same stencil: the leading 9 x 9 block of the same
+  // Cholesky factor (G's leading block), moments of order 2 only
+  bool ok2 = true;
+  auto order2 = [&]() {
+    const double cb2 = (lane == 3 || lane == 6 || lane == 8) ? cb : 0.0;
+    double z2, z0, y2, y0;
+    ok2 = solve_refined<MR, 9>(S, lane, lrow, rd, cb2, 0.0, z2, z0);
+    a_times_n<MR, 9>(S, lane, z2, z0, y2, y0);
+    return lane < m ? g.W * y2 : 0.0;
+  };
+  write_rows<MIXED>(lane, y, a0, m, pc, wl, wb, hc, order2, w64, w32, bw64, bw32, diag, inv_diag,
+                    hscale, dorder, w64ref);
+  if (!ok2 && lane == 0) fb_list[atomicAdd(fb_cnt, 1u)] = (int32_t)y;
 }
 
 // CSR weights -> the sliced layout (entry-major; padding entries 0)
@@ -573,22 +957,42 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
   const bool mixed = c->P.precision != APC_FP64;
   HIPCHK(hipMemsetAsync(&c->scratch->err, 0, sizeof(int), s));
   HIPCHK(hipMemsetAsync(&c->scratch->nfp64, 0, sizeof(unsigned long long), s));
+  HIPCHK(hipMemsetAsync(&c->scratch->fb_count, 0, sizeof(unsigned), s));
   if (n > 0) {
     const bool m56 = c->P.m_cap <= 56;
+    double *ref = mixed ? c->w64ref : nullptr;
+    // normal equations on the matrix cores for every node, then the Householder QR
+    // for the nodes listed by it (grid-stride over the list; the count stays on
+    // the device)
+#define APC_FIT4N(MX, R)                                                                       \
+  hipLaunchKernelGGL((k_fit4n<MX, R>), dim3((unsigned)((n + wpbn<R>() - 1) / wpbn<R>())),     \
+                     dim3(wpbn<R>() * 64), 0, s, n, c->st_off, c->st_idx, c->crd, ntot,        \
+                     c->level, c->rorder, c->unit, c->P.L, c->w64, c->w32, c->bw64, c->bw32,   \
+                     c->diag, c->inv_diag, c->hscale, c->dorder, ref, c->fb_list,              \
+                     &c->scratch->fb_count)
 #define APC_FIT4(MX, R)                                                                        \
-  hipLaunchKernelGGL((k_fit4<MX, R>), dim3(grid4(n)), dim3(WPB4 * 64), 0, s, n, c->st_off,     \
-                     c->st_idx, c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, c->w64,    \
-                     c->w32, c->bw64, c->bw32, c->diag, c->inv_diag, c->hscale, c->dorder,    \
-                     MX ? c->w64ref : nullptr, &c->scratch->err)
-    if (mixed && m56)
+  hipLaunchKernelGGL((k_fit4<MX, R>), dim3(1024), dim3(WPB4 * 64), 0, s,                       \
+                     (const int32_t *)c->fb_list, (const unsigned *)&c->scratch->fb_count,     \
+                     c->st_off, c->st_idx, c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, \
+                     c->w64, c->w32, c->bw64, c->bw32, c->diag, c->inv_diag, c->hscale,        \
+                     c->dorder, ref, &c->scratch->err)
+    if (mixed && m56) {
+      APC_FIT4N(true, 56);
       APC_FIT4(true, 56);
-    else if (mixed)
+    } else if (mixed) {
+      APC_FIT4N(true, APC_MAXM);
       APC_FIT4(true, APC_MAXM);
-    else if (m56)
+    } else if (m56) {
+      APC_FIT4N(false, 56);
       APC_FIT4(false, 56);
-    else
+    } else {
+      APC_FIT4N(false, APC_MAXM);
       APC_FIT4(false, APC_MAXM);
+    }
 #undef APC_FIT4
+#undef APC_FIT4N
+    hipLaunchKernelGGL(k_fb_report, dim3(1), dim3(64), 0, s, (const unsigned *)&c->scratch->fb_count,
+                       &c->scratch->nfp64);
     HIPCHK(hipGetLastError());
   }
   c->w64_mixed = mixed && c->w64ref != nullptr;
