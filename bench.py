@@ -228,14 +228,16 @@ def spmv_bytes(cloud, info, value_bytes, index_bytes_layout):
     """Bytes per operator SpMV launch.  survey: the algorithmic count per row of the
     hot-path table, (m_i + 1) (value + 4 B index) + 8 B y_i + 4 B row pointer + 8 B
     x_i, i.e. (value + 4) (nnz + n) + 20 n.  layout: what the sliced layout has to
-    move: per stored entry its index (3 B) and weight, nothing for uniform 2-ring
-    rows but 24 indices and a level byte, per row a 4 B row id, x_i and y_i (the
-    diagonal is implied by the zero row sums)."""
+    move: per stored entry its index (3 B) and weight, nothing for uniform rows
+    (the 24-node 2-ring of k = 2, the 56-node stencil of k = 4) but their indices
+    and a level byte, per row a 4 B row id, x_i and y_i (the diagonal is implied by
+    the zero row sums)."""
     n, nnz = info["n"], info["nnz"]
     oi = cloud.operator_info()
     survey = (value_bytes + 4) * (nnz + n) + 20 * n
     ib = index_bytes_layout
-    layout = oi["n_uniform"] * (24 * ib + 1) + oi["nnz_general"] * (ib + value_bytes) + n * 20
+    mu = 24 if cloud.p == 9 else 56
+    layout = oi["n_uniform"] * (mu * ib + 1) + oi["nnz_general"] * (ib + value_bytes) + n * 20
     return int(survey), int(layout)
 
 
@@ -251,9 +253,12 @@ def assembly_roofline(torch, cloud, reps, mixed):
     (mixed) or FP64 normal-equation fits: per stencil entry ~160 flop (monomials,
     Gaussian weight, 45 Gram FMAs, weight pass), per row ~650 (9 x 9 Cholesky and
     solves); bytes: CSR indices and the two weight copies per entry, the
-    coordinate array once, per-row metadata.  k = 4 counts the FP64 Householder QR
-    of the m x 34 systems, 2 m p^2 - 2 p^3 / 3 + 4 m p per node (FP64 in every
-    precision mode)."""
+    coordinate array once, per-row metadata.  k = 4 counts, for the fitted rows
+    (all but the uniform 56-node rows, which take the shell constants), the flops
+    of the FP64 Householder QR of the m x 34 systems, 2 m p^2 - 2 p^3 / 3 + 4 m p
+    per node (the oracle's method; FP64 in every precision mode); bytes: every
+    row's CSR indices and the Laplacian and density weights of its CSR and sliced
+    copies, per-row metadata, the coordinates once."""
     stream = torch.cuda.current_stream()
     for _ in range(2):
         cloud.assemble_gfd()
@@ -276,10 +281,11 @@ def assembly_roofline(torch, cloud, reps, mixed):
         kernel = "k_fit_sell"
     else:
         p, nnz = 34, cloud.nnz
-        byts = nnz * (4 + 2 * wb) + n * 44 + ntot * 12
-        flops = 2 * p * p * nnz - (2.0 / 3.0) * p ** 3 * n + 4 * p * nnz
+        nnz_g, n_g = oi["nnz_general"], n - oi["n_uniform"]
+        byts = nnz * (4 + 4 * wb) + n * 44 + ntot * 12
+        flops = 2 * p * p * nnz_g - (2.0 / 3.0) * p ** 3 * n_g + 4 * p * nnz_g
         peak = FP64_PEAK_GFLOPS
-        kernel = "k_fit4"
+        kernel = "k_fit4n (normal equations on MFMA) + k_fill4 + k_sell_copy"
     gbs = byts / (us * 1e-6) / 1e9
     gfl = flops / (us * 1e-6) / 1e9
     return dict(kernel=kernel, avg_us=round(us, 1), bytes_per_launch=int(byts),

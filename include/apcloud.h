@@ -187,9 +187,12 @@ int apc_assemble_gfd(apc_cloud *c, hipStream_t stream);
 int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host);
 
 /* Layout of the assembled operator as the solver streams it: n_uniform rows have
-   the uniform 24-node 2-ring stencil of their own level (their weights are the
-   shared shell constants and are not read), nnz_general entries belong to the
-   other rows, sell_entries is the padded entry count of the sliced layout,
+   the uniform stencil of their own level -- k = 2: the 24-node 2-ring, k = 4: the
+   56 nodes at lattice offsets with r^2 = 1 .. 5 cells -- (their weights are the
+   shared shell constants and are not read; at k = 4 the CSR rows returned by
+   apc_get_operator and apc_get_density_operator hold those constants),
+   nnz_general entries belong to the other rows, sell_entries is the padded entry
+   count of the sliced layout,
    m_entries the off-diagonal entries the learned M stores for the other rows
    (min(m, APC_MLP_OUT - 1) per row).  staged[4], if not NULL, receives the
    neighbour staging of the operator kernels: the number of 64-row slices whose

@@ -161,12 +161,29 @@ struct apc_cloud {
   int8_t *rkind = nullptr;
   double tmpl[3] = {0.0, 0.0, 0.0};
   int64_t n_template = 0;
+  // k = 4: rows whose stencil is the uniform 56-node lattice stencil of their own
+  // level (6, 12, 8, 6 and 24 nodes at r^2 = 1 .. 5 cells, in that order in the
+  // (r^2, index) order of the stencil) share one Laplacian row c_shell / h_c^2 and
+  // one density row (scale-free).  rkind4[i] is the level of such a row, -1
+  // otherwise; tmpl4 holds the 5 Laplacian shell weights at h_c = 1, then the 5
+  // density shell weights; dorder4 the order of that density row.  Their CSR rows
+  // are written from the constants; the SpMV reads no weights for them.  gen4
+  // lists the other rows (the ones the assembly fits).
+  int8_t *rkind4 = nullptr;
+  double tmpl4[10] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+  double tmpl4_sum = 0.0; // sum of the 56 Laplacian weights at h_c = 1
+  int dorder4 = 0;
+  int64_t n_uniform4 = 0;
+  int32_t *gen4 = nullptr;
+  int64_t n_gen4 = 0;
   // sliced-ELL copy of the operator used by the SpMV (see sell.hip)
   int64_t nsl = 0, sl_entries = 0;
   int64_t sl_cs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}; // slice range of each XCD chunk
   int32_t *sl_rows = nullptr;  // nsl * 64 row ids (-1 = padding lane)
   int32_t *sl_len = nullptr;   // entries per row in the slice
-  int32_t *sl_tmpl = nullptr;  // 1: uniform 2-ring slice (no weights); 32-bit: scalar loads
+  int32_t *sl_tmpl = nullptr;  // 1: uniform 2-ring slice (k = 2), 2: uniform 56-node slice
+                               // (k = 4; the SpMV reads no weights), 0: general; 32-bit:
+                               // scalar loads
   int64_t *sl_off = nullptr;   // first entry of the slice (a multiple of 4 x 64: slices
                                // hold a multiple of 4 entries per row)
   int32_t *sl_idx = nullptr;   // column indices, entry-major within a slice
@@ -228,6 +245,8 @@ int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s
 int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t np,
                     const int32_t *cand, int32_t *m, hipStream_t s);
 int apc_assemble4(apc_cloud *c, hipStream_t s);
+// uniform 56-node rows: canonical constants, rkind4 and the list of the other rows
+int apc_prepare_uniform4(apc_cloud *c, hipStream_t s);
 int apc_node_derivs4(apc_cloud *c, const double *f, double *D, hipStream_t s);
 int apc_interp4(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, hipStream_t s);
 int apc_interp4_with(apc_cloud *c, const double *phi, double *phi_p, double *grad_p, double *D,

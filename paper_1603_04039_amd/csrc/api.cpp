@@ -201,8 +201,8 @@ int apc_get_node_orders(const apc_cloud *c, int8_t *order_host) {
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
                       int64_t *sell_entries, int64_t *m_entries, int64_t *staged) {
   if (!c || !c->assembled) return APC_EINVAL;
-  if (n_uniform) *n_uniform = c->n_template;
-  if (nnz_general) *nnz_general = c->nnz - 24 * c->n_template;
+  if (n_uniform) *n_uniform = c->n_template + c->n_uniform4;
+  if (nnz_general) *nnz_general = c->nnz - 24 * c->n_template - 56 * c->n_uniform4;
   if (sell_entries) *sell_entries = c->sl_entries;
   if (m_entries) {
     DeviceGuard g(c->device);

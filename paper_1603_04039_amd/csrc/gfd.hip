@@ -516,8 +516,9 @@ int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
                        c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->rkind);
     HIPCHK(hipGetLastError());
   } else {
-    // k = 4: every row is fitted and stored (no uniform-row sharing)
+    // k = 4: no uniform 2-ring rows; the uniform 56-node rows are flagged in rkind4
     HIPCHK(hipMemsetAsync(c->rkind, 0xff, (size_t)(n > 0 ? n : 1), s));
+    APCCHK(apc_prepare_uniform4(c, s));
   }
   APCCHK(apc_build_sell(c, s));
   if (c->P.order == 4) {

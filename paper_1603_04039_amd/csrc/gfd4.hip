@@ -31,6 +31,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cmath>
+#include <cstring>
 
 #include "apc_internal.h"
 
@@ -776,9 +777,11 @@ __device__ __forceinline__ bool solve_refined(WaveN<MR> &S, int lane, const doub
   return ok;
 }
 
+// Runs over the rows list[0 .. n) (list null: rows 0 .. n-1), one wavefront per row.
 template <bool MIXED, int MR>
 __global__ void __launch_bounds__(wpbn<MR>() * 64)
-    k_fit4n(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+    k_fit4n(int64_t n, const int32_t *__restrict__ list, const int32_t *__restrict__ st_off,
+            const int32_t *__restrict__ st_idx,
             const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
             const int8_t *__restrict__ rorder, double unit, double L, double *__restrict__ w64,
             float *__restrict__ w32, double *__restrict__ bw64, float *__restrict__ bw32,
@@ -788,8 +791,9 @@ __global__ void __launch_bounds__(wpbn<MR>() * 64)
   constexpr int WPB = wpbn<MR>();
   __shared__ WaveN<MR> SH[WPB];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int64_t y = (int64_t)blockIdx.x * WPB + wv;
-  if (y >= n) return;
+  const int64_t t = (int64_t)blockIdx.x * WPB + wv;
+  if (t >= n) return;
+  const int64_t y = list ? (int64_t)list[t] : t;
   WaveN<MR> &S = SH[wv];
   const int32_t a0 = st_off[y];
   const int m = st_off[y + 1] - a0;
@@ -855,6 +859,118 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int m = row >= 0 ? st_off[row + 1] - a : 0;
   for (int k = 0; k < len; k++) sw[off + (int64_t)k * APC_SLICE] = k < m ? w[a + k] : T(0);
 }
+
+// ---------------------------------------------------------------- uniform 56-node rows
+// r^2 (in cells) of entry j of a uniform 56-node stencil in (r^2, index) order
+__device__ __forceinline__ int shell4_r2(int j) {
+  return j < 6 ? 1 : (j < 18 ? 2 : (j < 26 ? 3 : (j < 32 ? 4 : 5)));
+}
+
+// Structural test run at build time: is the node's stencil (an order-4 row) the
+// uniform 56-node stencil of its own level, i.e. the nodes at lattice offsets of
+// one cell spacing with r^2 = 1 .. 5 cells (6, 12, 8, 6 and 24 of them, every
+// offset with |q_d| <= 2 and |q|_1 <= 3)?  The stencil lists distinct nodes by
+// (r^2, index), so shell counts and offsets fix the set.  rkind4 = level if so,
+// else -1.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_classify4(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+                const int32_t *__restrict__ crd, int64_t ntot, const int32_t *__restrict__ level,
+                const int8_t *__restrict__ rorder, int D, int8_t *__restrict__ rkind4) {
+  const int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y >= n) return;
+  const int32_t a = st_off[y];
+  const int l = level[y];
+  bool ok = st_off[y + 1] - a == 56 && rorder[y] == 4;
+  if (ok) {
+    const int32_t sp = 1 << (D - l + 1);
+    const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y];
+    for (int j = 0; j < 56 && ok; j++) {
+      const int32_t v = st_idx[a + j];
+      const int32_t d[3] = {abs(crd[v] - c0), abs(crd[ntot + v] - c1), abs(crd[2 * ntot + v] - c2)};
+      int q2 = 0;
+      for (int k = 0; k < 3; k++) {
+        ok = ok && (d[k] == 0 || d[k] == sp || d[k] == 2 * sp);
+        const int q = d[k] == 0 ? 0 : (d[k] == sp ? 1 : 2);
+        q2 += q * q;
+      }
+      ok = ok && q2 == shell4_r2(j);
+    }
+  }
+  rkind4[y] = ok ? (int8_t)l : (int8_t)-1;
+}
+
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_gen_flag(const int8_t *__restrict__ rkind4, int64_t n, int32_t *__restrict__ f) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) f[i] = rkind4[i] < 0 ? 1 : 0;
+}
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_gen_list(const int8_t *__restrict__ rkind4, const int32_t *__restrict__ pos, int64_t n,
+               int32_t *__restrict__ list) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n && rkind4[i] < 0) list[pos[i]] = (int32_t)i;
+}
+
+// shell constants of the uniform 56-node rows
+struct Tmpl4 {
+  double tl[5]; // Laplacian at h_c = 1
+  double tb[5]; // density row (scale-free)
+  double sl;    // sum of the 56 Laplacian weights at h_c = 1
+  int dord;     // order of the density row
+};
+__device__ __forceinline__ double pick5(const double (&t)[5], int k) {
+  return k == 0 ? t[0] : (k == 1 ? t[1] : (k == 2 ? t[2] : (k == 3 ? t[3] : t[4])));
+}
+
+// Rows of the uniform 56-node nodes from the shell constants (what the fit gives
+// them up to rounding): Laplacian weight tl / h_c^2, density weight tb, into the
+// CSR copies the fitted rows go to; one wavefront per node.
+template <bool MIXED>
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_fill4(int64_t n, const int8_t *__restrict__ rkind4, const int32_t *__restrict__ st_off,
+            Tmpl4 T, double L, double *__restrict__ w64, float *__restrict__ w32,
+            double *__restrict__ bw64, float *__restrict__ bw32, double *__restrict__ diag,
+            double *__restrict__ inv_diag, double *__restrict__ hscale,
+            int8_t *__restrict__ dorder, double *__restrict__ w64ref) {
+  const int64_t y = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
+  if (y >= n) return;
+  const int l = rkind4[y];
+  if (l < 0) return;
+  const int lane = threadIdx.x & 63;
+  const double hc = L / (double)(1 << l);
+  const double ih2 = 1.0 / (hc * hc);
+  if (lane < 56) {
+    const int k = shell4_r2(lane) - 1;
+    const double wl = pick5(T.tl, k) * ih2, wb = pick5(T.tb, k);
+    const int64_t e = (int64_t)st_off[y] + lane;
+    if (MIXED) {
+      w32[e] = (float)wl;
+      bw32[e] = (float)wb;
+      if (w64ref) w64ref[e] = wl;
+    } else {
+      w64[e] = wl;
+      bw64[e] = wb;
+    }
+  }
+  if (lane == 0) {
+    const double sw = T.sl * ih2;
+    diag[y] = -sw;
+    inv_diag[y] = -1.0 / sw;
+    hscale[y] = hc * hc / 24.0;
+    dorder[y] = (int8_t)T.dord;
+  }
+}
+
+// the canonical uniform 56-node stencil: node 0 at (4, 4, 4), nodes 1 .. 56 at the
+// offsets of spacing 1 sorted by r^2, one cell of size 1 (L = 1, level 0)
+struct Canon4 {
+  int32_t crd[3 * 57];
+  int32_t st_off[2], st_idx[56], level[1], fb_list[1];
+  int8_t rorder[1], dorder[1];
+  unsigned fb_cnt;
+  int err;
+  double w64[56], bw64[56], diag[1], inv_diag[1], hscale[1];
+};
 
 // ---------------------------------------------------------------- derivatives
 template <int MR>
@@ -952,6 +1068,114 @@ int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t 
   return APC_OK;
 }
 
+// The shell constants of the uniform 56-node rows are the assembly's own fit (FP64
+// normal equations, Householder QR if they do not converge) of the canonical
+// stencil; by the stencil's cubic symmetry every shell then holds one value (up to
+// rounding: checked, the shell mean is kept).  Then the rows are classified and
+// the other rows listed for the assembly.  Synchronises.
+int apc_prepare_uniform4(apc_cloud *c, hipStream_t s) {
+  const int64_t n = c->n;
+  HIPCHK(apc_dev_alloc((void **)&c->rkind4, (size_t)(n > 0 ? n : 1)));
+  HIPCHK(apc_dev_alloc((void **)&c->gen4, (size_t)(n > 0 ? n : 1) * sizeof(int32_t)));
+  c->n_uniform4 = 0;
+  c->n_gen4 = n;
+  for (double &v : c->tmpl4) v = 0.0;
+  c->dorder4 = 0;
+  Canon4 h;
+  memset(&h, 0, sizeof(h));
+  int k = 1;
+  for (int a = 0; a < 3; a++) h.crd[57 * a] = 4;
+  for (int r2 = 1; r2 <= 5; r2++)
+    for (int dx = -2; dx <= 2; dx++)
+      for (int dy = -2; dy <= 2; dy++)
+        for (int dz = -2; dz <= 2; dz++) {
+          if (dx * dx + dy * dy + dz * dz != r2 || abs(dx) + abs(dy) + abs(dz) > 3) continue;
+          h.crd[k] = 4 + dx;
+          h.crd[57 + k] = 4 + dy;
+          h.crd[114 + k] = 4 + dz;
+          k++;
+        }
+  if (k != 57) return APC_EINVAL;
+  h.st_off[0] = 0;
+  h.st_off[1] = 56;
+  for (int j = 0; j < 56; j++) h.st_idx[j] = j + 1;
+  h.rorder[0] = 4;
+  Canon4 *d = nullptr;
+  HIPCHK(apc_malloc_async((void **)&d, sizeof(Canon4), s));
+  HIPCHK(hipMemcpyAsync(d, &h, sizeof(Canon4), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL((k_fit4n<false, 56>), dim3(1), dim3(wpbn<56>() * 64), 0, s, (int64_t)1,
+                     (const int32_t *)nullptr, d->st_off, d->st_idx, d->crd, (int64_t)57, d->level,
+                     d->rorder, 1.0, 1.0, d->w64, (float *)nullptr, d->bw64, (float *)nullptr,
+                     d->diag, d->inv_diag, d->hscale, d->dorder, (double *)nullptr, d->fb_list,
+                     &d->fb_cnt);
+  hipLaunchKernelGGL((k_fit4<false, 56>), dim3(1), dim3(WPB4 * 64), 0, s,
+                     (const int32_t *)d->fb_list, (const unsigned *)&d->fb_cnt, d->st_off,
+                     d->st_idx, d->crd, (int64_t)57, d->level, d->rorder, 1.0, 1.0, d->w64,
+                     (float *)nullptr, d->bw64, (float *)nullptr, d->diag, d->inv_diag, d->hscale,
+                     d->dorder, (double *)nullptr, &d->err);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(&h, d, sizeof(Canon4), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(apc_free_async(d, s));
+  const int lo[6] = {0, 6, 18, 26, 32, 56};
+  double tl[5], tb[5], dev = 0.0, wmax = 0.0, bmax = 0.0;
+  bool ok = h.err == 0;
+  for (int q = 0; q < 5; q++) {
+    double sl = 0.0, sb = 0.0;
+    for (int j = lo[q]; j < lo[q + 1]; j++) {
+      sl += h.w64[j];
+      sb += h.bw64[j];
+      wmax = fmax(wmax, fabs(h.w64[j]));
+      bmax = fmax(bmax, fabs(h.bw64[j]));
+    }
+    tl[q] = sl / (lo[q + 1] - lo[q]);
+    tb[q] = sb / (lo[q + 1] - lo[q]);
+  }
+  for (int q = 0; q < 5; q++)
+    for (int j = lo[q]; j < lo[q + 1]; j++) {
+      dev = fmax(dev, fabs(h.w64[j] - tl[q]) / wmax);
+      if (bmax > 0.0) dev = fmax(dev, fabs(h.bw64[j] - tb[q]) / bmax);
+    }
+  ok = ok && wmax > 0.0 && dev <= 1e-12 && std::isfinite(dev);
+  if (ok) {
+    double sw = 0.0;
+    for (int q = 0; q < 5; q++) sw += (double)(lo[q + 1] - lo[q]) * tl[q];
+    for (int q = 0; q < 5; q++) {
+      c->tmpl4[q] = tl[q];
+      c->tmpl4[5 + q] = tb[q];
+    }
+    c->tmpl4_sum = sw;
+    c->dorder4 = h.dorder[0];
+  }
+  if (n <= 0) return APC_OK;
+  const int64_t ntot = c->n + c->nb;
+  if (ok) {
+    hipLaunchKernelGGL(k_classify4, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
+                       c->st_idx, c->crd, ntot, c->level, c->rorder, c->P.max_depth, c->rkind4);
+  } else {
+    HIPCHK(hipMemsetAsync(c->rkind4, 0xff, (size_t)n, s));
+  }
+  HIPCHK(hipGetLastError());
+  int32_t *f = nullptr, *pos = nullptr;
+  HIPCHK(apc_malloc_async((void **)&f, (size_t)n * sizeof(int32_t), s));
+  HIPCHK(apc_malloc_async((void **)&pos, (size_t)n * sizeof(int32_t), s));
+  hipLaunchKernelGGL(k_gen_flag, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, (const int8_t *)c->rkind4,
+                     n, f);
+  APCCHK(apc_scan_i32(f, pos, n, s));
+  hipLaunchKernelGGL(k_gen_list, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, (const int8_t *)c->rkind4,
+                     (const int32_t *)pos, n, c->gen4);
+  HIPCHK(hipGetLastError());
+  int32_t lastf = 0, lastp = 0;
+  HIPCHK(hipMemcpyAsync(&lastf, f + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipMemcpyAsync(&lastp, pos + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(apc_free_async(f, s));
+  HIPCHK(apc_free_async(pos, s));
+  c->n_gen4 = (int64_t)lastp + lastf;
+  c->n_uniform4 = n - c->n_gen4;
+  return APC_OK;
+}
+
 int apc_assemble4(apc_cloud *c, hipStream_t s) {
   const int64_t n = c->n, ntot = c->n + c->nb;
   const bool mixed = c->P.precision != APC_FP64;
@@ -961,12 +1185,16 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
   if (n > 0) {
     const bool m56 = c->P.m_cap <= 56;
     double *ref = mixed ? c->w64ref : nullptr;
+    // the fitted rows: every row but the uniform 56-node ones
+    const int64_t nfit = c->n_uniform4 > 0 ? c->n_gen4 : n;
+    const int32_t *fit_list = c->n_uniform4 > 0 ? c->gen4 : nullptr;
     // normal equations on the matrix cores for every node, then the Householder QR
     // for the nodes listed by it (grid-stride over the list; the count stays on
     // the device)
 #define APC_FIT4N(MX, R)                                                                       \
-  hipLaunchKernelGGL((k_fit4n<MX, R>), dim3((unsigned)((n + wpbn<R>() - 1) / wpbn<R>())),     \
-                     dim3(wpbn<R>() * 64), 0, s, n, c->st_off, c->st_idx, c->crd, ntot,        \
+  if (nfit > 0)                                                                                \
+  hipLaunchKernelGGL((k_fit4n<MX, R>), dim3((unsigned)((nfit + wpbn<R>() - 1) / wpbn<R>())),  \
+                     dim3(wpbn<R>() * 64), 0, s, nfit, fit_list, c->st_off, c->st_idx, c->crd, ntot, \
                      c->level, c->rorder, c->unit, c->P.L, c->w64, c->w32, c->bw64, c->bw32,   \
                      c->diag, c->inv_diag, c->hscale, c->dorder, ref, c->fb_list,              \
                      &c->scratch->fb_count)
@@ -993,6 +1221,24 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
 #undef APC_FIT4N
     hipLaunchKernelGGL(k_fb_report, dim3(1), dim3(64), 0, s, (const unsigned *)&c->scratch->fb_count,
                        &c->scratch->nfp64);
+    if (c->n_uniform4 > 0) {
+      Tmpl4 T;
+      for (int q = 0; q < 5; q++) {
+        T.tl[q] = c->tmpl4[q];
+        T.tb[q] = c->tmpl4[5 + q];
+      }
+      T.sl = c->tmpl4_sum;
+      T.dord = c->dorder4;
+      const unsigned g = grid_for(n, APC_BLOCK / 64);
+      if (mixed)
+        hipLaunchKernelGGL(k_fill4<true>, dim3(g), dim3(APC_BLOCK), 0, s, n,
+                           (const int8_t *)c->rkind4, c->st_off, T, c->P.L, c->w64, c->w32, c->bw64,
+                           c->bw32, c->diag, c->inv_diag, c->hscale, c->dorder, ref);
+      else
+        hipLaunchKernelGGL(k_fill4<false>, dim3(g), dim3(APC_BLOCK), 0, s, n,
+                           (const int8_t *)c->rkind4, c->st_off, T, c->P.L, c->w64, c->w32, c->bw64,
+                           c->bw32, c->diag, c->inv_diag, c->hscale, c->dorder, ref);
+    }
     HIPCHK(hipGetLastError());
   }
   c->w64_mixed = mixed && c->w64ref != nullptr;

@@ -392,7 +392,9 @@ __global__ void __launch_bounds__(WPB * 64)
   float *H = hl[wv];
   for (int64_t s0 = (int64_t)blockIdx.x * WPB + wv; s0 < in.nsl; s0 += (int64_t)gridDim.x * WPB) {
     const int64_t s = __builtin_amdgcn_readfirstlane((int)s0);
-    const bool tmpl = io.mode == 2 ? true : in.sl_tmpl[s] != 0;
+    // uniform 2-ring slices (k = 2) take the per-level rows; every other slice,
+    // the uniform 56-node slices of k = 4 included, its own rows
+    const bool tmpl = io.mode == 2 ? true : in.sl_tmpl[s] == 1;
     if (io.mode == 1 && tmpl) {
       // uniform slices use the per-level rows; m_diag holds each row's safeguard
       // weight alpha (1: the network's row)
@@ -521,7 +523,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int lane = threadIdx.x & 63;
   const int32_t row = sl_rows[s * APC_SLICE + lane];
   if (row < 0) return;
-  if (sl_tmpl[s]) {
+  if (sl_tmpl[s] == 1) {
     const float *T = m_tmpl + NT * (int)rk[row];
     const int64_t off = sl_off[s] + lane;
     const double jd = 1.0 / diag[row];

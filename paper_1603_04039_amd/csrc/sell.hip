@@ -1,16 +1,18 @@
 // Sliced-ELL layout of the assembled operator for the solver's SpMV.
 //
 // Rows are cut into 8 contiguous chunks (one per XCD; the XCDs' L2s then each
-// hold the x-vector neighbourhood of one chunk).  Inside a chunk the uniform
-// 2-ring rows and the general rows each form slices of 64 rows (one wavefront,
-// one thread per row) in ascending row order.  A slice stores its column indices
+// hold the x-vector neighbourhood of one chunk).  Inside a chunk the uniform rows
+// (the 2-ring rows of k = 2, the 56-node rows of k = 4) and the general rows each
+// form slices of 64 rows (one wavefront, one thread per row) in ascending row
+// order.  A slice stores its column indices
 // entry-major (entry k of lane r at off + 64 k + r), so every index/weight load
 // of a wavefront is one contiguous 256-byte (or 512-byte) request and every lane
 // has all its neighbour gathers independent of each other.  Uniform slices have
-// exactly 24 entries and no weights (the weights are the shell constants);
-// general slices are padded to their longest row with (own index, weight 0).
+// exactly 24 entries (k = 2) or 56 (k = 4) and the SpMV reads no weights for them
+// (the weights are the shell constants); general slices are padded to their
+// longest row with (own index, weight 0).
 // This file builds the layout and the column indices at build time; the weights
-// are written by the assembly (k_fit_sell).
+// are written by the assembly (k_fit_sell for k = 2, k_sell_copy for k = 4).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -68,8 +70,9 @@ __global__ void __launch_bounds__(APC_BLOCK)
 
 // one 64-thread block per slice
 __global__ void __launch_bounds__(SL)
-    k_slices(Groups G, const int32_t *__restrict__ srow_t, const int32_t *__restrict__ srow_g,
-             const int32_t *__restrict__ st_off, int32_t *__restrict__ sl_rows,
+    k_slices(Groups G, int tkind, const int32_t *__restrict__ srow_t,
+             const int32_t *__restrict__ srow_g, const int32_t *__restrict__ st_off,
+             int32_t *__restrict__ sl_rows,
              int32_t *__restrict__ sl_len, int32_t *__restrict__ sl_tmpl,
              int64_t *__restrict__ sl_ent) {
   const int64_t s = blockIdx.x;
@@ -83,10 +86,10 @@ __global__ void __launch_bounds__(SL)
   const int32_t row = valid ? (type == 0 ? srow_t[G.r0[g] + q] : srow_g[G.r0[g] + q]) : -1;
   sl_rows[s * SL + lane] = row;
   const int m = valid ? st_off[row + 1] - st_off[row] : 0;
-  const int len = type == 0 ? 24 : wave_max_i(m);
+  const int len = type == 0 ? (tkind == 1 ? 24 : 56) : wave_max_i(m);
   if (lane == 0) {
     sl_len[s] = len;
-    sl_tmpl[s] = type == 0 ? 1 : 0;
+    sl_tmpl[s] = type == 0 ? tkind : 0;
     sl_ent[s] = (int64_t)((len + 3) & ~3) * SL; // storage padded to a multiple of 4 entries
   }
 }
@@ -226,9 +229,12 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   HIPCHK(apc_malloc_async((void **)&tpos, (size_t)(n + 1) * sizeof(int32_t), s));
   HIPCHK(apc_malloc_async((void **)&srow_t, (size_t)n * sizeof(int32_t), s));
   HIPCHK(apc_malloc_async((void **)&srow_g, (size_t)n * sizeof(int32_t), s));
-  hipLaunchKernelGGL(k_tflag, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, n, tf);
+  // uniform rows: the 2-ring rows of k = 2 or the 56-node rows of k = 4
+  const int8_t *rk = c->P.order == 4 ? c->rkind4 : c->rkind;
+  const int tkind = c->P.order == 4 ? 2 : 1;
+  hipLaunchKernelGGL(k_tflag, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, rk, n, tf);
   APCCHK(apc_scan_i32(tf, tpos, n, s));
-  hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, tpos, n, srow_t,
+  hipLaunchKernelGGL(k_split, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, rk, tpos, n, srow_t,
                      srow_g);
   HIPCHK(hipGetLastError());
   // template-row prefix counts at the 8 chunk boundaries
@@ -243,7 +249,7 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   HIPCHK(hipMemcpyAsync(&lastp, tpos + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   T[8] = lastp + lastf;
-  c->n_template = T[8];
+  c->n_template = tkind == 1 ? T[8] : 0;
   Groups G;
   int64_t ns = 0;
   for (int k = 0; k < 8; k++) {
@@ -281,7 +287,7 @@ int apc_build_sell(apc_cloud *c, hipStream_t s) {
   int64_t *ent = nullptr;
   HIPCHK(apc_malloc_async((void **)&ent, nsz * sizeof(int64_t), s));
   if (ns > 0) {
-    hipLaunchKernelGGL(k_slices, dim3((unsigned)ns), dim3(SL), 0, s, G, srow_t, srow_g, c->st_off,
+    hipLaunchKernelGGL(k_slices, dim3((unsigned)ns), dim3(SL), 0, s, G, tkind, srow_t, srow_g, c->st_off,
                        c->sl_rows, c->sl_len, c->sl_tmpl, ent);
     HIPCHK(hipGetLastError());
     APCCHK(apc_scan_i64(ent, c->sl_off, ns, s));

@@ -193,8 +193,9 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // out = M in for the learned preconditioner.  Row i of M has the operator's
 // pattern: m_ii in_i + sum_k m_ik in_{J_k}.  Uniform 2-ring slices read the
 // per-level row of M (25 floats: diagonal, then the 24 entries in slice order)
-// and no weights; general slices read their own weights, stored like the
-// operator's (entry-major; padding and boundary columns carry weight 0).
+// and no weights; general slices, and the uniform 56-node slices of k = 4, read
+// their own weights, stored like the operator's (entry-major; padding and
+// boundary columns carry weight 0).
 struct MOp {
   const float *diag, *sell, *tmpl;
 };
@@ -205,7 +206,7 @@ __device__ __forceinline__ void prec_slice(const Op &op, const MOp &M, const dou
   const int64_t o = op.sl_off[s];
   const int64_t off = o + lane, lb = (o >> 1) + lane, hb = (o >> 2) + lane;
   double *tile = STG ? stage_tile(op) : nullptr;
-  if (op.sl_tmpl[s]) {
+  if (op.sl_tmpl[s] == 1) {
     int32_t jj[24];
     if (STG) {
       uint32_t wq[12];

@@ -18,8 +18,11 @@ struct Op {
   const float *w32;
   const double *hs; // k = 2 density operator: x_i + hs_i (L x)_i
   int unit_diag;    // k = 4 density operator: x_i + (sum_j b_ij (x_j - x_i)) with its own weights
-  const int8_t *rk; // level of a uniform 2-ring row, -1 for a general row
+  const int8_t *rk; // level of a uniform row (2-ring, k = 2; 56-node, k = 4), else -1
   double tc[3];     // shell weights of the uniform 2-ring at h_c = 1
+  double t4[5];     // shell weights of the uniform 56-node row (Laplacian at h_c = 1,
+                    // or the density row)
+  int t4_scaled;    // 1: Laplacian (t4 scaled like tc), 0: density row (scale-free)
   double invL2;     // 1 / L^2: a level-l row scales tc by 4^l / L^2
   int64_t n;
   // sliced-ELL copy (the SpMV reads only this); column indices from the compact
@@ -133,6 +136,10 @@ __device__ __forceinline__ int stage_slot(const Op &op, int64_t lb, int k) {
 // (A x)_row for the lane's row of slice s (row = -1 on padding lanes, result 0).
 // Uniform 2-ring slices hold 24 entries ordered by shell (6 at r = 1 cell, 12 at
 // sqrt 2, 6 at 2) and no weights: their index loads go out before the row id.
+// Uniform 56-node slices (k = 4) hold 6, 12, 8, 6 and 24 entries at r^2 = 1 .. 5
+// cells and no weights: they run the general loop with the weight of entry k taken
+// from the shell constants (k is wave-uniform, so the choice is scalar) and the
+// level's scale applied once.
 // General slices run their entry loop unrolled by 8 so that 8 index/weight loads
 // and then 8 gathers are in flight together.  STG: the slice's u distinct
 // neighbour values are staged in the wavefront's LDS tile first, and each entry
@@ -147,7 +154,41 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
   double *tile = STG ? stage_tile(op) : nullptr;
   double acc;
   double xi;
-  if (op.sl_tmpl[s]) {
+  const int kind = op.sl_tmpl[s];
+  if (STG && kind == 2) {
+    // staged uniform 56-node slice: all 56 slots are loaded before the staging
+    // gathers so that their latency overlaps; same arithmetic, in the same order,
+    // as the unstaged loop below
+    uint32_t wq[28];
+#pragma unroll
+    for (int k = 0; k < 28; k++) wq[k] = op.sl_lx2[lb + (int64_t)SL * k];
+    stage_fill(tile, op.sl_uq + o, u, x);
+    row = op.sl_rows[(int64_t)s * SL + lane];
+    if (row < 0) return 0.0;
+    xi = x[row];
+    const double scale = op.t4_scaled ? ldexp(op.invL2, 2 * (int)op.rk[row]) : 1.0;
+#define APC_TS(k) tile[(wq[(k) >> 1] >> (16 * ((k) & 1))) & 0xffffu]
+#define APC_T4(c, k) ((k) < 6 ? c[0] : ((k) < 18 ? c[1] : ((k) < 26 ? c[2] : ((k) < 32 ? c[3] : c[4]))))
+    if (MODE == V32A32) {
+      float cf[5];
+#pragma unroll
+      for (int k = 0; k < 5; k++) cf[k] = (float)op.t4[k];
+      float af = 0.f;
+#pragma unroll
+      for (int k = 0; k < 56; k++) af += APC_T4(cf, k) * (float)(APC_TS(k) - xi);
+      acc = (double)af * scale;
+    } else {
+      double cd[5];
+#pragma unroll
+      for (int k = 0; k < 5; k++) cd[k] = MODE == V64 ? op.t4[k] : (double)(float)op.t4[k];
+      double ad = 0.0;
+#pragma unroll
+      for (int k = 0; k < 56; k++) ad += APC_T4(cd, k) * (APC_TS(k) - xi);
+      acc = ad * scale;
+    }
+#undef APC_T4
+#undef APC_TS
+  } else if (kind == 1) {
     int32_t jj[24];
     if (STG) {
       uint32_t wq[12];
@@ -191,7 +232,27 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
     if (row < 0) return 0.0;
     xi = x[row];
 #define APC_NB(k) (STG ? tile[stage_slot(op, lb, k)] : x[sl_col<TOP>(op, lb, hb, k)])
-    if (MODE == V32A32) {
+#define APC_T4(c, k) ((k) < 6 ? c[0] : ((k) < 18 ? c[1] : ((k) < 26 ? c[2] : ((k) < 32 ? c[3] : c[4]))))
+    if (kind == 2) {
+      const double scale = op.t4_scaled ? ldexp(op.invL2, 2 * (int)op.rk[row]) : 1.0;
+      if (MODE == V32A32) {
+        float cf[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) cf[k] = (float)op.t4[k];
+        float af = 0.f;
+#pragma unroll 8
+        for (int k = 0; k < 56; k++) af += APC_T4(cf, k) * (float)(APC_NB(k) - xi);
+        acc = (double)af * scale;
+      } else {
+        double cd[5];
+#pragma unroll
+        for (int k = 0; k < 5; k++) cd[k] = MODE == V64 ? op.t4[k] : (double)(float)op.t4[k];
+        double ad = 0.0;
+#pragma unroll 8
+        for (int k = 0; k < 56; k++) ad += APC_T4(cd, k) * (APC_NB(k) - xi);
+        acc = ad * scale;
+      }
+    } else if (MODE == V32A32) {
       const float *__restrict__ wv = op.sl_w32 + off;
       float af = 0.f;
 #pragma unroll 8
@@ -210,6 +271,7 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
       for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (APC_NB(k) - xi);
       acc = ad;
     }
+#undef APC_T4
 #undef APC_NB
   }
   return op.hs ? xi + op.hs[row] * acc : (op.unit_diag ? xi + acc : acc);
@@ -234,8 +296,10 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   op.w32 = b4 ? c->bw32 : c->w32;
   op.hs = (density && !b4) ? c->hscale : nullptr;
   op.unit_diag = b4 ? 1 : 0;
-  op.rk = c->rkind;
+  op.rk = c->P.order == 4 ? c->rkind4 : c->rkind;
   for (int k = 0; k < 3; k++) op.tc[k] = c->tmpl[k];
+  for (int k = 0; k < 5; k++) op.t4[k] = b4 ? c->tmpl4[5 + k] : c->tmpl4[k];
+  op.t4_scaled = b4 ? 0 : 1;
   op.invL2 = 1.0 / (c->P.L * c->P.L);
   op.n = c->n;
   op.sl_rows = c->sl_rows;

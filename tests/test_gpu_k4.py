@@ -76,6 +76,57 @@ def test_k4_operator_rows(pair):
     assert err <= 1e-12 and derr <= 1e-12
 
 
+SHELL56 = np.repeat(np.arange(1, 6), [6, 12, 8, 6, 24])  # r^2 (cells) of entry j
+
+
+def uniform56_rows(nd, orders, D):
+    """Rows (order 4) whose stencil is the uniform 56-node lattice stencil of their
+    own level: the entry j of the (r^2, index) order lies at a lattice offset of
+    one cell spacing with r^2 = SHELL56[j] (host classification from the node
+    arrays)."""
+    off, idx, lv, crd = nd["st_off"], nd["st_idx"], nd["level"], nd["ixyz"].astype(np.int64)
+    rows = np.flatnonzero((np.diff(off) == 56) & (orders == 4))
+    if rows.size == 0:
+        return rows
+    nb = idx[off[rows][:, None] + np.arange(56)[None, :]]
+    sp = (1 << (D - lv[rows] + 1)).astype(np.int64)[:, None]
+    r2 = np.zeros(nb.shape, np.int64)
+    good = np.ones(nb.shape, bool)
+    for d in range(3):
+        dd = np.abs(crd[d][nb] - crd[d][rows][:, None])
+        good &= (dd == 0) | (dd == sp) | (dd == 2 * sp)
+        r2 += (dd // sp) ** 2
+    good &= r2 == SHELL56[None, :]
+    return rows[good.all(axis=1)]
+
+
+def test_k4_uniform_rows(apc, pair):
+    """Rows with the uniform 56-node stencil share shell constants and the SpMV
+    reads no weights for them: the GPU flags exactly the rows a host
+    classification finds, their CSR rows (written from the constants) are within
+    1e-12 of the oracle's fits (test_k4_operator_rows), and the operator apply
+    equals the oracle's row by row within 1e-12 of |d_i| max|f|, on the uniform
+    rows and on the others."""
+    xyz, O, G = pair
+    nd = G.nodes()
+    uni = uniform56_rows(nd, G.node_orders(), G.max_depth)
+    info = G.operator_info()
+    note(f"k = 4 uniform 56-node rows: {info['n_uniform']} of {G.n} (host {uni.size})")
+    assert info["n_uniform"] == uni.size > 0
+    assert info["nnz_general"] == G.nnz - 56 * uni.size
+    rng = np.random.default_rng(12)
+    f = rng.standard_normal(G.n + G.nb)
+    got = G.apply_operator(torch.from_numpy(f).cuda()).cpu().numpy()
+    want = O.apply_laplacian(f)
+    _, d_o = O.assemble()
+    err = np.abs(got - want) / (np.abs(d_o) * np.abs(f).max())
+    mask = np.zeros(G.n, bool)
+    mask[uni] = True
+    note(f"k = 4 apply: max err uniform rows {err[mask].max():.2e}, "
+         f"other rows {err[~mask].max():.2e}")
+    assert err.max() <= 1e-12
+
+
 def test_k4_density_rows(pair):
     """Density rows (eq. density_linear_system) with the stability rule: row
     orders (4, 2 for the order-2 row of the same stencil, 0 for the identity)
@@ -196,6 +247,25 @@ def test_k4_lattice_stencils(apc, oracle_mod):
     np.testing.assert_array_equal(a["st_off"], b["st_off"])
     np.testing.assert_array_equal(a["st_idx"], b["st_idx"])
     assert np.diff(b["st_off"]).max() == 56
+    # the nodes two or more cells from every face have the uniform 56-node
+    # stencil: 12^3 of the 16^3 lattice
+    G.assemble_gfd()
+    uni = uniform56_rows(b, G.node_orders(), 4)
+    assert G.operator_info()["n_uniform"] == uni.size == 12 ** 3
+    w_g, d_g = G.operator()
+    w_o, d_o = O.assemble()
+    m = np.diff(a["st_off"])
+    assert np.max(np.abs(w_g - w_o) / np.repeat(np.abs(d_o), m)) <= 1e-12
+    bw_g, bd_g, ord_g = G.density_operator()
+    bw_o, bd_o = O.density_rows()
+    np.testing.assert_array_equal(ord_g, O.density_orders())
+    assert max(np.abs(bw_g - bw_o).max(), np.abs(bd_g - bd_o).max()) <= 1e-12
+    f = np.random.default_rng(13).standard_normal(G.n + G.nb)
+    got = G.apply_operator(torch.from_numpy(f).cuda()).cpu().numpy()
+    err = np.abs(got - O.apply_laplacian(f)) / (np.abs(d_o) * np.abs(f).max())
+    note(f"k = 4 lattice: {uni.size} uniform rows, density row order "
+         f"{int(ord_g[uni[0]])}, apply max err {err.max():.2e}")
+    assert err.max() <= 1e-12
     G.close()
 
 
