@@ -176,6 +176,12 @@ struct apc_cloud {
   int64_t n_uniform4 = 0;
   int32_t *gen4 = nullptr;
   int64_t n_gen4 = 0;
+  double *cder4 = nullptr; // 125 x 34: derivative operator of the canonical stencil by
+                           // lattice offset (25 (q_x+2) + 5 (q_y+2) + q_z+2), 0 off-stencil
+  // build: decision of the order-4 rank and stability test on the canonical 56-node
+  // stencil, taken by every uniform candidate (1 accept, 0 reject; -1 none: every
+  // candidate takes the QR; -2 not yet computed)
+  int uni4_rank = -2;
   // sliced-ELL copy of the operator used by the SpMV (see sell.hip)
   int64_t nsl = 0, sl_entries = 0;
   int64_t sl_cs[9] = {0, 0, 0, 0, 0, 0, 0, 0, 0}; // slice range of each XCD chunk
@@ -242,7 +248,7 @@ int apc_apply_precond_impl(apc_cloud *c, int precond, const double *in, double *
                            hipStream_t s);
 int apc_node_derivs_impl(apc_cloud *c, const double *f, double *D, hipStream_t s);
 // k = 4 (gfd4.hip)
-int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t np,
+int apc_rank_check4(apc_cloud *c, int pk, const int32_t *pending, int64_t np,
                     const int32_t *cand, int32_t *m, hipStream_t s);
 int apc_assemble4(apc_cloud *c, hipStream_t s);
 // uniform 56-node rows: canonical constants, rkind4 and the list of the other rows
@@ -291,5 +297,5 @@ int apc_build_sell(apc_cloud *c, hipStream_t s);
 int apc_pack_sell_idx(apc_cloud *c, hipStream_t s);
 void apc_free_sell(apc_cloud *c);
 // stencil rank test of pending nodes (k = 2); clears m[y] of rejected nodes
-int apc_rank_check(const apc_cloud *c, int order, const int32_t *pending, int64_t np,
+int apc_rank_check(apc_cloud *c, int order, const int32_t *pending, int64_t np,
                    const int32_t *cand, int32_t *m, hipStream_t s);

@@ -938,7 +938,7 @@ void apc_free_cloud(apc_cloud *c) {
   free_cloud_arrays(c);
   void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, c->scratch,
                  c->m_diag, c->m_sell, c->m_tmpl, c->bw64, c->bw32, c->sl_bw64, c->sl_bw32,
-                 c->rorder, c->dorder, c->w64ref, c->fb_list, c->rkind4, c->gen4};
+                 c->rorder, c->dorder, c->w64ref, c->fb_list, c->rkind4, c->gen4, c->cder4};
   for (void *q : ops)
     if (q) (void)apc_dev_free(q);
   delete c;

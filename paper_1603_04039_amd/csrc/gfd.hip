@@ -487,7 +487,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // 9x9 normal equations; k = 4 clouds (order-4 rows and their order-2 fallback
 // rows) by the column-parallel Householder QR (one wavefront per candidate
 // stencil), the oracle's algorithm.
-int apc_rank_check(const apc_cloud *c, int order, const int32_t *pending, int64_t np,
+int apc_rank_check(apc_cloud *c, int order, const int32_t *pending, int64_t np,
                    const int32_t *cand, int32_t *m, hipStream_t s) {
   if (c->P.order == 4) return apc_rank_check4(c, order == 4 ? 34 : 9, pending, np, cand, m, s);
   hipLaunchKernelGGL(k_rank9, dim3(grid_for(np)), dim3(APC_BLOCK), 0, s, pending, np, cand, m,

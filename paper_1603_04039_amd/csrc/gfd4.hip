@@ -32,6 +32,7 @@
 
 #include <cmath>
 #include <cstring>
+#include <vector>
 
 #include "apc_internal.h"
 
@@ -336,18 +337,53 @@ __device__ __forceinline__ void wv0_times(Wave4 &S, const Geo &g, int lane, int 
   z2 = s2;
 }
 
+// r^2 (in cells) of entry j of a uniform 56-node stencil in (r^2, index) order
+__device__ __forceinline__ int shell4_r2(int j) {
+  return j < 6 ? 1 : (j < 18 ? 2 : (j < 26 ? 3 : (j < 32 ? 4 : 5)));
+}
+
 // ---------------------------------------------------------------- rank test (build)
+// uni >= 0 (order-4 test only): a candidate that is the uniform 56-node stencil
+// (entry j at a lattice offset of spacing h/2 with r^2 = shell4_r2(j) spacings;
+// the stencil lists candidates by (r^2, index)) takes the decision `uni` of the
+// canonical stencil without a QR: its QR inputs (offsets over h, weights) equal the
+// canonical ones exactly, up to the order of rows within a shell.  diag (the
+// canonical run): ratio, s1, s2 of candidate 0.
 template <int MR>
 __global__ void __launch_bounds__(WPB4 * 64, 2)
     k_rank_qr(int pc, double tau, const int32_t *__restrict__ pending, int64_t np,
               const int32_t *__restrict__ cand, int32_t *__restrict__ m,
-              const int32_t *__restrict__ crd, int64_t ntot) {
+              const int32_t *__restrict__ crd, int64_t ntot, int uni, double *__restrict__ diag) {
   __shared__ Wave4 SH[WPB4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * WPB4 + wv;
   if (t >= np) return;
   const int mm = m[t];
   if (mm <= 0) return;
+  if (uni >= 0 && pc == P4 && mm == 56) {
+    const int32_t y = pending[t];
+    int32_t d[3] = {0, 0, 0};
+    if (lane < 56) {
+      const int32_t v = cand[t * APC_MAXM + lane];
+      for (int k = 0; k < 3; k++) d[k] = abs(crd[k * ntot + v] - crd[k * ntot + y]);
+    }
+    const int32_t h = wmax_i(max(d[0], max(d[1], d[2])));
+    const int32_t sp = h >> 1;
+    bool ok = true;
+    if (lane < 56) {
+      int q2 = 0;
+      for (int k = 0; k < 3; k++) {
+        ok = ok && (d[k] == 0 || d[k] == sp || d[k] == h);
+        const int q = d[k] == 0 ? 0 : (d[k] == sp ? 1 : 2);
+        q2 += q * q;
+      }
+      ok = ok && sp > 0 && (h & 1) == 0 && q2 == shell4_r2(lane);
+    }
+    if (wmax_i(ok ? 0 : 1) == 0) {
+      if (lane == 0 && uni == 0) m[t] = 0;
+      return;
+    }
+  }
   Wave4 &S = SH[wv];
   const Geo g = stencil_rows(S, lane, cand + t * APC_MAXM, mm, crd, ntot, pending[t]);
   wsync();
@@ -363,7 +399,12 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
     const double sv = lane < mm ? g.W * z1 : 0.0;
     const double s1 = wsum(sv), s2 = wsum(fabs(sv));
     ok = s1 > 0.0 && s2 <= tau * s1;
+    if (diag && lane == 0) {
+      diag[1] = s1;
+      diag[2] = s2;
+    }
   }
+  if (diag && lane == 0) diag[0] = ratio;
   if (lane == 0 && !ok) m[t] = 0;
 }
 
@@ -861,10 +902,6 @@ __global__ void __launch_bounds__(APC_BLOCK)
 }
 
 // ---------------------------------------------------------------- uniform 56-node rows
-// r^2 (in cells) of entry j of a uniform 56-node stencil in (r^2, index) order
-__device__ __forceinline__ int shell4_r2(int j) {
-  return j < 6 ? 1 : (j < 18 ? 2 : (j < 26 ? 3 : (j < 32 ? 4 : 5)));
-}
 
 // Structural test run at build time: is the node's stencil (an order-4 row) the
 // uniform 56-node stencil of its own level, i.e. the nodes at lattice offsets of
@@ -972,17 +1009,40 @@ struct Canon4 {
   double w64[56], bw64[56], diag[1], inv_diag[1], hscale[1];
 };
 
+// the canonical stencil (host): node 0 at (4, 4, 4), nodes 1 .. 56 at the 56
+// offsets in (r^2, enumeration) order
+static inline void canon4_stencil(Canon4 &h) {
+  memset(&h, 0, sizeof(h));
+  int k = 1;
+  for (int a = 0; a < 3; a++) h.crd[57 * a] = 4;
+  for (int r2 = 1; r2 <= 5; r2++)
+    for (int dx = -2; dx <= 2; dx++)
+      for (int dy = -2; dy <= 2; dy++)
+        for (int dz = -2; dz <= 2; dz++) {
+          if (dx * dx + dy * dy + dz * dz != r2 || abs(dx) + abs(dy) + abs(dz) > 3) continue;
+          h.crd[k] = 4 + dx;
+          h.crd[57 + k] = 4 + dy;
+          h.crd[114 + k] = 4 + dz;
+          k++;
+        }
+  h.st_off[0] = 0;
+  h.st_off[1] = 56;
+  for (int j = 0; j < 56; j++) h.st_idx[j] = j + 1;
+  h.rorder[0] = 4;
+}
+
 // ---------------------------------------------------------------- derivatives
 template <int MR>
 __global__ void __launch_bounds__(WPB4 * 64, 2)
-    k_node_derivs4(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
-                   const int32_t *__restrict__ crd, int64_t ntot, const int8_t *__restrict__ rorder,
-                   double unit,
+    k_node_derivs4(int64_t n, const int32_t *__restrict__ list, const int32_t *__restrict__ st_off,
+                   const int32_t *__restrict__ st_idx, const int32_t *__restrict__ crd, int64_t ntot,
+                   const int8_t *__restrict__ rorder, double unit,
                    const double *__restrict__ f, double *__restrict__ D) {
   __shared__ Wave4 SH[WPB4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
-  const int64_t y = (int64_t)blockIdx.x * WPB4 + wv;
-  if (y >= n) return;
+  const int64_t t = (int64_t)blockIdx.x * WPB4 + wv;
+  if (t >= n) return;
+  const int64_t y = list ? (int64_t)list[t] : t;
   Wave4 &S = SH[wv];
   const int32_t a0 = st_off[y];
   const int m = st_off[y + 1] - a0;
@@ -1001,6 +1061,69 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
     const double hp = (double)g.h * unit;
     for (int q = 0; q < ax + ay + az; q++) hk *= hp;
     D[y * P4 + lane] = ai / hk;
+  }
+}
+
+// Derivative operator of the canonical 56-node stencil: C[j][a] = the unknown a of
+// the fit of f = e_j (the same QR steps as k_node_derivs4), so that at a uniform
+// node d_a = sum_j C[j][a] (f_j - f_0) / hp^|alpha_a|.  One wavefront per j.
+__global__ void __launch_bounds__(WPB4 * 64, 2)
+    k_canon_derivs4(const int32_t *__restrict__ st_idx, const int32_t *__restrict__ crd,
+                    double *__restrict__ C) {
+  __shared__ Wave4 SH[WPB4];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int j = blockIdx.x * WPB4 + wv;
+  if (j >= 56) return;
+  Wave4 &S = SH[wv];
+  const Geo g = stencil_rows(S, lane, st_idx, 56, crd, 57, 0);
+  S.A[P4 * LD + lane] = lane == j ? g.W : 0.0;
+  wsync();
+  col_qr<56>(S, lane, P4, P4 + 1);
+  const double ai = solve_r(S, lane, P4, lane < P4 ? S.A[lane * RLD + P4] : 0.0);
+  if (lane < P4) C[j * P4 + lane] = ai;
+}
+
+// Derivatives of the uniform 56-node nodes from the canonical operator, tabulated
+// by lattice offset: T[o][a] with o = 25 (q_x + 2) + 5 (q_y + 2) + (q_z + 2) for the
+// offset q (in spacings) of a stencil node (the shells' order by node index differs
+// from node to node; the offset names the canonical entry).  One thread per node,
+// T in LDS; hp = 2 spacings.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_derivs_u4(int64_t n, const int8_t *__restrict__ rkind4, const int32_t *__restrict__ st_off,
+                const int32_t *__restrict__ st_idx, const int32_t *__restrict__ crd, int64_t ntot,
+                int Dmax, double unit, const double *__restrict__ T, const double *__restrict__ f,
+                double *__restrict__ D) {
+  __shared__ double Ts[125 * P4];
+  for (int q = threadIdx.x; q < 125 * P4; q += APC_BLOCK) Ts[q] = T[q];
+  __syncthreads();
+  const int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y >= n) return;
+  const int l = rkind4[y];
+  if (l < 0) return;
+  const int sh = Dmax - l + 1; // spacing 2^sh integer units
+  const int32_t a0 = st_off[y];
+  const double f0 = f[y];
+  const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y];
+  double acc[P4];
+#pragma unroll
+  for (int a = 0; a < P4; a++) acc[a] = 0.0;
+  for (int j = 0; j < 56; j++) {
+    const int32_t v = st_idx[a0 + j];
+    const int o = 25 * (((crd[v] - c0) >> sh) + 2) + 5 * (((crd[ntot + v] - c1) >> sh) + 2) +
+                  (((crd[2 * ntot + v] - c2) >> sh) + 2);
+    const double df = f[v] - f0;
+    const double *t = Ts + o * P4;
+#pragma unroll
+    for (int a = 0; a < P4; a++) acc[a] += t[a] * df;
+  }
+  const double hp = ldexp(unit, sh + 1);
+  double hk[5];
+  hk[0] = 1.0;
+  for (int q = 1; q <= 4; q++) hk[q] = hk[q - 1] * hp;
+#pragma unroll
+  for (int a = 0; a < P4; a++) {
+    const int deg = a < 3 ? 1 : (a < 9 ? 2 : (a < 19 ? 3 : 4));
+    D[y * P4 + a] = acc[a] / hk[deg];
   }
 }
 
@@ -1053,17 +1176,61 @@ inline unsigned grid4(int64_t count) {
 
 } // namespace
 
-int apc_rank_check4(const apc_cloud *c, int pk, const int32_t *pending, int64_t np,
+// The canonical stencil's order-4 rank and stability test (the same kernel, on the
+// canonical stencil): c->uni4_rank = its decision when both margins are wide
+// (ratio at least twice the rank bound, s2 / (tau s1) outside [1 - 1e-9, 1 + 1e-9]),
+// else -1 (every candidate takes the QR).  Synchronises.
+static int rank_uniform4(apc_cloud *c, double tau, hipStream_t s) {
+  Canon4 h;
+  canon4_stencil(h);
+  struct Buf {
+    Canon4 cn;
+    int32_t pend, m;
+    double diag[3];
+  };
+  Buf hb;
+  memset(&hb, 0, sizeof(hb));
+  hb.cn = h;
+  hb.pend = 0;
+  hb.m = 56;
+  Buf *d = nullptr;
+  HIPCHK(apc_malloc_async((void **)&d, sizeof(Buf), s));
+  HIPCHK(hipMemcpyAsync(d, &hb, sizeof(Buf), hipMemcpyHostToDevice, s));
+  // the canonical candidate list: nodes 1 .. 56 (cand has the APC_MAXM stride; one row)
+  int32_t *cand = nullptr;
+  HIPCHK(apc_malloc_async((void **)&cand, APC_MAXM * sizeof(int32_t), s));
+  int32_t hc[APC_MAXM];
+  for (int j = 0; j < APC_MAXM; j++) hc[j] = j < 56 ? j + 1 : 0;
+  HIPCHK(hipMemcpyAsync(cand, hc, sizeof(hc), hipMemcpyHostToDevice, s));
+  hipLaunchKernelGGL(k_rank_qr<56>, dim3(1), dim3(WPB4 * 64), 0, s, P4, tau,
+                     (const int32_t *)&d->pend, (int64_t)1, (const int32_t *)cand, &d->m,
+                     (const int32_t *)d->cn.crd, (int64_t)57, -1, d->diag);
+  HIPCHK(hipGetLastError());
+  HIPCHK(hipMemcpyAsync(&hb, d, sizeof(Buf), hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(apc_free_async(d, s));
+  HIPCHK(apc_free_async(cand, s));
+  const double ratio = hb.diag[0], s1 = hb.diag[1], s2 = hb.diag[2];
+  const bool wide_rank = ratio >= 2.0 * APC_TAU_RANK;
+  const double q = s1 > 0.0 ? s2 / (tau * s1) : 0.0;
+  const bool wide_dom = s1 > 0.0 && (q < 1.0 - 1e-9 || q > 1.0 + 1e-9);
+  c->uni4_rank = (wide_rank && wide_dom) ? (hb.m == 56 ? 1 : 0) : -1;
+  return APC_OK;
+}
+
+int apc_rank_check4(apc_cloud *c, int pk, const int32_t *pending, int64_t np,
                     const int32_t *cand, int32_t *m, hipStream_t s) {
   if (np <= 0) return APC_OK;
   // stencils hold at most m_cap rows (order-2 fallback: 40): QR over 56 or 64 rows
   const double tau = c->P.tau_dom > 0.0 ? c->P.tau_dom : APC_TAU_DOM;
+  if (pk == P4 && c->uni4_rank == -2) APCCHK(rank_uniform4(c, tau, s));
+  const int uni = pk == P4 ? c->uni4_rank : -1;
   if (c->P.m_cap <= 56)
     hipLaunchKernelGGL(k_rank_qr<56>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, tau, pending,
-                       np, cand, m, c->crd, c->n + c->nb);
+                       np, cand, m, c->crd, c->n + c->nb, uni, (double *)nullptr);
   else
     hipLaunchKernelGGL(k_rank_qr<APC_MAXM>, dim3(grid4(np)), dim3(WPB4 * 64), 0, s, pk, tau,
-                       pending, np, cand, m, c->crd, c->n + c->nb);
+                       pending, np, cand, m, c->crd, c->n + c->nb, uni, (double *)nullptr);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
@@ -1082,24 +1249,7 @@ int apc_prepare_uniform4(apc_cloud *c, hipStream_t s) {
   for (double &v : c->tmpl4) v = 0.0;
   c->dorder4 = 0;
   Canon4 h;
-  memset(&h, 0, sizeof(h));
-  int k = 1;
-  for (int a = 0; a < 3; a++) h.crd[57 * a] = 4;
-  for (int r2 = 1; r2 <= 5; r2++)
-    for (int dx = -2; dx <= 2; dx++)
-      for (int dy = -2; dy <= 2; dy++)
-        for (int dz = -2; dz <= 2; dz++) {
-          if (dx * dx + dy * dy + dz * dz != r2 || abs(dx) + abs(dy) + abs(dz) > 3) continue;
-          h.crd[k] = 4 + dx;
-          h.crd[57 + k] = 4 + dy;
-          h.crd[114 + k] = 4 + dz;
-          k++;
-        }
-  if (k != 57) return APC_EINVAL;
-  h.st_off[0] = 0;
-  h.st_off[1] = 56;
-  for (int j = 0; j < 56; j++) h.st_idx[j] = j + 1;
-  h.rorder[0] = 4;
+  canon4_stencil(h);
   Canon4 *d = nullptr;
   HIPCHK(apc_malloc_async((void **)&d, sizeof(Canon4), s));
   HIPCHK(hipMemcpyAsync(d, &h, sizeof(Canon4), hipMemcpyHostToDevice, s));
@@ -1113,10 +1263,25 @@ int apc_prepare_uniform4(apc_cloud *c, hipStream_t s) {
                      d->st_idx, d->crd, (int64_t)57, d->level, d->rorder, 1.0, 1.0, d->w64,
                      (float *)nullptr, d->bw64, (float *)nullptr, d->diag, d->inv_diag, d->hscale,
                      d->dorder, (double *)nullptr, &d->err);
+  // the canonical derivative operator (56 x 34), then tabulated by offset (125 x 34)
+  HIPCHK(apc_dev_alloc((void **)&c->cder4, 125 * P4 * sizeof(double)));
+  double *cj = nullptr;
+  HIPCHK(apc_malloc_async((void **)&cj, 56 * P4 * sizeof(double), s));
+  hipLaunchKernelGGL(k_canon_derivs4, dim3((56 + WPB4 - 1) / WPB4), dim3(WPB4 * 64), 0, s,
+                     (const int32_t *)d->st_idx, (const int32_t *)d->crd, cj);
   HIPCHK(hipGetLastError());
+  std::vector<double> hcj(56 * P4), tab(125 * P4, 0.0);
+  HIPCHK(hipMemcpyAsync(hcj.data(), cj, hcj.size() * sizeof(double), hipMemcpyDeviceToHost, s));
   HIPCHK(hipMemcpyAsync(&h, d, sizeof(Canon4), hipMemcpyDeviceToHost, s));
   HIPCHK(hipStreamSynchronize(s));
   HIPCHK(apc_free_async(d, s));
+  HIPCHK(apc_free_async(cj, s));
+  for (int j = 0; j < 56; j++) {
+    const int o = 25 * (h.crd[j + 1] - 2) + 5 * (h.crd[57 + j + 1] - 2) + (h.crd[114 + j + 1] - 2);
+    for (int a = 0; a < P4; a++) tab[o * P4 + a] = hcj[j * P4 + a];
+  }
+  HIPCHK(hipMemcpyAsync(c->cder4, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice, s));
+  HIPCHK(hipStreamSynchronize(s));
   const int lo[6] = {0, 6, 18, 26, 32, 56};
   double tl[5], tb[5], dev = 0.0, wmax = 0.0, bmax = 0.0;
   bool ok = h.err == 0;
@@ -1260,15 +1425,24 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
   return APC_OK;
 }
 
+// Householder QR per node for the general nodes; the uniform 56-node nodes through
+// the canonical derivative operator.
 int apc_node_derivs4(apc_cloud *c, const double *f, double *D, hipStream_t s) {
-  if (c->n > 0 && c->P.m_cap <= 56)
-    hipLaunchKernelGGL(k_node_derivs4<56>, dim3(grid4(c->n)), dim3(WPB4 * 64), 0, s, c->n,
+  const bool uni = c->n_uniform4 > 0 && c->cder4;
+  const int64_t cnt = uni ? c->n_gen4 : c->n;
+  const int32_t *list = uni ? c->gen4 : nullptr;
+  if (cnt > 0 && c->P.m_cap <= 56)
+    hipLaunchKernelGGL(k_node_derivs4<56>, dim3(grid4(cnt)), dim3(WPB4 * 64), 0, s, cnt, list,
                        c->st_off, c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder,
                        c->unit, f, D);
-  else if (c->n > 0)
-    hipLaunchKernelGGL(k_node_derivs4<APC_MAXM>, dim3(grid4(c->n)), dim3(WPB4 * 64), 0, s, c->n,
-                       c->st_off, c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder,
+  else if (cnt > 0)
+    hipLaunchKernelGGL(k_node_derivs4<APC_MAXM>, dim3(grid4(cnt)), dim3(WPB4 * 64), 0, s, cnt,
+                       list, c->st_off, c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder,
                        c->unit, f, D);
+  if (uni)
+    hipLaunchKernelGGL(k_derivs_u4, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n,
+                       (const int8_t *)c->rkind4, c->st_off, c->st_idx, c->crd, c->n + c->nb,
+                       c->P.max_depth, c->unit, (const double *)c->cder4, f, D);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }
