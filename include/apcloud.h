@@ -81,7 +81,7 @@ typedef struct {
   int precision;    /* APC_FP64, APC_MIXED or APC_MIXED_F32ACC, fixed at build time */
   int stage_cap;    /* operator kernels: a 64-row slice with at most this many distinct
                        neighbour columns gathers them once into LDS (performance only,
-                       same results bit for bit); 0 = default (1008, also the maximum),
+                       same results bit for bit); 0 = default (768), at most 1008,
                        -1 = never */
   int criterion_pow; /* exponent e of the criterion thresholds T_l = (c 2^l / L)^e:
                         0 = 2k - 2 (eq. errorbalance_implementation, the default);
@@ -203,6 +203,14 @@ int apc_get_operator(const apc_cloud *c, double *w_host, double *diag_host);
    the device. */
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
                       int64_t *sell_entries, int64_t *m_entries, int64_t *staged);
+
+/* Boxed slices of the operator layout (k = 4; 0 at k = 2): 64-row slices that are
+   one Morton-aligned 4 x 4 x 4 block of same-level rows with the uniform 56-node
+   stencil; the operator kernels address their neighbours through the block's
+   8 x 8 x 8 box of node ids (540 int32 per slice: the 512 cells, laid out with
+   padding) and read no per-entry column
+   index.  *n_boxed receives their count.  APC_EINVAL on NULL arguments. */
+int apc_operator_boxes(const apc_cloud *c, int64_t *n_boxed);
 
 /* WLS charge assignment (Sec. 3.2 step 1): rho_M_j = (1/h_j^3) sum_{i in cell j} q_i
    (NGP kernel: the node's own octree cell, edge h_j), then B rho~ = rho_M with

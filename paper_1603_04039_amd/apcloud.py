@@ -28,7 +28,8 @@ LEARN_QUAD = MLP_OUT * (MLP_OUT + 1) // 2 + MLP_OUT + 1
 # every symbol declared in include/apcloud.h
 EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_nodes",
            "apc_assemble_gfd", "apc_get_operator", "apc_get_node_orders",
-           "apc_get_density_operator", "apc_operator_info", "apc_deposit", "apc_density_solve",
+           "apc_get_density_operator", "apc_operator_info", "apc_operator_boxes", "apc_deposit",
+           "apc_density_solve",
            "apc_solve", "apc_interpolate_force", "apc_interpolate_force_noalloc", "apc_node_derivs", "apc_apply_operator",
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
@@ -103,6 +104,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_assemble_gfd.argtypes = [P, P]
     lib.apc_get_operator.argtypes = [P, P, P]
     lib.apc_operator_info.argtypes = [P] + [ct.POINTER(I64)] * 5
+    lib.apc_operator_boxes.argtypes = [P, ct.POINTER(I64)]
     lib.apc_get_node_orders.argtypes = [P, P]
     lib.apc_get_density_operator.argtypes = [P, P, P, P]
     lib.apc_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
@@ -284,6 +286,12 @@ class Cloud:
         _check(self.lib.apc_get_operator(self.h, w.ctypes.data_as(ct.c_void_p),
                                          d.ctypes.data_as(ct.c_void_p)), "apc_get_operator")
         return w, d
+
+    def operator_boxes(self):
+        """Number of boxed slices (64-row 4 x 4 x 4 blocks of uniform k = 4 rows)."""
+        v = ct.c_int64()
+        _check(self.lib.apc_operator_boxes(self.h, ct.byref(v)), "apc_operator_boxes")
+        return v.value
 
     def operator_info(self, m_entries=False, staged=False):
         v = [ct.c_int64() for _ in range(4)]

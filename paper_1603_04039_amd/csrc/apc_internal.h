@@ -25,7 +25,18 @@
 #ifndef APC_UCAP_MAX
 #define APC_UCAP_MAX 1008
 #endif
+// default tile cap (stage_cap = 0): 768 doubles a wave keep a 256-thread block at
+// 24,576 bytes, six blocks per compute unit (the register limit of the operator
+// kernels); on the 1e8-particle k = 4 cloud the apply ran 352-360 us against
+// 372-375 us at 1008 (same build, interleaved runs), 366 at 640, 425 at 544
+#define APC_UCAP_DEFAULT 768
 #define APC_SLICE 64      // rows per sliced-ELL slice: one wavefront
+// box of a boxed slice: cell (x, y, z) of the 8 x 8 x 8 box at x + 8 y + 64 z;
+// APC_BOX_N positions.  (A z stride of 68, 4 mod 32, halves the LDS bank conflicts
+// of the neighbour reads but ran slower: 443 against 423 us per apply on the 1e8
+// k = 4 cloud, the extra box positions cost more than the conflicts.)
+#define APC_BOX_SZ 64
+#define APC_BOX_N (7 + 8 * 7 + APC_BOX_SZ * 7 + 1)
 #define APC_TAU_FP32 0.1  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
 #define APC_MAX_LEVELS 24 // > max_depth (<= 20): per-level tables
 
@@ -188,8 +199,8 @@ struct apc_cloud {
   int32_t *sl_rows = nullptr;  // nsl * 64 row ids (-1 = padding lane)
   int32_t *sl_len = nullptr;   // entries per row in the slice
   int32_t *sl_tmpl = nullptr;  // 1: uniform 2-ring slice (k = 2), 2: uniform 56-node slice
-                               // (k = 4; the SpMV reads no weights), 0: general; 32-bit:
-                               // scalar loads
+                               // (k = 4; the SpMV reads no weights), 3 | (box << 2): boxed
+                               // slice (below), 0: general; 32-bit: scalar loads
   int64_t *sl_off = nullptr;   // first entry of the slice (a multiple of 4 x 64: slices
                                // hold a multiple of 4 entries per row)
   int32_t *sl_idx = nullptr;   // column indices, entry-major within a slice
@@ -207,6 +218,15 @@ struct apc_cloud {
   int32_t *sl_uq = nullptr;
   uint32_t *sl_lx2 = nullptr;
   int ucap = 0;
+  // boxed slices (k = 4): a slice whose 64 rows are one Morton-aligned 4 x 4 x 4
+  // block of uniform 56-node rows of one level (lane = Morton index within the
+  // block) has sl_tmpl = 3 | (box << 2); box b is sl_box[APC_BOX_N b ..]: the node
+  // of every cell of the 8 x 8 x 8 box around the block that a stencil of the block
+  // reaches, at (x + 2) + 8 (y + 2) + APC_BOX_SZ (z + 2) for the cell's local
+  // coordinates (-1 elsewhere).  The operator kernels find every neighbour's box position from
+  // the lane and the offset and read no per-entry index.
+  int64_t n_boxes = 0;
+  int32_t *sl_box = nullptr;
   double *sl_w64 = nullptr;    // weights (general slices), APC_FP64
   float *sl_w32 = nullptr;     // weights (general slices), mixed modes
   apc_solver_ws *ws = nullptr;

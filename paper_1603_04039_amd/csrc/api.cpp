@@ -198,6 +198,12 @@ int apc_get_node_orders(const apc_cloud *c, int8_t *order_host) {
   return APC_OK;
 }
 
+int apc_operator_boxes(const apc_cloud *c, int64_t *n_boxed) {
+  if (!c || !n_boxed) return APC_EINVAL;
+  *n_boxed = c->n_boxes;
+  return APC_OK;
+}
+
 int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_general,
                       int64_t *sell_entries, int64_t *m_entries, int64_t *staged) {
   if (!c || !c->assembled) return APC_EINVAL;

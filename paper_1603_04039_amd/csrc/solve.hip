@@ -584,7 +584,10 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *invd, const double
   APCCHK(launch_restart<TMODE>(w, op, b, x, 1, gs, s));
   const bool timed = (c->diag_flags & APC_DIAG_KERNEL_TIMES) != 0;
   if (timed && !w->kev_made) {
-    for (hipEvent_t &e : w->kev) HIPCHK(hipEventCreate(&e));
+    // timing-only events: no system-scope fence (the default event's cache write-back
+    // and invalidate would slow the SpMV it brackets; the chunk's read of the
+    // solver scalars synchronises before the times are read)
+    for (hipEvent_t &e : w->kev) HIPCHK(hipEventCreateWithFlags(&e, hipEventDisableSystemFence));
     w->kev_made = true;
   }
   int chunk = 8, nrest = 0, status = APC_ENOCONV, it0 = 0;

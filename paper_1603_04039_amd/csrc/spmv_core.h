@@ -36,6 +36,7 @@ struct Op {
   const int32_t *sl_un, *sl_uq;
   const uint32_t *sl_lx2;
   int ucap;
+  const int32_t *sl_box; // boxes of the boxed slices (APC_BOX_N node ids each, -1 unused)
   int64_t cs[9];
 };
 
@@ -108,21 +109,23 @@ __device__ __forceinline__ void wave_lds_sync() {
 }
 
 // Gathers x at the slice's u distinct columns (ascending, so that neighbouring
-// lanes read neighbouring addresses) into the tile: four loads a lane in flight.
-// Every lane of the wavefront takes part.
+// lanes read neighbouring addresses) into the tile: PER loads a lane in flight
+// (all PER column loads, then all PER gathers).  Every lane of the wavefront takes
+// part.
+template <int PER = 4>
 __device__ __forceinline__ void stage_fill(double *tile, const int32_t *__restrict__ uq, int u,
                                            const double *__restrict__ x) {
   const int lane = threadIdx.x & 63;
   wave_lds_sync();
-  for (int b = 0; b < u; b += 4 * SL) {
-    int32_t q[4];
-    double v[4];
+  for (int b = 0; b < u; b += PER * SL) {
+    int32_t q[PER];
+    double v[PER];
 #pragma unroll
-    for (int h = 0; h < 4; h++) q[h] = b + SL * h + lane < u ? uq[b + SL * h + lane] : -1;
+    for (int h = 0; h < PER; h++) q[h] = b + SL * h + lane < u ? uq[b + SL * h + lane] : -1;
 #pragma unroll
-    for (int h = 0; h < 4; h++) v[h] = q[h] >= 0 ? x[q[h]] : 0.0;
+    for (int h = 0; h < PER; h++) v[h] = q[h] >= 0 ? x[q[h]] : 0.0;
 #pragma unroll
-    for (int h = 0; h < 4; h++)
+    for (int h = 0; h < PER; h++)
       if (q[h] >= 0) tile[b + SL * h + lane] = v[h];
   }
   wave_lds_sync();
@@ -276,11 +279,80 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
   }
   return op.hs ? xi + op.hs[row] * acc : (op.unit_diag ? xi + acc : acc);
 }
+// Offsets (x + 8 y + APC_BOX_SZ z, in box positions) of the 56 nodes of the uniform stencil:
+// r^2 = 1 .. 5 cells, each shell in the enumeration order (dx, then dy, then dz
+// ascending).
+struct Box56 {
+  int off[56];
+  constexpr Box56() : off() {
+    int k = 0;
+    for (int r2 = 1; r2 <= 5; r2++)
+      for (int dx = -2; dx <= 2; dx++)
+        for (int dy = -2; dy <= 2; dy++)
+          for (int dz = -2; dz <= 2; dz++) {
+            const int ax = dx < 0 ? -dx : dx, ay = dy < 0 ? -dy : dy, az = dz < 0 ? -dz : dz;
+            if (dx * dx + dy * dy + dz * dz != r2 || ax + ay + az > 3) continue;
+            off[k++] = dx + 8 * dy + APC_BOX_SZ * dz;
+          }
+  }
+};
+constexpr Box56 kBox56{};
+
+// (A x)_row for the lane's row of a boxed slice (tk = its sl_tmpl): the lane's cell
+// sits at box position b = (lx + 2) + 8 (ly + 2) + APC_BOX_SZ (lz + 2), its
+// neighbour at offset q at b + q_x + 8 q_y + APC_BOX_SZ q_z.  STG: the box's x values are gathered into
+// the wavefront's LDS tile first (positions without a node are skipped); otherwise
+// each entry reads x through the box's node id.  Both sum the 56 entries in the
+// order of kBox56 with the shell weights, then scale once (same arithmetic, so the
+// same result bit for bit).
+template <int MODE, bool STG>
+__device__ __forceinline__ double box_apply(const Op &op, const double *__restrict__ x, int s,
+                                            int tk, int32_t &row) {
+  const int lane = threadIdx.x & 63;
+  const int32_t *__restrict__ bx = op.sl_box + (int64_t)(tk >> 2) * APC_BOX_N;
+  const int lx = ((lane >> 2) & 1) | (((lane >> 5) & 1) << 1);
+  const int ly = ((lane >> 1) & 1) | (((lane >> 4) & 1) << 1);
+  const int lz = (lane & 1) | (((lane >> 3) & 1) << 1);
+  const int b = (lx + 2) + 8 * (ly + 2) + APC_BOX_SZ * (lz + 2);
+  double *tile = STG ? stage_tile(op) : nullptr;
+  if (STG) stage_fill<APC_BOX_N / SL>(tile, bx, APC_BOX_N, x); // one batch: 8 per lane
+  row = op.sl_rows[(int64_t)s * SL + lane];
+  const double xi = x[row];
+  const double scale = op.t4_scaled ? ldexp(op.invL2, 2 * (int)op.rk[row]) : 1.0;
+#define APC_BV(k) (STG ? tile[b + kBox56.off[k]] : x[bx[b + kBox56.off[k]]])
+#define APC_T4(c, k) ((k) < 6 ? c[0] : ((k) < 18 ? c[1] : ((k) < 26 ? c[2] : ((k) < 32 ? c[3] : c[4]))))
+  double acc;
+  if (MODE == V32A32) {
+    float cf[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) cf[k] = (float)op.t4[k];
+    float af = 0.f;
+#pragma unroll 8
+    for (int k = 0; k < 56; k++) af += APC_T4(cf, k) * (float)(APC_BV(k) - xi);
+    acc = (double)af * scale;
+  } else {
+    double cd[5];
+#pragma unroll
+    for (int k = 0; k < 5; k++) cd[k] = MODE == V64 ? op.t4[k] : (double)(float)op.t4[k];
+    double ad = 0.0;
+#pragma unroll 8
+    for (int k = 0; k < 56; k++) ad += APC_T4(cd, k) * (APC_BV(k) - xi);
+    acc = ad * scale;
+  }
+#undef APC_T4
+#undef APC_BV
+  return op.unit_diag ? xi + acc : acc;
+}
+
 // Kernels that call this are launched with op_lds(op) bytes of dynamic LDS.
 template <int MODE>
 __device__ __forceinline__ double sell_apply(const Op &op, const double *__restrict__ x, int s_in,
                                              int32_t &row) {
   const int s = __builtin_amdgcn_readfirstlane(s_in);
+  const int tk = op.sl_tmpl[s];
+  if ((tk & 3) == 3)
+    return (op.sl_un && op.ucap >= APC_BOX_N) ? box_apply<MODE, true>(op, x, s, tk, row)
+                                        : box_apply<MODE, false>(op, x, s, tk, row);
   const int u = op.sl_un ? op.sl_un[s] : 0;
   if (u > 0) return sell_apply_t<MODE, false, true>(op, x, s, u, row);
   return op.sl_top4 ? sell_apply_t<MODE, true, false>(op, x, s, 0, row)
@@ -315,6 +387,7 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   op.sl_un = c->ucap > 0 ? c->sl_un : nullptr;
   op.sl_uq = c->sl_uq;
   op.sl_lx2 = c->sl_lx2;
+  op.sl_box = c->sl_box;
   for (int k = 0; k < 9; k++) op.cs[k] = c->sl_cs[k];
   return op;
 }

@@ -252,6 +252,8 @@ def test_k4_lattice_stencils(apc, oracle_mod):
     G.assemble_gfd()
     uni = uniform56_rows(b, G.node_orders(), 4)
     assert G.operator_info()["n_uniform"] == uni.size == 12 ** 3
+    # complete 4 x 4 x 4 blocks of uniform rows: origins at 4 and 8 per axis
+    assert G.operator_boxes() == 8
     w_g, d_g = G.operator()
     w_o, d_o = O.assemble()
     m = np.diff(a["st_off"])

@@ -37,16 +37,20 @@ def bits(t):
 
 
 LATTICE5 = dict(order=2, c=1e-3, max_depth=5)  # a uniform 32^3 grid: nearly all rows uniform
+# the same grid at fourth order: 216 boxed slices (complete 4 x 4 x 4 blocks of
+# uniform rows), which run from their box staged (tile >= 512) or unstaged
+LATTICE5_K4 = dict(order=4, c=1e-3, max_depth=5)
 
 
-@pytest.mark.parametrize("workload", ["beam_halo_1e5", "beam_halo_k4_3e4", "lattice5"])
+@pytest.mark.parametrize("workload", ["beam_halo_1e5", "beam_halo_k4_3e4", "lattice5",
+                                      "lattice5_k4"])
 @pytest.mark.parametrize("precision", ["fp64", "mixed"])
 def test_staging_changes_no_result(apc, workload, precision):
     from paper_1603_04039_amd import learned
-    cfg = LATTICE5 if workload == "lattice5" else CONFIGS[workload]
+    cfg = {"lattice5": LATTICE5, "lattice5_k4": LATTICE5_K4}.get(workload) or CONFIGS[workload]
     prec = apc.APC_FP64 if precision == "fp64" else apc.APC_MIXED
     note(f"staging: {workload} {precision}")
-    if workload == "lattice5":
+    if workload.startswith("lattice5"):
         xyz = uniform_lattice_points(5)
     else:
         xyz = beam_halo(cfg["N"], seed=cfg["seed"], sigma=cfg["sigma"], halo_frac=cfg["halo_frac"])
@@ -59,6 +63,8 @@ def test_staging_changes_no_result(apc, workload, precision):
         return cl
 
     full = build(0)
+    if workload == "lattice5_k4":
+        assert full.operator_boxes() == 216  # 4 x 4 x 4 blocks with origins 4 .. 24
     info = full.operator_info(staged=True)
     assert info["staged_slices"] > 0 and 0 < info["stage_tile"] <= 1008
     assert info["staged_distinct"] <= info["staged_entries"]
@@ -67,7 +73,7 @@ def test_staging_changes_no_result(apc, workload, precision):
     clouds = {"full": full, "off": build(-1), "part": build(mid_cap)}
     part = clouds["part"].operator_info(staged=True)
     assert 0 < part["staged_slices"] <= info["staged_slices"]
-    if workload != "lattice5":  # the lattice's slices may all sit at the mean
+    if not workload.startswith("lattice5"):  # the lattice's slices may all sit at the mean
         assert part["staged_slices"] < info["staged_slices"]
     assert part["stage_tile"] <= mid_cap
     assert clouds["off"].operator_info(staged=True)["staged_slices"] == 0
