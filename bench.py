@@ -225,19 +225,23 @@ def counted_traffic(name):
 
 
 def spmv_bytes(cloud, info, value_bytes, index_bytes_layout):
-    """Bytes per operator SpMV launch.  survey: the algorithmic count per row of the
-    hot-path table, (m_i + 1) (value + 4 B index) + 8 B y_i + 4 B row pointer + 8 B
-    x_i, i.e. (value + 4) (nnz + n) + 20 n.  layout: what the sliced layout has to
-    move: per stored entry its index (3 B) and weight, nothing for uniform rows
-    (the 24-node 2-ring of k = 2, the 56-node stencil of k = 4) but their indices
-    and a level byte, per row a 4 B row id, x_i and y_i (the diagonal is implied by
-    the zero row sums)."""
+    """Bytes per operator SpMV launch.  survey: the per-row count of the hot-path
+    table, (m_i + 1) (value + 4 B index) + 8 B y_i + 4 B row pointer + 8 B x_i, i.e.
+    (value + 4) (nnz + n) + 20 n -- a stored value for every entry.  layout: what
+    this operator's sliced layout has to move: per stored entry its index (3 B) and
+    weight; for uniform rows (the 24-node 2-ring of k = 2, the 56-node stencil of
+    k = 4) no weights, only their indices and a level byte; for the rows of boxed
+    slices (k = 4) no per-entry index either, the block's 512 box node ids (32 B a
+    row); per row a 4 B row id, x_i and y_i (the diagonal is implied by the zero
+    row sums)."""
     n, nnz = info["n"], info["nnz"]
     oi = cloud.operator_info()
     survey = (value_bytes + 4) * (nnz + n) + 20 * n
     ib = index_bytes_layout
     mu = 24 if cloud.p == 9 else 56
-    layout = oi["n_uniform"] * (mu * ib + 1) + oi["nnz_general"] * (ib + value_bytes) + n * 20
+    n_box = 64 * cloud.operator_boxes()
+    layout = (n_box * 32 + (oi["n_uniform"] - n_box) * (mu * ib + 1)
+              + oi["nnz_general"] * (ib + value_bytes) + n * 20)
     return int(survey), int(layout)
 
 
@@ -525,7 +529,10 @@ def main():
     vb = 8 if prec == apc.APC_FP64 else 4
     b_survey, b_layout = spmv_bytes(cloud, info, vb, index_bytes(cloud))
     avg_us = info["spmv_avg_us"]
-    gbs = b_survey / (avg_us * 1e-6) / 1e9
+    # achieved: the layout's bytes (what this operator must move: the uniform rows
+    # carry no weights, the boxed rows no per-entry indices); the per-row count of
+    # the hot-path table (a value for every entry) is given beside it
+    gbs = b_layout / (avg_us * 1e-6) / 1e9
     pmc_name = f"k_spmv_{args.workload}_{args.precision}_hbm_counters.md"
     traffic = counted_traffic(pmc_name)
     mode = {"fp64": "V64", "mixed": "V32A64", "mixed_f32acc": "V32A32"}[args.precision]
@@ -535,10 +542,11 @@ def main():
                 kernel=f"k_spmv_v<{mode}> and k_spmv_t<{mode}> (BiCGSTAB operator SpMVs, "
                        "sliced layout)",
                 avg_us=round(avg_us, 2), launches_per_step=info["spmv_launches_per_step"],
-                bytes_per_launch=b_survey, layout_bytes_per_launch=b_layout,
-                layout_GBs=round(b_layout / (avg_us * 1e-6) / 1e9, 1),
-                timing="HIP events around every SpMV launch of the timed solves, on the "
-                       "library's stream")
+                bytes_per_launch=b_layout, boxed_slices=cloud.operator_boxes(),
+                survey_bytes_per_launch=b_survey,
+                survey_GBs=round(b_survey / (avg_us * 1e-6) / 1e9, 1),
+                timing="HIP events (no system fence) around every SpMV launch of the timed "
+                       "solves, on the library's stream")
     if traffic is not None:
         roof["traffic_GBs"] = round(traffic / (avg_us * 1e-6) / 1e9, 1)
     log(f"roofline: {roof}")
@@ -596,11 +604,11 @@ def main():
             if (name, pcn) == ("mixed", "jacobi"):
                 sb, lb = spmv_bytes(cl2, info2, 4, index_bytes(cl2))
                 au = info2["spmv_avg_us"]
-                k2["spmv_mixed"] = dict(avg_us=round(au, 2), bytes_per_launch=sb,
-                                        GBs=round(sb / (au * 1e-6) / 1e9, 1),
-                                        frac=round(sb / (au * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
-                                        layout_bytes_per_launch=lb,
-                                        layout_GBs=round(lb / (au * 1e-6) / 1e9, 1))
+                k2["spmv_mixed"] = dict(avg_us=round(au, 2), bytes_per_launch=lb,
+                                        GBs=round(lb / (au * 1e-6) / 1e9, 1),
+                                        frac=round(lb / (au * 1e-6) / 1e9 / HBM_PEAK_GBS, 4),
+                                        survey_bytes_per_launch=sb,
+                                        survey_GBs=round(sb / (au * 1e-6) / 1e9, 1))
                 k2["assembly_mixed"] = assembly_roofline(torch, cl2, 10, True)
             if (name, pcn) == ("mixed", "none"):
                 r64, _ = fp64_reference_residual(apc, torch, cl2, rt2, args.tol)
