@@ -348,6 +348,28 @@ def batch_bench(apc, torch, steps, tol):
         e2.synchronize()
         seq += e0.elapsed_time(e2)
         S.close()
+    # the whole field solve (assembly, deposit + density solve, Poisson solve,
+    # interpolation) as one graph replay, against the same through the separate
+    # entry points (the pipeline's first call)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    bufs, _, _, used0 = B.pipeline(tol_density=1e-10, tol=tol, precond=apc.APC_PRECOND_JACOBI)
+    e1.record(stream)
+    e1.synchronize()
+    t_sep = e0.elapsed_time(e1)
+    pipe, used_all = [], True
+    for it in range(steps + 1):
+        e0.record(stream)
+        _, sd, sp, used = B.pipeline(tol_density=1e-10, tol=tol, precond=apc.APC_PRECOND_JACOBI,
+                                     out=bufs)
+        e1.record(stream)
+        e1.synchronize()
+        if any(x["status"] != 0 for x in sd + sp):
+            raise RuntimeError("batch pipeline did not converge")
+        if it > 0:
+            pipe.append(e0.elapsed_time(e1))
+            used_all = used_all and used
+    t_pipe = sum(pipe) / len(pipe)
     out = dict(workload=f"beam_halo_batch{BATCH['count']}", clouds=B.count,
                particles=int(B.N), nodes=int(n_tot),
                nodes_per_s=round(n_tot / ((t_asm + t_sol) * 1e-3), 1),
@@ -355,6 +377,11 @@ def batch_bench(apc, torch, steps, tol):
                iters_min=min(iters), iters_max=max(iters),
                sequential_nodes_per_s=round(n_tot / (seq * 1e-3), 1),
                speedup_vs_sequential=round(seq / (t_asm + t_sol), 3),
+               pipeline=dict(ms=round(t_pipe, 3), separate_ms=round(t_sep, 3),
+                             graph_every_step=used_all,
+                             what="assembly, deposit + density solve (1e-10), Poisson solve "
+                                  "(Jacobi), interpolation of all clouds: one HIP graph replay "
+                                  "per step, against the separate entry points"),
                tuned=dict(spmv_div=div, chunk=chunk, spmv_blocks=B.info["spmv_blocks"],
                           use_graph=B.info["use_graph"]))
     B.close()

@@ -410,6 +410,29 @@ int apc_batch_solve(apc_batch *b, const double *rho_t, const double *g, double *
    (N_total), grad_p (3 x N_total SoA).  Does not synchronise. */
 int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, double *grad_p,
                                 hipStream_t stream);
+/* One field solve of every cloud of the batch -- assembly, NGP deposit and density
+   solve, Poisson solve, interpolation -- replayed as one HIP graph with no host work
+   inside.  Each of the two BiCGSTAB solves runs a fixed budget of iterations in the
+   graph: every cloud tests its own convergence on the device and skips its rows
+   once it has stopped, and one true-residual check on the device closes each
+   solve.  The first call runs the separate entry points (apc_batch_assemble,
+   apc_batch_deposit, apc_batch_solve, apc_batch_interpolate_force) and sets the
+   budgets from every cloud's iteration counts (the largest, plus a quarter, at
+   least 4); later calls replay the graph, which is recorded again when a pointer,
+   a tolerance, maxit, the preconditioner or the SpMV launch shape changes.  A
+   replay that leaves a cloud unfinished (more iterations or a restart needed)
+   enlarges the budgets and runs that call through the separate entry points.
+   q (N_total or NULL), g (nb_total or NULL), rho_t (n_total + nb_total), phi
+   (n_total + nb_total), phi_p (N_total), grad_p (3 x N_total) as in those entry
+   points; precond APC_PRECOND_NONE or APC_PRECOND_JACOBI (the density solve runs
+   without).  st_density, st: count host records each (may be NULL; ms is the
+   graph's time when it ran); *graph_used (may be NULL): 1 when this call replayed
+   the graph.  Returns APC_ENOCONV if a cloud did not converge.  Synchronises.
+   The graph holds the batch's workspace: calls on one batch must not overlap. */
+int apc_batch_pipeline(apc_batch *b, const double *q, const double *g, double tol_density,
+                       double tol, int maxit, int precond, double *rho_t, double *phi,
+                       double *phi_p, double *grad_p, apc_stats *st_density, apc_stats *st,
+                       int *graph_used, hipStream_t stream);
 void apc_batch_destroy(apc_batch *b);
 
 /* ---- Vlasov-Poisson time loop (Sec. 1) ----

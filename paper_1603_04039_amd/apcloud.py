@@ -34,7 +34,8 @@ EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_n
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
            "apc_batch_configure", "apc_batch_tune", "apc_batch_assemble", "apc_batch_deposit",
-           "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_destroy", "apc_push",
+           "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_pipeline",
+           "apc_batch_destroy", "apc_push",
            "apc_step", "apc_set_diagnostics", "apc_destroy", "apc_strerror", "apc_last_error"]
 
 
@@ -128,6 +129,8 @@ def load_library(path: str = LIB_PATH):
     lib.apc_batch_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, P, P]
     lib.apc_batch_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, P, P]
     lib.apc_batch_interpolate_force.argtypes = [P, P, P, P, P]
+    lib.apc_batch_pipeline.argtypes = [P, P, P, ct.c_double, ct.c_double, ct.c_int, ct.c_int,
+                                       P, P, P, P, P, P, ct.POINTER(ct.c_int), P]
     lib.apc_batch_destroy.argtypes = [P]
     lib.apc_batch_destroy.restype = None
     lib.apc_push.argtypes = [ct.POINTER(Params), I64, P, P, P, ct.c_double, ct.c_double, P]
@@ -582,6 +585,32 @@ class Batch:
             self.h, _dptr(phi, torch.float64, self.n + self.nb), _dptr(phi_p), _dptr(grad_p),
             _stream(stream)), "apc_batch_interpolate_force")
         return phi_p, grad_p
+
+    def pipeline(self, q=None, g=None, tol_density=1e-12, tol=1e-8, maxit=20000,
+                 precond=APC_PRECOND_JACOBI, out=None, stream=None):
+        """Assembly, deposit with the density solve, Poisson solve and interpolation of
+        every cloud as one graph replay (apc_batch_pipeline).  out: the four output
+        tensors (rho_t, phi, phi_p, grad_p) to reuse, so that the recorded graph is
+        replayed (new buffers record it again).  Returns (rho_t, phi, phi_p, grad_p),
+        the density and Poisson records, and whether the graph ran."""
+        import torch
+        nt = self.n + self.nb
+        if out is None:
+            out = (torch.empty(nt, dtype=torch.float64, device="cuda"),
+                   torch.empty(nt, dtype=torch.float64, device="cuda"),
+                   torch.empty(self.N, dtype=torch.float64, device="cuda"),
+                   torch.empty((3, self.N), dtype=torch.float64, device="cuda"))
+        rho_t, phi, phi_p, grad_p = out
+        sd, sp = self._stats(), self._stats()
+        used = ct.c_int()
+        rc = _check(self.lib.apc_batch_pipeline(
+            self.h, _dptr(q, torch.float64, self.N), _dptr(g, torch.float64, self.nb),
+            tol_density, tol, maxit, precond, _dptr(rho_t, torch.float64, nt),
+            _dptr(phi, torch.float64, nt), _dptr(phi_p, torch.float64, self.N),
+            _dptr(grad_p, torch.float64, 3 * self.N), ct.cast(sd, ct.c_void_p),
+            ct.cast(sp, ct.c_void_p), ct.byref(used), _stream(stream)), "apc_batch_pipeline")
+        return (out, [dict(x.as_dict(), rc=rc) for x in sd], [dict(x.as_dict(), rc=rc) for x in sp],
+                bool(used.value))
 
 
 # C-ABI names as free functions

@@ -310,6 +310,10 @@ int apc_batch_deposit_impl(apc_batch *B, const double *q, double *rho_M, double 
 int apc_batch_solve_impl(apc_batch *B, const double *rho_t, const double *g, double *phi,
                          double tol, int maxit, int precond, apc_stats *st, hipStream_t s);
 int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, hipStream_t s);
+int apc_batch_pipeline_impl(apc_batch *B, const double *q, const double *g, double tol_d,
+                            double tol, int maxit, int precond, double *rho_t, double *phi,
+                            double *phi_p, double *grad_p, apc_stats *st_d, apc_stats *st,
+                            int *graph_used, hipStream_t s);
 void apc_free_solver(apc_cloud *c);
 int apc_build_sell(apc_cloud *c, hipStream_t s);
 // (re)build sl_lo2 / sl_hi4 / sl_top4 and the neighbour staging from sl_idx

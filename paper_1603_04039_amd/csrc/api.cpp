@@ -422,6 +422,19 @@ int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, 
   return apc_interpolate_force(apc_batch_union(b), phi, phi_p, grad_p, stream);
 }
 
+int apc_batch_pipeline(apc_batch *b, const double *q, const double *g, double tol_density,
+                       double tol, int maxit, int precond, double *rho_t, double *phi,
+                       double *phi_p, double *grad_p, apc_stats *st_density, apc_stats *st,
+                       int *graph_used, hipStream_t stream) {
+  if (!b || !rho_t || !phi || !phi_p || !grad_p || !(tol > 0.0) || !(tol_density > 0.0) ||
+      maxit < 1)
+    return APC_EINVAL;
+  DeviceGuard gd(apc_batch_union(b)->device);
+  if (!gd.ok) return APC_EHIP;
+  return apc_batch_pipeline_impl(b, q, g, tol_density, tol, maxit, precond, rho_t, phi, phi_p,
+                                 grad_p, st_density, st, graph_used, stream);
+}
+
 void apc_batch_destroy(apc_batch *b) {
   if (!b) return;
   DeviceGuard g(apc_batch_union(b)->device);

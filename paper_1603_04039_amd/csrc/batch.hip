@@ -372,6 +372,20 @@ __global__ void __launch_bounds__(APC_BLOCK)
   if (b < nb) v[n + b] = v[bowner[b]];
 }
 
+// fresh solver records (a kernel, so that a captured graph holds no host copy)
+__global__ void kb_init_sc(BScal *sc, int count, double tol, int maxit) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= count) return;
+  BScal q;
+  q.rho = q.alpha = q.omega = q.beta = 0.0;
+  q.bnorm = q.rnorm = q.rtrue = 0.0;
+  q.tol = tol;
+  q.it = 0;
+  q.maxit = maxit;
+  q.done = q.fin = q.nrest = q.reason = q.pad0 = q.pad1 = 0;
+  sc[c] = q;
+}
+
 // remember why each cloud stopped before the check overwrites done
 __global__ void kb_mark_reason(BScal *sc, int count) {
   const int c = blockIdx.x * blockDim.x + threadIdx.x;
@@ -405,6 +419,19 @@ struct apc_batch {
   hipGraph_t graph[2][3][2] = {};
   int gchunk[2][3][2] = {};
   int gdiv[2][3][2] = {};
+  // pipeline graph (apc_batch_pipeline): its own solver records (density, then
+  // Poisson), rho_M and the derivative workspace, the iteration budgets and what
+  // the graph was recorded with
+  BScal *sc_pipe = nullptr, *scp_host = nullptr;
+  double *rhoM = nullptr, *Dw = nullptr;
+  int budget_d = 0, budget_p = 0;
+  hipGraph_t pgraph = nullptr;
+  hipGraphExec_t pexec = nullptr;
+  struct Key {
+    const void *ptr[7];
+    double tol_d, tol;
+    int maxit, precond, budget_d, budget_p, div;
+  } pkey = {};
 };
 
 namespace {
@@ -839,6 +866,11 @@ int apc_build_batch_impl(const apc_params *P, int count, const double *const *xy
 
 void apc_destroy_batch_impl(apc_batch *B) {
   if (!B) return;
+  if (B->pexec) (void)hipGraphExecDestroy(B->pexec);
+  if (B->pgraph) (void)hipGraphDestroy(B->pgraph);
+  for (void *q : {(void *)B->sc_pipe, (void *)B->rhoM, (void *)B->Dw})
+    if (q) (void)hipFree(q);
+  if (B->scp_host) (void)hipHostFree(B->scp_host);
   for (int a = 0; a < 2; a++)
     for (int m = 0; m < 3; m++)
       for (int j = 0; j < 2; j++) {
@@ -1004,4 +1036,184 @@ int apc_batch_tune_impl(apc_batch *B, double tol, int *out_div, int *out_chunk, 
   if (out_div) *out_div = B->spmv_div;
   if (out_chunk) *out_chunk = B->chunk;
   return rc < 0 ? rc : APC_OK;
+}
+
+// ---------------------------------------------------------------- pipeline graph
+namespace {
+
+// one batched BiCGSTAB recorded into the capture stream: fresh records, x = 0, the
+// start, `budget` iterations (clouds that stop skip their rows), then one
+// true-residual check; sc: the solve's own records
+template <int MODE, bool JAC>
+void record_solve(apc_batch *B, bool density, BScal *sc, double tol, int maxit, int budget,
+                  hipStream_t cs) {
+  const Op op = make_op(B->u, density);
+  const BDesc D = make_desc(B);
+  BScal *save = B->sc;
+  B->sc = sc;
+  hipLaunchKernelGGL(kb_init_sc, dim3((B->count + 63) / 64), dim3(64), 0, cs, sc, B->count, tol,
+                     maxit);
+  hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(B->u->n)), dim3(APC_BLOCK), 0, cs, B->x, B->u->n, 0.0);
+  launch_restart<MODE>(B, op, D, 1, cs);
+  for (int k = 0; k < budget; k++) launch_iteration<MODE, JAC>(B, op, D, B->u->inv_diag, cs);
+  hipLaunchKernelGGL(kb_mark_reason, dim3((B->count + 255) / 256), dim3(256), 0, cs, sc, B->count);
+  launch_restart<MODE>(B, op, D, 0, cs);
+  B->sc = save;
+}
+
+template <int MODE>
+void record_solve_any(apc_batch *B, bool density, BScal *sc, double tol, int maxit, int budget,
+                      bool jac, hipStream_t cs) {
+  if (jac)
+    record_solve<MODE, true>(B, density, sc, tol, maxit, budget, cs);
+  else
+    record_solve<MODE, false>(B, density, sc, tol, maxit, budget, cs);
+}
+
+// assembly, deposit and density solve, Poisson solve and interpolation, recorded
+// on the batch's capture stream
+int record_pipeline(apc_batch *B, const double *q, const double *g, double tol_d, double tol,
+                    int maxit, int precond, double *rho_t, double *phi, double *phi_p,
+                    double *grad_p, hipStream_t cs) {
+  apc_cloud *u = B->u;
+  const bool jac = precond == APC_PRECOND_JACOBI;
+  APCCHK(apc_assemble_impl(u, cs));
+  hipLaunchKernelGGL(kb_deposit, dim3(grid_for(u->n)), dim3(APC_BLOCK), 0, cs, u->n, u->first,
+                     u->count, u->level, u->perm, q, (const double *)B->invN, u->P.L, B->rhoM);
+  if (u->nb > 0)
+    hipLaunchKernelGGL(kb_bnd_copy, dim3(grid_for(u->nb)), dim3(APC_BLOCK), 0, cs, u->n, u->nb,
+                       u->bowner, B->rhoM);
+  APCCHK(rhs(B, true, B->rhoM, 1.0, B->rhoM + u->n, cs));
+  auto solve = [&](bool density, BScal *sc, double t, int budget, bool j) {
+    switch (B->P.precision) {
+    case APC_MIXED_F32ACC: record_solve_any<V32A32>(B, density, sc, t, maxit, budget, j, cs); break;
+    case APC_MIXED: record_solve_any<V32A64>(B, density, sc, t, maxit, budget, j, cs); break;
+    default: record_solve_any<V64>(B, density, sc, t, maxit, budget, j, cs);
+    }
+  };
+  solve(true, B->sc_pipe, tol_d, B->budget_d, false);
+  hipLaunchKernelGGL(kb_write_out, dim3(grid_for(u->n + u->nb)), dim3(APC_BLOCK), 0, cs, u->n, u->nb,
+                     (const double *)B->x, (const double *)(B->rhoM + u->n), rho_t);
+  APCCHK(rhs(B, false, rho_t, B->P.poisson_c, g, cs));
+  solve(false, B->sc_pipe + B->count, tol, B->budget_p, jac);
+  hipLaunchKernelGGL(kb_write_out, dim3(grid_for(u->n + u->nb)), dim3(APC_BLOCK), 0, cs, u->n, u->nb,
+                     (const double *)B->x, g, phi);
+  APCCHK(apc_interp_with(u, phi, phi_p, grad_p, B->Dw, cs));
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
+void pipe_stats(const BScal &q, int precond, float ms, apc_stats *st) {
+  st->iters = q.it;
+  st->restarts = q.nrest;
+  st->sweeps = 1 + q.nrest;
+  st->status = q.fin == 1 ? APC_OK : APC_ENOCONV;
+  st->rel_resid = q.bnorm > 0.0 ? q.rnorm / q.bnorm : 0.0;
+  st->rel_resid_true = q.rtrue;
+  st->n_fp64_rows = 0;
+  st->precond_used = precond;
+  st->ms = ms;
+}
+
+} // namespace
+
+int apc_batch_pipeline_impl(apc_batch *B, const double *q, const double *g, double tol_d,
+                            double tol, int maxit, int precond, double *rho_t, double *phi,
+                            double *phi_p, double *grad_p, apc_stats *st_d, apc_stats *st,
+                            int *graph_used, hipStream_t s) {
+  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI) return APC_EINVAL;
+  if (B->P.order != 2) return APC_EINVAL;
+  APCCHK(ensure_bws(B));
+  apc_cloud *u = B->u;
+  const int64_t ntot = u->n + u->nb;
+  if (!B->sc_pipe) {
+    APCCHK(dmalloc(&B->sc_pipe, 2 * B->count));
+    APCCHK(dmalloc(&B->rhoM, ntot));
+    APCCHK(dmalloc(&B->Dw, u->n * 9)); // k = 2: 9 derivatives a node
+    HIPCHK(hipHostMalloc((void **)&B->scp_host, (size_t)2 * B->count * sizeof(BScal),
+                         hipHostMallocDefault));
+  }
+  if (graph_used) *graph_used = 0;
+  std::vector<apc_stats> sd((size_t)B->count), sp((size_t)B->count);
+  // the separate entry points: the first call (it sets the budgets) and any call
+  // whose graph left a cloud unfinished
+  auto separate = [&]() -> int {
+    APCCHK(apc_assemble_impl(u, s));
+    int rc = apc_batch_deposit_impl(B, q, B->rhoM, rho_t, tol_d, maxit, sd.data(), s);
+    if (rc < 0) return rc;
+    const int rc2 = apc_batch_solve_impl(B, rho_t, g, phi, tol, maxit, precond, sp.data(), s);
+    if (rc2 < 0) return rc2;
+    APCCHK(apc_interp_with(u, phi, phi_p, grad_p, B->Dw, s));
+    HIPCHK(hipStreamSynchronize(s));
+    int md = 0, mp = 0;
+    for (int c = 0; c < B->count; c++) {
+      md = std::max(md, sd[c].iters);
+      mp = std::max(mp, sp[c].iters);
+    }
+    // budgets: the largest count with a quarter (at least 4) to spare, raised
+    // when a graph fell short
+    B->budget_d = std::max(B->budget_d, md + std::max(4, md / 4));
+    B->budget_p = std::max(B->budget_p, mp + std::max(4, mp / 4));
+    if (st_d) memcpy(st_d, sd.data(), sd.size() * sizeof(apc_stats));
+    if (st) memcpy(st, sp.data(), sp.size() * sizeof(apc_stats));
+    return rc != APC_OK ? rc : rc2;
+  };
+  if (B->budget_d == 0 || B->budget_p == 0) return separate();
+  apc_batch::Key key;
+  memset(&key, 0, sizeof(key)); // compared bytewise, padding included
+  const void *ptrs[7] = {q, g, rho_t, phi, phi_p, grad_p, nullptr};
+  for (int k = 0; k < 7; k++) key.ptr[k] = ptrs[k];
+  key.tol_d = tol_d;
+  key.tol = tol;
+  key.maxit = maxit;
+  key.precond = precond;
+  key.budget_d = B->budget_d;
+  key.budget_p = B->budget_p;
+  key.div = B->spmv_div;
+  if (B->pexec && memcmp(&key, &B->pkey, sizeof(key)) != 0) {
+    HIPCHK(hipGraphExecDestroy(B->pexec));
+    HIPCHK(hipGraphDestroy(B->pgraph));
+    B->pexec = nullptr;
+    B->pgraph = nullptr;
+  }
+  if (!B->pexec) {
+    HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
+    const int rc = record_pipeline(B, q, g, tol_d, tol, maxit, precond, rho_t, phi, phi_p, grad_p,
+                                   B->cap);
+    hipGraph_t gr = nullptr;
+    const hipError_t e = hipStreamEndCapture(B->cap, &gr);
+    if (rc < 0) {
+      if (gr) (void)hipGraphDestroy(gr);
+      return rc;
+    }
+    HIPCHK(e);
+    B->pgraph = gr;
+    HIPCHK(hipGraphInstantiate(&B->pexec, gr, nullptr, nullptr, 0));
+    B->pkey = key;
+  }
+  HIPCHK(hipEventRecord(B->e0, s));
+  HIPCHK(hipGraphLaunch(B->pexec, s));
+  HIPCHK(hipEventRecord(B->e1, s));
+  HIPCHK(hipMemcpyAsync(B->scp_host, B->sc_pipe, (size_t)2 * B->count * sizeof(BScal),
+                        hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float ms = 0.f;
+  HIPCHK(hipEventElapsedTime(&ms, B->e0, B->e1));
+  bool all = true;
+  for (int c = 0; c < 2 * B->count; c++) all = all && B->scp_host[c].fin != 0;
+  if (!all) {
+    // a cloud needed more iterations or a restart: enlarge the budgets, record
+    // again on the next call, and run this one through the separate entry points
+    B->budget_d += std::max(4, B->budget_d / 2);
+    B->budget_p += std::max(4, B->budget_p / 2);
+    return separate();
+  }
+  int status = APC_OK;
+  for (int c = 0; c < B->count; c++) {
+    if (B->scp_host[c].fin != 1 || B->scp_host[B->count + c].fin != 1) status = APC_ENOCONV;
+    if (st_d) pipe_stats(B->scp_host[c], APC_PRECOND_NONE, ms, &st_d[c]);
+    if (st) pipe_stats(B->scp_host[B->count + c], precond, ms, &st[c]);
+  }
+  if (graph_used) *graph_used = 1;
+  return status;
 }

@@ -234,6 +234,10 @@ __global__ void __launch_bounds__(APC_BLOCK)
   rkind[y] = tmpl ? (int8_t)l : (int8_t)-1;
 }
 
+__global__ void k_zero_u64(unsigned long long *p) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) *p = 0ull;
+}
+
 // FP64 fit of a general row: weights into the CSR copy and the slice (FP32 storage
 // in the mixed modes), diagonal; returns the R-diagonal ratio.
 template <bool MIXED>
@@ -570,7 +574,9 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
     c->assembled = true;
     return APC_OK;
   }
-  HIPCHK(hipMemsetAsync(&c->scratch->nfp64, 0, sizeof(unsigned long long), s));
+  // the counter is cleared by a kernel (a memset node of a captured graph is what a
+  // batch pipeline would record here)
+  hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, s, &c->scratch->nfp64);
   if (c->nsl > 0) {
     if (mixed) {
       hipLaunchKernelGGL(k_fit_sell<true>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,

@@ -147,6 +147,46 @@ def test_batch_graph_replays_equal_eager(apc, small_batch):
     B.configure(use_graph=1, chunk=8)
 
 
+def test_batch_pipeline_graph(apc, small_batch):
+    """The whole field solve of the batch (assembly, deposit and density solve,
+    Poisson solve, interpolation) as one graph replay: the first call runs the
+    separate entry points and sets the iteration budgets, later calls replay the
+    graph and give the same outputs and iteration counts bit for bit, also with
+    other work of the program between replays; a tighter tolerance records a new
+    graph (or falls back once to the separate entry points and enlarges the
+    budgets) and still converges."""
+    note("batch pipeline graph vs the separate entry points")
+    B, singles, _, _ = small_batch
+    pc = apc.APC_PRECOND_JACOBI
+    out, sd0, sp0, used = B.pipeline(tol_density=1e-12, tol=1e-10, precond=pc)
+    assert not used
+    assert all(s["status"] == 0 for s in sd0 + sp0)
+    ref = [t.clone() for t in out]
+    # the separate entry points themselves give the same values
+    _, rho_t, _ = B.deposit(tol=1e-12, maxit=20000)
+    phi, _ = B.solve(rho_t, tol=1e-10, precond=pc)
+    assert torch.equal(rho_t, ref[0]) and torch.equal(phi, ref[1])
+    for rep in range(3):
+        out2, sd, sp, used = B.pipeline(tol_density=1e-12, tol=1e-10, precond=pc, out=out)
+        assert used, rep
+        for a, b in zip(out2, ref):
+            assert torch.equal(a, b), rep
+        assert [s["iters"] for s in sd] == [s["iters"] for s in sd0]
+        assert [s["iters"] for s in sp] == [s["iters"] for s in sp0]
+        assert all(s["status"] == 0 for s in sd + sp)
+        S = singles[rep % len(singles)]
+        S.apply_operator(torch.rand(S.n + S.nb, dtype=torch.float64, device="cuda"))
+        torch.cuda.synchronize()
+    used_any = False
+    for k in range(3):
+        out3, sd, sp, used = B.pipeline(tol_density=1e-12, tol=1e-12, precond=pc, out=out)
+        assert all(s["status"] == 0 for s in sd + sp)
+        assert all(s["rel_resid_true"] <= 1e-12 for s in sp)
+        note(f"  tol 1e-12 call {k}: graph {used}, iters {[s['iters'] for s in sp]}")
+        used_any = used_any or used
+    assert used_any
+
+
 def test_batch_tune(apc, small_batch):
     note("batch autotuner")
     B, _, _, _ = small_batch
