@@ -217,7 +217,8 @@ int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_gener
     HIPCHK(hipMemcpy(off.data(), c->st_off, off.size() * sizeof(int32_t), hipMemcpyDeviceToHost));
     std::vector<int8_t> rk((size_t)(c->n > 0 ? c->n : 1));
     if (c->n > 0)
-      HIPCHK(hipMemcpy(rk.data(), c->rkind, (size_t)c->n, hipMemcpyDeviceToHost));
+      HIPCHK(hipMemcpy(rk.data(), c->P.order == 4 ? c->rkind4 : c->rkind, (size_t)c->n,
+                       hipMemcpyDeviceToHost));
     int64_t tot = 0;
     for (int64_t i = 0; i < c->n; i++)
       if (rk[i] < 0) tot += std::min<int64_t>(off[i + 1] - off[i], APC_MLP_OUT - 1);

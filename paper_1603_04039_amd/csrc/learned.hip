@@ -24,8 +24,11 @@ constexpr int NQ = APC_LEARN_QUAD;
 static_assert(NQ == NQQ + OUT + 1, "quadratic data layout");
 constexpr int NW = 40; // stencil-weight feature slots (= OUT - 1)
 static_assert(NW == OUT - 1, "pattern");
-constexpr int NT = 26; // per-level row of M for uniform 2-ring rows: the diagonal, the 24
-                       // stencil entries, and 1 / d (the level's Jacobi row, for the safeguard)
+// per-level row of M for the uniform rows: the diagonal, the stencil entries of M (24 of a
+// 2-ring row, the first 40 of a 56-node row), and 1 / d (the level's Jacobi row, for the
+// safeguard); rows of NT2 (k = 2) or NT4 (k = 4) floats
+constexpr int NT2 = 26, NT4 = 42;
+__host__ __device__ constexpr int nt_of(int order) { return order == 4 ? NT4 : NT2; }
 // parameter offsets
 constexpr int OW1 = 0, OB1 = OW1 + IN * HID, OW2 = OB1 + HID, OB2 = OW2 + HID * HID,
               OW3 = OB2 + HID, OB3 = OW3 + HID * OUT, NPAR = OB3 + OUT;
@@ -35,7 +38,9 @@ struct RowOp {
   const int32_t *st_off, *st_idx;
   const double *w64;
   const float *w32;
-  const int8_t *rk;
+  const int8_t *rk;   // level of a uniform 2-ring row (k = 2; its weights are not stored)
+  const int8_t *lvl;  // level of a uniform row of the cloud's order (rkind or rkind4)
+  int order;
   const double *diag;
   const int32_t *level;
   double tc[3];
@@ -308,7 +313,7 @@ struct InferOut {
   float *o;             // mode 0: n x OUT
   float *m_diag;        // mode 1
   float *m_sell;        // mode 1 (operator's sliced layout)
-  float *m_tmpl;        // mode 2: APC_MAX_LEVELS x NT
+  float *m_tmpl;        // mode 2: APC_MAX_LEVELS x nt_of(order)
 };
 struct InferIn {
   RowOp r;
@@ -392,9 +397,9 @@ __global__ void __launch_bounds__(WPB * 64)
   float *H = hl[wv];
   for (int64_t s0 = (int64_t)blockIdx.x * WPB + wv; s0 < in.nsl; s0 += (int64_t)gridDim.x * WPB) {
     const int64_t s = __builtin_amdgcn_readfirstlane((int)s0);
-    // uniform 2-ring slices (k = 2) take the per-level rows; every other slice,
-    // the uniform 56-node slices of k = 4 included, its own rows
-    const bool tmpl = io.mode == 2 ? true : in.sl_tmpl[s] == 1;
+    // uniform slices (2-ring rows of k = 2; 56-node rows of k = 4, boxed or not)
+    // take the per-level rows; general slices their own rows
+    const bool tmpl = io.mode == 2 ? true : in.sl_tmpl[s] != 0;
     if (io.mode == 1 && tmpl) {
       // uniform slices use the per-level rows; m_diag holds each row's safeguard
       // weight alpha (1: the network's row)
@@ -408,6 +413,10 @@ __global__ void __launch_bounds__(WPB * 64)
       float f[IN];
       if (in.feat) {
         for (int j = 0; j < IN; j++) f[j] = row >= 0 ? in.feat[(int64_t)row * IN + j] : 0.0f;
+      } else if (io.mode == 2 && in.r.order == 4) {
+        // a uniform 56-node row: its CSR row holds the shell constants
+        if (row >= 0) row_features(in.r, row, f);
+        else for (int j = 0; j < IN; j++) f[j] = 0.0f;
       } else {
         slice_features(in, s, tmpl, l, row, f);
       }
@@ -484,8 +493,10 @@ __global__ void __launch_bounds__(WPB * 64)
         }
         const double inv = 1.0 / in.r.diag[rr];
         if (io.mode == 2) {
-          if (p < NT - 1) io.m_tmpl[NT * (int)in.r.rk[rr] + p] = (float)(((p == 0 ? 1.0 : 0.0) + (double)o) * inv);
-          if (p == NT - 1) io.m_tmpl[NT * (int)in.r.rk[rr] + p] = (float)inv;
+          const int nt = nt_of(in.r.order);
+          float *T = io.m_tmpl + nt * (int)in.r.lvl[rr];
+          if (p < nt - 1) T[p] = (float)(((p == 0 ? 1.0 : 0.0) + (double)o) * inv);
+          if (p == 0) T[nt - 1] = (float)inv;
           continue;
         }
         if (p == 0) {
@@ -508,13 +519,14 @@ __global__ void __launch_bounds__(WPB * 64)
 // sum_k (s_k + alpha t_k)^2 with s_k = U_k[i] / d_i - z_ki (the Jacobi row's probe
 // residual) and t_k = (m_i - j_i)^T U_k, then m_i <- j_i + alpha (m_i - j_i).
 // One wavefront per slice, one lane per row; U = A Z (K x ntot).  General rows
-// are scaled in place; a uniform 2-ring row keeps its level's row T of M and
-// stores alpha in m_diag (the apply forms alpha T + (1 - alpha) j_i).
+// are scaled in place; a uniform row keeps its level's row T of M (nt floats:
+// diagonal, nt - 2 stencil entries in the slice's order, 1 / d) and stores alpha in
+// m_diag (the apply forms alpha T + (1 - alpha) j_i).
 __global__ void __launch_bounds__(APC_BLOCK)
     k_safeguard(const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_tmpl,
                 const int32_t *__restrict__ sl_len, const int32_t *__restrict__ sl_idx,
                 const int64_t *__restrict__ sl_off, int64_t nsl, const double *__restrict__ diag,
-                const int8_t *__restrict__ rk, const float *__restrict__ m_tmpl,
+                const int8_t *__restrict__ rk, int nt, const float *__restrict__ m_tmpl,
                 const double *__restrict__ Z, const double *__restrict__ U, int K, int64_t n,
                 int64_t ntot, float *__restrict__ m_diag, float *__restrict__ m_sell) {
   const int64_t s0 = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
@@ -523,8 +535,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int lane = threadIdx.x & 63;
   const int32_t row = sl_rows[s * APC_SLICE + lane];
   if (row < 0) return;
-  if (sl_tmpl[s] == 1) {
-    const float *T = m_tmpl + NT * (int)rk[row];
+  if (sl_tmpl[s] != 0) {
+    const float *T = m_tmpl + nt * (int)rk[row];
     const int64_t off = sl_off[s] + lane;
     const double jd = 1.0 / diag[row];
     const double dd = (double)T[0] - jd;
@@ -534,7 +546,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
       const double ui = Uk[row];
       const double sk = ui * jd - Z[(int64_t)k * ntot + row];
       double tk = dd * ui;
-      for (int e = 0; e < 24; e++) // the 24 neighbours are interior nodes
+      for (int e = 0; e < nt - 2; e++) // the neighbours of a uniform row are interior nodes
         tk += (double)T[e + 1] * Uk[sl_idx[off + (int64_t)e * APC_SLICE]];
       st += sk * tk;
       tt += tk * tk;
@@ -592,7 +604,7 @@ __global__ void k_rep_slice(const int32_t *__restrict__ rep, int32_t *__restrict
                             float *__restrict__ tmpl) {
   const int t = threadIdx.x;
   if (t < APC_SLICE) tab[t] = (t < APC_MAX_LEVELS && rep[t] != INT_MAX) ? rep[t] : -1;
-  for (int q = t; q < APC_MAX_LEVELS * NT; q += blockDim.x) tmpl[q] = 0.f;
+  for (int q = t; q < APC_MAX_LEVELS * NT4; q += blockDim.x) tmpl[q] = 0.f;
 }
 
 __global__ void k_fill_i32(int32_t *p, int n, int32_t v) {
@@ -607,6 +619,8 @@ RowOp make_rowop(const apc_cloud *c) {
   r.w64 = c->w64;
   r.w32 = c->w32;
   r.rk = c->rkind;
+  r.lvl = c->P.order == 4 ? c->rkind4 : c->rkind;
+  r.order = c->P.order;
   r.diag = c->diag;
   r.level = c->level;
   for (int k = 0; k < 3; k++) r.tc[k] = c->tmpl[k];
@@ -759,7 +773,7 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
   if (!c->m_diag) HIPCHK(apc_dev_alloc((void **)&c->m_diag, (size_t)(n > 0 ? n : 1) * sizeof(float)));
   if (!c->m_sell)
     HIPCHK(apc_dev_alloc((void **)&c->m_sell, (size_t)(c->sl_entries > 0 ? c->sl_entries : 1) * sizeof(float)));
-  if (!c->m_tmpl) HIPCHK(apc_dev_alloc((void **)&c->m_tmpl, (size_t)APC_MAX_LEVELS * NT * sizeof(float)));
+  if (!c->m_tmpl) HIPCHK(apc_dev_alloc((void **)&c->m_tmpl, (size_t)APC_MAX_LEVELS * NT4 * sizeof(float)));
   uint16_t *wb = nullptr;
   int32_t *rep = nullptr;
   HIPCHK(apc_malloc_async((void **)&wb, (size_t)NWB * 2, s));
@@ -768,7 +782,8 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
   hipLaunchKernelGGL(k_pack_bf16, dim3(grid_for(HID * HID)), dim3(APC_BLOCK), 0, s, P, wb,
                      wb + HID * K1, wb + HID * K1 + HID * HID);
   hipLaunchKernelGGL(k_fill_i32, dim3(1), dim3(64), 0, s, rep, APC_MAX_LEVELS, INT_MAX);
-  hipLaunchKernelGGL(k_rep_rows, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, c->rkind, n, rep);
+  const int8_t *lvl = c->P.order == 4 ? c->rkind4 : c->rkind;
+  hipLaunchKernelGGL(k_rep_rows, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, lvl, n, rep);
   hipLaunchKernelGGL(k_rep_slice, dim3(1), dim3(APC_BLOCK), 0, s, (const int32_t *)rep, tab,
                      c->m_tmpl);
   // general slices: per-row M (features computed in the kernel); then the
@@ -795,7 +810,7 @@ int apc_set_learned_impl(apc_cloud *c, const float *P, const double *Z, int K, h
     }
     hipLaunchKernelGGL(k_safeguard, dim3(grid_for(c->nsl, APC_BLOCK / 64)), dim3(APC_BLOCK), 0, s,
                        c->sl_rows, c->sl_tmpl, c->sl_len, c->sl_idx, c->sl_off, c->nsl, c->diag,
-                       (const int8_t *)c->rkind, (const float *)c->m_tmpl, (const double *)Zc,
+                       lvl, nt_of(c->P.order), (const float *)c->m_tmpl, (const double *)Zc,
                        (const double *)U, K, n, ntot, c->m_diag, c->m_sell);
     HIPCHK(hipGetLastError());
     HIPCHK(apc_free_async(U, s));

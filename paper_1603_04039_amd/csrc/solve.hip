@@ -198,6 +198,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // boundary columns carry weight 0).
 struct MOp {
   const float *diag, *sell, *tmpl;
+  int nt; // floats per level row of tmpl: 26 (k = 2), 42 (k = 4)
 };
 template <bool TOP, bool STG>
 __device__ __forceinline__ void prec_slice(const Op &op, const MOp &M, const double *__restrict__ in,
@@ -223,12 +224,25 @@ __device__ __forceinline__ void prec_slice(const Op &op, const MOp &M, const dou
     if (row < 0) return;
     // the level's row T of M (diagonal, 24 entries, then 1 / d) and the row's
     // safeguard weight alpha: M_i = alpha T + (1 - alpha) e_i / d
-    const float *__restrict__ T = M.tmpl + 26 * (int)op.rk[row];
+    const float *__restrict__ T = M.tmpl + M.nt * (int)op.rk[row];
     double acc = (double)T[0] * in[row];
 #pragma unroll
     for (int k = 0; k < 24; k++) acc += (double)T[k + 1] * (STG ? tile[jj[k]] : in[jj[k]]);
     const float a = M.diag[row];
     out[row] = a == 1.0f ? acc : (double)a * acc + (1.0 - (double)a) * ((double)T[25] * in[row]);
+  } else if (op.sl_tmpl[s] != 0) {
+    // uniform 56-node row (k = 4, boxed or not): the level's row T of M on the first
+    // 40 stencil entries (the slice's order), like the 2-ring rows above
+    if (STG) stage_fill(tile, op.sl_uq + o, u, in);
+    const int32_t row = op.sl_rows[(int64_t)s * SL + lane];
+    if (row < 0) return;
+    const float *__restrict__ T = M.tmpl + M.nt * (int)op.rk[row];
+    double acc = (double)T[0] * in[row];
+#pragma unroll 8
+    for (int k = 0; k < APC_MLP_OUT - 1; k++)
+      acc += (double)T[k + 1] * (STG ? tile[stage_slot(op, lb, k)] : in[sl_col<TOP>(op, lb, hb, k)]);
+    const float a = M.diag[row];
+    out[row] = a == 1.0f ? acc : (double)a * acc + (1.0 - (double)a) * ((double)T[M.nt - 1] * in[row]);
   } else {
     // M holds the first APC_MLP_OUT - 1 stencil entries of a row (all of them
     // for k = 2; the nearest 40 of the up to 56 of k = 4)
@@ -593,7 +607,7 @@ static int bicgstab(apc_cloud *c, const Op &op, const double *invd, const double
   int chunk = 8, nrest = 0, status = APC_ENOCONV, it0 = 0;
   for (;;) {
     for (int k = 0; k < chunk; k++)
-      launch_iteration<MODE>(w, op, x, invd, MOp{c->m_diag, c->m_sell, c->m_tmpl}, prec,
+      launch_iteration<MODE>(w, op, x, invd, MOp{c->m_diag, c->m_sell, c->m_tmpl, c->P.order == 4 ? 42 : 26}, prec,
                              gs, s, timed ? &w->kev[4 * k] : nullptr);
     HIPCHK(hipGetLastError());
     APCCHK(read_sc(w, s));
@@ -807,7 +821,7 @@ int apc_apply_precond_impl(apc_cloud *c, int precond, const double *in, double *
     if (c->nsl > 0) {
       const Op op = make_op(c, false);
       hipLaunchKernelGGL(k_prec_apply, dim3(spmv_grid(c)), dim3(APC_BLOCK), op_lds(op), s, op,
-                         MOp{c->m_diag, c->m_sell, c->m_tmpl}, in, out, (const Scal *)nullptr);
+                         MOp{c->m_diag, c->m_sell, c->m_tmpl, c->P.order == 4 ? 42 : 26}, in, out, (const Scal *)nullptr);
     }
   } else if (precond == APC_PRECOND_JACOBI || precond == APC_PRECOND_NONE) {
     hipLaunchKernelGGL(k_scale_copy, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, in,
