@@ -232,6 +232,19 @@ typedef struct {
   int64_t idx;
 } kpair;
 
+/* Offset between two integer coordinates along one axis: the plain difference, or
+   on a periodic domain (side S = 2^(D+1) integer units) the minimum image in
+   [-S/2, S/2). */
+static int64_t doff(const apco_params *P, int64_t a, int64_t b) {
+  int64_t d = a - b;
+  if (P->periodic) {
+    const int64_t S = (int64_t)1 << (P->max_depth + 1);
+    if (d >= S / 2) d -= S;
+    else if (d < -(S / 2)) d += S;
+  }
+  return d;
+}
+
 static int cmp_kpair(const void *a, const void *b) {
   const kpair *x = a, *y = b;
   if (x->key != y->key) return x->key < y->key ? -1 : 1;
@@ -261,6 +274,10 @@ int apco_thresholds(const apco_params *P, double *T) {
     for (int e = 0; e < pw; e++) v *= t;
     T[l] = v;
   }
+  /* periodic: levels 0 and 1 always open, so that every leaf sees distinct cells
+     across its faces */
+  if (P->periodic)
+    for (int l = 0; l < 2 && l <= P->max_depth; l++) T[l] = 0.0;
   return 0;
 }
 
@@ -310,13 +327,17 @@ static int open_cell(apco_cloud *C, int64_t i, int why) {
 /* Face neighbour of cell i across face f (Sec. 4.3), read as the deepest cell of
    Q with level <= level(i) that shares face f with cell i (the paper's wording
    "no ancestor" is read as "no descendant": the neighbour's level only grows as
-   cells open).  -1 if the face lies on the domain boundary. */
+   cells open).  -1 if the face lies on the domain boundary (never on a periodic
+   domain). */
 static int64_t face_nb(const apco_cloud *C, int64_t i, int f) {
   const ocell *y = &C->cells[i];
   int32_t t[3] = {y->ix, y->iy, y->iz};
   int d = f / 2;
   t[d] += (f & 1) ? 1 : -1;
-  if (t[d] < 0 || t[d] >= (1 << y->level)) return -1;
+  if (C->P.periodic) /* the face across the domain boundary meets the opposite cell */
+    t[d] = (t[d] + (1 << y->level)) % (1 << y->level);
+  else if (t[d] < 0 || t[d] >= (1 << y->level))
+    return -1;
   int64_t cur = 0;
   while (C->cells[cur].child >= 0 && C->cells[cur].level < y->level) {
     int sh = y->level - C->cells[cur].level - 1;
@@ -379,7 +400,9 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
     int taken = 0;
     for (int64_t j = 0; j < cnt && taken < 2; j++) {
       const int32_t *c1 = &C->crd[3 * cd[j].idx];
-      if (!in_octant(o, c1[0] - c0[0], c1[1] - c0[1], c1[2] - c0[2])) continue;
+      if (!in_octant(o, doff(&C->P, c1[0], c0[0]), doff(&C->P, c1[1], c0[1]),
+                     doff(&C->P, c1[2], c0[2])))
+        continue;
       taken++;
       if (!pick[j] && got < want) {
         pick[j] = 1;
@@ -394,7 +417,7 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
       vals[0] = 0;
       for (int64_t j = 0; j < cnt; j++) {
         if (!pick[j]) continue;
-        int64_t o = (int64_t)C->crd[3 * cd[j].idx + d] - c0[d];
+        int64_t o = doff(&C->P, C->crd[3 * cd[j].idx + d], c0[d]);
         int seen = 0;
         for (int q = 0; q < nv; q++) seen |= vals[q] == o;
         if (!seen && nv <= MAXM) vals[nv++] = o;
@@ -403,7 +426,7 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
       int64_t add = -1;
       for (int64_t j = 0; j < cnt && add < 0; j++) {
         if (pick[j]) continue;
-        int64_t o = (int64_t)C->crd[3 * cd[j].idx + d] - c0[d];
+        int64_t o = doff(&C->P, C->crd[3 * cd[j].idx + d], c0[d]);
         int seen = 0;
         for (int q = 0; q < nv; q++) seen |= vals[q] == o;
         if (!seen) add = j;
@@ -426,7 +449,8 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
   double dx[MAXM], dy[MAXM], dz[MAXM];
   for (int j = 0; j < m; j++) {
     const int32_t *c1 = &C->crd[3 * cd[j].idx];
-    int64_t d0 = c1[0] - c0[0], d1 = c1[1] - c0[1], d2 = c1[2] - c0[2];
+    int64_t d0 = doff(&C->P, c1[0], c0[0]), d1 = doff(&C->P, c1[1], c0[1]),
+            d2 = doff(&C->P, c1[2], c0[2]);
     dx[j] = (double)d0;
     dy[j] = (double)d1;
     dz[j] = (double)d2;
@@ -488,7 +512,8 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
   if (!(P->order == 2 || P->order == 4) || P->max_depth < 1 || P->max_depth > 20 ||
       !(P->L > 0.0) || !(P->c > 0.0) || P->ring_min < 1 || P->ring_max < P->ring_min ||
       P->m_cap > MAXM || P->m_cap < p + 1 || N < 1 || P->criterion_pow < 0 ||
-      P->criterion_pow > 16 || !(P->tau_dom >= 0.0))
+      P->criterion_pow > 16 || !(P->tau_dom >= 0.0) || P->periodic < 0 || P->periodic > 1 ||
+      (P->periodic && P->max_depth < 2))
     return APCO_EINVAL;
   apco_cloud *C = calloc(1, sizeof(apco_cloud));
   if (!C) return APCO_ENOMEM;
@@ -627,7 +652,7 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
     int32_t ii[3] = {c->ix, c->iy, c->iz};
     for (int f = 0; f < 6; f++) {
       int d = f / 2;
-      int on = (f & 1) ? (ii[d] == (1 << c->level) - 1) : (ii[d] == 0);
+      int on = !P->periodic && ((f & 1) ? (ii[d] == (1 << c->level) - 1) : (ii[d] == 0));
       C->bidx[6 * j + f] = on ? (int32_t)(n + nb++) : -1;
     }
   }
@@ -754,9 +779,9 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
       }
       for (int64_t t = 1; t < nf; t++) {
         int32_t v = front[t];
-        int64_t d0 = C->crd[3 * v] - C->crd[3 * y];
-        int64_t d1 = C->crd[3 * v + 1] - C->crd[3 * y + 1];
-        int64_t d2 = C->crd[3 * v + 2] - C->crd[3 * y + 2];
+        int64_t d0 = doff(P, C->crd[3 * v], C->crd[3 * y]);
+        int64_t d1 = doff(P, C->crd[3 * v + 1], C->crd[3 * y + 1]);
+        int64_t d2 = doff(P, C->crd[3 * v + 2], C->crd[3 * y + 2]);
         cand[cnt].r2 = d0 * d0 + d1 * d1 + d2 * d2;
         cand[cnt].idx = v;
         cnt++;
@@ -866,9 +891,9 @@ static int node_fit(const apco_cloud *C, int64_t y, double *X, int *m, double *h
   double dx[MAXM], dy[MAXM], dz[MAXM];
   for (int j = 0; j < *m; j++) {
     int32_t v = C->st[a + j];
-    dx[j] = (double)(C->crd[3 * v] - C->crd[3 * y]);
-    dy[j] = (double)(C->crd[3 * v + 1] - C->crd[3 * y + 1]);
-    dz[j] = (double)(C->crd[3 * v + 2] - C->crd[3 * y + 2]);
+    dx[j] = (double)doff(&C->P, C->crd[3 * v], C->crd[3 * y]);
+    dy[j] = (double)doff(&C->P, C->crd[3 * v + 1], C->crd[3 * y + 1]);
+    dz[j] = (double)doff(&C->P, C->crd[3 * v + 2], C->crd[3 * y + 2]);
   }
   double h, ratio;
   const int ko = C->node_order[y];
@@ -980,9 +1005,9 @@ static int density_rows_ord(const apco_cloud *C, double *bw, double *bdiag, int8
       double dx[MAXM], dy[MAXM], dz[MAXM], h2, ratio2;
       for (int j = 0; j < m; j++) {
         int32_t v = C->st[a + j];
-        dx[j] = (double)(C->crd[3 * v] - C->crd[3 * y]);
-        dy[j] = (double)(C->crd[3 * v + 1] - C->crd[3 * y + 1]);
-        dz[j] = (double)(C->crd[3 * v + 2] - C->crd[3 * y + 2]);
+        dx[j] = (double)doff(&C->P, C->crd[3 * v], C->crd[3 * y]);
+        dy[j] = (double)doff(&C->P, C->crd[3 * v + 1], C->crd[3 * y + 1]);
+        dz[j] = (double)doff(&C->P, C->crd[3 * v + 2], C->crd[3 * y + 2]);
       }
       rc = wls_core(2, m, dx, dy, dz, X, &h2, &ratio2);
       if (rc) return rc;
@@ -1192,9 +1217,42 @@ static int poisson_system(const apco_cloud *C, const double *rho_t, const double
   if (!*w || !*diag || !*rhs) return APCO_ENOMEM;
   int rc = apco_assemble(C, *w, *diag);
   if (rc) return rc;
+  if (C->P.periodic) {
+    /* Delta phi = c (rho~ - rhobar), rhobar the volume-weighted mean of rho~ (the
+       neutralising background without which no periodic potential exists); the
+       operator's constant null space is removed by replacing the equation of node
+       0 with phi_0 = 0, and the solution is shifted to mean 0 afterwards */
+    double vol = 0.0, q = 0.0;
+    for (int64_t i = 0; i < n; i++) {
+      const double h = C->P.L / ldexp(1.0, C->cells[C->node_cell[i]].level);
+      vol += h * h * h;
+      q += rho_t[i] * h * h * h;
+    }
+    const double rbar = q / vol;
+    for (int64_t i = 0; i < n; i++) (*rhs)[i] = C->P.poisson_c * (rho_t[i] - rbar);
+    if (n > 0) {
+      (*rhs)[0] = 0.0;
+      (*diag)[0] = 1.0;
+      for (int32_t e = C->st_off[0]; e < C->st_off[1]; e++) (*w)[e] = 0.0;
+    }
+    return 0;
+  }
   for (int64_t i = 0; i < n; i++) (*rhs)[i] = C->P.poisson_c * rho_t[i];
   if (g) bnd_rhs(C, *w, g, *rhs);
   return 0;
+}
+
+/* periodic: phi shifted to volume-weighted mean 0 */
+static void zero_mean(const apco_cloud *C, double *phi) {
+  if (!C->P.periodic) return;
+  double vol = 0.0, q = 0.0;
+  for (int64_t i = 0; i < C->n; i++) {
+    const double h = C->P.L / ldexp(1.0, C->cells[C->node_cell[i]].level);
+    vol += h * h * h;
+    q += phi[i] * h * h * h;
+  }
+  const double m = q / vol;
+  for (int64_t i = 0; i < C->n; i++) phi[i] -= m;
 }
 
 int apco_poisson_solve(const apco_cloud *C, const double *rho_t, const double *g, double *phi,
@@ -1202,6 +1260,7 @@ int apco_poisson_solve(const apco_cloud *C, const double *rho_t, const double *g
   double *w = NULL, *diag = NULL, *rhs = NULL;
   int rc = poisson_system(C, rho_t, g, &w, &diag, &rhs);
   if (!rc) rc = bicgstab(C, diag, w, rhs, phi, tol, maxit, precond, st);
+  if (!rc) zero_mean(C, phi);
   if (!rc)
     for (int64_t b = 0; b < C->nb; b++) phi[C->n + b] = g ? g[b] : 0.0;
   free(w); free(diag); free(rhs);
@@ -1260,6 +1319,7 @@ int apco_poisson_lu(const apco_cloud *C, const double *rho_t, const double *g, d
       for (int64_t j = i + 1; j < n; j++) s -= A[i * n + j] * phi[j];
       phi[i] = s / A[i * n + i];
     }
+    if (!rc) zero_mean(C, phi);
     for (int64_t b = 0; b < C->nb; b++) phi[n + b] = g ? g[b] : 0.0;
   }
   free(A); free(w); free(diag); free(rhs);

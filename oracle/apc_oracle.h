@@ -47,6 +47,12 @@ typedef struct {
   double tau_dom; /* stability bound of order-4 Laplacian rows: accepted when the
                      diagonal is negative and sum_j |w_j| <= tau_dom |diag|;
                      0 = the default 10 */
+  int periodic;   /* 1: Omega is periodic in x, y and z (Sec. 4.3 "non-periodic region"
+                     read the other way): face neighbours wrap around, no boundary
+                     nodes, stencil offsets are minimum images, levels 0 and 1 are
+                     always opened (max_depth >= 2), and the Poisson problem is
+                     Delta phi = c (rho~ - mean rho~) with phi of mean 0 (means
+                     weighted by cell volume); 0: the Dirichlet box */
 } apco_params;
 
 typedef struct {

@@ -28,7 +28,7 @@ class _Params(ct.Structure):
     _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
-                ("criterion_pow", ct.c_int), ("tau_dom", ct.c_double)]
+                ("criterion_pow", ct.c_int), ("tau_dom", ct.c_double), ("periodic", ct.c_int)]
 
 
 class _Stats(ct.Structure):
@@ -92,7 +92,7 @@ def _check(rc, what):
 
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
-                ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0, tau_dom=0.0):
+                ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0, tau_dom=0.0, periodic=0):
     P = _Params()
     P.lo[:] = lo
     P.L = L
@@ -105,6 +105,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     P.poisson_c = poisson_c
     P.criterion_pow = criterion_pow
     P.tau_dom = tau_dom
+    P.periodic = int(periodic)
     return P
 
 
