@@ -1660,7 +1660,9 @@ int apco_node_orders(const apco_cloud *C, int8_t *ord) {
    u = (x - lo) / L is outside [0, 1]; with f = floor(u) whole lengths and
    r = u - f, the position after f wall crossings is r (f even) or 1 - r (f odd),
    x = lo + u L, and the velocity component flips sign when f is odd.  A particle
-   inside Omega keeps x + dt v as computed. */
+   inside Omega keeps x + dt v as computed.  On a periodic domain a particle that
+   leaves through one face re-enters through the opposite one: u = r, velocity
+   unchanged. */
 int apco_push(const apco_params *P, int64_t N, double *xyz, double *vel, const double *grad,
               double kick, double dt) {
   if (!P || N < 0 || !(P->L > 0.0) || !isfinite(kick) || !isfinite(dt)) return APCO_EINVAL;
@@ -1674,7 +1676,7 @@ int apco_push(const apco_params *P, int64_t N, double *xyz, double *vel, const d
         double u = (x - lo) / P->L;
         const double f = floor(u);
         const double r = u - f;
-        const int odd = fmod(f, 2.0) != 0.0;
+        const int odd = !P->periodic && fmod(f, 2.0) != 0.0;
         u = odd ? 1.0 - r : r;
         if (odd) v = -v;
         x = lo + u * P->L;

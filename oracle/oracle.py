@@ -109,14 +109,15 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     return P
 
 
-def push(xyz, vel, grad, kick, dt, lo=(0.0, 0.0, 0.0), L=1.0):
-    """Leapfrog kick-drift push with specular walls (apco_push).  xyz, vel: 3 x N
-    float64, updated copies are returned; grad: 3 x N."""
+def push(xyz, vel, grad, kick, dt, lo=(0.0, 0.0, 0.0), L=1.0, periodic=0):
+    """Leapfrog kick-drift push with specular walls, or wrap-around on a periodic
+    domain (apco_push).  xyz, vel: 3 x N float64, updated copies are returned;
+    grad: 3 x N."""
     x = np.array(xyz, dtype=np.float64, order="C", copy=True)
     v = np.array(vel, dtype=np.float64, order="C", copy=True)
     g = np.ascontiguousarray(grad, dtype=np.float64)
     assert x.shape == v.shape == g.shape and x.shape[0] == 3
-    P = make_params(lo=lo, L=L)
+    P = make_params(lo=lo, L=L, periodic=periodic)
     _check(_load().apco_push(ct.byref(P), x.shape[1], _ptr(x), _ptr(v), _ptr(g), kick, dt),
            "push")
     return x, v

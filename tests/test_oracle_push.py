@@ -96,3 +96,33 @@ def test_invalid_arguments():
         oracle.push(x, x, x, 1.0, np.inf)
     with pytest.raises(RuntimeError):
         oracle.push(x, x, x, 1.0, 1.0, L=0.0)
+
+
+@pytest.mark.parametrize("lo,L", [(0.0, 1.0), (-0.75, 2.5)])
+def test_periodic_wrap_against_exact_residue(lo, L):
+    # on a periodic domain a free particle moves on the torus: its position is
+    # lo + ((x + dt v - lo) mod L), exactly, and its velocity never changes
+    rng = np.random.default_rng(12)
+    n = 300
+    x0 = lo + L * rng.random((3, n))
+    v0 = L * rng.uniform(-7.5, 7.5, (3, n))
+    v0[:, :30] = L * rng.uniform(-0.2, 0.2, (3, 30))
+    x, v = oracle.push(x0, v0, np.zeros_like(x0), 0.0, 1.0, (lo,) * 3, L, periodic=1)
+    np.testing.assert_array_equal(v, v0)
+    for d in range(3):
+        for i in range(n):
+            pre = x0[d, i] + v0[d, i]
+            ex = Fraction(lo) + (Fraction(pre) - Fraction(lo)) % Fraction(L)
+            assert lo <= x[d, i] <= lo + L
+            assert abs(Fraction(x[d, i]) - ex) <= Fraction(8 * np.spacing(L * (1 + abs(pre - lo) / L)))
+            if lo <= pre <= lo + L:
+                assert x[d, i] == pre
+
+
+def test_periodic_wrap_edge_values():
+    # one and two lengths across a face; leaving by lo re-enters near lo + L
+    x0 = np.array([[0.5, 0.5, 0.5, 0.25]] * 3)
+    v0 = np.array([[1.25, -0.75, 2.0, -2.5]] * 3)
+    x, v = oracle.push(x0, v0, np.zeros_like(x0), 0.0, 1.0, periodic=1)
+    np.testing.assert_array_equal(x[0], [0.75, 0.75, 0.5, 0.75])
+    np.testing.assert_array_equal(v, v0)
