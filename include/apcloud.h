@@ -103,6 +103,16 @@ typedef struct {
                         d is negative and sum_j |w_j| <= tau_dom |d|, else the node
                         searches a larger ring and finally takes an order-2 row;
                         0 = default 10 */
+  int periodic;       /* 1: Omega is periodic in x, y and z (Sec. 4.3 speaks of "a
+                        non-periodic region"; this is the other case): face neighbours
+                        wrap around, there are no boundary nodes (nb = 0, g ignored),
+                        stencil offsets are minimum images, levels 0 and 1 are always
+                        opened (max_depth >= 2), and apc_solve solves
+                        Delta phi = c (rho~ - mean rho~) with the equation of node 0
+                        replaced by phi_0 = 0, then shifts phi to mean 0 (means
+                        weighted by cell volume); the FP64 residual diagnostic of
+                        the mixed modes is not computed (-1).  0 (default): the
+                        Dirichlet box */
 } apc_params;
 
 typedef struct {
@@ -379,7 +389,8 @@ typedef struct {
 
 /* Build count clouds (xyz[c]: device pointer of cloud c's 3 x N[c] SoA particles;
    xyz and N are host arrays), then their union.  Same errors as
-   apc_build_cloud, for the first cloud that fails.  Synchronises. */
+   apc_build_cloud, for the first cloud that fails; APC_EINVAL for order 4 or a
+   periodic domain (a batch holds bounded order-2 clouds).  Synchronises. */
 int apc_build_batch(const apc_params *p, int count, const double *const *xyz, const int64_t *N,
                     hipStream_t stream, apc_batch **out);
 /* Totals and launch shape; per-cloud sizes into host arrays (each may be NULL). */
@@ -448,8 +459,9 @@ void apc_batch_destroy(apc_batch *b);
    A particle that ends outside Omega = [p->lo, p->lo + p->L]^3 is reflected
    specularly: per axis u = (x - lo) / L, f = floor(u) wall crossings,
    r = u - f, u <- r (f even) or 1 - r (f odd), x = lo + u L, and the velocity
-   component changes sign for odd f; a particle inside keeps x + dt v.  Only
-   p->lo and p->L are read.  xyz, vel: 3 x N float64, updated in place; grad:
+   component changes sign for odd f; a particle inside keeps x + dt v.  With
+   p->periodic the particle re-enters through the opposite face instead (u <- r,
+   velocity unchanged).  Only p->lo, p->L and p->periodic are read.  xyz, vel: 3 x N float64, updated in place; grad:
    3 x N (as apc_interpolate_force writes it).  Errors: APC_EINVAL (N < 0,
    L <= 0, a non-finite lo, L, kick or dt, NULL arrays with N > 0).  Does not
    synchronise. */

@@ -50,7 +50,8 @@ class Params(ct.Structure):
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
                 ("precision", ct.c_int), ("stage_cap", ct.c_int), ("criterion_pow", ct.c_int),
-                ("ring_lds", ct.c_int), ("ring_first_cap", ct.c_int), ("tau_dom", ct.c_double)]
+                ("ring_lds", ct.c_int), ("ring_first_cap", ct.c_int), ("tau_dom", ct.c_double),
+                ("periodic", ct.c_int)]
 
 
 class Stats(ct.Structure):
@@ -165,7 +166,7 @@ def _check(rc, what):
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
                 ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64,
                 stage_cap=0, criterion_pow=0, ring_lds=0, ring_first_cap=0,
-                tau_dom=0.0) -> Params:
+                tau_dom=0.0, periodic=0) -> Params:
     p = Params()
     load_library().apc_default_params(ct.byref(p), order)
     p.lo[:] = lo
@@ -184,6 +185,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     p.ring_lds = ring_lds
     p.ring_first_cap = ring_first_cap
     p.tau_dom = tau_dom
+    p.periodic = periodic
     return p
 
 

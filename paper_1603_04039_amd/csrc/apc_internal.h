@@ -82,6 +82,18 @@ __host__ __device__ inline uint32_t apc_compact3(uint64_t v) {
   v = (v ^ (v >> 32)) & 0x1fffffull;
   return (uint32_t)v;
 }
+// Node coordinates are held as crd[3 (n + nb) + 1]: x, y and z of every node, then
+// one int32 S, the domain side in integer units on a periodic domain (0 on the
+// Dirichlet box).  Offsets between nodes are minimum images in [-S/2, S/2) then.
+__host__ __device__ inline int32_t apc_doff(int32_t a, int32_t b, int32_t S) {
+  int32_t d = a - b;
+  if (S) {
+    if (d >= (S >> 1)) d -= S;
+    else if (d < -(S >> 1)) d += S;
+  }
+  return d;
+}
+
 __host__ __device__ inline uint64_t apc_morton(uint32_t x, uint32_t y, uint32_t z) {
   return (apc_spread3(x) << 2) | (apc_spread3(y) << 1) | apc_spread3(z);
 }
@@ -116,11 +128,12 @@ struct apc_solver_ws;
 // small device block used by the assembly: canonical stencil, its shell
 // constants, error flag and the count of rows refitted in FP64
 struct apc_asm_scratch {
-  int32_t crd[3 * 25];
+  int32_t crd[3 * 25 + 1]; // canonical 2-ring, then S = 0
   double tc[3];
   int err;
   unsigned fb_count; // k = 4 assembly: nodes handed from the normal equations to the QR
   unsigned long long nfp64;
+  double pmean; // periodic solve: the volume-weighted mean being removed
 };
 
 struct apc_cloud {

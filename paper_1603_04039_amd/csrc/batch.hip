@@ -523,7 +523,8 @@ int merge(apc_batch *B, std::vector<apc_cloud *> &cl, hipStream_t s) {
   APCCHK(dmalloc(&u->level, nall));
   APCCHK(dmalloc(&u->first, nall));
   APCCHK(dmalloc(&u->count, nall));
-  APCCHK(dmalloc(&u->crd, 3 * ntot));
+  APCCHK(dmalloc(&u->crd, 3 * ntot + 1)); // + the periodic side slot (0: bounded)
+  HIPCHK(hipMemsetAsync(u->crd + 3 * ntot, 0, sizeof(int32_t), s));
   APCCHK(dmalloc(&u->bowner, nball));
   APCCHK(dmalloc(&u->bface, nball));
   APCCHK(dmalloc(&u->st_off, nall + 1));

@@ -144,7 +144,8 @@ __device__ inline void cell_index(uint64_t pre, uint32_t t[3]) {
 // corner of the same-level cell across it.
 __global__ void __launch_bounds__(APC_BLOCK)
     k_balance_mark(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
-                   const uint64_t *__restrict__ mc, int64_t n, int D, int32_t *__restrict__ mark) {
+                   const uint64_t *__restrict__ mc, int64_t n, int D, int periodic,
+                   int32_t *__restrict__ mark) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
   const int l = lev[y];
@@ -155,12 +156,13 @@ __global__ void __launch_bounds__(APC_BLOCK)
   for (int f = 0; f < 6; f++) {
     const int d = f >> 1;
     uint32_t t[3] = {t0[0], t0[1], t0[2]};
+    const uint32_t side = 1u << l;
     if (f & 1) {
-      if (t[d] + 1u >= (1u << l)) continue;
-      t[d] += 1u;
+      if (t[d] + 1u >= side && !periodic) continue;
+      t[d] = (t[d] + 1u) & (side - 1u); // periodic: the face across the domain boundary
     } else {
-      if (t[d] == 0u) continue;
-      t[d] -= 1u;
+      if (t[d] == 0u && !periodic) continue;
+      t[d] = (t[d] + side - 1u) & (side - 1u);
     }
     const uint64_t pc = apc_morton(t[0] << sh, t[1] << sh, t[2] << sh);
     const int64_t z = apc_last_le(mc, n, pc);
@@ -170,9 +172,13 @@ __global__ void __launch_bounds__(APC_BLOCK)
 
 // number of faces of each leaf lying on the domain boundary
 __global__ void __launch_bounds__(APC_BLOCK)
-    k_bcount(const uint64_t *pre, const int32_t *lev, int64_t n, int32_t *bc) {
+    k_bcount(const uint64_t *pre, const int32_t *lev, int64_t n, int periodic, int32_t *bc) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
+  if (periodic) { // no boundary faces
+    bc[y] = 0;
+    return;
+  }
   uint32_t t[3];
   cell_index(pre[y], t);
   const uint32_t top = (1u << lev[y]) - 1u;
@@ -185,9 +191,10 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // (2i+1) 2^(D-l); boundary nodes sit at the centre of their owner's face.
 __global__ void __launch_bounds__(APC_BLOCK)
     k_nodes(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
-            const int32_t *__restrict__ bstart, int64_t n, int64_t ntot, int D,
+            const int32_t *__restrict__ bstart, int64_t n, int64_t ntot, int D, int periodic,
             int32_t *__restrict__ crd, int32_t *__restrict__ bowner, int32_t *__restrict__ bface) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (y == 0) crd[3 * ntot] = periodic ? (1 << (D + 1)) : 0; // the side S
   if (y >= n) return;
   const int l = lev[y];
   uint32_t t[3];
@@ -202,7 +209,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   int64_t b = n + bstart[y];
   for (int f = 0; f < 6; f++) {
     const int d = f >> 1;
-    const bool on = (f & 1) ? (t[d] == top) : (t[d] == 0u);
+    const bool on = !periodic && ((f & 1) ? (t[d] == top) : (t[d] == 0u));
     if (!on) continue;
     for (int e = 0; e < 3; e++) crd[(int64_t)e * ntot + b] = c[e];
     crd[(int64_t)d * ntot + b] = (f & 1) ? (1 << (D + 1)) : 0;
@@ -217,7 +224,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
 __global__ void __launch_bounds__(APC_BLOCK)
     k_ring1(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
             const uint64_t *__restrict__ mc, const int32_t *__restrict__ bstart, int64_t n, int D,
-            int32_t *__restrict__ r1cnt, int32_t *__restrict__ r1, int *__restrict__ err) {
+            int periodic, int32_t *__restrict__ r1cnt, int32_t *__restrict__ r1,
+            int *__restrict__ err) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
   const int l = lev[y];
@@ -229,12 +237,12 @@ __global__ void __launch_bounds__(APC_BLOCK)
   for (int f = 0; f < 6; f++) {
     const int d = f >> 1;
     const bool bnd = (f & 1) ? (t0[d] == top) : (t0[d] == 0u);
-    if (bnd) {
+    if (bnd && !periodic) {
       out[k++] = (int32_t)(n + bstart[y] + kb++);
       continue;
     }
     uint32_t t[3] = {t0[0], t0[1], t0[2]};
-    t[d] = (f & 1) ? t[d] + 1u : t[d] - 1u;
+    t[d] = ((f & 1) ? t[d] + 1u : t[d] + top) & top; // wraps across a periodic boundary
     const int sh = D - l;
     const uint64_t pc = apc_morton(t[0] << sh, t[1] << sh, t[2] << sh);
     const int64_t z = apc_last_le(mc, n, pc);
@@ -365,12 +373,14 @@ __global__ void __launch_bounds__(APC_BLOCK)
     return;
   }
   const int32_t cy0 = crd[y], cy1 = crd[ntot + y], cy2 = crd[2 * ntot + y];
+  const int32_t S = crd[3 * ntot]; // periodic side (0: none): minimum-image offsets
   // candidates = list positions 1 .. cnt-1, heap-sorted by (r2, index).  Each key
   // carries the candidate's closed-octant mask in bits 48-55 (bit o: the offset lies
   // in octant o, a zero component counting on both sides); r2 < 2^44 below them.
   for (int j = 1; j < cnt; j++) {
     const int32_t v = LST(j);
-    const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
+    const int64_t d0 = apc_doff(crd[v], cy0, S), d1 = apc_doff(crd[ntot + v], cy1, S),
+                  d2 = apc_doff(crd[2 * ntot + v], cy2, S);
     const uint32_t mx = (d0 >= 0 ? 0xF0u : 0u) | (d0 <= 0 ? 0x0Fu : 0u);
     const uint32_t my = (d1 >= 0 ? 0xCCu : 0u) | (d1 <= 0 ? 0x33u : 0u);
     const uint32_t mz = (d2 >= 0 ? 0xAAu : 0u) | (d2 <= 0 ? 0x55u : 0u);
@@ -450,7 +460,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
       vals[0] = 0;
       for (int j = 1; j < cnt && nv < 5; j++) {
         if (LST(j) >= 0) continue;
-        const int64_t o = cd[-LST(j) - 1] - c0;
+        const int64_t o = apc_doff(cd[-LST(j) - 1], (int32_t)c0, S);
         bool seen = false;
         for (int q = 0; q < nv; q++) seen = seen || vals[q] == o;
         if (!seen) vals[nv++] = o;
@@ -459,7 +469,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
       int add = -1;
       for (int j = 1; j < cnt && add < 0; j++) {
         if (LST(j) < 0) continue;
-        const int64_t o = cd[LST(j)] - c0;
+        const int64_t o = apc_doff(cd[LST(j)], (int32_t)c0, S);
         bool seen = false;
         for (int q = 0; q < nv; q++) seen = seen || vals[q] == o;
         if (!seen) add = j;
@@ -582,8 +592,10 @@ __global__ void __launch_bounds__(APC_BLOCK)
   uint32_t msk = 0;
   if (lane < nc) {
     const int32_t cy0 = crd[y], cy1 = crd[ntot + y], cy2 = crd[2 * ntot + y];
+    const int32_t S = crd[3 * ntot]; // periodic side (0: none)
     v = Ls[lane + 1]; // slot 0 holds y
-    const int64_t d0 = crd[v] - cy0, d1 = crd[ntot + v] - cy1, d2 = crd[2 * ntot + v] - cy2;
+    const int64_t d0 = apc_doff(crd[v], cy0, S), d1 = apc_doff(crd[ntot + v], cy1, S),
+                  d2 = apc_doff(crd[2 * ntot + v], cy2, S);
     r2 = d0 * d0 + d1 * d1 + d2 * d2;
     const uint32_t mx = (d0 >= 0 ? 0xF0u : 0u) | (d0 <= 0 ? 0x0Fu : 0u);
     const uint32_t my = (d1 >= 0 ? 0xCCu : 0u) | (d1 <= 0 ? 0x33u : 0u);
@@ -715,8 +727,9 @@ __global__ void __launch_bounds__(APC_BLOCK)
     uint32_t msk = 0;
     if (tid < nc) {
       v = Ls[tid + 1]; // slot 0 holds y
-      const int64_t d0 = crd[v] - crd[y], d1 = crd[ntot + v] - crd[ntot + y],
-                    d2 = crd[2 * ntot + v] - crd[2 * ntot + y];
+      const int32_t S = crd[3 * ntot]; // periodic side (0: none)
+      const int64_t d0 = apc_doff(crd[v], crd[y], S), d1 = apc_doff(crd[ntot + v], crd[ntot + y], S),
+                    d2 = apc_doff(crd[2 * ntot + v], crd[2 * ntot + y], S);
       r2 = d0 * d0 + d1 * d1 + d2 * d2;
       const uint32_t mx = (d0 >= 0 ? 0xF0u : 0u) | (d0 <= 0 ? 0x0Fu : 0u);
       const uint32_t my = (d1 >= 0 ? 0xCCu : 0u) | (d1 <= 0 ? 0x33u : 0u);
@@ -1006,7 +1019,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
                        cl.n, D, mc);
     HIPCHK(hipMemsetAsync(cl.flag, 0, (size_t)cl.n * sizeof(int32_t), s));
     hipLaunchKernelGGL(k_balance_mark, dim3(grid_for(cl.n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev,
-                       mc, cl.n, D, cl.flag);
+                       mc, cl.n, D, P.periodic, cl.flag);
     HIPCHK(hipGetLastError());
     int64_t nm = 0;
     APCCHK(apc_sum_i32(cl.flag, cl.n, &nm, s));
@@ -1032,7 +1045,8 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   int32_t *bcnt = nullptr, *bstart = nullptr;
   APCCHK(dalloc(&bcnt, n, s));
   APCCHK(dalloc(&bstart, n, s));
-  hipLaunchKernelGGL(k_bcount, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, n, bcnt);
+  hipLaunchKernelGGL(k_bcount, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, n,
+                     P.periodic, bcnt);
   APCCHK(apc_scan_i32(bcnt, bstart, n, s));
   int32_t last[2];
   HIPCHK(hipMemcpyAsync(&last[0], bstart + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1041,11 +1055,11 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   const int64_t nb = (int64_t)last[0] + last[1];
   c->nb = nb;
   const int64_t ntot = n + nb;
-  HIPCHK(apc_dev_alloc((void **)&c->crd, (size_t)3 * ntot * sizeof(int32_t)));
+  HIPCHK(apc_dev_alloc((void **)&c->crd, (size_t)(3 * ntot + 1) * sizeof(int32_t)));
   HIPCHK(apc_dev_alloc((void **)&c->bowner, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
   HIPCHK(apc_dev_alloc((void **)&c->bface, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
   hipLaunchKernelGGL(k_nodes, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, bstart, n,
-                     ntot, D, c->crd, c->bowner, c->bface);
+                     ntot, D, P.periodic, c->crd, c->bowner, c->bface);
   HIPCHK(hipGetLastError());
 
   // 1-ring adjacency
@@ -1054,7 +1068,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   APCCHK(dalloc(&r1, n * 24, s));
   HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_ring1, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, mc, bstart,
-                     n, D, r1cnt, r1, err);
+                     n, D, P.periodic, r1cnt, r1, err);
   HIPCHK(hipGetLastError());
   APCCHK(read_err(err, s, &herr));
   if (herr) { // an unbalanced face: cannot happen after the balance phase
@@ -1319,7 +1333,8 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
       p->criterion_pow < 0 || p->criterion_pow > 16 || p->ring_lds < -1 || p->ring_lds > 1 ||
       p->ring_first_cap < 0 || p->ring_first_cap > APC_RING_CAP || !(p->tau_dom >= 0.0) ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
-        p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c))
+        p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c) ||
+      p->periodic < 0 || p->periodic > 1 || (p->periodic && p->max_depth < 2))
     return APC_EINVAL;
   apc_cloud *c = new apc_cloud();
   c->P = *p;
@@ -1336,6 +1351,9 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
     for (int e = 0; e < pw; e++) v *= t;
     c->T[l] = v;
   }
+  // periodic: levels 0 and 1 always open, so that every leaf sees distinct cells
+  // across its faces
+  if (p->periodic) c->T[0] = c->T[1] = 0.0;
   int rc = build_body(c, xyz, s);
   if (rc != APC_OK) {
     (void)hipStreamSynchronize(s);

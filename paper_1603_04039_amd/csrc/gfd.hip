@@ -36,6 +36,7 @@ __device__ __forceinline__ void mono9(T x, T y, T z, T v[P9]) {
 
 struct NodeGeom {
   int32_t c0, c1, c2; // own integer coordinates
+  int32_t S;          // periodic side (0: none): offsets are minimum images
   int32_t h;          // max |delta| (integer)
   double r2max;       // r_max^2 (integer units)
 };
@@ -47,6 +48,7 @@ __device__ inline NodeGeom node_geom(const int32_t *nb, int m, const int32_t *__
   g.c0 = crd[y];
   g.c1 = crd[ntot + y];
   g.c2 = crd[2 * ntot + y];
+  g.S = crd[3 * ntot];
   int32_t h = 0;
   int64_t r2max = 0;
   // loops over the stencil are unrolled by 4 so that four neighbours' coordinate
@@ -54,7 +56,8 @@ __device__ inline NodeGeom node_geom(const int32_t *nb, int m, const int32_t *__
 #pragma unroll 4
   for (int j = 0; j < m; j++) {
     const int32_t v = nb[j];
-    const int32_t d0 = crd[v] - g.c0, d1 = crd[ntot + v] - g.c1, d2 = crd[2 * ntot + v] - g.c2;
+    const int32_t d0 = apc_doff(crd[v], g.c0, g.S), d1 = apc_doff(crd[ntot + v], g.c1, g.S),
+                  d2 = apc_doff(crd[2 * ntot + v], g.c2, g.S);
     h = max(h, max(abs(d0), max(abs(d1), abs(d2))));
     const int64_t r2 = (int64_t)d0 * d0 + (int64_t)d1 * d1 + (int64_t)d2 * d2;
     r2max = r2 > r2max ? r2 : r2max;
@@ -68,7 +71,8 @@ __device__ inline NodeGeom node_geom(const int32_t *nb, int m, const int32_t *__
 template <typename T>
 __device__ __forceinline__ T row_w2(const NodeGeom &g, const int32_t *__restrict__ crd,
                                     int64_t ntot, int32_t v, T vv[P9]) {
-  const int32_t d0 = crd[v] - g.c0, d1 = crd[ntot + v] - g.c1, d2 = crd[2 * ntot + v] - g.c2;
+  const int32_t d0 = apc_doff(crd[v], g.c0, g.S), d1 = apc_doff(crd[ntot + v], g.c1, g.S),
+                d2 = apc_doff(crd[2 * ntot + v], g.c2, g.S);
   const T hd = (T)g.h;
   mono9<T>((T)d0 / hd, (T)d1 / hd, (T)d2 / hd, vv);
   const T r2 = (T)((int64_t)d0 * d0 + (int64_t)d1 * d1 + (int64_t)d2 * d2);
@@ -219,10 +223,11 @@ __global__ void __launch_bounds__(APC_BLOCK)
   bool tmpl = (m == 24);
   if (tmpl) {
     const int32_t sp = 1 << (D - l + 1);
-    const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y];
+    const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y], S = crd[3 * ntot];
     for (int j = 0; j < 24 && tmpl; j++) {
       const int32_t v = st_idx[a + j];
-      const int32_t d[3] = {abs(crd[v] - c0), abs(crd[ntot + v] - c1), abs(crd[2 * ntot + v] - c2)};
+      const int32_t d[3] = {abs(apc_doff(crd[v], c0, S)), abs(apc_doff(crd[ntot + v], c1, S)),
+                            abs(apc_doff(crd[2 * ntot + v], c2, S))};
       int32_t l1 = 0;
       for (int k = 0; k < 3; k++) {
         tmpl = tmpl && (d[k] == 0 || d[k] == sp || d[k] == 2 * sp);

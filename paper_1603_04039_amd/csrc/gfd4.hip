@@ -149,9 +149,10 @@ __device__ __forceinline__ Geo stencil_rows(Wave4 &S, int lane, const int32_t *n
   int32_t d0 = 0, d1 = 0, d2 = 0;
   if (lane < m) {
     const int32_t v = nb[lane];
-    d0 = crd[v] - crd[y];
-    d1 = crd[ntot + v] - crd[ntot + y];
-    d2 = crd[2 * ntot + v] - crd[2 * ntot + y];
+    const int32_t S = crd[3 * ntot]; // periodic side (0: none)
+    d0 = apc_doff(crd[v], crd[y], S);
+    d1 = apc_doff(crd[ntot + v], crd[ntot + y], S);
+    d2 = apc_doff(crd[2 * ntot + v], crd[2 * ntot + y], S);
   }
   Geo g;
   g.h = wmax_i(max(abs(d0), max(abs(d1), abs(d2))));
@@ -365,7 +366,8 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
     int32_t d[3] = {0, 0, 0};
     if (lane < 56) {
       const int32_t v = cand[t * APC_MAXM + lane];
-      for (int k = 0; k < 3; k++) d[k] = abs(crd[k * ntot + v] - crd[k * ntot + y]);
+      const int32_t S = crd[3 * ntot];
+      for (int k = 0; k < 3; k++) d[k] = abs(apc_doff(crd[k * ntot + v], crd[k * ntot + y], S));
     }
     const int32_t h = wmax_i(max(d[0], max(d[1], d[2])));
     const int32_t sp = h >> 1;
@@ -600,9 +602,10 @@ __device__ __forceinline__ Geo stencil_rows_n(WaveN<MR> &S, int lane, const int3
   int32_t d0 = 0, d1 = 0, d2 = 0;
   if (lane < m) {
     const int32_t v = nb[lane];
-    d0 = crd[v] - crd[y];
-    d1 = crd[ntot + v] - crd[ntot + y];
-    d2 = crd[2 * ntot + v] - crd[2 * ntot + y];
+    const int32_t S = crd[3 * ntot]; // periodic side (0: none)
+    d0 = apc_doff(crd[v], crd[y], S);
+    d1 = apc_doff(crd[ntot + v], crd[ntot + y], S);
+    d2 = apc_doff(crd[2 * ntot + v], crd[2 * ntot + y], S);
   }
   Geo g;
   g.h = wmax_i(max(abs(d0), max(abs(d1), abs(d2))));
@@ -920,10 +923,11 @@ __global__ void __launch_bounds__(APC_BLOCK)
   bool ok = st_off[y + 1] - a == 56 && rorder[y] == 4;
   if (ok) {
     const int32_t sp = 1 << (D - l + 1);
-    const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y];
+    const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y], S = crd[3 * ntot];
     for (int j = 0; j < 56 && ok; j++) {
       const int32_t v = st_idx[a + j];
-      const int32_t d[3] = {abs(crd[v] - c0), abs(crd[ntot + v] - c1), abs(crd[2 * ntot + v] - c2)};
+      const int32_t d[3] = {abs(apc_doff(crd[v], c0, S)), abs(apc_doff(crd[ntot + v], c1, S)),
+                            abs(apc_doff(crd[2 * ntot + v], c2, S))};
       int q2 = 0;
       for (int k = 0; k < 3; k++) {
         ok = ok && (d[k] == 0 || d[k] == sp || d[k] == 2 * sp);
@@ -1001,7 +1005,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // the canonical uniform 56-node stencil: node 0 at (4, 4, 4), nodes 1 .. 56 at the
 // offsets of spacing 1 sorted by r^2, one cell of size 1 (L = 1, level 0)
 struct Canon4 {
-  int32_t crd[3 * 57];
+  int32_t crd[3 * 57 + 1]; // then S = 0
   int32_t st_off[2], st_idx[56], level[1], fb_list[1];
   int8_t rorder[1], dorder[1];
   unsigned fb_cnt;
@@ -1103,14 +1107,15 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int sh = Dmax - l + 1; // spacing 2^sh integer units
   const int32_t a0 = st_off[y];
   const double f0 = f[y];
-  const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y];
+  const int32_t c0 = crd[y], c1 = crd[ntot + y], c2 = crd[2 * ntot + y], S = crd[3 * ntot];
   double acc[P4];
 #pragma unroll
   for (int a = 0; a < P4; a++) acc[a] = 0.0;
   for (int j = 0; j < 56; j++) {
     const int32_t v = st_idx[a0 + j];
-    const int o = 25 * (((crd[v] - c0) >> sh) + 2) + 5 * (((crd[ntot + v] - c1) >> sh) + 2) +
-                  (((crd[2 * ntot + v] - c2) >> sh) + 2);
+    const int o = 25 * ((apc_doff(crd[v], c0, S) >> sh) + 2) +
+                  5 * ((apc_doff(crd[ntot + v], c1, S) >> sh) + 2) +
+                  ((apc_doff(crd[2 * ntot + v], c2, S) >> sh) + 2);
     const double df = f[v] - f0;
     const double *t = Ts + o * P4;
 #pragma unroll

@@ -21,10 +21,12 @@ namespace {
 // outside [lo, lo + L] after the drift is folded back: u = (x - lo) / L, f =
 // floor(u) wall crossings, r = u - f; u becomes r (f even) or 1 - r (f odd) and
 // the velocity component changes sign for odd f.  Particles inside keep x + dt v.
+// On a periodic domain the particle re-enters through the opposite face: u = r,
+// velocity unchanged.
 __global__ void __launch_bounds__(APC_BLOCK)
     k_push(int64_t N, double *__restrict__ xyz, double *__restrict__ vel,
            const double *__restrict__ grad, double kick, double dt, double lo0, double lo1,
-           double lo2, double L) {
+           double lo2, double L, int periodic) {
 #pragma clang fp contract(off)
   const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (i >= N) return;
@@ -39,7 +41,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
     const double f = floor(u);
     const double r = u - f;
     const double half = f * 0.5;
-    const bool odd = floor(half) != half;
+    const bool odd = !periodic && floor(half) != half;
     u = odd ? 1.0 - r : r;
     if (odd) v = -v;
     x = lo + u * L;
@@ -61,7 +63,7 @@ int apc_push_impl(const apc_params *p, int64_t N, double *xyz, double *vel, cons
   if (!xyz || !vel || !grad) return APC_EINVAL;
   if (N > (int64_t)0x7fffffff * APC_BLOCK) return APC_EINVAL;
   hipLaunchKernelGGL(k_push, dim3(grid_for(N), 3), dim3(APC_BLOCK), 0, s, N, xyz, vel, grad, kick,
-                     dt, p->lo[0], p->lo[1], p->lo[2], p->L);
+                     dt, p->lo[0], p->lo[1], p->lo[2], p->L, p->periodic ? 1 : 0);
   HIPCHK(hipGetLastError());
   return APC_OK;
 }

@@ -106,13 +106,13 @@ __global__ void __launch_bounds__(SL)
   const int ly = ((lane >> 1) & 1) | (((lane >> 4) & 1) << 1);
   const int lz = (lane & 1) | (((lane >> 3) & 1) << 1);
   const int sh = D - level[row] + 1;
-  const int32_t c0 = crd[row], c1 = crd[ntot + row], c2 = crd[2 * ntot + row];
+  const int32_t c0 = crd[row], c1 = crd[ntot + row], c2 = crd[2 * ntot + row], S = crd[3 * ntot];
   const int32_t a = st_off[row];
   bx[(lx + 2) + 8 * (ly + 2) + APC_BOX_SZ * (lz + 2)] = row;
   for (int j = 0; j < 56; j++) {
     const int32_t v = st_idx[a + j];
-    const int qx = (crd[v] - c0) >> sh, qy = (crd[ntot + v] - c1) >> sh,
-              qz = (crd[2 * ntot + v] - c2) >> sh;
+    const int qx = apc_doff(crd[v], c0, S) >> sh, qy = apc_doff(crd[ntot + v], c1, S) >> sh,
+              qz = apc_doff(crd[2 * ntot + v], c2, S) >> sh;
     bx[(lx + 2 + qx) + 8 * (ly + 2 + qy) + APC_BOX_SZ * (lz + 2 + qz)] = v;
   }
 }

@@ -15,6 +15,8 @@
 // few iterations.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
+
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -672,7 +674,8 @@ static int run_once(apc_cloud *c, const Op &op, const double *invd, const double
 // When the learned solve does not reach tol, the solve is repeated with Jacobi.
 static int run_solve(apc_cloud *c, bool density, const double *b, double *x, double tol, int maxit,
                      int prec, apc_stats *st, hipStream_t s) {
-  const Op op = make_op(c, density);
+  Op op = make_op(c, density);
+  op.pin = (!density && c->P.periodic) ? 1 : 0;
   c->ws->spmv_ms = 0.0;
   c->ws->spmv_launches = 0;
   const double *invd = density ? nullptr : c->inv_diag; // the density solve is plain
@@ -734,6 +737,82 @@ int apc_density_solve_impl(apc_cloud *c, const double *rho_M, double *rho_t, dou
   return rc;
 }
 
+// ---------------------------------------------------------------- periodic domains
+// per-block partial sums of v_j h_j^3 and h_j^3 (cell volumes), PV blocks
+constexpr int PV = 1024;
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_vol_part(int64_t n, const int32_t *__restrict__ level, double L, const double *__restrict__ v,
+               double *__restrict__ part) {
+  double q = 0.0, vol = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * APC_BLOCK) {
+    const double h = ldexp(L, -level[i]);
+    const double h3 = h * h * h;
+    q += v[i] * h3;
+    vol += h3;
+  }
+  __shared__ double sq[APC_BLOCK / 64], sv[APC_BLOCK / 64];
+  q = wave_sum(q);
+  vol = wave_sum(vol);
+  if ((threadIdx.x & 63) == 0) {
+    sq[threadIdx.x >> 6] = q;
+    sv[threadIdx.x >> 6] = vol;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    double a = 0.0, b = 0.0;
+    for (int k = 0; k < APC_BLOCK / 64; k++) {
+      a += sq[k];
+      b += sv[k];
+    }
+    part[blockIdx.x] = a;
+    part[PV + blockIdx.x] = b;
+  }
+}
+// the volume-weighted mean from the partials (one block, fixed order)
+__global__ void __launch_bounds__(APC_BLOCK) k_vol_mean(const double *__restrict__ part, int nblk,
+                                                        double *__restrict__ mean) {
+  __shared__ double sq[APC_BLOCK], sv[APC_BLOCK];
+  double a = 0.0, b = 0.0;
+  for (int k = threadIdx.x; k < nblk; k += APC_BLOCK) {
+    a += part[k];
+    b += part[PV + k];
+  }
+  sq[threadIdx.x] = a;
+  sv[threadIdx.x] = b;
+  __syncthreads();
+  for (int w = APC_BLOCK / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      sq[threadIdx.x] += sq[threadIdx.x + w];
+      sv[threadIdx.x] += sv[threadIdx.x + w];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *mean = sv[0] > 0.0 ? sq[0] / sv[0] : 0.0;
+}
+// b = c (rho~ - mean), with the equation of node 0 replaced by phi_0 = 0
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_rhs_periodic(int64_t n, const double *__restrict__ rho, double c,
+                   const double *__restrict__ mean, double *__restrict__ b) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) b[i] = i == 0 ? 0.0 : c * (rho[i] - *mean);
+}
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_sub_mean(int64_t n, const double *__restrict__ mean, double *__restrict__ x) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) x[i] -= *mean;
+}
+
+static int vol_mean(apc_cloud *c, const double *v, hipStream_t s) {
+  const unsigned g = std::min(grid_for(c->n), (unsigned)PV);
+  hipLaunchKernelGGL(k_vol_part, dim3(g), dim3(APC_BLOCK), 0, s, c->n, c->level, c->P.L, v,
+                     c->ws->part);
+  hipLaunchKernelGGL(k_vol_mean, dim3(1), dim3(APC_BLOCK), 0, s, (const double *)c->ws->part,
+                     (int)g, &c->scratch->pmean);
+  HIPCHK(hipGetLastError());
+  return APC_OK;
+}
+
 int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *phi, double tol,
                    int maxit, int precond, apc_stats *st, hipStream_t s) {
   if (!c->assembled) return APC_EINVAL;
@@ -745,19 +824,26 @@ int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *p
   apc_solver_ws *w = c->ws;
   const Op op = make_op(c, false);
   HIPCHK(hipEventRecord(w->e0, s));
-  if (c->P.precision != APC_FP64)
+  if (c->P.periodic) {
+    // Delta phi = c (rho~ - mean rho~); phi_0 = 0 in place of node 0's equation
+    APCCHK(vol_mean(c, rho_t, s));
+    hipLaunchKernelGGL(k_rhs_periodic, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, rho_t,
+                       c->P.poisson_c, (const double *)&c->scratch->pmean, w->b);
+  } else if (c->P.precision != APC_FP64) {
     hipLaunchKernelGGL(k_rhs<V32A64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_t,
                        c->P.poisson_c, g, w->b);
-  else
+  } else {
     hipLaunchKernelGGL(k_rhs<V64>, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, op, c->n, rho_t,
                        c->P.poisson_c, g, w->b);
+  }
   HIPCHK(hipGetLastError());
   int rc = run_solve(c, false, w->b, w->x, tol, maxit, precond, st, s);
   if (rc < 0) return rc;
   double fp64ref = -1.0;
   if (c->P.precision == APC_FP64) {
     fp64ref = w->sc_host->rtrue;
-  } else if (c->diag_flags & APC_DIAG_FP64_RESIDUAL) {
+  } else if ((c->diag_flags & APC_DIAG_FP64_RESIDUAL) && !c->P.periodic) {
+    // (not for periodic domains: the FP64 rows below do not hold the pinned row)
     // ||b - A64 x|| / ||b|| with the FP64 fit of the same stencils (the mixed
     // modes iterate on FP32 weights); w->t is free after the solve
     const unsigned gr = vec_grid(c->n);
@@ -784,6 +870,11 @@ int apc_solve_impl(apc_cloud *c, const double *rho_t, const double *g, double *p
     }
   }
   if (st) st->rel_resid_fp64ref = fp64ref;
+  if (c->P.periodic) { // phi of volume-weighted mean 0
+    APCCHK(vol_mean(c, w->x, s));
+    hipLaunchKernelGGL(k_sub_mean, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n,
+                       (const double *)&c->scratch->pmean, w->x);
+  }
   hipLaunchKernelGGL(k_write_out, dim3(grid_for(c->n + c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
                      w->x, g, phi);
   HIPCHK(hipGetLastError());

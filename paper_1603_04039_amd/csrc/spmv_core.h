@@ -23,6 +23,7 @@ struct Op {
   double t4[5];     // shell weights of the uniform 56-node row (Laplacian at h_c = 1,
                     // or the density row)
   int t4_scaled;    // 1: Laplacian (t4 scaled like tc), 0: density row (scale-free)
+  int pin;          // periodic Poisson solve: row 0 is the identity (phi_0 = 0 is imposed)
   double invL2;     // 1 / L^2: a level-l row scales tc by 4^l / L^2
   int64_t n;
   // sliced-ELL copy (the SpMV reads only this); column indices from the compact
@@ -350,13 +351,20 @@ __device__ __forceinline__ double sell_apply(const Op &op, const double *__restr
                                              int32_t &row) {
   const int s = __builtin_amdgcn_readfirstlane(s_in);
   const int tk = op.sl_tmpl[s];
-  if ((tk & 3) == 3)
-    return (op.sl_un && op.ucap >= APC_BOX_N) ? box_apply<MODE, true>(op, x, s, tk, row)
-                                        : box_apply<MODE, false>(op, x, s, tk, row);
-  const int u = op.sl_un ? op.sl_un[s] : 0;
-  if (u > 0) return sell_apply_t<MODE, false, true>(op, x, s, u, row);
-  return op.sl_top4 ? sell_apply_t<MODE, true, false>(op, x, s, 0, row)
-                    : sell_apply_t<MODE, false, false>(op, x, s, 0, row);
+  double v;
+  if ((tk & 3) == 3) {
+    v = (op.sl_un && op.ucap >= APC_BOX_N) ? box_apply<MODE, true>(op, x, s, tk, row)
+                                          : box_apply<MODE, false>(op, x, s, tk, row);
+  } else {
+    const int u = op.sl_un ? op.sl_un[s] : 0;
+    if (u > 0)
+      v = sell_apply_t<MODE, false, true>(op, x, s, u, row);
+    else
+      v = op.sl_top4 ? sell_apply_t<MODE, true, false>(op, x, s, 0, row)
+                     : sell_apply_t<MODE, false, false>(op, x, s, 0, row);
+  }
+  if (op.pin && row == 0) v = x[0];
+  return v;
 }
 
 static inline Op make_op(const apc_cloud *c, bool density) {
@@ -372,6 +380,7 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   for (int k = 0; k < 3; k++) op.tc[k] = c->tmpl[k];
   for (int k = 0; k < 5; k++) op.t4[k] = b4 ? c->tmpl4[5 + k] : c->tmpl4[k];
   op.t4_scaled = b4 ? 0 : 1;
+  op.pin = 0; // set by the periodic Poisson solve
   op.invL2 = 1.0 / (c->P.L * c->P.L);
   op.n = c->n;
   op.sl_rows = c->sl_rows;
