@@ -513,7 +513,8 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
       !(P->L > 0.0) || !(P->c > 0.0) || P->ring_min < 1 || P->ring_max < P->ring_min ||
       P->m_cap > MAXM || P->m_cap < p + 1 || N < 1 || P->criterion_pow < 0 ||
       P->criterion_pow > 16 || !(P->tau_dom >= 0.0) || P->periodic < 0 || P->periodic > 1 ||
-      (P->periodic && P->max_depth < 2))
+      (P->periodic && P->max_depth < 2) || P->kernel < APCO_KERNEL_NGP ||
+      P->kernel > APCO_KERNEL_TSC)
     return APCO_EINVAL;
   apco_cloud *C = calloc(1, sizeof(apco_cloud));
   if (!C) return APCO_ENOMEM;
@@ -937,6 +938,91 @@ int apco_assemble(const apco_cloud *C, double *w, double *diag) {
   return 0;
 }
 
+/* Charge-assignment kernels Phi(u) = phi(u_x) phi(u_y) phi(u_z) of eq.
+   density_apcloud, u = (x - y) / h: each 1-D phi is a piecewise polynomial
+   c0 + c1 u + c2 u^2 on up to three pieces [a, b].  NGP: the characteristic
+   function of [-1/2, 1/2] (the node's own cell).  CIC: the tent 1 - |u| on
+   [-1, 1].  TSC: the quadratic B-spline, 3/4 - u^2 on [-1/2, 1/2] and
+   (3/2 - |u|)^2 / 2 on 1/2 <= |u| <= 3/2.  Each integrates to 1. */
+typedef struct {
+  int np;
+  double a[3], b[3], c[3][3];
+} kpieces;
+
+static kpieces kernel_pieces(int kernel) {
+  kpieces K;
+  memset(&K, 0, sizeof(K));
+  if (kernel == APCO_KERNEL_NGP) {
+    K.np = 1;
+    K.a[0] = -0.5; K.b[0] = 0.5; K.c[0][0] = 1.0;
+  } else if (kernel == APCO_KERNEL_CIC) {
+    K.np = 2;
+    K.a[0] = -1.0; K.b[0] = 0.0; K.c[0][0] = 1.0; K.c[0][1] = 1.0;
+    K.a[1] = 0.0; K.b[1] = 1.0; K.c[1][0] = 1.0; K.c[1][1] = -1.0;
+  } else {
+    K.np = 3;
+    /* (3/2 + u)^2 / 2 = 9/8 + 3/2 u + 1/2 u^2 */
+    K.a[0] = -1.5; K.b[0] = -0.5; K.c[0][0] = 1.125; K.c[0][1] = 1.5; K.c[0][2] = 0.5;
+    K.a[1] = -0.5; K.b[1] = 0.5; K.c[1][0] = 0.75; K.c[1][2] = -1.0;
+    K.a[2] = 0.5; K.b[2] = 1.5; K.c[2][0] = 1.125; K.c[2][1] = -1.5; K.c[2][2] = 0.5;
+  }
+  return K;
+}
+
+static double kernel_phi(const kpieces *K, double u) {
+  for (int q = 0; q < K->np; q++)
+    if (u >= K->a[q] && u <= K->b[q]) return K->c[q][0] + u * (K->c[q][1] + u * K->c[q][2]);
+  return 0.0;
+}
+
+static double kernel_halfsupport(int kernel) {
+  return kernel == APCO_KERNEL_NGP ? 0.5 : (kernel == APCO_KERNEL_CIC ? 1.0 : 1.5);
+}
+
+double apco_kernel_moment(int kernel, int k, double tlo, double thi) {
+  kpieces K = kernel_pieces(kernel);
+  const double hs = kernel_halfsupport(kernel);
+  /* a kernel symmetric about 0 has vanishing odd moments over its whole support */
+  if ((k & 1) && tlo <= -hs && thi >= hs) return 0.0;
+  double m = 0.0;
+  for (int q = 0; q < K.np; q++) {
+    const double lo = tlo > K.a[q] ? tlo : K.a[q], hi = thi < K.b[q] ? thi : K.b[q];
+    if (!(hi > lo)) continue;
+    for (int e = 0; e < 3; e++) {
+      if (K.c[q][e] == 0.0) continue;
+      const int r = k + e + 1;
+      m += K.c[q][e] * (ipow(hi, r) - ipow(lo, r)) / (double)r;
+    }
+  }
+  return m;
+}
+
+/* Truncation of node y's kernel by the walls, per axis: the kernel's argument
+   u = (x - y) / h runs over [tlo, thi] inside Omega (unbounded on a periodic
+   domain). */
+static void node_trunc(const apco_cloud *C, int64_t y, double *tlo, double *thi) {
+  const int l = C->cells[C->node_cell[y]].level;
+  const double hs = ldexp(1.0, C->P.max_depth + 1 - l); /* cell edge, integer units */
+  const double S = ldexp(1.0, C->P.max_depth + 1);
+  for (int d = 0; d < 3; d++) {
+    if (C->P.periodic) {
+      tlo[d] = -INFINITY;
+      thi[d] = INFINITY;
+    } else {
+      tlo[d] = -(double)C->crd[3 * y + d] / hs;
+      thi[d] = (S - (double)C->crd[3 * y + d]) / hs;
+    }
+  }
+}
+
+/* a_0(y): the kernel's mass inside Omega */
+static double node_a0(const apco_cloud *C, int64_t y) {
+  double tlo[3], thi[3], a0 = 1.0;
+  node_trunc(C, y, tlo, thi);
+  for (int d = 0; d < 3; d++) a0 *= apco_kernel_moment(C->P.kernel, 0, tlo[d], thi[d]);
+  return a0;
+}
+
 /* Density row (eq. density_linear_system): b = a^T V^+ C, with the kernel moments
    a_alpha = (1/h_c^3) int_cell (x - y)^alpha dx / alpha! of the NGP kernel (the
    characteristic function of the node's own cell, edge h_c).  Reading: the
@@ -945,18 +1031,29 @@ int apco_assemble(const apco_cloud *C, double *w, double *diag) {
    mu(e) = (h_c/2)^e / (e + 1).  The row is b_j = sum_alpha a_alpha X_alpha,j / h^|alpha|
    over the unknowns of the fit of order ko (moments of order <= ko); the
    diagonal is 1 - sum_j b_j (the row reproduces constants). */
-static void density_row(const double *X, int m, int ko, double hc, double hp, double *b,
-                        double *bdiag) {
+static void density_row(const double *X, int m, int ko, double hc, double hp, int kernel,
+                        const double *tlo, const double *thi, double *b, double *bdiag) {
   int32_t al[3 * MAXP];
   int pk = apco_num_unknowns(ko);
   apco_monomials(ko, al);
   double coef[MAXP];
+  double a0 = 1.0;
+  if (kernel != APCO_KERNEL_NGP)
+    for (int d = 0; d < 3; d++) a0 *= apco_kernel_moment(kernel, 0, tlo[d], thi[d]);
   for (int i = 0; i < pk; i++) {
     const int32_t *a = &al[3 * i];
     coef[i] = 0.0;
-    if ((a[0] | a[1] | a[2]) & 1) continue;
     double mom = 1.0;
-    for (int d = 0; d < 3; d++) mom *= ipow(hc / 2.0, a[d]) / (double)(a[d] + 1) / factorial(a[d]);
+    if (kernel == APCO_KERNEL_NGP) {
+      if ((a[0] | a[1] | a[2]) & 1) continue;
+      for (int d = 0; d < 3; d++) mom *= ipow(hc / 2.0, a[d]) / (double)(a[d] + 1) / factorial(a[d]);
+    } else {
+      /* a_alpha / a_0 = prod_d h^a_d mu_a_d / a_d! / a_0, mu over the truncated
+         support (odd and mixed moments appear beside the walls) */
+      for (int d = 0; d < 3; d++)
+        mom *= ipow(hc, a[d]) * apco_kernel_moment(kernel, a[d], tlo[d], thi[d]) / factorial(a[d]);
+      mom /= a0;
+    }
     coef[i] = mom / ipow(hp, a[0] + a[1] + a[2]);
   }
   double s = 0.0;
@@ -997,8 +1094,9 @@ static int density_rows_ord(const apco_cloud *C, double *bw, double *bdiag, int8
     if (rc) return rc;
     double hc = C->P.L / ldexp(1.0, C->cells[C->node_cell[y]].level);
     int ko = C->node_order[y];
-    double bd;
-    density_row(X, m, ko, hc, hp, b, &bd);
+    double bd, tlo[3], thi[3];
+    node_trunc(C, y, tlo, thi);
+    density_row(X, m, ko, hc, hp, C->P.kernel, tlo, thi, b, &bd);
     if (!density_row_ok(b, m, bd) && ko == 4) {
       /* the order-2 fit of the same stencil */
       int32_t a = C->st_off[y];
@@ -1012,7 +1110,7 @@ static int density_rows_ord(const apco_cloud *C, double *bw, double *bdiag, int8
       rc = wls_core(2, m, dx, dy, dz, X, &h2, &ratio2);
       if (rc) return rc;
       ko = 2;
-      density_row(X, m, 2, hc, hp, b, &bd);
+      density_row(X, m, 2, hc, hp, C->P.kernel, tlo, thi, b, &bd);
     }
     if (!density_row_ok(b, m, bd)) {
       ko = 0;
@@ -1064,6 +1162,42 @@ int apco_deposit(const apco_cloud *C, const double *q, double *rho_M) {
   }
   /* boundary nodes carry their owner's value (reading: boundary density is not
      solved for; it enters the rhs) */
+  for (int64_t b = 0; b < C->nb; b++) rho_M[C->n + b] = rho_M[C->bowner[b]];
+  return 0;
+}
+
+/* eq. density_apcloud's right-hand side with a CIC or TSC kernel: every particle
+   against every node (the kernel vanishes outside its support), in sorted
+   particle order.  Reading: the moments a(y) integrate over Omega, so beside a
+   wall the kernel's mass a_0(y) inside Omega is below 1; each row of the density
+   system is divided by a_0 (so that it reproduces constants with unit weight) and
+   so is rho_M here.  Offsets are minimum images on a periodic domain. */
+int apco_deposit_xyz(const apco_cloud *C, const double *xyz, const double *q, double *rho_M) {
+  if (C->P.kernel == APCO_KERNEL_NGP) return apco_deposit(C, q, rho_M);
+  if (!xyz) return APCO_EINVAL;
+  const int64_t N = C->N;
+  const double q0 = 1.0 / (double)N, L = C->P.L;
+  const kpieces K = kernel_pieces(C->P.kernel);
+  for (int64_t j = 0; j < C->n; j++) {
+    const double h = L / ldexp(1.0, C->cells[C->node_cell[j]].level);
+    double yc[3];
+    for (int d = 0; d < 3; d++) yc[d] = C->P.lo[d] + C->unit * (double)C->crd[3 * j + d];
+    double sum = 0.0;
+    for (int64_t s = 0; s < N; s++) {
+      const int64_t i = C->perm[s];
+      double w = 1.0;
+      for (int d = 0; d < 3 && w != 0.0; d++) {
+        double dx = xyz[d * N + i] - yc[d];
+        if (C->P.periodic) {
+          if (dx >= 0.5 * L) dx -= L;
+          else if (dx < -0.5 * L) dx += L;
+        }
+        w *= kernel_phi(&K, dx / h);
+      }
+      if (w != 0.0) sum += (q ? q[i] : q0) * w;
+    }
+    rho_M[j] = sum / (node_a0(C, j) * h * h * h);
+  }
   for (int64_t b = 0; b < C->nb; b++) rho_M[C->n + b] = rho_M[C->bowner[b]];
   return 0;
 }

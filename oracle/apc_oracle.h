@@ -53,7 +53,15 @@ typedef struct {
                      always opened (max_depth >= 2), and the Poisson problem is
                      Delta phi = c (rho~ - mean rho~) with phi of mean 0 (means
                      weighted by cell volume); 0: the Dirichlet box */
+  int kernel;     /* charge-assignment kernel Phi of eq. density_apcloud: APCO_KERNEL_NGP
+                     (0, the node's own cell), APCO_KERNEL_CIC (1, the tent, support
+                     |u| <= 1 per axis) or APCO_KERNEL_TSC (2, the quadratic B-spline,
+                     |u| <= 3/2), u = (x - y) / h with h the node's cell edge */
 } apco_params;
+
+#define APCO_KERNEL_NGP 0
+#define APCO_KERNEL_CIC 1
+#define APCO_KERNEL_TSC 2
 
 typedef struct {
   int iters;
@@ -119,6 +127,15 @@ int apco_density_orders(const apco_cloud *C, int8_t *ord);
 /* NGP deposit (Sec. 5.1 kernel choice): rho_M for all n+nb nodes (boundary node takes
    its owner's value).  q may be NULL: every particle then carries 1/N. */
 int apco_deposit(const apco_cloud *C, const double *q, double *rho_M);
+/* eq. density_apcloud's right-hand side with the cloud's kernel, from the
+   particle positions xyz (3 x N, the order the cloud was built from):
+   rho_M(y_j) = sum_i q_i Phi((p_i - y_j) / h_j) / (a_0(y_j) h_j^3), a_0 the
+   kernel's mass inside Omega (1 away from the walls).  The NGP kernel gives
+   apco_deposit's values.  q NULL: 1/N each. */
+int apco_deposit_xyz(const apco_cloud *C, const double *xyz, const double *q, double *rho_M);
+/* 1-D kernel moment int_{max(tlo,-s)}^{min(thi,s)} u^k phi(u) du of kernel
+   (APCO_KERNEL_*), s its half-support; tlo/thi may be +-INFINITY. */
+double apco_kernel_moment(int kernel, int k, double tlo, double thi);
 /* Solve B rho~ = rho_M over interior nodes (boundary values moved to the rhs).
    rho_M, rho_t: n+nb. precond: 0 none, 1 Jacobi (right). */
 int apco_density_solve(const apco_cloud *C, const double *rho_M, double *rho_t, double tol,

@@ -28,7 +28,8 @@ class _Params(ct.Structure):
     _fields_ = [("lo", ct.c_double * 3), ("L", ct.c_double), ("order", ct.c_int),
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
-                ("criterion_pow", ct.c_int), ("tau_dom", ct.c_double), ("periodic", ct.c_int)]
+                ("criterion_pow", ct.c_int), ("tau_dom", ct.c_double), ("periodic", ct.c_int),
+                ("kernel", ct.c_int)]
 
 
 class _Stats(ct.Structure):
@@ -58,6 +59,9 @@ def _load():
     lib.apco_assemble.argtypes = [P, P, P]
     lib.apco_density_rows.argtypes = [P, P, P]
     lib.apco_deposit.argtypes = [P, P, P]
+    lib.apco_deposit_xyz.argtypes = [P, P, P, P]
+    lib.apco_kernel_moment.argtypes = [ct.c_int, ct.c_int, ct.c_double, ct.c_double]
+    lib.apco_kernel_moment.restype = ct.c_double
     lib.apco_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.c_int,
                                        ct.POINTER(_Stats)]
     lib.apco_poisson_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int,
@@ -92,7 +96,8 @@ def _check(rc, what):
 
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
-                ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0, tau_dom=0.0, periodic=0):
+                ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0, tau_dom=0.0, periodic=0,
+                kernel=0):
     P = _Params()
     P.lo[:] = lo
     P.L = L
@@ -106,7 +111,16 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     P.criterion_pow = criterion_pow
     P.tau_dom = tau_dom
     P.periodic = int(periodic)
+    P.kernel = int(kernel)
     return P
+
+
+KERNEL_NGP, KERNEL_CIC, KERNEL_TSC = 0, 1, 2
+
+
+def kernel_moment(kernel, k, tlo=-np.inf, thi=np.inf):
+    """1-D moment of a charge-assignment kernel over [tlo, thi] (apco_kernel_moment)."""
+    return _load().apco_kernel_moment(int(kernel), int(k), float(tlo), float(thi))
 
 
 def push(xyz, vel, grad, kick, dt, lo=(0.0, 0.0, 0.0), L=1.0, periodic=0):
@@ -270,7 +284,7 @@ class OracleCloud:
     def deposit(self, q=None):
         r = np.zeros(self.n + self.nb)
         qq = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
-        _check(self.lib.apco_deposit(self.h, _ptr(qq), _ptr(r)), "deposit")
+        _check(self.lib.apco_deposit_xyz(self.h, _ptr(self.xyz), _ptr(qq), _ptr(r)), "deposit")
         return r
 
     def density_solve(self, rho_M, tol=1e-12, maxit=10000, precond=0):
