@@ -969,10 +969,16 @@ static kpieces kernel_pieces(int kernel) {
   return K;
 }
 
-static double kernel_phi(const kpieces *K, double u) {
-  for (int q = 0; q < K->np; q++)
-    if (u >= K->a[q] && u <= K->b[q]) return K->c[q][0] + u * (K->c[q][1] + u * K->c[q][2]);
-  return 0.0;
+/* phi(u) evaluated as defined (the expanded coefficients above serve the moment
+   integrals; near the edge of the support they would cancel) */
+static double kernel_phi(int kernel, double u) {
+  const double a = fabs(u);
+  if (kernel == APCO_KERNEL_CIC) return a <= 1.0 ? 1.0 - a : 0.0;
+  if (kernel == APCO_KERNEL_TSC) {
+    if (a <= 0.5) return 0.75 - a * a;
+    return a <= 1.5 ? 0.5 * (1.5 - a) * (1.5 - a) : 0.0;
+  }
+  return a <= 0.5 ? 1.0 : 0.0;
 }
 
 static double kernel_halfsupport(int kernel) {
@@ -1177,7 +1183,6 @@ int apco_deposit_xyz(const apco_cloud *C, const double *xyz, const double *q, do
   if (!xyz) return APCO_EINVAL;
   const int64_t N = C->N;
   const double q0 = 1.0 / (double)N, L = C->P.L;
-  const kpieces K = kernel_pieces(C->P.kernel);
   for (int64_t j = 0; j < C->n; j++) {
     const double h = L / ldexp(1.0, C->cells[C->node_cell[j]].level);
     double yc[3];
@@ -1192,7 +1197,7 @@ int apco_deposit_xyz(const apco_cloud *C, const double *xyz, const double *q, do
           if (dx >= 0.5 * L) dx -= L;
           else if (dx < -0.5 * L) dx += L;
         }
-        w *= kernel_phi(&K, dx / h);
+        w *= kernel_phi(C->P.kernel, dx / h);
       }
       if (w != 0.0) sum += (q ? q[i] : q0) * w;
     }
