@@ -113,7 +113,20 @@ typedef struct {
                         weighted by cell volume); the FP64 residual diagnostic of
                         the mixed modes is not computed (-1).  0 (default): the
                         Dirichlet box */
+  int kernel;         /* charge-assignment kernel Phi of eq. density_apcloud, per axis of
+                        u = (x - y) / h_c: APC_KERNEL_NGP (0, default: the node's own
+                        cell), APC_KERNEL_CIC (1: the tent 1 - |u|, |u| <= 1) or
+                        APC_KERNEL_TSC (2: the quadratic B-spline, |u| <= 3/2).  CIC and
+                        TSC gather every particle within reach of the node, neighbour
+                        cells included; their moments a(y) integrate over Omega, so a
+                        node whose kernel reaches past a wall has a_0 < 1 (the kernel's
+                        mass inside Omega) and odd and mixed moments: its density row
+                        and rho_M are divided by a_0.  Batches take NGP only. */
 } apc_params;
+
+#define APC_KERNEL_NGP 0
+#define APC_KERNEL_CIC 1
+#define APC_KERNEL_TSC 2
 
 typedef struct {
   int iters;             /* Krylov iterations (summed over refinement sweeps) */
@@ -389,8 +402,9 @@ typedef struct {
 
 /* Build count clouds (xyz[c]: device pointer of cloud c's 3 x N[c] SoA particles;
    xyz and N are host arrays), then their union.  Same errors as
-   apc_build_cloud, for the first cloud that fails; APC_EINVAL for order 4 or a
-   periodic domain (a batch holds bounded order-2 clouds).  Synchronises. */
+   apc_build_cloud, for the first cloud that fails; APC_EINVAL for order 4, a
+   periodic domain or a CIC / TSC kernel (a batch holds bounded order-2 clouds
+   with the NGP deposit).  Synchronises. */
 int apc_build_batch(const apc_params *p, int count, const double *const *xyz, const int64_t *N,
                     hipStream_t stream, apc_batch **out);
 /* Totals and launch shape; per-cloud sizes into host arrays (each may be NULL). */

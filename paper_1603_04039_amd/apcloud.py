@@ -19,6 +19,7 @@ APC_OK, APC_EINVAL, APC_ENOMEM, APC_EHIP, APC_EDOMAIN, APC_ESTENCIL = 0, -1, -2,
 APC_ENOCONV = 1
 APC_NOALLOC_BYTES = 32 << 20  # fixed derivative buffer of apc_interpolate_force_noalloc
 APC_FP64, APC_MIXED, APC_MIXED_F32ACC = 0, 1, 2
+APC_KERNEL_NGP, APC_KERNEL_CIC, APC_KERNEL_TSC = 0, 1, 2
 APC_PRECOND_NONE, APC_PRECOND_JACOBI, APC_PRECOND_LEARNED = 0, 1, 2
 APC_DIAG_KERNEL_TIMES, APC_DIAG_FP64_RESIDUAL = 1, 2
 MLP_IN, MLP_HID, MLP_OUT = 48, 64, 41
@@ -51,7 +52,7 @@ class Params(ct.Structure):
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
                 ("precision", ct.c_int), ("stage_cap", ct.c_int), ("criterion_pow", ct.c_int),
                 ("ring_lds", ct.c_int), ("ring_first_cap", ct.c_int), ("tau_dom", ct.c_double),
-                ("periodic", ct.c_int)]
+                ("periodic", ct.c_int), ("kernel", ct.c_int)]
 
 
 class Stats(ct.Structure):
@@ -166,7 +167,7 @@ def _check(rc, what):
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
                 ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64,
                 stage_cap=0, criterion_pow=0, ring_lds=0, ring_first_cap=0,
-                tau_dom=0.0, periodic=0) -> Params:
+                tau_dom=0.0, periodic=0, kernel=0) -> Params:
     p = Params()
     load_library().apc_default_params(ct.byref(p), order)
     p.lo[:] = lo
@@ -186,6 +187,7 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     p.ring_first_cap = ring_first_cap
     p.tau_dom = tau_dom
     p.periodic = periodic
+    p.kernel = kernel
     return p
 
 

@@ -94,6 +94,108 @@ __host__ __device__ inline int32_t apc_doff(int32_t a, int32_t b, int32_t S) {
   return d;
 }
 
+// ---- charge-assignment kernels of eq. density_apcloud (APC_KERNEL_*), per axis
+__host__ __device__ inline double apc_kernel_reach(int kernel) {
+  return kernel == APC_KERNEL_CIC ? 1.0 : (kernel == APC_KERNEL_TSC ? 1.5 : 0.5);
+}
+// phi(u) of CIC (tent) and TSC (quadratic B-spline)
+__host__ __device__ inline double apc_kernel_phi(int kernel, double u) {
+  const double a = fabs(u);
+  if (kernel == APC_KERNEL_CIC) return a < 1.0 ? 1.0 - a : 0.0;
+  if (a <= 0.5) return 0.75 - u * u;
+  if (a < 1.5) {
+    const double t = 1.5 - a;
+    return 0.5 * t * t;
+  }
+  return 0.0;
+}
+// u^k as a product of k factors
+__host__ __device__ inline double apc_powi(double u, int k) {
+  double r = 1.0;
+  for (int i = 0; i < k; i++) r *= u;
+  return r;
+}
+// int_lo^hi u^k phi(u) du, the integral of u^k (c0 + c1 u + c2 u^2) term by term
+__host__ __device__ inline double apc_piece_int(int k, double c0, double c1, double c2, double lo,
+                                                double hi) {
+  auto F = [&](double u) {
+    return c0 * apc_powi(u, k + 1) / (k + 1) + c1 * apc_powi(u, k + 2) / (k + 2) +
+           c2 * apc_powi(u, k + 3) / (k + 3);
+  };
+  return F(hi) - F(lo);
+}
+// 1-D moment int u^k phi(u) du over [lo, hi] intersected with the kernel's support
+// (lo, hi may be infinite).  Over the whole support odd moments vanish (phi is
+// even).  NGP: phi = 1 on [-1/2, 1/2].
+__host__ __device__ inline double apc_kernel_moment(int kernel, int k, double lo, double hi) {
+  const double r = apc_kernel_reach(kernel);
+  if ((k & 1) && lo <= -r && hi >= r) return 0.0;
+  double m = 0.0;
+  auto piece = [&](double a, double b, double c0, double c1, double c2) {
+    const double l = fmax(a, lo), h = fmin(b, hi);
+    if (h > l) m += apc_piece_int(k, c0, c1, c2, l, h);
+  };
+  if (kernel == APC_KERNEL_NGP) {
+    piece(-0.5, 0.5, 1.0, 0.0, 0.0);
+  } else if (kernel == APC_KERNEL_CIC) {
+    piece(-1.0, 0.0, 1.0, 1.0, 0.0);
+    piece(0.0, 1.0, 1.0, -1.0, 0.0);
+  } else { // (3/2 -+ u)^2 / 2 = 9/8 -+ 3/2 u + u^2 / 2 outside, 3/4 - u^2 inside
+    piece(-1.5, -0.5, 1.125, 1.5, 0.5);
+    piece(-0.5, 0.5, 0.75, 0.0, -1.0);
+    piece(0.5, 1.5, 1.125, -1.5, 0.5);
+  }
+  return m;
+}
+// Range [tlo, thi] of the kernel argument u = (x - y) / h_c inside Omega along
+// each axis for the node at integer coordinates c (units L / 2^(D+1)), cell edge E
+// in those units, domain side S2 = 2^(D+1) units; S2 = 0: no walls (periodic).
+__host__ __device__ inline void apc_node_trunc(int32_t c0, int32_t c1, int32_t c2, double E,
+                                               double S2, double tlo[3], double thi[3]) {
+  const int32_t c[3] = {c0, c1, c2};
+  for (int d = 0; d < 3; d++) {
+    tlo[d] = S2 > 0.0 ? -(double)c[d] / E : -INFINITY;
+    thi[d] = S2 > 0.0 ? (S2 - (double)c[d]) / E : INFINITY;
+  }
+}
+__host__ __device__ inline bool apc_truncated(int kernel, const double tlo[3], const double thi[3]) {
+  const double r = apc_kernel_reach(kernel);
+  return kernel != APC_KERNEL_NGP &&
+         (tlo[0] > -r || tlo[1] > -r || tlo[2] > -r || thi[0] < r || thi[1] < r || thi[2] < r);
+}
+// a_0: the kernel's mass inside Omega
+__host__ __device__ inline double apc_kernel_a0(int kernel, const double tlo[3], const double thi[3]) {
+  double a0 = 1.0;
+  for (int d = 0; d < 3; d++) a0 *= apc_kernel_moment(kernel, 0, tlo[d], thi[d]);
+  return a0;
+}
+// Density-row coefficient of the fitted unknown hp^|alpha| d^alpha f: (a_alpha / a_0)
+// / hp^|alpha|, a_alpha = prod_d hc^a_d mu_a_d / a_d! (the Taylor terms carry
+// 1/alpha!).  NGP: mu_e = (1/2)^e / (e + 1) for even e, 0 for odd.
+__host__ __device__ inline double apc_dens_coef(int kernel, int ax, int ay, int az, double hc,
+                                                double hp, const double tlo[3],
+                                                const double thi[3], double a0) {
+  const int e[3] = {ax, ay, az};
+  double mom = 1.0;
+  if (kernel == APC_KERNEL_NGP) {
+    if ((ax | ay | az) & 1) return 0.0;
+    for (int d = 0; d < 3; d++) {
+      double pw = 1.0, f = 1.0;
+      for (int q = 0; q < e[d]; q++) pw *= hc / 2.0;
+      for (int q = 2; q <= e[d]; q++) f *= q;
+      mom *= pw / (double)(e[d] + 1) / f;
+    }
+  } else {
+    for (int d = 0; d < 3; d++) {
+      double f = 1.0;
+      for (int q = 2; q <= e[d]; q++) f *= q;
+      mom *= apc_powi(hc, e[d]) * apc_kernel_moment(kernel, e[d], tlo[d], thi[d]) / f;
+    }
+    mom /= a0;
+  }
+  return mom / apc_powi(hp, ax + ay + az);
+}
+
 __host__ __device__ inline uint64_t apc_morton(uint32_t x, uint32_t y, uint32_t z) {
   return (apc_spread3(x) << 2) | (apc_spread3(y) << 1) | apc_spread3(z);
 }
@@ -162,6 +264,7 @@ struct apc_cloud {
   double *w64 = nullptr; // nnz (APC_FP64)
   float *w32 = nullptr;  // nnz (APC_MIXED)
   double *diag = nullptr, *inv_diag = nullptr; // n
+  double *dwx = nullptr;    // nnz (k = 2, CIC / TSC): explicit density rows (hscale < 0)
   double *hscale = nullptr;                    // n: h_c^2 / 24 (density operator, k = 2;
                                                // 0 for an identity density row)
   int32_t *fb_list = nullptr;                  // n (k = 4): nodes the assembly refits by QR

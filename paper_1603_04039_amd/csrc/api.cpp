@@ -166,15 +166,32 @@ int apc_get_density_operator(const apc_cloud *c, double *bw_host, double *bdiag_
       }
     }
   } else {
-    // k = 2: b = (h_c^2 / 24) w, diagonal 1 + (h_c^2 / 24) d; hscale 0 is the identity row
+    // k = 2: b = hs w, diagonal 1 + hs d (hs = h_c^2 mu_2 / 2); hscale 0 is the identity
+    // row, hscale < 0 an explicit row (dwx, a kernel reaching past a wall) with
+    // diagonal 1 - sum b
     std::vector<double> hs((size_t)(n > 0 ? n : 1)), d((size_t)(n > 0 ? n : 1));
     APCCHK(apc_get_operator(c, bw.data(), d.data()));
     if (n > 0) HIPCHK(hipMemcpy(hs.data(), c->hscale, (size_t)n * 8, hipMemcpyDeviceToHost));
+    std::vector<double> dx;
+    if (c->dwx && nnz > 0) {
+      dx.resize((size_t)nnz);
+      HIPCHK(hipMemcpy(dx.data(), c->dwx, (size_t)nnz * 8, hipMemcpyDeviceToHost));
+    }
     std::vector<int32_t> off((size_t)n + 1);
     HIPCHK(hipMemcpy(off.data(), c->st_off, (size_t)(n + 1) * 4, hipMemcpyDeviceToHost));
-    for (int64_t i = 0; i < n; i++)
-      for (int32_t e = off[i]; e < off[i + 1]; e++) bw[e] *= hs[i];
-    for (int64_t i = 0; i < n; i++) bd[i] = 1.0 + hs[i] * d[i];
+    for (int64_t i = 0; i < n; i++) {
+      if (hs[i] < 0.0) {
+        double sum = 0.0;
+        for (int32_t e = off[i]; e < off[i + 1]; e++) {
+          bw[e] = dx[e];
+          sum += dx[e];
+        }
+        bd[i] = 1.0 - sum;
+      } else {
+        for (int32_t e = off[i]; e < off[i + 1]; e++) bw[e] *= hs[i];
+        bd[i] = 1.0 + hs[i] * d[i];
+      }
+    }
   }
   if (c->P.order == 4) {
     std::vector<int32_t> off((size_t)n + 1);
@@ -369,6 +386,7 @@ int apc_build_batch(const apc_params *p, int count, const double *const *xyz, co
   *out = nullptr;
   if (p->order != 2) return APC_EINVAL; // the union carries k = 2 operators only
   if (p->periodic) return APC_EINVAL;   // batches hold bounded domains only
+  if (p->kernel != APC_KERNEL_NGP) return APC_EINVAL; // and the NGP deposit
   for (int c = 0; c < count; c++)
     if (!xyz[c] || N[c] < 1) return APC_EINVAL;
   return apc_build_batch_impl(p, count, xyz, N, stream, out);

@@ -949,7 +949,7 @@ void apc_free_cloud(apc_cloud *c) {
   apc_free_solver(c);
   apc_free_sell(c);
   free_cloud_arrays(c);
-  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->rkind, c->scratch,
+  void *ops[] = {c->w64, c->w32, c->diag, c->inv_diag, c->hscale, c->dwx, c->rkind, c->scratch,
                  c->m_diag, c->m_sell, c->m_tmpl, c->bw64, c->bw32, c->sl_bw64, c->sl_bw32,
                  c->rorder, c->dorder, c->w64ref, c->fb_list, c->rkind4, c->gen4, c->cder4};
   for (void *q : ops)
@@ -1334,7 +1334,8 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
       p->ring_first_cap < 0 || p->ring_first_cap > APC_RING_CAP || !(p->tau_dom >= 0.0) ||
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
         p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c) ||
-      p->periodic < 0 || p->periodic > 1 || (p->periodic && p->max_depth < 2))
+      p->periodic < 0 || p->periodic > 1 || (p->periodic && p->max_depth < 2) ||
+      p->kernel < APC_KERNEL_NGP || p->kernel > APC_KERNEL_TSC)
     return APC_EINVAL;
   apc_cloud *c = new apc_cloud();
   c->P = *p;

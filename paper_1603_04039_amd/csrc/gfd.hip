@@ -289,6 +289,47 @@ __device__ inline double fit64_row(int32_t row, int64_t off, const int32_t *__re
   return ratio;
 }
 
+// Density row of a node whose CIC / TSC kernel reaches past a wall (eq.
+// density_linear_system with the moments over Omega, divided by a_0): the FP64 fit
+// of the functional sum_alpha (a_alpha / a_0) d^alpha, b_j = W_j^2 (v_j . z), into
+// dwx (CSR order).  Returns whether the row meets the stability bound
+// sum |b_j| <= theta (1 - sum b_j) (else the caller takes the identity row).
+__device__ inline bool density_explicit(int32_t row, int kernel, double hc, double unit,
+                                        const double tlo[3], const double thi[3],
+                                        const int32_t *__restrict__ st_off,
+                                        const int32_t *__restrict__ st_idx,
+                                        const int32_t *__restrict__ crd, int64_t ntot,
+                                        double *__restrict__ dwx) {
+  const int32_t a = st_off[row];
+  const int m = st_off[row + 1] - a;
+  const int32_t *nb = st_idx + a;
+  const NodeGeom g = node_geom(nb, m, crd, ntot, row);
+  const double hp = (double)g.h * unit;
+  const double a0 = apc_kernel_a0(kernel, tlo, thi);
+  // unknowns in the order of mono9: x, y, z, xx, xy, xz, yy, yz, zz
+  constexpr int AX[P9] = {1, 0, 0, 2, 1, 1, 0, 0, 0}, AY[P9] = {0, 1, 0, 0, 1, 0, 2, 1, 0},
+                AZ[P9] = {0, 0, 1, 0, 0, 1, 0, 1, 2};
+  double G[G45], z[P9];
+  gram<double>(nb, m, g, crd, ntot, G);
+  cholesky9<double>(G);
+#pragma unroll
+  for (int k = 0; k < P9; k++) z[k] = apc_dens_coef(kernel, AX[k], AY[k], AZ[k], hc, hp, tlo, thi, a0);
+  chol_solve9<double>(G, z);
+  double sum = 0.0, asum = 0.0;
+  for (int j = 0; j < m; j++) {
+    double vv[P9];
+    const double w2 = row_w2<double>(g, crd, ntot, nb[j], vv);
+    double dotv = 0.0;
+#pragma unroll
+    for (int k = 0; k < P9; k++) dotv += vv[k] * z[k];
+    const double b = w2 * dotv;
+    dwx[a + j] = b;
+    sum += b;
+    asum += fabs(b);
+  }
+  return asum <= APC_THETA_B * (1.0 - sum);
+}
+
 // One wavefront per slice of the sliced layout (indices were laid out at build).
 // Uniform slices: the rows' diagonal from the canonical shell constants (their
 // CSR weights are implied by rkind and are not stored).  General slices: fit
@@ -308,7 +349,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
                float *__restrict__ w32, double *__restrict__ diag, double *__restrict__ inv_diag,
                double *__restrict__ hscale, int8_t *__restrict__ dorder,
                double *__restrict__ sw64, float *__restrict__ sw32,
-               int *__restrict__ err, unsigned long long *__restrict__ nfp64) {
+               int *__restrict__ err, unsigned long long *__restrict__ nfp64, int kernel,
+               double S2, double *__restrict__ dwx) {
   const int64_t s = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
   if (s >= nsl) return;
   const int lane = threadIdx.x & 63;
@@ -316,10 +358,24 @@ __global__ void __launch_bounds__(APC_BLOCK)
   if (row < 0) return;
   const int64_t off = sl_off[s] + lane;
   const double hc = L / (double)(1 << level[row]);
-  const double hs = hc * hc / 24.0;
+  // a_2 = h_c^2 mu_2 / 2 per axis: mu_2 = 1/12 (NGP), 1/6 (CIC), 1/4 (TSC)
+  const double hs = kernel == APC_KERNEL_CIC ? hc * hc / 12.0
+                                             : (kernel == APC_KERNEL_TSC ? hc * hc / 8.0 : hc * hc / 24.0);
+  double tlo[3], thi[3];
+  apc_node_trunc(crd[row], crd[ntot + row], crd[2 * ntot + row], hc / unit, S2, tlo, thi);
+  const bool trunc = apc_truncated(kernel, tlo, thi);
   // density row b = hs w (eq. density_linear_system at k = 2), diagonal 1 - hs sum w:
-  // kept when hs sum |w| <= theta (1 - hs sum w), else the identity row (hs = 0)
+  // kept when hs sum |w| <= theta (1 - hs sum w), else the identity row (hs = 0).
+  // A kernel that reaches past a wall has odd and mixed moments: that row is the
+  // FP64 fit of its own functional, stored in dwx (hs = -1 marks it).
   auto density_row = [&](double sum, double asum) {
+    if (trunc) {
+      const bool ok = density_explicit(row, kernel, hc, unit, tlo, thi, st_off, st_idx, crd,
+                                       ntot, dwx);
+      hscale[row] = ok ? -1.0 : 0.0;
+      if (dorder) dorder[row] = ok ? 2 : 0;
+      return;
+    }
     const bool ok = hs * asum <= APC_THETA_B * (1.0 - hs * sum);
     hscale[row] = ok ? hs : 0.0;
     if (dorder) dorder[row] = ok ? 2 : 0;
@@ -520,6 +576,8 @@ int apc_prepare_operator(apc_cloud *c, hipStream_t s) {
     HIPCHK(apc_dev_alloc((void **)&c->w32, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(float)));
   else
     HIPCHK(apc_dev_alloc((void **)&c->w64, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
+  if (c->P.order == 2 && c->P.kernel != APC_KERNEL_NGP) // explicit density rows beside walls
+    HIPCHK(apc_dev_alloc((void **)&c->dwx, (size_t)(c->nnz > 0 ? c->nnz : 1) * sizeof(double)));
   if (c->P.order == 2) {
     hipLaunchKernelGGL(k_classify, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, n, c->st_off,
                        c->st_idx, c->crd, ntot, c->level, c->P.max_depth, c->rkind);
@@ -588,13 +646,15 @@ int apc_assemble_impl(apc_cloud *c, hipStream_t s) {
                          c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
                          c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
                          c->inv_diag, c->hscale, c->dorder, c->sl_w64, c->sl_w32,
-                         &c->scratch->err, &c->scratch->nfp64);
+                         &c->scratch->err, &c->scratch->nfp64, c->P.kernel,
+                         c->P.periodic ? 0.0 : c->P.L / c->unit, c->dwx);
     } else {
       hipLaunchKernelGGL(k_fit_sell<false>, dim3(gsl), dim3(APC_BLOCK), 0, s, c->nsl, c->sl_rows,
                          c->sl_len, c->sl_off, c->sl_tmpl, c->st_off, c->st_idx, c->crd, ntot,
                          c->level, c->unit, c->P.L, c->scratch->tc, c->w64, c->w32, c->diag,
                          c->inv_diag, c->hscale, c->dorder, c->sl_w64, c->sl_w32,
-                         &c->scratch->err, &c->scratch->nfp64);
+                         &c->scratch->err, &c->scratch->nfp64, c->P.kernel,
+                         c->P.periodic ? 0.0 : c->P.L / c->unit, c->dwx);
     }
     HIPCHK(hipGetLastError());
   }

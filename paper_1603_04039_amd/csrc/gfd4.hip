@@ -411,29 +411,34 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
 }
 
 // ---------------------------------------------------------------- assembly
-// Moments of the cell (eq. density_linear_system) over h^|alpha| for unknown `lane`,
-// and the Laplacian's right-hand side (unknowns xx = 3, yy = 6, zz = 8)
-__device__ __forceinline__ void fit_rhs(int lane, int pc, double hc, double hp, double &cl,
-                                        double &cb) {
+// Kernel moments (eq. density_linear_system) over h^|alpha| for unknown `lane` --
+// of the node's own cell (NGP), or of the CIC / TSC kernel over its support inside
+// Omega ([tlo, thi] per axis) divided by the mass a0 there -- and the Laplacian's
+// right-hand side (unknowns xx = 3, yy = 6, zz = 8)
+__device__ __forceinline__ void fit_rhs(int lane, int pc, double hc, double hp, int kernel,
+                                        const double *tlo, const double *thi, double a0,
+                                        double &cl, double &cb) {
   cl = 0.0;
   cb = 0.0;
   if (lane < pc) {
     int ax, ay, az;
     alpha4(lane, ax, ay, az);
     cl = (lane == 3 || lane == 6 || lane == 8) ? 1.0 : 0.0;
-    if (((ax | ay | az) & 1) == 0) {
-      double mom = 1.0;
-      const int e[3] = {ax, ay, az};
-      for (int d = 0; d < 3; d++) {
-        double pw = 1.0;
-        for (int q = 0; q < e[d]; q++) pw *= hc / 2.0;
-        mom *= pw / (double)(e[d] + 1) / fact(e[d]);
-      }
-      double hk = 1.0;
-      for (int q = 0; q < ax + ay + az; q++) hk *= hp;
-      cb = mom / hk;
-    }
+    cb = apc_dens_coef(kernel, ax, ay, az, hc, hp, tlo, thi, a0);
   }
+}
+
+// the kernel's support inside Omega for node y (S2 = 0: no walls)
+struct Trunc {
+  double lo[3], hi[3], a0;
+};
+__device__ __forceinline__ Trunc node_trunc4(int kernel, const int32_t *__restrict__ crd,
+                                             int64_t ntot, int64_t y, double hc, double unit,
+                                             double S2) {
+  Trunc t;
+  apc_node_trunc(crd[y], crd[ntot + y], crd[2 * ntot + y], hc / unit, S2, t.lo, t.hi);
+  t.a0 = kernel == APC_KERNEL_NGP ? 1.0 : apc_kernel_a0(kernel, t.lo, t.hi);
+  return t;
 }
 
 // Writes one node's Laplacian and density rows (lane j: stencil entry j) and its
@@ -489,7 +494,7 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
            float *__restrict__ w32,
            double *__restrict__ bw64, float *__restrict__ bw32, double *__restrict__ diag,
            double *__restrict__ inv_diag, double *__restrict__ hscale, int8_t *__restrict__ dorder,
-           double *__restrict__ w64ref, int *__restrict__ err) {
+           double *__restrict__ w64ref, int *__restrict__ err, int kernel, double S2) {
   __shared__ Wave4 SH[WPB4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   Wave4 &S = SH[wv];
@@ -508,17 +513,18 @@ __global__ void __launch_bounds__(WPB4 * 64, 2)
     }
     const double hp = (double)g.h * unit;
     const double hc = L / (double)(1 << level[y]);
+    const Trunc tr = node_trunc4(kernel, crd, ntot, y, hc, unit, S2);
     double cl, cb;
-    fit_rhs(lane, pc, hc, hp, cl, cb);
+    fit_rhs(lane, pc, hc, hp, kernel, tr.lo, tr.hi, tr.a0, cl, cb);
     double ul, ub, zl, zb;
     solve_rrt(S, lane, pc, cl, cb, ul, ub);
     wv0_times(S, g, lane, pc, ul, ub, zl, zb);
     const double wl = lane < m ? g.W * zl / (hp * hp) : 0.0;
     const double wb = lane < m ? g.W * zb : 0.0;
     // the order-2 row of the same stencil: the leading 9 columns of the same
-    // factorisation, moments of order 2 only
+    // factorisation, moments of order <= 2 only
     auto order2 = [&]() {
-      const double cb2 = (lane == 3 || lane == 6 || lane == 8) ? cb : 0.0;
+      const double cb2 = lane < 9 ? cb : 0.0;
       double u2, u0, z2, z0;
       solve_rrt(S, lane, 9, cb2, 0.0, u2, u0);
       wv0_times(S, g, lane, 9, u2, u0, z2, z0);
@@ -831,7 +837,7 @@ __global__ void __launch_bounds__(wpbn<MR>() * 64)
             float *__restrict__ w32, double *__restrict__ bw64, float *__restrict__ bw32,
             double *__restrict__ diag, double *__restrict__ inv_diag, double *__restrict__ hscale,
             int8_t *__restrict__ dorder, double *__restrict__ w64ref, int32_t *__restrict__ fb_list,
-            unsigned *__restrict__ fb_cnt) {
+            unsigned *__restrict__ fb_cnt, int kernel, double S2) {
   constexpr int WPB = wpbn<MR>();
   __shared__ WaveN<MR> SH[WPB];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
@@ -846,8 +852,9 @@ __global__ void __launch_bounds__(wpbn<MR>() * 64)
   wsync();
   const double hp = (double)g.h * unit;
   const double hc = L / (double)(1 << level[y]);
+  const Trunc tr = node_trunc4(kernel, crd, ntot, y, hc, unit, S2);
   double cl, cb;
-  fit_rhs(lane, pc, hc, hp, cl, cb);
+  fit_rhs(lane, pc, hc, hp, kernel, tr.lo, tr.hi, tr.a0, cl, cb);
   double lrow[P4], rd, zl, zb;
   bool ok;
   if (pc == P4) {
@@ -873,10 +880,10 @@ __global__ void __launch_bounds__(wpbn<MR>() * 64)
   const double wl = lane < m ? g.W * yl / (hp * hp) : 0.0;
   const double wb = lane < m ? g.W * yb : 0.0;
   // the order-2 row of the same stencil: the leading 9 x 9 block of the same
-  // Cholesky factor (G's leading block), moments of order 2 only
+  // Cholesky factor (G's leading block), moments of order <= 2 only
   bool ok2 = true;
   auto order2 = [&]() {
-    const double cb2 = (lane == 3 || lane == 6 || lane == 8) ? cb : 0.0;
+    const double cb2 = lane < 9 ? cb : 0.0;
     double z2, z0, y2, y0;
     ok2 = solve_refined<MR, 9>(S, lane, lrow, rd, cb2, 0.0, z2, z0);
     a_times_n<MR, 9>(S, lane, z2, z0, y2, y0);
@@ -1262,12 +1269,12 @@ int apc_prepare_uniform4(apc_cloud *c, hipStream_t s) {
                      (const int32_t *)nullptr, d->st_off, d->st_idx, d->crd, (int64_t)57, d->level,
                      d->rorder, 1.0, 1.0, d->w64, (float *)nullptr, d->bw64, (float *)nullptr,
                      d->diag, d->inv_diag, d->hscale, d->dorder, (double *)nullptr, d->fb_list,
-                     &d->fb_cnt);
+                     &d->fb_cnt, c->P.kernel, 0.0);
   hipLaunchKernelGGL((k_fit4<false, 56>), dim3(1), dim3(WPB4 * 64), 0, s,
                      (const int32_t *)d->fb_list, (const unsigned *)&d->fb_cnt, d->st_off,
                      d->st_idx, d->crd, (int64_t)57, d->level, d->rorder, 1.0, 1.0, d->w64,
                      (float *)nullptr, d->bw64, (float *)nullptr, d->diag, d->inv_diag, d->hscale,
-                     d->dorder, (double *)nullptr, &d->err);
+                     d->dorder, (double *)nullptr, &d->err, c->P.kernel, 0.0);
   // the canonical derivative operator (56 x 34), then tabulated by offset (125 x 34)
   HIPCHK(apc_dev_alloc((void **)&c->cder4, 125 * P4 * sizeof(double)));
   double *cj = nullptr;
@@ -1358,6 +1365,7 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
     // the fitted rows: every row but the uniform 56-node ones
     const int64_t nfit = c->n_uniform4 > 0 ? c->n_gen4 : n;
     const int32_t *fit_list = c->n_uniform4 > 0 ? c->gen4 : nullptr;
+    const double s2 = c->P.periodic ? 0.0 : c->P.L / c->unit; // walls for the kernel moments
     // normal equations on the matrix cores for every node, then the Householder QR
     // for the nodes listed by it (grid-stride over the list; the count stays on
     // the device)
@@ -1367,13 +1375,13 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
                      dim3(wpbn<R>() * 64), 0, s, nfit, fit_list, c->st_off, c->st_idx, c->crd, ntot, \
                      c->level, c->rorder, c->unit, c->P.L, c->w64, c->w32, c->bw64, c->bw32,   \
                      c->diag, c->inv_diag, c->hscale, c->dorder, ref, c->fb_list,              \
-                     &c->scratch->fb_count)
+                     &c->scratch->fb_count, c->P.kernel, s2)
 #define APC_FIT4(MX, R)                                                                        \
   hipLaunchKernelGGL((k_fit4<MX, R>), dim3(1024), dim3(WPB4 * 64), 0, s,                       \
                      (const int32_t *)c->fb_list, (const unsigned *)&c->scratch->fb_count,     \
                      c->st_off, c->st_idx, c->crd, ntot, c->level, c->rorder, c->unit, c->P.L, \
                      c->w64, c->w32, c->bw64, c->bw32, c->diag, c->inv_diag, c->hscale,        \
-                     c->dorder, ref, &c->scratch->err)
+                     c->dorder, ref, &c->scratch->err, c->P.kernel, s2)
     if (mixed && m56) {
       APC_FIT4N(true, 56);
       APC_FIT4(true, 56);

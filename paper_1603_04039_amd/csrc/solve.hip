@@ -379,14 +379,16 @@ __global__ void __launch_bounds__(APC_BLOCK)
           const double *__restrict__ bval, double *__restrict__ b) {
   const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (i >= n) return;
+  const bool ex = op.hs && op.hs[i] < 0.0; // explicit density row
   double acc = 0.0;
   if (bval) {
     for (int32_t e = op.off[i]; e < op.off[i + 1]; e++) {
       const int32_t j = op.idx[e];
-      if (j >= n) acc += ((MODE == V64) ? op.w64[e] : (double)op.w32[e]) * bval[j - n];
+      if (j >= n)
+        acc += (ex ? op.dwx[e] : ((MODE == V64) ? op.w64[e] : (double)op.w32[e])) * bval[j - n];
     }
   }
-  b[i] = srcscale * src[i] - (op.hs ? op.hs[i] * acc : acc);
+  b[i] = srcscale * src[i] - ((op.hs && !ex) ? op.hs[i] * acc : acc);
 }
 
 __global__ void __launch_bounds__(APC_BLOCK)
@@ -427,6 +429,105 @@ __global__ void __launch_bounds__(APC_BLOCK)
   }
   const double hc = L / (double)(1 << level[j]);
   rho[j] = sum / (hc * hc * hc);
+}
+
+// last node whose code (Morton key of its cell's minimum corner) is <= key; the
+// leaves tile Omega, so that node's cell holds the key
+__device__ __forceinline__ int64_t leaf_of(const uint64_t *__restrict__ code, int64_t n,
+                                           uint64_t key) {
+  int64_t lo = 0, hi = n; // code[lo] <= key < code[hi] (code[0] = 0)
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (code[mid] <= key) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// CIC / TSC deposit (eq. density_apcloud): rho_M_j = sum_i q_i Phi((p_i - y_j) / h_j)
+// / (a_0 h_j^3), one thread per node.  The kernel's support lies in the 3 x 3 x 3
+// block of cells of the node's size around it; each such region R (an aligned cube,
+// so a contiguous range of Morton keys and of sorted particles) is either inside
+// one leaf (a coarser or equal cell: its particles are visited once, from the
+// region of the block that holds the leaf's lowest corner in it) or the union of
+// the leaves whose keys fall in R.  Minimum-image offsets on a periodic domain.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_deposit_kern(int64_t n, int64_t N, int kernel, int D, const uint64_t *__restrict__ code,
+                   const int32_t *__restrict__ level, const int32_t *__restrict__ first,
+                   const int32_t *__restrict__ count, const int32_t *__restrict__ crd,
+                   int64_t ntot, const double *__restrict__ sxyz, const int32_t *__restrict__ perm,
+                   const double *__restrict__ q, double lo0, double lo1, double lo2, double L,
+                   double unit, double *__restrict__ rho) {
+  const int64_t j = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (j >= n) return;
+  const int32_t side = 1 << D, S = crd[3 * ntot];
+  const bool per = S != 0;
+  const int l = level[j];
+  const int32_t E = 1 << (D - l); // cell edge in units L / 2^D
+  const int32_t c[3] = {crd[j], crd[ntot + j], crd[2 * ntot + j]};
+  const int32_t o[3] = {(c[0] - E) >> 1, (c[1] - E) >> 1, (c[2] - E) >> 1};
+  const double hc = L / (double)(1 << l);
+  const double yc[3] = {lo0 + unit * (double)c[0], lo1 + unit * (double)c[1],
+                        lo2 + unit * (double)c[2]};
+  const double q0 = 1.0 / (double)N;
+  // region coordinate along an axis (-1 when outside a bounded domain)
+  auto rc = [&](int d, int t) -> int32_t {
+    int32_t r = o[d] + t * E;
+    if (per) return (r + side) & (side - 1);
+    return (r < 0 || r >= side) ? -1 : r;
+  };
+  double sum = 0.0;
+  for (int tz = -1; tz <= 1; tz++)
+    for (int ty = -1; ty <= 1; ty++)
+      for (int tx = -1; tx <= 1; tx++) {
+        const int t[3] = {tx, ty, tz};
+        int32_t r[3];
+        bool valid = true;
+        for (int d = 0; d < 3; d++) {
+          r[d] = rc(d, t[d]);
+          valid = valid && r[d] >= 0;
+        }
+        if (!valid) continue;
+        const uint64_t k0 = apc_morton((uint32_t)r[0], (uint32_t)r[1], (uint32_t)r[2]);
+        const int64_t a = leaf_of(code, n, k0);
+        const int32_t Ea = 1 << (D - level[a]);
+        int32_t ps, pe;
+        if (Ea >= E) {
+          // R lies in leaf a: only the block's first region in that leaf (per
+          // axis the smallest offset t whose region is inside it) takes its particles
+          const int32_t oa[3] = {(crd[a] - Ea) >> 1, (crd[ntot + a] - Ea) >> 1,
+                                 (crd[2 * ntot + a] - Ea) >> 1};
+          bool firstr = true;
+          for (int d = 0; d < 3 && firstr; d++)
+            for (int u = -1; u < t[d]; u++) {
+              const int32_t rr = rc(d, u);
+              if (rr >= 0 && ((rr - oa[d] + side) & (side - 1)) < Ea) firstr = false;
+            }
+          if (!firstr) continue;
+          ps = first[a];
+          pe = ps + count[a];
+        } else {
+          const uint64_t e3 = (uint64_t)E * (uint64_t)E * (uint64_t)E;
+          const int64_t b = leaf_of(code, n, k0 + e3 - 1);
+          ps = first[a];
+          pe = first[b] + count[b];
+        }
+        for (int32_t s = ps; s < pe; s++) {
+          double w = 1.0;
+          for (int d = 0; d < 3 && w != 0.0; d++) {
+            double dx = sxyz[(int64_t)d * N + s] - yc[d];
+            if (per) {
+              if (dx >= 0.5 * L) dx -= L;
+              else if (dx < -0.5 * L) dx += L;
+            }
+            w *= apc_kernel_phi(kernel, dx / hc);
+          }
+          if (w != 0.0) sum += (q ? q[perm[s]] : q0) * w;
+        }
+      }
+  double tlo[3], thi[3];
+  apc_node_trunc(c[0], c[1], c[2], (double)(2 * E), per ? 0.0 : (double)(2 * side), tlo, thi);
+  rho[j] = sum / (apc_kernel_a0(kernel, tlo, thi) * (hc * hc * hc));
 }
 
 __global__ void __launch_bounds__(APC_BLOCK)
@@ -689,8 +790,14 @@ static int run_solve(apc_cloud *c, bool density, const double *b, double *x, dou
 }
 
 int apc_deposit_impl(apc_cloud *c, const double *q, double *rho_M, hipStream_t s) {
-  hipLaunchKernelGGL(k_deposit, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->N, c->first,
-                     c->count, c->level, c->perm, q, c->P.L, rho_M);
+  if (c->P.kernel == APC_KERNEL_NGP)
+    hipLaunchKernelGGL(k_deposit, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->N,
+                       c->first, c->count, c->level, c->perm, q, c->P.L, rho_M);
+  else
+    hipLaunchKernelGGL(k_deposit_kern, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->N,
+                       c->P.kernel, c->P.max_depth, (const uint64_t *)c->code, c->level, c->first,
+                       c->count, c->crd, c->n + c->nb, c->sxyz, c->perm, q, c->P.lo[0],
+                       c->P.lo[1], c->P.lo[2], c->P.L, c->unit, rho_M);
   if (c->nb > 0)
     hipLaunchKernelGGL(k_bnd_copy, dim3(grid_for(c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
                        c->bowner, rho_M);

@@ -16,7 +16,10 @@ struct Op {
   const int32_t *idx;
   const double *w64;
   const float *w32;
-  const double *hs; // k = 2 density operator: x_i + hs_i (L x)_i
+  const double *hs; // k = 2 density operator: x_i + hs_i (L x)_i; hs_i < 0: an explicit
+                    // row x_i + sum_j dwx_ij (x_j - x_i) in CSR order (a kernel reaching
+                    // past a wall)
+  const double *dwx;
   int unit_diag;    // k = 4 density operator: x_i + (sum_j b_ij (x_j - x_i)) with its own weights
   const int8_t *rk; // level of a uniform row (2-ring, k = 2; 56-node, k = 4), else -1
   double tc[3];     // shell weights of the uniform 2-ring at h_c = 1
@@ -278,7 +281,16 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
 #undef APC_T4
 #undef APC_NB
   }
-  return op.hs ? xi + op.hs[row] * acc : (op.unit_diag ? xi + acc : acc);
+  if (op.hs) {
+    const double hv = op.hs[row];
+    if (hv < 0.0) {
+      double e = 0.0;
+      for (int32_t k = op.off[row]; k < op.off[row + 1]; k++) e += op.dwx[k] * (x[op.idx[k]] - xi);
+      return xi + e;
+    }
+    return xi + hv * acc;
+  }
+  return op.unit_diag ? xi + acc : acc;
 }
 // Offsets (x + 8 y + APC_BOX_SZ z, in box positions) of the 56 nodes of the uniform stencil:
 // r^2 = 1 .. 5 cells, each shell in the enumeration order (dx, then dy, then dz
@@ -375,6 +387,7 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   op.w64 = b4 ? c->bw64 : c->w64;
   op.w32 = b4 ? c->bw32 : c->w32;
   op.hs = (density && !b4) ? c->hscale : nullptr;
+  op.dwx = (density && !b4) ? c->dwx : nullptr;
   op.unit_diag = b4 ? 1 : 0;
   op.rk = c->P.order == 4 ? c->rkind4 : c->rkind;
   for (int k = 0; k < 3; k++) op.tc[k] = c->tmpl[k];
