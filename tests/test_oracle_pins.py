@@ -754,12 +754,14 @@ def _ball_cell_average(lo, hc, R, ns=16):
     return out
 
 
-def test_uniform_sphere_closed_form(oracle_mod):
+@pytest.mark.parametrize("order", [2, 4])
+def test_uniform_sphere_closed_form(oracle_mod, order):
     """Closed form of a uniformly charged ball (density rho0 for r < R) under
     Delta phi = rho: phi = rho0 r^2 / 6 - rho0 R^2 / 2 inside, -rho0 R^3 / (3 r)
     outside.  With g = phi on the boundary nodes and the cell-averaged density as
     rho_M (density solve, then Poisson solve), the nodal error falls at about
-    second order on refined lattices although the density is discontinuous."""
+    second order on refined lattices although the density is discontinuous
+    (k = 2 and k = 4)."""
     R, rho0 = 0.3, 2.5
 
     def exact(pos):
@@ -769,7 +771,7 @@ def test_uniform_sphere_closed_form(oracle_mod):
 
     res = []
     for depth in (3, 4, 5):
-        C = uniform_cloud(oracle_mod, depth)
+        C = uniform_cloud(oracle_mod, depth, order=order)
         nd, pos = C.nodes(), C.positions()
         hc = C.L / 2.0 ** nd["level"]
         avg = rho0 * _ball_cell_average(pos[:, :C.n] - hc / 2, hc, R)
@@ -780,8 +782,10 @@ def test_uniform_sphere_closed_form(oracle_mod):
         assert st["status"] == 0
         res.append((C.n, np.linalg.norm(phi[:C.n] - ex[:C.n]) / np.linalg.norm(ex[:C.n])))
     for (n1, e1), (n2, e2) in zip(res, res[1:]):
-        order = math.log(e1 / e2) / math.log((n2 / n1) ** (1 / 3))
-        assert 1.5 <= order <= 2.6, res
+        rate = math.log(e1 / e2) / math.log((n2 / n1) ** (1 / 3))
+        # k = 4 may do better than second order on these lattices (its rows are
+        # exact on quartics), but not better than its smooth-case order
+        assert 1.5 <= rate <= (2.6 if order == 2 else 4.2), res
     assert res[-1][1] < 3e-3, res
 
 
