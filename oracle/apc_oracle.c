@@ -215,6 +215,10 @@ struct apco_cloud {
   int32_t *r1off, *r1;
   int32_t *st_off, *st, *st_ring;
   int8_t *node_order; /* GFD order of each node's row: the cloud's k, or 2 (fallback) */
+  uint8_t *pyr;       /* irregular domain: state of every cell of levels 0 .. mask_level
+                         (0 inside Omega, 1 excluded, 2 mixed), level l at pyr_off[l],
+                         index x + 2^l (y + 2^l z) */
+  int64_t pyr_off[8];
 };
 
 static uint64_t morton(uint64_t x, uint64_t y, uint64_t z, int bits) {
@@ -243,6 +247,21 @@ static int64_t doff(const apco_params *P, int64_t a, int64_t b) {
     else if (d < -(S / 2)) d += S;
   }
   return d;
+}
+
+/* State of the level-l cell (ix, iy, iz) on an irregular domain: 0 inside Omega,
+   1 excluded, 2 partly excluded (levels below mask_level only). */
+static int cell_state(const apco_cloud *C, int l, int64_t ix, int64_t iy, int64_t iz) {
+  const int ml = C->P.mask_level;
+  if (ml <= 0) return 0;
+  if (l > ml) {
+    ix >>= (l - ml);
+    iy >>= (l - ml);
+    iz >>= (l - ml);
+    l = ml;
+  }
+  const int64_t s = (int64_t)1 << l;
+  return C->pyr[C->pyr_off[l] + ix + s * (iy + s * iz)];
 }
 
 static int cmp_kpair(const void *a, const void *b) {
@@ -338,6 +357,8 @@ static int64_t face_nb(const apco_cloud *C, int64_t i, int f) {
     t[d] = (t[d] + (1 << y->level)) % (1 << y->level);
   else if (t[d] < 0 || t[d] >= (1 << y->level))
     return -1;
+  /* irregular domain: a face onto an excluded cell is a wall */
+  if (cell_state(C, y->level, t[0], t[1], t[2]) == 1) return -1;
   int64_t cur = 0;
   while (C->cells[cur].child >= 0 && C->cells[cur].level < y->level) {
     int sh = y->level - C->cells[cur].level - 1;
@@ -495,6 +516,7 @@ void apco_destroy(apco_cloud *C) {
   free(C->st);
   free(C->st_ring);
   free(C->node_order);
+  free(C->pyr);
   free(C);
 }
 
@@ -514,7 +536,9 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
       P->m_cap > MAXM || P->m_cap < p + 1 || N < 1 || P->criterion_pow < 0 ||
       P->criterion_pow > 16 || !(P->tau_dom >= 0.0) || P->periodic < 0 || P->periodic > 1 ||
       (P->periodic && P->max_depth < 2) || P->kernel < APCO_KERNEL_NGP ||
-      P->kernel > APCO_KERNEL_TSC)
+      P->kernel > APCO_KERNEL_TSC || P->mask_level < 0 || P->mask_level > 6 ||
+      P->mask_level > P->max_depth ||
+      (P->mask_level > 0 && (!P->mask || P->periodic || P->kernel != APCO_KERNEL_NGP)))
     return APCO_EINVAL;
   apco_cloud *C = calloc(1, sizeof(apco_cloud));
   if (!C) return APCO_ENOMEM;
@@ -524,6 +548,45 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
   const int D = P->max_depth;
   apco_thresholds(P, C->T);
   C->unit = P->L / ldexp(1.0, D + 1);
+
+  /* Irregular domain: the state pyramid of the mask, level mask_level from the
+     mask, each coarser cell from its 8 children (0 all inside, 1 all excluded,
+     2 mixed).  Omega must keep at least one cell. */
+  const int ml = P->mask_level;
+  if (ml > 0) {
+    int64_t tot = 0;
+    for (int l = 0; l <= ml; l++) {
+      C->pyr_off[l] = tot;
+      tot += (int64_t)1 << (3 * l);
+    }
+    C->pyr = malloc((size_t)tot);
+    CHECK_ALLOC(C->pyr);
+    const int64_t sm = (int64_t)1 << ml;
+    int64_t inside = 0;
+    for (int64_t q = 0; q < sm * sm * sm; q++) {
+      C->pyr[C->pyr_off[ml] + q] = P->mask[q] ? 1 : 0;
+      inside += P->mask[q] ? 0 : 1;
+    }
+    if (inside == 0) {
+      apco_destroy(C);
+      return APCO_EINVAL;
+    }
+    for (int l = ml - 1; l >= 0; l--) {
+      const int64_t s = (int64_t)1 << l;
+      for (int64_t z = 0; z < s; z++)
+        for (int64_t y = 0; y < s; y++)
+          for (int64_t x = 0; x < s; x++) {
+            int n0 = 0, n1 = 0;
+            for (int c = 0; c < 8; c++) {
+              const int st = cell_state(C, l + 1, 2 * x + ((c >> 2) & 1), 2 * y + ((c >> 1) & 1),
+                                        2 * z + (c & 1));
+              n0 += st == 0;
+              n1 += st == 1;
+            }
+            C->pyr[C->pyr_off[l] + x + s * (y + s * z)] = n0 == 8 ? 0 : (n1 == 8 ? 1 : 2);
+          }
+    }
+  }
 
   /* Morton keys and sort (Sec. 4): stable by (key, original index) */
   kpair *kp = malloc((size_t)N * sizeof(kpair));
@@ -550,6 +613,11 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
       if (v > top) v = top;
       u[d] = v;
     }
+    if (ml > 0 && cell_state(C, D, u[0], u[1], u[2]) == 1) { /* in an excluded cell */
+      free(kp);
+      apco_destroy(C);
+      return APCO_EDOMAIN;
+    }
     kp[i].key = morton((uint64_t)u[0], (uint64_t)u[1], (uint64_t)u[2], D);
     kp[i].idx = i;
   }
@@ -574,10 +642,13 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
     return APCO_ENOMEM;
   }
   /* Step 2: traverse Q (children appended during the traversal are visited too);
-     open every cell violating the error-balance criterion, below max_depth. */
+     open every cell violating the error-balance criterion, below max_depth.  On an
+     irregular domain excluded cells are never opened, and every other cell of a
+     level below mask_level is (so no leaf straddles a wall). */
   for (int64_t i = 0; i < C->ncells; i++) {
     const ocell *c = &C->cells[i];
-    if (c->level < D && (double)c->count >= C->T[c->level])
+    const int st = cell_state(C, c->level, c->ix, c->iy, c->iz);
+    if (c->level < D && st != 1 && (c->level < ml || (double)c->count >= C->T[c->level]))
       if (open_cell(C, i, 1)) {
         apco_destroy(C);
         return APCO_ENOMEM;
@@ -592,6 +663,7 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
   for (int l = lq; l >= 1; l--) {
     for (int64_t i = 0; i < C->ncells; i++) {
       if (C->cells[i].child >= 0 || C->cells[i].level != l) continue;
+      if (cell_state(C, l, C->cells[i].ix, C->cells[i].iy, C->cells[i].iz) == 1) continue;
       for (int f = 0; f < 6; f++) {
         for (;;) {
           int64_t z = face_nb(C, i, f);
@@ -609,15 +681,19 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
     }
   }
 
-  /* Nodes: every leaf (node candidate), ordered by the Morton code of its
-     minimum corner at max_depth. */
-  int64_t n = C->ncells - C->nopened;
-  lpair *lp = malloc((size_t)n * sizeof(lpair));
+  /* Nodes: every leaf (node candidate) inside Omega, ordered by the Morton code of
+     its minimum corner at max_depth. */
+  int64_t n = 0;
+  for (int64_t i = 0; i < C->ncells; i++) {
+    const ocell *c = &C->cells[i];
+    n += c->child < 0 && cell_state(C, c->level, c->ix, c->iy, c->iz) != 1;
+  }
+  lpair *lp = malloc((size_t)(n > 0 ? n : 1) * sizeof(lpair));
   CHECK_ALLOC(lp);
   int64_t k = 0;
   for (int64_t i = 0; i < C->ncells; i++) {
     const ocell *c = &C->cells[i];
-    if (c->child >= 0) continue;
+    if (c->child >= 0 || cell_state(C, c->level, c->ix, c->iy, c->iz) == 1) continue;
     int sh = D - c->level;
     lp[k].code = morton((uint64_t)c->ix << sh, (uint64_t)c->iy << sh, (uint64_t)c->iz << sh, D);
     lp[k].cell = i;
@@ -646,14 +722,12 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
   free(lp);
 
   /* Boundary nodes (Sec. 4.3 "add additional nodes on the boundary"): read as one
-     node at the centre of every leaf face lying on the domain boundary. */
+     node at the centre of every leaf face lying on the domain boundary (a box face,
+     or on an irregular domain a face onto an excluded cell). */
   int64_t nb = 0;
   for (int64_t j = 0; j < n; j++) {
-    const ocell *c = &C->cells[C->node_cell[j]];
-    int32_t ii[3] = {c->ix, c->iy, c->iz};
     for (int f = 0; f < 6; f++) {
-      int d = f / 2;
-      int on = !P->periodic && ((f & 1) ? (ii[d] == (1 << c->level) - 1) : (ii[d] == 0));
+      int on = face_nb(C, C->node_cell[j], f) < 0;
       C->bidx[6 * j + f] = on ? (int32_t)(n + nb++) : -1;
     }
   }
@@ -675,7 +749,7 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
       if (b < 0) continue;
       int d = f / 2;
       for (int e = 0; e < 3; e++) C->crd[3 * b + e] = C->crd[3 * j + e];
-      C->crd[3 * b + d] = (f & 1) ? (1 << (D + 1)) : 0;
+      C->crd[3 * b + d] += (f & 1) ? sz : -sz; /* the centre of face f */
       C->bowner[b - n] = (int32_t)j;
       C->bface[b - n] = f;
     }

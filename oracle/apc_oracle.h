@@ -57,6 +57,16 @@ typedef struct {
                      (0, the node's own cell), APCO_KERNEL_CIC (1, the tent, support
                      |u| <= 1 per axis) or APCO_KERNEL_TSC (2, the quadratic B-spline,
                      |u| <= 3/2), u = (x - y) / h with h the node's cell edge */
+  int mask_level; /* irregular domain (0: none): Omega is the box minus the cells of
+                     the uniform level-mask_level grid that mask excludes (1 ..
+                     min(6, max_depth)); the walls are the box faces and the faces
+                     between included and excluded cells.  Cells of a level below
+                     mask_level are always opened unless wholly excluded, excluded
+                     cells never; leaves in excluded cells are not nodes; a node's
+                     face on a wall carries a boundary node at its centre.  Not with
+                     periodic or a CIC / TSC kernel. */
+  const uint8_t *mask; /* (2^mask_level)^3 bytes, index x + s (y + s z), s = 2^mask_level;
+                          nonzero: excluded.  Read during apco_build_cloud only. */
 } apco_params;
 
 #define APCO_KERNEL_NGP 0

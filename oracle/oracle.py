@@ -29,7 +29,7 @@ class _Params(ct.Structure):
                 ("c", ct.c_double), ("max_depth", ct.c_int), ("ring_min", ct.c_int),
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
                 ("criterion_pow", ct.c_int), ("tau_dom", ct.c_double), ("periodic", ct.c_int),
-                ("kernel", ct.c_int)]
+                ("kernel", ct.c_int), ("mask_level", ct.c_int), ("mask", ct.c_void_p)]
 
 
 class _Stats(ct.Structure):
@@ -97,7 +97,9 @@ def _check(rc, what):
 
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
                 ring_max=5, m_cap=None, poisson_c=1.0, criterion_pow=0, tau_dom=0.0, periodic=0,
-                kernel=0):
+                kernel=0, mask=None):
+    """mask: None, or a (s, s, s) boolean array over the cells of the uniform grid of
+    level log2(s), indexed [ix, iy, iz]; True excludes the cell from Omega."""
     P = _Params()
     P.lo[:] = lo
     P.L = L
@@ -112,6 +114,15 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     P.tau_dom = tau_dom
     P.periodic = int(periodic)
     P.kernel = int(kernel)
+    if mask is not None:
+        m = np.asarray(mask).astype(np.uint8)
+        s = m.shape[0]
+        ml = int(s).bit_length() - 1
+        assert m.shape == (s, s, s) and (1 << ml) == s
+        flat = np.ascontiguousarray(m.transpose(2, 1, 0)).ravel()  # x fastest
+        P.mask_level = ml
+        P.mask = flat.ctypes.data
+        P._mask_ref = flat  # kept alive with the parameters
     return P
 
 
