@@ -122,6 +122,21 @@ typedef struct {
                         node whose kernel reaches past a wall has a_0 < 1 (the kernel's
                         mass inside Omega) and odd and mixed moments: its density row
                         and rho_M are divided by a_0.  Batches take NGP only. */
+  int mask_level;     /* irregular domain (0, default: the whole box): Omega is the box
+                        minus the cells of the uniform level-mask_level grid (1 ..
+                        min(6, max_depth)) that `mask` excludes, its walls the box faces
+                        and the faces between included and excluded cells (a reading of
+                        the method's independence of the domain's shape, Sec. 5.1).
+                        Cells of a level below mask_level are opened unless wholly
+                        excluded, excluded cells never; leaves in excluded cells are not
+                        nodes; every node face on a wall carries a boundary node at its
+                        centre (Dirichlet data g as on the box).  A particle in an
+                        excluded cell is outside Omega (APC_EDOMAIN).  Not with periodic,
+                        a CIC / TSC kernel, batches or apc_step (whose push knows the
+                        box's walls only): APC_EINVAL. */
+  const uint8_t *mask; /* host array of (2^mask_level)^3 bytes, index x + s (y + s z),
+                          s = 2^mask_level; nonzero excludes the cell.  Read by
+                          apc_build_cloud only (not kept by the cloud). */
 } apc_params;
 
 #define APC_KERNEL_NGP 0

@@ -52,7 +52,8 @@ class Params(ct.Structure):
                 ("ring_max", ct.c_int), ("m_cap", ct.c_int), ("poisson_c", ct.c_double),
                 ("precision", ct.c_int), ("stage_cap", ct.c_int), ("criterion_pow", ct.c_int),
                 ("ring_lds", ct.c_int), ("ring_first_cap", ct.c_int), ("tau_dom", ct.c_double),
-                ("periodic", ct.c_int), ("kernel", ct.c_int)]
+                ("periodic", ct.c_int), ("kernel", ct.c_int), ("mask_level", ct.c_int),
+                ("mask", ct.c_void_p)]
 
 
 class Stats(ct.Structure):
@@ -167,7 +168,7 @@ def _check(rc, what):
 def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_min=None,
                 ring_max=5, m_cap=None, poisson_c=1.0, precision=APC_FP64,
                 stage_cap=0, criterion_pow=0, ring_lds=0, ring_first_cap=0,
-                tau_dom=0.0, periodic=0, kernel=0) -> Params:
+                tau_dom=0.0, periodic=0, kernel=0, mask=None) -> Params:
     p = Params()
     load_library().apc_default_params(ct.byref(p), order)
     p.lo[:] = lo
@@ -188,6 +189,18 @@ def make_params(order=2, c=0.35, max_depth=6, lo=(0.0, 0.0, 0.0), L=1.0, ring_mi
     p.tau_dom = tau_dom
     p.periodic = periodic
     p.kernel = kernel
+    if mask is not None:
+        # (s, s, s) boolean array over the level-log2(s) grid, indexed [ix, iy, iz];
+        # True excludes the cell.  Handed over with x fastest.
+        m = np.asarray(mask).astype(np.uint8)
+        s = m.shape[0]
+        ml = int(s).bit_length() - 1
+        if m.shape != (s, s, s) or (1 << ml) != s:
+            raise ValueError("mask must be a (2^l, 2^l, 2^l) array")
+        flat = np.ascontiguousarray(m.transpose(2, 1, 0)).ravel()
+        p.mask_level = ml
+        p.mask = flat.ctypes.data
+        p._mask_ref = flat  # alive as long as the parameters
     return p
 
 

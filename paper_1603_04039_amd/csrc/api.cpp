@@ -387,6 +387,7 @@ int apc_build_batch(const apc_params *p, int count, const double *const *xyz, co
   if (p->order != 2) return APC_EINVAL; // the union carries k = 2 operators only
   if (p->periodic) return APC_EINVAL;   // batches hold bounded domains only
   if (p->kernel != APC_KERNEL_NGP) return APC_EINVAL; // and the NGP deposit
+  if (p->mask_level != 0) return APC_EINVAL;           // on the whole box
   for (int c = 0; c < count; c++)
     if (!xyz[c] || N[c] < 1) return APC_EINVAL;
   return apc_build_batch_impl(p, count, xyz, N, stream, out);

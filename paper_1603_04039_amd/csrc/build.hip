@@ -19,10 +19,27 @@ struct Thr {
   double T[24];
 };
 
+// Irregular domain: the state of every cell of levels 0 .. ml in Morton order
+// (level l at off[l] + its key prefix): 0 inside Omega, 1 excluded, 2 mixed.
+// ml = 0: no mask, every cell inside.
+struct Mask {
+  const uint8_t *pyr;
+  int ml;
+  int64_t off[8];
+};
+__device__ __forceinline__ int mask_state(const Mask &M, uint64_t pre, int l) {
+  if (M.ml <= 0) return 0;
+  if (l > M.ml) {
+    pre >>= 3 * (l - M.ml);
+    l = M.ml;
+  }
+  return M.pyr[M.off[l] + (int64_t)pre];
+}
+
 // ---------------------------------------------------------------- keys
 __global__ void __launch_bounds__(APC_BLOCK)
     k_keys(const double *__restrict__ xyz, int64_t N, double lo0, double lo1, double lo2, double L,
-           double s, int D, uint64_t *__restrict__ keys, int32_t *__restrict__ vals,
+           double s, int D, Mask M, uint64_t *__restrict__ keys, int32_t *__restrict__ vals,
            int *__restrict__ err) {
   int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (i >= N) return;
@@ -40,8 +57,10 @@ __global__ void __launch_bounds__(APC_BLOCK)
     if (q > (double)top) q = (double)top;
     u[d] = (uint32_t)q;
   }
+  const uint64_t k = apc_morton(u[0], u[1], u[2]);
+  if (mask_state(M, k, D) == 1) e |= 2; // in an excluded cell: outside Omega
   if (e) atomicOr(err, e);
-  keys[i] = apc_morton(u[0], u[1], u[2]);
+  keys[i] = k;
   vals[i] = (int32_t)i;
 }
 
@@ -91,12 +110,13 @@ __global__ void __launch_bounds__(APC_BLOCK) k_sizes(const int32_t *flag, int64_
 // Replace every flagged cell by its 8 children (Morton child order keeps the list
 // sorted); each child's particle range is the sub-range of its parent carrying the
 // child's key prefix.  With `criterion`, a child is flagged for the next pass when
-// it lies above max_depth and holds N' >= T_l particles.
+// it lies above max_depth and holds N' >= T_l particles; on an irregular domain
+// excluded children never, other children of a level below the mask's always.
 __global__ void __launch_bounds__(APC_BLOCK)
     k_expand(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
              const int32_t *__restrict__ fst, const int32_t *__restrict__ cnt,
              const int32_t *__restrict__ flag, const int32_t *__restrict__ off, int64_t n,
-             const uint64_t *__restrict__ keys, int D, Thr thr, int criterion,
+             const uint64_t *__restrict__ keys, int D, Thr thr, Mask M, int criterion,
              uint64_t *__restrict__ opre, int32_t *__restrict__ olev, int32_t *__restrict__ ofst,
              int32_t *__restrict__ ocnt, int32_t *__restrict__ oflag) {
   int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
@@ -122,7 +142,9 @@ __global__ void __launch_bounds__(APC_BLOCK)
     olev[o + c] = l;
     ofst[o + c] = (int32_t)a;
     ocnt[o + c] = k;
-    oflag[o + c] = criterion ? (l < D && (double)k >= thr.T[l]) : 0;
+    oflag[o + c] = criterion ? (l < D && mask_state(M, cp, l) != 1 &&
+                                (l < M.ml || (double)k >= thr.T[l]))
+                             : 0;
     a = b;
   }
 }
@@ -144,12 +166,13 @@ __device__ inline void cell_index(uint64_t pre, uint32_t t[3]) {
 // corner of the same-level cell across it.
 __global__ void __launch_bounds__(APC_BLOCK)
     k_balance_mark(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
-                   const uint64_t *__restrict__ mc, int64_t n, int D, int periodic,
+                   const uint64_t *__restrict__ mc, int64_t n, int D, int periodic, Mask M,
                    int32_t *__restrict__ mark) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
   const int l = lev[y];
   if (l < 2) return;
+  if (mask_state(M, pre[y], l) == 1) return; // excluded leaves are not nodes
   uint32_t t0[3];
   cell_index(pre[y], t0);
   const int sh = D - l;
@@ -164,26 +187,35 @@ __global__ void __launch_bounds__(APC_BLOCK)
       if (t[d] == 0u && !periodic) continue;
       t[d] = (t[d] + side - 1u) & (side - 1u);
     }
+    if (mask_state(M, apc_morton(t[0], t[1], t[2]), l) == 1) continue; // a wall
     const uint64_t pc = apc_morton(t[0] << sh, t[1] << sh, t[2] << sh);
     const int64_t z = apc_last_le(mc, n, pc);
     if (lev[z] < l - 1) mark[z] = 1;
   }
 }
 
-// number of faces of each leaf lying on the domain boundary
+// Face f of leaf y lies on a wall: a face of the box (not periodic), or on an
+// irregular domain a face onto an excluded cell.
+__device__ inline bool wall_face(const Mask &M, const uint32_t t0[3], int l, int f, int periodic) {
+  const int d = f >> 1;
+  const uint32_t top = (1u << l) - 1u;
+  const bool box = (f & 1) ? (t0[d] == top) : (t0[d] == 0u);
+  if (box) return !periodic;
+  if (M.ml <= 0) return false;
+  uint32_t t[3] = {t0[0], t0[1], t0[2]};
+  t[d] = (f & 1) ? t[d] + 1u : t[d] - 1u;
+  return mask_state(M, apc_morton(t[0], t[1], t[2]), l) == 1;
+}
+
+// number of faces of each leaf lying on a wall
 __global__ void __launch_bounds__(APC_BLOCK)
-    k_bcount(const uint64_t *pre, const int32_t *lev, int64_t n, int periodic, int32_t *bc) {
+    k_bcount(const uint64_t *pre, const int32_t *lev, int64_t n, int periodic, Mask M, int32_t *bc) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
-  if (periodic) { // no boundary faces
-    bc[y] = 0;
-    return;
-  }
   uint32_t t[3];
   cell_index(pre[y], t);
-  const uint32_t top = (1u << lev[y]) - 1u;
   int k = 0;
-  for (int d = 0; d < 3; d++) k += (t[d] == 0u) + (t[d] == top);
+  for (int f = 0; f < 6; f++) k += wall_face(M, t, lev[y], f, periodic);
   bc[y] = k;
 }
 
@@ -192,7 +224,8 @@ __global__ void __launch_bounds__(APC_BLOCK)
 __global__ void __launch_bounds__(APC_BLOCK)
     k_nodes(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
             const int32_t *__restrict__ bstart, int64_t n, int64_t ntot, int D, int periodic,
-            int32_t *__restrict__ crd, int32_t *__restrict__ bowner, int32_t *__restrict__ bface) {
+            Mask M, int32_t *__restrict__ crd, int32_t *__restrict__ bowner,
+            int32_t *__restrict__ bface) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y == 0) crd[3 * ntot] = periodic ? (1 << (D + 1)) : 0; // the side S
   if (y >= n) return;
@@ -205,14 +238,12 @@ __global__ void __launch_bounds__(APC_BLOCK)
     c[d] = (int32_t)(2u * t[d] + 1u) * sz;
     crd[(int64_t)d * ntot + y] = c[d];
   }
-  const uint32_t top = (1u << l) - 1u;
   int64_t b = n + bstart[y];
   for (int f = 0; f < 6; f++) {
     const int d = f >> 1;
-    const bool on = !periodic && ((f & 1) ? (t[d] == top) : (t[d] == 0u));
-    if (!on) continue;
+    if (!wall_face(M, t, l, f, periodic)) continue;
     for (int e = 0; e < 3; e++) crd[(int64_t)e * ntot + b] = c[e];
-    crd[(int64_t)d * ntot + b] = (f & 1) ? (1 << (D + 1)) : 0;
+    crd[(int64_t)d * ntot + b] = c[d] + ((f & 1) ? sz : -sz); // the centre of face f
     bowner[b - n] = (int32_t)y;
     bface[b - n] = f;
     b++;
@@ -224,7 +255,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 __global__ void __launch_bounds__(APC_BLOCK)
     k_ring1(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
             const uint64_t *__restrict__ mc, const int32_t *__restrict__ bstart, int64_t n, int D,
-            int periodic, int32_t *__restrict__ r1cnt, int32_t *__restrict__ r1,
+            int periodic, Mask M, int32_t *__restrict__ r1cnt, int32_t *__restrict__ r1,
             int *__restrict__ err) {
   int64_t y = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (y >= n) return;
@@ -236,8 +267,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   int k = 0, kb = 0;
   for (int f = 0; f < 6; f++) {
     const int d = f >> 1;
-    const bool bnd = (f & 1) ? (t0[d] == top) : (t0[d] == 0u);
-    if (bnd && !periodic) {
+    if (wall_face(M, t0, l, f, periodic)) {
       out[k++] = (int32_t)(n + bstart[y] + kb++);
       continue;
     }
@@ -902,7 +932,8 @@ int dfree(T *&p, hipStream_t s) {
 }
 
 // flagged cells -> 8 children; returns the new list in `c`
-int expand(Cells &c, const uint64_t *keys, int D, const Thr &thr, int criterion, hipStream_t s) {
+int expand(Cells &c, const uint64_t *keys, int D, const Thr &thr, const Mask &M, int criterion,
+           hipStream_t s) {
   int32_t *sz = nullptr, *off = nullptr;
   APCCHK(dalloc(&sz, c.n, s));
   APCCHK(dalloc(&off, c.n, s));
@@ -917,7 +948,7 @@ int expand(Cells &c, const uint64_t *keys, int D, const Thr &thr, int criterion,
   Cells o;
   APCCHK(cells_alloc(o, m, s));
   hipLaunchKernelGGL(k_expand, dim3(grid_for(c.n)), dim3(APC_BLOCK), 0, s, c.pre, c.lev, c.fst,
-                     c.cnt, c.flag, off, c.n, keys, D, thr, criterion, o.pre, o.lev, o.fst, o.cnt,
+                     c.cnt, c.flag, off, c.n, keys, D, thr, M, criterion, o.pre, o.lev, o.fst, o.cnt,
                      o.flag);
   HIPCHK(hipGetLastError());
   APCCHK(dfree(sz, s));
@@ -925,6 +956,28 @@ int expand(Cells &c, const uint64_t *keys, int D, const Thr &thr, int criterion,
   APCCHK(cells_free(c, s));
   c = o;
   return APC_OK;
+}
+
+// flag[i] = 1 for the leaves inside Omega
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_inside(const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev, int64_t n, Mask M,
+             int32_t *__restrict__ flag) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i < n) flag[i] = mask_state(M, pre[i], lev[i]) != 1;
+}
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_keep_cells(const int32_t *__restrict__ flag, const int32_t *__restrict__ off, int64_t n,
+                 const uint64_t *__restrict__ pre, const int32_t *__restrict__ lev,
+                 const int32_t *__restrict__ fst, const int32_t *__restrict__ cnt,
+                 uint64_t *__restrict__ opre, int32_t *__restrict__ olev,
+                 int32_t *__restrict__ ofst, int32_t *__restrict__ ocnt) {
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n || !flag[i]) return;
+  const int64_t o = off[i];
+  opre[o] = pre[i];
+  olev[o] = lev[i];
+  ofst[o] = fst[i];
+  ocnt[o] = cnt[i];
 }
 
 int read_err(int *err, hipStream_t s, int *host) {
@@ -965,6 +1018,44 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   for (int l = 0; l < 24; l++) thr.T[l] = 0.0;
   for (int l = 0; l <= D; l++) thr.T[l] = c->T[l];
 
+  // irregular domain: the state pyramid of the mask (host), in Morton order
+  Mask M;
+  M.pyr = nullptr;
+  M.ml = P.mask_level;
+  uint8_t *pyr_dev = nullptr;
+  if (M.ml > 0) {
+    int64_t tot = 0;
+    for (int l = 0; l <= M.ml; l++) {
+      M.off[l] = tot;
+      tot += (int64_t)1 << (3 * l);
+    }
+    std::vector<uint8_t> h((size_t)tot);
+    const uint32_t sm = 1u << M.ml;
+    for (uint32_t z = 0; z < sm; z++)
+      for (uint32_t y = 0; y < sm; y++)
+        for (uint32_t x = 0; x < sm; x++)
+          h[(size_t)(M.off[M.ml] + (int64_t)apc_morton(x, y, z))] =
+              P.mask[x + (size_t)sm * (y + (size_t)sm * z)] ? 1 : 0;
+    for (int l = M.ml - 1; l >= 0; l--)
+      for (int64_t q = 0; q < ((int64_t)1 << (3 * l)); q++) {
+        int n0 = 0, n1 = 0;
+        for (int c8 = 0; c8 < 8; c8++) {
+          const uint8_t v = h[(size_t)(M.off[l + 1] + 8 * q + c8)];
+          n0 += v == 0;
+          n1 += v == 1;
+        }
+        h[(size_t)(M.off[l] + q)] = n0 == 8 ? 0 : (n1 == 8 ? 1 : 2);
+      }
+    if (h[0] == 1) {
+      apc_set_error_msg("the mask excludes the whole domain");
+      return APC_EINVAL;
+    }
+    APCCHK(dalloc(&pyr_dev, tot, s));
+    HIPCHK(hipMemcpyAsync(pyr_dev, h.data(), (size_t)tot, hipMemcpyHostToDevice, s));
+    HIPCHK(hipStreamSynchronize(s));
+    M.pyr = pyr_dev;
+  }
+
   // keys + sort
   uint64_t *keys = nullptr;
   int *err = nullptr;
@@ -974,7 +1065,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
   const double scale = ldexp(1.0, D) / P.L;
   hipLaunchKernelGGL(k_keys, dim3(grid_for(N)), dim3(APC_BLOCK), 0, s, xyz, N, P.lo[0], P.lo[1],
-                     P.lo[2], P.L, scale, D, keys, c->perm, err);
+                     P.lo[2], P.L, scale, D, M, keys, c->perm, err);
   HIPCHK(hipGetLastError());
   int herr = 0;
   APCCHK(read_err(err, s, &herr));
@@ -994,7 +1085,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   {
     const uint64_t z = 0;
     const int32_t zi = 0, n32 = (int32_t)N;
-    const int32_t op = (0 < D && (double)N >= c->T[0]) ? 1 : 0;
+    const int32_t op = (0 < D && (M.ml > 0 || (double)N >= c->T[0])) ? 1 : 0;
     HIPCHK(hipMemcpyAsync(cl.pre, &z, sizeof(z), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(cl.lev, &zi, sizeof(zi), hipMemcpyHostToDevice, s));
     HIPCHK(hipMemcpyAsync(cl.fst, &zi, sizeof(zi), hipMemcpyHostToDevice, s));
@@ -1008,7 +1099,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
     APCCHK(apc_sum_i32(cl.flag, cl.n, &nf, s));
     if (nf == 0) break;
     opened += nf;
-    APCCHK(expand(cl, keys, D, thr, 1, s));
+    APCCHK(expand(cl, keys, D, thr, M, 1, s));
   }
   // balance phase: mark, expand, repeat until no leaf is marked
   uint64_t *mc = nullptr;
@@ -1019,13 +1110,36 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
                        cl.n, D, mc);
     HIPCHK(hipMemsetAsync(cl.flag, 0, (size_t)cl.n * sizeof(int32_t), s));
     hipLaunchKernelGGL(k_balance_mark, dim3(grid_for(cl.n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev,
-                       mc, cl.n, D, P.periodic, cl.flag);
+                       mc, cl.n, D, P.periodic, M, cl.flag);
     HIPCHK(hipGetLastError());
     int64_t nm = 0;
     APCCHK(apc_sum_i32(cl.flag, cl.n, &nm, s));
     if (nm == 0) break;
     opened += nm;
-    APCCHK(expand(cl, keys, D, thr, 0, s));
+    APCCHK(expand(cl, keys, D, thr, M, 0, s));
+  }
+  if (M.ml > 0) { // the leaves inside Omega become the nodes
+    int32_t *off = nullptr;
+    APCCHK(dalloc(&off, cl.n, s));
+    hipLaunchKernelGGL(k_inside, dim3(grid_for(cl.n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev,
+                       cl.n, M, cl.flag);
+    APCCHK(apc_scan_i32(cl.flag, off, cl.n, s));
+    int32_t last[2];
+    HIPCHK(hipMemcpyAsync(&last[0], off + cl.n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipMemcpyAsync(&last[1], cl.flag + cl.n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
+    HIPCHK(hipStreamSynchronize(s));
+    Cells in;
+    APCCHK(cells_alloc(in, (int64_t)last[0] + last[1], s));
+    hipLaunchKernelGGL(k_keep_cells, dim3(grid_for(cl.n)), dim3(APC_BLOCK), 0, s, cl.flag, off,
+                       cl.n, cl.pre, cl.lev, cl.fst, cl.cnt, in.pre, in.lev, in.fst, in.cnt);
+    HIPCHK(hipGetLastError());
+    APCCHK(dfree(off, s));
+    APCCHK(cells_free(cl, s));
+    cl = in;
+    APCCHK(dfree(mc, s));
+    APCCHK(dalloc(&mc, cl.n, s));
+    hipLaunchKernelGGL(k_mincorner, dim3(grid_for(cl.n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev,
+                       cl.n, D, mc);
   }
   const int64_t n = cl.n;
   c->n = n;
@@ -1046,7 +1160,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   APCCHK(dalloc(&bcnt, n, s));
   APCCHK(dalloc(&bstart, n, s));
   hipLaunchKernelGGL(k_bcount, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, n,
-                     P.periodic, bcnt);
+                     P.periodic, M, bcnt);
   APCCHK(apc_scan_i32(bcnt, bstart, n, s));
   int32_t last[2];
   HIPCHK(hipMemcpyAsync(&last[0], bstart + n - 1, sizeof(int32_t), hipMemcpyDeviceToHost, s));
@@ -1059,7 +1173,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   HIPCHK(apc_dev_alloc((void **)&c->bowner, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
   HIPCHK(apc_dev_alloc((void **)&c->bface, (size_t)(nb > 0 ? nb : 1) * sizeof(int32_t)));
   hipLaunchKernelGGL(k_nodes, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, bstart, n,
-                     ntot, D, P.periodic, c->crd, c->bowner, c->bface);
+                     ntot, D, P.periodic, M, c->crd, c->bowner, c->bface);
   HIPCHK(hipGetLastError());
 
   // 1-ring adjacency
@@ -1068,7 +1182,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   APCCHK(dalloc(&r1, n * 24, s));
   HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
   hipLaunchKernelGGL(k_ring1, dim3(grid_for(n)), dim3(APC_BLOCK), 0, s, cl.pre, cl.lev, mc, bstart,
-                     n, D, P.periodic, r1cnt, r1, err);
+                     n, D, P.periodic, M, r1cnt, r1, err);
   HIPCHK(hipGetLastError());
   APCCHK(read_err(err, s, &herr));
   if (herr) { // an unbalanced face: cannot happen after the balance phase
@@ -1079,6 +1193,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   APCCHK(dfree(bstart, s));
   APCCHK(dfree(mc, s));
   APCCHK(cells_free(cl, s));
+  if (pyr_dev) APCCHK(dfree(pyr_dev, s));
 
   // stencils, ring by ring over the nodes still pending
   int32_t *stbuf = nullptr, *mnode = nullptr, *pending = nullptr;
@@ -1335,7 +1450,9 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
       !(p->precision == APC_FP64 || p->precision == APC_MIXED ||
         p->precision == APC_MIXED_F32ACC) || !std::isfinite(p->poisson_c) ||
       p->periodic < 0 || p->periodic > 1 || (p->periodic && p->max_depth < 2) ||
-      p->kernel < APC_KERNEL_NGP || p->kernel > APC_KERNEL_TSC)
+      p->kernel < APC_KERNEL_NGP || p->kernel > APC_KERNEL_TSC || p->mask_level < 0 ||
+      p->mask_level > 6 || p->mask_level > p->max_depth ||
+      (p->mask_level > 0 && (!p->mask || p->periodic || p->kernel != APC_KERNEL_NGP)))
     return APC_EINVAL;
   apc_cloud *c = new apc_cloud();
   c->P = *p;
@@ -1356,6 +1473,7 @@ int apc_build_impl(const apc_params *p, const double *xyz, int64_t N, hipStream_
   // across its faces
   if (p->periodic) c->T[0] = c->T[1] = 0.0;
   int rc = build_body(c, xyz, s);
+  c->P.mask = nullptr; // the caller's mask is read by the build only
   if (rc != APC_OK) {
     (void)hipStreamSynchronize(s);
     apc_free_cloud(c);

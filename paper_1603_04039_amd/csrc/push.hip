@@ -94,6 +94,7 @@ int apc_step_impl(const apc_params *p, double *xyz, double *vel, const double *q
       !(tol_density > 0.0) || maxit < 1 || !std::isfinite(kick) || !std::isfinite(dt))
     return APC_EINVAL;
   if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI) return APC_EINVAL;
+  if (p->mask_level != 0) return APC_EINVAL; // the push knows the box's walls only
   StepEvents ev;
   for (; ev.made < 7; ev.made++) HIPCHK(hipEventCreate(&ev.e[ev.made]));
   HIPCHK(hipEventRecord(ev.e[0], s));

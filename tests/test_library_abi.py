@@ -46,11 +46,12 @@ def test_error_strings_and_defaults(apc):
 def test_struct_layouts_match_header(apc):
     # apc_params: lo[3], L, order (+pad), c, max_depth, ring_min, ring_max, m_cap, poisson_c,
     # precision, stage_cap, criterion_pow, ring_lds, ring_first_cap (+pad), tau_dom,
-    # periodic, kernel
-    assert ct.sizeof(apc.Params) == 3 * 8 + 8 + 8 + 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8 + 8
+    # periodic, kernel, mask_level (+pad), mask
+    assert ct.sizeof(apc.Params) == 3 * 8 + 8 + 8 + 8 + 4 * 4 + 8 + 8 + 8 + 8 + 8 + 8 + 8 + 8
     assert apc.Params.criterion_pow.offset == 80 and apc.Params.ring_lds.offset == 84
     assert apc.Params.ring_first_cap.offset == 88 and apc.Params.tau_dom.offset == 96
     assert apc.Params.periodic.offset == 104 and apc.Params.kernel.offset == 108
+    assert apc.Params.mask_level.offset == 112 and apc.Params.mask.offset == 120
     assert ct.sizeof(apc.Stats) == 4 * 4 + 8 + 8 + 8 + 8 + 4 + 4 + 8 + 8 + 8
 
 
