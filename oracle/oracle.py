@@ -1,4 +1,5 @@
-"""ctypes binding of the C oracle (oracle/apc_oracle.c).  Test infrastructure only."""
+"""ctypes binding of the C oracle (oracle/apc_oracle.c, and oracle/apc_oracle2d.c for the
+two-dimensional variant).  Test infrastructure only."""
 from __future__ import annotations
 
 import ctypes as ct
@@ -9,6 +10,7 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "apc_oracle.c")
+_SRC2 = os.path.join(_HERE, "apc_oracle2d.c")
 _LIB = os.path.join(_HERE, "libapc_oracle.so")
 _lib = None
 
@@ -19,7 +21,7 @@ ERRORS = {0: "ok", -1: "invalid argument", -2: "out of memory", -4: "particle ou
 def build_oracle_lib() -> str:
     """Compile the oracle with gcc (plain -O2, no fast-math, no FMA contraction)."""
     cmd = ["gcc", "-O2", "-std=c11", "-fPIC", "-shared", "-ffp-contract=off",
-           "-o", _LIB, _SRC, "-lm"]
+           "-o", _LIB, _SRC, _SRC2, "-lm"]
     subprocess.run(cmd, check=True)
     return _LIB
 
@@ -41,7 +43,8 @@ def _load():
     global _lib
     if _lib is not None:
         return _lib
-    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < os.path.getmtime(_SRC):
+    if not os.path.exists(_LIB) or os.path.getmtime(_LIB) < max(os.path.getmtime(_SRC),
+                                                                 os.path.getmtime(_SRC2)):
         build_oracle_lib()
     lib = ct.CDLL(_LIB)
     P = ct.c_void_p
@@ -79,6 +82,21 @@ def _load():
     lib.apco_mlp_loss_grad.argtypes = [P, P, P, P, ct.c_int, P, P]
     lib.apco_mlp_forward.argtypes = [P, P, ct.c_int64, P]
     lib.apco_learned_m.argtypes = [P, P, P, ct.c_int, P, P]
+    lib.apco2_build_cloud.argtypes = [ct.POINTER(_Params), P, ct.c_int64, ct.POINTER(ct.c_void_p)]
+    lib.apco2_destroy.argtypes = [P]
+    lib.apco2_destroy.restype = None
+    lib.apco2_info.argtypes = [P] + [ct.POINTER(ct.c_int64)] * 4
+    lib.apco2_get_nodes.argtypes = [P] * 10
+    lib.apco2_node_coords.argtypes = [P, P]
+    lib.apco2_ring1.argtypes = [P, P, P, ct.c_int64]
+    lib.apco2_assemble.argtypes = [P, P, P]
+    lib.apco2_density_rows.argtypes = [P, P, P, P]
+    lib.apco2_deposit.argtypes = [P, P, P]
+    lib.apco2_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(_Stats)]
+    lib.apco2_poisson_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int,
+                                        ct.POINTER(_Stats)]
+    lib.apco2_node_derivs.argtypes = [P, P, P]
+    lib.apco2_interpolate.argtypes = [P, P, P, P, P]
     lib.apco_push.argtypes = [ct.POINTER(_Params), ct.c_int64, P, P, P, ct.c_double,
                               ct.c_double]
     _lib = lib
@@ -382,4 +400,119 @@ class OracleCloud:
         gp = np.zeros((3, self.N))
         _check(self.lib.apco_interpolate(self.h, _ptr(phi), _ptr(xyz), _ptr(pp), _ptr(gp)),
                "interpolate")
+        return pp, gp
+
+
+class OracleCloud2D:
+    """A two-dimensional oracle node cloud (quadtree, k = 2) from particles (2 x N
+    float64).  Parameters as for OracleCloud (lo and L of the square; m_cap
+    defaults to 8, the paper's 8 neighbours in two dimensions)."""
+
+    def __init__(self, xy: np.ndarray, **params):
+        self.lib = _load()
+        params.setdefault("m_cap", 8)
+        params.setdefault("ring_min", 2)
+        lo = params.pop("lo", (0.0, 0.0))
+        self.params = make_params(lo=(lo[0], lo[1], 0.0), **params)
+        self.xy = np.ascontiguousarray(xy, dtype=np.float64)
+        assert self.xy.ndim == 2 and self.xy.shape[0] == 2
+        self.N = self.xy.shape[1]
+        h = ct.c_void_p()
+        _check(self.lib.apco2_build_cloud(ct.byref(self.params), _ptr(self.xy), self.N,
+                                          ct.byref(h)), "build_cloud_2d")
+        self.h = h
+        v = [ct.c_int64() for _ in range(4)]
+        self.lib.apco2_info(self.h, *[ct.byref(x) for x in v])
+        self.n, self.nb, self.nnz, self.n_opened = [x.value for x in v]
+        self.L = self.params.L
+        self.lo = np.array(self.params.lo[:2])
+        self.max_depth = self.params.max_depth
+        self.unit = self.L / 2.0 ** (self.max_depth + 1)
+
+    def __del__(self):
+        if getattr(self, "h", None):
+            self.lib.apco2_destroy(self.h)
+            self.h = None
+
+    def nodes(self):
+        n, nb, nnz = self.n, self.nb, self.nnz
+        out = dict(perm=np.zeros(self.N, np.int64), code=np.zeros(n, np.uint64),
+                   level=np.zeros(n, np.int32), first=np.zeros(n, np.int64),
+                   count=np.zeros(n, np.int64), bowner=np.zeros(nb, np.int32),
+                   bface=np.zeros(nb, np.int32), st_off=np.zeros(n + 1, np.int32),
+                   st_idx=np.zeros(nnz, np.int32))
+        self.lib.apco2_get_nodes(self.h, *[_ptr(out[k]) for k in
+                                           ["perm", "code", "level", "first", "count", "bowner",
+                                            "bface", "st_off", "st_idx"]])
+        return out
+
+    def coords(self):
+        a = np.zeros((2, self.n + self.nb), np.int32)
+        self.lib.apco2_node_coords(self.h, _ptr(a))
+        return a
+
+    def positions(self):
+        return self.lo[:, None] + self.unit * self.coords().astype(np.float64)
+
+    def ring1(self):
+        off = np.zeros(self.n + 1, np.int32)
+        idx = np.zeros(8 * self.n + 4, np.int32)
+        _check(self.lib.apco2_ring1(self.h, _ptr(off), _ptr(idx), idx.size), "ring1_2d")
+        return off, idx[: off[-1]].copy()
+
+    def assemble(self):
+        w, d = np.zeros(self.nnz), np.zeros(self.n)
+        _check(self.lib.apco2_assemble(self.h, _ptr(w), _ptr(d)), "assemble_2d")
+        return w, d
+
+    def density_rows(self):
+        w, d, o = np.zeros(self.nnz), np.zeros(self.n), np.zeros(self.n, np.int8)
+        _check(self.lib.apco2_density_rows(self.h, _ptr(w), _ptr(d), _ptr(o)), "density_rows_2d")
+        return w, d, o
+
+    def deposit(self, q=None):
+        r = np.zeros(self.n + self.nb)
+        qq = None if q is None else np.ascontiguousarray(q, dtype=np.float64)
+        _check(self.lib.apco2_deposit(self.h, _ptr(qq), _ptr(r)), "deposit_2d")
+        return r
+
+    def density_solve(self, rho_M, tol=1e-12, maxit=10000):
+        rho_M = np.ascontiguousarray(rho_M, dtype=np.float64)
+        out = np.zeros(self.n + self.nb)
+        st = _Stats()
+        _check(self.lib.apco2_density_solve(self.h, _ptr(rho_M), _ptr(out), tol, maxit,
+                                            ct.byref(st)), "density_solve_2d")
+        return out, dict(iters=st.iters, status=st.status, rel_resid=st.rel_resid,
+                         rel_resid_true=st.rel_resid_true)
+
+    def poisson_solve(self, rho_t, g=None, tol=1e-12, maxit=20000, precond=1):
+        rho_t = np.ascontiguousarray(rho_t, dtype=np.float64)
+        gg = None if g is None else np.ascontiguousarray(g, dtype=np.float64)
+        out = np.zeros(self.n + self.nb)
+        st = _Stats()
+        _check(self.lib.apco2_poisson_solve(self.h, _ptr(rho_t), _ptr(gg), _ptr(out), tol, maxit,
+                                            precond, ct.byref(st)), "poisson_solve_2d")
+        return out, dict(iters=st.iters, status=st.status, rel_resid=st.rel_resid,
+                         rel_resid_true=st.rel_resid_true)
+
+    def apply_laplacian(self, f):
+        """sum_j w_ij (f_j - f_i) over each row (f over all n + nb nodes)."""
+        w, _ = self.assemble()
+        nd = self.nodes()
+        rows = np.repeat(np.arange(self.n), np.diff(nd["st_off"]))
+        f = np.asarray(f, dtype=np.float64)
+        return np.bincount(rows, weights=w * (f[nd["st_idx"]] - f[rows]), minlength=self.n)
+
+    def node_derivs(self, f):
+        f = np.ascontiguousarray(f, dtype=np.float64)
+        D = np.zeros((self.n, 5))
+        _check(self.lib.apco2_node_derivs(self.h, _ptr(f), _ptr(D)), "node_derivs_2d")
+        return D
+
+    def interpolate(self, phi, xy=None):
+        phi = np.ascontiguousarray(phi, dtype=np.float64)
+        xy = self.xy if xy is None else np.ascontiguousarray(xy, dtype=np.float64)
+        pp, gp = np.zeros(self.N), np.zeros((2, self.N))
+        _check(self.lib.apco2_interpolate(self.h, _ptr(phi), _ptr(xy), _ptr(pp), _ptr(gp)),
+               "interpolate_2d")
         return pp, gp

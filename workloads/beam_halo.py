@@ -138,3 +138,36 @@ def paper_beam_3d(N: int, seed: int):
         return out[:, :n]
 
     return np.ascontiguousarray(np.concatenate([truncated(N - nh, t1), truncated(nh, t2)], axis=1))
+
+
+# The 2-D beam with halo of Sec. 5.1 on Omega = [-1, 1]^2 (the paper prints tau1 = 0.02,
+# a2 = 1e-5, tau2 = 0.3, a1 = 396.1), read with 2 tau^2 in the exponents:
+# rho = a1 [exp(-|x|^2/(2 tau1^2)) + a2 exp(-|x|^2/(2 tau2^2))], under which a1 = 396.1
+# normalises the charge in Omega to 1 (with tau^2 it would be 0.50).
+BEAM2D = dict(tau1=0.02, tau2=0.3, a2=1e-5, a1=396.1)
+
+
+def paper_beam_2d(N: int, seed: int):
+    """N particles of the 2-D beam with halo, (2, N) float64: each from the halo with
+    the halo's share of the charge in Omega (binomial count), else from the core,
+    each an isotropic Gaussian of standard deviation tau truncated to Omega by
+    re-drawing.  Draw order: the halo count, the core block, the halo block."""
+    import math
+    t1, t2, a2 = BEAM2D["tau1"], BEAM2D["tau2"], BEAM2D["a2"]
+
+    def mass(t):  # integral of exp(-|x|^2 / (2 t^2)) over [-1, 1]^2
+        return (math.sqrt(2 * math.pi) * t * math.erf(1 / (math.sqrt(2) * t))) ** 2
+
+    rng = np.random.default_rng(seed)
+    p_halo = a2 * mass(t2) / (mass(t1) + a2 * mass(t2))
+    nh = int(rng.binomial(N, p_halo))
+
+    def truncated(n, t):
+        out = np.empty((2, 0))
+        while out.shape[1] < n:
+            x = t * rng.standard_normal((2, 2 * (n - out.shape[1]) + 16))
+            out = np.concatenate([out, x[:, np.all(np.abs(x) <= 1.0, axis=0)]], axis=1)
+        return out[:, :n]
+
+    return np.ascontiguousarray(np.concatenate([truncated(N - nh, t1), truncated(nh, t2)], axis=1))
+
