@@ -534,6 +534,69 @@ int apc_step(const apc_params *p, double *xyz, double *vel, const double *q, int
 int apc_set_diagnostics(apc_cloud *c, int flags);
 
 void apc_destroy(apc_cloud *c);
+
+/* ---- the two-dimensional variant (quadtree nodes, k = 2; Sec. 5.1) ----
+   The method of the calls above with one dimension fewer: Omega = [lo[0], lo[0] +
+   L] x [lo[1], lo[1] + L]; cells open when N' >= (c 2^l / L)^2 (eq.
+   errorbalance_implementation) below max_depth, then the 2:1 balance across the 4
+   faces; nodes are the leaves in Morton order (x bit above y), boundary nodes sit
+   at the centre of every leaf face on the boundary (faces 0..3 = -x, +x, -y, +y),
+   ordered by (owner, face); stencils by the quadrant criterion (Sec. 3.1: the two
+   nearest candidates of every closed quadrant, then the nearest remaining ones up
+   to m_cap, 8 being the paper's choice) from the R-ring (R = ring_min ..
+   ring_max), accepted when every closed quadrant holds a chosen node, m >= 6 and
+   the weighted normal equations have min/max Cholesky diagonal >= 1e-6; the
+   second-order fit has the 5 unknowns of x, y, x^2/2, xy, y^2/2; NGP deposit onto
+   the node's cell (area h^2); density rows b = (h_c^2 / 24) w with the stability
+   rule of the three-dimensional k = 2 rows; FP64 throughout.  Integer node
+   coordinates are in units of L 2^-(max_depth+1) from lo. */
+typedef struct apc2_cloud apc2_cloud;
+/* xy: device pointer, 2 x N float64 (SoA).  Reads lo[0..1], L, order (must be 2),
+   c, max_depth (1..20), ring_min, ring_max, m_cap (6..64), poisson_c and
+   criterion_pow.  Errors: APC_EINVAL (parameters, NaN), APC_EDOMAIN (a particle
+   outside Omega), APC_ESTENCIL (no acceptable stencil up to ring_max, or a ring
+   beyond 1024 nodes).  Synchronises. */
+int apc2_build_cloud(const apc_params *p, const double *xy, int64_t N, hipStream_t stream,
+                     apc2_cloud **out);
+int apc2_cloud_info(const apc2_cloud *c, int64_t *n, int64_t *nb, int64_t *nnz,
+                    int64_t *n_opened);
+/* Host arrays (each may be NULL): perm[N] (sorted position -> caller's index),
+   code/level/first/count [n], bowner/bface [nb], st_off [n+1], st_idx [nnz] (the
+   stencils in (r^2, index) order), ixy [2 x (n + nb)].  Synchronises. */
+int apc2_get_nodes(const apc2_cloud *c, int32_t *perm, uint64_t *code, int32_t *level,
+                   int32_t *first, int32_t *count, int32_t *bowner, int32_t *bface,
+                   int32_t *st_off, int32_t *st_idx, int32_t *ixy);
+/* Laplacian and density rows of every node (Sec. 3.1, eq. density_linear_system).
+   APC_ESTENCIL if a stencil lost rank.  Synchronises. */
+int apc2_assemble(apc2_cloud *c, hipStream_t stream);
+/* Host copies (each may be NULL): Laplacian w [nnz] (difference form) and diagonal
+   [n]; density rows bw [nnz], diagonal [n], order [n] (2, or 0 for the identity
+   row).  APC_EINVAL before apc2_assemble.  Synchronises. */
+int apc2_get_operator(const apc2_cloud *c, double *w_host, double *diag_host, double *bw_host,
+                      double *bdiag_host, int8_t *order_host);
+/* rho_M [n + nb] (device): the charge in each node's cell over h^2 (q: device
+   array of N charges in the caller's order, or NULL for 1/N each); boundary nodes
+   take their owner's value.  Does not synchronise. */
+int apc2_deposit(apc2_cloud *c, const double *q, double *rho_M, hipStream_t stream);
+/* B rho~ = rho_M (eq. density_linear_system), plain BiCGSTAB to tol; rho_t [n + nb]
+   (boundary values copied).  Returns APC_OK, APC_ENOCONV, or an error.
+   Synchronises. */
+int apc2_density_solve(apc2_cloud *c, const double *rho_M, double *rho_t, double tol, int maxit,
+                       apc_stats *st, hipStream_t stream);
+/* Delta phi = poisson_c rho~ (eq. Poisson) with phi = g on the boundary nodes (g:
+   device [nb] or NULL for 0); precond APC_PRECOND_NONE or APC_PRECOND_JACOBI.
+   phi [n + nb].  Synchronises. */
+int apc2_solve(apc2_cloud *c, const double *rho_t, const double *g, double *phi, double tol,
+               int maxit, int precond, apc_stats *st, hipStream_t stream);
+/* Derivatives of each node's fitted quadratic, D [n x 5] (device): phi_x, phi_y,
+   phi_xx, phi_xy, phi_yy.  Does not synchronise. */
+int apc2_node_derivs(apc2_cloud *c, const double *f, double *D, hipStream_t stream);
+/* Taylor interpolation (Sec. 3.2 step 3) of phi [n + nb] to the particles, in the
+   caller's order: phi_p [N] and grad_p [2 x N] (device).  Does not synchronise. */
+int apc2_interpolate_force(apc2_cloud *c, const double *phi, double *phi_p, double *grad_p,
+                           hipStream_t stream);
+void apc2_destroy(apc2_cloud *c);
+
 const char *apc_strerror(int code);
 /* Text of the last HIP error seen by the calling thread (empty if none). */
 const char *apc_last_error(void);

@@ -37,7 +37,10 @@ EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_n
            "apc_batch_configure", "apc_batch_tune", "apc_batch_assemble", "apc_batch_deposit",
            "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_pipeline",
            "apc_batch_destroy", "apc_push",
-           "apc_step", "apc_set_diagnostics", "apc_destroy", "apc_strerror", "apc_last_error"]
+           "apc_step", "apc_set_diagnostics", "apc_destroy", "apc_strerror", "apc_last_error",
+           "apc2_build_cloud", "apc2_cloud_info", "apc2_get_nodes", "apc2_assemble",
+           "apc2_get_operator", "apc2_deposit", "apc2_density_solve", "apc2_solve",
+           "apc2_node_derivs", "apc2_interpolate_force", "apc2_destroy"]
 
 
 class ApcError(RuntimeError):
@@ -143,6 +146,18 @@ def load_library(path: str = LIB_PATH):
     lib.apc_set_diagnostics.argtypes = [P, ct.c_int]
     lib.apc_destroy.argtypes = [P]
     lib.apc_destroy.restype = None
+    lib.apc2_build_cloud.argtypes = [ct.POINTER(Params), P, I64, P, ct.POINTER(P)]
+    lib.apc2_cloud_info.argtypes = [P] + [ct.POINTER(I64)] * 4
+    lib.apc2_get_nodes.argtypes = [P] * 11
+    lib.apc2_assemble.argtypes = [P, P]
+    lib.apc2_get_operator.argtypes = [P] * 6
+    lib.apc2_deposit.argtypes = [P, P, P, P]
+    lib.apc2_density_solve.argtypes = [P, P, P, ct.c_double, ct.c_int, ct.POINTER(Stats), P]
+    lib.apc2_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, ct.POINTER(Stats), P]
+    lib.apc2_node_derivs.argtypes = [P, P, P, P]
+    lib.apc2_interpolate_force.argtypes = [P, P, P, P, P]
+    lib.apc2_destroy.argtypes = [P]
+    lib.apc2_destroy.restype = None
     lib.apc_strerror.argtypes = [ct.c_int]
     lib.apc_strerror.restype = ct.c_char_p
     lib.apc_last_error.argtypes = []
@@ -649,3 +664,102 @@ def solve(cloud: Cloud, rho_t, g=None, **kw):
 
 def interpolate_force(cloud: Cloud, phi, stream=None):
     return cloud.interpolate_force(phi, stream)
+
+
+class Cloud2D:
+    """A two-dimensional node cloud (quadtree, k = 2) built on the GPU from particles
+    xy (2 x N float64 CUDA tensor).  params as for make_params (lo of the square as
+    a pair; m_cap defaults to 8, the paper's 8 neighbours in two dimensions)."""
+
+    def __init__(self, xy, stream=None, **params):
+        import torch
+        self.lib = load_library()
+        params.setdefault("m_cap", 8)
+        params.setdefault("ring_min", 2)
+        lo = params.pop("lo", (0.0, 0.0))
+        self.params = make_params(lo=(lo[0], lo[1], 0.0), **params)
+        if not (isinstance(xy, torch.Tensor) and xy.dim() == 2 and xy.shape[0] == 2):
+            raise ValueError("expected a 2 x N tensor")
+        self.N = xy.shape[1]
+        h = ct.c_void_p()
+        _check(self.lib.apc2_build_cloud(ct.byref(self.params), _dptr(xy, torch.float64), self.N,
+                                         _stream(stream), ct.byref(h)), "apc2_build_cloud")
+        self.h = h
+        v = [ct.c_int64() for _ in range(4)]
+        self.lib.apc2_cloud_info(self.h, *[ct.byref(x) for x in v])
+        self.n, self.nb, self.nnz, self.n_opened = [x.value for x in v]
+
+    def close(self):
+        if getattr(self, "h", None):
+            self.lib.apc2_destroy(self.h)
+            self.h = None
+
+    def __del__(self):
+        self.close()
+
+    def nodes(self):
+        n, nb, nnz, N = self.n, self.nb, self.nnz, self.N
+        out = dict(perm=np.zeros(N, np.int32), code=np.zeros(n, np.uint64),
+                   level=np.zeros(n, np.int32), first=np.zeros(n, np.int32),
+                   count=np.zeros(n, np.int32), bowner=np.zeros(nb, np.int32),
+                   bface=np.zeros(nb, np.int32), st_off=np.zeros(n + 1, np.int32),
+                   st_idx=np.zeros(nnz, np.int32), ixy=np.zeros((2, n + nb), np.int32))
+        _check(self.lib.apc2_get_nodes(self.h, *[out[k].ctypes.data for k in
+                                                 ["perm", "code", "level", "first", "count",
+                                                  "bowner", "bface", "st_off", "st_idx", "ixy"]]),
+               "apc2_get_nodes")
+        return out
+
+    def assemble(self, stream=None):
+        _check(self.lib.apc2_assemble(self.h, _stream(stream)), "apc2_assemble")
+
+    def operator(self):
+        """(w, diag, bw, bdiag, order) on the host."""
+        w, d = np.zeros(self.nnz), np.zeros(self.n)
+        bw, bd, o = np.zeros(self.nnz), np.zeros(self.n), np.zeros(self.n, np.int8)
+        _check(self.lib.apc2_get_operator(self.h, w.ctypes.data, d.ctypes.data, bw.ctypes.data,
+                                          bd.ctypes.data, o.ctypes.data), "apc2_get_operator")
+        return w, d, bw, bd, o
+
+    def deposit(self, q=None, stream=None):
+        import torch
+        rho = torch.empty(self.n + self.nb, dtype=torch.float64, device="cuda")
+        _check(self.lib.apc2_deposit(self.h, _dptr(q, torch.float64, self.N), _dptr(rho),
+                                     _stream(stream)), "apc2_deposit")
+        return rho
+
+    def density_solve(self, rho_M, tol=1e-12, maxit=1000, stream=None):
+        import torch
+        out = torch.empty(self.n + self.nb, dtype=torch.float64, device="cuda")
+        st = Stats()
+        rc = _check(self.lib.apc2_density_solve(self.h, _dptr(rho_M, torch.float64, self.n + self.nb),
+                                                _dptr(out), tol, maxit, ct.byref(st),
+                                                _stream(stream)), "apc2_density_solve")
+        return out, dict(st.as_dict(), rc=rc)
+
+    def solve(self, rho_t, g=None, tol=1e-10, maxit=20000, precond=APC_PRECOND_JACOBI,
+              stream=None):
+        import torch
+        phi = torch.empty(self.n + self.nb, dtype=torch.float64, device="cuda")
+        st = Stats()
+        rc = _check(self.lib.apc2_solve(self.h, _dptr(rho_t, torch.float64, self.n),
+                                        _dptr(g, torch.float64, self.nb), _dptr(phi), tol, maxit,
+                                        precond, ct.byref(st), _stream(stream)), "apc2_solve")
+        return phi, dict(st.as_dict(), rc=rc)
+
+    def node_derivs(self, f, stream=None):
+        import torch
+        D = torch.empty((self.n, 5), dtype=torch.float64, device="cuda")
+        _check(self.lib.apc2_node_derivs(self.h, _dptr(f, torch.float64, self.n + self.nb),
+                                         _dptr(D), _stream(stream)), "apc2_node_derivs")
+        return D
+
+    def interpolate_force(self, phi, stream=None):
+        import torch
+        pp = torch.empty(self.N, dtype=torch.float64, device="cuda")
+        gp = torch.empty((2, self.N), dtype=torch.float64, device="cuda")
+        _check(self.lib.apc2_interpolate_force(self.h, _dptr(phi, torch.float64, self.n + self.nb),
+                                               _dptr(pp), _dptr(gp), _stream(stream)),
+               "apc2_interpolate_force")
+        return pp, gp
+

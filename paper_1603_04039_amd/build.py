@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libapcloud.so")
 SOURCES = ["primitives.hip", "build.hip", "gfd.hip", "gfd4.hip", "sell.hip", "solve.hip",
-           "learned.hip", "batch.hip", "push.hip", "noalloc.hip", "api.cpp"]
+           "learned.hip", "batch.hip", "push.hip", "noalloc.hip", "quad2d.hip", "api.cpp"]
 
 
 def build_library(verbose: bool = False, jobs: int = 0) -> str:

@@ -12,7 +12,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _declared():
     src = open(os.path.join(ROOT, "include", "apcloud.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(apc_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(apc2?_[a-z_0-9]+)\s*\(", src)))
 
 
 @pytest.fixture(scope="module")
