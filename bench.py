@@ -456,6 +456,54 @@ def paper_beam_bench(apc, torch, cs=(1.0, 0.3, 0.1)):
                 clouds=out)
 
 
+# Running times of the paper's 2-D beam (Sec. 5.1, Figure stack; its CPU, unnamed), N = 1e6:
+# nodes and the sum of the seven phases in seconds
+PAPER_2D_STACK = [(1888, 1.044), (4420, 1.251), (11190, 2.036)]
+
+
+def paper_beam2d_bench(apc, torch, cs=(0.3, 0.1, 0.03)):
+    """The paper's 2-D beam with halo (1e6 particles in [-1, 1]^2) through the 2-D
+    path, FP64: build, assembly, deposit, density solve to 1e-12, Poisson solve to
+    1e-10 with Jacobi, interpolation; wall time per phase of the second run."""
+    from workloads import paper_beam_2d
+    xy = torch.from_numpy(paper_beam_2d(1_000_000, seed=1)).cuda()
+    out = []
+    for c in cs:
+        kw = dict(order=2, c=c, max_depth=12, lo=(-1.0, -1.0), L=2.0)
+        for _ in range(2):  # the second run is reported
+            t = {}
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            G = apc.Cloud2D(xy, **kw)
+            torch.cuda.synchronize()
+            t["build"] = time.perf_counter()
+            G.assemble()
+            torch.cuda.synchronize()
+            t["assemble"] = time.perf_counter()
+            rho_M = G.deposit()
+            rho_t, sd = G.density_solve(rho_M, tol=1e-12)
+            torch.cuda.synchronize()
+            t["deposit"] = time.perf_counter()
+            phi, st = G.solve(rho_t[:G.n].contiguous(), tol=1e-10)
+            torch.cuda.synchronize()
+            t["solve"] = time.perf_counter()
+            G.interpolate_force(phi)
+            torch.cuda.synchronize()
+            t["interpolate"] = time.perf_counter()
+            ms, prev = {}, t0
+            for k in ("build", "assemble", "deposit", "solve", "interpolate"):
+                ms[k] = round((t[k] - prev) * 1e3, 3)
+                prev = t[k]
+            n = G.n
+            G.close()
+        near = min(PAPER_2D_STACK, key=lambda r: abs(r[0] - n) / r[0])
+        out.append(dict(c=c, nodes=n, iters=st["iters"], density_iters=sd["iters"], phases_ms=ms,
+                        wall_ms=round(sum(ms.values()), 3),
+                        paper_nearest=dict(nodes=near[0], s=near[1])))
+    return dict(workload="2-D Gaussian beam with halo of Sec. 5.1, 1e6 particles, FP64",
+                clouds=out)
+
+
 def cpu_model():
     try:
         for line in open("/proc/cpuinfo"):
@@ -663,10 +711,13 @@ def main():
         batch = batch_bench(apc, torch, 3, args.tol)
         log(f"batch: {batch}")
 
-    pbeam = None
+    pbeam = pbeam2 = None
     if not args.no_paper_beam:
         log("paper's 3-D beam with halo")
         pbeam = paper_beam_bench(apc, torch)
+        log("paper's 2-D beam with halo")
+        pbeam2 = paper_beam2d_bench(apc, torch)
+        log(f"2-D beam: {pbeam2}")
 
     probes = None
     if not args.no_probes:
@@ -723,6 +774,8 @@ def main():
         out["batch"] = batch
     if pbeam is not None:
         out["paper_beam3d"] = pbeam
+    if pbeam2 is not None:
+        out["paper_beam2d"] = pbeam2
     if probes is not None:
         out["probes"] = probes
     print(json.dumps(out), flush=True)
