@@ -86,7 +86,8 @@ typedef struct {
   int criterion_pow; /* exponent e of the criterion thresholds T_l = (c 2^l / L)^e:
                         0 = 2k - 2 (eq. errorbalance_implementation, the default);
                         4 with k = 2 is the balance of the supraconvergent
-                        second-order error bound (Sec. 3.3), h = c N'^(-1/4);
+                        second-order error bound (Sec. 3.3; its optimal h, Sec. 3.4),
+                        h = c N'^(-1/4);
                         1..16 accepted */
   int ring_lds;      /* order-2 stencil search (performance only, same stencils bit
                         for bit): 0 = default, rings of up to 63 candidates with one

@@ -285,7 +285,8 @@ int apco_thresholds(const apco_params *P, double *T) {
      h = L 2^-l (cell edge, as in the worked example of Sec. 4.3) is N' < T_l;
      a cell is opened when N' >= T_l.  Evaluated as t = (c * 2^l) / L and then
      repeated multiplication from 1.0.  For k = 2 the supraconvergent bound of
-     Sec. 3.3 balances with h ~ N'^(-1/4) instead: exponent 4 (criterion_pow). */
+     Sec. 3.3, with the optimal h of Sec. 3.4, balances with h ~ N'^(-1/4) instead:
+     exponent 4 (criterion_pow). */
   const int pw = P->criterion_pow > 0 ? P->criterion_pow : 2 * P->order - 2;
   for (int l = 0; l <= P->max_depth; l++) {
     double t = (P->c * ldexp(1.0, l)) / P->L;

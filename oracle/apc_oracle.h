@@ -42,8 +42,8 @@ typedef struct {
   double poisson_c; /* Delta phi = c rho (eq. Poisson) */
   int criterion_pow; /* exponent e of T_l = (c 2^l / L)^e: 0 = 2k - 2 (eq.
                         errorbalance_implementation); 4 with k = 2 is the balance
-                        of the supraconvergent second-order error bound (Sec. 3.3),
-                        h = c N'^(-1/4) */
+                        of the supraconvergent second-order error bound (Sec. 3.3;
+                        its optimal h, Sec. 3.4), h = c N'^(-1/4) */
   double tau_dom; /* stability bound of order-4 Laplacian rows: accepted when the
                      diagonal is negative and sum_j |w_j| <= tau_dom |diag|;
                      0 = the default 10 */
