@@ -246,8 +246,7 @@ int apc_operator_info(const apc_cloud *c, int64_t *n_uniform, int64_t *nnz_gener
 /* Boxed slices of the operator layout (k = 4; 0 at k = 2): 64-row slices that are
    one Morton-aligned 4 x 4 x 4 block of same-level rows with the uniform 56-node
    stencil; the operator kernels address their neighbours through the block's
-   8 x 8 x 8 box of node ids (540 int32 per slice: the 512 cells, laid out with
-   padding) and read no per-entry column
+   8 x 8 x 8 box of node ids (512 int32 per slice) and read no per-entry column
    index.  *n_boxed receives their count.  APC_EINVAL on NULL arguments. */
 int apc_operator_boxes(const apc_cloud *c, int64_t *n_boxed);
 
