@@ -34,7 +34,7 @@
 // box of a boxed slice: cell (x, y, z) of the 8 x 8 x 8 box at x + 8 y + 64 z;
 // APC_BOX_N positions.  (A z stride of 68, 4 mod 32, halves the LDS bank conflicts
 // of the neighbour reads but ran slower: 443 against 423 us per apply on the 1e8
-// k = 4 cloud, the extra box positions cost more than the conflicts.)
+// k = 4 cloud, and strides of 66 and 68 staged in one batch still ran 1.5% slower.)
 #define APC_BOX_SZ 64
 #define APC_BOX_N (7 + 8 * 7 + APC_BOX_SZ * 7 + 1)
 #define APC_TAU_FP32 0.1  // mixed modes: FP32 fit kept when min|R_ii| / max|R_ii| >= this
