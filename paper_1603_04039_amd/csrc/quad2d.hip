@@ -4,7 +4,8 @@
 // 5 unknowns, NGP deposit and density rows (Sec. 3.2), Poisson rows, BiCGSTAB,
 // derivatives and Taylor interpolation.  Clouds of this variant are small (the
 // paper's reach 1e4 - 1e5 nodes), so the kernels are one thread per node or
-// particle and the solver keeps its scalars on the host.
+// particle, and the solver keeps its scalars on the device (one read of the
+// state per chunk of iterations).
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -741,6 +742,193 @@ __global__ void __launch_bounds__(APC_BLOCK)
   else if (i < n + nb) out[i] = bval ? bval[i - n] : 0.0;
 }
 
+// ---- BiCGSTAB with its scalars on the device: each step is a kernel that returns
+// at once when the solve has stopped, so the host launches iterations in chunks
+// and reads the state once per chunk.  done: 0 running, 1 recursive residual
+// below tol (or omega = 0), 2 breakdown (rho or (rh, v) zero or not finite),
+// 3 iteration limit.
+struct Scal2 {
+  double rho, alpha, omega, beta, bnorm, tol, rnorm;
+  int it, maxit, done;
+};
+constexpr unsigned G2 = 1024; // blocks of the reducing kernels (partials per value)
+
+template <int K>
+__device__ __forceinline__ void q_partials(double (&v)[K], double *part) {
+  __shared__ double sh[K][APC_BLOCK / 64];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double x = v[k];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) x += __shfl_xor(x, o, 64);
+    if ((threadIdx.x & 63) == 0) sh[k][threadIdx.x >> 6] = x;
+  }
+  __syncthreads();
+  if (threadIdx.x < K) {
+    double x = 0.0;
+    for (int w = 0; w < APC_BLOCK / 64; w++) x += sh[threadIdx.x][w];
+    part[threadIdx.x * G2 + blockIdx.x] = x;
+  }
+}
+template <int K>
+__device__ __forceinline__ void q_fin(const double *part, unsigned G, double (&out)[K]) {
+  __shared__ double sh[K][APC_BLOCK];
+#pragma unroll
+  for (int k = 0; k < K; k++) {
+    double x = 0.0;
+    for (unsigned b = threadIdx.x; b < G; b += APC_BLOCK) x += part[k * G2 + b];
+    sh[k][threadIdx.x] = x;
+  }
+  __syncthreads();
+  for (int h = APC_BLOCK / 2; h > 0; h >>= 1) {
+    if ((int)threadIdx.x < h)
+#pragma unroll
+      for (int k = 0; k < K; k++) sh[k][threadIdx.x] += sh[k][threadIdx.x + h];
+    __syncthreads();
+  }
+#pragma unroll
+  for (int k = 0; k < K; k++) out[k] = sh[k][0];
+}
+
+// partials of (a, b) over n
+__global__ void __launch_bounds__(APC_BLOCK)
+    q_dotp(int64_t n, const double *__restrict__ a, const double *__restrict__ b, double *part) {
+  double v[1] = {0.0};
+  for (int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * APC_BLOCK)
+    v[0] += a[i] * b[i];
+  q_partials<1>(v, part);
+}
+// (re)start from r (rh = r, p = v = 0 before this): rho = (r, r); first call sets
+// the norm of b from the same sum (r = b there)
+__global__ void __launch_bounds__(APC_BLOCK)
+    q_fin_start(const double *part, unsigned G, Scal2 *sc, double tol, int maxit, int first) {
+  double o[1];
+  q_fin<1>(part, G, o);
+  if (threadIdx.x == 0) {
+    if (first) {
+      sc->bnorm = sqrt(o[0]);
+      sc->tol = tol;
+      sc->maxit = maxit;
+      sc->it = 0;
+    }
+    sc->rho = o[0];
+    sc->alpha = sc->omega = 1.0;
+    sc->beta = 0.0;
+    sc->rnorm = sqrt(o[0]);
+    sc->done = (o[0] == 0.0 || !isfinite(o[0])) ? 2 : (sc->it >= sc->maxit ? 3 : 0);
+  }
+}
+// p = r + beta (p - omega v); ph = dinv p (when scaled)
+__global__ void __launch_bounds__(APC_BLOCK)
+    q_upd_p(int64_t n, const double *__restrict__ r, double *__restrict__ p,
+            const double *__restrict__ v, const double *__restrict__ dinv, double *__restrict__ ph,
+            const Scal2 *sc) {
+  if (sc->done) return;
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const double pi = r[i] + sc->beta * (p[i] - sc->omega * v[i]);
+  p[i] = pi;
+  if (dinv) ph[i] = pi * dinv[i];
+}
+// y = A x and partials (a, y) [, (y, y)]
+template <int K>
+__global__ void __launch_bounds__(APC_BLOCK)
+    q_spmv_dot(int64_t n, const int32_t *__restrict__ st_off, const int32_t *__restrict__ st_idx,
+               const double *__restrict__ w, const double *__restrict__ hs,
+               const double *__restrict__ x, double *__restrict__ y, const double *__restrict__ a,
+               double *part, const Scal2 *sc) {
+  if (sc->done) return;
+  double v[K];
+#pragma unroll
+  for (int k = 0; k < K; k++) v[k] = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * APC_BLOCK) {
+    const double xi = x[i];
+    double acc = 0.0;
+    for (int32_t e = st_off[i]; e < st_off[i + 1]; e++) acc += w[e] * (x[st_idx[e]] - xi);
+    const double yi = hs ? xi + hs[i] * acc : acc;
+    y[i] = yi;
+    v[0] += a[i] * yi;
+    if (K > 1) v[K - 1] += yi * yi;
+  }
+  q_partials<K>(v, part);
+}
+// alpha = rho / (rh, v)
+__global__ void __launch_bounds__(APC_BLOCK) q_fin_alpha(const double *part, unsigned G, Scal2 *sc) {
+  if (sc->done) return;
+  double o[1];
+  q_fin<1>(part, G, o);
+  if (threadIdx.x == 0) {
+    const double al = sc->rho / o[0];
+    if (o[0] == 0.0 || !isfinite(al)) {
+      sc->done = 2;
+      sc->it += 1; // the iteration that broke down counts
+    } else {
+      sc->alpha = al;
+    }
+  }
+}
+// s = r - alpha v; sh = dinv s (when scaled)
+__global__ void __launch_bounds__(APC_BLOCK)
+    q_upd_s(int64_t n, const double *__restrict__ r, const double *__restrict__ v,
+            double *__restrict__ sv, const double *__restrict__ dinv, double *__restrict__ sh,
+            const Scal2 *sc) {
+  if (sc->done) return;
+  const int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (i >= n) return;
+  const double si = r[i] - sc->alpha * v[i];
+  sv[i] = si;
+  if (dinv) sh[i] = si * dinv[i];
+}
+// omega = (t, s) / (t, t)
+__global__ void __launch_bounds__(APC_BLOCK) q_fin_omega(const double *part, unsigned G, Scal2 *sc) {
+  if (sc->done) return;
+  double o[2];
+  q_fin<2>(part, G, o);
+  if (threadIdx.x == 0) sc->omega = o[1] > 0.0 ? o[0] / o[1] : 0.0;
+}
+// x += alpha ph + omega sh; r = s - omega t; partials (rh, r), (r, r)
+__global__ void __launch_bounds__(APC_BLOCK)
+    q_upd_xr(int64_t n, double *__restrict__ x, const double *__restrict__ ph,
+             const double *__restrict__ sh, const double *__restrict__ sv,
+             const double *__restrict__ t, double *__restrict__ r, const double *__restrict__ rh,
+             double *part, const Scal2 *sc) {
+  if (sc->done) return;
+  const double al = sc->alpha, om = sc->omega;
+  double v[2] = {0.0, 0.0};
+  for (int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x; i < n;
+       i += (int64_t)gridDim.x * APC_BLOCK) {
+    x[i] += al * ph[i] + om * sh[i];
+    const double ri = sv[i] - om * t[i];
+    r[i] = ri;
+    v[0] += rh[i] * ri;
+    v[1] += ri * ri;
+  }
+  q_partials<2>(v, part);
+}
+// rho' = (rh, r), ||r||: convergence test, then beta for the next iteration
+__global__ void __launch_bounds__(APC_BLOCK) q_fin_rho(const double *part, unsigned G, Scal2 *sc) {
+  if (sc->done) return;
+  double o[2];
+  q_fin<2>(part, G, o);
+  if (threadIdx.x == 0) {
+    const double rho_new = o[0], om = sc->omega;
+    sc->it += 1;
+    sc->rnorm = sqrt(o[1]);
+    if (sc->rnorm <= sc->tol * sc->bnorm || om == 0.0) {
+      sc->done = 1;
+    } else if (rho_new == 0.0 || !isfinite(rho_new)) {
+      sc->done = 2;
+    } else if (sc->it >= sc->maxit) {
+      sc->done = 3;
+    } else {
+      sc->beta = (rho_new / sc->rho) * (sc->alpha / om);
+      sc->rho = rho_new;
+    }
+  }
+}
+
 } // namespace
 
 struct apc2_cloud {
@@ -762,6 +950,7 @@ struct apc2_cloud {
   double *vx = nullptr, *vr = nullptr, *vrh = nullptr, *vp = nullptr, *vv = nullptr,
          *vs = nullptr, *vt = nullptr, *vph = nullptr, *vsh = nullptr, *vb = nullptr,
          *part = nullptr;
+  Scal2 *sc = nullptr;
 };
 
 namespace {
@@ -772,7 +961,7 @@ void free2(apc2_cloud *c) {
   void *ps[] = {c->perm, c->pnode, c->sxy, c->code, c->level, c->first, c->count, c->crd,
                 c->bowner, c->bface, c->st_off, c->st_idx, c->w, c->diag, c->hs, c->dinv,
                 c->dord, c->vx, c->vr, c->vrh, c->vp, c->vv, c->vs, c->vt, c->vph, c->vsh,
-                c->vb, c->part};
+                c->vb, c->part, c->sc};
   for (void *q : ps)
     if (q) (void)apc_dev_free(q);
   delete c;
@@ -969,7 +1158,8 @@ int build2(apc2_cloud *c, const double *xy, hipStream_t s) {
     APCCHK(palloc(v, ntot));
     HIPCHK(hipMemsetAsync(*v, 0, (size_t)ntot * 8, s));
   }
-  APCCHK(palloc(&c->part, 1024));
+  APCCHK(palloc(&c->part, 2 * (int64_t)G2));
+  APCCHK(palloc(&c->sc, 1));
   HIPCHK(hipStreamSynchronize(s));
   return APC_OK;
 }
@@ -986,72 +1176,83 @@ double dot2(apc2_cloud *c, const double *a, const double *b, hipStream_t s, int 
   return t;
 }
 
-// BiCGSTAB (x0 = 0, shadow residual r0, right Jacobi scaling with dinv when given);
-// stops when the recursive ||r|| / ||b|| <= tol and the true residual agrees, else
-// restarts from the true residual
+// BiCGSTAB (x0 = 0, shadow residual r0, right Jacobi scaling with dinv when given)
+// with its scalars on the device; stops when the recursive ||r|| / ||b|| <= tol and
+// the true residual agrees, else restarts from the true residual (also after a
+// breakdown)
 int bicgstab2(apc2_cloud *c, const double *hs, const double *dinv, double tol, int maxit,
               apc_stats *st, hipStream_t s) {
   const int64_t n = c->n;
-  const unsigned g = grid_for(n);
+  const unsigned g = grid_for(n), gr = std::min<unsigned>(g, G2);
+  constexpr int CHUNK = 16; // iterations launched between reads of the state
   int rc = APC_OK;
-  auto A = [&](const double *x, double *y) {
-    hipLaunchKernelGGL(q_apply, dim3(g), dim3(APC_BLOCK), 0, s, n, c->st_off, c->st_idx, c->w, hs,
-                       x, y);
-  };
+  double *ph = dinv ? c->vph : c->vp, *sh = dinv ? c->vsh : c->vs;
   HIPCHK(hipMemsetAsync(c->vx, 0, (size_t)n * 8, s));
-  const double bn = sqrt(dot2(c, c->vb, c->vb, s, &rc));
+  HIPCHK(hipMemcpyAsync(c->vr, c->vb, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
   int it = 0, status = APC_ENOCONV;
-  double rel = 0.0, relt = 0.0;
-  if (bn == 0.0) {
-    status = APC_OK;
-  } else {
-    HIPCHK(hipMemcpyAsync(c->vr, c->vb, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-    while (status != APC_OK && it < maxit && rc == APC_OK) {
-      HIPCHK(hipMemcpyAsync(c->vrh, c->vr, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-      HIPCHK(hipMemsetAsync(c->vp, 0, (size_t)n * 8, s));
-      HIPCHK(hipMemsetAsync(c->vv, 0, (size_t)n * 8, s));
-      double rho_old = 1.0, alpha = 1.0, omega = 1.0;
-      bool restart = false;
-      while (it < maxit && !restart && rc == APC_OK) {
-        it++;
-        const double rho = dot2(c, c->vrh, c->vr, s, &rc);
-        if (rho == 0.0 || !std::isfinite(rho)) break;
-        const double beta = (rho / rho_old) * (alpha / omega);
-        hipLaunchKernelGGL(q_pupdate, dim3(g), dim3(APC_BLOCK), 0, s, n, (const double *)c->vr, beta,
-                           omega, (const double *)c->vv, c->vp);
-        hipLaunchKernelGGL(q_scale, dim3(g), dim3(APC_BLOCK), 0, s, n, (const double *)c->vp, dinv,
-                           c->vph);
-        A(c->vph, c->vv);
-        const double rv = dot2(c, c->vrh, c->vv, s, &rc);
-        if (rv == 0.0 || !std::isfinite(rv)) break;
-        alpha = rho / rv;
-        HIPCHK(hipMemcpyAsync(c->vs, c->vr, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(q_axpby, dim3(g), dim3(APC_BLOCK), 0, s, n, -alpha, (const double *)c->vv,
-                           1.0, c->vs);
-        hipLaunchKernelGGL(q_scale, dim3(g), dim3(APC_BLOCK), 0, s, n, (const double *)c->vs, dinv,
-                           c->vsh);
-        A(c->vsh, c->vt);
-        const double tt = dot2(c, c->vt, c->vt, s, &rc);
-        omega = tt > 0.0 ? dot2(c, c->vt, c->vs, s, &rc) / tt : 0.0;
-        hipLaunchKernelGGL(q_axpby, dim3(g), dim3(APC_BLOCK), 0, s, n, alpha, (const double *)c->vph,
-                           1.0, c->vx);
-        hipLaunchKernelGGL(q_axpby, dim3(g), dim3(APC_BLOCK), 0, s, n, omega, (const double *)c->vsh,
-                           1.0, c->vx);
-        HIPCHK(hipMemcpyAsync(c->vr, c->vs, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-        hipLaunchKernelGGL(q_axpby, dim3(g), dim3(APC_BLOCK), 0, s, n, -omega, (const double *)c->vt,
-                           1.0, c->vr);
-        rho_old = rho;
-        rel = sqrt(dot2(c, c->vr, c->vr, s, &rc)) / bn;
-        if (rel <= tol || omega == 0.0) restart = true;
+  double bn = 0.0, rel = 0.0, relt = 0.0;
+  Scal2 h{};
+  for (int first = 1;; first = 0) {
+    // (re)start: rh = r, p = v = 0, rho = (r, r)
+    HIPCHK(hipMemcpyAsync(c->vrh, c->vr, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemsetAsync(c->vp, 0, (size_t)n * 8, s));
+    HIPCHK(hipMemsetAsync(c->vv, 0, (size_t)n * 8, s));
+    hipLaunchKernelGGL(q_dotp, dim3(gr), dim3(APC_BLOCK), 0, s, n, (const double *)c->vr,
+                       (const double *)c->vr, c->part);
+    hipLaunchKernelGGL(q_fin_start, dim3(1), dim3(APC_BLOCK), 0, s, (const double *)c->part, gr,
+                       c->sc, tol, maxit, first);
+    HIPCHK(hipGetLastError());
+    if (first) {
+      HIPCHK(hipMemcpyAsync(&h, c->sc, sizeof(Scal2), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+      bn = h.bnorm;
+      if (bn == 0.0) {
+        status = APC_OK;
+        break;
       }
-      // true residual
-      A(c->vx, c->vt);
-      HIPCHK(hipMemcpyAsync(c->vr, c->vb, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
-      hipLaunchKernelGGL(q_axpby, dim3(g), dim3(APC_BLOCK), 0, s, n, -1.0, (const double *)c->vt, 1.0,
-                         c->vr);
-      relt = sqrt(dot2(c, c->vr, c->vr, s, &rc)) / bn;
-      if (relt <= tol) status = APC_OK;
     }
+    const int it0 = it;
+    do {
+      for (int k = 0; k < CHUNK; k++) {
+        hipLaunchKernelGGL(q_upd_p, dim3(g), dim3(APC_BLOCK), 0, s, n, (const double *)c->vr, c->vp,
+                           (const double *)c->vv, dinv, c->vph, (const Scal2 *)c->sc);
+        hipLaunchKernelGGL(q_spmv_dot<1>, dim3(gr), dim3(APC_BLOCK), 0, s, n, c->st_off, c->st_idx,
+                           c->w, hs, (const double *)ph, c->vv, (const double *)c->vrh, c->part,
+                           (const Scal2 *)c->sc);
+        hipLaunchKernelGGL(q_fin_alpha, dim3(1), dim3(APC_BLOCK), 0, s, (const double *)c->part, gr,
+                           c->sc);
+        hipLaunchKernelGGL(q_upd_s, dim3(g), dim3(APC_BLOCK), 0, s, n, (const double *)c->vr,
+                           (const double *)c->vv, c->vs, dinv, c->vsh, (const Scal2 *)c->sc);
+        hipLaunchKernelGGL(q_spmv_dot<2>, dim3(gr), dim3(APC_BLOCK), 0, s, n, c->st_off, c->st_idx,
+                           c->w, hs, (const double *)sh, c->vt, (const double *)c->vs, c->part,
+                           (const Scal2 *)c->sc);
+        hipLaunchKernelGGL(q_fin_omega, dim3(1), dim3(APC_BLOCK), 0, s, (const double *)c->part, gr,
+                           c->sc);
+        hipLaunchKernelGGL(q_upd_xr, dim3(gr), dim3(APC_BLOCK), 0, s, n, c->vx, (const double *)ph,
+                           (const double *)sh, (const double *)c->vs, (const double *)c->vt, c->vr,
+                           (const double *)c->vrh, c->part, (const Scal2 *)c->sc);
+        hipLaunchKernelGGL(q_fin_rho, dim3(1), dim3(APC_BLOCK), 0, s, (const double *)c->part, gr,
+                           c->sc);
+      }
+      HIPCHK(hipGetLastError());
+      HIPCHK(hipMemcpyAsync(&h, c->sc, sizeof(Scal2), hipMemcpyDeviceToHost, s));
+      HIPCHK(hipStreamSynchronize(s));
+    } while (h.done == 0);
+    it = h.it;
+    rel = h.rnorm / bn;
+    // true residual
+    hipLaunchKernelGGL(q_apply, dim3(g), dim3(APC_BLOCK), 0, s, n, c->st_off, c->st_idx, c->w, hs,
+                       (const double *)c->vx, c->vt);
+    HIPCHK(hipMemcpyAsync(c->vr, c->vb, (size_t)n * 8, hipMemcpyDeviceToDevice, s));
+    hipLaunchKernelGGL(q_axpby, dim3(g), dim3(APC_BLOCK), 0, s, n, -1.0, (const double *)c->vt, 1.0,
+                       c->vr);
+    relt = sqrt(dot2(c, c->vr, c->vr, s, &rc)) / bn;
+    if (rc != APC_OK) break;
+    if (relt <= tol) {
+      status = APC_OK;
+      break;
+    }
+    if (it >= maxit || it == it0) break; // the limit, or a restart that made no step
   }
   HIPCHK(hipGetLastError());
   if (rc != APC_OK) return rc;
