@@ -328,7 +328,7 @@ __device__ __forceinline__ double box_apply(const Op &op, const double *__restri
   const int lz = (lane & 1) | (((lane >> 3) & 1) << 1);
   const int b = (lx + 2) + 8 * (ly + 2) + APC_BOX_SZ * (lz + 2);
   double *tile = STG ? stage_tile(op) : nullptr;
-  if (STG) stage_fill<(APC_BOX_N + SL - 1) / SL>(tile, bx, APC_BOX_N, x); // one batch
+  if (STG) stage_fill<APC_BOX_N / SL>(tile, bx, APC_BOX_N, x); // one batch: 8 per lane
   row = op.sl_rows[(int64_t)s * SL + lane];
   const double xi = x[row];
   const double scale = op.t4_scaled ? ldexp(op.invL2, 2 * (int)op.rk[row]) : 1.0;
