@@ -403,21 +403,25 @@ static int in_octant(int o, int64_t d0, int64_t d1, int64_t d2) {
    offsets counting the centre's 0 (on fewer planes a degree-4 polynomial
    vanishes on the whole stencil), then the nearest remaining candidates, until
    min(count, m_cap) nodes are chosen; the chosen set is kept in candidate order.
-   It is accepted when (i) every closed octant holds at least one chosen node,
-   (ii) m >= p + 1, (iii) the weighted V0 has full column rank:
+   It is accepted when (i) every closed octant holds at least one chosen node --
+   with relax set, every closed octant in which the ring holds a candidate at all
+   (on an irregular domain at ring_max: at a convex corner of the voxel staircase
+   an octant can hold no node of any ring, and the rule asks for a neighbour in
+   each octant where the domain has one) --, (ii) m >= p + 1, (iii) the weighted V0 has full column rank:
    min|R_ii| / max|R_ii| >= 1e-6, and (iv, order 4) its Laplacian row has a
    negative diagonal d and sum |w_j| <= 10 |d|.  Returns m (>0) on acceptance, 0
    otherwise; the chosen candidates are compacted to the front of cd. */
 #define TAU_RANK 1e-6
 #define TAU_DOM_DEFAULT 10.0
 static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cnt, int m_cap,
-                          int order) {
+                          int order, int relax) {
   const int32_t *c0 = &C->crd[3 * y];
   int64_t want = cnt < m_cap ? cnt : m_cap;
   static unsigned char pick[1 << 20];
   if (cnt > (int64_t)sizeof(pick)) return 0;
   memset(pick, 0, (size_t)cnt);
   int64_t got = 0;
+  int populated[8];
   for (int o = 0; o < 8; o++) {
     int taken = 0;
     for (int64_t j = 0; j < cnt && taken < 2; j++) {
@@ -431,6 +435,7 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
         got++;
       }
     }
+    populated[o] = taken > 0;
   }
   for (int d = 0; order == 4 && d < 3; d++) {
     for (;;) {
@@ -479,7 +484,7 @@ static int choose_stencil(const apco_cloud *C, int32_t y, cand_t *cd, int64_t cn
     for (int o = 0; o < 8; o++) oct[o] += in_octant(o, d0, d1, d2);
   }
   for (int o = 0; o < 8; o++)
-    if (oct[o] < 1) return 0;
+    if (oct[o] < 1 && (populated[o] || !relax)) return 0;
   static double X[MAXP * MAXM];
   double h, ratio;
   wls_core(order, m, dx, dy, dz, X, &h, &ratio);
@@ -798,7 +803,8 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
      node index); a stencil is chosen from ring_min upward until one is accepted.
      Order fallback (k = 4 only): a node with no acceptable order-4 stencil up to
      ring_max takes an order-2 row, chosen by the order-2 rule from ring 2 with
-     m_cap 40.  Past ring_max at order 2 the build fails. */
+     m_cap 40.  Past ring_max at order 2 the build fails.  On an irregular domain the
+     last ring (ring_max) does not ask for the octants in which it holds no node. */
   int64_t ntot = n + nb;
   int32_t *stamp = malloc((size_t)ntot * sizeof(int32_t));
   int32_t *front = malloc((size_t)ntot * sizeof(int32_t));
@@ -865,7 +871,8 @@ int apco_build_cloud(const apco_params *P, const double *xyz, int64_t N, apco_cl
       /* reset stamps for the next ring size of this node */
       for (int64_t t = 0; t < nf; t++) stamp[front[t]] = -1;
       qsort(cand, (size_t)cnt, sizeof(cand_t), cmp_cand);
-      int m = choose_stencil(C, (int32_t)y, cand, cnt, mcap, ko);
+      int m = choose_stencil(C, (int32_t)y, cand, cnt, mcap, ko,
+                             P->mask_level > 0 && R == P->ring_max);
       if (m > 0) {
         if (ne + m > stcap) {
           stcap = 2 * stcap + m;

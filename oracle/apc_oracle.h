@@ -63,8 +63,10 @@ typedef struct {
                      between included and excluded cells.  Cells of a level below
                      mask_level are always opened unless wholly excluded, excluded
                      cells never; leaves in excluded cells are not nodes; a node's
-                     face on a wall carries a boundary node at its centre.  Not with
-                     periodic or a CIC / TSC kernel. */
+                     face on a wall carries a boundary node at its centre.  The
+                     stencil rule's last ring (ring_max) does not ask for an octant
+                     in which it holds no node (a convex corner of the staircase).
+                     Not with periodic or a CIC / TSC kernel. */
   const uint8_t *mask; /* (2^mask_level)^3 bytes, index x + s (y + s z), s = 2^mask_level;
                           nonzero: excluded.  Read during apco_build_cloud only. */
 } apco_params;

@@ -11,7 +11,11 @@ coarse levels; on an L-shaped and a ball-shaped domain the nodes tile Omega
 exactly, the boundary faces equal an independent geometric enumeration, the
 1-ring equals geometric face contact and 2:1 balance holds across every inside
 face; the GFD solve of a smooth manufactured solution on the L-shaped domain
-converges at second order; the parameter rules are enforced.
+converges at second order; the parameter rules are enforced.  Where the staircase
+of a ball has a convex corner, the last ring may hold no node at all in one
+octant: the stencil then covers every other octant, and the uncovered octant's
+corner-diagonal direction leaves Omega (checked geometrically, not through the
+ring search).
 """
 import itertools
 
@@ -170,3 +174,35 @@ def test_irregular_parameter_rules():
             OracleCloud(ok, **args)
     with pytest.raises(RuntimeError, match=r"\(-1\)"):
         OracleCloud(ok, order=2, c=0.35, max_depth=5, mask=np.ones((4, 4, 4), bool))
+
+
+def test_convex_corner_octants():
+    """Ball of radius 0.45 on an 8^3 voxel grid, beam of 2e5 particles, depth 8: a
+    node at a convex corner of the staircase has no node of any ring in one octant.
+    Every stencil covers all 8 closed octants except such ones, which occur only at
+    ring_max and point at an excluded voxel (or out of the box) from the node's
+    cell corner."""
+    mask = ball_mask(3, 0.45)
+    xyz = filtered(beam_halo(200000, seed=2, sigma=(0.08, 0.08, 0.08), halo_frac=0.05), mask)
+    depth = 8
+    C = OracleCloud(xyz, order=2, c=0.04, max_depth=depth, mask=mask)
+    nd = C.nodes()
+    crd = C.coords().astype(np.int64)
+    off, idx = nd["st_off"].astype(np.int64), nd["st_idx"]
+    rows = np.repeat(np.arange(C.n), np.diff(off))
+    d = crd[:, idx] - crd[:, rows]
+    s = mask.shape[0]
+    exempt = 0
+    for sx, sy, sz in itertools.product((-1, 1), repeat=3):
+        inq = (sx * d[0] >= 0) & (sy * d[1] >= 0) & (sz * d[2] >= 0)
+        covered = np.zeros(C.n, bool)
+        np.logical_or.at(covered, rows[inq], True)
+        for y in np.flatnonzero(~covered):
+            exempt += 1
+            assert nd["st_ring"][y] == 5  # ring_max
+            h = 2 ** (depth - int(nd["level"][y]) + 1)  # cell edge in coordinate units
+            p = (crd[:, y] + (h // 2 + 1) * np.array([sx, sy, sz])) / 2.0 ** (depth + 1)
+            if np.all((p >= 0) & (p < 1)):
+                v = np.floor(p * s).astype(int)
+                assert mask[v[0], v[1], v[2]], (y, (sx, sy, sz))
+    assert exempt >= 1
