@@ -314,7 +314,10 @@ __global__ void __launch_bounds__(APC_BLOCK)
 // the axis until it spans 5 distinct offsets (the centre's 0 included; on fewer
 // planes a quartic vanishes on the whole stencil); then the nearest remaining ones
 // up to min(count, m_cap).  Accepted (m > 0) when every closed octant holds a
-// chosen node and m >= p + 1; the rank test follows in a separate kernel.
+// chosen node (relax: every closed octant in which the ring holds a candidate; set
+// for the last ring of an irregular domain, where at a convex corner of the voxel
+// staircase an octant holds no node of any ring) and m >= p + 1; the rank test
+// follows in a separate kernel.
 //
 // One thread per pending node (thread t works on position pos = tmap ? tmap[t] : t
 // of the chunk and writes mout[pos], cand[pos]).  The ring lives in per-thread
@@ -343,7 +346,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
               const int32_t *__restrict__ bowner, int cap, int64_t stride, uint32_t hmask,
               uint32_t gen, int32_t *__restrict__ lst_all, int64_t *__restrict__ key_all,
               uint64_t *__restrict__ hash_all, int full, int32_t *__restrict__ cand,
-              int32_t *__restrict__ mout, int *__restrict__ err) {
+              int32_t *__restrict__ mout, int *__restrict__ err, int relax) {
   const int64_t t = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
   if (t >= np) return;
   const int64_t pos = tmap ? tmap[t] : t;
@@ -453,6 +456,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   // picked candidates are marked by storing -(v+1).  Octant by octant, the two
   // nearest candidates in the octant are taken and picked unless picked already:
   // one pass over the sorted list finds each octant's two nearest.
+  uint32_t popm = 0; // octants in which the ring holds a candidate
   {
     int f0[8], f1[8], nf[8];
 #pragma unroll
@@ -468,6 +472,9 @@ __global__ void __launch_bounds__(APC_BLOCK)
           if (++nf[o] == 2) open &= ~(1u << o);
         }
     }
+#pragma unroll
+    for (int o = 0; o < 8; o++)
+      if (nf[o] > 0) popm |= 1u << o;
 #pragma unroll
     for (int o = 0; o < 8; o++)
 #pragma unroll
@@ -529,7 +536,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
 #undef LST
 #undef KEY
   bool ok = m >= p + 1 && m <= APC_MAXM;
-  for (int o = 0; o < 8; o++) ok = ok && oct[o] >= 1;
+  for (int o = 0; o < 8; o++) ok = ok && (oct[o] >= 1 || (relax && !((popm >> o) & 1u)));
   mout[pos] = ok ? m : 0;
 }
 
@@ -554,7 +561,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
                    const int32_t *__restrict__ crd, int64_t ntot, int64_t n,
                    const int32_t *__restrict__ r1cnt, const int32_t *__restrict__ r1,
                    const int32_t *__restrict__ bowner, int32_t *__restrict__ cand,
-                   int32_t *__restrict__ mout) {
+                   int32_t *__restrict__ mout, int relax) {
   __shared__ int32_t sh_h[APC_BLOCK / 64][WV_HASH];
   __shared__ int32_t sh_l[APC_BLOCK / 64][64];
   __shared__ int32_t sh_c[APC_BLOCK / 64];
@@ -671,7 +678,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
   const int m = __popcll(P);
   bool ok = m >= p + 1 && m <= APC_MAXM;
 #pragma unroll
-  for (int o = 0; o < 8; o++) ok = ok && (P & inO[o]) != 0;
+  for (int o = 0; o < 8; o++) ok = ok && ((P & inO[o]) != 0 || (relax && inO[o] == 0));
   if ((P >> lane) & 1ull)
     cand[pos * APC_MAXM + __popcll(P & ((1ull << lane) - 1ull))] = v;
   if (lane == 0) mout[pos] = ok ? m : 0;
@@ -689,7 +696,7 @@ __global__ void __launch_bounds__(APC_BLOCK)
                     int64_t np, int R, int m_cap, int p, const int32_t *__restrict__ crd,
                     int64_t ntot, int64_t n, const int32_t *__restrict__ r1cnt,
                     const int32_t *__restrict__ r1, const int32_t *__restrict__ bowner,
-                    int32_t *__restrict__ cand, int32_t *__restrict__ mout) {
+                    int32_t *__restrict__ cand, int32_t *__restrict__ mout, int relax) {
   __shared__ int32_t H[BK_HASH];
   __shared__ int32_t Ls[APC_BLOCK];
   __shared__ int64_t Kr[APC_BLOCK];
@@ -832,9 +839,12 @@ __global__ void __launch_bounds__(APC_BLOCK)
     }
     bool ok = got >= p + 1 && got <= APC_MAXM;
     for (int o = 0; o < 8; o++) {
-      bool any = false;
-      for (int q = 0; q < APC_BLOCK / 64; q++) any = any || (P[q] & inO[o][q]) != 0;
-      ok = ok && any;
+      bool any = false, pop = false;
+      for (int q = 0; q < APC_BLOCK / 64; q++) {
+        any = any || (P[q] & inO[o][q]) != 0;
+        pop = pop || inO[o][q] != 0;
+      }
+      ok = ok && (any || (relax && !pop));
     }
     for (int q = 0; q < APC_BLOCK / 64; q++) Pm[q] = P[q];
     mres = ok ? got : 0;
@@ -1301,6 +1311,8 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
   const int pk = ko == 2 ? 9 : 34;
   const int rmin = att == 0 ? P.ring_min : 2, mcap = att == 0 ? P.m_cap : 40;
   for (int R = rmin; R <= P.ring_max && np > 0; R++) {
+    // irregular domain, last ring: an octant with no node in the ring is not asked for
+    const int relax = P.mask_level > 0 && R == P.ring_max ? 1 : 0;
     HIPCHK(hipMemsetAsync(err, 0, sizeof(int), s));
     const int cap1 = ring_cap(R);
     const int64_t CH = chunk_nodes(cap1, W1);
@@ -1337,7 +1349,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
           hipLaunchKernelGGL(k_stencil, dim3(grid_for(rn)), dim3(APC_BLOCK), 0, s, pending + c0,
                              (const int32_t *)(rlist + r0), rn, R, mcap, pk, ko, c->crd, ntot, n,
                              r1cnt, r1, c->bowner, capx, stride, S.mask, ++gen, S.lst, S.key,
-                             S.tab, full, cand, mch, err);
+                             S.tab, full, cand, mch, err, relax);
           HIPCHK(hipGetLastError());
         }
         return APC_OK;
@@ -1347,14 +1359,14 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
         // block per node; the rest by k_stencil at capacity cap1
         hipLaunchKernelGGL(k_stencil_wave, dim3(grid_for(cn, APC_BLOCK / 64)), dim3(APC_BLOCK), 0,
                            s, pending + c0, cn, R, mcap, pk, c->crd, ntot, n, r1cnt, r1,
-                           c->bowner, cand, mch);
+                           c->bowner, cand, mch, relax);
         HIPCHK(hipGetLastError());
         int64_t nb = 0;
         if (P.ring_lds == 0) APCCHK(compact_open(&nb));
         if (nb > 0) {
           hipLaunchKernelGGL(k_stencil_block, dim3((unsigned)nb), dim3(APC_BLOCK), 0, s,
                              pending + c0, (const int32_t *)rlist, nb, R, mcap, pk, c->crd, ntot,
-                             n, r1cnt, r1, c->bowner, cand, mch);
+                             n, r1cnt, r1, c->bowner, cand, mch, relax);
           HIPCHK(hipGetLastError());
         }
         APCCHK(rerun(cap1, 1, CH, CH, 0));
@@ -1364,7 +1376,7 @@ static int build_body(apc_cloud *c, const double *xyz, hipStream_t s) {
         hipLaunchKernelGGL(k_stencil, dim3(grid_for(cn)), dim3(APC_BLOCK), 0, s, pending + c0,
                            (const int32_t *)nullptr, cn, R, mcap, pk, ko, c->crd, ntot, n, r1cnt,
                            r1, c->bowner, cap1, CH, S1.mask, ++gen, S1.lst, S1.key, S1.tab, 0,
-                           cand, mch, err);
+                           cand, mch, err, relax);
         HIPCHK(hipGetLastError());
       }
       // rerun the nodes whose ring outgrew cap1 with the full capacity

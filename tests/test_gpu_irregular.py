@@ -122,6 +122,30 @@ def test_irregular_rows_and_solves(pair):
     assert e_gp <= 1e-9
 
 
+def test_convex_corner_cloud_bit_exact(apc, oracle_mod):
+    """Ball on an 8^3 voxel grid, 2e5 beam particles, depth 8: nodes at convex
+    corners of the staircase take their stencil at ring_max without the octant that
+    holds no node (the oracle's pin checks the geometry); same cloud and rows as the
+    oracle."""
+    mask = ball_mask(3)
+    xyz = filtered(beam_halo(200000, seed=2, sigma=(0.08, 0.08, 0.08), halo_frac=0.05), mask)
+    kw = dict(order=2, c=0.04, max_depth=8, mask=mask)
+    note(f"irregular convex corners: {xyz.shape[1]} particles")
+    O = oracle_mod.OracleCloud(xyz, **kw)
+    G = apc.Cloud(cuda(xyz), precision=apc.APC_FP64, **kw)
+    assert (G.n, G.nb, G.nnz, G.n_opened) == (O.n, O.nb, O.nnz, O.n_opened)
+    a, b = O.nodes(), G.nodes()
+    for k in ("code", "level", "bowner", "bface", "st_off", "st_idx"):
+        np.testing.assert_array_equal(a[k].astype(np.int64), b[k].astype(np.int64), err_msg=k)
+    G.assemble_gfd()
+    w_g, d_g = G.operator()
+    w_o, d_o = O.assemble()
+    m = np.diff(a["st_off"])
+    assert np.max(np.abs(w_g - w_o) / np.repeat(np.abs(d_o), m)) <= 1e-12
+    note(f"  n={G.n} nb={G.nb} nnz={G.nnz}")
+    G.close()
+
+
 def test_irregular_lattice_uniform_rows(apc, oracle_mod):
     """The lattice inside the L (uniform rows, boxed slices of k = 4 away from the
     walls): structure bit-exact, rows and the operator apply within 1e-12."""
