@@ -46,9 +46,10 @@ def log(msg):
 
 
 def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="none",
-              params=None, timing=True, keep_last=False):
+              params=None, timing=True, keep_last=False, extra=None):
     """warmup + timed steps of the whole path; per-phase mean device ms over the
-    timed steps, and the SpMV launch times the library recorded during them."""
+    timed steps, and the SpMV launch times the library recorded during them.
+    extra: further build parameters (periodic, kernel, mask)."""
     stream = torch.cuda.current_stream()
     names = ["build", "assemble", "install", "deposit", "solve", "interpolate"]
     pc = PRECOND[precond]
@@ -56,6 +57,7 @@ def run_steps(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, precond="no
     spmv_ms, spmv_n = 0.0, 0
     info, last = {}, None
     kw = dict(order=cfg["order"], c=cfg["c"], max_depth=cfg["max_depth"], precision=precision)
+    kw.update(extra or {})
     t0 = None
     for it in range(warmup + steps):
         timed = it >= warmup
@@ -429,6 +431,57 @@ def vlasov_bench(apc, torch, xyz_d, cfg, precision, steps, warmup, tol, dt=1e-3)
 PAPER_3D_TABLE = [(1546, 0.921), (4067, 1.14), (13687, 2.10), (59349, 7.22)]
 
 
+def ball_mask(level, radius):
+    """Voxel mask of the domain [0, 1]^3 minus the voxels (2^level a side) whose
+    centres lie outside the ball of the given radius about the centre."""
+    import numpy as np
+    s = 1 << level
+    g = (np.arange(s) + 0.5) / s - 0.5
+    x, y, z = np.meshgrid(g, g, g, indexing="ij")
+    return x * x + y * y + z * z > radius * radius
+
+
+def inside_mask(xyz, mask):
+    import numpy as np
+    s = mask.shape[0]
+    i = np.clip(np.floor(xyz * s).astype(np.int64), 0, s - 1)
+    return np.ascontiguousarray(xyz[:, ~mask[i[0], i[1], i[2]]])
+
+
+def next_rows_bench(apc, torch, xyz, cfg, tol, steps=3, warmup=1):
+    """The boundary and charge-assignment forms beyond the paper's base case, each as
+    the whole field path (FP64, no preconditioner) on the 1e7-particle second-order
+    beam: NGP on the box (reference), the periodic box, CIC and TSC charge assignment,
+    and an irregular domain (the box minus the voxels of a 32^3 grid outside a ball
+    of radius 0.45).  Per form: phases, iterations, and the operator SpMV against
+    HBM by the layout's bytes."""
+    forms = [("ngp", {}, xyz), ("periodic", dict(periodic=1), xyz),
+             ("cic", dict(kernel=apc.APC_KERNEL_CIC), xyz),
+             ("tsc", dict(kernel=apc.APC_KERNEL_TSC), xyz)]
+    mask = ball_mask(5, 0.45)
+    forms.append(("irregular_ball", dict(mask=mask), inside_mask(xyz, mask)))
+    out = dict(workload=f"beam_halo_1e7 ({cfg['N']} particles, k = 2, depth "
+                        f"{cfg['max_depth']}, c = {cfg['c']}), FP64, no preconditioner")
+    for name, extra, pts in forms:
+        xd = torch.from_numpy(pts).cuda()
+        ms, info, wall, last = run_steps(apc, torch, xd, cfg, apc.APC_FP64, steps, warmup, tol,
+                                         extra=extra, keep_last=True)
+        cloud, _ = last
+        _, lb = spmv_bytes(cloud, info, 8, index_bytes(cloud))
+        au = info["spmv_avg_us"]
+        r = leg(ms, info, wall)
+        r.update(particles=int(pts.shape[1]), nodes=info["n"], boundary_nodes=info["nb"],
+                 nnz=info["nnz"],
+                 spmv=dict(avg_us=round(au, 2), bytes_per_launch=lb,
+                           GBs=round(lb / (au * 1e-6) / 1e9, 1),
+                           frac=round(lb / (au * 1e-6) / 1e9 / HBM_PEAK_GBS, 4)))
+        out[name] = r
+        cloud.close()
+        del xd, last, cloud
+        log(f"next rows {name}: {r}")
+    return out
+
+
 def paper_beam_bench(apc, torch, cs=(1.0, 0.3, 0.1)):
     """The paper's 3-D beam with halo (1e6 particles in [-1, 1]^3) timed end to end
     (build, assembly, deposit with density solve to 1e-12, Poisson solve to 1e-10
@@ -566,6 +619,11 @@ def main():
     ap.add_argument("--no-vlasov", action="store_true",
                     help="skip the Vlasov-Poisson time steps (apc_step)")
     ap.add_argument("--no-probes", action="store_true", help="skip the bandwidth probes")
+    ap.add_argument("--no-next-rows", action="store_true",
+                    help="skip the periodic / CIC / TSC / irregular-domain legs")
+    ap.add_argument("--only-next-rows", action="store_true",
+                    help="run only the periodic / CIC / TSC / irregular-domain legs (for "
+                         "profiling) and print their JSON")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build runs on one GPU only (got --gpus {args.gpus}); "
@@ -580,6 +638,12 @@ def main():
     apc.load_library()
     torch.cuda.set_device(0)
     PREC = {"fp64": apc.APC_FP64, "mixed": apc.APC_MIXED, "mixed_f32acc": apc.APC_MIXED_F32ACC}
+    if args.only_next_rows:
+        c2 = CONFIGS["beam_halo_1e7"]
+        x2h = beam_halo(c2["N"], seed=c2["seed"], sigma=c2["sigma"], halo_frac=c2["halo_frac"])
+        print(json.dumps({"next_rows": next_rows_bench(apc, torch, x2h, c2, args.tol)}),
+              flush=True)
+        return
     cfg = CONFIGS[args.workload]
     log(f"generating {args.workload}: N={cfg['N']}")
     xyz_d = torch.from_numpy(beam_halo(cfg["N"], seed=cfg["seed"], sigma=cfg["sigma"],
@@ -660,12 +724,12 @@ def main():
     torch.cuda.empty_cache()
 
     # ---- second-order workload at 1e7 particles (five variants)
-    k2 = None
+    k2 = next_rows = None
     if not args.no_k2 and args.workload != "beam_halo_1e7":
         c2 = CONFIGS["beam_halo_1e7"]
         log("beam_halo_1e7 legs")
-        x2 = torch.from_numpy(beam_halo(c2["N"], seed=c2["seed"], sigma=c2["sigma"],
-                                        halo_frac=c2["halo_frac"])).cuda()
+        x2h = beam_halo(c2["N"], seed=c2["seed"], sigma=c2["sigma"], halo_frac=c2["halo_frac"])
+        x2 = torch.from_numpy(x2h).cuda()
         k2 = dict(workload="beam_halo_1e7", particles=c2["N"], order=2,
                   max_depth=c2["max_depth"], c=c2["c"])
         for name, pcn in (("fp64", "none"), ("fp64", "jacobi"), ("mixed", "none"),
@@ -700,7 +764,10 @@ def main():
             log("Vlasov-Poisson time steps")
             vlasov = vlasov_bench(apc, torch, x2, c2, apc.APC_MIXED, 5, 1, args.tol)
             log(f"vlasov: {vlasov}")
-        del x2
+        if not args.no_next_rows:
+            log("periodic / CIC / TSC / irregular-domain legs")
+            next_rows = next_rows_bench(apc, torch, x2h, c2, args.tol)
+        del x2, x2h
         torch.cuda.empty_cache()
     else:
         vlasov = None
@@ -770,6 +837,8 @@ def main():
         out["k2"] = k2
     if vlasov is not None:
         out["vlasov"] = vlasov
+    if next_rows is not None:
+        out["next_rows"] = next_rows
     if batch is not None:
         out["batch"] = batch
     if pbeam is not None:

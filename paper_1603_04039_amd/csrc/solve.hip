@@ -444,22 +444,74 @@ __device__ __forceinline__ int64_t leaf_of(const uint64_t *__restrict__ code, in
   return lo;
 }
 
+// Leaf lookup table of level L0 (<= max_depth): tab[k] = the leaf that holds the
+// lowest corner of level-L0 cell k (a coarser leaf covers all its level-L0 cells);
+// -1 where no leaf lies (cells outside Omega).  The leaf holding a key then lies
+// between the entries of the key's cell and of the next cell.
+__global__ void __launch_bounds__(APC_BLOCK)
+    k_leaf_table(int64_t n, const uint64_t *__restrict__ code, const int32_t *__restrict__ level,
+                 int D, int L0, int32_t *__restrict__ tab) {
+  const int64_t j = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
+  if (j >= n) return;
+  const int sh = 3 * (D - L0);
+  const uint64_t cc = code[j] >> sh;
+  const int l = level[j];
+  if (l >= L0) {
+    if (j == 0 || (code[j - 1] >> sh) != cc) tab[cc] = (int32_t)j;
+  } else {
+    const uint64_t m = 1ull << (3 * (L0 - l));
+    for (uint64_t k = 0; k < m; k++) tab[cc + k] = (int32_t)j;
+  }
+}
+
+// the last leaf with code <= key, searched between the table entries of the key's
+// level-L0 cell and of the next one (the whole list where the table has no entry)
+__device__ __forceinline__ int64_t leaf_of_tab(const uint64_t *__restrict__ code, int64_t n,
+                                               const int32_t *__restrict__ tab, int64_t ncell,
+                                               int sh, uint64_t key) {
+  const int64_t cc = (int64_t)(key >> sh);
+  const int32_t t0 = tab[cc];
+  if (t0 < 0) return leaf_of(code, n, key);
+  int64_t hi = n;
+  for (int64_t k = cc + 1; k < ncell; k++) // the next cell with an entry
+    if (tab[k] >= 0) {
+      hi = tab[k];
+      break;
+    }
+  int64_t lo = t0; // code[lo] <= key < code[hi]
+  if (hi <= lo) return lo;
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (code[mid] <= key) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
 // CIC / TSC deposit (eq. density_apcloud): rho_M_j = sum_i q_i Phi((p_i - y_j) / h_j)
-// / (a_0 h_j^3), one thread per node.  The kernel's support lies in the 3 x 3 x 3
+// / (a_0 h_j^3), one wavefront per node.  The kernel's support lies in the 3 x 3 x 3
 // block of cells of the node's size around it; each such region R (an aligned cube,
 // so a contiguous range of Morton keys and of sorted particles) is either inside
 // one leaf (a coarser or equal cell: its particles are visited once, from the
 // region of the block that holds the leaf's lowest corner in it) or the union of
-// the leaves whose keys fall in R.  Minimum-image offsets on a periodic domain.
+// the leaves whose keys fall in R.  Lane t < 27 finds region t's particle range;
+// the ranges are then walked as one list, 64 consecutive particles at a time (each
+// lane its own particle: coalesced loads), and the lanes' partial sums are reduced
+// in a fixed order.  Minimum-image offsets on a periodic domain.
 __global__ void __launch_bounds__(APC_BLOCK)
     k_deposit_kern(int64_t n, int64_t N, int kernel, int D, const uint64_t *__restrict__ code,
                    const int32_t *__restrict__ level, const int32_t *__restrict__ first,
                    const int32_t *__restrict__ count, const int32_t *__restrict__ crd,
                    int64_t ntot, const double *__restrict__ sxyz, const int32_t *__restrict__ perm,
                    const double *__restrict__ q, double lo0, double lo1, double lo2, double L,
-                   double unit, double *__restrict__ rho) {
-  const int64_t j = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x;
-  if (j >= n) return;
+                   double unit, const int32_t *__restrict__ tab, int L0,
+                   double *__restrict__ rho) {
+  __shared__ int32_t s_end[APC_BLOCK / 64][32], s_off[APC_BLOCK / 64][32];
+  const int tsh = 3 * (D - L0);
+  const int64_t ncell = (int64_t)1 << (3 * L0);
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t j = (int64_t)blockIdx.x * (APC_BLOCK / 64) + w;
+  if (j >= n) return; // whole wavefronts
   const int32_t side = 1 << D, S = crd[3 * ntot];
   const bool per = S != 0;
   const int l = level[j];
@@ -476,58 +528,85 @@ __global__ void __launch_bounds__(APC_BLOCK)
     if (per) return (r + side) & (side - 1);
     return (r < 0 || r >= side) ? -1 : r;
   };
-  double sum = 0.0;
-  for (int tz = -1; tz <= 1; tz++)
-    for (int ty = -1; ty <= 1; ty++)
-      for (int tx = -1; tx <= 1; tx++) {
-        const int t[3] = {tx, ty, tz};
-        int32_t r[3];
-        bool valid = true;
-        for (int d = 0; d < 3; d++) {
-          r[d] = rc(d, t[d]);
-          valid = valid && r[d] >= 0;
-        }
-        if (!valid) continue;
-        const uint64_t k0 = apc_morton((uint32_t)r[0], (uint32_t)r[1], (uint32_t)r[2]);
-        const int64_t a = leaf_of(code, n, k0);
-        const int32_t Ea = 1 << (D - level[a]);
-        int32_t ps, pe;
-        if (Ea >= E) {
-          // R lies in leaf a: only the block's first region in that leaf (per
-          // axis the smallest offset t whose region is inside it) takes its particles
-          const int32_t oa[3] = {(crd[a] - Ea) >> 1, (crd[ntot + a] - Ea) >> 1,
-                                 (crd[2 * ntot + a] - Ea) >> 1};
-          bool firstr = true;
-          for (int d = 0; d < 3 && firstr; d++)
-            for (int u = -1; u < t[d]; u++) {
-              const int32_t rr = rc(d, u);
-              if (rr >= 0 && ((rr - oa[d] + side) & (side - 1)) < Ea) firstr = false;
-            }
-          if (!firstr) continue;
+  int32_t ps = 0, pe = 0;
+  if (lane < 27) {
+    const int t[3] = {lane % 3 - 1, (lane / 3) % 3 - 1, lane / 9 - 1};
+    int32_t r[3];
+    bool valid = true;
+    for (int d = 0; d < 3; d++) {
+      r[d] = rc(d, t[d]);
+      valid = valid && r[d] >= 0;
+    }
+    if (valid) {
+      const uint64_t k0 = apc_morton((uint32_t)r[0], (uint32_t)r[1], (uint32_t)r[2]);
+      const int64_t a = leaf_of_tab(code, n, tab, ncell, tsh, k0);
+      const int32_t Ea = 1 << (D - level[a]);
+      if (Ea >= E) {
+        // R lies in leaf a: only the block's first region in that leaf (per axis
+        // the smallest offset t whose region is inside it) takes its particles
+        const int32_t oa[3] = {(crd[a] - Ea) >> 1, (crd[ntot + a] - Ea) >> 1,
+                               (crd[2 * ntot + a] - Ea) >> 1};
+        bool firstr = true;
+        for (int d = 0; d < 3 && firstr; d++)
+          for (int u = -1; u < t[d]; u++) {
+            const int32_t rr = rc(d, u);
+            if (rr >= 0 && ((rr - oa[d] + side) & (side - 1)) < Ea) firstr = false;
+          }
+        if (firstr) {
           ps = first[a];
           pe = ps + count[a];
-        } else {
-          const uint64_t e3 = (uint64_t)E * (uint64_t)E * (uint64_t)E;
-          const int64_t b = leaf_of(code, n, k0 + e3 - 1);
-          ps = first[a];
-          pe = first[b] + count[b];
         }
-        for (int32_t s = ps; s < pe; s++) {
-          double w = 1.0;
-          for (int d = 0; d < 3 && w != 0.0; d++) {
-            double dx = sxyz[(int64_t)d * N + s] - yc[d];
-            if (per) {
-              if (dx >= 0.5 * L) dx -= L;
-              else if (dx < -0.5 * L) dx += L;
-            }
-            w *= apc_kernel_phi(kernel, dx / hc);
-          }
-          if (w != 0.0) sum += (q ? q[perm[s]] : q0) * w;
-        }
+      } else {
+        const uint64_t e3 = (uint64_t)E * (uint64_t)E * (uint64_t)E;
+        const int64_t b = leaf_of_tab(code, n, tab, ncell, tsh, k0 + e3 - 1);
+        ps = first[a];
+        pe = first[b] + count[b];
       }
-  double tlo[3], thi[3];
-  apc_node_trunc(c[0], c[1], c[2], (double)(2 * E), per ? 0.0 : (double)(2 * side), tlo, thi);
-  rho[j] = sum / (apc_kernel_a0(kernel, tlo, thi) * (hc * hc * hc));
+    }
+  }
+  // the ranges as one list: region t holds list positions [end_t - len_t, end_t)
+  const int32_t len = pe - ps;
+  int32_t incl = len;
+#pragma unroll
+  for (int sh = 1; sh < 64; sh <<= 1) {
+    const int32_t v = __shfl_up(incl, sh, 64);
+    if (lane >= sh) incl += v;
+  }
+  const int32_t T = __shfl(incl, 63, 64);
+  if (lane < 32) {
+    s_end[w][lane] = lane < 27 ? incl : INT32_MAX;
+    s_off[w][lane] = ps - (incl - len); // particle = list position + off
+  }
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  double sum = 0.0;
+  for (int32_t i = lane; i < T; i += 64) {
+    int lo = 0, hi = 26; // the first region with end > i
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (s_end[w][mid] > i) hi = mid;
+      else lo = mid + 1;
+    }
+    const int32_t sp = i + s_off[w][lo];
+    double wgt = 1.0;
+    for (int d = 0; d < 3 && wgt != 0.0; d++) {
+      double dx = sxyz[(int64_t)d * N + sp] - yc[d];
+      if (per) {
+        if (dx >= 0.5 * L) dx -= L;
+        else if (dx < -0.5 * L) dx += L;
+      }
+      wgt *= apc_kernel_phi(kernel, dx / hc);
+    }
+    if (wgt != 0.0) sum += (q ? q[perm[sp]] : q0) * wgt;
+  }
+#pragma unroll
+  for (int sh = 32; sh > 0; sh >>= 1) sum += __shfl_xor(sum, sh, 64);
+  if (lane == 0) {
+    double tlo[3], thi[3];
+    apc_node_trunc(c[0], c[1], c[2], (double)(2 * E), per ? 0.0 : (double)(2 * side), tlo, thi);
+    rho[j] = sum / (apc_kernel_a0(kernel, tlo, thi) * (hc * hc * hc));
+  }
 }
 
 __global__ void __launch_bounds__(APC_BLOCK)
@@ -790,14 +869,24 @@ static int run_solve(apc_cloud *c, bool density, const double *b, double *x, dou
 }
 
 int apc_deposit_impl(apc_cloud *c, const double *q, double *rho_M, hipStream_t s) {
-  if (c->P.kernel == APC_KERNEL_NGP)
+  if (c->P.kernel == APC_KERNEL_NGP) {
     hipLaunchKernelGGL(k_deposit, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->N,
                        c->first, c->count, c->level, c->perm, q, c->P.L, rho_M);
-  else
-    hipLaunchKernelGGL(k_deposit_kern, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n, c->N,
-                       c->P.kernel, c->P.max_depth, (const uint64_t *)c->code, c->level, c->first,
+  } else if (c->n > 0) {
+    const int D = c->P.max_depth, L0 = D < 7 ? D : 7; // table of 8^L0 entries (8 MiB at most)
+    const size_t ncell = (size_t)1 << (3 * L0);
+    int32_t *tab = nullptr;
+    HIPCHK(apc_malloc_async((void **)&tab, ncell * sizeof(int32_t), s));
+    HIPCHK(hipMemsetAsync(tab, 0xff, ncell * sizeof(int32_t), s));
+    hipLaunchKernelGGL(k_leaf_table, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n,
+                       (const uint64_t *)c->code, c->level, D, L0, tab);
+    hipLaunchKernelGGL(k_deposit_kern, dim3(grid_for(c->n, APC_BLOCK / 64)), dim3(APC_BLOCK), 0, s,
+                       c->n, c->N, c->P.kernel, D, (const uint64_t *)c->code, c->level, c->first,
                        c->count, c->crd, c->n + c->nb, c->sxyz, c->perm, q, c->P.lo[0],
-                       c->P.lo[1], c->P.lo[2], c->P.L, c->unit, rho_M);
+                       c->P.lo[1], c->P.lo[2], c->P.L, c->unit, (const int32_t *)tab, L0, rho_M);
+    HIPCHK(hipGetLastError());
+    HIPCHK(apc_free_async(tab, s));
+  }
   if (c->nb > 0)
     hipLaunchKernelGGL(k_bnd_copy, dim3(grid_for(c->nb)), dim3(APC_BLOCK), 0, s, c->n, c->nb,
                        c->bowner, rho_M);
