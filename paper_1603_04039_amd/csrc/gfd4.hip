@@ -1043,17 +1043,98 @@ static inline void canon4_stencil(Canon4 &h) {
 }
 
 // ---------------------------------------------------------------- derivatives
+// The least-squares derivatives by the normal equations on the matrix cores: G = A^T
+// A (A = W V0, PC columns), c = A^T b with b = W (f_j - f_0), z = G^-1 c, then one
+// refinement step with the residual of the least-squares problem itself, z += G^-1
+// A^T (b - A z) (semi-normal equations: the step contracts the error of z by about
+// kappa(G) eps).  True when the Cholesky pivots are positive and the last correction
+// is at most 1e-7 of z.
+template <int MR, int PC>
+__device__ __forceinline__ bool derivs_ne(WaveN<MR> &S, int lane, double b, double &z) {
+  gram_mfma<MR, PC>(S, lane);
+  wsync();
+  double g[P4], rd;
+  if (!cholesky_n<MR, PC>(S, lane, g, rd)) return false;
+  if (lane < MR) {
+    S.y[lane] = b;
+    S.y[MR + lane] = 0.0;
+  }
+  wsync();
+  double c0, c1;
+  at_times_n<MR, PC>(S, lane, c0, c1);
+  double z0 = c0, z1 = 0.0;
+  chol_solve_n<MR, PC>(S, lane, g, rd, z0, z1);
+  double y0, y1;
+  a_times_n<MR, PC>(S, lane, lane < PC ? z0 : 0.0, 0.0, y0, y1);
+  if (lane < MR) {
+    S.y[lane] = b - y0;
+    S.y[MR + lane] = 0.0;
+  }
+  wsync();
+  double d0, d1;
+  at_times_n<MR, PC>(S, lane, d0, d1);
+  double e0 = lane < PC ? d0 : 0.0, e1 = 0.0;
+  chol_solve_n<MR, PC>(S, lane, g, rd, e0, e1);
+  if (lane < PC) z0 += e0;
+  const double dm = wmax_d(lane < PC ? fabs(e0) : 0.0);
+  const double zm = wmax_d(lane < PC ? fabs(z0) : 0.0);
+  z = z0;
+  return dm <= 1e-7 * zm;
+}
+
+// Derivatives of the rows listed (list null: rows 0 .. n-1), one wavefront per row,
+// by derivs_ne; a row it does not accept gets a NaN as its first derivative and is
+// taken by k_node_derivs4 (flagged = 1).
+template <int MR>
+__global__ void __launch_bounds__(wpbn<MR>() * 64)
+    k_node_derivs4n(int64_t n, const int32_t *__restrict__ list, const int32_t *__restrict__ st_off,
+                    const int32_t *__restrict__ st_idx, const int32_t *__restrict__ crd,
+                    int64_t ntot, const int8_t *__restrict__ rorder, double unit,
+                    const double *__restrict__ f, double *__restrict__ D) {
+  constexpr int WPB = wpbn<MR>();
+  __shared__ WaveN<MR> SH[WPB];
+  const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
+  const int64_t t = (int64_t)blockIdx.x * WPB + wv;
+  if (t >= n) return;
+  const int64_t y = list ? (int64_t)list[t] : t;
+  WaveN<MR> &S = SH[wv];
+  const int32_t a0 = st_off[y];
+  const int m = st_off[y + 1] - a0;
+  const int pc = rorder[y] == 4 ? P4 : 9;
+  const Geo g = stencil_rows_n<MR>(S, lane, st_idx + a0, m, crd, ntot, y);
+  const double b = lane < m ? g.W * (f[st_idx[a0 + lane]] - f[y]) : 0.0;
+  wsync();
+  double z;
+  const bool ok = pc == P4 ? derivs_ne<MR, P4>(S, lane, b, z) : derivs_ne<MR, 9>(S, lane, b, z);
+  if (!ok) {
+    if (lane == 0) D[y * P4] = __builtin_nan("");
+    return;
+  }
+  if (lane >= pc && lane < P4) D[y * P4 + lane] = 0.0; // order-2 fallback row
+  if (lane < pc) {
+    int ax, ay, az;
+    alpha4(lane, ax, ay, az);
+    double hk = 1.0;
+    const double hp = (double)g.h * unit;
+    for (int q = 0; q < ax + ay + az; q++) hk *= hp;
+    D[y * P4 + lane] = z / hk;
+  }
+}
+
+// The same derivatives by the Householder QR of W V0 (the oracle's route), for the
+// rows listed; flagged: only those whose first derivative k_node_derivs4n left NaN.
 template <int MR>
 __global__ void __launch_bounds__(WPB4 * 64, 2)
     k_node_derivs4(int64_t n, const int32_t *__restrict__ list, const int32_t *__restrict__ st_off,
                    const int32_t *__restrict__ st_idx, const int32_t *__restrict__ crd, int64_t ntot,
                    const int8_t *__restrict__ rorder, double unit,
-                   const double *__restrict__ f, double *__restrict__ D) {
+                   const double *__restrict__ f, double *__restrict__ D, int flagged) {
   __shared__ Wave4 SH[WPB4];
   const int wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6), lane = threadIdx.x & 63;
   const int64_t t = (int64_t)blockIdx.x * WPB4 + wv;
   if (t >= n) return;
   const int64_t y = list ? (int64_t)list[t] : t;
+  if (flagged && !isnan(D[y * P4])) return;
   Wave4 &S = SH[wv];
   const int32_t a0 = st_off[y];
   const int m = st_off[y + 1] - a0;
@@ -1438,20 +1519,29 @@ int apc_assemble4(apc_cloud *c, hipStream_t s) {
   return APC_OK;
 }
 
-// Householder QR per node for the general nodes; the uniform 56-node nodes through
-// the canonical derivative operator.
+// The general nodes by the normal equations on the matrix cores (k_node_derivs4n),
+// the few it does not accept by the Householder QR; the uniform 56-node nodes
+// through the canonical derivative operator.
 int apc_node_derivs4(apc_cloud *c, const double *f, double *D, hipStream_t s) {
   const bool uni = c->n_uniform4 > 0 && c->cder4;
   const int64_t cnt = uni ? c->n_gen4 : c->n;
   const int32_t *list = uni ? c->gen4 : nullptr;
-  if (cnt > 0 && c->P.m_cap <= 56)
+  if (cnt > 0 && c->P.m_cap <= 56) {
+    hipLaunchKernelGGL(k_node_derivs4n<56>, dim3((unsigned)((cnt + wpbn<56>() - 1) / wpbn<56>())),
+                       dim3(wpbn<56>() * 64), 0, s, cnt, list, c->st_off, c->st_idx, c->crd,
+                       c->n + c->nb, (const int8_t *)c->rorder, c->unit, f, D);
     hipLaunchKernelGGL(k_node_derivs4<56>, dim3(grid4(cnt)), dim3(WPB4 * 64), 0, s, cnt, list,
                        c->st_off, c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder,
-                       c->unit, f, D);
-  else if (cnt > 0)
+                       c->unit, f, D, 1);
+  } else if (cnt > 0) {
+    hipLaunchKernelGGL(k_node_derivs4n<APC_MAXM>,
+                       dim3((unsigned)((cnt + wpbn<APC_MAXM>() - 1) / wpbn<APC_MAXM>())),
+                       dim3(wpbn<APC_MAXM>() * 64), 0, s, cnt, list, c->st_off, c->st_idx, c->crd,
+                       c->n + c->nb, (const int8_t *)c->rorder, c->unit, f, D);
     hipLaunchKernelGGL(k_node_derivs4<APC_MAXM>, dim3(grid4(cnt)), dim3(WPB4 * 64), 0, s, cnt,
                        list, c->st_off, c->st_idx, c->crd, c->n + c->nb, (const int8_t *)c->rorder,
-                       c->unit, f, D);
+                       c->unit, f, D, 1);
+  }
   if (uni)
     hipLaunchKernelGGL(k_derivs_u4, dim3(grid_for(c->n)), dim3(APC_BLOCK), 0, s, c->n,
                        (const int8_t *)c->rkind4, c->st_off, c->st_idx, c->crd, c->n + c->nb,
