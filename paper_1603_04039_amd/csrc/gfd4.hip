@@ -894,21 +894,43 @@ __global__ void __launch_bounds__(wpbn<MR>() * 64)
   if (!ok2 && lane == 0) fb_list[atomicAdd(fb_cnt, 1u)] = (int32_t)y;
 }
 
-// CSR weights -> the sliced layout (entry-major; padding entries 0)
+// CSR weights -> the sliced layout (entry-major; padding entries 0), one wavefront
+// per slice, through an LDS tile of 16 entries x 64 rows: a load instruction reads
+// 16 consecutive entries of each of 4 rows (coalesced along the CSR rows), a store
+// instruction writes one entry of all 64 rows (coalesced along the slice).
 template <typename T>
 __global__ void __launch_bounds__(APC_BLOCK)
     k_sell_copy(int64_t nsl, const int32_t *__restrict__ sl_rows, const int32_t *__restrict__ sl_len,
                 const int64_t *__restrict__ sl_off, const int32_t *__restrict__ st_off,
                 const T *__restrict__ w, T *__restrict__ sw) {
-  const int64_t s = (int64_t)blockIdx.x * (APC_BLOCK / 64) + (threadIdx.x >> 6);
-  if (s >= nsl) return;
+  __shared__ T tile[APC_BLOCK / 64][16][APC_SLICE + 1];
+  const int wv = threadIdx.x >> 6;
+  const int64_t s = (int64_t)blockIdx.x * (APC_BLOCK / 64) + wv;
+  if (s >= nsl) return; // whole wavefronts
   const int lane = threadIdx.x & 63;
+  const int kk = lane & 15, rr = lane >> 4;
+  // the lane's own row (for the 4 x 16 loads: rows r0 + rr read by shuffles)
   const int32_t row = sl_rows[s * APC_SLICE + lane];
-  const int len = sl_len[s];
-  const int64_t off = sl_off[s] + lane;
   const int32_t a = row >= 0 ? st_off[row] : 0;
   const int m = row >= 0 ? st_off[row + 1] - a : 0;
-  for (int k = 0; k < len; k++) sw[off + (int64_t)k * APC_SLICE] = k < m ? w[a + k] : T(0);
+  const int len = sl_len[s];
+  const int64_t off = sl_off[s];
+  for (int k0 = 0; k0 < len; k0 += 16) {
+    for (int r0 = 0; r0 < APC_SLICE; r0 += 4) {
+      const int r = r0 + rr;
+      const int32_t ar = __shfl(a, r, 64), mr = __shfl(m, r, 64);
+      const int k = k0 + kk;
+      tile[wv][kk][r] = k < mr ? w[ar + k] : T(0);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    const int kn = len - k0 < 16 ? len - k0 : 16;
+    for (int q = 0; q < kn; q++) sw[off + (int64_t)(k0 + q) * APC_SLICE + lane] = tile[wv][q][lane];
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  }
 }
 
 // ---------------------------------------------------------------- uniform 56-node rows
