@@ -386,6 +386,39 @@ def batch_bench(apc, torch, steps, tol):
                                   "per step, against the separate entry points"),
                tuned=dict(spmv_div=div, chunk=chunk, spmv_blocks=B.info["spmv_blocks"],
                           use_graph=B.info["use_graph"]))
+    # the learned preconditioner of every cloud, installed once on the union
+    # (install timed apart), against the Jacobi solves above
+    import numpy as np
+    from paper_1603_04039_amd import learned
+    params = torch.from_numpy(np.load(learned.params_path(2))).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(0)
+    Z = torch.randn((learned.SAFEGUARD_PROBES, B.n + B.nb), dtype=torch.float64, device="cuda",
+                    generator=gen)
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record(stream)
+    B.set_learned_precond(params, Z)
+    e1.record(stream)
+    e1.synchronize()
+    t_inst = e0.elapsed_time(e1)
+    lt, li = [], None
+    for it in range(steps + 1):
+        e0.record(stream)
+        _, stl = B.solve(rho_t, tol=tol, maxit=20000, precond=apc.APC_PRECOND_LEARNED)
+        e1.record(stream)
+        e1.synchronize()
+        if any(x["status"] != 0 for x in stl):
+            raise RuntimeError("batch learned solve did not converge")
+        li = [x["iters"] for x in stl]
+        if it > 0:
+            lt.append(e0.elapsed_time(e1))
+    t_l = sum(lt) / len(lt)
+    out["learned"] = dict(install_ms=round(t_inst, 3), solve_ms=round(t_l, 3),
+                          iters_min=min(li), iters_max=max(li),
+                          iters_mean=round(sum(li) / len(li), 1),
+                          jacobi_iters_mean=round(sum(iters) / len(iters), 1),
+                          nodes_per_s=round(n_tot / ((t_asm + t_inst + t_l) * 1e-3), 1),
+                          speedup_solve_vs_jacobi=round(t_sol / t_l, 3))
     B.close()
     return out
 

@@ -441,11 +441,22 @@ int apc_batch_assemble(apc_batch *b, hipStream_t stream);
 int apc_batch_deposit(apc_batch *b, const double *q, double *rho_M, double *rho_t, double tol,
                       int maxit, apc_stats *st, hipStream_t stream);
 /* apc_solve for every cloud: rho_t (n_total, or longer), g (nb_total or NULL),
-   phi (n_total + nb_total), precond APC_PRECOND_NONE or APC_PRECOND_JACOBI; st:
-   count host records (may be NULL).  Returns APC_ENOCONV if any cloud did not
-   converge (see its record).  Synchronises. */
+   phi (n_total + nb_total), precond APC_PRECOND_NONE, APC_PRECOND_JACOBI or
+   APC_PRECOND_LEARNED (after apc_batch_set_learned_precond; APC_EINVAL
+   otherwise); st: count host records (may be NULL).  Returns APC_ENOCONV if any
+   cloud did not converge (see its record).  Synchronises. */
 int apc_batch_solve(apc_batch *b, const double *rho_t, const double *g, double *phi, double tol,
                     int maxit, int precond, apc_stats *st, hipStream_t stream);
+/* apc_set_learned_precond for every cloud of a second-order batch, on the union
+   (features and M rows are local to a row's stencil, so each cloud's rows of M
+   are those of a single-cloud install; the uniform 2-ring rows of one level share
+   one row of M across the batch).  params: APC_MLP_NPARAM floats (device); Z: K
+   probe vectors of n_total + nb_total float64 for the safeguard (device, or NULL
+   for none).  Requires apc_batch_assemble (APC_EINVAL otherwise, and for order
+   4).  The pipeline (apc_batch_pipeline) keeps to Jacobi and none.
+   Synchronises. */
+int apc_batch_set_learned_precond(apc_batch *b, const float *params, const double *Z, int K,
+                                  hipStream_t stream);
 /* apc_interpolate_force for every cloud: phi (n_total + nb_total), phi_p
    (N_total), grad_p (3 x N_total SoA).  Does not synchronise. */
 int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, double *grad_p,

@@ -35,7 +35,8 @@ EXPORTS = ["apc_default_params", "apc_build_cloud", "apc_cloud_info", "apc_get_n
            "apc_learn_data", "apc_mlp_loss_grad", "apc_mlp_adam", "apc_mlp_infer",
            "apc_set_learned_precond", "apc_apply_precond", "apc_build_batch", "apc_batch_info",
            "apc_batch_configure", "apc_batch_tune", "apc_batch_assemble", "apc_batch_deposit",
-           "apc_batch_solve", "apc_batch_interpolate_force", "apc_batch_pipeline",
+           "apc_batch_solve", "apc_batch_set_learned_precond", "apc_batch_interpolate_force",
+           "apc_batch_pipeline",
            "apc_batch_destroy", "apc_push",
            "apc_step", "apc_set_diagnostics", "apc_destroy", "apc_strerror", "apc_last_error",
            "apc2_build_cloud", "apc2_cloud_info", "apc2_get_nodes", "apc2_assemble",
@@ -134,6 +135,7 @@ def load_library(path: str = LIB_PATH):
     lib.apc_batch_assemble.argtypes = [P, P]
     lib.apc_batch_deposit.argtypes = [P, P, P, P, ct.c_double, ct.c_int, P, P]
     lib.apc_batch_solve.argtypes = [P, P, P, P, ct.c_double, ct.c_int, ct.c_int, P, P]
+    lib.apc_batch_set_learned_precond.argtypes = [P, P, P, ct.c_int, P]
     lib.apc_batch_interpolate_force.argtypes = [P, P, P, P, P]
     lib.apc_batch_pipeline.argtypes = [P, P, P, ct.c_double, ct.c_double, ct.c_int, ct.c_int,
                                        P, P, P, P, P, P, ct.POINTER(ct.c_int), P]
@@ -608,6 +610,18 @@ class Batch:
                                              maxit, precond, ct.cast(st, ct.c_void_p),
                                              _stream(stream)), "apc_batch_solve")
         return phi, [dict(x.as_dict(), rc=rc) for x in st]
+
+    def set_learned_precond(self, params, Z=None, stream=None):
+        """Install the learned M of every cloud on the union (second order); Z
+        (K x (n_total + nb_total) float64 probes) enables the per-row safeguard."""
+        import torch
+        K = 0
+        if Z is not None:
+            assert Z.dim() == 2 and Z.shape[1] == self.n + self.nb
+            K = Z.shape[0]
+        _check(self.lib.apc_batch_set_learned_precond(
+            self.h, _dptr(params, torch.float32, MLP_NPARAM), _dptr(Z, torch.float64), K,
+            _stream(stream)), "apc_batch_set_learned_precond")
 
     def interpolate_force(self, phi, stream=None):
         import torch

@@ -418,6 +418,8 @@ int apc_build_batch_impl(const apc_params *P, int count, const double *const *xy
                          const int64_t *N, hipStream_t s, apc_batch **out);
 void apc_destroy_batch_impl(apc_batch *B);
 apc_cloud *apc_batch_union(apc_batch *B);
+int apc_batch_set_learned_impl(apc_batch *B, const float *params, const double *Z, int K,
+                               hipStream_t s);
 int apc_batch_info_impl(const apc_batch *B, apc_batch_info_t *info, int64_t *cN, int64_t *cn,
                         int64_t *cnb);
 int apc_batch_configure_impl(apc_batch *B, int use_graph, int chunk, int spmv_div);

@@ -437,6 +437,14 @@ int apc_batch_solve(apc_batch *b, const double *rho_t, const double *g, double *
   return apc_batch_solve_impl(b, rho_t, g, phi, tol, maxit, precond, st, stream);
 }
 
+int apc_batch_set_learned_precond(apc_batch *b, const float *params, const double *Z, int K,
+                                  hipStream_t stream) {
+  if (!b || !params || (Z && K < 1)) return APC_EINVAL;
+  DeviceGuard gd(apc_batch_union(b)->device);
+  if (!gd.ok) return APC_EHIP;
+  return apc_batch_set_learned_impl(b, params, Z, Z ? K : 0, stream);
+}
+
 int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, double *grad_p,
                                 hipStream_t stream) {
   if (!b) return APC_EINVAL;

@@ -18,11 +18,13 @@
 
 #include <algorithm>
 #include <climits>
+#include <type_traits>
 #include <cstring>
 #include <vector>
 
 #include "apc_internal.h"
 #include "spmv_core.h"
+#include "prec_core.h"
 
 void apc_free_cloud(apc_cloud *c);
 
@@ -124,6 +126,24 @@ __global__ void __launch_bounds__(APC_BLOCK)
       part[s] = a;
       part[B.nsl + s] = b;
     }
+  }
+}
+
+// out = M in (the learned preconditioner of the union) over the slices of the clouds
+// still iterating; launched with op_lds(op) bytes of dynamic LDS
+__global__ void __launch_bounds__(APC_BLOCK)
+    kb_prec(Op op, MOp M, BDesc B, const BScal *__restrict__ sc, const double *__restrict__ in,
+            double *__restrict__ out) {
+  for (SlIter it = sl_iter(op); it.s < it.end; it.s += it.step) {
+    const int s = __builtin_amdgcn_readfirstlane(it.s);
+    if (sc[B.sl_cloud[s]].done) continue;
+    const int u = op.sl_un ? op.sl_un[s] : 0;
+    if (u > 0)
+      prec_slice<false, true>(op, M, in, out, s, u);
+    else if (op.sl_top4)
+      prec_slice<true, false>(op, M, in, out, s, 0);
+    else
+      prec_slice<false, false>(op, M, in, out, s, 0);
   }
 }
 
@@ -415,10 +435,11 @@ struct apc_batch {
   hipStream_t cap = nullptr; // private stream for graph capture
   // launch shape and graphs
   int use_graph = 1, chunk = 8, spmv_div = 1;
-  hipGraphExec_t gexec[2][3][2] = {}; // [density][mode][jacobi] for the current chunk
-  hipGraph_t graph[2][3][2] = {};
-  int gchunk[2][3][2] = {};
-  int gdiv[2][3][2] = {};
+  // [density][mode][preconditioner: none, Jacobi, learned] for the current chunk
+  hipGraphExec_t gexec[2][3][3] = {};
+  hipGraph_t graph[2][3][3] = {};
+  int gchunk[2][3][3] = {};
+  int gdiv[2][3][3] = {};
   // pipeline graph (apc_batch_pipeline): its own solver records (density, then
   // Poisson), rho_M and the derivative workspace, the iteration budgets and what
   // the graph was recorded with
@@ -654,21 +675,31 @@ void launch_restart(apc_batch *B, const Op &op, const BDesc &D, int first, hipSt
                      B->sc, first);
 }
 
-template <int MODE, bool JAC>
+// one iteration; PC: 0 no preconditioner, 1 Jacobi (invd), 2 the learned M of the
+// union (ph = M p and sh = M s by kb_prec)
+template <int MODE, int PC>
 void launch_iteration(apc_batch *B, const Op &op, const BDesc &D, const double *invd, hipStream_t s) {
+  constexpr bool JAC = PC == 1;
   const unsigned g = batch_spmv_grid(B);
   const unsigned gr = (unsigned)(B->nrb_all > 0 ? B->nrb_all : 1);
   const BScal *sc = B->sc;
-  double *ph = JAC ? B->ph : B->p;
-  double *sh = JAC ? B->sh : B->s;
+  double *ph = PC ? B->ph : B->p;
+  double *sh = PC ? B->sh : B->s;
+  const MOp M{B->u->m_diag, B->u->m_sell, B->u->m_tmpl, 26};
   hipLaunchKernelGGL(kb_upd_p<JAC>, dim3(gr), dim3(RB), 0, s, D, sc, (const double *)B->r, B->p,
                      (const double *)B->v, ph, invd);
+  if (PC == 2)
+    hipLaunchKernelGGL(kb_prec, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, M, D, sc,
+                       (const double *)B->p, B->ph);
   hipLaunchKernelGGL(kb_spmv_v<MODE>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, D, sc, (const double *)ph,
                      B->v, (const double *)B->rh, B->part_sl);
   hipLaunchKernelGGL(kb_fin_alpha, dim3(B->count), dim3(FB), 0, s, D, (const double *)B->part_sl,
                      B->sc);
   hipLaunchKernelGGL(kb_upd_s<JAC>, dim3(gr), dim3(RB), 0, s, D, sc, (const double *)B->r,
                      (const double *)B->v, B->s, sh, invd);
+  if (PC == 2)
+    hipLaunchKernelGGL(kb_prec, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, M, D, sc,
+                       (const double *)B->s, B->sh);
   hipLaunchKernelGGL(kb_spmv_t<MODE>, dim3(g), dim3(APC_BLOCK), op_lds(op), s, op, D, sc, (const double *)sh,
                      (const double *)B->s, B->t, B->part_sl);
   hipLaunchKernelGGL(kb_fin_omega, dim3(B->count), dim3(FB), 0, s, D, (const double *)B->part_sl,
@@ -680,15 +711,15 @@ void launch_iteration(apc_batch *B, const Op &op, const BDesc &D, const double *
                      B->sc);
 }
 
-template <int MODE, bool JAC>
+template <int MODE, int PC>
 int run_chunk(apc_batch *B, const Op &op, const BDesc &D, const double *invd, bool density,
               hipStream_t s) {
   if (!B->use_graph) {
-    for (int k = 0; k < B->chunk; k++) launch_iteration<MODE, JAC>(B, op, D, invd, s);
+    for (int k = 0; k < B->chunk; k++) launch_iteration<MODE, PC>(B, op, D, invd, s);
     HIPCHK(hipGetLastError());
     return APC_OK;
   }
-  const int di = density ? 1 : 0, ji = JAC ? 1 : 0;
+  const int di = density ? 1 : 0, ji = PC;
   hipGraphExec_t &ex = B->gexec[di][MODE][ji];
   if (ex && (B->gchunk[di][MODE][ji] != B->chunk || B->gdiv[di][MODE][ji] != B->spmv_div)) {
     HIPCHK(hipGraphExecDestroy(ex));
@@ -699,7 +730,7 @@ int run_chunk(apc_batch *B, const Op &op, const BDesc &D, const double *invd, bo
     // record C iterations once on the private stream; kernel arguments (device
     // pointers of the batch's own workspace) stay valid for the batch's life
     HIPCHK(hipStreamBeginCapture(B->cap, hipStreamCaptureModeThreadLocal));
-    for (int k = 0; k < B->chunk; k++) launch_iteration<MODE, JAC>(B, op, D, invd, B->cap);
+    for (int k = 0; k < B->chunk; k++) launch_iteration<MODE, PC>(B, op, D, invd, B->cap);
     hipGraph_t g = nullptr;
     const hipError_t e = hipStreamEndCapture(B->cap, &g);
     HIPCHK(e);
@@ -718,7 +749,7 @@ int read_sc(apc_batch *B, hipStream_t s) {
   return APC_OK;
 }
 
-template <int MODE, bool JAC>
+template <int MODE, int PC>
 int bicgstab(apc_batch *B, bool density, double tol, int maxit, apc_stats *st, hipStream_t s) {
   const Op op = make_op(B->u, density);
   const BDesc D = make_desc(B);
@@ -747,7 +778,7 @@ int bicgstab(apc_batch *B, bool density, double tol, int maxit, apc_stats *st, h
       HIPCHK(hipGetLastError());
       continue;
     }
-    APCCHK((run_chunk<MODE, JAC>(B, op, D, invd, density, s)));
+    APCCHK((run_chunk<MODE, PC>(B, op, D, invd, density, s)));
     if (guard > 4 * (maxit + 64)) return APC_EHIP; // cannot happen: every chunk advances it
   }
   int status = APC_OK;
@@ -763,7 +794,7 @@ int bicgstab(apc_batch *B, bool density, double tol, int maxit, apc_stats *st, h
       st[c].rel_resid = q.bnorm > 0.0 ? q.rnorm / q.bnorm : 0.0;
       st[c].rel_resid_true = q.rtrue;
       st[c].n_fp64_rows = 0;
-      st[c].precond_used = JAC ? APC_PRECOND_JACOBI : APC_PRECOND_NONE;
+      st[c].precond_used = PC == 2 ? APC_PRECOND_LEARNED : (PC == 1 ? APC_PRECOND_JACOBI : APC_PRECOND_NONE);
     }
   }
   return status;
@@ -771,17 +802,16 @@ int bicgstab(apc_batch *B, bool density, double tol, int maxit, apc_stats *st, h
 
 int run_bsolve(apc_batch *B, bool density, double tol, int maxit, int prec, apc_stats *st,
                hipStream_t s) {
-  const bool jac = prec == APC_PRECOND_JACOBI;
+  auto run = [&](auto mode) {
+    constexpr int MODE = decltype(mode)::value;
+    return prec == APC_PRECOND_LEARNED  ? bicgstab<MODE, 2>(B, density, tol, maxit, st, s)
+           : prec == APC_PRECOND_JACOBI ? bicgstab<MODE, 1>(B, density, tol, maxit, st, s)
+                                        : bicgstab<MODE, 0>(B, density, tol, maxit, st, s);
+  };
   switch (B->P.precision) {
-  case APC_MIXED_F32ACC:
-    return jac ? bicgstab<V32A32, true>(B, density, tol, maxit, st, s)
-               : bicgstab<V32A32, false>(B, density, tol, maxit, st, s);
-  case APC_MIXED:
-    return jac ? bicgstab<V32A64, true>(B, density, tol, maxit, st, s)
-               : bicgstab<V32A64, false>(B, density, tol, maxit, st, s);
-  default:
-    return jac ? bicgstab<V64, true>(B, density, tol, maxit, st, s)
-               : bicgstab<V64, false>(B, density, tol, maxit, st, s);
+  case APC_MIXED_F32ACC: return run(std::integral_constant<int, V32A32>{});
+  case APC_MIXED: return run(std::integral_constant<int, V32A64>{});
+  default: return run(std::integral_constant<int, V64>{});
   }
 }
 
@@ -874,7 +904,7 @@ void apc_destroy_batch_impl(apc_batch *B) {
   if (B->scp_host) (void)hipHostFree(B->scp_host);
   for (int a = 0; a < 2; a++)
     for (int m = 0; m < 3; m++)
-      for (int j = 0; j < 2; j++) {
+      for (int j = 0; j < 3; j++) {
         if (B->gexec[a][m][j]) (void)hipGraphExecDestroy(B->gexec[a][m][j]);
         if (B->graph[a][m][j]) (void)hipGraphDestroy(B->graph[a][m][j]);
       }
@@ -891,6 +921,15 @@ void apc_destroy_batch_impl(apc_batch *B) {
 }
 
 apc_cloud *apc_batch_union(apc_batch *B) { return B->u; }
+
+// The learned preconditioner of every cloud, installed on the union: a row's
+// features and M row are local to its stencil, and the uniform 2-ring rows of one
+// level (identical in every cloud of the batch) share one row of M.
+int apc_batch_set_learned_impl(apc_batch *B, const float *params, const double *Z, int K,
+                               hipStream_t s) {
+  if (!B->u->assembled || B->P.order != 2) return APC_EINVAL;
+  return apc_set_learned_impl(B->u, params, Z, K, s);
+}
 
 int apc_batch_info_impl(const apc_batch *B, apc_batch_info_t *info, int64_t *cN, int64_t *cn,
                         int64_t *cnb) {
@@ -952,7 +991,9 @@ int apc_batch_deposit_impl(apc_batch *B, const double *q, double *rho_M, double 
 int apc_batch_solve_impl(apc_batch *B, const double *rho_t, const double *g, double *phi,
                          double tol, int maxit, int precond, apc_stats *st, hipStream_t s) {
   if (!B->u->assembled) return APC_EINVAL;
-  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI) return APC_EINVAL;
+  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI &&
+      !(precond == APC_PRECOND_LEARNED && B->u->learned))
+    return APC_EINVAL;
   APCCHK(ensure_bws(B));
   HIPCHK(hipEventRecord(B->e0, s));
   APCCHK(rhs(B, false, rho_t, B->P.poisson_c, g, s));
@@ -1056,7 +1097,7 @@ void record_solve(apc_batch *B, bool density, BScal *sc, double tol, int maxit, 
                      maxit);
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(B->u->n)), dim3(APC_BLOCK), 0, cs, B->x, B->u->n, 0.0);
   launch_restart<MODE>(B, op, D, 1, cs);
-  for (int k = 0; k < budget; k++) launch_iteration<MODE, JAC>(B, op, D, B->u->inv_diag, cs);
+  for (int k = 0; k < budget; k++) launch_iteration<MODE, JAC ? 1 : 0>(B, op, D, B->u->inv_diag, cs);
   hipLaunchKernelGGL(kb_mark_reason, dim3((B->count + 255) / 256), dim3(256), 0, cs, sc, B->count);
   launch_restart<MODE>(B, op, D, 0, cs);
   B->sc = save;

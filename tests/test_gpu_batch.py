@@ -106,6 +106,45 @@ def test_batch_solve_matches_single(apc, small_batch, precond):
         assert abs(st[c]["iters"] - st1["iters"]) <= max(3, st1["iters"] // 10)
 
 
+def test_batch_learned_matches_single(apc, small_batch):
+    """The learned preconditioner installed on the batch (one install over the
+    union, probes Z) against each cloud's own install with the same probes (its
+    columns of Z): the per-cloud solves agree as the Jacobi ones do, and the
+    learned solves take fewer iterations than Jacobi."""
+    from paper_1603_04039_amd import learned
+    note("batch learned preconditioner vs single clouds")
+    B, singles, _, _ = small_batch
+    _, rho_t, _ = B.deposit(tol=1e-12, maxit=4000)
+    with pytest.raises(apc.ApcError) as e:
+        B.solve(rho_t, tol=1e-10, precond=apc.APC_PRECOND_LEARNED)
+    assert e.value.code == apc.APC_EINVAL
+    params = torch.from_numpy(np.load(learned.params_path(2))).cuda()
+    gen = torch.Generator(device="cuda")
+    gen.manual_seed(11)
+    Z = torch.randn((learned.SAFEGUARD_PROBES, B.n + B.nb), dtype=torch.float64, device="cuda",
+                    generator=gen)
+    B.set_learned_precond(params, Z)
+    phi, st = B.solve(rho_t, tol=1e-10, maxit=20000, precond=apc.APC_PRECOND_LEARNED)
+    _, stj = B.solve(rho_t, tol=1e-10, maxit=20000, precond=apc.APC_PRECOND_JACOBI)
+    it_l = it_j = 0
+    for c, S in enumerate(singles):
+        idx = torch.from_numpy(B.node_index(c)).cuda()
+        S.set_learned_precond(params, Z[:, idx].contiguous())
+        rt = rho_t[idx][:S.n].contiguous()
+        phi1, st1 = S.solve(rt, tol=1e-10, maxit=20000, precond=apc.APC_PRECOND_LEARNED)
+        assert st[c]["status"] == 0 and st1["status"] == 0
+        assert st[c]["precond_used"] == apc.APC_PRECOND_LEARNED
+        assert st[c]["rel_resid_true"] <= 1e-10
+        d = (phi[idx] - phi1).abs().max().item()
+        note(f"cloud {c}: n={S.n} iters batch {st[c]['iters']} single {st1['iters']} "
+             f"(Jacobi {stj[c]['iters']}) diff {d:.2e}")
+        assert d <= 1e-6 * phi1.abs().max().item()
+        assert abs(st[c]["iters"] - st1["iters"]) <= max(3, st1["iters"] // 10)
+        it_l += st[c]["iters"]
+        it_j += stj[c]["iters"]
+    assert it_l < it_j
+
+
 def test_batch_interpolation_bit_exact(apc, small_batch):
     note("batch interpolation vs single clouds on the same phi")
     B, singles, _, _ = small_batch
