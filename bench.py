@@ -413,7 +413,21 @@ def batch_bench(apc, torch, steps, tol):
         if it > 0:
             lt.append(e0.elapsed_time(e1))
     t_l = sum(lt) / len(lt)
+    # the whole field solve with the learned M as one graph replay
+    bl, _, _, _ = B.pipeline(tol_density=1e-10, tol=tol, precond=apc.APC_PRECOND_LEARNED)
+    pl = []
+    for it in range(steps + 1):
+        e0.record(stream)
+        _, sd, sp, used = B.pipeline(tol_density=1e-10, tol=tol,
+                                     precond=apc.APC_PRECOND_LEARNED, out=bl)
+        e1.record(stream)
+        e1.synchronize()
+        if any(x["status"] != 0 for x in sd + sp):
+            raise RuntimeError("batch learned pipeline did not converge")
+        if it > 0:
+            pl.append(e0.elapsed_time(e1))
     out["learned"] = dict(install_ms=round(t_inst, 3), solve_ms=round(t_l, 3),
+                          pipeline_ms=round(sum(pl) / len(pl), 3),
                           iters_min=min(li), iters_max=max(li),
                           iters_mean=round(sum(li) / len(li), 1),
                           jacobi_iters_mean=round(sum(iters) / len(iters), 1),

@@ -453,8 +453,7 @@ int apc_batch_solve(apc_batch *b, const double *rho_t, const double *g, double *
    one row of M across the batch).  params: APC_MLP_NPARAM floats (device); Z: K
    probe vectors of n_total + nb_total float64 for the safeguard (device, or NULL
    for none).  Requires apc_batch_assemble (APC_EINVAL otherwise, and for order
-   4).  The pipeline (apc_batch_pipeline) keeps to Jacobi and none.
-   Synchronises. */
+   4).  Synchronises. */
 int apc_batch_set_learned_precond(apc_batch *b, const float *params, const double *Z, int K,
                                   hipStream_t stream);
 /* apc_interpolate_force for every cloud: phi (n_total + nb_total), phi_p
@@ -475,8 +474,9 @@ int apc_batch_interpolate_force(apc_batch *b, const double *phi, double *phi_p, 
    enlarges the budgets and runs that call through the separate entry points.
    q (N_total or NULL), g (nb_total or NULL), rho_t (n_total + nb_total), phi
    (n_total + nb_total), phi_p (N_total), grad_p (3 x N_total) as in those entry
-   points; precond APC_PRECOND_NONE or APC_PRECOND_JACOBI (the density solve runs
-   without).  st_density, st: count host records each (may be NULL; ms is the
+   points; precond APC_PRECOND_NONE, APC_PRECOND_JACOBI or APC_PRECOND_LEARNED
+   (after apc_batch_set_learned_precond; the density solve runs without).
+   st_density, st: count host records each (may be NULL; ms is the
    graph's time when it ran); *graph_used (may be NULL): 1 when this call replayed
    the graph.  Returns APC_ENOCONV if a cloud did not converge.  Synchronises.
    The graph holds the batch's workspace: calls on one batch must not overlap. */

@@ -1086,7 +1086,7 @@ namespace {
 // one batched BiCGSTAB recorded into the capture stream: fresh records, x = 0, the
 // start, `budget` iterations (clouds that stop skip their rows), then one
 // true-residual check; sc: the solve's own records
-template <int MODE, bool JAC>
+template <int MODE, int PC>
 void record_solve(apc_batch *B, bool density, BScal *sc, double tol, int maxit, int budget,
                   hipStream_t cs) {
   const Op op = make_op(B->u, density);
@@ -1097,7 +1097,7 @@ void record_solve(apc_batch *B, bool density, BScal *sc, double tol, int maxit, 
                      maxit);
   hipLaunchKernelGGL(k_fill_f64, dim3(grid_for(B->u->n)), dim3(APC_BLOCK), 0, cs, B->x, B->u->n, 0.0);
   launch_restart<MODE>(B, op, D, 1, cs);
-  for (int k = 0; k < budget; k++) launch_iteration<MODE, JAC ? 1 : 0>(B, op, D, B->u->inv_diag, cs);
+  for (int k = 0; k < budget; k++) launch_iteration<MODE, PC>(B, op, D, B->u->inv_diag, cs);
   hipLaunchKernelGGL(kb_mark_reason, dim3((B->count + 255) / 256), dim3(256), 0, cs, sc, B->count);
   launch_restart<MODE>(B, op, D, 0, cs);
   B->sc = save;
@@ -1105,11 +1105,13 @@ void record_solve(apc_batch *B, bool density, BScal *sc, double tol, int maxit, 
 
 template <int MODE>
 void record_solve_any(apc_batch *B, bool density, BScal *sc, double tol, int maxit, int budget,
-                      bool jac, hipStream_t cs) {
-  if (jac)
-    record_solve<MODE, true>(B, density, sc, tol, maxit, budget, cs);
+                      int pc, hipStream_t cs) {
+  if (pc == APC_PRECOND_LEARNED)
+    record_solve<MODE, 2>(B, density, sc, tol, maxit, budget, cs);
+  else if (pc == APC_PRECOND_JACOBI)
+    record_solve<MODE, 1>(B, density, sc, tol, maxit, budget, cs);
   else
-    record_solve<MODE, false>(B, density, sc, tol, maxit, budget, cs);
+    record_solve<MODE, 0>(B, density, sc, tol, maxit, budget, cs);
 }
 
 // assembly, deposit and density solve, Poisson solve and interpolation, recorded
@@ -1118,26 +1120,27 @@ int record_pipeline(apc_batch *B, const double *q, const double *g, double tol_d
                     int maxit, int precond, double *rho_t, double *phi, double *phi_p,
                     double *grad_p, hipStream_t cs) {
   apc_cloud *u = B->u;
-  const bool jac = precond == APC_PRECOND_JACOBI;
+  const bool keep = u->learned; // same rows every assembly: an installed M stays valid
   APCCHK(apc_assemble_impl(u, cs));
+  u->learned = keep;
   hipLaunchKernelGGL(kb_deposit, dim3(grid_for(u->n)), dim3(APC_BLOCK), 0, cs, u->n, u->first,
                      u->count, u->level, u->perm, q, (const double *)B->invN, u->P.L, B->rhoM);
   if (u->nb > 0)
     hipLaunchKernelGGL(kb_bnd_copy, dim3(grid_for(u->nb)), dim3(APC_BLOCK), 0, cs, u->n, u->nb,
                        u->bowner, B->rhoM);
   APCCHK(rhs(B, true, B->rhoM, 1.0, B->rhoM + u->n, cs));
-  auto solve = [&](bool density, BScal *sc, double t, int budget, bool j) {
+  auto solve = [&](bool density, BScal *sc, double t, int budget, int j) {
     switch (B->P.precision) {
     case APC_MIXED_F32ACC: record_solve_any<V32A32>(B, density, sc, t, maxit, budget, j, cs); break;
     case APC_MIXED: record_solve_any<V32A64>(B, density, sc, t, maxit, budget, j, cs); break;
     default: record_solve_any<V64>(B, density, sc, t, maxit, budget, j, cs);
     }
   };
-  solve(true, B->sc_pipe, tol_d, B->budget_d, false);
+  solve(true, B->sc_pipe, tol_d, B->budget_d, APC_PRECOND_NONE);
   hipLaunchKernelGGL(kb_write_out, dim3(grid_for(u->n + u->nb)), dim3(APC_BLOCK), 0, cs, u->n, u->nb,
                      (const double *)B->x, (const double *)(B->rhoM + u->n), rho_t);
   APCCHK(rhs(B, false, rho_t, B->P.poisson_c, g, cs));
-  solve(false, B->sc_pipe + B->count, tol, B->budget_p, jac);
+  solve(false, B->sc_pipe + B->count, tol, B->budget_p, precond);
   hipLaunchKernelGGL(kb_write_out, dim3(grid_for(u->n + u->nb)), dim3(APC_BLOCK), 0, cs, u->n, u->nb,
                      (const double *)B->x, g, phi);
   APCCHK(apc_interp_with(u, phi, phi_p, grad_p, B->Dw, cs));
@@ -1163,7 +1166,9 @@ int apc_batch_pipeline_impl(apc_batch *B, const double *q, const double *g, doub
                             double tol, int maxit, int precond, double *rho_t, double *phi,
                             double *phi_p, double *grad_p, apc_stats *st_d, apc_stats *st,
                             int *graph_used, hipStream_t s) {
-  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI) return APC_EINVAL;
+  if (precond != APC_PRECOND_NONE && precond != APC_PRECOND_JACOBI &&
+      !(precond == APC_PRECOND_LEARNED && B->u->learned))
+    return APC_EINVAL;
   if (B->P.order != 2) return APC_EINVAL;
   APCCHK(ensure_bws(B));
   apc_cloud *u = B->u;
@@ -1180,7 +1185,11 @@ int apc_batch_pipeline_impl(apc_batch *B, const double *q, const double *g, doub
   // the separate entry points: the first call (it sets the budgets) and any call
   // whose graph left a cloud unfinished
   auto separate = [&]() -> int {
+    // the union's rows come out of its assembly the same every time, so an
+    // installed M stays valid across it
+    const bool keep = u->learned;
     APCCHK(apc_assemble_impl(u, s));
+    u->learned = keep;
     int rc = apc_batch_deposit_impl(B, q, B->rhoM, rho_t, tol_d, maxit, sd.data(), s);
     if (rc < 0) return rc;
     const int rc2 = apc_batch_solve_impl(B, rho_t, g, phi, tol, maxit, precond, sp.data(), s);

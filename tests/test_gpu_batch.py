@@ -143,6 +143,17 @@ def test_batch_learned_matches_single(apc, small_batch):
         it_l += st[c]["iters"]
         it_j += stj[c]["iters"]
     assert it_l < it_j
+    # the pipeline graph with the learned M: replays equal the separate entry points
+    bufs, sd0, sp0, used0 = B.pipeline(tol_density=1e-10, tol=1e-10,
+                                       precond=apc.APC_PRECOND_LEARNED)
+    ref = [b.clone() for b in bufs]
+    for _ in range(2):
+        out, sd, sp, used = B.pipeline(tol_density=1e-10, tol=1e-10,
+                                       precond=apc.APC_PRECOND_LEARNED, out=bufs)
+        assert used and all(x["status"] == 0 for x in sd + sp)
+        assert all(x["precond_used"] == apc.APC_PRECOND_LEARNED for x in sp)
+        for a, b in zip(out, ref):
+            assert torch.equal(a, b)
 
 
 def test_batch_interpolation_bit_exact(apc, small_batch):
