@@ -151,3 +151,22 @@ def test_kernel_rejected_by_batches(apc):
     with pytest.raises(apc.ApcError) as e:
         apc.Cloud(x, order=2, max_depth=5, kernel=3)
     assert e.value.code == apc.APC_EINVAL
+
+
+@pytest.mark.parametrize("kernel,periodic", [(CIC, 0), (TSC, 1)])
+def test_kernel_deposit_deep_tree(apc, oracle_mod, kernel, periodic):
+    """A tree deeper than the deposit's leaf table (levels 8 and 9 under the
+    table's level 7): rho_M within 1e-13 of the oracle, bounded and periodic."""
+    xyz = beam_halo(20000, seed=4, sigma=(0.03, 0.03, 0.03))
+    kw = dict(order=2, c=0.01, max_depth=9, kernel=kernel, periodic=periodic)
+    note(f"deep tree deposit, kernel {kernel}, periodic {periodic}")
+    O = oracle_mod.OracleCloud(xyz, **kw)
+    G = apc.Cloud(cuda(xyz), precision=apc.APC_FP64, **kw)
+    G.assemble_gfd()
+    assert G.nodes()["level"].max() >= 8
+    rm_o = O.deposit()
+    rho_M, _, st = G.deposit(tol=1e-12)
+    err = np.max(np.abs(rho_M.cpu().numpy() - rm_o) / np.maximum(np.abs(rm_o), 1e-300))
+    note(f"  n={G.n}: deposit {err:.2e}")
+    assert err <= 1e-13 and st["status"] == 0
+    G.close()
