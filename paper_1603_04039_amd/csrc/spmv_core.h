@@ -42,6 +42,7 @@ struct Op {
   int ucap;
   const int32_t *sl_box; // boxes of the boxed slices (APC_BOX_N node ids each, -1 unused)
   int64_t cs[9];
+  int nt; // layout read with non-temporal loads (see ld_layout)
 };
 
 // Dynamic LDS of a kernel that applies the operator through sell_apply or
@@ -85,16 +86,33 @@ static inline unsigned spmv_grid(const apc_cloud *c) {
   const int64_t g = 8 * per;
   return (unsigned)(g < (int64_t)GSPMV ? g : (int64_t)GSPMV);
 }
+// The layout arrays (packed column indices, staging lists and slots, box ids,
+// weights) are read once per apply.  When they are far larger than the 256 MB
+// Infinity Cache (op.nt) they go through non-temporal loads, so that the caches
+// keep the gathered vector instead (same values; 408 -> 365 us per FP64 solver
+// SpMV on the 1e8-particle fourth-order cloud); a smaller layout stays cached from
+// one apply to the next, which non-temporal loads would defeat (42 -> 51 us on the
+// 1e7-particle second-order cloud).  The choice is made once per slice call
+// (sell_apply, prec_slice); a run-time select at each load let the compiler merge
+// the two loads into a plain one.
+template <bool NT, typename T>
+__device__ __forceinline__ T ld_layout(const T *p) {
+  if constexpr (NT)
+    return __builtin_nontemporal_load(p);
+  else
+    return *p;
+}
+//
 // Column index of entry k of the lane's row: lb = o/2 + lane and hb = o/4 + lane
 // for the slice at entry offset o.  Three bytes per entry (four with TOP): two
 // 32-bit loads cover two and four entries, so a uniform row's 24 indices take 18
 // loads instead of 24.
-template <bool TOP>
+template <bool TOP, bool NT>
 __device__ __forceinline__ int32_t sl_col(const Op &op, int64_t lb, int64_t hb, int k) {
-  const uint32_t lo = (op.sl_lo2[lb + (int64_t)SL * (k >> 1)] >> (16 * (k & 1))) & 0xffffu;
-  const uint32_t hi = (op.sl_hi4[hb + (int64_t)SL * (k >> 2)] >> (8 * (k & 3))) & 0xffu;
+  const uint32_t lo = (ld_layout<NT>(&op.sl_lo2[lb + (int64_t)SL * (k >> 1)]) >> (16 * (k & 1))) & 0xffffu;
+  const uint32_t hi = (ld_layout<NT>(&op.sl_hi4[hb + (int64_t)SL * (k >> 2)]) >> (8 * (k & 3))) & 0xffu;
   uint32_t j = lo | (hi << 16);
-  if (TOP) j |= ((op.sl_top4[hb + (int64_t)SL * (k >> 2)] >> (8 * (k & 3))) & 0xffu) << 24;
+  if (TOP) j |= ((ld_layout<NT>(&op.sl_top4[hb + (int64_t)SL * (k >> 2)]) >> (8 * (k & 3))) & 0xffu) << 24;
   return (int32_t)j;
 }
 
@@ -116,7 +134,7 @@ __device__ __forceinline__ void wave_lds_sync() {
 // lanes read neighbouring addresses) into the tile: PER loads a lane in flight
 // (all PER column loads, then all PER gathers).  Every lane of the wavefront takes
 // part.
-template <int PER = 4>
+template <bool NT, int PER = 4>
 __device__ __forceinline__ void stage_fill(double *tile, const int32_t *__restrict__ uq, int u,
                                            const double *__restrict__ x) {
   const int lane = threadIdx.x & 63;
@@ -125,7 +143,7 @@ __device__ __forceinline__ void stage_fill(double *tile, const int32_t *__restri
     int32_t q[PER];
     double v[PER];
 #pragma unroll
-    for (int h = 0; h < PER; h++) q[h] = b + SL * h + lane < u ? uq[b + SL * h + lane] : -1;
+    for (int h = 0; h < PER; h++) q[h] = b + SL * h + lane < u ? ld_layout<NT>(&uq[b + SL * h + lane]) : -1;
 #pragma unroll
     for (int h = 0; h < PER; h++) v[h] = q[h] >= 0 ? x[q[h]] : 0.0;
 #pragma unroll
@@ -136,8 +154,9 @@ __device__ __forceinline__ void stage_fill(double *tile, const int32_t *__restri
 }
 
 // tile slot of entry k of the lane (lb = o/2 + lane)
+template <bool NT>
 __device__ __forceinline__ int stage_slot(const Op &op, int64_t lb, int k) {
-  return (int)((op.sl_lx2[lb + (int64_t)SL * (k >> 1)] >> (16 * (k & 1))) & 0xffffu);
+  return (int)((ld_layout<NT>(&op.sl_lx2[lb + (int64_t)SL * (k >> 1)]) >> (16 * (k & 1))) & 0xffffu);
 }
 
 // (A x)_row for the lane's row of slice s (row = -1 on padding lanes, result 0).
@@ -152,7 +171,7 @@ __device__ __forceinline__ int stage_slot(const Op &op, int64_t lb, int k) {
 // neighbour values are staged in the wavefront's LDS tile first, and each entry
 // reads its slot there (same values, same arithmetic, so the result is the same
 // bit for bit); otherwise every entry gathers from x.
-template <int MODE, bool TOP, bool STG>
+template <int MODE, bool TOP, bool STG, bool NT>
 __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__restrict__ x, int s,
                                                int u, int32_t &row) {
   const int lane = threadIdx.x & 63;
@@ -168,8 +187,8 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
     // as the unstaged loop below
     uint32_t wq[28];
 #pragma unroll
-    for (int k = 0; k < 28; k++) wq[k] = op.sl_lx2[lb + (int64_t)SL * k];
-    stage_fill(tile, op.sl_uq + o, u, x);
+    for (int k = 0; k < 28; k++) wq[k] = ld_layout<NT>(&op.sl_lx2[lb + (int64_t)SL * k]);
+    stage_fill<NT>(tile, op.sl_uq + o, u, x);
     row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return 0.0;
     xi = x[row];
@@ -200,13 +219,13 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
     if (STG) {
       uint32_t wq[12];
 #pragma unroll
-      for (int k = 0; k < 12; k++) wq[k] = op.sl_lx2[lb + (int64_t)SL * k];
-      stage_fill(tile, op.sl_uq + o, u, x);
+      for (int k = 0; k < 12; k++) wq[k] = ld_layout<NT>(&op.sl_lx2[lb + (int64_t)SL * k]);
+      stage_fill<NT>(tile, op.sl_uq + o, u, x);
 #pragma unroll
       for (int k = 0; k < 24; k++) jj[k] = (int32_t)((wq[k >> 1] >> (16 * (k & 1))) & 0xffffu);
     } else {
 #pragma unroll
-      for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP>(op, lb, hb, k);
+      for (int k = 0; k < 24; k++) jj[k] = sl_col<TOP, NT>(op, lb, hb, k);
     }
     row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return 0.0;
@@ -234,11 +253,11 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
     }
   } else {
     const int len = op.sl_len[s];
-    if (STG) stage_fill(tile, op.sl_uq + o, u, x);
+    if (STG) stage_fill<NT>(tile, op.sl_uq + o, u, x);
     row = op.sl_rows[(int64_t)s * SL + lane];
     if (row < 0) return 0.0;
     xi = x[row];
-#define APC_NB(k) (STG ? tile[stage_slot(op, lb, k)] : x[sl_col<TOP>(op, lb, hb, k)])
+#define APC_NB(k) (STG ? tile[stage_slot<NT>(op, lb, k)] : x[sl_col<TOP, NT>(op, lb, hb, k)])
 #define APC_T4(c, k) ((k) < 6 ? c[0] : ((k) < 18 ? c[1] : ((k) < 26 ? c[2] : ((k) < 32 ? c[3] : c[4]))))
     if (kind == 2) {
       const double scale = op.t4_scaled ? ldexp(op.invL2, 2 * (int)op.rk[row]) : 1.0;
@@ -263,19 +282,19 @@ __device__ __forceinline__ double sell_apply_t(const Op &op, const double *__res
       const float *__restrict__ wv = op.sl_w32 + off;
       float af = 0.f;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) af += wv[k * SL] * (float)(APC_NB(k) - xi);
+      for (int k = 0; k < len; k++) af += ld_layout<NT>(&wv[k * SL]) * (float)(APC_NB(k) - xi);
       acc = (double)af;
     } else if (MODE == V64) {
       const double *__restrict__ wv = op.sl_w64 + off;
       double ad = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) ad += wv[k * SL] * (APC_NB(k) - xi);
+      for (int k = 0; k < len; k++) ad += ld_layout<NT>(&wv[k * SL]) * (APC_NB(k) - xi);
       acc = ad;
     } else {
       const float *__restrict__ wv = op.sl_w32 + off;
       double ad = 0.0;
 #pragma unroll 8
-      for (int k = 0; k < len; k++) ad += (double)wv[k * SL] * (APC_NB(k) - xi);
+      for (int k = 0; k < len; k++) ad += (double)ld_layout<NT>(&wv[k * SL]) * (APC_NB(k) - xi);
       acc = ad;
     }
 #undef APC_T4
@@ -318,7 +337,7 @@ constexpr Box56 kBox56{};
 // each entry reads x through the box's node id.  Both sum the 56 entries in the
 // order of kBox56 with the shell weights, then scale once (same arithmetic, so the
 // same result bit for bit).
-template <int MODE, bool STG>
+template <int MODE, bool STG, bool NT>
 __device__ __forceinline__ double box_apply(const Op &op, const double *__restrict__ x, int s,
                                             int tk, int32_t &row) {
   const int lane = threadIdx.x & 63;
@@ -328,7 +347,7 @@ __device__ __forceinline__ double box_apply(const Op &op, const double *__restri
   const int lz = (lane & 1) | (((lane >> 3) & 1) << 1);
   const int b = (lx + 2) + 8 * (ly + 2) + APC_BOX_SZ * (lz + 2);
   double *tile = STG ? stage_tile(op) : nullptr;
-  if (STG) stage_fill<APC_BOX_N / SL>(tile, bx, APC_BOX_N, x); // one batch: 8 per lane
+  if (STG) stage_fill<NT, APC_BOX_N / SL>(tile, bx, APC_BOX_N, x); // one batch: 8 per lane
   row = op.sl_rows[(int64_t)s * SL + lane];
   const double xi = x[row];
   const double scale = op.t4_scaled ? ldexp(op.invL2, 2 * (int)op.rk[row]) : 1.0;
@@ -357,26 +376,32 @@ __device__ __forceinline__ double box_apply(const Op &op, const double *__restri
   return op.unit_diag ? xi + acc : acc;
 }
 
+template <int MODE, bool NT>
+__device__ __forceinline__ double sell_apply_nt(const Op &op, const double *__restrict__ x, int s,
+                                                int32_t &row) {
+  const int tk = op.sl_tmpl[s];
+  double v;
+  if ((tk & 3) == 3) {
+    v = (op.sl_un && op.ucap >= APC_BOX_N) ? box_apply<MODE, true, NT>(op, x, s, tk, row)
+                                          : box_apply<MODE, false, NT>(op, x, s, tk, row);
+  } else {
+    const int u = op.sl_un ? op.sl_un[s] : 0;
+    if (u > 0)
+      v = sell_apply_t<MODE, false, true, NT>(op, x, s, u, row);
+    else
+      v = op.sl_top4 ? sell_apply_t<MODE, true, false, NT>(op, x, s, 0, row)
+                     : sell_apply_t<MODE, false, false, NT>(op, x, s, 0, row);
+  }
+  if (op.pin && row == 0) v = x[0];
+  return v;
+}
+
 // Kernels that call this are launched with op_lds(op) bytes of dynamic LDS.
 template <int MODE>
 __device__ __forceinline__ double sell_apply(const Op &op, const double *__restrict__ x, int s_in,
                                              int32_t &row) {
   const int s = __builtin_amdgcn_readfirstlane(s_in);
-  const int tk = op.sl_tmpl[s];
-  double v;
-  if ((tk & 3) == 3) {
-    v = (op.sl_un && op.ucap >= APC_BOX_N) ? box_apply<MODE, true>(op, x, s, tk, row)
-                                          : box_apply<MODE, false>(op, x, s, tk, row);
-  } else {
-    const int u = op.sl_un ? op.sl_un[s] : 0;
-    if (u > 0)
-      v = sell_apply_t<MODE, false, true>(op, x, s, u, row);
-    else
-      v = op.sl_top4 ? sell_apply_t<MODE, true, false>(op, x, s, 0, row)
-                     : sell_apply_t<MODE, false, false>(op, x, s, 0, row);
-  }
-  if (op.pin && row == 0) v = x[0];
-  return v;
+  return op.nt ? sell_apply_nt<MODE, true>(op, x, s, row) : sell_apply_nt<MODE, false>(op, x, s, row);
 }
 
 static inline Op make_op(const apc_cloud *c, bool density) {
@@ -410,6 +435,8 @@ static inline Op make_op(const apc_cloud *c, bool density) {
   op.sl_uq = c->sl_uq;
   op.sl_lx2 = c->sl_lx2;
   op.sl_box = c->sl_box;
+  // non-temporal layout loads past 64M stored entries (about 0.5 GB of layout)
+  op.nt = c->sl_entries > ((int64_t)64 << 20) ? 1 : 0;
   for (int k = 0; k < 9; k++) op.cs[k] = c->sl_cs[k];
   return op;
 }
