@@ -229,10 +229,14 @@ __global__ void __launch_bounds__(APC_BLOCK)
   double val[2] = {0.0, 0.0};
   for (int64_t i = (int64_t)blockIdx.x * APC_BLOCK + threadIdx.x; i < n;
        i += (int64_t)gridDim.x * APC_BLOCK) {
-    x[i] += al * ph[i] + om * sh[i];
-    const double ri = s[i] - om * t[i];
+    // x, t and rh are not read again before the next iteration's update: they
+    // bypass the caches, which keep p, s and r for the next operator applies
+    // (same arithmetic: x + (alpha ph + omega sh))
+    const double dx = al * ph[i] + om * sh[i];
+    __builtin_nontemporal_store(__builtin_nontemporal_load(&x[i]) + dx, &x[i]);
+    const double ri = s[i] - om * __builtin_nontemporal_load(&t[i]);
     r[i] = ri;
-    val[0] += rh[i] * ri;
+    val[0] += __builtin_nontemporal_load(&rh[i]) * ri;
     val[1] += ri * ri;
   }
   block_partials<2>(val, part);
